@@ -1,0 +1,117 @@
+"""Form-factor projected fermionic loops chi^pp, chi^ph and their T-derivatives.
+
+TEST INFRASTRUCTURE ONLY (plain FP64 CPU oracle; never used by the GPU path).
+
+Paper: eqn. chis (Sec. 2.4) defines
+    chi^pp_mn(l) = int dp G(l/2 + p) G(l/2 - p) f_m(p) f_n(p),
+    chi^ph_mn(l) = int dp G(p + l/2) G(p - l/2) f_m(p) f_n(p),
+with int dp = T sum_{Matsubara n} (1/N_k) sum_p at zero bosonic frequency
+(frequency dependence dropped, Sec. 2.3).  The regulator here is the
+temperature: G(i w, eps) = 1/(i w - eps) unrescaled, and the "dot" of the
+flow (Fig. diags-fleq: a scale derivative is implicit on closed loops) is
+d/dT of the loop.
+
+Per (q, p), with eps1 = eps(p + q/2), eps2 = eps(p - q/2) (the pp pair
+eps(q/2 + p), eps(q/2 - p) is the same pair because eps is even),
+a = eps1/T, b = eps2/T, the Matsubara sums are the textbook closed forms
+    L^ph = T sum_n G(i w_n, eps1) G(i w_n, eps2)
+         = (n_F(eps1) - n_F(eps2))/(eps1 - eps2)
+         = -(1/4T) sinhc((a-b)/2) sech(a/2) sech(b/2),
+    L^pp = T sum_n G(i w_n, eps1) G(-i w_n, eps2)
+         = (1 - n_F(eps1) - n_F(eps2))/(eps1 + eps2)
+         = +(1/4T) sinhc((a+b)/2) sech(a/2) sech(b/2),
+and differentiating at fixed energies,
+    dL/dT = (L/T) [ (a/2) tanh(a/2) + (b/2) tanh(b/2) - x coth x ],
+with x = (a-b)/2 (ph) or (a+b)/2 (pp) and x coth x = 1 at x = 0.
+These are evaluated in the log domain so that no intermediate overflows.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .lattice import FormFactors, dispersion, k_grid, q_grid
+
+LN2 = np.log(2.0)
+
+
+def _ln_sinhc_tail(x):
+    """log(sinh(x)/x) - |x|: the part left after the linear term |x|."""
+    x = np.abs(np.asarray(x, dtype=float))
+    out = np.empty_like(x)
+    small = x < 1e-3
+    xs = x[small]
+    out[small] = np.log1p(xs * xs / 6.0 + xs ** 4 / 120.0) - xs
+    xl = x[~small]
+    out[~small] = np.log1p(-np.exp(-2.0 * xl)) - np.log(2.0 * xl)
+    return out
+
+
+def _ln_cosh_tail(y):
+    """log(cosh(y)) - |y| = log1p(exp(-2|y|)) - log 2."""
+    return np.log1p(np.exp(-2.0 * np.abs(y))) - LN2
+
+
+def _x_coth_x(x):
+    x = np.asarray(x, dtype=float)
+    out = np.empty_like(x)
+    small = np.abs(x) < 1e-3
+    xs = x[small]
+    out[small] = 1.0 + xs * xs / 3.0 - xs ** 4 / 45.0
+    xl = x[~small]
+    out[~small] = xl / np.tanh(xl)
+    return out
+
+
+def loop(eps1, eps2, T, channel: str):
+    """L^X(eps1, eps2; T) for X in {'ph', 'pp'}."""
+    a = np.asarray(eps1, dtype=float) / T
+    b = np.asarray(eps2, dtype=float) / T
+    if channel == "ph":
+        x, sign = 0.5 * (a - b), -1.0
+    elif channel == "pp":
+        x, sign = 0.5 * (a + b), +1.0
+    else:
+        raise ValueError(channel)
+    # log of sinhc(x) sech(a/2) sech(b/2); the linear parts |x| - |a|/2 - |b|/2
+    # are combined first so that no large terms cancel at |a|, |b| >> 1
+    lin = np.abs(x) - 0.5 * np.abs(a) - 0.5 * np.abs(b)
+    ln = lin + _ln_sinhc_tail(x) - _ln_cosh_tail(0.5 * a) - _ln_cosh_tail(0.5 * b)
+    return sign * np.exp(ln) / (4.0 * T)
+
+
+def loop_dot(eps1, eps2, T, channel: str):
+    """dL^X/dT at fixed energies."""
+    a = np.asarray(eps1, dtype=float) / T
+    b = np.asarray(eps2, dtype=float) / T
+    x = 0.5 * (a - b) if channel == "ph" else 0.5 * (a + b)
+    L = loop(eps1, eps2, T, channel)
+    bracket = 0.5 * a * np.tanh(0.5 * a) + 0.5 * b * np.tanh(0.5 * b) - _x_coth_x(x)
+    return L * bracket / T
+
+
+def bubbles(point, T: float, which: str = "dot", ff: FormFactors | None = None,
+            q_index=None):
+    """chi (which='value') or d chi/dT (which='dot') on the transfer grid.
+
+    Returns an array [2][nq_sel][nff][nff] ordered (pp, ph).  The loop
+    integral is the literal pairwise grid average
+        chi_mn(q) = (1/N_k) sum_p L(eps(p+q/2), eps(p-q/2)) f_m(p) f_n(p)
+    (discretised eqn. chis: p on the unshifted fine grid, energies taken at
+    p +- q/2, form factors at p).
+    """
+    ff = ff or FormFactors(point.shells)
+    qx, qy = q_grid(point.Lq)
+    if q_index is not None:
+        qx, qy = qx[q_index], qy[q_index]
+    px, py = k_grid(point.Lk)
+    F = ff.values(px, py)                         # [nff, Nk]
+    Nk = px.size
+    fn = loop_dot if which == "dot" else loop
+    out = np.empty((2, qx.size, ff.nff, ff.nff))
+    for i in range(qx.size):
+        e1 = dispersion(px + 0.5 * qx[i], py + 0.5 * qy[i], point.t, point.tp, point.mu)
+        e2 = dispersion(px - 0.5 * qx[i], py - 0.5 * qy[i], point.t, point.tp, point.mu)
+        for c, ch in enumerate(("pp", "ph")):
+            w = fn(e1, e2, T, ch)
+            out[c, i] = (F * w) @ F.T / Nk
+    return out
