@@ -23,7 +23,9 @@ a = eps1/T, b = eps2/T, the Matsubara sums are the textbook closed forms
 and differentiating at fixed energies,
     dL/dT = (L/T) [ (a/2) tanh(a/2) + (b/2) tanh(b/2) - x coth x ],
 with x = (a-b)/2 (ph) or (a+b)/2 (pp) and x coth x = 1 at x = 0.
-These are evaluated in the log domain so that no intermediate overflows.
+L is evaluated in the log domain so that no intermediate overflows; the
+bracket is split into its exact linear part and small one-signed tails, so
+that exponentially small derivatives keep their relative accuracy.
 """
 from __future__ import annotations
 
@@ -51,42 +53,56 @@ def _ln_cosh_tail(y):
     return np.log1p(np.exp(-2.0 * np.abs(y))) - LN2
 
 
-def _x_coth_x(x):
-    x = np.asarray(x, dtype=float)
-    out = np.empty_like(x)
-    small = np.abs(x) < 1e-3
-    xs = x[small]
-    out[small] = 1.0 + xs * xs / 3.0 - xs ** 4 / 45.0
-    xl = x[~small]
-    out[~small] = xl / np.tanh(xl)
-    return out
+def _x_and_linear_part(a, b, channel):
+    """x of the channel and the exact value of |x| - |a|/2 - |b|/2.
+
+    ph: x = (a - b)/2, pp: x = (a + b)/2.  |x| equals |a|/2 + |b|/2 or
+    | |a|/2 - |b|/2 | depending on the signs, so the linear part is exactly
+    0 or -2 min(|a|, |b|)/2.
+    """
+    if channel == "ph":
+        x, cancel = 0.5 * (a - b), (a * b >= 0)
+    elif channel == "pp":
+        x, cancel = 0.5 * (a + b), (a * b < 0)
+    else:
+        raise ValueError(channel)
+    lin = np.where(cancel, -np.minimum(np.abs(a), np.abs(b)), 0.0)
+    return x, lin
 
 
 def loop(eps1, eps2, T, channel: str):
     """L^X(eps1, eps2; T) for X in {'ph', 'pp'}."""
     a = np.asarray(eps1, dtype=float) / T
     b = np.asarray(eps2, dtype=float) / T
-    if channel == "ph":
-        x, sign = 0.5 * (a - b), -1.0
-    elif channel == "pp":
-        x, sign = 0.5 * (a + b), +1.0
-    else:
-        raise ValueError(channel)
-    # log of sinhc(x) sech(a/2) sech(b/2); the linear parts |x| - |a|/2 - |b|/2
-    # are combined first so that no large terms cancel at |a|, |b| >> 1
-    lin = np.abs(x) - 0.5 * np.abs(a) - 0.5 * np.abs(b)
+    x, lin = _x_and_linear_part(a, b, channel)
+    sign = -1.0 if channel == "ph" else 1.0
+    # log of sinhc(x) sech(a/2) sech(b/2) with the linear parts taken exactly
     ln = lin + _ln_sinhc_tail(x) - _ln_cosh_tail(0.5 * a) - _ln_cosh_tail(0.5 * b)
     return sign * np.exp(ln) / (4.0 * T)
 
 
 def loop_dot(eps1, eps2, T, channel: str):
-    """dL^X/dT at fixed energies."""
+    """dL^X/dT at fixed energies: (L/T) [(a/2) tanh(a/2) + (b/2) tanh(b/2) - x coth x].
+
+    With A = |a|/2, B = |b|/2, X = |x| (each term is even), y tanh y =
+    y - 2y/(e^{2y}+1) and x coth x = x + 2x/(e^{2x}-1), so the bracket is
+    (A + B - X) - 2A/(e^{2A}+1) - 2B/(e^{2B}+1) - 2X/expm1(2X), whose
+    linear part is exact (see _x_and_linear_part) and whose remaining terms
+    share one sign: exponentially small derivatives keep relative accuracy.
+    """
     a = np.asarray(eps1, dtype=float) / T
     b = np.asarray(eps2, dtype=float) / T
-    x = 0.5 * (a - b) if channel == "ph" else 0.5 * (a + b)
-    L = loop(eps1, eps2, T, channel)
-    bracket = 0.5 * a * np.tanh(0.5 * a) + 0.5 * b * np.tanh(0.5 * b) - _x_coth_x(x)
-    return L * bracket / T
+    x, lin = _x_and_linear_part(a, b, channel)
+    A, B, X = 0.5 * np.abs(a), 0.5 * np.abs(b), np.abs(x)
+    with np.errstate(over="ignore"):
+        tail_a = 2.0 * A / (np.exp(2.0 * A) + 1.0)
+        tail_b = 2.0 * B / (np.exp(2.0 * B) + 1.0)
+    small = X < 1e-8
+    Xs = np.where(small, 1.0, X)
+    with np.errstate(over="ignore"):
+        tail_x = np.where(small, 1.0 - X, 2.0 * Xs / np.expm1(2.0 * Xs))
+    bracket = -lin - tail_a - tail_b - tail_x
+    return loop(eps1, eps2, T, channel) * bracket / T
 
 
 def bubbles(point, T: float, which: str = "dot", ff: FormFactors | None = None,

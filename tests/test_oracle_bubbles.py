@@ -135,3 +135,30 @@ def test_bubble_symmetric_parity_blocks_and_c4v(shells):
         j = int(np.flatnonzero(np.isclose(qx, -qy[i]) & np.isclose(qy, qx[i]))[0])
         for c in range(2):
             np.testing.assert_allclose(d[c, j], CS @ d[c, i] @ CS.T, atol=1e-14 * np.abs(d).max())
+
+
+def _fermi_form_dot(e1, e2, T, ch):
+    """d/dT of (n_F(e1) - n_F(e2))/(e1 - e2) or (1 - n_F(e1) - n_F(e2))/(e1 + e2).
+
+    600 digits: n_F = 1 - O(e^{-|eps|/T}) must stay distinguishable from 1."""
+    mp.mp.dps = 600
+    a, b = mp.mpf(e1), mp.mpf(e2)
+    nF = lambda e, t: 1 / (mp.exp(e / t) + 1)
+    if ch == "ph":
+        f = lambda t: (nF(a, t) - nF(b, t)) / (a - b)
+    else:
+        f = lambda t: (1 - nF(a, t) - nF(b, t)) / (a + b)
+    r = float(mp.diff(f, mp.mpf(T)))
+    mp.mp.dps = 15
+    return r
+
+
+@pytest.mark.parametrize("ch", ["ph", "pp"])
+@pytest.mark.parametrize("e1,e2,T", [(0.05, 0.06, 1e-3), (-0.4, -0.3, 1e-3), (0.2, -0.35, 1e-3),
+                                     (3.0, 2.5, 0.01), (-6.0, 5.0, 0.02), (0.12, -0.11, 2e-3)])
+def test_loop_dot_relative_accuracy_in_tails(e1, e2, T, ch):
+    """Far from the Fermi surface dL/dT is exponentially small; it must keep its
+    relative accuracy there (no cancellation between O(|eps|/T) terms)."""
+    ref = _fermi_form_dot(e1, e2, T, ch)
+    val = float(loop_dot(e1, e2, T, ch))
+    assert abs(val - ref) <= 1e-11 * abs(ref), (val, ref)
