@@ -1,0 +1,237 @@
+"""ctypes binding of the C ABI in include/tufrg.h (marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CHANNELS = ("P", "C", "D")
+IRREPS = ("A1", "B1", "B2", "A2", "E")
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONFINITE", -5: "EUNSUPPORTED"}
+FLOW_STATUS = {1: "diverged", 2: "reached_tmin", 3: "nonfinite"}
+SCHEMES = {"rk4": 0, "dopri5": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+NO_CROSS = 1
+
+# every entry point declared in include/tufrg.h
+EXPORTS = ("tufrg_init", "tufrg_layout", "tufrg_bubbles", "tufrg_project", "tufrg_rhs",
+           "tufrg_flow", "tufrg_sync", "tufrg_flop_count", "tufrg_mu_from_filling",
+           "tufrg_free", "tufrg_last_error")
+
+
+class TufrgError(RuntimeError):
+    pass
+
+
+class _Point(C.Structure):
+    _fields_ = [("t", C.c_double), ("tp", C.c_double), ("mu", C.c_double), ("U", C.c_double),
+                ("Lq", C.c_int32), ("Lk", C.c_int32), ("shells", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class _Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("flags", C.c_uint32)]
+
+
+class _FlowOpts(C.Structure):
+    _fields_ = [("T0", C.c_double), ("Tmin", C.c_double), ("Xmax", C.c_double),
+                ("scheme", C.c_int32), ("nsteps", C.c_int32), ("rtol", C.c_double),
+                ("atol", C.c_double), ("h0", C.c_double), ("max_steps", C.c_int32),
+                ("use_graph", C.c_int32)]
+
+
+class _FlowResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("channel", C.c_int32), ("q_index", C.c_int32),
+                ("irrep", C.c_int32), ("Tc", C.c_double), ("max_abs_X", C.c_double),
+                ("n_rhs", C.c_int64), ("n_steps", C.c_int64)]
+
+
+_LIB = None
+
+
+def library_path() -> str:
+    return os.path.join(HERE, "_lib", "libtufrg.so")
+
+
+def load_library():
+    """Load the built native library; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise TufrgError(f"native library missing: {path} (run python -m paper_1604_06296_amd.build)")
+    lib = C.CDLL(path)
+    vp, dp, i32, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int64
+    lib.tufrg_init.argtypes = [C.POINTER(_Point), i32, C.POINTER(_Options), vp, C.POINTER(vp)]
+    lib.tufrg_layout.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
+                                 C.POINTER(i64)]
+    lib.tufrg_bubbles.argtypes = [vp, dp, vp]
+    lib.tufrg_project.argtypes = [vp, vp, vp]
+    lib.tufrg_rhs.argtypes = [vp, dp, vp, vp]
+    lib.tufrg_flow.argtypes = [vp, C.POINTER(_FlowOpts), vp, C.POINTER(_FlowResult)]
+    lib.tufrg_sync.argtypes = [vp]
+    lib.tufrg_flop_count.argtypes = [vp, dp]
+    lib.tufrg_mu_from_filling.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, i32, dp]
+    lib.tufrg_free.argtypes = [vp]
+    lib.tufrg_free.restype = None
+    lib.tufrg_last_error.argtypes = [vp]
+    lib.tufrg_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("tufrg_free", "tufrg_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _LIB = lib
+    return lib
+
+
+def _check(lib, ctx, status):
+    if status != 0:
+        msg = lib.tufrg_last_error(ctx).decode()
+        raise TufrgError(f"{STATUS.get(status, status)}: {msg}")
+
+
+def mu_from_filling(t: float, tp: float, n: float, T: float, L: int = 1024) -> float:
+    """Chemical potential for filling n (native host routine)."""
+    lib = load_library()
+    out = C.c_double()
+    _check(lib, None, lib.tufrg_mu_from_filling(t, tp, n, T, L, C.byref(out)))
+    return out.value
+
+
+@dataclasses.dataclass
+class FlowOptions:
+    T0: float = 10.0
+    Tmin: float = 0.01
+    Xmax: float = 20.0
+    scheme: str = "rk4"
+    nsteps: int = 200
+    rtol: float = 1e-7
+    atol: float = 1e-9
+    h0: float = 0.0
+    max_steps: int = 0
+    use_graph: bool = False
+
+
+@dataclasses.dataclass
+class FlowResult:
+    status: str
+    Tc: Optional[float]
+    channel: Optional[str]
+    q_index: Optional[int]
+    irrep: Optional[str]
+    max_abs_X: float
+    n_rhs: int
+    n_steps: int
+
+
+class Context:
+    """A set of model points with their device tables and workspace.
+
+    points: objects with attributes t, tp, mu, U, Lq, Lk, shells.
+    Arrays are torch float64 CUDA tensors laid out [channels][S]
+    (channel-major, then point blocks [Nq][Nff][Nff]).
+    """
+
+    def __init__(self, points: Sequence, precision: str = "fp64", no_cross: bool = False,
+                 stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise TufrgError("a GPU is required (torch.cuda.is_available() is False)")
+        self._torch = torch
+        self.lib = load_library()
+        n = len(points)
+        arr = (_Point * n)()
+        for i, p in enumerate(points):
+            if p.mu is None:
+                raise TufrgError("point has no mu; solve mu_from_filling first")
+            arr[i] = _Point(p.t, p.tp, p.mu, p.U, p.Lq, p.Lk, p.shells, 0)
+        opt = _Options(PRECISIONS[precision], NO_CROSS if no_cross else 0)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        handle = C.c_void_p()
+        _check(self.lib, None, self.lib.tufrg_init(arr, n, C.byref(opt),
+                                                    C.c_void_p(self.stream.cuda_stream),
+                                                    C.byref(handle)))
+        self.ctx = handle
+        self.npts = n
+        self.layouts = []
+        for i in range(n):
+            off, nq, nff, tot = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int64()
+            _check(self.lib, self.ctx, self.lib.tufrg_layout(self.ctx, i, C.byref(off), C.byref(nq),
+                                                             C.byref(nff), C.byref(tot)))
+            self.layouts.append((off.value, nq.value, nff.value))
+            self.S = tot.value
+
+    # ---------------------------------------------------------------- helpers
+    def _T(self, T) -> "C.Array":
+        Ts = [float(T)] * self.npts if not hasattr(T, "__len__") else [float(x) for x in T]
+        return (C.c_double * self.npts)(*Ts)
+
+    def _dev(self, x, nch: int):
+        t = self._torch
+        if not (isinstance(x, t.Tensor) and x.is_cuda and x.dtype == t.float64 and x.is_contiguous()):
+            raise TufrgError("expected a contiguous float64 CUDA tensor")
+        if x.numel() != nch * self.S:
+            raise TufrgError(f"expected {nch} x {self.S} elements, got {x.numel()}")
+        return C.c_void_p(x.data_ptr())
+
+    def empty(self, nch: int):
+        return self._torch.empty((nch, self.S), dtype=self._torch.float64, device="cuda")
+
+    def view(self, arr, point: int = 0):
+        """[nch][S] array -> [nch][Nq][Nff][Nff] view of one point."""
+        off, nq, nff = self.layouts[point]
+        return arr.view(arr.shape[0], -1)[:, off:off + nq * nff * nff].reshape(arr.shape[0], nq, nff, nff)
+
+    # ------------------------------------------------------------------ calls
+    def bubbles(self, T, out=None):
+        out = self.empty(2) if out is None else out
+        _check(self.lib, self.ctx, self.lib.tufrg_bubbles(self.ctx, self._T(T), self._dev(out, 2)))
+        return out
+
+    def project(self, X, out=None):
+        out = self.empty(3) if out is None else out
+        _check(self.lib, self.ctx, self.lib.tufrg_project(self.ctx, self._dev(X, 3), self._dev(out, 3)))
+        return out
+
+    def rhs(self, T, X, out=None):
+        out = self.empty(3) if out is None else out
+        _check(self.lib, self.ctx, self.lib.tufrg_rhs(self.ctx, self._T(T), self._dev(X, 3),
+                                                      self._dev(out, 3)))
+        return out
+
+    def sync(self):
+        _check(self.lib, self.ctx, self.lib.tufrg_sync(self.ctx))
+
+    def flop_count(self):
+        out = (C.c_double * 3)()
+        _check(self.lib, self.ctx, self.lib.tufrg_flop_count(self.ctx, out))
+        return {"loops": out[0], "projections": out[1], "products": out[2]}
+
+    def flow(self, X, opts: FlowOptions, raise_nonfinite: bool = False) -> List[FlowResult]:
+        o = _FlowOpts(opts.T0, opts.Tmin, opts.Xmax, SCHEMES[opts.scheme], opts.nsteps, opts.rtol,
+                      opts.atol, opts.h0, opts.max_steps, int(opts.use_graph))
+        res = (_FlowResult * self.npts)()
+        st = self.lib.tufrg_flow(self.ctx, C.byref(o), self._dev(X, 3), res)
+        if st != -4 or raise_nonfinite:
+            _check(self.lib, self.ctx, st)
+        out = []
+        for r in res:
+            div = r.status == 1
+            out.append(FlowResult(FLOW_STATUS.get(r.status, str(r.status)), r.Tc if div else None,
+                                  CHANNELS[r.channel] if div else None, r.q_index if div else None,
+                                  IRREPS[r.irrep] if div else None, r.max_abs_X, r.n_rhs, r.n_steps))
+        return out
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.tufrg_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,528 @@
+// HIP kernels for gfx950 (CDNA4): loops, projections, products and ODE helpers
+// of the TUfRG flow right-hand side.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "loop_math.h"
+#include "tufrg_internal.h"
+
+namespace tufrg {
+namespace {
+
+constexpr int kBubThreads = 512;   // upper bound of the loop kernel's block size
+
+// ------------------------------------------------------------------ loops
+// Step ii.) of Sec. 2.4, eqn. chis, at one temperature.  One block per
+// transfer momentum q.  Threads own one px column of the fine grid and a
+// chunk of py rows (py in [0, Lk/2] only: the loop weight is even in p, the
+// self-paired rows py = 0, Lk/2 carry weight 1 and the others weight 2).
+// Each thread accumulates row sums of the loop derivative against cos(n py)
+// and sin(n py), n <= SMAX; the block then contracts the rows against
+// cos(px Sx), sin(px Sx) into ghat(q, S) = (1/Nk) sum_p L'(p) cos(p.S) for
+// the half set of harmonics S in bonds + bonds, and finally
+// chi'_mn(q) = sum_S Ebub_{mn,S} ghat(q, S).
+struct DevRcp {
+  __device__ double operator()(double x) const {
+    double r = __builtin_amdgcn_rcp(x);       // hardware estimate, refined by Newton steps
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+  }
+};
+
+template <int SMAX>
+__global__ void __launch_bounds__(kBubThreads)
+k_loops_f64(DevTables d, double T, int nchunk, double* __restrict__ dchi, int64_t S) {
+  constexpr int NH = 2 * SMAX + 1;     // row sums per channel: cos n=0..SMAX, sin n=1..SMAX
+  const int q = blockIdx.x;
+  const int lk = d.lk;
+  const int rows = lk / 2 + 1;
+  const int lq = d.lq;
+  const int ix = q / lq, iy = q % lq;
+  const double qx = 2.0 * M_PI * (double)(ix - lq / 2) / (double)lq;
+  const double qy = 2.0 * M_PI * (double)(iy - lq / 2) / (double)lq;
+  const double inv2T = 0.5 / T;
+
+  extern __shared__ double smem[];
+  double* y1 = smem;                        // cos(py + qy/2)        [rows]
+  double* y2 = y1 + rows;                   // cos(py - qy/2)        [rows]
+  double* pyt = y2 + rows;                  // weighted py harmonics [rows][NH]
+  double* rs = pyt + rows * NH;             // row sums              [lk][2][NH]
+  double* gh = rs + lk * 2 * NH;            // harmonic partials     [nseg][2 nsh]
+
+  for (int j = threadIdx.x; j < rows; j += blockDim.x) {
+    const double py = 2.0 * M_PI * (double)j / (double)lk;
+    y1[j] = cos(py + 0.5 * qy);
+    y2[j] = cos(py - 0.5 * qy);
+  }
+  for (int j = threadIdx.x; j < rows * NH; j += blockDim.x) pyt[j] = d.pytab[j];
+  for (int j = threadIdx.x; j < lk * 2 * NH; j += blockDim.x) rs[j] = 0.0;
+  __syncthreads();
+
+  // thread t owns column px = t % lk and row chunk c = t / lk
+  const int t = threadIdx.x;
+  const bool active = t < lk * nchunk;
+  const int px = t % lk, c = t / lk;
+  double acc[2][NH];
+#pragma unroll
+  for (int n = 0; n < NH; ++n) acc[0][n] = acc[1][n] = 0.0;
+  if (active) {
+    const double pxa = 2.0 * M_PI * (double)px / (double)lk;
+    const double cx1 = cos(pxa + 0.5 * qx);
+    const double cx2 = cos(pxa - 0.5 * qx);
+    // alpha = eps(p + q/2)/(2T) = A1 + B1 cos(py + qy/2); beta likewise
+    const double A1 = (-2.0 * d.t * cx1 - d.mu) * inv2T;
+    const double B1 = (-2.0 * d.t - 4.0 * d.tp * cx1) * inv2T;
+    const double A2 = (-2.0 * d.t * cx2 - d.mu) * inv2T;
+    const double B2 = (-2.0 * d.t - 4.0 * d.tp * cx2) * inv2T;
+    const int r0 = (int)((int64_t)rows * c / nchunk);
+    const int r1 = (int)((int64_t)rows * (c + 1) / nchunk);
+    for (int r = r0; r < r1; ++r) {
+      const double al = fma(B1, y1[r], A1);
+      const double be = fma(B2, y2[r], A2);
+      double dph, dpp;
+      loop_dot_pair_t(al, be, dph, dpp, DevRcp());
+      const double* w = pyt + r * NH;
+#pragma unroll
+      for (int n = 0; n < NH; ++n) {
+        acc[0][n] = fma(dpp, w[n], acc[0][n]);
+        acc[1][n] = fma(dph, w[n], acc[1][n]);
+      }
+    }
+  }
+  // add the chunks into the row sums one after another (fixed order)
+  for (int cc = 0; cc < nchunk; ++cc) {
+    if (active && c == cc) {
+      double* dst = rs + px * 2 * NH;
+#pragma unroll
+      for (int n = 0; n < NH; ++n) {
+        dst[n] += acc[0][n];
+        dst[NH + n] += acc[1][n];
+      }
+    }
+    __syncthreads();
+  }
+
+  // contraction over px into the half-set harmonics, split into segments
+  const int nout = 2 * d.nsh;
+  int nseg = (int)blockDim.x / nout;
+  if (nseg < 1) nseg = 1;
+  for (int w = threadIdx.x; w < nout * nseg; w += blockDim.x) {
+    const int o = w % nout, seg = w / nout;
+    const int ch = o / d.nsh, j = o % d.nsh;
+    const int sx = d.hx[j], sy = d.hy[j];          // sx >= 0
+    const int ay = sy < 0 ? -sy : sy;
+    const double sg = sy < 0 ? -1.0 : 1.0;
+    double g = 0.0;
+    for (int x = seg; x < lk; x += nseg) {
+      const double* r = rs + x * 2 * NH + ch * NH;
+      // cos(px sx + py sy) = cos(px sx) cos(py |sy|) - sin(px sx) sgn(sy) sin(py |sy|)
+      double v = d.pxtab[x * NH + sx] * r[ay];
+      if (sx > 0 && ay > 0) v = fma(-sg * d.pxtab[x * NH + SMAX + sx], r[SMAX + ay], v);
+      g += v;
+    }
+    gh[seg * nout + o] = g;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+    double g = 0.0;
+    for (int s = 0; s < nseg; ++s) g += gh[s * nout + o];
+    gh[o] = g;
+  }
+  __syncthreads();
+  // chi'_mn = sum_j Ebub ghat; pp carries -1/(4 T^2 Nk), ph +1/(4 T^2 Nk)
+  const int nff2 = d.nff * d.nff;
+  const double base = 1.0 / (4.0 * T * T * (double)lk * (double)lk);
+  for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
+    const int ch = w / nff2, mn = w % nff2;
+    const double* e = d.ebub + (size_t)mn * d.nsh;
+    const double* g = gh + ch * d.nsh;
+    double v = 0.0;
+    for (int j = 0; j < d.nsh; ++j) v = fma(e[j], g[j], v);
+    dchi[(size_t)ch * S + (size_t)q * nff2 + mn] = (ch == 0 ? -base : base) * v;
+  }
+}
+
+// ------------------------------------------------------- projections
+// GEMM1 of the projections: the partial Fourier transform over the transfer
+// grid at the half-integer frequencies S/2,
+//   xt[ch][k][mn] = (1/Nq) sum_u E[u][k] X[ch][u][mn],
+// E = (cos(u.S'/2) | sin(u.S'/2)).  Tiles of 32 (k) x 64 (mn), 16 u per stage.
+__global__ void __launch_bounds__(256)
+k_dft_fwd(const double* __restrict__ eph, int nq, int ncol, const double* __restrict__ X,
+          int64_t S, int nff2, double* __restrict__ xt) {
+  constexpr int BM = 32, BN = 64, BK = 16;
+  __shared__ double As[BK][BM];
+  __shared__ double Bs[BK][BN];
+  const int ch = blockIdx.z;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const double* Xc = X + (size_t)ch * S;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;   // 16 x 16 threads, 2 x 4 outputs each
+  double acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int k0 = 0; k0 < nq; k0 += BK) {
+    for (int i = threadIdx.x; i < BK * BM; i += 256) {
+      int kk = i / BM, mm = i % BM;
+      int u = k0 + kk, col = m0 + mm;
+      As[kk][mm] = (u < nq && col < ncol) ? eph[(size_t)u * ncol + col] : 0.0;
+    }
+    for (int i = threadIdx.x; i < BK * BN; i += 256) {
+      int kk = i / BN, nn = i % BN;
+      int u = k0 + kk, mn = n0 + nn;
+      Bs[kk][nn] = (u < nq && mn < nff2) ? Xc[(size_t)u * nff2 + mn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      double a0 = As[kk][ty * 2], a1 = As[kk][ty * 2 + 1];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double b = Bs[kk][tx + 16 * j];
+        acc[0][j] = fma(a0, b, acc[0][j]);
+        acc[1][j] = fma(a1, b, acc[1][j]);
+      }
+    }
+    __syncthreads();
+  }
+  const double inv = 1.0 / (double)nq;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 4; ++j) {
+      int col = m0 + ty * 2 + i, mn = n0 + tx + 16 * j;
+      if (col < ncol && mn < nff2) xt[((size_t)ch * ncol + col) * nff2 + mn] = acc[i][j] * inv;
+    }
+}
+
+// Middle step of the projections, independent of the transfer momentum.
+// One block per (output channel X, half-set harmonic j).  For V = +S'_j and
+// V = -S'_j it gathers the bond-space coefficients
+//   M^X_AB(V) = sum_entries (+-) Yhat^{in}_{R1R2}(W),
+//   Yhat = sum_{m'n'} c_{m'R1} c_{n'R2} xt^{in}_{m'n'}(2W - R1 - R2),
+// changes basis N^X(V) = C M^X(V) C^T, and writes the real coefficients of
+// cos(l.V/2) and sin(l.V/2) for GEMM2.
+__global__ void __launch_bounds__(256)
+k_proj_mid(DevTables d, const double* __restrict__ xt, double* __restrict__ g2) {
+  const int X = blockIdx.y, j = blockIdx.x;
+  const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol;
+  const int nv = 2 * nsh - 1;
+  const int nvl = (j == 0) ? 1 : 2;
+  extern __shared__ double sm[];
+  double* Mre = sm;                  // [2][nff2]
+  double* Mim = Mre + 2 * nff2;
+  for (int w = threadIdx.x; w < nvl * nff2; w += blockDim.x) {
+    const int vi = w / nff2, ab = w % nff2;
+    const int vf = (vi == 0) ? j : (nsh - 1 + j);
+    const size_t row = ((size_t)X * nv + vf) * nff2 + ab;
+    double re = 0.0, im = 0.0;
+    for (int e = d.mrow[row]; e < d.mrow[row + 1]; ++e) {
+      const int32_t pk = d.ment[e];
+      const int in = pk & 3, b1 = (pk >> 2) & 31, b2 = (pk >> 7) & 31, jj = (pk >> 12) & 127;
+      const int conj = (pk >> 19) & 1, neg = (pk >> 20) & 1;
+      const double* xr = xt + ((size_t)in * ncol + jj) * nff2;
+      const double* xi = (jj > 0) ? xt + ((size_t)in * ncol + nsh - 1 + jj) * nff2 : nullptr;
+      const int s1 = d.shell_of[b1], s2 = d.shell_of[b2];
+      double yr = 0.0, yi = 0.0;
+      for (int mp = d.shell_start[s1]; mp < d.shell_start[s1 + 1]; ++mp) {
+        const double c1r = d.cre[mp * nff + b1], c1i = d.cim[mp * nff + b1];
+        for (int np = d.shell_start[s2]; np < d.shell_start[s2 + 1]; ++np) {
+          const double c2r = d.cre[np * nff + b2], c2i = d.cim[np * nff + b2];
+          const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
+          const double ar = xr[mp * nff + np];
+          double ai = xi ? xi[mp * nff + np] : 0.0;
+          if (conj) ai = -ai;
+          yr += wr * ar - wi * ai;
+          yi += wr * ai + wi * ar;
+        }
+      }
+      if (neg) { yr = -yr; yi = -yi; }
+      re += yr;
+      im += yi;
+    }
+    Mre[vi * nff2 + ab] = re;
+    Mim[vi * nff2 + ab] = im;
+  }
+  __syncthreads();
+  for (int mn = threadIdx.x; mn < nff2; mn += blockDim.x) {
+    const int m = mn / nff, n = mn % nff;
+    const int sm_ = d.shell_of[m], sn = d.shell_of[n];
+    double nr[2] = {0.0, 0.0}, ni[2] = {0.0, 0.0};
+    for (int a = d.shell_start[sm_]; a < d.shell_start[sm_ + 1]; ++a) {
+      const double c1r = d.cre[m * nff + a], c1i = d.cim[m * nff + a];
+      for (int b = d.shell_start[sn]; b < d.shell_start[sn + 1]; ++b) {
+        const double c2r = d.cre[n * nff + b], c2i = d.cim[n * nff + b];
+        const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
+        for (int vi = 0; vi < nvl; ++vi) {
+          const double mr = Mre[vi * nff2 + a * nff + b], mi = Mim[vi * nff2 + a * nff + b];
+          nr[vi] += wr * mr - wi * mi;
+          ni[vi] += wr * mi + wi * mr;
+        }
+      }
+    }
+    // Re[e^{-il.V/2} N(V) + e^{+il.V/2} N(-V)] = cos (ReN+ + ReN-) + sin (ImN+ - ImN-)
+    if (j == 0) {
+      g2[((size_t)X * ncol + 0) * nff2 + mn] = nr[0];
+    } else {
+      g2[((size_t)X * ncol + j) * nff2 + mn] = nr[0] + nr[1];
+      g2[((size_t)X * ncol + nsh - 1 + j) * nff2 + mn] = ni[0] - ni[1];
+    }
+  }
+}
+
+// GEMM2 of the projections fused with the assembly of eqns. proj_VP/VC/VD
+// and, in mode 1, with the products of eqns. matmul-P/C/D.
+// One block per LT consecutive transfer momenta l.
+//   K^X_mn(l) = sum_k E[l][k] g2[X][k][mn]
+//   V^P = U e0e0 - P + K^P,  V^C = U e0e0 + C + K^C,  V^D = U e0e0 + D + K^D
+//   dP = V^P chi'pp V^P, dC = -V^C chi'ph V^C,
+//   dD = (W chi'ph W - V^C chi'ph V^C)/2 with W = 2 V^D - V^C (the SU(2) form
+//   of eqn. matmul-D: 2 dD - dC = W chi'ph W).
+constexpr int kLT = 4;   // largest number of momenta per block
+__global__ void __launch_bounds__(256)
+k_proj_out(DevTables d, const double* __restrict__ X, int64_t S, const double* __restrict__ g2,
+           const double* __restrict__ dchi, double* __restrict__ out, int mode, int cross,
+           double scale, int lt) {
+  const int nff = d.nff, nff2 = nff * nff, ncol = d.ncol, nq = d.nq;
+  const int l0 = blockIdx.x * lt;
+  const int nl = min(lt, nq - l0);
+  extern __shared__ double sm[];
+  double* Et = sm;                         // [lt][ncol]
+  double* Vs = Et + lt * ncol;             // [lt][3][nff2]
+  double* T1 = Vs + lt * 3 * nff2;         // [3][nff2]
+  double* T2 = T1 + 3 * nff2;              // [3][nff2]
+  double* Ch = T2 + 3 * nff2;              // [2][nff2]
+  double* Wm = Ch + 2 * nff2;              // [nff2]
+  for (int i = threadIdx.x; i < nl * ncol; i += blockDim.x)
+    Et[i] = d.eph[(size_t)(l0 + i / ncol) * ncol + i % ncol];
+  __syncthreads();
+  for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
+    const int ch = w / nff2, mn = w % nff2;
+    double acc[kLT];
+#pragma unroll
+    for (int i = 0; i < kLT; ++i) acc[i] = 0.0;
+    if (cross) {
+      const double* g = g2 + (size_t)ch * ncol * nff2 + mn;
+      for (int k = 0; k < ncol; ++k) {
+        const double gv = g[(size_t)k * nff2];
+#pragma unroll
+        for (int i = 0; i < kLT; ++i)
+          if (i < nl) acc[i] = fma(Et[i * ncol + k], gv, acc[i]);
+      }
+    }
+    const double bare = (mn == 0) ? d.U : 0.0;
+    const double sgn = (ch == 0) ? -1.0 : 1.0;
+    for (int i = 0; i < nl; ++i) {
+      const double own = X[(size_t)ch * S + (size_t)(l0 + i) * nff2 + mn];
+      Vs[(i * 3 + ch) * nff2 + mn] = bare + sgn * own + acc[i];
+    }
+  }
+  __syncthreads();
+  if (mode == 0) {
+    for (int w = threadIdx.x; w < nl * 3 * nff2; w += blockDim.x) {
+      const int i = w / (3 * nff2), r = w % (3 * nff2), ch = r / nff2, mn = r % nff2;
+      out[(size_t)ch * S + (size_t)(l0 + i) * nff2 + mn] = Vs[w];
+    }
+    return;
+  }
+  for (int i = 0; i < nl; ++i) {
+    const int l = l0 + i;
+    const double* VP = Vs + (i * 3 + 0) * nff2;
+    const double* VC = Vs + (i * 3 + 1) * nff2;
+    const double* VD = Vs + (i * 3 + 2) * nff2;
+    for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x)
+      Ch[w] = dchi[(size_t)(w / nff2) * S + (size_t)l * nff2 + w % nff2];
+    for (int w = threadIdx.x; w < nff2; w += blockDim.x) Wm[w] = 2.0 * VD[w] - VC[w];
+    __syncthreads();
+    // T1 = chi'pp V^P, chi'ph V^C, chi'ph W
+    for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
+      const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
+      const double* A = Ch + (which == 0 ? 0 : nff2) + m * nff;
+      const double* B = which == 0 ? VP : (which == 1 ? VC : Wm);
+      double v = 0.0;
+      for (int k = 0; k < nff; ++k) v = fma(A[k], B[k * nff + n], v);
+      T1[w] = v;
+    }
+    __syncthreads();
+    // T2 = V^P T1p, V^C T1c, W T1w
+    for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
+      const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
+      const double* A = (which == 0 ? VP : (which == 1 ? VC : Wm)) + m * nff;
+      const double* B = T1 + which * nff2;
+      double v = 0.0;
+      for (int k = 0; k < nff; ++k) v = fma(A[k], B[k * nff + n], v);
+      T2[w] = v;
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < nff2; w += blockDim.x) {
+      const size_t o = (size_t)l * nff2 + w;
+      out[o] = scale * T2[w];
+      out[(size_t)S + o] = -scale * T2[nff2 + w];
+      out[2 * (size_t)S + o] = 0.5 * scale * (T2[2 * nff2 + w] - T2[nff2 + w]);
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------- ODE helpers
+struct SlopeSet {
+  const double* k[7];
+  double coef[7];
+};
+
+__global__ void k_axpy_stage(const double* __restrict__ X, SlopeSet ks, int nk, double h,
+                             double* __restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < nk; ++j) acc = fma(ks.coef[j], ks.k[j][i], acc);
+    out[i] = fma(h, acc, X[i]);
+  }
+}
+
+// max |x| as the ordered bit pattern of a non-negative double (NaN sorts
+// above +inf, so a non-finite state is seen)
+__global__ void k_maxabs(const double* __restrict__ X, int64_t n, unsigned long long* word) {
+  __shared__ unsigned long long red[256];
+  unsigned long long m = 0ull;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(fabs(X[i]));
+    if (X[i] != X[i]) b = 0x7ff8000000000000ull;
+    m = b > m ? b : m;
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s && red[threadIdx.x + s] > red[threadIdx.x])
+      red[threadIdx.x] = red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(word, red[0]);
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Partial sums of ((h sum_j e_j k_j) / (atol + rtol max(|y0|,|y5|)))^2 per
+// block, in a fixed tree order (deterministic).
+__global__ void k_errnorm(const double* __restrict__ y0, const double* __restrict__ y5,
+                          SlopeSet ks, int nk, double h, double rtol, double atol, int64_t n,
+                          double* red_out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double e = 0.0;
+    for (int j = 0; j < nk; ++j) e = fma(ks.coef[j], ks.k[j][i], e);
+    e *= h;
+    const double sc = atol + rtol * fmax(fabs(y0[i]), fabs(y5[i]));
+    const double r = e / sc;
+    acc = fma(r, r, acc);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) red_out[blockIdx.x] = red[0];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+static int loop_chunks(int nq, int lk) {
+  // enough waves to cover the chip (256 CUs x 4 SIMDs x ~4 waves) without
+  // making a block larger than kBubThreads or a chunk shorter than 6 rows
+  const int rows = lk / 2 + 1;
+  int nchunk = 1;
+  while (nchunk < 8 && lk * (nchunk + 1) <= kBubThreads && rows / (nchunk + 1) >= 6 &&
+         (int64_t)nq * lk * nchunk < (int64_t)4096 * 64)
+    ++nchunk;
+  return nchunk;
+}
+
+size_t loop_smem_bytes(const DevTables& d, int threads) {
+  const int rows = d.lk / 2 + 1, NH = 2 * d.smax + 1, nout = 2 * d.nsh;
+  int nseg = threads / nout;
+  if (nseg < 1) nseg = 1;
+  return sizeof(double) * ((size_t)2 * rows + (size_t)rows * NH + (size_t)d.lk * 2 * NH +
+                           (size_t)nseg * nout);
+}
+
+void launch_bubbles(const DevTables& d, double T, double* dchi, int64_t S, int precision,
+                    hipStream_t s) {
+  (void)precision;
+  const int nchunk = loop_chunks(d.nq, d.lk);
+  int threads = ((d.lk * nchunk + 63) / 64) * 64;
+  const size_t shmem = loop_smem_bytes(d, threads);
+  switch (d.smax) {
+    case 0:
+      hipLaunchKernelGGL(k_loops_f64<0>, dim3(d.nq), dim3(threads), shmem, s, d, T, nchunk, dchi, S);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_loops_f64<2>, dim3(d.nq), dim3(threads), shmem, s, d, T, nchunk, dchi, S);
+      break;
+    default:
+      hipLaunchKernelGGL(k_loops_f64<4>, dim3(d.nq), dim3(threads), shmem, s, d, T, nchunk, dchi, S);
+      break;
+  }
+}
+
+void launch_project(const DevTables& d, const double* X, int64_t S, double* xt, double* g2,
+                    const double* dchi, double* out, int mode, uint32_t flags, double scale,
+                    hipStream_t s) {
+  const int nff2 = d.nff * d.nff;
+  const int cross = (flags & TUFRG_NO_CROSS) ? 0 : 1;
+  if (cross) {
+    dim3 g1((nff2 + 63) / 64, (d.ncol + 31) / 32, 3);
+    hipLaunchKernelGGL(k_dft_fwd, g1, dim3(256), 0, s, d.eph, d.nq, d.ncol, X, S, nff2, xt);
+    const size_t sm_mid = sizeof(double) * 4 * (size_t)nff2;
+    hipLaunchKernelGGL(k_proj_mid, dim3(d.nsh, 3), dim3(256), sm_mid, s, d, xt, g2);
+  }
+  // momenta per block: as many as fit in 64 KB of LDS (at most kLT)
+  int lt = kLT;
+  auto sm_bytes = [&](int l) {
+    return sizeof(double) * ((size_t)l * d.ncol + (size_t)l * 3 * nff2 + 9 * (size_t)nff2);
+  };
+  while (lt > 1 && sm_bytes(lt) > 65536) --lt;
+  hipLaunchKernelGGL(k_proj_out, dim3((d.nq + lt - 1) / lt), dim3(256), sm_bytes(lt), s, d, X, S,
+                     g2, dchi, out, mode, cross, scale, lt);
+}
+
+void launch_axpy_stage(const double* X, const double* const* k, const double* coef, int nk,
+                       double h, double* out, int64_t n, hipStream_t s) {
+  SlopeSet ks{};
+  for (int j = 0; j < nk; ++j) {
+    ks.k[j] = k[j];
+    ks.coef[j] = coef[j];
+  }
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_axpy_stage, dim3(blocks), dim3(256), 0, s, X, ks, nk, h, out, n);
+}
+
+void launch_maxabs(const double* X, int64_t n, unsigned long long* word, hipStream_t s) {
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_maxabs, dim3(blocks), dim3(256), 0, s, X, n, word);
+}
+
+void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+}
+
+void launch_errnorm(const double* y0, const double* y5, const double* const* k, const double* e,
+                    int nk, double h, double rtol, double atol, int64_t n, double* red, int nred,
+                    hipStream_t s) {
+  SlopeSet ks{};
+  for (int j = 0; j < nk; ++j) {
+    ks.k[j] = k[j];
+    ks.coef[j] = e[j];
+  }
+  hipLaunchKernelGGL(k_errnorm, dim3(nred), dim3(256), 0, s, y0, y5, ks, nk, h, rtol, atol, n,
+                     red);
+}
+
+}  // namespace tufrg

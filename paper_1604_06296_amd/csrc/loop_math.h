@@ -1,0 +1,98 @@
+// Loop derivative of one (q, p) pair in the temperature flow.
+//
+// With alpha = eps(p + q/2)/(2T), beta = eps(p - q/2)/(2T) and
+// h(y) = y sech^2(y), the T-derivatives of the Matsubara-summed loops of
+// eqn. chis are divided differences of h:
+//   dL^ph/dT = +Dh(alpha, beta)  / (4 T^2),
+//   dL^pp/dT = -Dh(alpha, -beta) / (4 T^2),
+//   Dh(a, b) = (h(a) - h(b)) / (a - b).
+// (L^ph = (n_F(eps1) - n_F(eps2))/(eps1 - eps2), L^pp = (1 - n_F(eps1) -
+// n_F(eps2))/(eps1 + eps2); d/dT at fixed energies.)  Close to the
+// diagonal (|a - b| < tau) the divided difference cancels, and the exact
+// identity
+//   Dh(a, b) = sech^2 b - a (tanh a + tanh b) sinhc(a - b) sech a sech b
+// is used instead; it involves only bounded factors, so nothing overflows
+// at |eps/T| ~ 1e4.  Both branches are accurate to a few ulp of max |Dh|.
+//
+// The functions compile for host and device; the reciprocal is a template
+// parameter so that the device can use its hardware reciprocal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+namespace tufrg {
+
+struct IeeeRcp {
+  __host__ __device__ double operator()(double x) const { return 1.0 / x; }
+};
+
+// e^{-x} for x >= 0 by Cody-Waite argument reduction: k = rint(x / ln2),
+// r = k ln2 - x in [-ln2/2, ln2/2] with ln2 split into a high part exact in
+// k * ln2_hi and a low part (fdlibm's split), e^{-x} = 2^{-k} e^{r}, and e^{r}
+// from its degree-13 Taylor polynomial (truncation < 5e-18).
+__host__ __device__ inline double exp_neg(double x) {
+  const double kLn2Hi = 6.93147180369123816490e-01;
+  const double kLn2Lo = 1.90821492927058770002e-10;
+  const double kInvLn2 = 1.44269504088896338700e+00;
+  x = fmin(x, 746.0);
+  const double k = rint(x * kInvLn2);
+  double r = fma(k, kLn2Hi, -x);
+  r = fma(k, kLn2Lo, r);           // r = k ln2 - x in [-ln2/2, ln2/2]
+  double p = 1.0 / 6227020800.0;   // 1/13!
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, -(int)k);        // e^{-x} = 2^{-k} e^{r}
+}
+
+// sinh(d)/d for |d| < 1/4: Taylor series to d^12 (next term < 1e-17)
+__host__ __device__ inline double sinhc_small(double d) {
+  const double z = d * d;
+  double p = 1.0 / 6227020800.0;
+  p = fma(p, z, 1.0 / 39916800.0);
+  p = fma(p, z, 1.0 / 362880.0);
+  p = fma(p, z, 1.0 / 5040.0);
+  p = fma(p, z, 1.0 / 120.0);
+  p = fma(p, z, 1.0 / 6.0);
+  return fma(p, z, 1.0);
+}
+
+constexpr double kNearDiag = 0.25;
+
+// Dh(a, b) and Dh(a, -b) (the ph and pp divided differences)
+template <class Rcp>
+__host__ __device__ inline void loop_dot_pair_t(double a, double b, double& dph, double& dpp,
+                                                Rcp rcp) {
+  const double ea = exp_neg(fabs(a)), eb = exp_neg(fabs(b));   // e^{-|a|}, e^{-|b|}
+  const double qa = ea * ea, qb = eb * eb;
+  const double ra = rcp(1.0 + qa), rb = rcp(1.0 + qb);
+  const double sa = 2.0 * ea * ra, sb = 2.0 * eb * rb;        // sech
+  const double ta = copysign((1.0 - qa) * ra, a);              // tanh
+  const double tb = copysign((1.0 - qb) * rb, b);
+  const double s2b = sb * sb;
+  const double ha = a * sa * sa, hb = b * s2b;                 // h = y sech^2 y
+  const double dm = a - b, dp = a + b;
+  const double sab = a * sa * sb;
+  // far from the diagonal: plain divided differences
+  const double far_ph = (ha - hb) * rcp(dm);
+  const double far_pp = (ha + hb) * rcp(dp);
+  // near the diagonal: bounded identity
+  const double near_ph = fma(-sab * (ta + tb), sinhc_small(dm), s2b);
+  const double near_pp = fma(-sab * (ta - tb), sinhc_small(dp), s2b);
+  dph = fabs(dm) < kNearDiag ? near_ph : far_ph;
+  dpp = fabs(dp) < kNearDiag ? near_pp : far_pp;
+}
+
+}  // namespace tufrg

@@ -1,0 +1,68 @@
+"""C-ABI checks that need no GPU: symbols, host-only routines, argument validation."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import synth
+from oracle.lattice import mu_from_filling
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1604_06296_amd as tf
+    return tf.load_library()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    hdr = open(os.path.join(ROOT, "include", "tufrg.h")).read()
+    declared = set(re.findall(r"\b(tufrg_[a-z_0-9]+)\s*\(", hdr))
+    assert {"tufrg_init", "tufrg_bubbles", "tufrg_project", "tufrg_rhs", "tufrg_flow"} <= declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    import paper_1604_06296_amd.binding as b
+    assert set(b.EXPORTS) == declared
+
+
+def test_native_mu_from_filling_matches_oracle():
+    import paper_1604_06296_amd as tf
+    for (t, tp, n, T, L) in [(1.0, -0.25, 0.85, 1e-3, 256), (1.0, 0.0, 1.0, 0.01, 64),
+                             (1.0, -0.35, 0.72, 0.01, 128)]:
+        assert abs(tf.mu_from_filling(t, tp, n, T, L) - mu_from_filling(n, t, tp, T, L)) < 1e-12
+
+
+def test_native_mu_rejects_bad_filling(lib):
+    out = C.c_double()
+    assert lib.tufrg_mu_from_filling(1.0, 0.0, 2.5, 0.1, 16, C.byref(out)) == -1
+    assert lib.tufrg_mu_from_filling(1.0, 0.0, 0.5, 0.0, 16, C.byref(out)) == -1
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(Lq=7), "Lq"), (dict(Lq=4, shells=1), "Lq"), (dict(Lq=8, shells=3), "Lq"),
+    (dict(Lk=9), "Lk"), (dict(Lk=2), "Lk"), (dict(shells=5), "shells"), (dict(t=0.0), "t must"),
+    (dict(Lk=1024), "Lk"),
+])
+def test_init_validation_without_gpu(lib, kw, msg):
+    """Invalid points are rejected before any device call."""
+    from paper_1604_06296_amd.binding import _Options, _Point
+    p = dict(t=1.0, tp=-0.2, mu=-0.3, U=3.0, Lq=10, Lk=16, shells=1)
+    p.update(kw)
+    arr = (_Point * 1)(_Point(p["t"], p["tp"], p["mu"], p["U"], p["Lq"], p["Lk"], p["shells"], 0))
+    h = C.c_void_p()
+    st = lib.tufrg_init(arr, 1, C.byref(_Options(0, 0)), None, C.byref(h))
+    assert st == -1 and not h.value
+    assert msg in lib.tufrg_last_error(None).decode()
+
+
+def test_workload_definitions():
+    w2 = synth.cfg2()
+    assert w2.points[0].nq == 576 and w2.points[0].nff == 13 and w2.points[0].Lk == 96
+    w3 = synth.cfg3()
+    assert -1.2 <= w3.points[0].mu <= 0.0 and w3.points[0].nff == 21
+    w4 = synth.cfg4()
+    assert len(w4.points) == 64
+    assert {p.Lk for p in w4.points} == {4 * p.Lq for p in w4.points}
+    assert all(16 <= p.Lq <= 40 and p.Lq % 2 == 0 for p in w4.points)

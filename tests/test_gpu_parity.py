@@ -1,0 +1,220 @@
+"""GPU parity: every C-ABI step against the FP64 CPU oracle on seeded inputs.
+
+Tolerance (FP64): max |gpu - oracle| <= 1e-10 * max |oracle| per channel
+(normwise; symmetry zeros make elementwise ratios meaningless).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bubbles as obub
+from oracle import flow as oflow
+from oracle import projections as oproj
+from oracle import rhs as orhs
+from oracle.lattice import FormFactors, mu_from_filling
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def tf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1604_06296_amd as tf
+    tf.load_library()
+    return tf
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _to_dev(ctx, arrs, point=0, nch=3):
+    """Host [nch][nq][nff][nff] for one point -> [nch][S] device array."""
+    torch = _torch()
+    out = torch.zeros((nch, ctx.S), dtype=torch.float64, device="cuda")
+    ctx.view(out, point).copy_(torch.from_numpy(np.ascontiguousarray(arrs)))
+    return out
+
+
+def _host(ctx, dev, point=0):
+    return ctx.view(dev, point).cpu().numpy()
+
+
+def _assert_normwise(got, ref, tol=TOL, what=""):
+    for c in range(ref.shape[0]):
+        scale = np.abs(ref[c]).max()
+        err = np.abs(got[c] - ref[c]).max()
+        assert err <= tol * max(scale, 1e-300), f"{what} channel {c}: err {err:.3e} scale {scale:.3e}"
+
+
+POINTS = [
+    # (shells, Lq, Lk) spanning N_ff = 1..21, ragged Lq and Lk, Lk not a multiple of 4
+    (0, 6, 12), (1, 6, 20), (1, 8, 34), (2, 10, 16), (3, 10, 24), (4, 10, 22), (4, 14, 40),
+]
+
+
+def _pt(shells, Lq, Lk, tp=-0.27, mu=-0.61, U=2.7):
+    return synth.Point(t=1.0, tp=tp, U=U, Lq=Lq, Lk=Lk, shells=shells, mu=mu)
+
+
+@pytest.mark.parametrize("shells,Lq,Lk", POINTS)
+def test_bubbles_small(tf, shells, Lq, Lk):
+    pt = _pt(shells, Lq, Lk)
+    print(f"[bubbles] shells={shells} Lq={Lq} Lk={Lk}", flush=True)
+    ctx = tf.Context([pt])
+    for T in (7.3, 0.21, 0.013, 1.1e-3):
+        ref = obub.bubbles(pt, T, "dot")
+        got = _host(ctx, ctx.bubbles(T))
+        _assert_normwise(got, ref, what=f"bubbles T={T}")
+
+
+@pytest.mark.parametrize("shells,Lq,Lk", POINTS)
+def test_project_small(tf, shells, Lq, Lk):
+    pt = _pt(shells, Lq, Lk)
+    print(f"[project] shells={shells} Lq={Lq} Lk={Lk}", flush=True)
+    ff = FormFactors(shells)
+    ctx = tf.Context([pt])
+    X = synth.random_channels(pt.nq, ff.nff, seed=10 + shells, scale=0.7)
+    ref = oproj.project(pt, X, ff)
+    got = _host(ctx, ctx.project(_to_dev(ctx, X)))
+    _assert_normwise(got, ref, what="project")
+    # nonsymmetric input too: no symmetry is assumed anywhere
+    Xn = synth.random_channels(pt.nq, ff.nff, seed=20 + shells, scale=0.7, symmetric=False)
+    _assert_normwise(_host(ctx, ctx.project(_to_dev(ctx, Xn))), oproj.project(pt, Xn, ff),
+                     what="project nonsym")
+
+
+@pytest.mark.parametrize("shells,Lq,Lk", POINTS)
+def test_rhs_small(tf, shells, Lq, Lk):
+    pt = _pt(shells, Lq, Lk)
+    print(f"[rhs] shells={shells} Lq={Lq} Lk={Lk}", flush=True)
+    ff = FormFactors(shells)
+    ctx = tf.Context([pt])
+    X = synth.random_channels(pt.nq, ff.nff, seed=30 + shells, scale=0.5)
+    for T in (0.9, 0.02):
+        ref = orhs.rhs(pt, T, X, ff)
+        got = _host(ctx, ctx.rhs(T, _to_dev(ctx, X)))
+        _assert_normwise(got, ref, what=f"rhs T={T}")
+
+
+def test_no_cross_seam(tf):
+    pt = _pt(2, 8, 16)
+    ff = FormFactors(2)
+    ctx = tf.Context([pt], no_cross=True)
+    X = synth.random_channels(pt.nq, ff.nff, seed=3)
+    _assert_normwise(_host(ctx, ctx.project(_to_dev(ctx, X))), oproj.project(pt, X, ff, no_cross=True))
+    ref = orhs.rhs(pt, 0.3, X, ff, no_cross=True)
+    _assert_normwise(_host(ctx, ctx.rhs(0.3, _to_dev(ctx, X))), ref)
+
+
+def test_multi_point_context(tf):
+    """Uneven points in one context: each block equals its own single-point result."""
+    pts = [_pt(1, 6, 12, tp=-0.1), _pt(3, 12, 20, tp=-0.3, mu=-1.0), _pt(0, 8, 8, U=2.0)]
+    ctx = tf.Context(pts)
+    Ts = [0.5, 0.05, 0.2]
+    Xs = [synth.random_channels(p.nq, FormFactors(p.shells).nff, seed=40 + i) for i, p in enumerate(pts)]
+    torch = _torch()
+    Xd = torch.zeros((3, ctx.S), dtype=torch.float64, device="cuda")
+    for i, X in enumerate(Xs):
+        ctx.view(Xd, i).copy_(torch.from_numpy(X))
+    d = ctx.rhs(Ts, Xd)
+    b = ctx.bubbles(Ts)
+    for i, p in enumerate(pts):
+        ff = FormFactors(p.shells)
+        _assert_normwise(ctx.view(d, i).cpu().numpy(), orhs.rhs(p, Ts[i], Xs[i], ff), what=f"pt{i}")
+        _assert_normwise(ctx.view(b, i).cpu().numpy(), obub.bubbles(p, Ts[i], "dot", ff))
+
+
+def test_cfg1_full(tf):
+    w = synth.cfg1()
+    pt = w.points[0]
+    ff = FormFactors(pt.shells)
+    ctx = tf.Context([pt])
+    X = synth.random_channels(pt.nq, ff.nff, seed=1, scale=2.0)
+    for T in (10.0, 0.3, 0.01):
+        _assert_normwise(_host(ctx, ctx.bubbles(T)), obub.bubbles(pt, T, "dot", ff))
+        _assert_normwise(_host(ctx, ctx.rhs(T, _to_dev(ctx, X))), orhs.rhs(pt, T, X, ff))
+    _assert_normwise(_host(ctx, ctx.project(_to_dev(ctx, X))), oproj.project(pt, X, ff))
+
+
+def test_cfg2_full(tf):
+    """The benchmark workload (N_ff = 13, 24x24 transfer grid, 96x96 fine grid), in full."""
+    w = synth.cfg2()
+    pt = w.points[0]
+    pt.mu = tf.mu_from_filling(pt.t, pt.tp, pt.filling, pt.mu_T, pt.mu_L)
+    assert abs(pt.mu - mu_from_filling(pt.filling, pt.t, pt.tp, pt.mu_T, pt.mu_L)) < 1e-12
+    ff = FormFactors(pt.shells)
+    ctx = tf.Context([pt])
+    X = synth.random_channels(pt.nq, ff.nff, seed=2, scale=1.5)
+    T = 0.037
+    ref_rhs, ref_V, ref_chi = orhs.rhs(pt, T, X, ff, return_parts=True)
+    Xd = _to_dev(ctx, X)
+    _assert_normwise(_host(ctx, ctx.bubbles(T)), ref_chi, what="cfg2 bubbles")
+    _assert_normwise(_host(ctx, ctx.project(Xd)), ref_V, what="cfg2 project")
+    _assert_normwise(_host(ctx, ctx.rhs(T, Xd)), ref_rhs, what="cfg2 rhs")
+
+
+def test_determinism(tf):
+    pt = _pt(3, 12, 32)
+    ff = FormFactors(3)
+    ctx = tf.Context([pt])
+    X = _to_dev(ctx, synth.random_channels(pt.nq, ff.nff, seed=8))
+    a = ctx.rhs(0.07, X).cpu().numpy()
+    b = ctx.rhs(0.07, X).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_flow_cfg1_rk4(tf):
+    """cfg1 flow: same critical scale (1%) and leading instability as the oracle."""
+    w = synth.cfg1()
+    pt = w.points[0]
+    ctx = tf.Context([pt])
+    X = ctx.empty(3).zero_()
+    r = ctx.flow(X, tf.FlowOptions(T0=w.T0, Tmin=w.Tmin, Xmax=w.Xmax, scheme="rk4", nsteps=w.nsteps))[0]
+    ref = oflow.flow_rk4(pt, w.T0, w.Tmin, w.nsteps, w.Xmax)
+    print("gpu", r, "oracle", ref.Tc, ref.channel, ref.q_index, ref.irrep, flush=True)
+    assert r.status == "diverged" and ref.status == oflow.STATUS_DIVERGED
+    assert abs(r.Tc / ref.Tc - 1) < 1e-6        # identical algorithm: far inside 1%
+    assert (r.channel, r.q_index, r.irrep) == (ref.channel, ref.q_index, ref.irrep)
+    assert r.n_steps == ref.n_steps and r.n_rhs == ref.n_rhs
+    # the stopped state itself
+    _assert_normwise(_host(ctx, X), ref.X, tol=1e-8, what="X at stop")
+
+
+def test_flow_dopri5_small(tf):
+    pt = _pt(1, 6, 16, tp=0.0, mu=0.0, U=3.0)
+    ctx = tf.Context([pt])
+    X = ctx.empty(3).zero_()
+    r = ctx.flow(X, tf.FlowOptions(T0=10.0, Tmin=0.01, Xmax=20.0, scheme="dopri5", rtol=1e-7,
+                                   atol=1e-9))[0]
+    ref = oflow.flow_dopri5(pt, 10.0, 0.01, 20.0, rtol=1e-7, atol=1e-9)
+    assert r.status == "diverged" and ref.status == oflow.STATUS_DIVERGED
+    assert abs(r.Tc / ref.Tc - 1) < 1e-3
+    assert (r.channel, r.q_index, r.irrep) == (ref.channel, ref.q_index, ref.irrep)
+
+
+def test_flow_no_cross_is_rpa(tf):
+    pt = _pt(0, 6, 16, tp=-0.1, mu=-0.2, U=2.0)
+    ctx = tf.Context([pt], no_cross=True)
+    X = ctx.empty(3).zero_()
+    r = ctx.flow(X, tf.FlowOptions(T0=10.0, Tmin=0.3, Xmax=1e9, scheme="rk4", nsteps=200))[0]
+    assert r.status == "reached_tmin"
+    b0, b1 = obub.bubbles(pt, 10.0, "value"), obub.bubbles(pt, 0.3, "value")
+    dph = b1[1, :, 0, 0] - b0[1, :, 0, 0]
+    C = _host(ctx, X)[1, :, 0, 0]
+    np.testing.assert_allclose(2.0 + C, 2.0 / (1 + 2.0 * dph), rtol=2e-8)
+
+
+def test_flow_nonfinite_detected(tf):
+    pt = _pt(0, 6, 8)
+    ctx = tf.Context([pt])
+    Xh = np.zeros((3, 36, 1, 1))
+    Xh[2, 5, 0, 0] = np.nan
+    X = _to_dev(ctx, Xh)
+    r = ctx.flow(X, tf.FlowOptions(T0=10.0, Tmin=0.1, Xmax=20.0, nsteps=5))[0]
+    assert r.status == "nonfinite" and r.n_steps == 1
