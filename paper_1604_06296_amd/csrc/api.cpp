@@ -57,13 +57,22 @@ tufrg_status dalloc(tufrg_ctx* ctx, size_t bytes, void** out) {
     if (s_ != TUFRG_OK) return s_;        \
   } while (0)
 
-// One right-hand side of point p: out = scale * dX/dT (mode 1) at temperature T.
+// One right-hand side of point p: out = scale * dX/dT at temperature T.
+// The loops depend on T only and run on the side stream, concurrently with
+// the X-dependent front end of the projections on the main stream; the back
+// end (inverse transform, V, products) joins both.
 void rhs_point(tufrg_ctx* ctx, int p, double T, const double* X, double* out, double scale) {
   const DevTables& d = ctx->dev[p];
   const int64_t off = ctx->off[p];
-  launch_bubbles(d, T, ctx->ws.dchi + off, ctx->S, ctx->opt.precision, ctx->stream);
-  launch_project(d, X + off, ctx->S, ctx->ws.xt, ctx->ws.g2, ctx->ws.dchi + off, out + off, 1,
-                 ctx->opt.flags, scale, ctx->stream);
+  hipEventRecord(ctx->ev_fork, ctx->stream);
+  hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+  launch_loops(d, T, ctx->ws.dchi + off, ctx->S, ctx->ws.dpart, false, ctx->side);
+  hipEventRecord(ctx->ev_join, ctx->side);
+  launch_project_front(d, X + off, ctx->S, ctx->ws.xt, ctx->ws.yb, ctx->ws.g2, ctx->opt.flags,
+                       ctx->stream);
+  hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
+  launch_project_back(d, X + off, ctx->S, ctx->ws.g2, ctx->ws.dchi + off, ctx->ws.dpart, out + off,
+                      1, ctx->opt.flags, scale, ctx->stream);
 }
 
 // ----------------------------------------------------- classification
@@ -169,7 +178,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   ctx->host.resize(npts);
   ctx->off.resize(npts);
   int64_t S = 0;
-  size_t max_xt = 8;
+  size_t max_xt = 8, max_yb = 8, max_gp = 8;
   for (int p = 0; p < npts; ++p) {
     std::string e = build_tables(pts[p], ctx->host[p]);
     if (!e.empty()) {
@@ -184,6 +193,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     ctx->off[p] = S;
     S += (int64_t)t.nq * t.nff * t.nff;
     max_xt = std::max(max_xt, (size_t)3 * t.ncol * t.nff * t.nff);
+    max_yb = std::max(max_yb, (size_t)2 * 3 * (2 * t.nsh - 1) * t.nff * t.nff);
   }
   ctx->S = S;
   // device tables (first device call: every argument has been validated)
@@ -210,6 +220,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
         (st = upload(ctx, ss, &d.shell_start)) || (st = upload(ctx, so, &d.shell_of)) ||
         (st = upload(ctx, t.ebub, &d.ebub)) || (st = upload(ctx, t.pxtab, &d.pxtab)) ||
         (st = upload(ctx, t.pytab, &d.pytab)) || (st = upload(ctx, t.eph, &d.eph)) ||
+        (st = upload(ctx, t.cshift, &d.cshift)) ||
         (st = upload(ctx, t.mrow, &d.mrow)) || (st = upload(ctx, t.ment, &d.ment)) ||
         (st = upload(ctx, hx, &d.hx)) || (st = upload(ctx, hy, &d.hy))) {
       std::string m = ctx->err;
@@ -218,11 +229,12 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     }
     int dev_smem = 0;
     hipDeviceGetAttribute(&dev_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
-    size_t need = loop_smem_bytes(d, 512);
-    if (dev_smem > 0 && need > (size_t)dev_smem) {
+    const LoopGeom g = loop_geometry(d);
+    if (dev_smem > 0 && g.smem > (size_t)dev_smem) {
       tufrg_free(ctx);
       return fail(nullptr, TUFRG_EINVAL, "point " + std::to_string(p) + ": fine grid too large");
     }
+    max_gp = std::max(max_gp, (size_t)g.nsplit * 2 * t.nq * t.nff * t.nff);
   }
   // workspace
   Workspace& w = ctx->ws;
@@ -233,6 +245,10 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   w.xt = (double*)v;
   if ((st = dalloc(ctx, sizeof(double) * max_xt, &v))) goto bad;
   w.g2 = (double*)v;
+  if ((st = dalloc(ctx, sizeof(double) * max_yb, &v))) goto bad;
+  w.yb = (double*)v;
+  if ((st = dalloc(ctx, sizeof(double) * max_gp, &v))) goto bad;
+  w.dpart = (double*)v;
   if ((st = dalloc(ctx, sizeof(double) * 2 * (size_t)S, &v))) goto bad;
   w.dchi = (double*)v;
   if ((st = dalloc(ctx, b3, &v))) goto bad;
@@ -247,6 +263,13 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   w.red = (double*)v;
   if ((st = dalloc(ctx, sizeof(unsigned long long) * std::max(npts, 1), &v))) goto bad;
   w.umax = (unsigned long long*)v;
+  // side stream (default priority) and the fork/join events of the right-hand side
+  if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
+    st = fail(ctx, TUFRG_EHIP, "stream or event creation failed");
+    goto bad;
+  }
   if (hipDeviceSynchronize() != hipSuccess) {
     st = fail(ctx, TUFRG_EHIP, "device synchronize failed after init");
     goto bad;
@@ -279,8 +302,8 @@ tufrg_status tufrg_bubbles(tufrg_ctx* ctx, const double* T_host, double* dchi) {
     if (!(T_host[p] > 0.0) || !std::isfinite(T_host[p]))
       return fail(ctx, TUFRG_EINVAL, "T must be finite and > 0");
   for (size_t p = 0; p < ctx->dev.size(); ++p)
-    launch_bubbles(ctx->dev[p], T_host[p], dchi + ctx->off[p], ctx->S, ctx->opt.precision,
-                   ctx->stream);
+    launch_loops(ctx->dev[p], T_host[p], dchi + ctx->off[p], ctx->S, ctx->ws.dpart, true,
+                 ctx->stream);
   HIP_TRY(ctx, hipGetLastError());
   return TUFRG_OK;
 }
@@ -289,9 +312,12 @@ tufrg_status tufrg_project(tufrg_ctx* ctx, const double* X, double* V) {
   if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
   if (!X || !V) return fail(ctx, TUFRG_EINVAL, "NULL argument");
   if (X == V) return fail(ctx, TUFRG_EINVAL, "X and V must not alias");
-  for (size_t p = 0; p < ctx->dev.size(); ++p)
-    launch_project(ctx->dev[p], X + ctx->off[p], ctx->S, ctx->ws.xt, ctx->ws.g2, nullptr,
-                   V + ctx->off[p], 0, ctx->opt.flags, 1.0, ctx->stream);
+  for (size_t p = 0; p < ctx->dev.size(); ++p) {
+    launch_project_front(ctx->dev[p], X + ctx->off[p], ctx->S, ctx->ws.xt, ctx->ws.yb, ctx->ws.g2,
+                         ctx->opt.flags, ctx->stream);
+    launch_project_back(ctx->dev[p], X + ctx->off[p], ctx->S, ctx->ws.g2, nullptr, nullptr,
+                        V + ctx->off[p], 0, ctx->opt.flags, 1.0, ctx->stream);
+  }
   HIP_TRY(ctx, hipGetLastError());
   return TUFRG_OK;
 }
@@ -540,6 +566,12 @@ tufrg_status tufrg_flow(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tuf
 void tufrg_free(tufrg_ctx* ctx) {
   if (!ctx) return;
   if (!ctx->allocations.empty()) hipStreamSynchronize(ctx->stream);
+  if (ctx->side) {
+    hipStreamSynchronize(ctx->side);
+    hipStreamDestroy(ctx->side);
+  }
+  if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
   for (void* p : ctx->allocations) hipFree(p);
   delete ctx;
 }

@@ -34,34 +34,37 @@ struct DevRcp {
 
 template <int SMAX>
 __global__ void __launch_bounds__(kBubThreads)
-k_loops_f64(DevTables d, double T, int nchunk, double* __restrict__ dchi, int64_t S) {
+k_loops_f64(DevTables d, double T, int nsplit, int nchunk, double* __restrict__ dchi, int64_t S,
+            double* __restrict__ dpart) {
   constexpr int NH = 2 * SMAX + 1;     // row sums per channel: cos n=0..SMAX, sin n=1..SMAX
-  const int q = blockIdx.x;
+  const int q = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
   const int lk = d.lk;
   const int rows = lk / 2 + 1;
+  const int R0 = (int)((int64_t)rows * split / nsplit);
+  const int R1 = (int)((int64_t)rows * (split + 1) / nsplit);
+  const int nr = R1 - R0;
   const int lq = d.lq;
   const int ix = q / lq, iy = q % lq;
-  const double qx = 2.0 * M_PI * (double)(ix - lq / 2) / (double)lq;
-  const double qy = 2.0 * M_PI * (double)(iy - lq / 2) / (double)lq;
   const double inv2T = 0.5 / T;
 
   extern __shared__ double smem[];
-  double* y1 = smem;                        // cos(py + qy/2)        [rows]
-  double* y2 = y1 + rows;                   // cos(py - qy/2)        [rows]
-  double* pyt = y2 + rows;                  // weighted py harmonics [rows][NH]
-  double* rs = pyt + rows * NH;             // row sums              [lk][2][NH]
+  double* y1 = smem;                        // cos(py + qy/2)        [nr]
+  double* y2 = y1 + nr;                     // cos(py - qy/2)        [nr]
+  double* pyt = y2 + nr;                    // weighted py harmonics [nr][NH]
+  double* rs = pyt + nr * NH;               // row sums              [lk][2][NH]
   double* gh = rs + lk * 2 * NH;            // harmonic partials     [nseg][2 nsh]
 
-  for (int j = threadIdx.x; j < rows; j += blockDim.x) {
-    const double py = 2.0 * M_PI * (double)j / (double)lk;
-    y1[j] = cos(py + 0.5 * qy);
-    y2[j] = cos(py - 0.5 * qy);
+  // cos(py +- qy/2) for this block's rows from the init-time table [lq][lk][2]
+  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
+    const double* c = d.cshift + ((size_t)iy * lk + (R0 + j)) * 2;
+    y1[j] = c[0];
+    y2[j] = c[1];
   }
-  for (int j = threadIdx.x; j < rows * NH; j += blockDim.x) pyt[j] = d.pytab[j];
+  for (int j = threadIdx.x; j < nr * NH; j += blockDim.x) pyt[j] = d.pytab[R0 * NH + j];
   for (int j = threadIdx.x; j < lk * 2 * NH; j += blockDim.x) rs[j] = 0.0;
   __syncthreads();
 
-  // thread t owns column px = t % lk and row chunk c = t / lk
+  // thread t owns column px = t % lk and the chunk c = t / lk of this block's rows
   const int t = threadIdx.x;
   const bool active = t < lk * nchunk;
   const int px = t % lk, c = t / lk;
@@ -69,16 +72,16 @@ k_loops_f64(DevTables d, double T, int nchunk, double* __restrict__ dchi, int64_
 #pragma unroll
   for (int n = 0; n < NH; ++n) acc[0][n] = acc[1][n] = 0.0;
   if (active) {
-    const double pxa = 2.0 * M_PI * (double)px / (double)lk;
-    const double cx1 = cos(pxa + 0.5 * qx);
-    const double cx2 = cos(pxa - 0.5 * qx);
+    const double cx1 = d.cshift[((size_t)ix * lk + px) * 2];       // cos(px + qx/2)
+    const double cx2 = d.cshift[((size_t)ix * lk + px) * 2 + 1];   // cos(px - qx/2)
     // alpha = eps(p + q/2)/(2T) = A1 + B1 cos(py + qy/2); beta likewise
     const double A1 = (-2.0 * d.t * cx1 - d.mu) * inv2T;
     const double B1 = (-2.0 * d.t - 4.0 * d.tp * cx1) * inv2T;
     const double A2 = (-2.0 * d.t * cx2 - d.mu) * inv2T;
     const double B2 = (-2.0 * d.t - 4.0 * d.tp * cx2) * inv2T;
-    const int r0 = (int)((int64_t)rows * c / nchunk);
-    const int r1 = (int)((int64_t)rows * (c + 1) / nchunk);
+    const int r0 = (int)((int64_t)nr * c / nchunk);
+    const int r1 = (int)((int64_t)nr * (c + 1) / nchunk);
+#pragma unroll 2
     for (int r = r0; r < r1; ++r) {
       const double al = fma(B1, y1[r], A1);
       const double be = fma(B2, y2[r], A2);
@@ -132,7 +135,10 @@ k_loops_f64(DevTables d, double T, int nchunk, double* __restrict__ dchi, int64_
     gh[o] = g;
   }
   __syncthreads();
-  // chi'_mn = sum_j Ebub ghat; pp carries -1/(4 T^2 Nk), ph +1/(4 T^2 Nk)
+  // chi'_mn = sgn / (4 T^2 Nk) sum_j Ebub_{mn,j} ghat_j (pp carries the minus
+  // sign of dL^pp/dT = -Dh/(4T^2)).  With one split the block writes chi'
+  // itself; otherwise its rows' share goes to slice `split` of dpart
+  // [nsplit][2][Nq][nff^2] and the consumer adds the slices in split order.
   const int nff2 = d.nff * d.nff;
   const double base = 1.0 / (4.0 * T * T * (double)lk * (double)lk);
   for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
@@ -141,71 +147,128 @@ k_loops_f64(DevTables d, double T, int nchunk, double* __restrict__ dchi, int64_
     const double* g = gh + ch * d.nsh;
     double v = 0.0;
     for (int j = 0; j < d.nsh; ++j) v = fma(e[j], g[j], v);
-    dchi[(size_t)ch * S + (size_t)q * nff2 + mn] = (ch == 0 ? -base : base) * v;
+    v *= (ch == 0 ? -base : base);
+    if (nsplit == 1)
+      dchi[(size_t)ch * S + (size_t)q * nff2 + mn] = v;
+    else
+      dpart[(((size_t)split * 2 + ch) * d.nq + q) * nff2 + mn] = v;
+  }
+}
+
+// chi' = sum over the split slices in split order (loops with nsplit > 1)
+__global__ void __launch_bounds__(256)
+k_chi_sum(const double* __restrict__ dpart, int nsplit, int nq, int nff2, double* __restrict__ dchi,
+          int64_t S) {
+  const int64_t n = (int64_t)2 * nq * nff2;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int s = 0; s < nsplit; ++s) v += dpart[(size_t)s * n + i];
+    const int64_t ch = i / ((int64_t)nq * nff2), r = i % ((int64_t)nq * nff2);
+    dchi[ch * S + r] = v;
   }
 }
 
 // ------------------------------------------------------- projections
-// GEMM1 of the projections: the partial Fourier transform over the transfer
-// grid at the half-integer frequencies S/2,
-//   xt[ch][k][mn] = (1/Nq) sum_u E[u][k] X[ch][u][mn],
-// E = (cos(u.S'/2) | sin(u.S'/2)).  Tiles of 32 (k) x 64 (mn), 16 u per stage.
-__global__ void __launch_bounds__(256)
+// Forward transform of the projections: the partial Fourier sums over the
+// transfer grid at the half-integer frequencies S/2,
+//   xt[ch][k][mn] = (1/Nq) sum_u E[u][k] X[ch][u][mn],  E = (cos(u.S'/2) | sin(u.S'/2)).
+// A block owns 64 consecutive columns (ch, mn) and KG harmonic columns; its NW
+// waves split the transfer grid and are reduced in LDS in a fixed order.
+template <int KG, int NW>
+__global__ void __launch_bounds__(64 * NW)
 k_dft_fwd(const double* __restrict__ eph, int nq, int ncol, const double* __restrict__ X,
           int64_t S, int nff2, double* __restrict__ xt) {
-  constexpr int BM = 32, BN = 64, BK = 16;
-  __shared__ double As[BK][BM];
-  __shared__ double Bs[BK][BN];
-  const int ch = blockIdx.z;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const double* Xc = X + (size_t)ch * S;
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;   // 16 x 16 threads, 2 x 4 outputs each
-  double acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-  for (int k0 = 0; k0 < nq; k0 += BK) {
-    for (int i = threadIdx.x; i < BK * BM; i += 256) {
-      int kk = i / BM, mm = i % BM;
-      int u = k0 + kk, col = m0 + mm;
-      As[kk][mm] = (u < nq && col < ncol) ? eph[(size_t)u * ncol + col] : 0.0;
-    }
-    for (int i = threadIdx.x; i < BK * BN; i += 256) {
-      int kk = i / BN, nn = i % BN;
-      int u = k0 + kk, mn = n0 + nn;
-      Bs[kk][nn] = (u < nq && mn < nff2) ? Xc[(size_t)u * nff2 + mn] : 0.0;
-    }
-    __syncthreads();
+  __shared__ double red[NW][KG][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int col = blockIdx.x * 64 + lane;
+  const int k0 = blockIdx.y * KG;
+  const int kn = min(KG, ncol - k0);
+  const bool ok = col < 3 * nff2;
+  const int ch = ok ? col / nff2 : 0, mn = ok ? col % nff2 : 0;
+  const double* xp = X + (size_t)ch * S + mn;
+  const int u0 = (int)((int64_t)nq * w / NW), u1 = (int)((int64_t)nq * (w + 1) / NW);
+  double acc[KG];
 #pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      double a0 = As[kk][ty * 2], a1 = As[kk][ty * 2 + 1];
+  for (int i = 0; i < KG; ++i) acc[i] = 0.0;
+#pragma unroll 4
+  for (int u = u0; u < u1; ++u) {
+    const double x = ok ? xp[(size_t)u * nff2] : 0.0;
+    const double* e = eph + (size_t)u * ncol + k0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        double b = Bs[kk][tx + 16 * j];
-        acc[0][j] = fma(a0, b, acc[0][j]);
-        acc[1][j] = fma(a1, b, acc[1][j]);
-      }
-    }
-    __syncthreads();
+    for (int i = 0; i < KG; ++i)
+      if (i < kn) acc[i] = fma(e[i], x, acc[i]);
   }
-  const double inv = 1.0 / (double)nq;
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 4; ++j) {
-      int col = m0 + ty * 2 + i, mn = n0 + tx + 16 * j;
-      if (col < ncol && mn < nff2) xt[((size_t)ch * ncol + col) * nff2 + mn] = acc[i][j] * inv;
+#pragma unroll
+  for (int i = 0; i < KG; ++i) red[w][i][lane] = acc[i];
+  __syncthreads();
+  if (w == 0 && ok) {
+    const double inv = 1.0 / (double)nq;
+    for (int i = 0; i < kn; ++i) {
+      double v = 0.0;
+      for (int ww = 0; ww < NW; ++ww) v += red[ww][i][lane];
+      xt[((size_t)ch * ncol + k0 + i) * nff2 + mn] = v * inv;
     }
+  }
 }
 
-// Middle step of the projections, independent of the transfer momentum.
-// One block per (output channel X, half-set harmonic j).  For V = +S'_j and
-// V = -S'_j it gathers the bond-space coefficients
-//   M^X_AB(V) = sum_entries (+-) Yhat^{in}_{R1R2}(W),
-//   Yhat = sum_{m'n'} c_{m'R1} c_{n'R2} xt^{in}_{m'n'}(2W - R1 - R2),
-// changes basis N^X(V) = C M^X(V) C^T, and writes the real coefficients of
-// cos(l.V/2) and sin(l.V/2) for GEMM2.
+// Bond basis of the transformed propagators, for every harmonic of the full
+// list v (+S'_j for v < nsh, -S'_{v-nsh+1} otherwise):
+//   yb[in][v][b1 b2] = sum_{m' in shell(b1), n' in shell(b2)} c_{m'b1} c_{n'b2} xt^{in}_{m'n'}(v)
+// with xt(-S') = conj(xt(S')).  These are the bond-space Fourier coefficients
+// Yhat_{R1R2}(W) of the propagators at frequency 2W - R1 - R2 = v.
 __global__ void __launch_bounds__(256)
-k_proj_mid(DevTables d, const double* __restrict__ xt, double* __restrict__ g2) {
+k_bond_basis(DevTables d, const double* __restrict__ xt, double* __restrict__ yb) {
+  const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol, nv = 2 * nsh - 1;
+  const int total = 3 * nv * nff2;
+  __shared__ double cs[2 * 441];
+  for (int i = threadIdx.x; i < nff2; i += blockDim.x) {
+    cs[i] = d.cre[i];
+    cs[nff2 + i] = d.cim[i];
+  }
+  __syncthreads();
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int in = idx / (nv * nff2), v = (idx / nff2) % nv, b = idx % nff2;
+  const int b1 = b / nff, b2 = b % nff;
+  const int j = v < nsh ? v : v - nsh + 1;
+  const double sim = v < nsh ? 1.0 : -1.0;
+  const double* xr = xt + ((size_t)in * ncol + j) * nff2;
+  const double* xi = xt + ((size_t)in * ncol + (nsh - 1 + j)) * nff2;
+  const int s1 = d.shell_of[b1], s2 = d.shell_of[b2];
+  double yr = 0.0, yi = 0.0;
+  const int m0 = d.shell_start[s1], m1 = d.shell_start[s1 + 1];
+  const int n0 = d.shell_start[s2], n1 = d.shell_start[s2 + 1];
+  for (int mp = m0; mp < m1; ++mp) {
+    const double c1r = cs[mp * nff + b1], c1i = cs[nff2 + mp * nff + b1];
+#pragma unroll 4
+    for (int np = n0; np < n1; ++np) {
+      const double c2r = cs[np * nff + b2], c2i = cs[nff2 + np * nff + b2];
+      const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
+      const double ar = xr[mp * nff + np];
+      const double ai = j > 0 ? sim * xi[mp * nff + np] : 0.0;
+      yr = fma(wr, ar, fma(-wi, ai, yr));
+      yi = fma(wr, ai, fma(wi, ar, yi));
+    }
+  }
+  yb[idx] = yr;
+  yb[(size_t)total + idx] = yi;
+}
+
+// Gather and basis change, independent of the transfer momentum.  One block
+// per (output channel X, half-set harmonic j).  For V = +S'_j and V = -S'_j:
+//   M^X_AB(V) = sum_entries (+-) yb^{in}_{b1 b2}(v)          (eqn. proj_pos in bonds)
+//   N^X(V) = C M^X(V) C^T                                  (back to form factors)
+// and the real coefficients of cos(l.V/2), sin(l.V/2) for the inverse transform:
+//   Re[e^{-il.V/2} N(V) + e^{+il.V/2} N(-V)] = cos (ReN+ + ReN-) + sin (ImN+ - ImN-).
+__global__ void __launch_bounds__(256)
+k_gather_g2(DevTables d, const double* __restrict__ yb, double* __restrict__ g2) {
   const int X = blockIdx.y, j = blockIdx.x;
   const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol;
   const int nv = 2 * nsh - 1;
   const int nvl = (j == 0) ? 1 : 2;
+  const size_t ybim = (size_t)3 * nv * nff2;
   extern __shared__ double sm[];
   double* Mre = sm;                  // [2][nff2]
   double* Mim = Mre + 2 * nff2;
@@ -216,27 +279,11 @@ k_proj_mid(DevTables d, const double* __restrict__ xt, double* __restrict__ g2) 
     double re = 0.0, im = 0.0;
     for (int e = d.mrow[row]; e < d.mrow[row + 1]; ++e) {
       const int32_t pk = d.ment[e];
-      const int in = pk & 3, b1 = (pk >> 2) & 31, b2 = (pk >> 7) & 31, jj = (pk >> 12) & 127;
-      const int conj = (pk >> 19) & 1, neg = (pk >> 20) & 1;
-      const double* xr = xt + ((size_t)in * ncol + jj) * nff2;
-      const double* xi = (jj > 0) ? xt + ((size_t)in * ncol + nsh - 1 + jj) * nff2 : nullptr;
-      const int s1 = d.shell_of[b1], s2 = d.shell_of[b2];
-      double yr = 0.0, yi = 0.0;
-      for (int mp = d.shell_start[s1]; mp < d.shell_start[s1 + 1]; ++mp) {
-        const double c1r = d.cre[mp * nff + b1], c1i = d.cim[mp * nff + b1];
-        for (int np = d.shell_start[s2]; np < d.shell_start[s2 + 1]; ++np) {
-          const double c2r = d.cre[np * nff + b2], c2i = d.cim[np * nff + b2];
-          const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
-          const double ar = xr[mp * nff + np];
-          double ai = xi ? xi[mp * nff + np] : 0.0;
-          if (conj) ai = -ai;
-          yr += wr * ar - wi * ai;
-          yi += wr * ai + wi * ar;
-        }
-      }
-      if (neg) { yr = -yr; yi = -yi; }
-      re += yr;
-      im += yi;
+      const int in = pk & 3, b1 = (pk >> 2) & 31, b2 = (pk >> 7) & 31, v = (pk >> 12) & 127;
+      const int neg = (pk >> 19) & 1;
+      const size_t o = ((size_t)in * nv + v) * nff2 + b1 * nff + b2;
+      const double yr = yb[o], yi = yb[ybim + o];
+      if (neg) { re -= yr; im -= yi; } else { re += yr; im += yi; }
     }
     Mre[vi * nff2 + ab] = re;
     Mim[vi * nff2 + ab] = im;
@@ -258,7 +305,6 @@ k_proj_mid(DevTables d, const double* __restrict__ xt, double* __restrict__ g2) 
         }
       }
     }
-    // Re[e^{-il.V/2} N(V) + e^{+il.V/2} N(-V)] = cos (ReN+ + ReN-) + sin (ImN+ - ImN-)
     if (j == 0) {
       g2[((size_t)X * ncol + 0) * nff2 + mn] = nr[0];
     } else {
@@ -268,9 +314,8 @@ k_proj_mid(DevTables d, const double* __restrict__ xt, double* __restrict__ g2) 
   }
 }
 
-// GEMM2 of the projections fused with the assembly of eqns. proj_VP/VC/VD
-// and, in mode 1, with the products of eqns. matmul-P/C/D.
-// One block per LT consecutive transfer momenta l.
+// Inverse transform fused with the assembly of eqns. proj_VP/VC/VD and, in
+// mode 1, with the products of eqns. matmul-P/C/D.  One block per lt momenta l.
 //   K^X_mn(l) = sum_k E[l][k] g2[X][k][mn]
 //   V^P = U e0e0 - P + K^P,  V^C = U e0e0 + C + K^C,  V^D = U e0e0 + D + K^D
 //   dP = V^P chi'pp V^P, dC = -V^C chi'ph V^C,
@@ -278,9 +323,9 @@ k_proj_mid(DevTables d, const double* __restrict__ xt, double* __restrict__ g2) 
 //   of eqn. matmul-D: 2 dD - dC = W chi'ph W).
 constexpr int kLT = 4;   // largest number of momenta per block
 __global__ void __launch_bounds__(256)
-k_proj_out(DevTables d, const double* __restrict__ X, int64_t S, const double* __restrict__ g2,
-           const double* __restrict__ dchi, double* __restrict__ out, int mode, int cross,
-           double scale, int lt) {
+k_proj_back(DevTables d, const double* __restrict__ X, int64_t S, const double* __restrict__ g2,
+            const double* __restrict__ dchi, const double* __restrict__ dpart, int nsplit,
+            double* __restrict__ out, int mode, int cross, double scale, int lt) {
   const int nff = d.nff, nff2 = nff * nff, ncol = d.ncol, nq = d.nq;
   const int l0 = blockIdx.x * lt;
   const int nl = min(lt, nq - l0);
@@ -301,6 +346,7 @@ k_proj_out(DevTables d, const double* __restrict__ X, int64_t S, const double* _
     for (int i = 0; i < kLT; ++i) acc[i] = 0.0;
     if (cross) {
       const double* g = g2 + (size_t)ch * ncol * nff2 + mn;
+#pragma unroll 8
       for (int k = 0; k < ncol; ++k) {
         const double gv = g[(size_t)k * nff2];
 #pragma unroll
@@ -328,8 +374,16 @@ k_proj_out(DevTables d, const double* __restrict__ X, int64_t S, const double* _
     const double* VP = Vs + (i * 3 + 0) * nff2;
     const double* VC = Vs + (i * 3 + 1) * nff2;
     const double* VD = Vs + (i * 3 + 2) * nff2;
-    for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x)
-      Ch[w] = dchi[(size_t)(w / nff2) * S + (size_t)l * nff2 + w % nff2];
+    for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
+      const int ch = w / nff2, mn = w % nff2;
+      if (nsplit == 1) {
+        Ch[w] = dchi[(size_t)ch * S + (size_t)l * nff2 + mn];
+      } else {
+        double v = 0.0;
+        for (int s = 0; s < nsplit; ++s) v += dpart[(((size_t)s * 2 + ch) * nq + l) * nff2 + mn];
+        Ch[w] = v;
+      }
+    }
     for (int w = threadIdx.x; w < nff2; w += blockDim.x) Wm[w] = 2.0 * VD[w] - VC[w];
     __syncthreads();
     // T1 = chi'pp V^P, chi'ph V^C, chi'ph W
@@ -432,63 +486,98 @@ __global__ void k_errnorm(const double* __restrict__ y0, const double* __restric
 }  // namespace
 
 // ------------------------------------------------------------- launchers
-static int loop_chunks(int nq, int lk) {
-  // enough waves to cover the chip (256 CUs x 4 SIMDs x ~4 waves) without
-  // making a block larger than kBubThreads or a chunk shorter than 6 rows
-  const int rows = lk / 2 + 1;
-  int nchunk = 1;
-  while (nchunk < 8 && lk * (nchunk + 1) <= kBubThreads && rows / (nchunk + 1) >= 6 &&
-         (int64_t)nq * lk * nchunk < (int64_t)4096 * 64)
-    ++nchunk;
-  return nchunk;
-}
-
-size_t loop_smem_bytes(const DevTables& d, int threads) {
-  const int rows = d.lk / 2 + 1, NH = 2 * d.smax + 1, nout = 2 * d.nsh;
-  int nseg = threads / nout;
+LoopGeom loop_geometry(const DevTables& d) {
+  // Split the half fine grid of every transfer momentum into nsplit row blocks
+  // of lk * nchunk threads until about 8 waves per SIMD are in flight, keeping
+  // at least 4 rows per thread and at most kBubThreads threads per block.
+  const int rows = d.lk / 2 + 1;
+  const int64_t target = (int64_t)256 * 4 * 8 * 64;   // lanes for ~8 waves per SIMD
+  int nsplit = 1, nchunk = 1;
+  for (;;) {
+    const int64_t lanes = (int64_t)d.nq * d.lk * nsplit * nchunk;
+    if (lanes >= target) break;
+    if (d.lk * (nchunk + 1) <= kBubThreads && rows / (nsplit * (nchunk + 1)) >= 4) {
+      ++nchunk;
+    } else if (nsplit < 16 && rows / ((nsplit + 1) * nchunk) >= 4) {
+      ++nsplit;
+    } else {
+      break;
+    }
+  }
+  LoopGeom g;
+  g.nsplit = nsplit;
+  g.nchunk = nchunk;
+  g.threads = ((d.lk * nchunk + 63) / 64) * 64;
+  const int nrmax = (rows + nsplit - 1) / nsplit;
+  const int NH = 2 * d.smax + 1, nout = 2 * d.nsh;
+  int nseg = g.threads / nout;
   if (nseg < 1) nseg = 1;
-  return sizeof(double) * ((size_t)2 * rows + (size_t)rows * NH + (size_t)d.lk * 2 * NH +
-                           (size_t)nseg * nout);
+  g.smem = sizeof(double) * ((size_t)2 * nrmax + (size_t)nrmax * NH + (size_t)d.lk * 2 * NH +
+                             (size_t)nseg * nout);
+  return g;
 }
 
-void launch_bubbles(const DevTables& d, double T, double* dchi, int64_t S, int precision,
-                    hipStream_t s) {
-  (void)precision;
-  const int nchunk = loop_chunks(d.nq, d.lk);
-  int threads = ((d.lk * nchunk + 63) / 64) * 64;
-  const size_t shmem = loop_smem_bytes(d, threads);
+void launch_loops(const DevTables& d, double T, double* dchi, int64_t S, double* dpart,
+                  bool sum_slices, hipStream_t s) {
+  const LoopGeom g = loop_geometry(d);
+  const dim3 grid((unsigned)(d.nq * g.nsplit));
   switch (d.smax) {
     case 0:
-      hipLaunchKernelGGL(k_loops_f64<0>, dim3(d.nq), dim3(threads), shmem, s, d, T, nchunk, dchi, S);
+      hipLaunchKernelGGL(k_loops_f64<0>, grid, dim3(g.threads), g.smem, s, d, T, g.nsplit, g.nchunk,
+                         dchi, S, dpart);
       break;
     case 2:
-      hipLaunchKernelGGL(k_loops_f64<2>, dim3(d.nq), dim3(threads), shmem, s, d, T, nchunk, dchi, S);
+      hipLaunchKernelGGL(k_loops_f64<2>, grid, dim3(g.threads), g.smem, s, d, T, g.nsplit, g.nchunk,
+                         dchi, S, dpart);
       break;
     default:
-      hipLaunchKernelGGL(k_loops_f64<4>, dim3(d.nq), dim3(threads), shmem, s, d, T, nchunk, dchi, S);
+      hipLaunchKernelGGL(k_loops_f64<4>, grid, dim3(g.threads), g.smem, s, d, T, g.nsplit, g.nchunk,
+                         dchi, S, dpart);
       break;
+  }
+  if (sum_slices && g.nsplit > 1) {
+    const int nff2 = d.nff * d.nff;
+    const int64_t n = (int64_t)2 * d.nq * nff2;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_chi_sum, dim3(blocks), dim3(256), 0, s, dpart, g.nsplit, d.nq, nff2, dchi, S);
   }
 }
 
-void launch_project(const DevTables& d, const double* X, int64_t S, double* xt, double* g2,
-                    const double* dchi, double* out, int mode, uint32_t flags, double scale,
-                    hipStream_t s) {
+void launch_project_front(const DevTables& d, const double* X, int64_t S, double* xt, double* yb,
+                          double* g2, uint32_t flags, hipStream_t s) {
+  if (flags & TUFRG_NO_CROSS) return;
   const int nff2 = d.nff * d.nff;
-  const int cross = (flags & TUFRG_NO_CROSS) ? 0 : 1;
-  if (cross) {
-    dim3 g1((nff2 + 63) / 64, (d.ncol + 31) / 32, 3);
-    hipLaunchKernelGGL(k_dft_fwd, g1, dim3(256), 0, s, d.eph, d.nq, d.ncol, X, S, nff2, xt);
-    const size_t sm_mid = sizeof(double) * 4 * (size_t)nff2;
-    hipLaunchKernelGGL(k_proj_mid, dim3(d.nsh, 3), dim3(256), sm_mid, s, d, xt, g2);
+  const int ncols = 3 * nff2;
+  if (d.nq * ncols >= 2000000) {
+    dim3 g1((ncols + 63) / 64, (d.ncol + 7) / 8);
+    hipLaunchKernelGGL((k_dft_fwd<8, 8>), g1, dim3(512), 0, s, d.eph, d.nq, d.ncol, X, S, nff2, xt);
+  } else {
+    dim3 g1((ncols + 63) / 64, (d.ncol + 3) / 4);
+    hipLaunchKernelGGL((k_dft_fwd<4, 16>), g1, dim3(1024), 0, s, d.eph, d.nq, d.ncol, X, S, nff2, xt);
   }
-  // momenta per block: as many as fit in 64 KB of LDS (at most kLT)
-  int lt = kLT;
+  const int nv = 2 * d.nsh - 1;
+  const int total = 3 * nv * nff2;
+  hipLaunchKernelGGL(k_bond_basis, dim3((total + 255) / 256), dim3(256), 0, s, d, xt, yb);
+  const size_t sm_mid = sizeof(double) * 4 * (size_t)nff2;
+  hipLaunchKernelGGL(k_gather_g2, dim3(d.nsh, 3), dim3(256), sm_mid, s, d, yb, g2);
+}
+
+void launch_project_back(const DevTables& d, const double* X, int64_t S, const double* g2,
+                         const double* dchi, const double* dpart, double* out, int mode,
+                         uint32_t flags, double scale, hipStream_t s) {
+  const int nff2 = d.nff * d.nff;
+  const int nsplit = loop_geometry(d).nsplit;
+  const int cross = (flags & TUFRG_NO_CROSS) ? 0 : 1;
   auto sm_bytes = [&](int l) {
     return sizeof(double) * ((size_t)l * d.ncol + (size_t)l * 3 * nff2 + 9 * (size_t)nff2);
   };
+  // momenta per block: two on large grids (halves the reads of g2), one
+  // otherwise; always within 64 KB of LDS
+  int lt = d.nq >= 1024 ? 2 : 1;
   while (lt > 1 && sm_bytes(lt) > 65536) --lt;
-  hipLaunchKernelGGL(k_proj_out, dim3((d.nq + lt - 1) / lt), dim3(256), sm_bytes(lt), s, d, X, S,
-                     g2, dchi, out, mode, cross, scale, lt);
+  hipLaunchKernelGGL(k_proj_back, dim3((d.nq + lt - 1) / lt), dim3(256), sm_bytes(lt), s, d, X, S,
+                     g2, dchi, dpart, nsplit, out, mode, cross, scale, lt);
 }
 
 void launch_axpy_stage(const double* X, const double* const* k, const double* coef, int nk,

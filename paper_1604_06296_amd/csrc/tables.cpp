@@ -206,6 +206,18 @@ std::string build_tables(const tufrg_point& p, HostTables& t) {
     }
   }
 
+  // shifted cosines of the loop energies, one axis: p_j = 2 pi j/Lk,
+  // q_i = 2 pi (i - Lq/2)/Lq
+  t.cshift.assign((size_t)p.Lq * lk * 2, 0.0);
+  for (int i = 0; i < p.Lq; ++i) {
+    const double qh = M_PI * (double)(i - p.Lq / 2) / (double)p.Lq;   // q_i / 2
+    for (int j = 0; j < lk; ++j) {
+      const double pj = two_pi * (double)j / (double)lk;
+      t.cshift[((size_t)i * lk + j) * 2] = std::cos(pj + qh);
+      t.cshift[((size_t)i * lk + j) * 2 + 1] = std::cos(pj - qh);
+    }
+  }
+
   // projection phase table E[u][k] over the transfer grid, u.S/2 with
   // u_i = 2 pi (i - Lq/2)/Lq; reduced exactly modulo 2 pi in units of pi/Lq
   const int lq = p.Lq;
@@ -245,10 +257,8 @@ std::string build_tables(const tufrg_point& p, HostTables& t) {
   };
   auto add = [&](int X, int a, int b, int vx, int vy, int in, int b1, int b2, int sox, int soy,
                  int neg) {
-    int conj;
-    int j = half_of(sox, soy, &conj);
     size_t row = (((size_t)X * nv + vfull(vx, vy)) * nff + a) * nff + b;
-    lists[row].push_back(pack_entry(in, b1, b2, j, conj, neg));
+    lists[row].push_back(pack_entry(in, b1, b2, vfull(sox, soy), neg));
   };
   const int rW = t.smax;
   for (int a = 0; a < nff; ++a)
@@ -299,18 +309,28 @@ std::string build_tables(const tufrg_point& p, HostTables& t) {
   }
   t.mrow[rows] = (int32_t)t.ment.size();
 
-  // algorithmic flop counts of one right-hand side (FP64 flops, FMA = 2)
+  // algorithmic flop counts of one right-hand side (FP64 flops, FMA = 2).
+  // Loops: per (q, p) pair of the half fine grid, 162 flops for the two loop
+  // derivatives (two exponentials, reciprocals, both divided-difference
+  // branches, as counted in the compiled kernel) plus 2 channels x (2 smax + 1)
+  // harmonic multiply-adds; per transfer momentum the contraction over px
+  // (2 N_S' outputs x Lk columns x 2 multiply-adds) and the form-factor
+  // epilogue (2 nff^2 N_S' multiply-adds).
   const double nq = t.nq, f2 = (double)nff * nff, f3 = f2 * nff;
   const double pairs = nq * (double)lk * (lk / 2 + 1);
-  const double c_pair = 120.0;                  // loop-kernel arithmetic per (q,p) pair
+  const double c_pair = 162.0;
   const double c_acc = 2.0 * 2.0 * (2 * t.smax + 1);
-  t.flops_loops = (int64_t)(pairs * (c_pair + c_acc) + nq * 2.0 * 2.0 * f2 * t.nsh);
-  double mid = 0.0;
-  for (int32_t e : t.ment) {
-    (void)e;
-    mid += 8.0 * 16.0;  // bilinear form over <= 4x4 (shells 1-3) form factors, complex
+  t.flops_loops = (int64_t)(pairs * (c_pair + c_acc) +
+                            nq * (2.0 * t.nsh * lk * 4.0 + 2.0 * 2.0 * f2 * t.nsh));
+  // forward and inverse transforms (2 flops per real multiply-add), the bond
+  // basis change of the transformed propagators and the gathered sums
+  double bb = 0.0;
+  for (int s = 0; s < t.nshell; ++s) {
+    const double ns = t.shell_start[s + 1] - t.shell_start[s];
+    bb += ns * ns;
   }
-  t.flops_proj = (int64_t)(2.0 * 3.0 * f2 * t.ncol * nq * 2.0 + mid);
+  const double basis = 3.0 * nv * 8.0 * bb * f2 * 2.0;   // two sides, complex, both stages
+  t.flops_proj = (int64_t)(2.0 * 3.0 * f2 * t.ncol * nq * 2.0 + basis + 2.0 * t.ment.size());
   t.flops_prod = (int64_t)(nq * 6.0 * 2.0 * f3);
   return "";
 }

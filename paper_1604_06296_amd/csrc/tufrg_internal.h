@@ -39,6 +39,8 @@ struct HostTables {
   // per-py weighted harmonics w(py) cos(n py), w(py) sin(n py) for py in [0, Lk/2]
   std::vector<double> pxtab;      // [Lk][2*smax+1]
   std::vector<double> pytab;      // [Lk/2+1][2*smax+1]
+  // loops: cos(p_j + q_i/2), cos(p_j - q_i/2) for one axis, [Lq][Lk][2]
+  std::vector<double> cshift;
   // projections: phase table E[u][k] = cos(u.S'_k/2) (k < nsh), sin(u.S'_{k-nsh+1}/2)
   std::vector<double> eph;        // [nq][ncol]
   // projections: entry lists per (out channel, V in full set index, A, B)
@@ -49,10 +51,11 @@ struct HostTables {
   int64_t flops_loops = 0, flops_proj = 0, flops_prod = 0;
 };
 
-// packed mid-step entry: in channel (2 bits), b1 (5), b2 (5), harmonic j (7),
-// conj (1), negative sign (1)
-inline int32_t pack_entry(int in, int b1, int b2, int j, int conj, int neg) {
-  return in | (b1 << 2) | (b2 << 7) | (j << 12) | (conj << 19) | (neg << 20);
+// packed gather entry: input channel (2 bits), bonds b1, b2 (5 bits each),
+// harmonic index v in the full list [+S'_0..+S'_{nsh-1}, -S'_1..-S'_{nsh-1}]
+// (7 bits), negative sign (1 bit)
+inline int32_t pack_entry(int in, int b1, int b2, int v, int neg) {
+  return in | (b1 << 2) | (b2 << 7) | (v << 12) | (neg << 19);
 }
 
 std::string build_tables(const tufrg_point& p, HostTables& t);   // "" on success
@@ -69,6 +72,7 @@ struct DevTables {
   double* ebub;  // [nff*nff*nsh]
   double* pxtab; // [lk][2 smax + 1]
   double* pytab; // [lk/2+1][2 smax + 1]
+  double* cshift; // [lq][lk][2]: cos(p_j + q_i/2), cos(p_j - q_i/2) per axis
   double* eph;   // [nq][ncol]
   int32_t* mrow;
   int32_t* ment;
@@ -78,8 +82,10 @@ struct DevTables {
 };
 
 struct Workspace {
-  double* xt;    // GEMM1 output [3][ncol][nff^2] per point (max size)
-  double* g2;    // mid output [3][ncol][nff^2]
+  double* xt;    // forward transform [3][ncol][nff^2] (largest point)
+  double* yb;    // bond-basis transform [2 (re, im)][3][2 nsh - 1][nff^2]
+  double* g2;    // inverse-transform coefficients [3][ncol][nff^2]
+  double* dpart; // loop slices [nsplit][2][Nq][nff^2] (largest point)
   double* dchi;  // loops [2][S]
   double* stage; // RK stage state [3][S]
   double* k[7];  // RK slopes [3][S] each
@@ -97,6 +103,8 @@ struct tufrg_ctx {
   int64_t S = 0;              // total elements per channel
   tufrg_options opt{};
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;      // loops run here, concurrently with the projections
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   tufrg::Workspace ws{};
   std::vector<void*> allocations;
   std::string err;
@@ -105,14 +113,27 @@ struct tufrg_ctx {
 
 namespace tufrg {
 // kernel launchers (kernels.hip); all asynchronous on `s`
-// dchi / X / out point at this point's block inside [channels][S] arrays
-void launch_bubbles(const DevTables& d, double T, double* dchi, int64_t S, int precision,
-                    hipStream_t s);
-// mode 0: out = V (projection only); mode 1: out = scale * dX/dT (products with dchi)
-void launch_project(const DevTables& d, const double* X, int64_t S, double* xt, double* g2,
-                    const double* dchi, double* out, int mode, uint32_t flags, double scale,
-                    hipStream_t s);
-size_t loop_smem_bytes(const DevTables& d, int threads);
+// Loop launch geometry of one point: nsplit blocks per transfer momentum, each
+// with lk * nchunk threads (rounded up to whole waves).
+struct LoopGeom {
+  int nsplit, nchunk, threads;
+  size_t smem;
+};
+LoopGeom loop_geometry(const DevTables& d);
+// loops at temperature T.  With one split per momentum they land in dchi (this
+// point's block in [2][S]); otherwise in the slices dpart[nsplit][2][Nq][nff^2],
+// which are added into dchi when sum_slices is set (else the consumer adds them)
+void launch_loops(const DevTables& d, double T, double* dchi, int64_t S, double* dpart,
+                  bool sum_slices, hipStream_t s);
+// projection front end (depends on X only): forward transform, bond basis,
+// gather into the inverse-transform coefficients g2
+void launch_project_front(const DevTables& d, const double* X, int64_t S, double* xt, double* yb,
+                          double* g2, uint32_t flags, hipStream_t s);
+// projection back end: mode 0 -> out = V; mode 1 -> out = scale * dX/dT with the
+// loops from dchi (one split) or the slices dpart
+void launch_project_back(const DevTables& d, const double* X, int64_t S, const double* g2,
+                         const double* dchi, const double* dpart, double* out, int mode,
+                         uint32_t flags, double scale, hipStream_t s);
 void launch_axpy_stage(const double* X, const double* const* k, const double* coef, int nk,
                        double h, double* out, int64_t n, hipStream_t s);
 void launch_maxabs(const double* X, int64_t n, unsigned long long* word, hipStream_t s);
