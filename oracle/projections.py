@@ -77,13 +77,15 @@ def _coef_vector(ff: FormFactors, R) -> np.ndarray:
     return ff.coefficient_column(R)
 
 
-def kernel_K1(X: np.ndarray, ff: FormFactors, Lq: int) -> np.ndarray:
-    """K1[X]_mn(l) on the transfer grid: array [nq, nff, nff] (complex).
+def kernel_K1(X: np.ndarray, ff: FormFactors, Lq: int, l_index=None) -> np.ndarray:
+    """K1[X]_mn(l) on the transfer grid (or at the momenta l_index): [nl, nff, nff] complex.
 
     K1[X]_mn(l) = sum_{R1,R2} exp(-i l.(R1+R2)/2) sum_W c_{m,R2-W} c_{n,R1-W} Yhat_{R1R2}(W).
     """
-    qx, qy = q_grid(Lq)
     Y = gauged_fourier(X, ff, Lq)
+    qx, qy = q_grid(Lq)
+    if l_index is not None:
+        qx, qy = qx[l_index], qy[l_index]
     out = np.zeros((qx.size, ff.nff, ff.nff), dtype=complex)
     for b1, R1 in enumerate(ff.bonds):
         for b2, R2 in enumerate(ff.bonds):
@@ -99,13 +101,15 @@ def kernel_K1(X: np.ndarray, ff: FormFactors, Lq: int) -> np.ndarray:
     return out
 
 
-def kernel_K2(X: np.ndarray, ff: FormFactors, Lq: int) -> np.ndarray:
-    """K2[X]_mn(l) on the transfer grid: array [nq, nff, nff] (complex).
+def kernel_K2(X: np.ndarray, ff: FormFactors, Lq: int, l_index=None) -> np.ndarray:
+    """K2[X]_mn(l) on the transfer grid (or at the momenta l_index): [nl, nff, nff] complex.
 
     K2[X]_mn(l) = sum_{R1,R2} exp(-i l.(R1-R2)/2) sum_W c_{m,-W} c_{n,W-R1-R2} Yhat_{R1R2}(W).
     """
-    qx, qy = q_grid(Lq)
     Y = gauged_fourier(X, ff, Lq)
+    qx, qy = q_grid(Lq)
+    if l_index is not None:
+        qx, qy = qx[l_index], qy[l_index]
     out = np.zeros((qx.size, ff.nff, ff.nff), dtype=complex)
     for b1, R1 in enumerate(ff.bonds):
         for b2, R2 in enumerate(ff.bonds):
@@ -129,7 +133,7 @@ def _real(Z: np.ndarray, what: str) -> np.ndarray:
     return Z.real.copy()
 
 
-def cross_projections(point, X: np.ndarray, ff: FormFactors | None = None) -> dict:
+def cross_projections(point, X: np.ndarray, ff: FormFactors | None = None, l_index=None) -> dict:
     """The six cross projections of eqns. proj_VP/VC/VD for state X[3][nq][nff][nff].
 
     Keys: 'P[C]', 'P[D]', 'C[P]', 'C[D]', 'D[P]', 'D[C]' meaning e.g.
@@ -138,8 +142,8 @@ def cross_projections(point, X: np.ndarray, ff: FormFactors | None = None) -> di
     ff = ff or FormFactors(point.shells)
     P, C, D = X
     pi = ff.parity
-    K1C, K1D, K1P = (kernel_K1(Z, ff, point.Lq) for Z in (C, D, P))
-    K2D, K2C, K2P = (kernel_K2(Z, ff, point.Lq) for Z in (D, C, P))
+    K1C, K1D, K1P = (kernel_K1(Z, ff, point.Lq, l_index) for Z in (C, D, P))
+    K2D, K2C, K2P = (kernel_K2(Z, ff, point.Lq, l_index) for Z in (D, C, P))
     return {
         "P[C]": _real(K1C, "P[C]"),
         "P[D]": _real(K1D * pi[None, None, :], "P[D]"),
@@ -151,20 +155,23 @@ def cross_projections(point, X: np.ndarray, ff: FormFactors | None = None) -> di
 
 
 def project(point, X: np.ndarray, ff: FormFactors | None = None,
-            no_cross: bool = False) -> np.ndarray:
+            no_cross: bool = False, l_index=None) -> np.ndarray:
     """V[3][nq][nff][nff] = (V^P, V^C, V^D) per eqns. proj_VP, proj_VC, proj_VD.
 
+    l_index selects the momenta l at which V is returned (all by default).
     no_cross drops every inter-channel term (decoupled channels); it is a
     test seam for closed forms, not part of the method.
     """
     ff = ff or FormFactors(point.shells)
     P, C, D = X
+    if l_index is not None:
+        P, C, D = P[l_index], C[l_index], D[l_index]
     nq, nff = P.shape[0], ff.nff
     bare = np.zeros((nq, nff, nff))
     bare[:, 0, 0] = point.U
     if no_cross:
         return np.stack([bare - P, bare + C, bare + D])
-    k = cross_projections(point, X, ff)
+    k = cross_projections(point, X, ff, l_index)
     VP = bare - P + k["P[C]"] + k["P[D]"]
     VC = bare - k["C[P]"] + C + k["C[D]"]
     VD = bare - k["D[P]"] + k["D[C]"] + D

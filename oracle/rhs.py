@@ -29,11 +29,11 @@ def products(V: np.ndarray, dchi: np.ndarray) -> np.ndarray:
 
 
 def rhs(point, T: float, X: np.ndarray, ff: FormFactors | None = None,
-        no_cross: bool = False, return_parts: bool = False):
-    """dX/dT at temperature T for state X = (P, C, D)."""
+        no_cross: bool = False, return_parts: bool = False, q_index=None):
+    """dX/dT at temperature T for state X = (P, C, D), at the momenta q_index (all by default)."""
     ff = ff or FormFactors(point.shells)
-    V = project(point, X, ff, no_cross=no_cross)
-    dchi = bubbles(point, T, "dot", ff)
+    V = project(point, X, ff, no_cross=no_cross, l_index=q_index)
+    dchi = bubbles(point, T, "dot", ff, q_index=q_index)
     dX = products(V, dchi)
     if return_parts:
         return dX, V, dchi

@@ -64,6 +64,19 @@ tufrg_status dalloc(tufrg_ctx* ctx, size_t bytes, void** out) {
 void rhs_point(tufrg_ctx* ctx, int p, double T, const double* X, double* out, double scale) {
   const DevTables& d = ctx->dev[p];
   const int64_t off = ctx->off[p];
+  if (ctx->opt.precision == TUFRG_MIXED) {
+    hipEventRecord(ctx->ev_fork, ctx->stream);
+    hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+    launch_loops_mixed(d, T, ctx->ws.dchi + off, ctx->S, ctx->ws.dpart, false, ctx->side);
+    hipEventRecord(ctx->ev_join, ctx->side);
+    launch_project_front_mixed(d, X + off, ctx->S, ctx->ws.xt, ctx->ws.yb, ctx->ws.g2,
+                               ctx->opt.flags, ctx->stream);
+    launch_inverse_mixed(d, ctx->ws.g2, ctx->ws.kinv, ctx->opt.flags, ctx->stream);
+    hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
+    launch_products_mixed(d, X + off, ctx->S, ctx->ws.kinv, ctx->ws.dchi + off, ctx->ws.dpart,
+                          out + off, 1, ctx->opt.flags, scale, ctx->stream);
+    return;
+  }
   hipEventRecord(ctx->ev_fork, ctx->stream);
   hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
   launch_loops(d, T, ctx->ws.dchi + off, ctx->S, ctx->ws.dpart, false, ctx->side);
@@ -149,6 +162,30 @@ double interp_tc(double s0, double s1, double m0, double m1, double xmax) {
   return std::exp(sc);
 }
 
+// round-to-nearest-even BF16 bits of a float, and the hi/lo split of a double
+unsigned short bf16_bits(float f) {
+  unsigned int u;
+  std::memcpy(&u, &f, sizeof u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+float bf16_value(unsigned short h) {
+  unsigned int u = ((unsigned int)h) << 16;
+  float f;
+  std::memcpy(&f, &u, sizeof f);
+  return f;
+}
+void split_table(const std::vector<double>& x, std::vector<unsigned short>& hi,
+                 std::vector<unsigned short>& lo) {
+  hi.resize(x.size());
+  lo.resize(x.size());
+  for (size_t i = 0; i < x.size(); ++i) {
+    const float f = (float)x[i];
+    hi[i] = bf16_bits(f);
+    lo[i] = bf16_bits(f - bf16_value(hi[i]));
+  }
+}
+
 double word_to_double(unsigned long long w) {
   double d;
   std::memcpy(&d, &w, sizeof d);
@@ -169,8 +206,6 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   if (opt) o = *opt;
   if (o.precision != TUFRG_FP64 && o.precision != TUFRG_MIXED)
     return fail(nullptr, TUFRG_EINVAL, "precision must be TUFRG_FP64 or TUFRG_MIXED");
-  if (o.precision == TUFRG_MIXED)
-    return fail(nullptr, TUFRG_EUNSUPPORTED, "mixed precision is not available in this build");
   if (o.flags & ~(uint32_t)TUFRG_NO_CROSS) return fail(nullptr, TUFRG_EINVAL, "unknown flag bits");
   auto* ctx = new tufrg_ctx();
   ctx->opt = o;
@@ -178,7 +213,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   ctx->host.resize(npts);
   ctx->off.resize(npts);
   int64_t S = 0;
-  size_t max_xt = 8, max_yb = 8, max_gp = 8;
+  size_t max_xt = 8, max_yb = 8, max_gp = 8, max_k = 8;
   for (int p = 0; p < npts; ++p) {
     std::string e = build_tables(pts[p], ctx->host[p]);
     if (!e.empty()) {
@@ -194,6 +229,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     S += (int64_t)t.nq * t.nff * t.nff;
     max_xt = std::max(max_xt, (size_t)3 * t.ncol * t.nff * t.nff);
     max_yb = std::max(max_yb, (size_t)2 * 3 * (2 * t.nsh - 1) * t.nff * t.nff);
+    max_k = std::max(max_k, (size_t)3 * t.nq * t.nff * t.nff);
   }
   ctx->S = S;
   // device tables (first device call: every argument has been validated)
@@ -215,12 +251,15 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     for (int s = 0; s < t.nshell; ++s)
       for (int m = t.shell_start[s]; m < t.shell_start[s + 1]; ++m) so[m] = s;
     std::vector<int32_t> hx(t.hx.begin(), t.hx.end()), hy(t.hy.begin(), t.hy.end());
+    std::vector<unsigned short> ehi, elo;
+    split_table(t.eph, ehi, elo);
     tufrg_status st;
     if ((st = upload(ctx, cre, &d.cre)) || (st = upload(ctx, cim, &d.cim)) ||
         (st = upload(ctx, ss, &d.shell_start)) || (st = upload(ctx, so, &d.shell_of)) ||
         (st = upload(ctx, t.ebub, &d.ebub)) || (st = upload(ctx, t.pxtab, &d.pxtab)) ||
         (st = upload(ctx, t.pytab, &d.pytab)) || (st = upload(ctx, t.eph, &d.eph)) ||
-        (st = upload(ctx, t.cshift, &d.cshift)) ||
+        (st = upload(ctx, t.cshift, &d.cshift)) || (st = upload(ctx, ehi, &d.eph_hi)) ||
+        (st = upload(ctx, elo, &d.eph_lo)) ||
         (st = upload(ctx, t.mrow, &d.mrow)) || (st = upload(ctx, t.ment, &d.ment)) ||
         (st = upload(ctx, hx, &d.hx)) || (st = upload(ctx, hy, &d.hy))) {
       std::string m = ctx->err;
@@ -249,6 +288,10 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   w.yb = (double*)v;
   if ((st = dalloc(ctx, sizeof(double) * max_gp, &v))) goto bad;
   w.dpart = (double*)v;
+  if (o.precision == TUFRG_MIXED) {
+    if ((st = dalloc(ctx, sizeof(float) * max_k, &v))) goto bad;
+    w.kinv = (float*)v;
+  }
   if ((st = dalloc(ctx, sizeof(double) * 2 * (size_t)S, &v))) goto bad;
   w.dchi = (double*)v;
   if ((st = dalloc(ctx, b3, &v))) goto bad;
@@ -301,9 +344,14 @@ tufrg_status tufrg_bubbles(tufrg_ctx* ctx, const double* T_host, double* dchi) {
   for (size_t p = 0; p < ctx->dev.size(); ++p)
     if (!(T_host[p] > 0.0) || !std::isfinite(T_host[p]))
       return fail(ctx, TUFRG_EINVAL, "T must be finite and > 0");
-  for (size_t p = 0; p < ctx->dev.size(); ++p)
-    launch_loops(ctx->dev[p], T_host[p], dchi + ctx->off[p], ctx->S, ctx->ws.dpart, true,
-                 ctx->stream);
+  for (size_t p = 0; p < ctx->dev.size(); ++p) {
+    if (ctx->opt.precision == TUFRG_MIXED)
+      launch_loops_mixed(ctx->dev[p], T_host[p], dchi + ctx->off[p], ctx->S, ctx->ws.dpart, true,
+                         ctx->stream);
+    else
+      launch_loops(ctx->dev[p], T_host[p], dchi + ctx->off[p], ctx->S, ctx->ws.dpart, true,
+                   ctx->stream);
+  }
   HIP_TRY(ctx, hipGetLastError());
   return TUFRG_OK;
 }
@@ -313,6 +361,15 @@ tufrg_status tufrg_project(tufrg_ctx* ctx, const double* X, double* V) {
   if (!X || !V) return fail(ctx, TUFRG_EINVAL, "NULL argument");
   if (X == V) return fail(ctx, TUFRG_EINVAL, "X and V must not alias");
   for (size_t p = 0; p < ctx->dev.size(); ++p) {
+    if (ctx->opt.precision == TUFRG_MIXED) {
+      const DevTables& d = ctx->dev[p];
+      launch_project_front_mixed(d, X + ctx->off[p], ctx->S, ctx->ws.xt, ctx->ws.yb, ctx->ws.g2,
+                                 ctx->opt.flags, ctx->stream);
+      launch_inverse_mixed(d, ctx->ws.g2, ctx->ws.kinv, ctx->opt.flags, ctx->stream);
+      launch_products_mixed(d, X + ctx->off[p], ctx->S, ctx->ws.kinv, nullptr, nullptr,
+                            V + ctx->off[p], 0, ctx->opt.flags, 1.0, ctx->stream);
+      continue;
+    }
     launch_project_front(ctx->dev[p], X + ctx->off[p], ctx->S, ctx->ws.xt, ctx->ws.yb, ctx->ws.g2,
                          ctx->opt.flags, ctx->stream);
     launch_project_back(ctx->dev[p], X + ctx->off[p], ctx->S, ctx->ws.g2, nullptr, nullptr,

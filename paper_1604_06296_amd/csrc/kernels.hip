@@ -416,6 +416,331 @@ k_proj_back(DevTables d, const double* __restrict__ X, int64_t S, const double* 
   }
 }
 
+// ======================================================= mixed precision
+// Loops in FP32: energies and alpha +- beta in FP64, the pair math in FP32,
+// row sums blocked over 8 rows in FP32 and added into Neumaier-compensated
+// FP32 running sums; the short reductions over columns and slices in FP64.
+struct Exp2F { __device__ float operator()(float x) const { return __builtin_amdgcn_exp2f(x); } };
+struct RcpF { __device__ float operator()(float x) const { return __builtin_amdgcn_rcpf(x); } };
+
+__device__ __forceinline__ void neumaier_add(float& s, float& c, float v) {
+  const float t = s + v;
+  const bool sbig = fabsf(s) >= fabsf(v);
+  const float big = sbig ? s : v, small = sbig ? v : s;
+  c += (big - t) + small;
+  s = t;
+}
+
+template <int SMAX>
+__global__ void __launch_bounds__(kBubThreads)
+k_loops_mixed(DevTables d, double T, int nsplit, int nchunk, double* __restrict__ dchi, int64_t S,
+              double* __restrict__ dpart) {
+  constexpr int NH = 2 * SMAX + 1;
+  constexpr int RB = 8;
+  const int q = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
+  const int lk = d.lk;
+  const int rows = lk / 2 + 1;
+  const int R0 = (int)((int64_t)rows * split / nsplit);
+  const int R1 = (int)((int64_t)rows * (split + 1) / nsplit);
+  const int nr = R1 - R0;
+  const int lq = d.lq;
+  const int ix = q / lq, iy = q % lq;
+  const double inv2T = 0.5 / T;
+
+  extern __shared__ double smem[];
+  double* y1 = smem;
+  double* y2 = y1 + nr;
+  float* pyt = reinterpret_cast<float*>(y2 + nr);      // [nr][NH] (FP32 weights)
+  double* rs = reinterpret_cast<double*>(pyt + ((nr * NH + 1) & ~1));
+  double* gh = rs + lk * 2 * NH;
+
+  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
+    const double* c = d.cshift + ((size_t)iy * lk + (R0 + j)) * 2;
+    y1[j] = c[0];
+    y2[j] = c[1];
+  }
+  for (int j = threadIdx.x; j < nr * NH; j += blockDim.x) pyt[j] = (float)d.pytab[R0 * NH + j];
+  for (int j = threadIdx.x; j < lk * 2 * NH; j += blockDim.x) rs[j] = 0.0;
+  __syncthreads();
+
+  const int t = threadIdx.x;
+  const bool active = t < lk * nchunk;
+  const int px = t % lk, c = t / lk;
+  float sum[2][NH], cmp[2][NH];
+#pragma unroll
+  for (int n = 0; n < NH; ++n) sum[0][n] = sum[1][n] = cmp[0][n] = cmp[1][n] = 0.0f;
+  if (active) {
+    const double cx1 = d.cshift[((size_t)ix * lk + px) * 2];
+    const double cx2 = d.cshift[((size_t)ix * lk + px) * 2 + 1];
+    const double A1 = (-2.0 * d.t * cx1 - d.mu) * inv2T;
+    const double B1 = (-2.0 * d.t - 4.0 * d.tp * cx1) * inv2T;
+    const double A2 = (-2.0 * d.t * cx2 - d.mu) * inv2T;
+    const double B2 = (-2.0 * d.t - 4.0 * d.tp * cx2) * inv2T;
+    const int r0 = (int)((int64_t)nr * c / nchunk);
+    const int r1 = (int)((int64_t)nr * (c + 1) / nchunk);
+    for (int rb = r0; rb < r1; rb += RB) {
+      float blk[2][NH];
+#pragma unroll
+      for (int n = 0; n < NH; ++n) blk[0][n] = blk[1][n] = 0.0f;
+      const int re = min(rb + RB, r1);
+      for (int r = rb; r < re; ++r) {
+        const double al = fma(B1, y1[r], A1);
+        const double be = fma(B2, y2[r], A2);
+        float dph, dpp;
+        loop_dot_pair_f32((float)al, (float)be, (float)(al - be), (float)(al + be), dph, dpp,
+                          Exp2F(), RcpF());
+        const float* w = pyt + r * NH;
+#pragma unroll
+        for (int n = 0; n < NH; ++n) {
+          blk[0][n] = fmaf(dpp, w[n], blk[0][n]);
+          blk[1][n] = fmaf(dph, w[n], blk[1][n]);
+        }
+      }
+#pragma unroll
+      for (int n = 0; n < NH; ++n) {
+        neumaier_add(sum[0][n], cmp[0][n], blk[0][n]);
+        neumaier_add(sum[1][n], cmp[1][n], blk[1][n]);
+      }
+    }
+  }
+  for (int cc = 0; cc < nchunk; ++cc) {
+    if (active && c == cc) {
+      double* dst = rs + px * 2 * NH;
+#pragma unroll
+      for (int n = 0; n < NH; ++n) {
+        dst[n] += (double)sum[0][n] + (double)cmp[0][n];
+        dst[NH + n] += (double)sum[1][n] + (double)cmp[1][n];
+      }
+    }
+    __syncthreads();
+  }
+  const int nout = 2 * d.nsh;
+  int nseg = (int)blockDim.x / nout;
+  if (nseg < 1) nseg = 1;
+  for (int w = threadIdx.x; w < nout * nseg; w += blockDim.x) {
+    const int o = w % nout, seg = w / nout;
+    const int ch = o / d.nsh, j = o % d.nsh;
+    const int sx = d.hx[j], sy = d.hy[j];
+    const int ay = sy < 0 ? -sy : sy;
+    const double sg = sy < 0 ? -1.0 : 1.0;
+    double g = 0.0;
+    for (int x = seg; x < lk; x += nseg) {
+      const double* r = rs + x * 2 * NH + ch * NH;
+      double v = d.pxtab[x * NH + sx] * r[ay];
+      if (sx > 0 && ay > 0) v = fma(-sg * d.pxtab[x * NH + SMAX + sx], r[SMAX + ay], v);
+      g += v;
+    }
+    gh[seg * nout + o] = g;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+    double g = 0.0;
+    for (int s2 = 0; s2 < nseg; ++s2) g += gh[s2 * nout + o];
+    gh[o] = g;
+  }
+  __syncthreads();
+  const int nff2 = d.nff * d.nff;
+  const double base = 1.0 / (4.0 * T * T * (double)lk * (double)lk);
+  for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
+    const int ch = w / nff2, mn = w % nff2;
+    const double* e = d.ebub + (size_t)mn * d.nsh;
+    const double* g = gh + ch * d.nsh;
+    double v = 0.0;
+    for (int j = 0; j < d.nsh; ++j) v = fma(e[j], g[j], v);
+    v *= (ch == 0 ? -base : base);
+    if (nsplit == 1)
+      dchi[(size_t)ch * S + (size_t)q * nff2 + mn] = v;
+    else
+      dpart[(((size_t)split * 2 + ch) * d.nq + q) * nff2 + mn] = v;
+  }
+}
+
+// BF16 hi/lo split with round to nearest even: x ~ hi + lo (about 16 mantissa
+// bits); products hi*hi + hi*lo + lo*hi accumulate in FP32 on the matrix cores.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+  return __uint_as_float(((unsigned int)h) << 16);
+}
+__device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigned short& lo) {
+  const float f = (float)x;
+  hi = bf16_rne(f);
+  lo = bf16_rne(f - bf16_to_f32(hi));
+}
+
+// Forward transform on the matrix cores:
+//   xt[ch][k][mn] = (1/Nq) sum_u E[u][k] X[ch][u][mn]
+// as C[M=ncol][N=3 nff^2] = A^T B with A = E (pre-split, [Nq][ncol]) and
+// B = X (split on the fly).  One 16x16 output tile per block; its 4 waves
+// split the transfer grid and are added in LDS in a fixed order.
+// v_mfma_f32_16x16x16bf16_1k operand layout: lane l holds A[l%16][4(l/16)+j],
+// B[4(l/16)+j][l%16] (j = 0..3) and D[4(l/16)+j][l%16].
+__global__ void __launch_bounds__(256)
+k_dft_fwd_mfma(const unsigned short* __restrict__ eh, const unsigned short* __restrict__ el,
+               int nq, int ncol, const double* __restrict__ X, int64_t S, int nff2,
+               double* __restrict__ xt) {
+  __shared__ float red[4][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m0 = blockIdx.x * 16, n0 = blockIdx.y * 16;
+  const int ml = m0 + (lane & 15), nl = n0 + (lane & 15), kq = 4 * (lane >> 4);
+  const bool mok = ml < ncol, nok = nl < 3 * nff2;
+  const int ch = nok ? nl / nff2 : 0, mn = nok ? nl % nff2 : 0;
+  const double* xp = X + (size_t)ch * S + mn;
+  const int nsteps = (nq + 15) / 16;
+  const int s0 = nsteps * w / 4, s1 = nsteps * (w + 1) / 4;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int st = s0; st < s1; ++st) {
+    bf16x4 ah, al, bh, bl;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int u = st * 16 + kq + j;
+      const bool ok = u < nq;
+      ah[j] = (short)((ok && mok) ? eh[(size_t)u * ncol + ml] : 0);
+      al[j] = (short)((ok && mok) ? el[(size_t)u * ncol + ml] : 0);
+      unsigned short h = 0, l = 0;
+      if (ok && nok) split_bf16(xp[(size_t)u * nff2], h, l);
+      bh[j] = (short)h;
+      bl[j] = (short)l;
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) red[w][lane * 4 + j] = acc[j];
+  __syncthreads();
+  if (w == 0) {
+    const double inv = 1.0 / (double)nq;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double v = ((double)red[0][lane * 4 + j] + (double)red[1][lane * 4 + j]) +
+                       ((double)red[2][lane * 4 + j] + (double)red[3][lane * 4 + j]);
+      const int m = m0 + kq + j, n = n0 + (lane & 15);
+      if (m < ncol && n < 3 * nff2) {
+        const int c2 = n / nff2, mn2 = n % nff2;
+        xt[((size_t)c2 * ncol + m) * nff2 + mn2] = v * inv;
+      }
+    }
+  }
+}
+
+// Inverse transform on the matrix cores:
+//   K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn]
+// as C[M=Nq][N=3 nff^2] = A B with A = E (pre-split, [Nq][ncol]) and B = g2
+// (split on the fly).  Each wave owns one 16x16 output tile.
+__global__ void __launch_bounds__(256)
+k_dft_inv_mfma(const unsigned short* __restrict__ eh, const unsigned short* __restrict__ el,
+               int nq, int ncol, const double* __restrict__ g2, int nff2, float* __restrict__ K) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m0 = blockIdx.x * 16, n0 = (blockIdx.y * 4 + w) * 16;
+  const int ml = m0 + (lane & 15), nl = n0 + (lane & 15), kq = 4 * (lane >> 4);
+  const bool mok = ml < nq, nok = nl < 3 * nff2;
+  const int ch = nok ? nl / nff2 : 0, mn = nok ? nl % nff2 : 0;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < ncol; k0 += 16) {
+    bf16x4 ah, al, bh, bl;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + kq + j;
+      const bool ok = k < ncol;
+      ah[j] = (short)((ok && mok) ? eh[(size_t)ml * ncol + k] : 0);
+      al[j] = (short)((ok && mok) ? el[(size_t)ml * ncol + k] : 0);
+      unsigned short h = 0, l = 0;
+      if (ok && nok) split_bf16(g2[((size_t)ch * ncol + k) * nff2 + mn], h, l);
+      bh[j] = (short)h;
+      bl[j] = (short)l;
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int m = m0 + kq + j, n = n0 + (lane & 15);
+    if (m < nq && n < 3 * nff2) {
+      const int c2 = n / nff2, mn2 = n % nff2;
+      K[((size_t)c2 * nq + m) * nff2 + mn2] = acc[j];
+    }
+  }
+}
+
+// Assembly of V and the products in FP32; one block per momentum.  Inputs:
+// K (inverse transform, FP32, may be null without cross terms), X and the
+// loops (FP64); output scale * dX/dT in FP64.
+__global__ void __launch_bounds__(256)
+k_products_f32(DevTables d, const double* __restrict__ X, int64_t S, const float* __restrict__ K,
+               const double* __restrict__ dchi, const double* __restrict__ dpart, int nsplit,
+               double* __restrict__ out, int mode, double scale) {
+  const int nff = d.nff, nff2 = nff * nff, nq = d.nq;
+  const int l = blockIdx.x;
+  extern __shared__ float fsm[];
+  float* Vs = fsm;              // [3][nff2]
+  float* Ch = Vs + 3 * nff2;    // [2][nff2]
+  float* Wm = Ch + 2 * nff2;    // [nff2]
+  float* T1 = Wm + nff2;        // [3][nff2]
+  float* T2 = T1 + 3 * nff2;    // [3][nff2]
+  for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
+    const int ch = w / nff2, mn = w % nff2;
+    const float bare = (mn == 0) ? (float)d.U : 0.0f;
+    const float own = (float)X[(size_t)ch * S + (size_t)l * nff2 + mn];
+    const float kk = K ? K[((size_t)ch * nq + l) * nff2 + mn] : 0.0f;
+    Vs[w] = bare + (ch == 0 ? -own : own) + kk;
+  }
+  if (mode == 0) {
+    __syncthreads();
+    for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x)
+      out[(size_t)(w / nff2) * S + (size_t)l * nff2 + w % nff2] = (double)Vs[w];
+    return;
+  }
+  for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
+    const int ch = w / nff2, mn = w % nff2;
+    double v;
+    if (nsplit == 1) {
+      v = dchi[(size_t)ch * S + (size_t)l * nff2 + mn];
+    } else {
+      v = 0.0;
+      for (int s2 = 0; s2 < nsplit; ++s2) v += dpart[(((size_t)s2 * 2 + ch) * nq + l) * nff2 + mn];
+    }
+    Ch[w] = (float)v;
+  }
+  __syncthreads();
+  const float* VP = Vs;
+  const float* VC = Vs + nff2;
+  const float* VD = Vs + 2 * nff2;
+  for (int w = threadIdx.x; w < nff2; w += blockDim.x) Wm[w] = 2.0f * VD[w] - VC[w];
+  __syncthreads();
+  for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
+    const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
+    const float* A = Ch + (which == 0 ? 0 : nff2) + m * nff;
+    const float* B = which == 0 ? VP : (which == 1 ? VC : Wm);
+    float v = 0.0f;
+    for (int k = 0; k < nff; ++k) v = fmaf(A[k], B[k * nff + n], v);
+    T1[w] = v;
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
+    const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
+    const float* A = (which == 0 ? VP : (which == 1 ? VC : Wm)) + m * nff;
+    const float* B = T1 + which * nff2;
+    float v = 0.0f;
+    for (int k = 0; k < nff; ++k) v = fmaf(A[k], B[k * nff + n], v);
+    T2[w] = v;
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < nff2; w += blockDim.x) {
+    const size_t o = (size_t)l * nff2 + w;
+    out[o] = scale * (double)T2[w];
+    out[(size_t)S + o] = -scale * (double)T2[nff2 + w];
+    out[2 * (size_t)S + o] = 0.5 * scale * ((double)T2[2 * nff2 + w] - (double)T2[nff2 + w]);
+  }
+}
+
 // ----------------------------------------------------------- ODE helpers
 struct SlopeSet {
   const double* k[7];
@@ -578,6 +903,76 @@ void launch_project_back(const DevTables& d, const double* X, int64_t S, const d
   while (lt > 1 && sm_bytes(lt) > 65536) --lt;
   hipLaunchKernelGGL(k_proj_back, dim3((d.nq + lt - 1) / lt), dim3(256), sm_bytes(lt), s, d, X, S,
                      g2, dchi, dpart, nsplit, out, mode, cross, scale, lt);
+}
+
+size_t loop_smem_mixed(const DevTables& d, const LoopGeom& g) {
+  const int rows = d.lk / 2 + 1, nrmax = (rows + g.nsplit - 1) / g.nsplit;
+  const int NH = 2 * d.smax + 1, nout = 2 * d.nsh;
+  int nseg = g.threads / nout;
+  if (nseg < 1) nseg = 1;
+  return sizeof(double) * ((size_t)2 * nrmax + (size_t)d.lk * 2 * NH + (size_t)nseg * nout) +
+         sizeof(float) * (((size_t)nrmax * NH + 1) & ~(size_t)1);
+}
+
+void launch_loops_mixed(const DevTables& d, double T, double* dchi, int64_t S, double* dpart,
+                        bool sum_slices, hipStream_t s) {
+  const LoopGeom g = loop_geometry(d);
+  const size_t sm = loop_smem_mixed(d, g);
+  const dim3 grid((unsigned)(d.nq * g.nsplit));
+  switch (d.smax) {
+    case 0:
+      hipLaunchKernelGGL(k_loops_mixed<0>, grid, dim3(g.threads), sm, s, d, T, g.nsplit, g.nchunk,
+                         dchi, S, dpart);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_loops_mixed<2>, grid, dim3(g.threads), sm, s, d, T, g.nsplit, g.nchunk,
+                         dchi, S, dpart);
+      break;
+    default:
+      hipLaunchKernelGGL(k_loops_mixed<4>, grid, dim3(g.threads), sm, s, d, T, g.nsplit, g.nchunk,
+                         dchi, S, dpart);
+      break;
+  }
+  if (sum_slices && g.nsplit > 1) {
+    const int nff2 = d.nff * d.nff;
+    const int64_t n = (int64_t)2 * d.nq * nff2;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_chi_sum, dim3(blocks), dim3(256), 0, s, dpart, g.nsplit, d.nq, nff2, dchi, S);
+  }
+}
+
+void launch_project_front_mixed(const DevTables& d, const double* X, int64_t S, double* xt,
+                                double* yb, double* g2, uint32_t flags, hipStream_t s) {
+  if (flags & TUFRG_NO_CROSS) return;
+  const int nff2 = d.nff * d.nff;
+  dim3 g1((d.ncol + 15) / 16, (3 * nff2 + 15) / 16);
+  hipLaunchKernelGGL(k_dft_fwd_mfma, g1, dim3(256), 0, s, d.eph_hi, d.eph_lo, d.nq, d.ncol, X, S,
+                     nff2, xt);
+  const int nv = 2 * d.nsh - 1;
+  const int total = 3 * nv * nff2;
+  hipLaunchKernelGGL(k_bond_basis, dim3((total + 255) / 256), dim3(256), 0, s, d, xt, yb);
+  const size_t sm_mid = sizeof(double) * 4 * (size_t)nff2;
+  hipLaunchKernelGGL(k_gather_g2, dim3(d.nsh, 3), dim3(256), sm_mid, s, d, yb, g2);
+}
+
+void launch_inverse_mixed(const DevTables& d, const double* g2, float* K, uint32_t flags,
+                          hipStream_t s) {
+  if (flags & TUFRG_NO_CROSS) return;
+  const int nff2 = d.nff * d.nff;
+  dim3 g((d.nq + 15) / 16, (3 * nff2 + 63) / 64);
+  hipLaunchKernelGGL(k_dft_inv_mfma, g, dim3(256), 0, s, d.eph_hi, d.eph_lo, d.nq, d.ncol, g2, nff2,
+                     K);
+}
+
+void launch_products_mixed(const DevTables& d, const double* X, int64_t S, const float* K,
+                           const double* dchi, const double* dpart, double* out, int mode,
+                           uint32_t flags, double scale, hipStream_t s) {
+  const int nff2 = d.nff * d.nff;
+  const int nsplit = loop_geometry(d).nsplit;
+  const float* Kp = (flags & TUFRG_NO_CROSS) ? nullptr : K;
+  hipLaunchKernelGGL(k_products_f32, dim3(d.nq), dim3(256), sizeof(float) * 12 * (size_t)nff2, s, d,
+                     X, S, Kp, dchi, dpart, nsplit, out, mode, scale);
 }
 
 void launch_axpy_stage(const double* X, const double* const* k, const double* coef, int nk,

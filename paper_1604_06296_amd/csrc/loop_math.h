@@ -96,3 +96,48 @@ __host__ __device__ inline void loop_dot_pair_t(double a, double b, double& dph,
 }
 
 }  // namespace tufrg
+
+namespace tufrg {
+
+// ------------------------------------------------------------- FP32 form
+// The same divided differences in single precision, for the mixed-precision
+// loops.  The caller forms a = alpha, b = beta and dm = alpha - beta,
+// dp = alpha + beta in FP64 (the energies carry |eps/T| up to ~1e4 at the
+// lowest temperatures, where FP32 energies would lose the Fermi surface) and
+// passes them rounded to FP32.  Exp2 and the reciprocal are template
+// parameters (hardware v_exp_f32 / v_rcp_f32 on the device, libm on the host).
+template <class Exp2, class Rcp>
+__host__ __device__ inline void loop_dot_pair_f32(float a, float b, float dm, float dp, float& dph,
+                                                  float& dpp, Exp2 ex2, Rcp rcp) {
+  const float kLog2e = 1.44269504088896341f;
+  const float ea = ex2(-fabsf(a) * kLog2e), eb = ex2(-fabsf(b) * kLog2e);   // e^{-|a|}, e^{-|b|}
+  const float qa = ea * ea, qb = eb * eb;
+  const float ra = rcp(1.0f + qa), rb = rcp(1.0f + qb);
+  const float sa = 2.0f * ea * ra, sb = 2.0f * eb * rb;                      // sech
+  const float ta = copysignf((1.0f - qa) * ra, a);                             // tanh
+  const float tb = copysignf((1.0f - qb) * rb, b);
+  const float s2b = sb * sb;
+  const float ha = a * sa * sa, hb = b * s2b;                                  // y sech^2 y
+  const float sab = a * sa * sb;
+  const float far_ph = (ha - hb) * rcp(dm);
+  const float far_pp = (ha + hb) * rcp(dp);
+  // The near-diagonal branch reaches out to |d| < 1 in single precision, so
+  // the far branch's cancellation is amplified by at most max|h|/1 (FP64 uses
+  // 1/4 with a shorter series).  sinh(d)/d to d^12 (next term < 2e-10 at |d| = 1).
+  auto sinhc1 = [](float d) {
+    const float z = d * d;
+    float p = 1.0f / 6227020800.0f;
+    p = fmaf(p, z, 1.0f / 39916800.0f);
+    p = fmaf(p, z, 1.0f / 362880.0f);
+    p = fmaf(p, z, 1.0f / 5040.0f);
+    p = fmaf(p, z, 1.0f / 120.0f);
+    p = fmaf(p, z, 1.0f / 6.0f);
+    return fmaf(p, z, 1.0f);
+  };
+  const float near_ph = fmaf(-sab * (ta + tb), sinhc1(dm), s2b);
+  const float near_pp = fmaf(-sab * (ta - tb), sinhc1(dp), s2b);
+  dph = fabsf(dm) < 1.0f ? near_ph : far_ph;
+  dpp = fabsf(dp) < 1.0f ? near_pp : far_pp;
+}
+
+}  // namespace tufrg

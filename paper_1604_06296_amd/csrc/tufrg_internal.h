@@ -74,6 +74,8 @@ struct DevTables {
   double* pytab; // [lk/2+1][2 smax + 1]
   double* cshift; // [lq][lk][2]: cos(p_j + q_i/2), cos(p_j - q_i/2) per axis
   double* eph;   // [nq][ncol]
+  unsigned short* eph_hi;  // BF16 split of eph (mixed precision): eph ~ hi + lo
+  unsigned short* eph_lo;
   int32_t* mrow;
   int32_t* ment;
   int32_t* hx;   // half set [nsh]
@@ -86,6 +88,7 @@ struct Workspace {
   double* yb;    // bond-basis transform [2 (re, im)][3][2 nsh - 1][nff^2]
   double* g2;    // inverse-transform coefficients [3][ncol][nff^2]
   double* dpart; // loop slices [nsplit][2][Nq][nff^2] (largest point)
+  float* kinv;   // mixed precision: inverse transform K [3][Nq][nff^2] (largest point)
   double* dchi;  // loops [2][S]
   double* stage; // RK stage state [3][S]
   double* k[7];  // RK slopes [3][S] each
@@ -134,6 +137,17 @@ void launch_project_front(const DevTables& d, const double* X, int64_t S, double
 void launch_project_back(const DevTables& d, const double* X, int64_t S, const double* g2,
                          const double* dchi, const double* dpart, double* out, int mode,
                          uint32_t flags, double scale, hipStream_t s);
+// mixed precision (TUFRG_MIXED): FP32 loops, BF16-split MFMA transforms, FP32 products
+void launch_loops_mixed(const DevTables& d, double T, double* dchi, int64_t S, double* dpart,
+                        bool sum_slices, hipStream_t s);
+void launch_project_front_mixed(const DevTables& d, const double* X, int64_t S, double* xt,
+                                double* yb, double* g2, uint32_t flags, hipStream_t s);
+void launch_inverse_mixed(const DevTables& d, const double* g2, float* K, uint32_t flags,
+                          hipStream_t s);
+void launch_products_mixed(const DevTables& d, const double* X, int64_t S, const float* K,
+                           const double* dchi, const double* dpart, double* out, int mode,
+                           uint32_t flags, double scale, hipStream_t s);
+size_t loop_smem_mixed(const DevTables& d, const LoopGeom& g);
 void launch_axpy_stage(const double* X, const double* const* k, const double* coef, int nk,
                        double h, double* out, int64_t n, hipStream_t s);
 void launch_maxabs(const double* X, int64_t n, unsigned long long* word, hipStream_t s);

@@ -159,6 +159,23 @@ def test_cfg2_full(tf):
     _assert_normwise(_host(ctx, ctx.rhs(T, Xd)), ref_rhs, what="cfg2 rhs")
 
 
+@pytest.mark.parametrize("which", ["cfg3", "cfg5"])
+def test_full_size_sampled(tf, which):
+    """N_ff = 21 at 48x48/128x128 and 64x64/160x160: every step on sampled momenta."""
+    w = synth.cfg3() if which == "cfg3" else synth.cfg5()
+    pt = w.points[0]
+    ff = FormFactors(pt.shells)
+    ctx = tf.Context([pt])
+    X = synth.random_channels(pt.nq, ff.nff, seed=4, scale=1.0)
+    qi = list(synth.sample_indices(pt.nq, 4, seed=9)) + [0, pt.nq - 1]
+    Xd = _to_dev(ctx, X)
+    T = 0.011
+    ref_rhs, ref_V, ref_chi = orhs.rhs(pt, T, X, ff, return_parts=True, q_index=qi)
+    _assert_normwise(_host(ctx, ctx.bubbles(T))[:, qi], ref_chi, what=f"{which} bubbles")
+    _assert_normwise(_host(ctx, ctx.project(Xd))[:, qi], ref_V, what=f"{which} project")
+    _assert_normwise(_host(ctx, ctx.rhs(T, Xd))[:, qi], ref_rhs, what=f"{which} rhs")
+
+
 def test_determinism(tf):
     pt = _pt(3, 12, 32)
     ff = FormFactors(3)
