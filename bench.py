@@ -147,7 +147,7 @@ def main():
         "config": {"workload": w.name, "Lq": pt.Lq, "Lk": pt.Lk, "nff": nff, "t": pt.t,
                    "tp": pt.tp, "filling": pt.filling, "mu": pt.mu, "U": pt.U,
                    "flow": flow_info, "flops_per_rhs": flops},
-        "roofline": {"bound": "alu", "kernel": "k_loops_f64", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": "k_loops", "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": None, "launch_us": loop_ms * 1e3},
         "cpu_baseline": cpu,

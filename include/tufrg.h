@@ -43,8 +43,11 @@
  * synchronising call (tufrg_sync, tufrg_flow).
  *
  * Concurrency: a context belongs to one host thread and one HIP stream.
- * Calls on one context must not overlap.  The hot calls (bubbles, project,
- * rhs, flow) allocate nothing; all workspace is allocated by tufrg_init.
+ * Calls on one context must not overlap.  The step calls (bubbles, project,
+ * rhs) allocate nothing; all their workspace is allocated by tufrg_init.
+ * tufrg_flow allocates its RK4 step tables the first time a larger nsteps
+ * is asked for, and instantiates (then destroys) a HIP graph when use_graph
+ * is set.
  */
 #ifndef TUFRG_H
 #define TUFRG_H
@@ -83,14 +86,27 @@ enum {
 };
 
 enum {
-  TUFRG_NO_CROSS = 1u << 0 /* drop every inter-channel projection term: V^P = U - P,
-                              V^C = U + C, V^D = U + D (decoupled channels; a test
-                              seam for closed forms, not part of the method) */
+  TUFRG_NO_CROSS = 1u << 0, /* drop every inter-channel projection term: V^P = U - P,
+                               V^C = U + C, V^D = U + D (decoupled channels; a test
+                               seam for closed forms, not part of the method) */
+  TUFRG_AUTOTUNE = 1u << 1, /* time candidate loop-kernel geometries (row slices per
+                               momentum x row chunks per column) for every distinct
+                               point shape, then both launch forms of the whole
+                               batch, during tufrg_init and keep the fastest;
+                               choices are read from and appended to the text file
+                               named by the environment variable TUFRG_TUNE_CACHE
+                               when it is set.  Results differ from the default
+                               geometry only by summation order. */
+  TUFRG_LOOP_QUEUE = 1u << 2 /* run the loop kernel as persistent blocks that take
+                               work items from a queue (default: one block per work
+                               item, items ordered costliest first); bit-identical
+                               results.  TUFRG_AUTOTUNE times both forms and keeps
+                               the faster, whatever this bit says. */
 };
 
 typedef struct {
   int32_t precision;       /* TUFRG_FP64 or TUFRG_MIXED */
-  uint32_t flags;          /* TUFRG_NO_CROSS */
+  uint32_t flags;          /* TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE */
 } tufrg_options;
 
 enum { TUFRG_RK4_LOG = 0, TUFRG_DOPRI5_LOG = 1 };
@@ -107,7 +123,12 @@ typedef struct {
   int32_t nsteps;
   double rtol, atol, h0;
   int32_t max_steps;       /* DOPRI5 step budget (0: 100000) */
-  int32_t use_graph;       /* RK4: capture each step in a HIP graph (1) or launch eagerly (0) */
+  int32_t use_graph;       /* RK4: capture one step of all points in a HIP graph and
+                              replay it (1), or launch every step eagerly (0).  Both
+                              give identical results: stage temperatures come from a
+                              device table indexed by a device step counter, and a
+                              point stops (is skipped by every kernel) at the end of
+                              the first step with max|X| > Xmax. */
 } tufrg_flow_opts;
 
 enum { TUFRG_FLOW_DIVERGED = 1, TUFRG_FLOW_REACHED_TMIN = 2, TUFRG_FLOW_NONFINITE = 3 };
@@ -139,6 +160,15 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
  * any output pointer may be NULL.  *total (if non-NULL) receives S. */
 tufrg_status tufrg_layout(const tufrg_ctx* ctx, int32_t point, int64_t* offset,
                           int32_t* Nq, int32_t* Nff, int64_t* total);
+
+/* Loop-kernel geometry chosen for point `point` (default heuristic or the
+ * autotuner): row slices of the half fine grid per transfer momentum, row
+ * chunks per fine-grid column, the block size shared by all points of the
+ * context, and the launch form (1: persistent blocks taking work items from
+ * a queue; 0: one block per work item, items ordered costliest first).  Any
+ * output pointer may be NULL.  Host-only. */
+tufrg_status tufrg_geometry(const tufrg_ctx* ctx, int32_t point, int32_t* nsplit,
+                            int32_t* nchunk, int32_t* threads, int32_t* persistent);
 
 /* Step ii.): dchi[2][S] = d/dT of the loops chi^pp, chi^ph of eqn. chis at
  * temperature T_host[p] > 0 for every point p.  dchi: device pointer. */

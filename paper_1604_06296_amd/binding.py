@@ -15,10 +15,12 @@ FLOW_STATUS = {1: "diverged", 2: "reached_tmin", 3: "nonfinite"}
 SCHEMES = {"rk4": 0, "dopri5": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 NO_CROSS = 1
+AUTOTUNE = 2
+LOOP_QUEUE = 4
 
 # every entry point declared in include/tufrg.h
-EXPORTS = ("tufrg_init", "tufrg_layout", "tufrg_bubbles", "tufrg_project", "tufrg_rhs",
-           "tufrg_flow", "tufrg_sync", "tufrg_flop_count", "tufrg_mu_from_filling",
+EXPORTS = ("tufrg_init", "tufrg_layout", "tufrg_geometry", "tufrg_bubbles", "tufrg_project",
+           "tufrg_rhs", "tufrg_flow", "tufrg_sync", "tufrg_flop_count", "tufrg_mu_from_filling",
            "tufrg_free", "tufrg_last_error")
 
 
@@ -69,6 +71,8 @@ def load_library():
     lib.tufrg_init.argtypes = [C.POINTER(_Point), i32, C.POINTER(_Options), vp, C.POINTER(vp)]
     lib.tufrg_layout.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
                                  C.POINTER(i64)]
+    lib.tufrg_geometry.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                   C.POINTER(i32)]
     lib.tufrg_bubbles.argtypes = [vp, dp, vp]
     lib.tufrg_project.argtypes = [vp, vp, vp]
     lib.tufrg_rhs.argtypes = [vp, dp, vp, vp]
@@ -136,7 +140,7 @@ class Context:
     """
 
     def __init__(self, points: Sequence, precision: str = "fp64", no_cross: bool = False,
-                 stream=None):
+                 stream=None, autotune: bool = False, loop_queue: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise TufrgError("a GPU is required (torch.cuda.is_available() is False)")
@@ -148,7 +152,9 @@ class Context:
             if p.mu is None:
                 raise TufrgError("point has no mu; solve mu_from_filling first")
             arr[i] = _Point(p.t, p.tp, p.mu, p.U, p.Lq, p.Lk, p.shells, 0)
-        opt = _Options(PRECISIONS[precision], NO_CROSS if no_cross else 0)
+        opt = _Options(PRECISIONS[precision],
+                       (NO_CROSS if no_cross else 0) | (AUTOTUNE if autotune else 0)
+                       | (LOOP_QUEUE if loop_queue else 0))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = C.c_void_p()
         _check(self.lib, None, self.lib.tufrg_init(arr, n, C.byref(opt),
@@ -163,6 +169,13 @@ class Context:
                                                              C.byref(nff), C.byref(tot)))
             self.layouts.append((off.value, nq.value, nff.value))
             self.S = tot.value
+
+    def geometry(self, point: int = 0):
+        """Loop kernel: (row slices per momentum, row chunks per column, block size, persistent)."""
+        ns, nc, th, pe = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(self.lib, self.ctx, self.lib.tufrg_geometry(self.ctx, point, C.byref(ns), C.byref(nc),
+                                                           C.byref(th), C.byref(pe)))
+        return ns.value, nc.value, th.value, bool(pe.value)
 
     # ---------------------------------------------------------------- helpers
     def _T(self, T) -> "C.Array":

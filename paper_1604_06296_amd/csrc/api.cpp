@@ -1,11 +1,17 @@
-// C ABI of the TUfRG library: context, validation, workspace, step calls and
-// the ODE flow driver.
+// C ABI of the TUfRG library: context, validation, tables and workspace, the
+// work-item tables that let one launch cover any set of points, the step
+// calls, the loop-geometry autotuner and the ODE flow driver (batched RK4 with
+// device-side stopping and optional HIP-graph replay; per-point Dormand-Prince).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -30,65 +36,593 @@ tufrg_status fail(tufrg_ctx* ctx, tufrg_status st, const std::string& msg) {
       return fail(ctx, TUFRG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+#define ST_TRY(expr)               \
+  do {                             \
+    tufrg_status s_ = (expr);      \
+    if (s_ != TUFRG_OK) return s_; \
+  } while (0)
+
+// device allocation of `count` elements recorded in `list` (freed with it)
 template <class T>
-tufrg_status upload(tufrg_ctx* ctx, const std::vector<T>& v, T** out) {
-  *out = nullptr;
-  size_t bytes = std::max<size_t>(sizeof(T), v.size() * sizeof(T));
+tufrg_status dalloc(tufrg_ctx* ctx, size_t count, T** out, std::vector<void*>& list) {
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return fail(ctx, TUFRG_ENOMEM, "hipMalloc failed (tables)");
-  ctx->allocations.push_back(p);
-  if (!v.empty()) HIP_TRY(ctx, hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  if (hipMalloc(&p, std::max<size_t>(count * sizeof(T), 16)) != hipSuccess)
+    return fail(ctx, TUFRG_ENOMEM, "hipMalloc failed (" + std::to_string(count * sizeof(T)) + " bytes)");
+  list.push_back(p);
   *out = static_cast<T*>(p);
   return TUFRG_OK;
 }
 
-tufrg_status dalloc(tufrg_ctx* ctx, size_t bytes, void** out) {
-  void* p = nullptr;
-  if (hipMalloc(&p, std::max<size_t>(bytes, 8)) != hipSuccess)
-    return fail(ctx, TUFRG_ENOMEM, "hipMalloc failed (workspace)");
-  ctx->allocations.push_back(p);
-  *out = p;
+template <class T>
+tufrg_status upload(tufrg_ctx* ctx, const std::vector<T>& v, T** out, std::vector<void*>& list) {
+  ST_TRY(dalloc(ctx, std::max<size_t>(v.size(), 1), out, list));
+  if (!v.empty()) HIP_TRY(ctx, hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   return TUFRG_OK;
 }
 
-#define ST_TRY(expr)                      \
-  do {                                    \
-    tufrg_status s_ = (expr);             \
-    if (s_ != TUFRG_OK) return s_;        \
-  } while (0)
-
-// One right-hand side of point p: out = scale * dX/dT at temperature T.
-// The loops depend on T only and run on the side stream, concurrently with
-// the X-dependent front end of the projections on the main stream; the back
-// end (inverse transform, V, products) joins both.
-void rhs_point(tufrg_ctx* ctx, int p, double T, const double* X, double* out, double scale) {
-  const DevTables& d = ctx->dev[p];
-  const int64_t off = ctx->off[p];
-  if (ctx->opt.precision == TUFRG_MIXED) {
-    hipEventRecord(ctx->ev_fork, ctx->stream);
-    hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
-    launch_loops_mixed(d, T, ctx->ws.dchi + off, ctx->S, ctx->ws.dpart, false, ctx->side);
-    hipEventRecord(ctx->ev_join, ctx->side);
-    launch_project_front_mixed(d, X + off, ctx->S, ctx->ws.xt, ctx->ws.yb, ctx->ws.g2,
-                               ctx->opt.flags, ctx->stream);
-    launch_inverse_mixed(d, ctx->ws.g2, ctx->ws.kinv, ctx->opt.flags, ctx->stream);
-    hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
-    launch_products_mixed(d, X + off, ctx->S, ctx->ws.kinv, ctx->ws.dchi + off, ctx->ws.dpart,
-                          out + off, 1, ctx->opt.flags, scale, ctx->stream);
-    return;
+// ------------------------------------------------------- BF16 split (host)
+// round-to-nearest-even BF16 bits of a float, and the hi/lo split of a double
+unsigned short bf16_bits(float f) {
+  unsigned int u;
+  std::memcpy(&u, &f, sizeof u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+float bf16_value(unsigned short h) {
+  unsigned int u = ((unsigned int)h) << 16;
+  float f;
+  std::memcpy(&f, &u, sizeof f);
+  return f;
+}
+void split_table(const std::vector<double>& x, std::vector<unsigned short>& hi,
+                 std::vector<unsigned short>& lo) {
+  hi.resize(x.size());
+  lo.resize(x.size());
+  for (size_t i = 0; i < x.size(); ++i) {
+    const float f = (float)x[i];
+    hi[i] = bf16_bits(f);
+    lo[i] = bf16_bits(f - bf16_value(hi[i]));
   }
-  hipEventRecord(ctx->ev_fork, ctx->stream);
-  hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
-  launch_loops(d, T, ctx->ws.dchi + off, ctx->S, ctx->ws.dpart, false, ctx->side);
-  hipEventRecord(ctx->ev_join, ctx->side);
-  launch_project_front(d, X + off, ctx->S, ctx->ws.xt, ctx->ws.yb, ctx->ws.g2, ctx->opt.flags,
-                       ctx->stream);
-  hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
-  launch_project_back(d, X + off, ctx->S, ctx->ws.g2, ctx->ws.dchi + off, ctx->ws.dpart, out + off,
-                      1, ctx->opt.flags, scale, ctx->stream);
 }
 
-// ----------------------------------------------------- classification
+double word_to_double(unsigned long long w) {
+  double d;
+  std::memcpy(&d, &w, sizeof d);
+  return d;
+}
+
+// ------------------------------------------------------- loop geometry
+int round64(int x) { return ((x + 63) / 64) * 64; }
+
+// LDS bytes of the loop kernel for point d in blocks of `threads` threads
+size_t loop_smem_of(const DevTables& d, int threads) {
+  const int rows = d.lk / 2 + 1, nrmax = (rows + d.nsplit - 1) / d.nsplit;
+  const int NH = 2 * d.smax + 1, nout = 2 * d.nsh;
+  int nseg = threads / nout;
+  if (nseg < 1) nseg = 1;
+  return sizeof(double) *
+         ((size_t)2 * nrmax + (size_t)nrmax * NH + (size_t)d.lk * 2 * NH + (size_t)nseg * nout);
+}
+
+// Default loop geometry: split the half fine grid of every transfer momentum
+// into row slices (separate work items) and row chunks (threads of one
+// column) until about 8 waves per SIMD are in flight, keeping at least 4 rows
+// per thread and at most kLoopThreadsMax threads per block.
+void default_geometry(DevTables& d) {
+  const int rows = d.lk / 2 + 1;
+  const int64_t target = (int64_t)256 * 4 * 8 * 64;
+  int nsplit = 1, nchunk = 1;
+  for (;;) {
+    const int64_t lanes = (int64_t)d.nq * d.lk * nsplit * nchunk;
+    if (lanes >= target) break;
+    if (d.lk * (nchunk + 1) <= kLoopThreadsMax && rows / (nsplit * (nchunk + 1)) >= 4) {
+      ++nchunk;
+    } else if (nsplit < 16 && rows / ((nsplit + 1) * nchunk) >= 4) {
+      ++nsplit;
+    } else {
+      break;
+    }
+  }
+  d.nsplit = nsplit;
+  d.nchunk = nchunk;
+}
+
+// ------------------------------------------------------------ item tables
+struct HostItems {
+  std::vector<int4> loop, chi, fwd, fwd_mfma, basis, gather, inv_mfma, back, prod, seg;
+};
+
+template <class F>
+void mark(std::vector<int4>& v, ItemRange& rg, F fill) {
+  rg.begin = (int)v.size();
+  fill(v);
+  rg.n = (int)v.size() - rg.begin;
+}
+
+// The work items of point p for every kernel, appended to h; r receives the
+// point's ranges.  Item layouts are those documented at each kernel.
+void add_point_items(const DevTables& d, int p, HostItems& h, Ranges& r) {
+  const int nff2 = d.nff * d.nff, nv = 2 * d.nsh - 1;
+  mark(h.chi, r.chi, [&](std::vector<int4>& v) {
+    if (d.nsplit > 1)
+      for (int b = 0; b < (2 * d.nq * nff2 + 255) / 256; ++b) v.push_back(make_int4(p, b, 0, 0));
+  });
+  mark(h.fwd, r.fwd, [&](std::vector<int4>& v) {
+    for (int c = 0; c < (3 * nff2 + 63) / 64; ++c)
+      for (int k = 0; k < (d.ncol + 3) / 4; ++k) v.push_back(make_int4(p, c, k, 0));
+  });
+  mark(h.fwd_mfma, r.fwd_mfma, [&](std::vector<int4>& v) {
+    for (int m = 0; m < (d.ncol + 15) / 16; ++m)
+      for (int n = 0; n < (3 * nff2 + 15) / 16; ++n) v.push_back(make_int4(p, m, n, 0));
+  });
+  mark(h.basis, r.basis, [&](std::vector<int4>& v) {
+    for (int b = 0; b < (3 * nv * nff2 + 255) / 256; ++b) v.push_back(make_int4(p, b, 0, 0));
+  });
+  mark(h.gather, r.gather, [&](std::vector<int4>& v) {
+    for (int j = 0; j < d.nsh; ++j)
+      for (int X = 0; X < 3; ++X) v.push_back(make_int4(p, j, X, 0));
+  });
+  mark(h.inv_mfma, r.inv_mfma, [&](std::vector<int4>& v) {
+    for (int m = 0; m < (d.nq + 15) / 16; ++m)
+      for (int n = 0; n < (3 * nff2 + 63) / 64; ++n) v.push_back(make_int4(p, m, n, 0));
+  });
+  mark(h.back, r.back, [&](std::vector<int4>& v) {
+    for (int l0 = 0; l0 < d.nq; l0 += d.lt) v.push_back(make_int4(p, l0, std::min(d.lt, d.nq - l0), 0));
+  });
+  mark(h.prod, r.prod, [&](std::vector<int4>& v) {
+    for (int l = 0; l < d.nq; ++l) v.push_back(make_int4(p, l, 0, 0));
+  });
+  mark(h.seg, r.seg, [&](std::vector<int4>& v) {
+    const int chunks = (d.nq * nff2 + kSeg - 1) / kSeg;
+    for (int c = 0; c < 3; ++c)
+      for (int k = 0; k < chunks; ++k) v.push_back(make_int4(p, c, k, 0));
+  });
+}
+
+// loop items of one point: one per (transfer momentum, row slice)
+void add_loop_items(const DevTables& d, int p, std::vector<int4>& v, ItemRange& r) {
+  mark(v, r, [&](std::vector<int4>& w) {
+    for (int b = 0; b < d.nq * d.nsplit; ++b) w.push_back(make_int4(p, b, 0, 0));
+  });
+}
+
+bool mixed_of(const tufrg_ctx* ctx) { return ctx->opt.precision == TUFRG_MIXED; }
+bool cross_of(const tufrg_ctx* ctx) { return !(ctx->opt.flags & TUFRG_NO_CROSS); }
+
+// Item tables, slice buffers, launch shapes and the device table array from
+// the current per-point geometry (replaces those of an earlier build).
+tufrg_status build_launch(tufrg_ctx* ctx) {
+  const int npts = (int)ctx->dev.size();
+  const bool mixed = mixed_of(ctx);
+  if (!ctx->geometry_allocations.empty()) {
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    for (void* p : ctx->geometry_allocations) hipFree(p);
+    ctx->geometry_allocations.clear();
+  }
+  HostItems h;
+  ctx->per_point.assign(npts, Ranges());
+  // Loop items of costlier points first: the persistent loop kernel takes
+  // items in table order, so the longest tasks start first.
+  std::vector<int> order(npts);
+  std::iota(order.begin(), order.end(), 0);
+  auto cost = [&](int p) {
+    const DevTables& d = ctx->dev[p];
+    return (double)d.lk * (d.lk / 2 + 1) / d.nsplit * (2 * d.smax + 5);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  for (int p : order) add_loop_items(ctx->dev[p], p, h.loop, ctx->per_point[p].loop);
+  for (int p = 0; p < npts; ++p) add_point_items(ctx->dev[p], p, h, ctx->per_point[p]);
+  int smax_max = 0, threads = 64;
+  size_t lsm = 0, gsm = 0, bsm = 0, psm = 0;
+  int64_t dpart = 0;
+  for (int p = 0; p < npts; ++p) {
+    DevTables& d = ctx->dev[p];
+    smax_max = std::max(smax_max, d.smax);
+    threads = std::max(threads, round64(d.lk * d.nchunk));
+    const int nff2 = d.nff * d.nff;
+    gsm = std::max(gsm, sizeof(double) * 4 * (size_t)nff2);
+    bsm = std::max(bsm, sizeof(double) * ((size_t)d.lt * d.ncol + (size_t)d.lt * 3 * nff2 +
+                                          9 * (size_t)nff2));
+    psm = std::max(psm, sizeof(float) * 12 * (size_t)nff2);
+    d.ws_dpart = dpart;
+    if (d.nsplit > 1) dpart += (int64_t)d.nsplit * 2 * d.nq * nff2;
+  }
+  for (int p = 0; p < npts; ++p) lsm = std::max(lsm, loop_smem_of(ctx->dev[p], threads));
+  int dev_smem = 0;
+  hipDeviceGetAttribute(&dev_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
+  if (dev_smem > 0 && (lsm > (size_t)dev_smem || bsm > (size_t)dev_smem))
+    return fail(ctx, TUFRG_EINVAL, "grids too large for the shared memory of one block");
+  auto whole = [](const std::vector<int4>& v) {
+    ItemRange r;
+    r.n = (int)v.size();
+    return r;
+  };
+  Ranges& all = ctx->all;
+  all.loop = whole(h.loop); all.chi = whole(h.chi); all.fwd = whole(h.fwd);
+  all.fwd_mfma = whole(h.fwd_mfma); all.basis = whole(h.basis); all.gather = whole(h.gather);
+  all.inv_mfma = whole(h.inv_mfma); all.back = whole(h.back); all.prod = whole(h.prod);
+  all.seg = whole(h.seg);
+  Launch& L = ctx->L;
+  std::vector<void*>& g = ctx->geometry_allocations;
+  int4* t = nullptr;
+  ST_TRY(upload(ctx, h.loop, &t, g)); L.loop_items = t;
+  ST_TRY(upload(ctx, h.chi, &t, g)); L.chi_items = t;
+  ST_TRY(upload(ctx, h.fwd, &t, g)); L.fwd_items = t;
+  ST_TRY(upload(ctx, h.fwd_mfma, &t, g)); L.fwd_mfma_items = t;
+  ST_TRY(upload(ctx, h.basis, &t, g)); L.basis_items = t;
+  ST_TRY(upload(ctx, h.gather, &t, g)); L.gather_items = t;
+  ST_TRY(upload(ctx, h.inv_mfma, &t, g)); L.inv_mfma_items = t;
+  ST_TRY(upload(ctx, h.back, &t, g)); L.back_items = t;
+  ST_TRY(upload(ctx, h.prod, &t, g)); L.prod_items = t;
+  ST_TRY(upload(ctx, h.seg, &t, g)); L.seg_items = t;
+  L.b.dpart = nullptr;
+  if (dpart > 0) ST_TRY(dalloc(ctx, (size_t)dpart, &L.b.dpart, g));
+  DevTables* dp = nullptr;
+  ST_TRY(upload(ctx, ctx->dev, &dp, g));
+  L.b.pts = dp;
+  L.b.S = ctx->S;
+  L.b.Tp = ctx->Tp;
+  L.b.frozen = nullptr;
+  L.smax_max = smax_max;
+  L.loop_threads = threads;
+  L.loop_smem = lsm;
+  L.gather_smem = gsm;
+  L.back_smem = bsm;
+  L.prod_smem = psm;
+  // persistent loop grid: every CU filled to the kernel's occupancy
+  int per_cu = 0, cus = 0;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop_kernel_symbol(smax_max, mixed),
+                                                   threads, lsm) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  if (cus < 1) cus = 1;
+  L.loop_blocks = cus * per_cu;
+  L.loop_persistent = ctx->loop_persistent;
+  return TUFRG_OK;
+}
+
+// ------------------------------------------------------------ RHS driver
+// One right-hand side over the item ranges r on stream ms: out = dX/dT, or
+// T dX/dT (= dX/ds) when scale_T.  The loops depend on T only and run on the
+// side stream, concurrently with the X-dependent front end of the
+// projections; the back end (V and the products) joins both.
+void rhs_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, const double* X, double* out,
+                bool scale_T, hipStream_t ms) {
+  const bool mixed = mixed_of(ctx), cross = cross_of(ctx);
+  hipEventRecord(ctx->ev_fork, ms);
+  hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+  launch_loops(L, r.loop, ctx->queue, mixed, ctx->side);
+  hipEventRecord(ctx->ev_join, ctx->side);
+  if (cross) launch_front(L, r, X, mixed, ms);
+  hipStreamWaitEvent(ms, ctx->ev_join, 0);
+  launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms);
+}
+
+tufrg_status check_temperatures(tufrg_ctx* ctx, const double* T_host) {
+  for (size_t p = 0; p < ctx->dev.size(); ++p)
+    if (!(T_host[p] > 0.0) || !std::isfinite(T_host[p]))
+      return fail(ctx, TUFRG_EINVAL, "T must be finite and > 0 (point " + std::to_string(p) + ")");
+  return TUFRG_OK;
+}
+
+// ------------------------------------------------------------ autotuner
+// Times every candidate loop geometry (row slices x row chunks) of each
+// distinct point shape in launches of that point alone and keeps the fastest.
+std::string tune_key(const DevTables& d, int precision) {
+  char k[128];
+  std::snprintf(k, sizeof k, "gfx950_nq%d_lk%d_nff%d_prec%d", d.nq, d.lk, d.nff, precision);
+  return k;
+}
+
+tufrg_status autotune(tufrg_ctx* ctx) {
+  const int npts = (int)ctx->dev.size();
+  const bool mixed = mixed_of(ctx);
+  std::map<std::string, std::pair<int, int>> known;
+  const char* path = std::getenv("TUFRG_TUNE_CACHE");
+  if (path) {
+    std::ifstream in(path);
+    std::string k;
+    int a, b;
+    while (in >> k >> a >> b)
+      if (a >= 1 && b >= 1) known[k] = {a, b};
+  }
+  std::vector<double> T(npts, 0.05);
+  launch_set_T_values(ctx->Tp, T.data(), npts, ctx->stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  std::map<std::string, std::pair<int, int>> fresh;
+  tufrg_status st = TUFRG_OK;
+  for (int p = 0; p < npts && !st; ++p) {
+    DevTables& d = ctx->dev[p];
+    const std::string key = tune_key(d, ctx->opt.precision);
+    const int rows = d.lk / 2 + 1;
+    auto fits = [&](int ns, int nc) { return d.lk * nc <= kLoopThreadsMax && rows / (ns * nc) >= 3; };
+    std::pair<int, int> prior{0, 0};
+    if (known.count(key)) prior = known[key];
+    else if (fresh.count(key)) prior = fresh[key];
+    if (prior.first > 0 && fits(prior.first, prior.second)) {
+      d.nsplit = prior.first;
+      d.nchunk = prior.second;
+      continue;
+    }
+    double best = 1e300;
+    int bs = d.nsplit, bc = d.nchunk;
+    for (int ns = 1; ns <= 8 && !st; ns *= 2)
+      for (int nc = 1; nc <= 8 && !st; ++nc) {
+        if (!fits(ns, nc)) continue;
+        d.nsplit = ns;
+        d.nchunk = nc;
+        if ((st = build_launch(ctx))) break;
+        const ItemRange r = ctx->per_point[p].loop;
+        for (int w = 0; w < 2; ++w) launch_loops(ctx->L, r, ctx->queue, mixed, ctx->stream);
+        const int reps = 5;
+        float ms = 0.f;
+        if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = fail(ctx, TUFRG_EHIP, "event"); break; }
+        for (int w = 0; w < reps; ++w) launch_loops(ctx->L, r, ctx->queue, mixed, ctx->stream);
+        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          st = fail(ctx, TUFRG_EHIP, "autotuner timing failed");
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          bs = ns;
+          bc = nc;
+        }
+      }
+    d.nsplit = bs;
+    d.nchunk = bc;
+    fresh[key] = {bs, bc};
+  }
+  // launch form of the whole batch: one block per item, or the persistent queue
+  if (!st) st = build_launch(ctx);
+  double form_ms[2] = {0.0, 0.0};
+  for (int f = 0; f < 2 && !st; ++f) {
+    ctx->L.loop_persistent = (f == 1);
+    for (int w = 0; w < 2; ++w) launch_loops(ctx->L, ctx->all.loop, ctx->queue, mixed, ctx->stream);
+    const int reps = 5;
+    float ms = 0.f;
+    if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = fail(ctx, TUFRG_EHIP, "event"); break; }
+    for (int w = 0; w < reps; ++w) launch_loops(ctx->L, ctx->all.loop, ctx->queue, mixed, ctx->stream);
+    if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(ctx, TUFRG_EHIP, "autotuner timing failed");
+      break;
+    }
+    form_ms[f] = ms;
+  }
+  ctx->loop_persistent = !st && form_ms[1] < form_ms[0];
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st) return st;
+  if (path && !fresh.empty()) {
+    std::ofstream out(path, std::ios::app);
+    for (auto& kv : fresh)
+      if (!known.count(kv.first)) out << kv.first << " " << kv.second.first << " " << kv.second.second << "\n";
+  }
+  return build_launch(ctx);
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_options* opt, void* stream,
+                        tufrg_ctx** out) {
+  if (!out) return fail(nullptr, TUFRG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!pts || npts <= 0) return fail(nullptr, TUFRG_EINVAL, "need at least one point");
+  tufrg_options o{};
+  if (opt) o = *opt;
+  if (o.precision != TUFRG_FP64 && o.precision != TUFRG_MIXED)
+    return fail(nullptr, TUFRG_EINVAL, "precision must be TUFRG_FP64 or TUFRG_MIXED");
+  if (o.flags & ~(uint32_t)(TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE))
+    return fail(nullptr, TUFRG_EINVAL, "unknown flag bits");
+  auto* ctx = new tufrg_ctx();
+  ctx->opt = o;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  ctx->loop_persistent = (o.flags & TUFRG_LOOP_QUEUE) != 0;
+  ctx->host.resize(npts);
+  ctx->off.resize(npts);
+  ctx->dev.assign(npts, DevTables());
+  int64_t S = 0, ws_xt = 0, ws_yb = 0, ws_g2 = 0, ws_k = 0;
+  for (int p = 0; p < npts; ++p) {
+    std::string e = build_tables(pts[p], ctx->host[p]);
+    if (e.empty() && ctx->host[p].lk > kLoopThreadsMax)
+      e = "Lk must be <= " + std::to_string(kLoopThreadsMax);
+    if (!e.empty()) {
+      delete ctx;
+      return fail(nullptr, TUFRG_EINVAL, "point " + std::to_string(p) + ": " + e);
+    }
+    const HostTables& t = ctx->host[p];
+    DevTables& d = ctx->dev[p];
+    std::memset(&d, 0, sizeof d);
+    d.nff = t.nff; d.nq = t.nq; d.lq = t.p.Lq; d.lk = t.lk; d.nsh = t.nsh; d.ncol = t.ncol;
+    d.smax = t.smax; d.nshell = t.nshell;
+    d.t = t.p.t; d.tp = t.p.tp; d.mu = t.p.mu; d.U = t.p.U;
+    default_geometry(d);
+    // momenta per block of the FP64 back end: 2 on large grids while its LDS
+    // stays within 64 KiB
+    const int nff2 = t.nff * t.nff;
+    auto back_bytes = [&](int l) {
+      return sizeof(double) * ((size_t)l * t.ncol + (size_t)l * 3 * nff2 + 9 * (size_t)nff2);
+    };
+    d.lt = t.nq >= 1024 ? 2 : 1;
+    while (d.lt > 1 && back_bytes(d.lt) > 65536) --d.lt;
+    d.off = S;
+    ctx->off[p] = S;
+    S += (int64_t)t.nq * nff2;
+    d.ws_xt = ws_xt;
+    ws_xt += (int64_t)3 * t.ncol * nff2;
+    d.ws_g2 = ws_g2;
+    ws_g2 += (int64_t)3 * t.ncol * nff2;
+    d.ws_yb = ws_yb;
+    ws_yb += (int64_t)2 * 3 * (2 * t.nsh - 1) * nff2;
+    d.ws_k = ws_k;
+    ws_k += (int64_t)3 * t.nq * nff2;
+  }
+  ctx->S = S;
+  // first device call: every argument has been validated
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return fail(nullptr, TUFRG_EHIP, "no HIP device");
+  }
+  auto bad = [&](tufrg_status st) {
+    std::string m = ctx->err;
+    tufrg_free(ctx);
+    return fail(nullptr, st, m);
+  };
+  std::vector<void*>& A = ctx->allocations;
+  for (int p = 0; p < npts; ++p) {
+    const HostTables& t = ctx->host[p];
+    DevTables& d = ctx->dev[p];
+    std::vector<double> cre(t.c.size()), cim(t.c.size());
+    for (size_t i = 0; i < t.c.size(); ++i) {
+      cre[i] = t.c[i].real();
+      cim[i] = t.c[i].imag();
+    }
+    std::vector<int> ss(t.shell_start, t.shell_start + t.nshell + 1);
+    std::vector<int> so(t.nff);
+    for (int s = 0; s < t.nshell; ++s)
+      for (int m = t.shell_start[s]; m < t.shell_start[s + 1]; ++m) so[m] = s;
+    std::vector<int32_t> hx(t.hx.begin(), t.hx.end()), hy(t.hy.begin(), t.hy.end());
+    std::vector<unsigned short> ehi, elo;
+    split_table(t.eph, ehi, elo);
+    tufrg_status st;
+    if ((st = upload(ctx, cre, &d.cre, A)) || (st = upload(ctx, cim, &d.cim, A)) ||
+        (st = upload(ctx, ss, &d.shell_start, A)) || (st = upload(ctx, so, &d.shell_of, A)) ||
+        (st = upload(ctx, t.ebub, &d.ebub, A)) || (st = upload(ctx, t.pxtab, &d.pxtab, A)) ||
+        (st = upload(ctx, t.pytab, &d.pytab, A)) || (st = upload(ctx, t.eph, &d.eph, A)) ||
+        (st = upload(ctx, t.cshift, &d.cshift, A)) || (st = upload(ctx, ehi, &d.eph_hi, A)) ||
+        (st = upload(ctx, elo, &d.eph_lo, A)) || (st = upload(ctx, t.mrow, &d.mrow, A)) ||
+        (st = upload(ctx, t.ment, &d.ment, A)) || (st = upload(ctx, hx, &d.hx, A)) ||
+        (st = upload(ctx, hy, &d.hy, A)))
+      return bad(st);
+  }
+  // workspace, state buffers and control words
+  Batch& B = ctx->L.b;
+  const size_t s3 = 3 * (size_t)S;
+  tufrg_status st = TUFRG_OK;
+  if (!st) st = dalloc(ctx, 2 * (size_t)S, &B.dchi, A);
+  if (!st) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_xt, 1), &B.xt, A);
+  if (!st) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_yb, 1), &B.yb, A);
+  if (!st) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_g2, 1), &B.g2, A);
+  B.kinv = nullptr;
+  if (!st && o.precision == TUFRG_MIXED) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_k, 1), &B.kinv, A);
+  if (!st) st = dalloc(ctx, (size_t)npts, &ctx->Tp, A);
+  if (!st) st = dalloc(ctx, (size_t)npts, &ctx->frozen, A);
+  if (!st) st = dalloc(ctx, 2, &ctx->queue, A);
+  if (!st) st = dalloc(ctx, s3, &ctx->stage, A);
+  if (!st) st = dalloc(ctx, s3, &ctx->ytmp, A);
+  for (int i = 0; i < 7 && !st; ++i) st = dalloc(ctx, s3, &ctx->kk[i], A);
+  if (!st) st = dalloc(ctx, (size_t)npts, &ctx->umax, A);
+  if (!st) st = dalloc(ctx, 1, &ctx->step, A);
+  if (st) return bad(st);
+  if (hipHostMalloc((void**)&ctx->umax_host, sizeof(unsigned long long) * npts, 0) != hipSuccess)
+    return bad(fail(ctx, TUFRG_ENOMEM, "pinned host allocation failed"));
+  // side and graph streams (default priority) and the fork/join events
+  if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->gs, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_gs, hipEventDisableTiming) != hipSuccess)
+    return bad(fail(ctx, TUFRG_EHIP, "stream or event creation failed"));
+  // loop-kernel work queue: zero once, then reset by every launch at its end
+  launch_fill_i32(ctx->queue, 2, 0, ctx->stream);
+  // item tables and launch shapes, tuned on request
+  st = build_launch(ctx);
+  if (!st && (o.flags & TUFRG_AUTOTUNE)) st = autotune(ctx);
+  if (st) return bad(st);
+  if (hipDeviceSynchronize() != hipSuccess)
+    return bad(fail(ctx, TUFRG_EHIP, "device synchronize failed after init"));
+  *out = ctx;
+  return TUFRG_OK;
+}
+
+tufrg_status tufrg_layout(const tufrg_ctx* ctx, int32_t point, int64_t* offset, int32_t* Nq,
+                          int32_t* Nff, int64_t* total) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  if (point < 0 || point >= (int)ctx->host.size())
+    return fail(const_cast<tufrg_ctx*>(ctx), TUFRG_EINVAL, "point out of range");
+  if (offset) *offset = ctx->off[point];
+  if (Nq) *Nq = ctx->host[point].nq;
+  if (Nff) *Nff = ctx->host[point].nff;
+  if (total) *total = ctx->S;
+  return TUFRG_OK;
+}
+
+tufrg_status tufrg_geometry(const tufrg_ctx* ctx, int32_t point, int32_t* nsplit, int32_t* nchunk,
+                            int32_t* threads, int32_t* persistent) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  if (point < 0 || point >= (int)ctx->dev.size())
+    return fail(const_cast<tufrg_ctx*>(ctx), TUFRG_EINVAL, "point out of range");
+  if (nsplit) *nsplit = ctx->dev[point].nsplit;
+  if (nchunk) *nchunk = ctx->dev[point].nchunk;
+  if (threads) *threads = ctx->L.loop_threads;
+  if (persistent) *persistent = ctx->L.loop_persistent ? 1 : 0;
+  return TUFRG_OK;
+}
+
+tufrg_status tufrg_bubbles(tufrg_ctx* ctx, const double* T_host, double* dchi) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  if (!T_host || !dchi) return fail(ctx, TUFRG_EINVAL, "NULL argument");
+  ST_TRY(check_temperatures(ctx, T_host));
+  launch_set_T_values(ctx->Tp, T_host, (int)ctx->dev.size(), ctx->stream);
+  Launch L = ctx->L;
+  L.b.dchi = dchi;
+  launch_loops(L, ctx->all.loop, ctx->queue, mixed_of(ctx), ctx->stream);
+  launch_chi_sum(L, ctx->all.chi, dchi, ctx->stream);
+  HIP_TRY(ctx, hipGetLastError());
+  return TUFRG_OK;
+}
+
+tufrg_status tufrg_project(tufrg_ctx* ctx, const double* X, double* V) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  if (!X || !V) return fail(ctx, TUFRG_EINVAL, "NULL argument");
+  if (X == V) return fail(ctx, TUFRG_EINVAL, "X and V must not alias");
+  const bool mixed = mixed_of(ctx), cross = cross_of(ctx);
+  if (cross) launch_front(ctx->L, ctx->all, X, mixed, ctx->stream);
+  launch_back(ctx->L, ctx->all, X, V, 0, cross, false, mixed, ctx->stream);
+  HIP_TRY(ctx, hipGetLastError());
+  return TUFRG_OK;
+}
+
+tufrg_status tufrg_rhs(tufrg_ctx* ctx, const double* T_host, const double* X, double* dXdT) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  if (!T_host || !X || !dXdT) return fail(ctx, TUFRG_EINVAL, "NULL argument");
+  if (X == dXdT) return fail(ctx, TUFRG_EINVAL, "X and dXdT must not alias");
+  ST_TRY(check_temperatures(ctx, T_host));
+  launch_set_T_values(ctx->Tp, T_host, (int)ctx->dev.size(), ctx->stream);
+  rhs_launch(ctx, ctx->L, ctx->all, X, dXdT, false, ctx->stream);
+  HIP_TRY(ctx, hipGetLastError());
+  return TUFRG_OK;
+}
+
+tufrg_status tufrg_sync(tufrg_ctx* ctx) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  HIP_TRY(ctx, hipGetLastError());
+  return TUFRG_OK;
+}
+
+tufrg_status tufrg_flop_count(const tufrg_ctx* ctx, double out[3]) {
+  if (!ctx || !out) return fail(nullptr, TUFRG_EINVAL, "NULL argument");
+  out[0] = out[1] = out[2] = 0.0;
+  for (const HostTables& t : ctx->host) {
+    out[0] += (double)t.flops_loops;
+    out[1] += (double)t.flops_proj;
+    out[2] += (double)t.flops_prod;
+  }
+  return TUFRG_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ flow
+namespace {
+
 // Cyclic Jacobi eigenvalue iteration for a small real symmetric matrix.
 void jacobi_eig(std::vector<double> a, int n, std::vector<double>& w, std::vector<double>& v) {
   v.assign((size_t)n * n, 0.0);
@@ -134,7 +668,10 @@ void classify(const HostTables& t, const std::vector<double>& x /*[3][nq][nff][n
   size_t best = 0;
   double bv = -1.0;
   for (size_t i = 0; i < x.size(); ++i)
-    if (std::fabs(x[i]) > bv) { bv = std::fabs(x[i]); best = i; }
+    if (std::fabs(x[i]) > bv) {
+      bv = std::fabs(x[i]);
+      best = i;
+    }
   const int ch = (int)(best / ((size_t)t.nq * nff2));
   const int q = (int)((best / nff2) % t.nq);
   std::vector<double> m((size_t)nff2);
@@ -162,348 +699,160 @@ double interp_tc(double s0, double s1, double m0, double m1, double xmax) {
   return std::exp(sc);
 }
 
-// round-to-nearest-even BF16 bits of a float, and the hi/lo split of a double
-unsigned short bf16_bits(float f) {
-  unsigned int u;
-  std::memcpy(&u, &f, sizeof u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-float bf16_value(unsigned short h) {
-  unsigned int u = ((unsigned int)h) << 16;
-  float f;
-  std::memcpy(&f, &u, sizeof f);
-  return f;
-}
-void split_table(const std::vector<double>& x, std::vector<unsigned short>& hi,
-                 std::vector<unsigned short>& lo) {
-  hi.resize(x.size());
-  lo.resize(x.size());
-  for (size_t i = 0; i < x.size(); ++i) {
-    const float f = (float)x[i];
-    hi[i] = bf16_bits(f);
-    lo[i] = bf16_bits(f - bf16_value(hi[i]));
-  }
-}
-
-double word_to_double(unsigned long long w) {
-  double d;
-  std::memcpy(&d, &w, sizeof d);
-  return d;
-}
-
-}  // namespace
-
-// ================================================================== C ABI
-extern "C" {
-
-tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_options* opt, void* stream,
-                        tufrg_ctx** out) {
-  if (!out) return fail(nullptr, TUFRG_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!pts || npts <= 0) return fail(nullptr, TUFRG_EINVAL, "need at least one point");
-  tufrg_options o{};
-  if (opt) o = *opt;
-  if (o.precision != TUFRG_FP64 && o.precision != TUFRG_MIXED)
-    return fail(nullptr, TUFRG_EINVAL, "precision must be TUFRG_FP64 or TUFRG_MIXED");
-  if (o.flags & ~(uint32_t)TUFRG_NO_CROSS) return fail(nullptr, TUFRG_EINVAL, "unknown flag bits");
-  auto* ctx = new tufrg_ctx();
-  ctx->opt = o;
-  ctx->stream = static_cast<hipStream_t>(stream);
-  ctx->host.resize(npts);
-  ctx->off.resize(npts);
-  int64_t S = 0;
-  size_t max_xt = 8, max_yb = 8, max_gp = 8, max_k = 8;
-  for (int p = 0; p < npts; ++p) {
-    std::string e = build_tables(pts[p], ctx->host[p]);
-    if (!e.empty()) {
-      delete ctx;
-      return fail(nullptr, TUFRG_EINVAL, "point " + std::to_string(p) + ": " + e);
-    }
-    const HostTables& t = ctx->host[p];
-    if (t.lk > 512) {
-      delete ctx;
-      return fail(nullptr, TUFRG_EINVAL, "point " + std::to_string(p) + ": Lk must be <= 512");
-    }
-    ctx->off[p] = S;
-    S += (int64_t)t.nq * t.nff * t.nff;
-    max_xt = std::max(max_xt, (size_t)3 * t.ncol * t.nff * t.nff);
-    max_yb = std::max(max_yb, (size_t)2 * 3 * (2 * t.nsh - 1) * t.nff * t.nff);
-    max_k = std::max(max_k, (size_t)3 * t.nq * t.nff * t.nff);
-  }
-  ctx->S = S;
-  // device tables (first device call: every argument has been validated)
-  if (hipGetDevice(&ctx->device) != hipSuccess) {
-    delete ctx;
-    return fail(nullptr, TUFRG_EHIP, "no HIP device");
-  }
-  ctx->dev.resize(npts);
-  for (int p = 0; p < npts; ++p) {
-    const HostTables& t = ctx->host[p];
-    DevTables& d = ctx->dev[p];
-    d.nff = t.nff; d.nq = t.nq; d.lq = t.p.Lq; d.lk = t.lk; d.nsh = t.nsh; d.ncol = t.ncol;
-    d.smax = t.smax; d.nshell = t.nshell;
-    d.t = t.p.t; d.tp = t.p.tp; d.mu = t.p.mu; d.U = t.p.U;
-    std::vector<double> cre(t.c.size()), cim(t.c.size());
-    for (size_t i = 0; i < t.c.size(); ++i) { cre[i] = t.c[i].real(); cim[i] = t.c[i].imag(); }
-    std::vector<int> ss(t.shell_start, t.shell_start + t.nshell + 1);
-    std::vector<int> so(t.nff);
-    for (int s = 0; s < t.nshell; ++s)
-      for (int m = t.shell_start[s]; m < t.shell_start[s + 1]; ++m) so[m] = s;
-    std::vector<int32_t> hx(t.hx.begin(), t.hx.end()), hy(t.hy.begin(), t.hy.end());
-    std::vector<unsigned short> ehi, elo;
-    split_table(t.eph, ehi, elo);
-    tufrg_status st;
-    if ((st = upload(ctx, cre, &d.cre)) || (st = upload(ctx, cim, &d.cim)) ||
-        (st = upload(ctx, ss, &d.shell_start)) || (st = upload(ctx, so, &d.shell_of)) ||
-        (st = upload(ctx, t.ebub, &d.ebub)) || (st = upload(ctx, t.pxtab, &d.pxtab)) ||
-        (st = upload(ctx, t.pytab, &d.pytab)) || (st = upload(ctx, t.eph, &d.eph)) ||
-        (st = upload(ctx, t.cshift, &d.cshift)) || (st = upload(ctx, ehi, &d.eph_hi)) ||
-        (st = upload(ctx, elo, &d.eph_lo)) ||
-        (st = upload(ctx, t.mrow, &d.mrow)) || (st = upload(ctx, t.ment, &d.ment)) ||
-        (st = upload(ctx, hx, &d.hx)) || (st = upload(ctx, hy, &d.hy))) {
-      std::string m = ctx->err;
-      tufrg_free(ctx);
-      return fail(nullptr, st, m);
-    }
-    int dev_smem = 0;
-    hipDeviceGetAttribute(&dev_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
-    const LoopGeom g = loop_geometry(d);
-    if (dev_smem > 0 && g.smem > (size_t)dev_smem) {
-      tufrg_free(ctx);
-      return fail(nullptr, TUFRG_EINVAL, "point " + std::to_string(p) + ": fine grid too large");
-    }
-    max_gp = std::max(max_gp, (size_t)g.nsplit * 2 * t.nq * t.nff * t.nff);
-  }
-  // workspace
-  Workspace& w = ctx->ws;
-  const size_t b3 = sizeof(double) * 3 * (size_t)S;
-  tufrg_status st = TUFRG_OK;
-  void* v = nullptr;
-  if ((st = dalloc(ctx, sizeof(double) * max_xt, &v))) goto bad;
-  w.xt = (double*)v;
-  if ((st = dalloc(ctx, sizeof(double) * max_xt, &v))) goto bad;
-  w.g2 = (double*)v;
-  if ((st = dalloc(ctx, sizeof(double) * max_yb, &v))) goto bad;
-  w.yb = (double*)v;
-  if ((st = dalloc(ctx, sizeof(double) * max_gp, &v))) goto bad;
-  w.dpart = (double*)v;
-  if (o.precision == TUFRG_MIXED) {
-    if ((st = dalloc(ctx, sizeof(float) * max_k, &v))) goto bad;
-    w.kinv = (float*)v;
-  }
-  if ((st = dalloc(ctx, sizeof(double) * 2 * (size_t)S, &v))) goto bad;
-  w.dchi = (double*)v;
-  if ((st = dalloc(ctx, b3, &v))) goto bad;
-  w.stage = (double*)v;
-  if ((st = dalloc(ctx, b3, &v))) goto bad;
-  w.ytmp = (double*)v;
-  for (int i = 0; i < 7; ++i) {
-    if ((st = dalloc(ctx, b3, &v))) goto bad;
-    w.k[i] = (double*)v;
-  }
-  if ((st = dalloc(ctx, sizeof(double) * 1024, &v))) goto bad;
-  w.red = (double*)v;
-  if ((st = dalloc(ctx, sizeof(unsigned long long) * std::max(npts, 1), &v))) goto bad;
-  w.umax = (unsigned long long*)v;
-  // side stream (default priority) and the fork/join events of the right-hand side
-  if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
-    st = fail(ctx, TUFRG_EHIP, "stream or event creation failed");
-    goto bad;
-  }
-  if (hipDeviceSynchronize() != hipSuccess) {
-    st = fail(ctx, TUFRG_EHIP, "device synchronize failed after init");
-    goto bad;
-  }
-  *out = ctx;
-  return TUFRG_OK;
-bad : {
-  std::string m = ctx->err;
-  tufrg_free(ctx);
-  return fail(nullptr, st, m);
-}
-}
-
-tufrg_status tufrg_layout(const tufrg_ctx* ctx, int32_t point, int64_t* offset, int32_t* Nq,
-                          int32_t* Nff, int64_t* total) {
-  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
-  if (point < 0 || point >= (int)ctx->host.size())
-    return fail(const_cast<tufrg_ctx*>(ctx), TUFRG_EINVAL, "point out of range");
-  if (offset) *offset = ctx->off[point];
-  if (Nq) *Nq = ctx->host[point].nq;
-  if (Nff) *Nff = ctx->host[point].nff;
-  if (total) *total = ctx->S;
-  return TUFRG_OK;
-}
-
-tufrg_status tufrg_bubbles(tufrg_ctx* ctx, const double* T_host, double* dchi) {
-  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
-  if (!T_host || !dchi) return fail(ctx, TUFRG_EINVAL, "NULL argument");
-  for (size_t p = 0; p < ctx->dev.size(); ++p)
-    if (!(T_host[p] > 0.0) || !std::isfinite(T_host[p]))
-      return fail(ctx, TUFRG_EINVAL, "T must be finite and > 0");
-  for (size_t p = 0; p < ctx->dev.size(); ++p) {
-    if (ctx->opt.precision == TUFRG_MIXED)
-      launch_loops_mixed(ctx->dev[p], T_host[p], dchi + ctx->off[p], ctx->S, ctx->ws.dpart, true,
-                         ctx->stream);
-    else
-      launch_loops(ctx->dev[p], T_host[p], dchi + ctx->off[p], ctx->S, ctx->ws.dpart, true,
-                   ctx->stream);
-  }
-  HIP_TRY(ctx, hipGetLastError());
-  return TUFRG_OK;
-}
-
-tufrg_status tufrg_project(tufrg_ctx* ctx, const double* X, double* V) {
-  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
-  if (!X || !V) return fail(ctx, TUFRG_EINVAL, "NULL argument");
-  if (X == V) return fail(ctx, TUFRG_EINVAL, "X and V must not alias");
-  for (size_t p = 0; p < ctx->dev.size(); ++p) {
-    if (ctx->opt.precision == TUFRG_MIXED) {
-      const DevTables& d = ctx->dev[p];
-      launch_project_front_mixed(d, X + ctx->off[p], ctx->S, ctx->ws.xt, ctx->ws.yb, ctx->ws.g2,
-                                 ctx->opt.flags, ctx->stream);
-      launch_inverse_mixed(d, ctx->ws.g2, ctx->ws.kinv, ctx->opt.flags, ctx->stream);
-      launch_products_mixed(d, X + ctx->off[p], ctx->S, ctx->ws.kinv, nullptr, nullptr,
-                            V + ctx->off[p], 0, ctx->opt.flags, 1.0, ctx->stream);
-      continue;
-    }
-    launch_project_front(ctx->dev[p], X + ctx->off[p], ctx->S, ctx->ws.xt, ctx->ws.yb, ctx->ws.g2,
-                         ctx->opt.flags, ctx->stream);
-    launch_project_back(ctx->dev[p], X + ctx->off[p], ctx->S, ctx->ws.g2, nullptr, nullptr,
-                        V + ctx->off[p], 0, ctx->opt.flags, 1.0, ctx->stream);
-  }
-  HIP_TRY(ctx, hipGetLastError());
-  return TUFRG_OK;
-}
-
-tufrg_status tufrg_rhs(tufrg_ctx* ctx, const double* T_host, const double* X, double* dXdT) {
-  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
-  if (!T_host || !X || !dXdT) return fail(ctx, TUFRG_EINVAL, "NULL argument");
-  if (X == dXdT) return fail(ctx, TUFRG_EINVAL, "X and dXdT must not alias");
-  for (size_t p = 0; p < ctx->dev.size(); ++p)
-    if (!(T_host[p] > 0.0) || !std::isfinite(T_host[p]))
-      return fail(ctx, TUFRG_EINVAL, "T must be finite and > 0");
-  for (size_t p = 0; p < ctx->dev.size(); ++p) rhs_point(ctx, (int)p, T_host[p], X, dXdT, 1.0);
-  HIP_TRY(ctx, hipGetLastError());
-  return TUFRG_OK;
-}
-
-tufrg_status tufrg_sync(tufrg_ctx* ctx) {
-  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  HIP_TRY(ctx, hipGetLastError());
-  return TUFRG_OK;
-}
-
-tufrg_status tufrg_flop_count(const tufrg_ctx* ctx, double out[3]) {
-  if (!ctx || !out) return fail(nullptr, TUFRG_EINVAL, "NULL argument");
-  out[0] = out[1] = out[2] = 0.0;
-  for (const HostTables& t : ctx->host) {
-    out[0] += (double)t.flops_loops;
-    out[1] += (double)t.flops_proj;
-    out[2] += (double)t.flops_prod;
-  }
-  return TUFRG_OK;
-}
-
-// ------------------------------------------------------------------ flow
-namespace {
-
-struct PointView {
-  // a point's three channel blocks inside [3][S] arrays are addressed as
-  // ptr + off + c*S; the ODE kernels work on the whole [3][S] range when the
-  // context has one point and on per-channel blocks otherwise
-  int64_t off, n;
-};
-
-// out = X + h * sum_j coef_j k_j over the point's three channel blocks
-void axpy_point(tufrg_ctx* ctx, int p, const double* X, double* const* k, const double* coef, int nk,
-                double h, double* out) {
-  const int64_t off = ctx->off[p], S = ctx->S;
-  const HostTables& t = ctx->host[p];
-  const int64_t n = (int64_t)t.nq * t.nff * t.nff;
-  for (int c = 0; c < 3; ++c) {
-    const double* kk[7];
-    for (int j = 0; j < nk; ++j) kk[j] = k[j] + c * S + off;
-    launch_axpy_stage(X + c * S + off, kk, coef, nk, h, out + c * S + off, n, ctx->stream);
-  }
-}
-
-tufrg_status maxabs_point(tufrg_ctx* ctx, int p, const double* X, double* result) {
-  const int64_t off = ctx->off[p], S = ctx->S;
-  const HostTables& t = ctx->host[p];
-  const int64_t n = (int64_t)t.nq * t.nff * t.nff;
-  launch_fill_u64(ctx->ws.umax + p, 1, 0ull, ctx->stream);
-  for (int c = 0; c < 3; ++c) launch_maxabs(X + c * S + off, n, ctx->ws.umax + p, ctx->stream);
-  unsigned long long w = 0;
-  HIP_TRY(ctx, hipMemcpyAsync(&w, ctx->ws.umax + p, sizeof w, hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  *result = word_to_double(w);
-  return TUFRG_OK;
-}
-
-tufrg_status finish_point(tufrg_ctx* ctx, int p, const double* X, int status,
-                          const std::vector<double>& s_hist, const std::vector<double>& m_hist,
-                          double xmax, int64_t n_rhs, int64_t n_steps, tufrg_flow_result* r) {
+// Result of point p: status, counters, and for a divergence Tc by log-linear
+// interpolation between the last two accepted steps (s0, m0) -> (s1, m1) and
+// the classification of the stopped state X.
+tufrg_status finish_point(tufrg_ctx* ctx, int p, const double* X, int status, double s0, double s1,
+                          double m0, double m1, double xmax, int64_t n_rhs, int64_t n_steps,
+                          hipStream_t ms, tufrg_flow_result* r) {
   std::memset(r, 0, sizeof *r);
   r->status = status;
   r->n_rhs = n_rhs;
   r->n_steps = n_steps;
-  r->max_abs_X = m_hist.back();
+  r->max_abs_X = m1;
   r->channel = r->q_index = r->irrep = -1;
   r->Tc = 0.0;
   if (status == TUFRG_FLOW_DIVERGED) {
-    const size_t k = s_hist.size();
-    r->Tc = interp_tc(s_hist[k - 2], s_hist[k - 1], m_hist[k - 2], m_hist[k - 1], xmax);
+    r->Tc = interp_tc(s0, s1, m0, m1, xmax);
     const HostTables& t = ctx->host[p];
     const int64_t n = (int64_t)t.nq * t.nff * t.nff;
     std::vector<double> x((size_t)3 * n);
     for (int c = 0; c < 3; ++c)
-      HIP_TRY(ctx, hipMemcpy(x.data() + c * n, X + c * ctx->S + ctx->off[p], n * sizeof(double),
-                             hipMemcpyDeviceToHost));
+      HIP_TRY(ctx, hipMemcpyAsync(x.data() + c * n, X + c * ctx->S + ctx->off[p], n * sizeof(double),
+                                  hipMemcpyDeviceToHost, ms));
+    HIP_TRY(ctx, hipStreamSynchronize(ms));
     classify(t, x, r);
   }
   return TUFRG_OK;
 }
 
-tufrg_status flow_rk4_point(tufrg_ctx* ctx, int p, const tufrg_flow_opts* o, double* X,
-                            tufrg_flow_result* r) {
-  double* const* k = ctx->ws.k;
-  double* stage = ctx->ws.stage;
-  const double s0 = std::log(o->T0);
-  const double h = (std::log(o->Tmin) - s0) / o->nsteps;
-  std::vector<double> s_hist{s0}, m_hist;
-  double m;
-  ST_TRY(maxabs_point(ctx, p, X, &m));
-  m_hist.push_back(m);
-  int64_t n_rhs = 0;
-  double s = s0;
+// One RK4 step of every point still flowing, in s = ln T: stage temperatures
+// from the device table at the device step counter, slopes dX/ds, the update
+// (stopped points untouched), per-point max|X| and the device-side stop test.
+void rk4_step(tufrg_ctx* ctx, const Launch& L, double* X, double h, double xmax, int nsteps,
+              hipStream_t ms) {
+  double* const* k = ctx->kk;
+  const int npts = (int)ctx->dev.size();
   const double half[1] = {0.5}, one[1] = {1.0};
   const double fin[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-  for (int step = 0; step < o->nsteps; ++step) {
-    double T1 = std::exp(s), Th = std::exp(s + 0.5 * h), T2 = std::exp(s + h);
-    rhs_point(ctx, p, T1, X, k[0], T1);
-    axpy_point(ctx, p, X, &k[0], half, 1, h, stage);
-    rhs_point(ctx, p, Th, stage, k[1], Th);
-    axpy_point(ctx, p, X, &k[1], half, 1, h, stage);
-    rhs_point(ctx, p, Th, stage, k[2], Th);
-    axpy_point(ctx, p, X, &k[2], one, 1, h, stage);
-    rhs_point(ctx, p, T2, stage, k[3], T2);
-    axpy_point(ctx, p, X, k, fin, 4, h, X);
-    n_rhs += 4;
-    s = s0 + (step + 1) * h;
-    ST_TRY(maxabs_point(ctx, p, X, &m));
-    s_hist.push_back(s);
-    m_hist.push_back(m);
-    if (!std::isfinite(m))
-      return finish_point(ctx, p, X, TUFRG_FLOW_NONFINITE, s_hist, m_hist, o->Xmax, n_rhs, step + 1, r);
-    if (m > o->Xmax)
-      return finish_point(ctx, p, X, TUFRG_FLOW_DIVERGED, s_hist, m_hist, o->Xmax, n_rhs, step + 1, r);
+  const Ranges& r = ctx->all;
+  launch_set_T(ctx->Tp, npts, ctx->Ttab, ctx->step, 0, ms);
+  rhs_launch(ctx, L, r, X, k[0], true, ms);
+  launch_axpy(L, r.seg, X, &k[0], half, 1, h, ctx->stage, true, ms);
+  launch_set_T(ctx->Tp, npts, ctx->Ttab, ctx->step, 1, ms);
+  rhs_launch(ctx, L, r, ctx->stage, k[1], true, ms);
+  launch_axpy(L, r.seg, X, &k[1], half, 1, h, ctx->stage, true, ms);
+  launch_set_T(ctx->Tp, npts, ctx->Ttab, ctx->step, 2, ms);
+  rhs_launch(ctx, L, r, ctx->stage, k[2], true, ms);
+  launch_axpy(L, r.seg, X, &k[2], one, 1, h, ctx->stage, true, ms);
+  launch_set_T(ctx->Tp, npts, ctx->Ttab, ctx->step, 3, ms);
+  rhs_launch(ctx, L, r, ctx->stage, k[3], true, ms);
+  launch_axpy(L, r.seg, X, k, fin, 4, h, X, true, ms);
+  launch_maxabs(L, r.seg, X, ctx->umax, ms);
+  launch_step_end(ctx->umax, npts, ctx->frozen, ctx->hist, ctx->step, nsteps, xmax, ms);
+}
+
+tufrg_status flow_rk4_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tufrg_flow_result* res) {
+  const int npts = (int)ctx->dev.size();
+  const int nsteps = o->nsteps;
+  const double s0 = std::log(o->T0);
+  const double h = (std::log(o->Tmin) - s0) / nsteps;
+  // stage temperatures of every step (one spare row read by nothing) and the
+  // max|X| history
+  if (ctx->ttab_cap < nsteps) {
+    ST_TRY(dalloc(ctx, (size_t)4 * (nsteps + 1), &ctx->Ttab, ctx->allocations));
+    ST_TRY(dalloc(ctx, (size_t)(nsteps + 2) * npts, &ctx->hist, ctx->allocations));
+    ctx->ttab_cap = nsteps;
   }
-  return finish_point(ctx, p, X, TUFRG_FLOW_REACHED_TMIN, s_hist, m_hist, o->Xmax, n_rhs, o->nsteps, r);
+  std::vector<double> tt((size_t)4 * (nsteps + 1), 0.0);
+  for (int i = 0; i < nsteps; ++i) {
+    const double s = s0 + i * h;
+    tt[4 * i + 0] = std::exp(s);
+    tt[4 * i + 1] = std::exp(s + 0.5 * h);
+    tt[4 * i + 2] = std::exp(s + 0.5 * h);
+    tt[4 * i + 3] = std::exp(s0 + (i + 1) * h);
+  }
+  for (int j = 0; j < 4; ++j) tt[4 * nsteps + j] = tt[4 * (nsteps - 1) + 3];
+  // graph replay runs on the context's own capture stream, ordered after the
+  // caller's stream
+  hipStream_t ms = ctx->stream;
+  if (o->use_graph) {
+    ms = ctx->gs;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_gs, ctx->stream));
+    HIP_TRY(ctx, hipStreamWaitEvent(ms, ctx->ev_gs, 0));
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->Ttab, tt.data(), tt.size() * sizeof(double), hipMemcpyHostToDevice, ms));
+  launch_fill_i32(ctx->frozen, npts, 0, ms);
+  launch_fill_i32(ctx->step, 1, 0, ms);
+  launch_fill_u64(ctx->umax, npts, 0ull, ms);
+  Launch Lf = ctx->L;
+  Lf.b.frozen = ctx->frozen;
+  launch_maxabs(Lf, ctx->all.seg, X, ctx->umax, ms);
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->umax_host, ctx->umax, sizeof(unsigned long long) * npts,
+                              hipMemcpyDeviceToHost, ms));
+  launch_fill_u64(ctx->umax, npts, 0ull, ms);
+  HIP_TRY(ctx, hipStreamSynchronize(ms));
+  std::vector<double> m0(npts);
+  for (int p = 0; p < npts; ++p) m0[p] = word_to_double(ctx->umax_host[p]);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto cleanup = [&]() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+  };
+  if (o->use_graph) {
+    HIP_TRY(ctx, hipStreamBeginCapture(ms, hipStreamCaptureModeThreadLocal));
+    rk4_step(ctx, Lf, X, h, o->Xmax, nsteps, ms);
+    hipError_t e = hipStreamEndCapture(ms, &graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      cleanup();
+      return fail(ctx, TUFRG_EHIP, std::string("graph capture of the RK4 step: ") + hipGetErrorString(e));
+    }
+  }
+  // steps in batches; the host checks the stop flags between batches
+  std::vector<int> frozen(npts, 0);
+  int done = 0;
+  const int batch = 8;
+  while (done < nsteps) {
+    const int nb = std::min(batch, nsteps - done);
+    for (int i = 0; i < nb; ++i) {
+      if (exec) {
+        hipError_t e = hipGraphLaunch(exec, ms);
+        if (e != hipSuccess) {
+          cleanup();
+          return fail(ctx, TUFRG_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        }
+      } else {
+        rk4_step(ctx, Lf, X, h, o->Xmax, nsteps, ms);
+      }
+    }
+    done += nb;
+    hipError_t e = hipMemcpyAsync(frozen.data(), ctx->frozen, sizeof(int) * npts, hipMemcpyDeviceToHost, ms);
+    if (e == hipSuccess) e = hipStreamSynchronize(ms);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+      cleanup();
+      return fail(ctx, TUFRG_EHIP, std::string("RK4 flow: ") + hipGetErrorString(e));
+    }
+    if (std::all_of(frozen.begin(), frozen.end(), [](int f) { return f != 0; })) break;
+  }
+  cleanup();
+  std::vector<double> hist((size_t)(done + 1) * npts);
+  HIP_TRY(ctx, hipMemcpyAsync(hist.data(), ctx->hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost, ms));
+  HIP_TRY(ctx, hipStreamSynchronize(ms));
+  for (int p = 0; p < npts; ++p) hist[p] = m0[p];
+  for (int p = 0; p < npts; ++p) {
+    const int f = frozen[p];
+    const int last = f ? f : done;
+    const double mlast = hist[(size_t)last * npts + p];
+    const double mprev = hist[(size_t)(last - 1) * npts + p];
+    int status = TUFRG_FLOW_REACHED_TMIN;
+    if (f) status = std::isfinite(mlast) ? TUFRG_FLOW_DIVERGED : TUFRG_FLOW_NONFINITE;
+    ST_TRY(finish_point(ctx, p, X, status, s0 + (last - 1) * h, s0 + last * h, mprev, mlast, o->Xmax,
+                        4 * (int64_t)last, last, ms, &res[p]));
+  }
+  return TUFRG_OK;
 }
 
 // Dormand-Prince 5(4) tableau (Dormand & Prince 1980)
@@ -521,80 +870,89 @@ const double kDpB5[7] = {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6
 const double kDpB4[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200,
                          187.0 / 2100, 1.0 / 40};
 
+// dX/ds of point p alone at temperature T
+void rhs_point(tufrg_ctx* ctx, int p, double T, const double* X, double* out) {
+  launch_set_T_values(ctx->Tp + p, &T, 1, ctx->stream);
+  rhs_launch(ctx, ctx->L, ctx->per_point[p], X, out, true, ctx->stream);
+}
+
+tufrg_status maxabs_point(tufrg_ctx* ctx, int p, const double* X, double* result) {
+  launch_fill_u64(ctx->umax + p, 1, 0ull, ctx->stream);
+  launch_maxabs(ctx->L, ctx->per_point[p].seg, X, ctx->umax, ctx->stream);
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->umax_host + p, ctx->umax + p, sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  *result = word_to_double(ctx->umax_host[p]);
+  return TUFRG_OK;
+}
+
 tufrg_status flow_dopri5_point(tufrg_ctx* ctx, int p, const tufrg_flow_opts* o, double* X,
                                tufrg_flow_result* r) {
   double* k[7];
-  for (int i = 0; i < 7; ++i) k[i] = ctx->ws.k[i];
-  double* stage = ctx->ws.stage;
-  double* y5 = ctx->ws.ytmp;
+  for (int i = 0; i < 7; ++i) k[i] = ctx->kk[i];
+  double* stage = ctx->stage;
+  double* y5 = ctx->ytmp;
+  const ItemRange seg = ctx->per_point[p].seg;
   const HostTables& t = ctx->host[p];
   const int64_t n = (int64_t)t.nq * t.nff * t.nff;
-  const int nred = 256;
+  if (ctx->nred < seg.n) {
+    ST_TRY(dalloc(ctx, (size_t)seg.n, &ctx->red, ctx->allocations));
+    ctx->nred = seg.n;
+  }
   double s = std::log(o->T0);
   const double s_end = std::log(o->Tmin);
   double h = (o->h0 != 0.0) ? o->h0 : (s_end - s) / 200.0;
   const int max_steps = o->max_steps > 0 ? o->max_steps : 100000;
-  std::vector<double> s_hist{s}, m_hist;
-  double m;
+  double m, mprev, sprev = s;
   ST_TRY(maxabs_point(ctx, p, X, &m));
-  m_hist.push_back(m);
-  double T = std::exp(s);
-  rhs_point(ctx, p, T, X, k[0], T);
+  mprev = m;
+  rhs_point(ctx, p, std::exp(s), X, k[0]);
   int64_t n_rhs = 1, n_acc = 0;
-  std::vector<double> red(nred * 3);
+  std::vector<double> red(seg.n);
   double e[7];
   for (int j = 0; j < 7; ++j) e[j] = kDpB5[j] - kDpB4[j];
+  const hipStream_t ms = ctx->stream;
   for (int it = 0; it < max_steps; ++it) {
     if (s + h < s_end) h = s_end - s;
     for (int i = 1; i < 7; ++i) {
-      axpy_point(ctx, p, X, k, kDpA[i], i, h, stage);
-      const double Ti = std::exp(s + kDpC[i] * h);
-      rhs_point(ctx, p, Ti, stage, k[i], Ti);
+      launch_axpy(ctx->L, seg, X, k, kDpA[i], i, h, stage, false, ms);
+      rhs_point(ctx, p, std::exp(s + kDpC[i] * h), stage, k[i]);
     }
     n_rhs += 6;
-    axpy_point(ctx, p, X, k, kDpB5, 7, h, y5);
-    // RMS error norm over the point's 3 n elements
-    for (int c = 0; c < 3; ++c) {
-      const double* kk[7];
-      for (int j = 0; j < 7; ++j) kk[j] = k[j] + c * ctx->S + ctx->off[p];
-      launch_errnorm(X + c * ctx->S + ctx->off[p], y5 + c * ctx->S + ctx->off[p], kk, e, 7, h,
-                     o->rtol, o->atol, n, ctx->ws.red + c * nred, nred, ctx->stream);
-    }
-    HIP_TRY(ctx, hipMemcpyAsync(red.data(), ctx->ws.red, sizeof(double) * 3 * nred,
-                                hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    launch_axpy(ctx->L, seg, X, k, kDpB5, 7, h, y5, false, ms);
+    launch_errnorm(ctx->L, seg, X, y5, k, e, 7, h, o->rtol, o->atol, ctx->red, ms);
+    HIP_TRY(ctx, hipMemcpyAsync(red.data(), ctx->red, sizeof(double) * seg.n, hipMemcpyDeviceToHost, ms));
+    HIP_TRY(ctx, hipStreamSynchronize(ms));
     double sum = 0.0;
     for (double v : red) sum += v;
     const double err = std::sqrt(sum / (3.0 * (double)n));
-    if (!std::isfinite(err)) {
-      s_hist.push_back(s + h);
-      m_hist.push_back(NAN);
-      return finish_point(ctx, p, y5, TUFRG_FLOW_NONFINITE, s_hist, m_hist, o->Xmax, n_rhs, n_acc, r);
-    }
+    if (!std::isfinite(err))
+      return finish_point(ctx, p, y5, TUFRG_FLOW_NONFINITE, s, s + h, m, NAN, o->Xmax, n_rhs, n_acc, ms, r);
     if (err <= 1.0) {
+      sprev = s;
+      mprev = m;
       s = s + h;
       for (int c = 0; c < 3; ++c)
         HIP_TRY(ctx, hipMemcpyAsync(X + c * ctx->S + ctx->off[p], y5 + c * ctx->S + ctx->off[p],
-                                    n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-      std::swap(ctx->ws.k[0], ctx->ws.k[6]);
-      k[0] = ctx->ws.k[0];
-      k[6] = ctx->ws.k[6];
+                                    n * sizeof(double), hipMemcpyDeviceToDevice, ms));
+      std::swap(k[0], k[6]);  // first-same-as-last: the slope at the new state
       ++n_acc;
       ST_TRY(maxabs_point(ctx, p, X, &m));
-      s_hist.push_back(s);
-      m_hist.push_back(m);
       if (m > o->Xmax)
-        return finish_point(ctx, p, X, TUFRG_FLOW_DIVERGED, s_hist, m_hist, o->Xmax, n_rhs, n_acc, r);
+        return finish_point(ctx, p, X, TUFRG_FLOW_DIVERGED, sprev, s, mprev, m, o->Xmax, n_rhs, n_acc, ms, r);
       if (s <= s_end + 1e-15)
-        return finish_point(ctx, p, X, TUFRG_FLOW_REACHED_TMIN, s_hist, m_hist, o->Xmax, n_rhs, n_acc, r);
+        return finish_point(ctx, p, X, TUFRG_FLOW_REACHED_TMIN, sprev, s, mprev, m, o->Xmax, n_rhs, n_acc,
+                            ms, r);
     }
     const double fac = err == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.9 * std::pow(err, -0.2)));
     h *= fac;
   }
-  return finish_point(ctx, p, X, TUFRG_FLOW_REACHED_TMIN, s_hist, m_hist, o->Xmax, n_rhs, n_acc, r);
+  return finish_point(ctx, p, X, TUFRG_FLOW_REACHED_TMIN, sprev, s, mprev, m, o->Xmax, n_rhs, n_acc, ms, r);
 }
 
 }  // namespace
+
+extern "C" {
 
 tufrg_status tufrg_flow(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tufrg_flow_result* res) {
   if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
@@ -603,32 +961,30 @@ tufrg_status tufrg_flow(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tuf
     return fail(ctx, TUFRG_EINVAL, "need T0 > Tmin > 0 and Xmax > 0");
   if (o->scheme == TUFRG_RK4_LOG) {
     if (o->nsteps <= 0) return fail(ctx, TUFRG_EINVAL, "nsteps must be > 0");
+    ST_TRY(flow_rk4_all(ctx, o, X, res));
   } else if (o->scheme == TUFRG_DOPRI5_LOG) {
     if (!(o->rtol > 0.0) || !(o->atol > 0.0)) return fail(ctx, TUFRG_EINVAL, "rtol, atol must be > 0");
+    for (size_t p = 0; p < ctx->dev.size(); ++p) ST_TRY(flow_dopri5_point(ctx, (int)p, o, X, &res[p]));
   } else {
     return fail(ctx, TUFRG_EINVAL, "unknown scheme");
   }
-  bool nonfinite = false;
-  for (size_t p = 0; p < ctx->dev.size(); ++p) {
-    tufrg_status st = (o->scheme == TUFRG_RK4_LOG) ? flow_rk4_point(ctx, (int)p, o, X, &res[p])
-                                                   : flow_dopri5_point(ctx, (int)p, o, X, &res[p]);
-    if (st != TUFRG_OK) return st;
-    if (res[p].status == TUFRG_FLOW_NONFINITE) nonfinite = true;
-  }
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  if (nonfinite) return fail(ctx, TUFRG_ENONFINITE, "flow state became non-finite");
+  for (size_t p = 0; p < ctx->dev.size(); ++p)
+    if (res[p].status == TUFRG_FLOW_NONFINITE)
+      return fail(ctx, TUFRG_ENONFINITE, "flow state of point " + std::to_string(p) + " became non-finite");
   return TUFRG_OK;
 }
 
 void tufrg_free(tufrg_ctx* ctx) {
   if (!ctx) return;
-  if (!ctx->allocations.empty()) hipStreamSynchronize(ctx->stream);
-  if (ctx->side) {
-    hipStreamSynchronize(ctx->side);
-    hipStreamDestroy(ctx->side);
-  }
+  if (!ctx->allocations.empty() || !ctx->geometry_allocations.empty()) hipDeviceSynchronize();
+  if (ctx->side) hipStreamDestroy(ctx->side);
+  if (ctx->gs) hipStreamDestroy(ctx->gs);
   if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
+  if (ctx->ev_gs) hipEventDestroy(ctx->ev_gs);
+  if (ctx->umax_host) hipHostFree(ctx->umax_host);
+  for (void* p : ctx->geometry_allocations) hipFree(p);
   for (void* p : ctx->allocations) hipFree(p);
   delete ctx;
 }

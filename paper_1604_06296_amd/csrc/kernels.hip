@@ -1,7 +1,15 @@
 // HIP kernels for gfx950 (CDNA4): loops, projections, products and ODE helpers
 // of the TUfRG flow right-hand side.
+//
+// Every kernel is driven by a table of work items (point, a, b, c): one launch
+// covers any set of points with uneven grids and truncations, a single point
+// being a batch of one.  The point's tables are read from a device array of
+// DevTables; temperatures are read from a per-point device array (so that a
+// captured HIP graph can be replayed with new temperatures), and points whose
+// flow has stopped are skipped through a per-point device flag.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "loop_math.h"
@@ -10,18 +18,10 @@
 namespace tufrg {
 namespace {
 
-constexpr int kBubThreads = 512;   // upper bound of the loop kernel's block size
+__device__ __forceinline__ bool skip_point(const Batch& b, int p) {
+  return b.frozen != nullptr && b.frozen[p] != 0;
+}
 
-// ------------------------------------------------------------------ loops
-// Step ii.) of Sec. 2.4, eqn. chis, at one temperature.  One block per
-// transfer momentum q.  Threads own one px column of the fine grid and a
-// chunk of py rows (py in [0, Lk/2] only: the loop weight is even in p, the
-// self-paired rows py = 0, Lk/2 carry weight 1 and the others weight 2).
-// Each thread accumulates row sums of the loop derivative against cos(n py)
-// and sin(n py), n <= SMAX; the block then contracts the rows against
-// cos(px Sx), sin(px Sx) into ghat(q, S) = (1/Nk) sum_p L'(p) cos(p.S) for
-// the half set of harmonics S in bonds + bonds, and finally
-// chi'_mn(q) = sum_S Ebub_{mn,S} ghat(q, S).
 struct DevRcp {
   __device__ double operator()(double x) const {
     double r = __builtin_amdgcn_rcp(x);       // hardware estimate, refined by Newton steps
@@ -31,13 +31,42 @@ struct DevRcp {
     return fma(r, e, r);
   }
 };
+struct Exp2F { __device__ float operator()(float x) const { return __builtin_amdgcn_exp2f(x); } };
+struct RcpF { __device__ float operator()(float x) const { return __builtin_amdgcn_rcpf(x); } };
 
-template <int SMAX>
-__global__ void __launch_bounds__(kBubThreads)
-k_loops_f64(DevTables d, double T, int nsplit, int nchunk, double* __restrict__ dchi, int64_t S,
-            double* __restrict__ dpart) {
-  constexpr int NH = 2 * SMAX + 1;     // row sums per channel: cos n=0..SMAX, sin n=1..SMAX
-  const int q = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
+__device__ __forceinline__ void neumaier_add(float& s, float& c, float v) {
+  const float t = s + v;
+  const bool sbig = fabsf(s) >= fabsf(v);
+  const float big = sbig ? s : v, small = sbig ? v : s;
+  c += (big - t) + small;
+  s = t;
+}
+
+// ------------------------------------------------------------------ loops
+// Step ii.) of Sec. 2.4, eqn. chis, at the point's temperature.  Work item
+// (p, q * nsplit + split): one transfer momentum q and one slice of the rows
+// py in [0, Lk/2] of the fine grid (the loop weight is even in p: the
+// self-paired rows py = 0 and Lk/2 carry weight 1, the others weight 2).
+// Threads own one column px and a chunk of the slice's rows; they accumulate
+// row sums of the loop derivative against cos(n py) and sin(n py), n <= smax.
+// The block contracts the rows against cos(px Sx), sin(px Sx) into
+// ghat(q, S) = (1/Nk) sum_p L'(p) cos(p.S) for the half set of harmonics S in
+// bonds + bonds and applies chi'_mn(q) = sum_S Ebub_{mn,S} ghat(q, S).
+// In the persistent form queue[0] is the next item and queue[1] counts
+// finished blocks; both are zero at entry, and the last block to finish sets
+// them back to zero for the next launch (device-scope atomics, valid across
+// XCDs).  MIXED selects the FP32 pair math with blocked Neumaier-compensated
+// FP32 row sums; otherwise everything is FP64.
+//
+// One loop work item with the point's exact harmonic count NH = 2 smax + 1
+// (compile-time, so the per-row harmonic loops carry no guards).
+template <int SMAX, bool MIXED>
+__device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, int p, int item_b,
+                                          double* smem) {
+  constexpr int NH = 2 * SMAX + 1;
+  const int t = threadIdx.x;
+  const int nsplit = d.nsplit, nchunk = d.nchunk;
+  const int q = item_b / nsplit, split = item_b % nsplit;
   const int lk = d.lk;
   const int rows = lk / 2 + 1;
   const int R0 = (int)((int64_t)rows * split / nsplit);
@@ -45,27 +74,23 @@ k_loops_f64(DevTables d, double T, int nsplit, int nchunk, double* __restrict__ 
   const int nr = R1 - R0;
   const int lq = d.lq;
   const int ix = q / lq, iy = q % lq;
+  const double T = b.Tp[p];
   const double inv2T = 0.5 / T;
 
-  extern __shared__ double smem[];
   double* y1 = smem;                        // cos(py + qy/2)        [nr]
   double* y2 = y1 + nr;                     // cos(py - qy/2)        [nr]
   double* pyt = y2 + nr;                    // weighted py harmonics [nr][NH]
   double* rs = pyt + nr * NH;               // row sums              [lk][2][NH]
   double* gh = rs + lk * 2 * NH;            // harmonic partials     [nseg][2 nsh]
-
-  // cos(py +- qy/2) for this block's rows from the init-time table [lq][lk][2]
-  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
+  for (int j = t; j < nr; j += blockDim.x) {
     const double* c = d.cshift + ((size_t)iy * lk + (R0 + j)) * 2;
     y1[j] = c[0];
     y2[j] = c[1];
   }
-  for (int j = threadIdx.x; j < nr * NH; j += blockDim.x) pyt[j] = d.pytab[R0 * NH + j];
-  for (int j = threadIdx.x; j < lk * 2 * NH; j += blockDim.x) rs[j] = 0.0;
+  for (int j = t; j < nr * NH; j += blockDim.x) pyt[j] = d.pytab[R0 * NH + j];
+  for (int j = t; j < lk * 2 * NH; j += blockDim.x) rs[j] = 0.0;
   __syncthreads();
 
-  // thread t owns column px = t % lk and the chunk c = t / lk of this block's rows
-  const int t = threadIdx.x;
   const bool active = t < lk * nchunk;
   const int px = t % lk, c = t / lk;
   double acc[2][NH];
@@ -81,17 +106,56 @@ k_loops_f64(DevTables d, double T, int nsplit, int nchunk, double* __restrict__ 
     const double B2 = (-2.0 * d.t - 4.0 * d.tp * cx2) * inv2T;
     const int r0 = (int)((int64_t)nr * c / nchunk);
     const int r1 = (int)((int64_t)nr * (c + 1) / nchunk);
+    if constexpr (!MIXED) {
 #pragma unroll 2
-    for (int r = r0; r < r1; ++r) {
-      const double al = fma(B1, y1[r], A1);
-      const double be = fma(B2, y2[r], A2);
-      double dph, dpp;
-      loop_dot_pair_t(al, be, dph, dpp, DevRcp());
-      const double* w = pyt + r * NH;
+      for (int r = r0; r < r1; ++r) {
+        const double al = fma(B1, y1[r], A1);
+        const double be = fma(B2, y2[r], A2);
+        double dph, dpp;
+        loop_dot_pair_t(al, be, dph, dpp, DevRcp());
+        const double* w = pyt + r * NH;
+#pragma unroll
+        for (int n = 0; n < NH; ++n) {
+          acc[0][n] = fma(dpp, w[n], acc[0][n]);
+          acc[1][n] = fma(dph, w[n], acc[1][n]);
+        }
+      }
+    } else {
+      // FP32 pair math from FP64 energies; rows blocked by 8 in FP32 and
+      // added into Neumaier-compensated FP32 running sums
+      constexpr int RB = 8;
+      float sum[2][NH], cmp[2][NH];
+#pragma unroll
+      for (int n = 0; n < NH; ++n) sum[0][n] = sum[1][n] = cmp[0][n] = cmp[1][n] = 0.0f;
+      for (int rb = r0; rb < r1; rb += RB) {
+        float blk[2][NH];
+#pragma unroll
+        for (int n = 0; n < NH; ++n) blk[0][n] = blk[1][n] = 0.0f;
+        const int re = min(rb + RB, r1);
+        for (int r = rb; r < re; ++r) {
+          const double al = fma(B1, y1[r], A1);
+          const double be = fma(B2, y2[r], A2);
+          float dph, dpp;
+          loop_dot_pair_f32((float)al, (float)be, (float)(al - be), (float)(al + be), dph, dpp,
+                            Exp2F(), RcpF());
+          const double* w = pyt + r * NH;
+#pragma unroll
+          for (int n = 0; n < NH; ++n) {
+            const float wf = (float)w[n];
+            blk[0][n] = fmaf(dpp, wf, blk[0][n]);
+            blk[1][n] = fmaf(dph, wf, blk[1][n]);
+          }
+        }
+#pragma unroll
+        for (int n = 0; n < NH; ++n) {
+          neumaier_add(sum[0][n], cmp[0][n], blk[0][n]);
+          neumaier_add(sum[1][n], cmp[1][n], blk[1][n]);
+        }
+      }
 #pragma unroll
       for (int n = 0; n < NH; ++n) {
-        acc[0][n] = fma(dpp, w[n], acc[0][n]);
-        acc[1][n] = fma(dph, w[n], acc[1][n]);
+        acc[0][n] = (double)sum[0][n] + (double)cmp[0][n];
+        acc[1][n] = (double)sum[1][n] + (double)cmp[1][n];
       }
     }
   }
@@ -107,12 +171,11 @@ k_loops_f64(DevTables d, double T, int nsplit, int nchunk, double* __restrict__ 
     }
     __syncthreads();
   }
-
   // contraction over px into the half-set harmonics, split into segments
   const int nout = 2 * d.nsh;
   int nseg = (int)blockDim.x / nout;
   if (nseg < 1) nseg = 1;
-  for (int w = threadIdx.x; w < nout * nseg; w += blockDim.x) {
+  for (int w = t; w < nout * nseg; w += blockDim.x) {
     const int o = w % nout, seg = w / nout;
     const int ch = o / d.nsh, j = o % d.nsh;
     const int sx = d.hx[j], sy = d.hy[j];          // sx >= 0
@@ -129,19 +192,19 @@ k_loops_f64(DevTables d, double T, int nsplit, int nchunk, double* __restrict__ 
     gh[seg * nout + o] = g;
   }
   __syncthreads();
-  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+  for (int o = t; o < nout; o += blockDim.x) {
     double g = 0.0;
     for (int s = 0; s < nseg; ++s) g += gh[s * nout + o];
     gh[o] = g;
   }
   __syncthreads();
   // chi'_mn = sgn / (4 T^2 Nk) sum_j Ebub_{mn,j} ghat_j (pp carries the minus
-  // sign of dL^pp/dT = -Dh/(4T^2)).  With one split the block writes chi'
-  // itself; otherwise its rows' share goes to slice `split` of dpart
-  // [nsplit][2][Nq][nff^2] and the consumer adds the slices in split order.
+  // sign of dL^pp/dT = -Dh/(4T^2)).  With one slice the block writes chi'
+  // itself; otherwise its share goes to slice `split` of the point's
+  // [nsplit][2][Nq][nff^2] buffer and the consumer adds the slices in order.
   const int nff2 = d.nff * d.nff;
   const double base = 1.0 / (4.0 * T * T * (double)lk * (double)lk);
-  for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
+  for (int w = t; w < 2 * nff2; w += blockDim.x) {
     const int ch = w / nff2, mn = w % nff2;
     const double* e = d.ebub + (size_t)mn * d.nsh;
     const double* g = gh + ch * d.nsh;
@@ -149,45 +212,119 @@ k_loops_f64(DevTables d, double T, int nsplit, int nchunk, double* __restrict__ 
     for (int j = 0; j < d.nsh; ++j) v = fma(e[j], g[j], v);
     v *= (ch == 0 ? -base : base);
     if (nsplit == 1)
-      dchi[(size_t)ch * S + (size_t)q * nff2 + mn] = v;
+      b.dchi[(size_t)ch * b.S + d.off + (size_t)q * nff2 + mn] = v;
     else
-      dpart[(((size_t)split * 2 + ch) * d.nq + q) * nff2 + mn] = v;
+      b.dpart[d.ws_dpart + (((size_t)split * 2 + ch) * d.nq + q) * nff2 + mn] = v;
+  }
+  __syncthreads();
+}
+
+template <int SMAX, bool MIXED>
+__device__ __forceinline__ void loop_dispatch(const Batch& b, const int4 item, double* smem) {
+  const int p = item.x;
+  if (skip_point(b, p)) return;
+  const DevTables& d = b.pts[p];
+  if constexpr (SMAX >= 4) {
+    if (d.smax == 4) {
+      loop_item<4, MIXED>(b, d, p, item.y, smem);
+      return;
+    }
+  }
+  if constexpr (SMAX >= 2) {
+    if (d.smax == 2) {
+      loop_item<2, MIXED>(b, d, p, item.y, smem);
+      return;
+    }
+  }
+  loop_item<0, MIXED>(b, d, p, item.y, smem);
+}
+
+// Loop kernel over work items (p, q * nsplit + split); SMAX is the largest
+// smax of the batch, and each item runs the body compiled for its own smax.
+// Without a queue every block runs item blockIdx.x (the hardware dispatcher
+// balances the load, items being ordered costliest first); with a queue the
+// kernel is persistent and blocks take items until the queue is empty.
+template <int SMAX, bool MIXED>
+__global__ void __launch_bounds__(kLoopThreadsMax)
+k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ queue) {
+  extern __shared__ double smem[];
+  __shared__ int cur;
+  if (queue == nullptr) {
+    loop_dispatch<SMAX, MIXED>(b, items[blockIdx.x], smem);
+    return;
+  }
+  const int t = threadIdx.x;
+  for (;;) {
+    if (t == 0) cur = atomicAdd(queue, 1);
+    __syncthreads();
+    const int it = cur;
+    __syncthreads();
+    if (it >= nitems) break;
+    loop_dispatch<SMAX, MIXED>(b, items[it], smem);
+  }
+  if (t == 0 && atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {
+    atomicExch(queue, 0);
+    atomicExch(queue + 1, 0);
   }
 }
 
-// chi' = sum over the split slices in split order (loops with nsplit > 1)
+// chi' = sum of the slices in slice order; item (p, block)
 __global__ void __launch_bounds__(256)
-k_chi_sum(const double* __restrict__ dpart, int nsplit, int nq, int nff2, double* __restrict__ dchi,
-          int64_t S) {
-  const int64_t n = (int64_t)2 * nq * nff2;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    double v = 0.0;
-    for (int s = 0; s < nsplit; ++s) v += dpart[(size_t)s * n + i];
-    const int64_t ch = i / ((int64_t)nq * nff2), r = i % ((int64_t)nq * nff2);
-    dchi[ch * S + r] = v;
+k_chi_sum(Batch b, const int4* __restrict__ items, double* __restrict__ dchi) {
+  const int4 item = items[blockIdx.x];
+  const int p = item.x;
+  if (skip_point(b, p)) return;
+  const DevTables& d = b.pts[p];
+  const int nff2 = d.nff * d.nff;
+  const int64_t n = (int64_t)2 * d.nq * nff2;
+  const int64_t i = (int64_t)item.y * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = 0.0;
+  for (int s = 0; s < d.nsplit; ++s) v += b.dpart[d.ws_dpart + (size_t)s * n + i];
+  const int64_t ch = i / ((int64_t)d.nq * nff2), r = i % ((int64_t)d.nq * nff2);
+  dchi[ch * b.S + d.off + r] = v;
+}
+
+// chi'(l) of one point into LDS (used by the FP64 back end)
+__device__ __forceinline__ void load_chi(const Batch& b, const DevTables& d, int l, double* Ch) {
+  const int nff2 = d.nff * d.nff, nq = d.nq;
+  for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
+    const int ch = w / nff2, mn = w % nff2;
+    if (d.nsplit == 1) {
+      Ch[w] = b.dchi[(size_t)ch * b.S + d.off + (size_t)l * nff2 + mn];
+    } else {
+      double v = 0.0;
+      for (int s = 0; s < d.nsplit; ++s)
+        v += b.dpart[d.ws_dpart + (((size_t)s * 2 + ch) * nq + l) * nff2 + mn];
+      Ch[w] = v;
+    }
   }
 }
 
 // ------------------------------------------------------- projections
-// Forward transform of the projections: the partial Fourier sums over the
-// transfer grid at the half-integer frequencies S/2,
+// Forward transform: the partial Fourier sums over the transfer grid at the
+// half-integer frequencies S/2,
 //   xt[ch][k][mn] = (1/Nq) sum_u E[u][k] X[ch][u][mn],  E = (cos(u.S'/2) | sin(u.S'/2)).
-// A block owns 64 consecutive columns (ch, mn) and KG harmonic columns; its NW
-// waves split the transfer grid and are reduced in LDS in a fixed order.
+// Item (p, column tile, harmonic group): 64 consecutive columns (ch, mn) and
+// KG harmonic columns; the NW waves split the transfer grid and are added in
+// LDS in a fixed order.
 template <int KG, int NW>
 __global__ void __launch_bounds__(64 * NW)
-k_dft_fwd(const double* __restrict__ eph, int nq, int ncol, const double* __restrict__ X,
-          int64_t S, int nff2, double* __restrict__ xt) {
+k_dft_fwd(Batch b, const int4* __restrict__ items, const double* __restrict__ X) {
   __shared__ double red[NW][KG][64];
+  const int4 item = items[blockIdx.x];
+  const int p = item.x;
+  if (skip_point(b, p)) return;
+  const DevTables& d = b.pts[p];
+  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int col = blockIdx.x * 64 + lane;
-  const int k0 = blockIdx.y * KG;
+  const int col = item.y * 64 + lane;
+  const int k0 = item.z * KG;
   const int kn = min(KG, ncol - k0);
   const bool ok = col < 3 * nff2;
   const int ch = ok ? col / nff2 : 0, mn = ok ? col % nff2 : 0;
-  const double* xp = X + (size_t)ch * S + mn;
+  const double* xp = X + (size_t)ch * b.S + d.off + mn;
   const int u0 = (int)((int64_t)nq * w / NW), u1 = (int)((int64_t)nq * (w + 1) / NW);
   double acc[KG];
 #pragma unroll
@@ -195,7 +332,7 @@ k_dft_fwd(const double* __restrict__ eph, int nq, int ncol, const double* __rest
 #pragma unroll 4
   for (int u = u0; u < u1; ++u) {
     const double x = ok ? xp[(size_t)u * nff2] : 0.0;
-    const double* e = eph + (size_t)u * ncol + k0;
+    const double* e = d.eph + (size_t)u * ncol + k0;
 #pragma unroll
     for (int i = 0; i < KG; ++i)
       if (i < kn) acc[i] = fma(e[i], x, acc[i]);
@@ -205,6 +342,7 @@ k_dft_fwd(const double* __restrict__ eph, int nq, int ncol, const double* __rest
   __syncthreads();
   if (w == 0 && ok) {
     const double inv = 1.0 / (double)nq;
+    double* xt = b.xt + d.ws_xt;
     for (int i = 0; i < kn; ++i) {
       double v = 0.0;
       for (int ww = 0; ww < NW; ++ww) v += red[ww][i][lane];
@@ -218,8 +356,13 @@ k_dft_fwd(const double* __restrict__ eph, int nq, int ncol, const double* __rest
 //   yb[in][v][b1 b2] = sum_{m' in shell(b1), n' in shell(b2)} c_{m'b1} c_{n'b2} xt^{in}_{m'n'}(v)
 // with xt(-S') = conj(xt(S')).  These are the bond-space Fourier coefficients
 // Yhat_{R1R2}(W) of the propagators at frequency 2W - R1 - R2 = v.
+// Item (p, block of 256 outputs).
 __global__ void __launch_bounds__(256)
-k_bond_basis(DevTables d, const double* __restrict__ xt, double* __restrict__ yb) {
+k_bond_basis(Batch b, const int4* __restrict__ items) {
+  const int4 item = items[blockIdx.x];
+  const int p = item.x;
+  if (skip_point(b, p)) return;
+  const DevTables& d = b.pts[p];
   const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol, nv = 2 * nsh - 1;
   const int total = 3 * nv * nff2;
   __shared__ double cs[2 * 441];
@@ -228,18 +371,19 @@ k_bond_basis(DevTables d, const double* __restrict__ xt, double* __restrict__ yb
     cs[nff2 + i] = d.cim[i];
   }
   __syncthreads();
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = item.y * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int in = idx / (nv * nff2), v = (idx / nff2) % nv, b = idx % nff2;
-  const int b1 = b / nff, b2 = b % nff;
+  const int in = idx / (nv * nff2), v = (idx / nff2) % nv, bb = idx % nff2;
+  const int b1 = bb / nff, b2 = bb % nff;
   const int j = v < nsh ? v : v - nsh + 1;
   const double sim = v < nsh ? 1.0 : -1.0;
+  const double* xt = b.xt + d.ws_xt;
   const double* xr = xt + ((size_t)in * ncol + j) * nff2;
   const double* xi = xt + ((size_t)in * ncol + (nsh - 1 + j)) * nff2;
   const int s1 = d.shell_of[b1], s2 = d.shell_of[b2];
-  double yr = 0.0, yi = 0.0;
   const int m0 = d.shell_start[s1], m1 = d.shell_start[s1 + 1];
   const int n0 = d.shell_start[s2], n1 = d.shell_start[s2 + 1];
+  double yr = 0.0, yi = 0.0;
   for (int mp = m0; mp < m1; ++mp) {
     const double c1r = cs[mp * nff + b1], c1i = cs[nff2 + mp * nff + b1];
 #pragma unroll 4
@@ -252,23 +396,30 @@ k_bond_basis(DevTables d, const double* __restrict__ xt, double* __restrict__ yb
       yi = fma(wr, ai, fma(wi, ar, yi));
     }
   }
+  double* yb = b.yb + d.ws_yb;
   yb[idx] = yr;
   yb[(size_t)total + idx] = yi;
 }
 
-// Gather and basis change, independent of the transfer momentum.  One block
-// per (output channel X, half-set harmonic j).  For V = +S'_j and V = -S'_j:
+// Gather and basis change, independent of the transfer momentum.  Item
+// (p, half-set harmonic j, output channel X).  For V = +S'_j and V = -S'_j:
 //   M^X_AB(V) = sum_entries (+-) yb^{in}_{b1 b2}(v)          (eqn. proj_pos in bonds)
 //   N^X(V) = C M^X(V) C^T                                  (back to form factors)
 // and the real coefficients of cos(l.V/2), sin(l.V/2) for the inverse transform:
 //   Re[e^{-il.V/2} N(V) + e^{+il.V/2} N(-V)] = cos (ReN+ + ReN-) + sin (ImN+ - ImN-).
 __global__ void __launch_bounds__(256)
-k_gather_g2(DevTables d, const double* __restrict__ yb, double* __restrict__ g2) {
-  const int X = blockIdx.y, j = blockIdx.x;
+k_gather_g2(Batch b, const int4* __restrict__ items) {
+  const int4 item = items[blockIdx.x];
+  const int p = item.x;
+  if (skip_point(b, p)) return;
+  const DevTables& d = b.pts[p];
+  const int j = item.y, X = item.z;
   const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol;
   const int nv = 2 * nsh - 1;
   const int nvl = (j == 0) ? 1 : 2;
   const size_t ybim = (size_t)3 * nv * nff2;
+  const double* yb = b.yb + d.ws_yb;
+  double* g2 = b.g2 + d.ws_g2;
   extern __shared__ double sm[];
   double* Mre = sm;                  // [2][nff2]
   double* Mim = Mre + 2 * nff2;
@@ -295,11 +446,11 @@ k_gather_g2(DevTables d, const double* __restrict__ yb, double* __restrict__ g2)
     double nr[2] = {0.0, 0.0}, ni[2] = {0.0, 0.0};
     for (int a = d.shell_start[sm_]; a < d.shell_start[sm_ + 1]; ++a) {
       const double c1r = d.cre[m * nff + a], c1i = d.cim[m * nff + a];
-      for (int b = d.shell_start[sn]; b < d.shell_start[sn + 1]; ++b) {
-        const double c2r = d.cre[n * nff + b], c2i = d.cim[n * nff + b];
+      for (int bb = d.shell_start[sn]; bb < d.shell_start[sn + 1]; ++bb) {
+        const double c2r = d.cre[n * nff + bb], c2i = d.cim[n * nff + bb];
         const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
         for (int vi = 0; vi < nvl; ++vi) {
-          const double mr = Mre[vi * nff2 + a * nff + b], mi = Mim[vi * nff2 + a * nff + b];
+          const double mr = Mre[vi * nff2 + a * nff + bb], mi = Mim[vi * nff2 + a * nff + bb];
           nr[vi] += wr * mr - wi * mi;
           ni[vi] += wr * mi + wi * mr;
         }
@@ -315,20 +466,26 @@ k_gather_g2(DevTables d, const double* __restrict__ yb, double* __restrict__ g2)
 }
 
 // Inverse transform fused with the assembly of eqns. proj_VP/VC/VD and, in
-// mode 1, with the products of eqns. matmul-P/C/D.  One block per lt momenta l.
+// mode 1, with the products of eqns. matmul-P/C/D.  Item (p, l0, nl): nl
+// consecutive momenta of point p starting at l0.
 //   K^X_mn(l) = sum_k E[l][k] g2[X][k][mn]
 //   V^P = U e0e0 - P + K^P,  V^C = U e0e0 + C + K^C,  V^D = U e0e0 + D + K^D
 //   dP = V^P chi'pp V^P, dC = -V^C chi'ph V^C,
 //   dD = (W chi'ph W - V^C chi'ph V^C)/2 with W = 2 V^D - V^C (the SU(2) form
 //   of eqn. matmul-D: 2 dD - dC = W chi'ph W).
-constexpr int kLT = 4;   // largest number of momenta per block
+// mode 1 writes scale * dX/dT with scale = T (dX/ds, s = ln T) if scale_T, else 1.
 __global__ void __launch_bounds__(256)
-k_proj_back(DevTables d, const double* __restrict__ X, int64_t S, const double* __restrict__ g2,
-            const double* __restrict__ dchi, const double* __restrict__ dpart, int nsplit,
-            double* __restrict__ out, int mode, int cross, double scale, int lt) {
-  const int nff = d.nff, nff2 = nff * nff, ncol = d.ncol, nq = d.nq;
-  const int l0 = blockIdx.x * lt;
-  const int nl = min(lt, nq - l0);
+k_proj_back(Batch b, const int4* __restrict__ items, const double* __restrict__ X,
+            double* __restrict__ out, int mode, int cross, int scale_T) {
+  const int4 item = items[blockIdx.x];
+  const int p = item.x;
+  if (skip_point(b, p)) return;
+  const DevTables& d = b.pts[p];
+  const int nff = d.nff, nff2 = nff * nff, ncol = d.ncol;
+  const int l0 = item.y, nl = item.z, lt = d.lt;
+  const double scale = scale_T ? b.Tp[p] : 1.0;
+  const double* g2 = b.g2 + d.ws_g2;
+  const size_t S = (size_t)b.S;
   extern __shared__ double sm[];
   double* Et = sm;                         // [lt][ncol]
   double* Vs = Et + lt * ncol;             // [lt][3][nff2]
@@ -341,23 +498,23 @@ k_proj_back(DevTables d, const double* __restrict__ X, int64_t S, const double* 
   __syncthreads();
   for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
     const int ch = w / nff2, mn = w % nff2;
-    double acc[kLT];
+    double acc[kMaxLT];
 #pragma unroll
-    for (int i = 0; i < kLT; ++i) acc[i] = 0.0;
+    for (int i = 0; i < kMaxLT; ++i) acc[i] = 0.0;
     if (cross) {
       const double* g = g2 + (size_t)ch * ncol * nff2 + mn;
 #pragma unroll 8
       for (int k = 0; k < ncol; ++k) {
         const double gv = g[(size_t)k * nff2];
 #pragma unroll
-        for (int i = 0; i < kLT; ++i)
+        for (int i = 0; i < kMaxLT; ++i)
           if (i < nl) acc[i] = fma(Et[i * ncol + k], gv, acc[i]);
       }
     }
     const double bare = (mn == 0) ? d.U : 0.0;
     const double sgn = (ch == 0) ? -1.0 : 1.0;
     for (int i = 0; i < nl; ++i) {
-      const double own = X[(size_t)ch * S + (size_t)(l0 + i) * nff2 + mn];
+      const double own = X[ch * S + d.off + (size_t)(l0 + i) * nff2 + mn];
       Vs[(i * 3 + ch) * nff2 + mn] = bare + sgn * own + acc[i];
     }
   }
@@ -365,7 +522,7 @@ k_proj_back(DevTables d, const double* __restrict__ X, int64_t S, const double* 
   if (mode == 0) {
     for (int w = threadIdx.x; w < nl * 3 * nff2; w += blockDim.x) {
       const int i = w / (3 * nff2), r = w % (3 * nff2), ch = r / nff2, mn = r % nff2;
-      out[(size_t)ch * S + (size_t)(l0 + i) * nff2 + mn] = Vs[w];
+      out[ch * S + d.off + (size_t)(l0 + i) * nff2 + mn] = Vs[w];
     }
     return;
   }
@@ -374,16 +531,7 @@ k_proj_back(DevTables d, const double* __restrict__ X, int64_t S, const double* 
     const double* VP = Vs + (i * 3 + 0) * nff2;
     const double* VC = Vs + (i * 3 + 1) * nff2;
     const double* VD = Vs + (i * 3 + 2) * nff2;
-    for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
-      const int ch = w / nff2, mn = w % nff2;
-      if (nsplit == 1) {
-        Ch[w] = dchi[(size_t)ch * S + (size_t)l * nff2 + mn];
-      } else {
-        double v = 0.0;
-        for (int s = 0; s < nsplit; ++s) v += dpart[(((size_t)s * 2 + ch) * nq + l) * nff2 + mn];
-        Ch[w] = v;
-      }
-    }
+    load_chi(b, d, l, Ch);
     for (int w = threadIdx.x; w < nff2; w += blockDim.x) Wm[w] = 2.0 * VD[w] - VC[w];
     __syncthreads();
     // T1 = chi'pp V^P, chi'ph V^C, chi'ph W
@@ -407,156 +555,20 @@ k_proj_back(DevTables d, const double* __restrict__ X, int64_t S, const double* 
     }
     __syncthreads();
     for (int w = threadIdx.x; w < nff2; w += blockDim.x) {
-      const size_t o = (size_t)l * nff2 + w;
+      const size_t o = d.off + (size_t)l * nff2 + w;
       out[o] = scale * T2[w];
-      out[(size_t)S + o] = -scale * T2[nff2 + w];
-      out[2 * (size_t)S + o] = 0.5 * scale * (T2[2 * nff2 + w] - T2[nff2 + w]);
+      out[S + o] = -scale * T2[nff2 + w];
+      out[2 * S + o] = 0.5 * scale * (T2[2 * nff2 + w] - T2[nff2 + w]);
     }
     __syncthreads();
   }
 }
 
 // ======================================================= mixed precision
-// Loops in FP32: energies and alpha +- beta in FP64, the pair math in FP32,
-// row sums blocked over 8 rows in FP32 and added into Neumaier-compensated
-// FP32 running sums; the short reductions over columns and slices in FP64.
-struct Exp2F { __device__ float operator()(float x) const { return __builtin_amdgcn_exp2f(x); } };
-struct RcpF { __device__ float operator()(float x) const { return __builtin_amdgcn_rcpf(x); } };
-
-__device__ __forceinline__ void neumaier_add(float& s, float& c, float v) {
-  const float t = s + v;
-  const bool sbig = fabsf(s) >= fabsf(v);
-  const float big = sbig ? s : v, small = sbig ? v : s;
-  c += (big - t) + small;
-  s = t;
-}
-
-template <int SMAX>
-__global__ void __launch_bounds__(kBubThreads)
-k_loops_mixed(DevTables d, double T, int nsplit, int nchunk, double* __restrict__ dchi, int64_t S,
-              double* __restrict__ dpart) {
-  constexpr int NH = 2 * SMAX + 1;
-  constexpr int RB = 8;
-  const int q = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
-  const int lk = d.lk;
-  const int rows = lk / 2 + 1;
-  const int R0 = (int)((int64_t)rows * split / nsplit);
-  const int R1 = (int)((int64_t)rows * (split + 1) / nsplit);
-  const int nr = R1 - R0;
-  const int lq = d.lq;
-  const int ix = q / lq, iy = q % lq;
-  const double inv2T = 0.5 / T;
-
-  extern __shared__ double smem[];
-  double* y1 = smem;
-  double* y2 = y1 + nr;
-  float* pyt = reinterpret_cast<float*>(y2 + nr);      // [nr][NH] (FP32 weights)
-  double* rs = reinterpret_cast<double*>(pyt + ((nr * NH + 1) & ~1));
-  double* gh = rs + lk * 2 * NH;
-
-  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
-    const double* c = d.cshift + ((size_t)iy * lk + (R0 + j)) * 2;
-    y1[j] = c[0];
-    y2[j] = c[1];
-  }
-  for (int j = threadIdx.x; j < nr * NH; j += blockDim.x) pyt[j] = (float)d.pytab[R0 * NH + j];
-  for (int j = threadIdx.x; j < lk * 2 * NH; j += blockDim.x) rs[j] = 0.0;
-  __syncthreads();
-
-  const int t = threadIdx.x;
-  const bool active = t < lk * nchunk;
-  const int px = t % lk, c = t / lk;
-  float sum[2][NH], cmp[2][NH];
-#pragma unroll
-  for (int n = 0; n < NH; ++n) sum[0][n] = sum[1][n] = cmp[0][n] = cmp[1][n] = 0.0f;
-  if (active) {
-    const double cx1 = d.cshift[((size_t)ix * lk + px) * 2];
-    const double cx2 = d.cshift[((size_t)ix * lk + px) * 2 + 1];
-    const double A1 = (-2.0 * d.t * cx1 - d.mu) * inv2T;
-    const double B1 = (-2.0 * d.t - 4.0 * d.tp * cx1) * inv2T;
-    const double A2 = (-2.0 * d.t * cx2 - d.mu) * inv2T;
-    const double B2 = (-2.0 * d.t - 4.0 * d.tp * cx2) * inv2T;
-    const int r0 = (int)((int64_t)nr * c / nchunk);
-    const int r1 = (int)((int64_t)nr * (c + 1) / nchunk);
-    for (int rb = r0; rb < r1; rb += RB) {
-      float blk[2][NH];
-#pragma unroll
-      for (int n = 0; n < NH; ++n) blk[0][n] = blk[1][n] = 0.0f;
-      const int re = min(rb + RB, r1);
-      for (int r = rb; r < re; ++r) {
-        const double al = fma(B1, y1[r], A1);
-        const double be = fma(B2, y2[r], A2);
-        float dph, dpp;
-        loop_dot_pair_f32((float)al, (float)be, (float)(al - be), (float)(al + be), dph, dpp,
-                          Exp2F(), RcpF());
-        const float* w = pyt + r * NH;
-#pragma unroll
-        for (int n = 0; n < NH; ++n) {
-          blk[0][n] = fmaf(dpp, w[n], blk[0][n]);
-          blk[1][n] = fmaf(dph, w[n], blk[1][n]);
-        }
-      }
-#pragma unroll
-      for (int n = 0; n < NH; ++n) {
-        neumaier_add(sum[0][n], cmp[0][n], blk[0][n]);
-        neumaier_add(sum[1][n], cmp[1][n], blk[1][n]);
-      }
-    }
-  }
-  for (int cc = 0; cc < nchunk; ++cc) {
-    if (active && c == cc) {
-      double* dst = rs + px * 2 * NH;
-#pragma unroll
-      for (int n = 0; n < NH; ++n) {
-        dst[n] += (double)sum[0][n] + (double)cmp[0][n];
-        dst[NH + n] += (double)sum[1][n] + (double)cmp[1][n];
-      }
-    }
-    __syncthreads();
-  }
-  const int nout = 2 * d.nsh;
-  int nseg = (int)blockDim.x / nout;
-  if (nseg < 1) nseg = 1;
-  for (int w = threadIdx.x; w < nout * nseg; w += blockDim.x) {
-    const int o = w % nout, seg = w / nout;
-    const int ch = o / d.nsh, j = o % d.nsh;
-    const int sx = d.hx[j], sy = d.hy[j];
-    const int ay = sy < 0 ? -sy : sy;
-    const double sg = sy < 0 ? -1.0 : 1.0;
-    double g = 0.0;
-    for (int x = seg; x < lk; x += nseg) {
-      const double* r = rs + x * 2 * NH + ch * NH;
-      double v = d.pxtab[x * NH + sx] * r[ay];
-      if (sx > 0 && ay > 0) v = fma(-sg * d.pxtab[x * NH + SMAX + sx], r[SMAX + ay], v);
-      g += v;
-    }
-    gh[seg * nout + o] = g;
-  }
-  __syncthreads();
-  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
-    double g = 0.0;
-    for (int s2 = 0; s2 < nseg; ++s2) g += gh[s2 * nout + o];
-    gh[o] = g;
-  }
-  __syncthreads();
-  const int nff2 = d.nff * d.nff;
-  const double base = 1.0 / (4.0 * T * T * (double)lk * (double)lk);
-  for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
-    const int ch = w / nff2, mn = w % nff2;
-    const double* e = d.ebub + (size_t)mn * d.nsh;
-    const double* g = gh + ch * d.nsh;
-    double v = 0.0;
-    for (int j = 0; j < d.nsh; ++j) v = fma(e[j], g[j], v);
-    v *= (ch == 0 ? -base : base);
-    if (nsplit == 1)
-      dchi[(size_t)ch * S + (size_t)q * nff2 + mn] = v;
-    else
-      dpart[(((size_t)split * 2 + ch) * d.nq + q) * nff2 + mn] = v;
-  }
-}
-
 // BF16 hi/lo split with round to nearest even: x ~ hi + lo (about 16 mantissa
 // bits); products hi*hi + hi*lo + lo*hi accumulate in FP32 on the matrix cores.
+// v_mfma_f32_16x16x16bf16_1k operand layout: lane l holds A[l%16][4(l/16)+j],
+// B[4(l/16)+j][l%16] (j = 0..3) and D[4(l/16)+j][l%16].
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -574,24 +586,26 @@ __device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigne
   lo = bf16_rne(f - bf16_to_f32(hi));
 }
 
-// Forward transform on the matrix cores:
-//   xt[ch][k][mn] = (1/Nq) sum_u E[u][k] X[ch][u][mn]
-// as C[M=ncol][N=3 nff^2] = A^T B with A = E (pre-split, [Nq][ncol]) and
-// B = X (split on the fly).  One 16x16 output tile per block; its 4 waves
-// split the transfer grid and are added in LDS in a fixed order.
-// v_mfma_f32_16x16x16bf16_1k operand layout: lane l holds A[l%16][4(l/16)+j],
-// B[4(l/16)+j][l%16] (j = 0..3) and D[4(l/16)+j][l%16].
+// Forward transform on the matrix cores: xt = (1/Nq) E^T X as
+// C[M=ncol][N=3 nff^2] with A = E (pre-split, [Nq][ncol]) and B = X (split on
+// the fly).  Item (p, M tile, N tile): one 16x16 output tile; the 4 waves split
+// the transfer grid and are added in LDS in a fixed order.
 __global__ void __launch_bounds__(256)
-k_dft_fwd_mfma(const unsigned short* __restrict__ eh, const unsigned short* __restrict__ el,
-               int nq, int ncol, const double* __restrict__ X, int64_t S, int nff2,
-               double* __restrict__ xt) {
+k_dft_fwd_mfma(Batch b, const int4* __restrict__ items, const double* __restrict__ X) {
   __shared__ float red[4][256];
+  const int4 item = items[blockIdx.x];
+  const int p = item.x;
+  if (skip_point(b, p)) return;
+  const DevTables& d = b.pts[p];
+  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = blockIdx.x * 16, n0 = blockIdx.y * 16;
+  const int m0 = item.y * 16, n0 = item.z * 16;
   const int ml = m0 + (lane & 15), nl = n0 + (lane & 15), kq = 4 * (lane >> 4);
   const bool mok = ml < ncol, nok = nl < 3 * nff2;
   const int ch = nok ? nl / nff2 : 0, mn = nok ? nl % nff2 : 0;
-  const double* xp = X + (size_t)ch * S + mn;
+  const double* xp = X + (size_t)ch * b.S + d.off + mn;
+  const unsigned short* eh = d.eph_hi;
+  const unsigned short* el = d.eph_lo;
   const int nsteps = (nq + 15) / 16;
   const int s0 = nsteps * w / 4, s1 = nsteps * (w + 1) / 4;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -617,6 +631,7 @@ k_dft_fwd_mfma(const unsigned short* __restrict__ eh, const unsigned short* __re
   __syncthreads();
   if (w == 0) {
     const double inv = 1.0 / (double)nq;
+    double* xt = b.xt + d.ws_xt;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const double v = ((double)red[0][lane * 4 + j] + (double)red[1][lane * 4 + j]) +
@@ -630,18 +645,24 @@ k_dft_fwd_mfma(const unsigned short* __restrict__ eh, const unsigned short* __re
   }
 }
 
-// Inverse transform on the matrix cores:
-//   K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn]
-// as C[M=Nq][N=3 nff^2] = A B with A = E (pre-split, [Nq][ncol]) and B = g2
-// (split on the fly).  Each wave owns one 16x16 output tile.
+// Inverse transform on the matrix cores: K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn]
+// as C[M=Nq][N=3 nff^2] with A = E (pre-split) and B = g2 (split on the fly).
+// Item (p, M tile, N tile group): each wave owns one 16x16 output tile.
 __global__ void __launch_bounds__(256)
-k_dft_inv_mfma(const unsigned short* __restrict__ eh, const unsigned short* __restrict__ el,
-               int nq, int ncol, const double* __restrict__ g2, int nff2, float* __restrict__ K) {
+k_dft_inv_mfma(Batch b, const int4* __restrict__ items) {
+  const int4 item = items[blockIdx.x];
+  const int p = item.x;
+  if (skip_point(b, p)) return;
+  const DevTables& d = b.pts[p];
+  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = blockIdx.x * 16, n0 = (blockIdx.y * 4 + w) * 16;
+  const int m0 = item.y * 16, n0 = (item.z * 4 + w) * 16;
   const int ml = m0 + (lane & 15), nl = n0 + (lane & 15), kq = 4 * (lane >> 4);
   const bool mok = ml < nq, nok = nl < 3 * nff2;
   const int ch = nok ? nl / nff2 : 0, mn = nok ? nl % nff2 : 0;
+  const unsigned short* eh = d.eph_hi;
+  const unsigned short* el = d.eph_lo;
+  const double* g2 = b.g2 + d.ws_g2;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < ncol; k0 += 16) {
     bf16x4 ah, al, bh, bl;
@@ -660,6 +681,7 @@ k_dft_inv_mfma(const unsigned short* __restrict__ eh, const unsigned short* __re
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
   }
+  float* K = b.kinv + d.ws_k;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int m = m0 + kq + j, n = n0 + (lane & 15);
@@ -670,15 +692,21 @@ k_dft_inv_mfma(const unsigned short* __restrict__ eh, const unsigned short* __re
   }
 }
 
-// Assembly of V and the products in FP32; one block per momentum.  Inputs:
-// K (inverse transform, FP32, may be null without cross terms), X and the
-// loops (FP64); output scale * dX/dT in FP64.
+// Assembly of V and the products in FP32; item (p, l).  Inputs: the inverse
+// transform K (FP32; unused without cross terms), X and the loops (FP64);
+// output scale * dX/dT (mode 1) or V (mode 0) in FP64.
 __global__ void __launch_bounds__(256)
-k_products_f32(DevTables d, const double* __restrict__ X, int64_t S, const float* __restrict__ K,
-               const double* __restrict__ dchi, const double* __restrict__ dpart, int nsplit,
-               double* __restrict__ out, int mode, double scale) {
+k_products_f32(Batch b, const int4* __restrict__ items, const double* __restrict__ X,
+               double* __restrict__ out, int mode, int cross, int scale_T) {
+  const int4 item = items[blockIdx.x];
+  const int p = item.x;
+  if (skip_point(b, p)) return;
+  const DevTables& d = b.pts[p];
   const int nff = d.nff, nff2 = nff * nff, nq = d.nq;
-  const int l = blockIdx.x;
+  const int l = item.y;
+  const double scale = scale_T ? b.Tp[p] : 1.0;
+  const size_t S = (size_t)b.S;
+  const float* K = b.kinv + d.ws_k;
   extern __shared__ float fsm[];
   float* Vs = fsm;              // [3][nff2]
   float* Ch = Vs + 3 * nff2;    // [2][nff2]
@@ -688,24 +716,25 @@ k_products_f32(DevTables d, const double* __restrict__ X, int64_t S, const float
   for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
     const int ch = w / nff2, mn = w % nff2;
     const float bare = (mn == 0) ? (float)d.U : 0.0f;
-    const float own = (float)X[(size_t)ch * S + (size_t)l * nff2 + mn];
-    const float kk = K ? K[((size_t)ch * nq + l) * nff2 + mn] : 0.0f;
+    const float own = (float)X[ch * S + d.off + (size_t)l * nff2 + mn];
+    const float kk = cross ? K[((size_t)ch * nq + l) * nff2 + mn] : 0.0f;
     Vs[w] = bare + (ch == 0 ? -own : own) + kk;
   }
   if (mode == 0) {
     __syncthreads();
     for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x)
-      out[(size_t)(w / nff2) * S + (size_t)l * nff2 + w % nff2] = (double)Vs[w];
+      out[(size_t)(w / nff2) * S + d.off + (size_t)l * nff2 + w % nff2] = (double)Vs[w];
     return;
   }
   for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
     const int ch = w / nff2, mn = w % nff2;
     double v;
-    if (nsplit == 1) {
-      v = dchi[(size_t)ch * S + (size_t)l * nff2 + mn];
+    if (d.nsplit == 1) {
+      v = b.dchi[(size_t)ch * S + d.off + (size_t)l * nff2 + mn];
     } else {
       v = 0.0;
-      for (int s2 = 0; s2 < nsplit; ++s2) v += dpart[(((size_t)s2 * 2 + ch) * nq + l) * nff2 + mn];
+      for (int s2 = 0; s2 < d.nsplit; ++s2)
+        v += b.dpart[d.ws_dpart + (((size_t)s2 * 2 + ch) * nq + l) * nff2 + mn];
     }
     Ch[w] = (float)v;
   }
@@ -734,39 +763,65 @@ k_products_f32(DevTables d, const double* __restrict__ X, int64_t S, const float
   }
   __syncthreads();
   for (int w = threadIdx.x; w < nff2; w += blockDim.x) {
-    const size_t o = (size_t)l * nff2 + w;
+    const size_t o = d.off + (size_t)l * nff2 + w;
     out[o] = scale * (double)T2[w];
-    out[(size_t)S + o] = -scale * (double)T2[nff2 + w];
-    out[2 * (size_t)S + o] = 0.5 * scale * ((double)T2[2 * nff2 + w] - (double)T2[nff2 + w]);
+    out[S + o] = -scale * (double)T2[nff2 + w];
+    out[2 * S + o] = 0.5 * scale * ((double)T2[2 * nff2 + w] - (double)T2[nff2 + w]);
   }
 }
 
 // ----------------------------------------------------------- ODE helpers
+// Segment items (p, channel, chunk): kSeg consecutive elements of one point's
+// channel block in a [3][S] array.
 struct SlopeSet {
   const double* k[7];
   double coef[7];
 };
 
-__global__ void k_axpy_stage(const double* __restrict__ X, SlopeSet ks, int nk, double h,
-                             double* __restrict__ out, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+__device__ __forceinline__ bool seg_range(const Batch& b, const int4& it, size_t& base, int& n) {
+  const DevTables& d = b.pts[it.x];
+  const int64_t len = (int64_t)d.nq * d.nff * d.nff;
+  const int64_t s0 = (int64_t)it.z * kSeg;
+  if (s0 >= len) return false;
+  n = (int)min((int64_t)kSeg, len - s0);
+  base = (size_t)it.y * b.S + d.off + s0;
+  return true;
+}
+
+// out = X + h sum_j coef_j k_j; frozen points untouched when skip_frozen
+__global__ void __launch_bounds__(256)
+k_axpy(Batch b, const int4* __restrict__ items, const double* __restrict__ X, SlopeSet ks, int nk,
+       double h, double* __restrict__ out, int skip_frozen) {
+  const int4 it = items[blockIdx.x];
+  if (skip_frozen && skip_point(b, it.x)) return;
+  size_t base;
+  int n;
+  if (!seg_range(b, it, base, n)) return;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const size_t e = base + i;
     double acc = 0.0;
-    for (int j = 0; j < nk; ++j) acc = fma(ks.coef[j], ks.k[j][i], acc);
-    out[i] = fma(h, acc, X[i]);
+    for (int j = 0; j < nk; ++j) acc = fma(ks.coef[j], ks.k[j][e], acc);
+    out[e] = fma(h, acc, X[e]);
   }
 }
 
-// max |x| as the ordered bit pattern of a non-negative double (NaN sorts
-// above +inf, so a non-finite state is seen)
-__global__ void k_maxabs(const double* __restrict__ X, int64_t n, unsigned long long* word) {
+// per-point max |x| as the ordered bit pattern of a non-negative double (NaN
+// sorts above +inf, so a non-finite state is seen)
+__global__ void __launch_bounds__(256)
+k_maxabs(Batch b, const int4* __restrict__ items, const double* __restrict__ X,
+         unsigned long long* __restrict__ words) {
   __shared__ unsigned long long red[256];
+  const int4 it = items[blockIdx.x];
   unsigned long long m = 0ull;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    unsigned long long b = (unsigned long long)__double_as_longlong(fabs(X[i]));
-    if (X[i] != X[i]) b = 0x7ff8000000000000ull;
-    m = b > m ? b : m;
+  size_t base;
+  int n;
+  if (!skip_point(b, it.x) && seg_range(b, it, base, n)) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double x = X[base + i];
+      unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(x));
+      if (x != x) bits = 0x7ff8000000000000ull;
+      m = bits > m ? bits : m;
+    }
   }
   red[threadIdx.x] = m;
   __syncthreads();
@@ -775,29 +830,30 @@ __global__ void k_maxabs(const double* __restrict__ X, int64_t n, unsigned long 
       red[threadIdx.x] = red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicMax(word, red[0]);
-}
-
-__global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  if (threadIdx.x == 0 && red[0] != 0ull) atomicMax(words + it.x, red[0]);
 }
 
 // Partial sums of ((h sum_j e_j k_j) / (atol + rtol max(|y0|,|y5|)))^2 per
-// block, in a fixed tree order (deterministic).
-__global__ void k_errnorm(const double* __restrict__ y0, const double* __restrict__ y5,
-                          SlopeSet ks, int nk, double h, double rtol, double atol, int64_t n,
-                          double* red_out) {
+// segment, in a fixed tree order (deterministic).
+__global__ void __launch_bounds__(256)
+k_errnorm(Batch b, const int4* __restrict__ items, const double* __restrict__ y0,
+          const double* __restrict__ y5, SlopeSet ks, int nk, double h, double rtol, double atol,
+          double* __restrict__ red_out) {
   __shared__ double red[256];
+  const int4 it = items[blockIdx.x];
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    double e = 0.0;
-    for (int j = 0; j < nk; ++j) e = fma(ks.coef[j], ks.k[j][i], e);
-    e *= h;
-    const double sc = atol + rtol * fmax(fabs(y0[i]), fabs(y5[i]));
-    const double r = e / sc;
-    acc = fma(r, r, acc);
+  size_t base;
+  int n;
+  if (seg_range(b, it, base, n)) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const size_t e = base + i;
+      double er = 0.0;
+      for (int j = 0; j < nk; ++j) er = fma(ks.coef[j], ks.k[j][e], er);
+      er *= h;
+      const double sc = atol + rtol * fmax(fabs(y0[e]), fabs(y5[e]));
+      const double r = er / sc;
+      acc = fma(r, r, acc);
+    }
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -808,205 +864,180 @@ __global__ void k_errnorm(const double* __restrict__ y0, const double* __restric
   if (threadIdx.x == 0) red_out[blockIdx.x] = red[0];
 }
 
+__global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_i32(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Tp[p] = Ttab[4 * step + stage] for every point (the RK4 stage temperature)
+__global__ void k_set_T(double* Tp, int npts, const double* __restrict__ Ttab,
+                        const int* __restrict__ step, int stage) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < npts) Tp[i] = Ttab[4 * step[0] + stage];
+}
+
+// Tp[i] = T[i] for a host array passed by value (up to 64 points per launch)
+struct TValues {
+  double v[64];
+};
+__global__ void k_set_Tv(double* Tp, int n, TValues tv) {
+  const int i = threadIdx.x;
+  if (i < n) Tp[i] = tv.v[i];
+}
+
+// End of an RK4 step: record max|X| per point, stop points whose state passed
+// Xmax or became non-finite (frozen = step index of the stop), clear the max
+// words and advance the step counter.
+__global__ void k_step_end(unsigned long long* words, int npts, int* frozen, double* hist,
+                           int* step, int nsteps, double xmax) {
+  const int i = threadIdx.x;
+  const int s = step[0];
+  for (int p = i; p < npts; p += blockDim.x) {
+    const double m = __longlong_as_double((long long)words[p]);
+    if (!frozen[p]) {
+      hist[(size_t)(s + 1) * npts + p] = m;
+      if (!(m <= xmax)) frozen[p] = s + 1;
+    }
+    words[p] = 0ull;
+  }
+  __syncthreads();
+  if (i == 0 && s < nsteps) step[0] = s + 1;
+}
+
 }  // namespace
 
-// ------------------------------------------------------------- launchers
-LoopGeom loop_geometry(const DevTables& d) {
-  // Split the half fine grid of every transfer momentum into nsplit row blocks
-  // of lk * nchunk threads until about 8 waves per SIMD are in flight, keeping
-  // at least 4 rows per thread and at most kBubThreads threads per block.
-  const int rows = d.lk / 2 + 1;
-  const int64_t target = (int64_t)256 * 4 * 8 * 64;   // lanes for ~8 waves per SIMD
-  int nsplit = 1, nchunk = 1;
-  for (;;) {
-    const int64_t lanes = (int64_t)d.nq * d.lk * nsplit * nchunk;
-    if (lanes >= target) break;
-    if (d.lk * (nchunk + 1) <= kBubThreads && rows / (nsplit * (nchunk + 1)) >= 4) {
-      ++nchunk;
-    } else if (nsplit < 16 && rows / ((nsplit + 1) * nchunk) >= 4) {
-      ++nsplit;
-    } else {
-      break;
-    }
-  }
-  LoopGeom g;
-  g.nsplit = nsplit;
-  g.nchunk = nchunk;
-  g.threads = ((d.lk * nchunk + 63) / 64) * 64;
-  const int nrmax = (rows + nsplit - 1) / nsplit;
-  const int NH = 2 * d.smax + 1, nout = 2 * d.nsh;
-  int nseg = g.threads / nout;
-  if (nseg < 1) nseg = 1;
-  g.smem = sizeof(double) * ((size_t)2 * nrmax + (size_t)nrmax * NH + (size_t)d.lk * 2 * NH +
-                             (size_t)nseg * nout);
-  return g;
-}
-
-void launch_loops(const DevTables& d, double T, double* dchi, int64_t S, double* dpart,
-                  bool sum_slices, hipStream_t s) {
-  const LoopGeom g = loop_geometry(d);
-  const dim3 grid((unsigned)(d.nq * g.nsplit));
-  switch (d.smax) {
+// ============================================================== launchers
+void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, hipStream_t s) {
+  if (r.n <= 0) return;
+  if (!L.loop_persistent) queue = nullptr;
+  const int grid = L.loop_persistent ? std::min(r.n, L.loop_blocks) : r.n;
+  const dim3 blk(L.loop_threads);
+  const size_t sm = L.loop_smem;
+  const int4* it = L.loop_items + r.begin;
+  switch (L.smax_max) {
     case 0:
-      hipLaunchKernelGGL(k_loops_f64<0>, grid, dim3(g.threads), g.smem, s, d, T, g.nsplit, g.nchunk,
-                         dchi, S, dpart);
+      if (mixed) hipLaunchKernelGGL((k_loops<0, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
+      else hipLaunchKernelGGL((k_loops<0, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
       break;
     case 2:
-      hipLaunchKernelGGL(k_loops_f64<2>, grid, dim3(g.threads), g.smem, s, d, T, g.nsplit, g.nchunk,
-                         dchi, S, dpart);
+      if (mixed) hipLaunchKernelGGL((k_loops<2, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
+      else hipLaunchKernelGGL((k_loops<2, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
       break;
     default:
-      hipLaunchKernelGGL(k_loops_f64<4>, grid, dim3(g.threads), g.smem, s, d, T, g.nsplit, g.nchunk,
-                         dchi, S, dpart);
+      if (mixed) hipLaunchKernelGGL((k_loops<4, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
+      else hipLaunchKernelGGL((k_loops<4, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
       break;
   }
-  if (sum_slices && g.nsplit > 1) {
-    const int nff2 = d.nff * d.nff;
-    const int64_t n = (int64_t)2 * d.nq * nff2;
-    int blocks = (int)((n + 255) / 256);
-    if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(k_chi_sum, dim3(blocks), dim3(256), 0, s, dpart, g.nsplit, d.nq, nff2, dchi, S);
+}
+
+void launch_chi_sum(const Launch& L, const ItemRange& r, double* dchi, hipStream_t s) {
+  if (r.n <= 0) return;
+  hipLaunchKernelGGL(k_chi_sum, dim3(r.n), dim3(256), 0, s, L.b, L.chi_items + r.begin, dchi);
+}
+
+void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s) {
+  if (mixed) {
+    if (r.fwd_mfma.n > 0)
+      hipLaunchKernelGGL(k_dft_fwd_mfma, dim3(r.fwd_mfma.n), dim3(256), 0, s, L.b,
+                         L.fwd_mfma_items + r.fwd_mfma.begin, X);
+  } else if (r.fwd.n > 0) {
+    hipLaunchKernelGGL((k_dft_fwd<4, 16>), dim3(r.fwd.n), dim3(1024), 0, s, L.b,
+                       L.fwd_items + r.fwd.begin, X);
   }
+  if (r.basis.n > 0)
+    hipLaunchKernelGGL(k_bond_basis, dim3(r.basis.n), dim3(256), 0, s, L.b,
+                       L.basis_items + r.basis.begin);
+  if (r.gather.n > 0)
+    hipLaunchKernelGGL(k_gather_g2, dim3(r.gather.n), dim3(256), L.gather_smem, s, L.b,
+                       L.gather_items + r.gather.begin);
+  if (mixed && r.inv_mfma.n > 0)
+    hipLaunchKernelGGL(k_dft_inv_mfma, dim3(r.inv_mfma.n), dim3(256), 0, s, L.b,
+                       L.inv_mfma_items + r.inv_mfma.begin);
 }
 
-void launch_project_front(const DevTables& d, const double* X, int64_t S, double* xt, double* yb,
-                          double* g2, uint32_t flags, hipStream_t s) {
-  if (flags & TUFRG_NO_CROSS) return;
-  const int nff2 = d.nff * d.nff;
-  const int ncols = 3 * nff2;
-  if (d.nq * ncols >= 2000000) {
-    dim3 g1((ncols + 63) / 64, (d.ncol + 7) / 8);
-    hipLaunchKernelGGL((k_dft_fwd<8, 8>), g1, dim3(512), 0, s, d.eph, d.nq, d.ncol, X, S, nff2, xt);
-  } else {
-    dim3 g1((ncols + 63) / 64, (d.ncol + 3) / 4);
-    hipLaunchKernelGGL((k_dft_fwd<4, 16>), g1, dim3(1024), 0, s, d.eph, d.nq, d.ncol, X, S, nff2, xt);
+void launch_back(const Launch& L, const Ranges& r, const double* X, double* out, int mode,
+                 bool cross, bool scale_T, bool mixed, hipStream_t s) {
+  if (mixed) {
+    if (r.prod.n > 0)
+      hipLaunchKernelGGL(k_products_f32, dim3(r.prod.n), dim3(256), L.prod_smem, s, L.b,
+                         L.prod_items + r.prod.begin, X, out, mode, cross ? 1 : 0, scale_T ? 1 : 0);
+    return;
   }
-  const int nv = 2 * d.nsh - 1;
-  const int total = 3 * nv * nff2;
-  hipLaunchKernelGGL(k_bond_basis, dim3((total + 255) / 256), dim3(256), 0, s, d, xt, yb);
-  const size_t sm_mid = sizeof(double) * 4 * (size_t)nff2;
-  hipLaunchKernelGGL(k_gather_g2, dim3(d.nsh, 3), dim3(256), sm_mid, s, d, yb, g2);
+  if (r.back.n > 0)
+    hipLaunchKernelGGL(k_proj_back, dim3(r.back.n), dim3(256), L.back_smem, s, L.b,
+                       L.back_items + r.back.begin, X, out, mode, cross ? 1 : 0, scale_T ? 1 : 0);
 }
 
-void launch_project_back(const DevTables& d, const double* X, int64_t S, const double* g2,
-                         const double* dchi, const double* dpart, double* out, int mode,
-                         uint32_t flags, double scale, hipStream_t s) {
-  const int nff2 = d.nff * d.nff;
-  const int nsplit = loop_geometry(d).nsplit;
-  const int cross = (flags & TUFRG_NO_CROSS) ? 0 : 1;
-  auto sm_bytes = [&](int l) {
-    return sizeof(double) * ((size_t)l * d.ncol + (size_t)l * 3 * nff2 + 9 * (size_t)nff2);
-  };
-  // momenta per block: two on large grids (halves the reads of g2), one
-  // otherwise; always within 64 KB of LDS
-  int lt = d.nq >= 1024 ? 2 : 1;
-  while (lt > 1 && sm_bytes(lt) > 65536) --lt;
-  hipLaunchKernelGGL(k_proj_back, dim3((d.nq + lt - 1) / lt), dim3(256), sm_bytes(lt), s, d, X, S,
-                     g2, dchi, dpart, nsplit, out, mode, cross, scale, lt);
-}
-
-size_t loop_smem_mixed(const DevTables& d, const LoopGeom& g) {
-  const int rows = d.lk / 2 + 1, nrmax = (rows + g.nsplit - 1) / g.nsplit;
-  const int NH = 2 * d.smax + 1, nout = 2 * d.nsh;
-  int nseg = g.threads / nout;
-  if (nseg < 1) nseg = 1;
-  return sizeof(double) * ((size_t)2 * nrmax + (size_t)d.lk * 2 * NH + (size_t)nseg * nout) +
-         sizeof(float) * (((size_t)nrmax * NH + 1) & ~(size_t)1);
-}
-
-void launch_loops_mixed(const DevTables& d, double T, double* dchi, int64_t S, double* dpart,
-                        bool sum_slices, hipStream_t s) {
-  const LoopGeom g = loop_geometry(d);
-  const size_t sm = loop_smem_mixed(d, g);
-  const dim3 grid((unsigned)(d.nq * g.nsplit));
-  switch (d.smax) {
-    case 0:
-      hipLaunchKernelGGL(k_loops_mixed<0>, grid, dim3(g.threads), sm, s, d, T, g.nsplit, g.nchunk,
-                         dchi, S, dpart);
-      break;
-    case 2:
-      hipLaunchKernelGGL(k_loops_mixed<2>, grid, dim3(g.threads), sm, s, d, T, g.nsplit, g.nchunk,
-                         dchi, S, dpart);
-      break;
-    default:
-      hipLaunchKernelGGL(k_loops_mixed<4>, grid, dim3(g.threads), sm, s, d, T, g.nsplit, g.nchunk,
-                         dchi, S, dpart);
-      break;
-  }
-  if (sum_slices && g.nsplit > 1) {
-    const int nff2 = d.nff * d.nff;
-    const int64_t n = (int64_t)2 * d.nq * nff2;
-    int blocks = (int)((n + 255) / 256);
-    if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(k_chi_sum, dim3(blocks), dim3(256), 0, s, dpart, g.nsplit, d.nq, nff2, dchi, S);
-  }
-}
-
-void launch_project_front_mixed(const DevTables& d, const double* X, int64_t S, double* xt,
-                                double* yb, double* g2, uint32_t flags, hipStream_t s) {
-  if (flags & TUFRG_NO_CROSS) return;
-  const int nff2 = d.nff * d.nff;
-  dim3 g1((d.ncol + 15) / 16, (3 * nff2 + 15) / 16);
-  hipLaunchKernelGGL(k_dft_fwd_mfma, g1, dim3(256), 0, s, d.eph_hi, d.eph_lo, d.nq, d.ncol, X, S,
-                     nff2, xt);
-  const int nv = 2 * d.nsh - 1;
-  const int total = 3 * nv * nff2;
-  hipLaunchKernelGGL(k_bond_basis, dim3((total + 255) / 256), dim3(256), 0, s, d, xt, yb);
-  const size_t sm_mid = sizeof(double) * 4 * (size_t)nff2;
-  hipLaunchKernelGGL(k_gather_g2, dim3(d.nsh, 3), dim3(256), sm_mid, s, d, yb, g2);
-}
-
-void launch_inverse_mixed(const DevTables& d, const double* g2, float* K, uint32_t flags,
-                          hipStream_t s) {
-  if (flags & TUFRG_NO_CROSS) return;
-  const int nff2 = d.nff * d.nff;
-  dim3 g((d.nq + 15) / 16, (3 * nff2 + 63) / 64);
-  hipLaunchKernelGGL(k_dft_inv_mfma, g, dim3(256), 0, s, d.eph_hi, d.eph_lo, d.nq, d.ncol, g2, nff2,
-                     K);
-}
-
-void launch_products_mixed(const DevTables& d, const double* X, int64_t S, const float* K,
-                           const double* dchi, const double* dpart, double* out, int mode,
-                           uint32_t flags, double scale, hipStream_t s) {
-  const int nff2 = d.nff * d.nff;
-  const int nsplit = loop_geometry(d).nsplit;
-  const float* Kp = (flags & TUFRG_NO_CROSS) ? nullptr : K;
-  hipLaunchKernelGGL(k_products_f32, dim3(d.nq), dim3(256), sizeof(float) * 12 * (size_t)nff2, s, d,
-                     X, S, Kp, dchi, dpart, nsplit, out, mode, scale);
-}
-
-void launch_axpy_stage(const double* X, const double* const* k, const double* coef, int nk,
-                       double h, double* out, int64_t n, hipStream_t s) {
+void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const double* const* k,
+                 const double* coef, int nk, double h, double* out, bool skip_frozen, hipStream_t s) {
+  if (r.n <= 0) return;
   SlopeSet ks{};
   for (int j = 0; j < nk; ++j) {
     ks.k[j] = k[j];
     ks.coef[j] = coef[j];
   }
-  int blocks = (int)((n + 255) / 256);
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_axpy_stage, dim3(blocks), dim3(256), 0, s, X, ks, nk, h, out, n);
+  hipLaunchKernelGGL(k_axpy, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, X, ks, nk, h,
+                     out, skip_frozen ? 1 : 0);
 }
 
-void launch_maxabs(const double* X, int64_t n, unsigned long long* word, hipStream_t s) {
-  int blocks = (int)((n + 255) / 256);
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_maxabs, dim3(blocks), dim3(256), 0, s, X, n, word);
+void launch_maxabs(const Launch& L, const ItemRange& r, const double* X, unsigned long long* words,
+                   hipStream_t s) {
+  if (r.n <= 0) return;
+  hipLaunchKernelGGL(k_maxabs, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, X, words);
+}
+
+void launch_errnorm(const Launch& L, const ItemRange& r, const double* y0, const double* y5,
+                    const double* const* k, const double* e, int nk, double h, double rtol,
+                    double atol, double* red, hipStream_t s) {
+  if (r.n <= 0) return;
+  SlopeSet ks{};
+  for (int j = 0; j < nk; ++j) {
+    ks.k[j] = k[j];
+    ks.coef[j] = e[j];
+  }
+  hipLaunchKernelGGL(k_errnorm, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, y0, y5, ks,
+                     nk, h, rtol, atol, red);
 }
 
 void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u64, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
 }
 
-void launch_errnorm(const double* y0, const double* y5, const double* const* k, const double* e,
-                    int nk, double h, double rtol, double atol, int64_t n, double* red, int nred,
-                    hipStream_t s) {
-  SlopeSet ks{};
-  for (int j = 0; j < nk; ++j) {
-    ks.k[j] = k[j];
-    ks.coef[j] = e[j];
+void launch_fill_i32(int* p, int n, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+}
+
+void launch_set_T(double* Tp, int npts, const double* Ttab, const int* step, int stage,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_set_T, dim3((npts + 255) / 256), dim3(256), 0, s, Tp, npts, Ttab, step, stage);
+}
+
+void launch_set_T_values(double* Tp, const double* T_host, int n, hipStream_t s) {
+  for (int p0 = 0; p0 < n; p0 += 64) {
+    TValues tv{};
+    const int m = std::min(64, n - p0);
+    for (int i = 0; i < m; ++i) tv.v[i] = T_host[p0 + i];
+    hipLaunchKernelGGL(k_set_Tv, dim3(1), dim3(64), 0, s, Tp + p0, m, tv);
   }
-  hipLaunchKernelGGL(k_errnorm, dim3(nred), dim3(256), 0, s, y0, y5, ks, nk, h, rtol, atol, n,
-                     red);
+}
+
+void launch_step_end(unsigned long long* words, int npts, int* frozen, double* hist, int* step,
+                     int nsteps, double xmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(256), 0, s, words, npts, frozen, hist, step, nsteps,
+                     xmax);
+}
+
+const void* loop_kernel_symbol(int smax_max, bool mixed) {
+  switch (smax_max) {
+    case 0: return mixed ? (const void*)k_loops<0, true> : (const void*)k_loops<0, false>;
+    case 2: return mixed ? (const void*)k_loops<2, true> : (const void*)k_loops<2, false>;
+    default: return mixed ? (const void*)k_loops<4, true> : (const void*)k_loops<4, false>;
+  }
 }
 
 }  // namespace tufrg

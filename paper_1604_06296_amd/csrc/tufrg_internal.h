@@ -62,97 +62,131 @@ std::string build_tables(const tufrg_point& p, HostTables& t);   // "" on succes
 int nff_of_shells(int shells);
 
 // ---------------------------------------------------------- device side
+constexpr int kLoopThreadsMax = 512;   // loop kernel block size bound
+constexpr int kMaxLT = 4;              // momenta per block of the FP64 back end
+constexpr int kSeg = 4096;             // elements per ODE segment item
+
+// Per-point tables and launch parameters as seen by the kernels (device array).
 struct DevTables {
-  int nff, nq, lq, lk, nsh, ncol, smax;
+  int nff, nq, lq, lk, nsh, ncol, smax, nshell;
+  int nsplit, nchunk;     // loop geometry: row slices per momentum, row chunks per column
+  int lt;                 // momenta per block of the FP64 back end
+  int pad;
   double t, tp, mu, U;
-  double* cre;   // [nff*nff]
+  int64_t off;            // element offset of the point inside one channel of [3][S] / [2][S]
+  int64_t ws_xt, ws_yb, ws_g2, ws_dpart, ws_k;   // element offsets into the shared workspace
+  double* cre;            // [nff*nff]
   double* cim;
   int* shell_start;       // [nshell+1]
   int* shell_of;          // [nff]
-  double* ebub;  // [nff*nff*nsh]
-  double* pxtab; // [lk][2 smax + 1]
-  double* pytab; // [lk/2+1][2 smax + 1]
-  double* cshift; // [lq][lk][2]: cos(p_j + q_i/2), cos(p_j - q_i/2) per axis
-  double* eph;   // [nq][ncol]
-  unsigned short* eph_hi;  // BF16 split of eph (mixed precision): eph ~ hi + lo
+  double* ebub;           // [nff*nff*nsh]
+  double* pxtab;          // [lk][2 smax + 1]
+  double* pytab;          // [lk/2+1][2 smax + 1]
+  double* cshift;         // [lq][lk][2]: cos(p_j + q_i/2), cos(p_j - q_i/2) per axis
+  double* eph;            // [nq][ncol]
+  unsigned short* eph_hi; // BF16 split of eph (mixed precision): eph ~ hi + lo
   unsigned short* eph_lo;
   int32_t* mrow;
   int32_t* ment;
-  int32_t* hx;   // half set [nsh]
+  int32_t* hx;            // half set [nsh]
   int32_t* hy;
-  int nshell;
 };
 
-struct Workspace {
-  double* xt;    // forward transform [3][ncol][nff^2] (largest point)
-  double* yb;    // bond-basis transform [2 (re, im)][3][2 nsh - 1][nff^2]
-  double* g2;    // inverse-transform coefficients [3][ncol][nff^2]
-  double* dpart; // loop slices [nsplit][2][Nq][nff^2] (largest point)
-  float* kinv;   // mixed precision: inverse transform K [3][Nq][nff^2] (largest point)
-  double* dchi;  // loops [2][S]
-  double* stage; // RK stage state [3][S]
-  double* k[7];  // RK slopes [3][S] each
-  double* ytmp;  // [3][S]
-  double* red;   // reduction scratch (doubles)
-  unsigned long long* umax; // max-abs words per point
+// Kernel-side view of one launch: tables, temperatures, stop flags, workspace.
+struct Batch {
+  const DevTables* pts;   // device array [npts]
+  int64_t S;              // channel stride of [3][S] / [2][S] arrays
+  const double* Tp;       // per-point temperatures (device)
+  const int* frozen;      // per-point stop flags (device) or null
+  double* dchi;           // loops [2][S]
+  double* dpart;          // loop slices
+  double* xt;             // forward transforms
+  double* yb;             // bond-basis transforms
+  double* g2;             // inverse-transform coefficients
+  float* kinv;            // inverse transforms (mixed precision)
 };
+
+struct ItemRange {
+  int begin = 0, n = 0;
+};
+
+// Item ranges of one launch set (all points, or one point)
+struct Ranges {
+  ItemRange loop, chi, fwd, fwd_mfma, basis, gather, inv_mfma, back, prod, seg;
+};
+
+// Device item tables and launch shapes shared by all launches of a context.
+struct Launch {
+  Batch b;
+  const int4* loop_items;
+  const int4* chi_items;
+  const int4* fwd_items;
+  const int4* fwd_mfma_items;
+  const int4* basis_items;
+  const int4* gather_items;
+  const int4* inv_mfma_items;
+  const int4* back_items;
+  const int4* prod_items;
+  const int4* seg_items;
+  int loop_threads, loop_blocks, smax_max;
+  bool loop_persistent;   // loop kernel: persistent work queue, or one block per item
+  size_t loop_smem, gather_smem, back_smem, prod_smem;
+};
+
+void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, hipStream_t s);
+void launch_chi_sum(const Launch& L, const ItemRange& r, double* dchi, hipStream_t s);
+void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s);
+void launch_back(const Launch& L, const Ranges& r, const double* X, double* out, int mode,
+                 bool cross, bool scale_T, bool mixed, hipStream_t s);
+void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const double* const* k,
+                 const double* coef, int nk, double h, double* out, bool skip_frozen, hipStream_t s);
+void launch_maxabs(const Launch& L, const ItemRange& r, const double* X, unsigned long long* words,
+                   hipStream_t s);
+void launch_errnorm(const Launch& L, const ItemRange& r, const double* y0, const double* y5,
+                    const double* const* k, const double* e, int nk, double h, double rtol,
+                    double atol, double* red, hipStream_t s);
+void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
+void launch_fill_i32(int* p, int n, int v, hipStream_t s);
+void launch_set_T(double* Tp, int npts, const double* Ttab, const int* step, int stage,
+                  hipStream_t s);
+void launch_set_T_values(double* Tp, const double* T_host, int n, hipStream_t s);
+void launch_step_end(unsigned long long* words, int npts, int* frozen, double* hist, int* step,
+                     int nsteps, double xmax, hipStream_t s);
+const void* loop_kernel_symbol(int smax_max, bool mixed);
 
 }  // namespace tufrg
 
 struct tufrg_ctx {
   std::vector<tufrg::HostTables> host;
-  std::vector<tufrg::DevTables> dev;
-  std::vector<int64_t> off;   // element offset of each point within a channel
-  int64_t S = 0;              // total elements per channel
+  std::vector<tufrg::DevTables> dev;       // host copy of the device array
+  std::vector<int64_t> off;                // element offset of each point within a channel
+  int64_t S = 0;                           // total elements per channel
   tufrg_options opt{};
   hipStream_t stream = nullptr;
-  hipStream_t side = nullptr;      // loops run here, concurrently with the projections
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  tufrg::Workspace ws{};
-  std::vector<void*> allocations;
+  hipStream_t side = nullptr;              // loops run here, concurrently with the projections
+  hipStream_t gs = nullptr;                // capture and replay stream of the graph-driven flow
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gs = nullptr;
+  tufrg::Launch L{};
+  tufrg::Ranges all;                       // item ranges of all points
+  std::vector<tufrg::Ranges> per_point;    // item ranges of each point
+  // device buffers owned by the context
+  double* Tp = nullptr;                    // per-point temperatures
+  int* frozen = nullptr;                   // per-point stop flags
+  int* queue = nullptr;                    // loop-kernel work queue: next item, finished blocks
+  double* stage = nullptr;                 // RK stage state [3][S]
+  double* kk[7] = {nullptr};               // RK slopes [3][S]
+  double* ytmp = nullptr;                  // [3][S]
+  double* red = nullptr;                   // reduction scratch
+  int nred = 0;
+  unsigned long long* umax = nullptr;      // per-point max words
+  unsigned long long* umax_host = nullptr; // pinned
+  double* Ttab = nullptr;                  // RK4 stage temperatures [nsteps][4]
+  double* hist = nullptr;                  // max|X| history [nsteps+1][npts]
+  int* step = nullptr;                     // device step counter
+  int ttab_cap = 0;
+  bool loop_persistent = false;            // launch form of the loop kernel
+  std::vector<void*> allocations;          // freed by tufrg_free
+  std::vector<void*> geometry_allocations; // item tables and slices; rebuilt by the autotuner
   std::string err;
   int device = 0;
 };
-
-namespace tufrg {
-// kernel launchers (kernels.hip); all asynchronous on `s`
-// Loop launch geometry of one point: nsplit blocks per transfer momentum, each
-// with lk * nchunk threads (rounded up to whole waves).
-struct LoopGeom {
-  int nsplit, nchunk, threads;
-  size_t smem;
-};
-LoopGeom loop_geometry(const DevTables& d);
-// loops at temperature T.  With one split per momentum they land in dchi (this
-// point's block in [2][S]); otherwise in the slices dpart[nsplit][2][Nq][nff^2],
-// which are added into dchi when sum_slices is set (else the consumer adds them)
-void launch_loops(const DevTables& d, double T, double* dchi, int64_t S, double* dpart,
-                  bool sum_slices, hipStream_t s);
-// projection front end (depends on X only): forward transform, bond basis,
-// gather into the inverse-transform coefficients g2
-void launch_project_front(const DevTables& d, const double* X, int64_t S, double* xt, double* yb,
-                          double* g2, uint32_t flags, hipStream_t s);
-// projection back end: mode 0 -> out = V; mode 1 -> out = scale * dX/dT with the
-// loops from dchi (one split) or the slices dpart
-void launch_project_back(const DevTables& d, const double* X, int64_t S, const double* g2,
-                         const double* dchi, const double* dpart, double* out, int mode,
-                         uint32_t flags, double scale, hipStream_t s);
-// mixed precision (TUFRG_MIXED): FP32 loops, BF16-split MFMA transforms, FP32 products
-void launch_loops_mixed(const DevTables& d, double T, double* dchi, int64_t S, double* dpart,
-                        bool sum_slices, hipStream_t s);
-void launch_project_front_mixed(const DevTables& d, const double* X, int64_t S, double* xt,
-                                double* yb, double* g2, uint32_t flags, hipStream_t s);
-void launch_inverse_mixed(const DevTables& d, const double* g2, float* K, uint32_t flags,
-                          hipStream_t s);
-void launch_products_mixed(const DevTables& d, const double* X, int64_t S, const float* K,
-                           const double* dchi, const double* dpart, double* out, int mode,
-                           uint32_t flags, double scale, hipStream_t s);
-size_t loop_smem_mixed(const DevTables& d, const LoopGeom& g);
-void launch_axpy_stage(const double* X, const double* const* k, const double* coef, int nk,
-                       double h, double* out, int64_t n, hipStream_t s);
-void launch_maxabs(const double* X, int64_t n, unsigned long long* word, hipStream_t s);
-void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
-void launch_errnorm(const double* y0, const double* y5, const double* const* k, const double* e,
-                    int nk, double h, double rtol, double atol, int64_t n, double* red,
-                    int nred, hipStream_t s);
-}  // namespace tufrg

@@ -1,0 +1,197 @@
+"""Batched launches: many uneven points per launch, device-side stopping,
+HIP-graph replay of the RK4 step, and the loop-geometry autotuner.
+
+Every point of a batch must give its own single-point result (up to the
+summation order of the px contraction, which follows the block size shared
+by the batch: 1e-12 normwise), the oracle's result (1e-10 normwise), and the
+graph-replayed flow must equal the eagerly launched one bit for bit.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import rhs as orhs
+from oracle.lattice import FormFactors
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def tf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1604_06296_amd as tf
+    tf.load_library()
+    return tf
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _normwise(got, ref, tol, what=""):
+    for c in range(ref.shape[0]):
+        scale = np.abs(ref[c]).max()
+        err = np.abs(got[c] - ref[c]).max()
+        assert err <= tol * max(scale, 1e-300), f"{what} channel {c}: err {err:.3e} scale {scale:.3e}"
+
+
+def _pack(ctx, Xs):
+    torch = _torch()
+    Xd = torch.zeros((3, ctx.S), dtype=torch.float64, device="cuda")
+    for i, X in enumerate(Xs):
+        ctx.view(Xd, i).copy_(torch.from_numpy(np.ascontiguousarray(X)))
+    return Xd
+
+
+# uneven points: every truncation, ragged grids, different fillings and U
+BATCH = [
+    synth.Point(t=1.0, tp=-0.30, U=3.0, Lq=10, Lk=24, shells=4, mu=-0.9),
+    synth.Point(t=1.0, tp=-0.10, U=2.2, Lq=6, Lk=12, shells=1, mu=-0.2),
+    synth.Point(t=1.0, tp=0.00, U=3.4, Lq=8, Lk=20, shells=0, mu=0.0),
+    synth.Point(t=1.0, tp=-0.25, U=2.8, Lq=12, Lk=36, shells=3, mu=-0.7),
+    synth.Point(t=1.0, tp=-0.20, U=2.5, Lq=8, Lk=14, shells=2, mu=-0.4),
+    synth.Point(t=1.0, tp=-0.15, U=3.8, Lq=6, Lk=32, shells=1, mu=-0.1),
+]
+
+
+def test_batch_rhs_matches_single_and_oracle(tf):
+    print("[batch] rhs of 6 uneven points", flush=True)
+    ctx = tf.Context(BATCH)
+    Ts = [0.4, 0.05, 2.0, 0.011, 0.13, 0.9]
+    Xs = [synth.random_channels(p.nq, FormFactors(p.shells).nff, seed=70 + i) for i, p in enumerate(BATCH)]
+    Xd = _pack(ctx, Xs)
+    d = ctx.rhs(Ts, Xd).cpu()
+    V = ctx.project(Xd).cpu()
+    b = ctx.bubbles(Ts).cpu()
+    for i, p in enumerate(BATCH):
+        ff = FormFactors(p.shells)
+        ref, refV, refb = orhs.rhs(p, Ts[i], Xs[i], ff, return_parts=True)
+        _normwise(ctx.view(d, i).numpy(), ref, TOL, f"pt{i} rhs")
+        _normwise(ctx.view(V, i).numpy(), refV, TOL, f"pt{i} V")
+        _normwise(ctx.view(b, i).numpy(), refb, TOL, f"pt{i} bubbles")
+        one = tf.Context([p])
+        Xo = _pack(one, [Xs[i]])
+        _normwise(ctx.view(d, i).numpy(), one.view(one.rhs(Ts[i], Xo)).cpu().numpy(), 1e-12,
+                  f"pt{i} batch vs single")
+        one.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_loop_queue_form_identical(tf, precision):
+    """Persistent work-queue launch and one block per item: the same bits."""
+    print(f"[batch] loop launch forms, {precision}", flush=True)
+    a = tf.Context(BATCH, precision=precision)
+    b = tf.Context(BATCH, precision=precision, loop_queue=True)
+    assert not a.geometry(0)[3] and b.geometry(0)[3]
+    Ts = [0.4, 0.05, 2.0, 0.011, 0.13, 0.9]
+    Xs = [synth.random_channels(p.nq, FormFactors(p.shells).nff, seed=80 + i) for i, p in enumerate(BATCH)]
+    torch = _torch()
+    for rep in range(3):        # the queue resets itself between launches
+        assert torch.equal(a.bubbles(Ts), b.bubbles(Ts))
+        assert torch.equal(a.rhs(Ts, _pack(a, Xs)), b.rhs(Ts, _pack(b, Xs)))
+
+
+def _flow_opts(tf, graph, nsteps=80):
+    return tf.FlowOptions(T0=10.0, Tmin=0.01, Xmax=20.0, scheme="rk4", nsteps=nsteps, use_graph=graph)
+
+
+def test_batch_flow_stops_each_point(tf):
+    """Batched RK4: each point stops at its own step, as in its own flow."""
+    print("[batch] rk4 flow of 6 points, eager", flush=True)
+    ctx = tf.Context(BATCH)
+    X = ctx.empty(3).zero_()
+    res = ctx.flow(X, _flow_opts(tf, False))
+    Xh = X.cpu()
+    steps = set()
+    for i, p in enumerate(BATCH):
+        one = tf.Context([p])
+        Xo = one.empty(3).zero_()
+        r1 = one.flow(Xo, _flow_opts(tf, False))[0]
+        r = res[i]
+        print(f"  pt{i}: {r.status} Tc={r.Tc} {r.channel} q={r.q_index} {r.irrep} steps={r.n_steps}",
+              flush=True)
+        assert r.status == r1.status and r.n_steps == r1.n_steps and r.n_rhs == 4 * r.n_steps
+        assert (r.channel, r.q_index, r.irrep) == (r1.channel, r1.q_index, r1.irrep)
+        if r.status == "diverged":
+            assert abs(r.Tc / r1.Tc - 1) < 1e-8
+        _normwise(ctx.view(Xh, i).numpy(), one.view(Xo).cpu().numpy(), 1e-8, f"pt{i} X at stop")
+        steps.add(r.n_steps)
+        one.close()
+    assert len(steps) > 1, "the batch should stop its points at different steps"
+
+
+def test_graph_replay_equals_eager(tf):
+    print("[batch] rk4 flow: graph replay vs eager", flush=True)
+    ctx = tf.Context(BATCH, loop_queue=True)
+    Xa = ctx.empty(3).zero_()
+    Xb = ctx.empty(3).zero_()
+    ra = ctx.flow(Xa, _flow_opts(tf, False))
+    rb = ctx.flow(Xb, _flow_opts(tf, True))
+    assert ra == rb
+    assert _torch().equal(Xa, Xb)
+    # a second replay set on the same context (state reset) is identical too
+    Xc = ctx.empty(3).zero_()
+    assert ctx.flow(Xc, _flow_opts(tf, True)) == ra and _torch().equal(Xa, Xc)
+
+
+def test_graph_reached_tmin(tf):
+    """No point diverges: every step runs and the graph path reports REACHED_TMIN."""
+    pts = [synth.Point(t=1.0, tp=-0.1, U=0.5, Lq=6, Lk=12, shells=1, mu=-0.3),
+           synth.Point(t=1.0, tp=-0.2, U=0.4, Lq=8, Lk=16, shells=0, mu=-0.5)]
+    ctx = tf.Context(pts)
+    X = ctx.empty(3).zero_()
+    res = ctx.flow(X, tf.FlowOptions(T0=10.0, Tmin=0.5, Xmax=20.0, scheme="rk4", nsteps=12,
+                                     use_graph=True))
+    assert all(r.status == "reached_tmin" and r.n_steps == 12 and r.n_rhs == 48 for r in res)
+
+
+def test_autotune_geometry_and_cache(tf, tmp_path):
+    cache = tmp_path / "tune.txt"
+    os.environ["TUFRG_TUNE_CACHE"] = str(cache)
+    try:
+        pts = BATCH[:4]
+        print("[autotune] 4 points", flush=True)
+        tuned = tf.Context(pts, autotune=True)
+        plain = tf.Context(pts)
+        lines = cache.read_text().split()
+        assert len(lines) == 3 * len({(p.nq, p.Lk, FormFactors(p.shells).nff) for p in pts})
+        for i, p in enumerate(pts):
+            ns, nc, th, _ = tuned.geometry(i)
+            assert ns >= 1 and nc >= 1 and p.Lk * nc <= th <= 512
+        Ts = [0.3, 0.02, 1.0, 0.07]
+        Xs = [synth.random_channels(p.nq, FormFactors(p.shells).nff, seed=90 + i) for i, p in enumerate(pts)]
+        a = tuned.rhs(Ts, _pack(tuned, Xs)).cpu()
+        b = plain.rhs(Ts, _pack(plain, Xs)).cpu()
+        for i in range(len(pts)):
+            _normwise(tuned.view(a, i).numpy(), plain.view(b, i).numpy(), 1e-12, f"pt{i} tuned")
+        # the cache is read back: same choices, nothing appended
+        again = tf.Context(pts, autotune=True)
+        assert [again.geometry(i) for i in range(4)] == [tuned.geometry(i) for i in range(4)]
+        assert cache.read_text().split() == lines
+    finally:
+        del os.environ["TUFRG_TUNE_CACHE"]
+
+
+def test_cfg4_full_batch_sampled(tf):
+    """The 64-point sweep in one context: sampled points and momenta against the oracle."""
+    w = synth.cfg4()
+    for p in w.points:
+        p.mu = tf.mu_from_filling(p.t, p.tp, p.filling, p.mu_T, p.mu_L)
+    print("[cfg4] 64 points, S =", end=" ", flush=True)
+    ctx = tf.Context(w.points)
+    print(ctx.S, flush=True)
+    rng = np.random.default_rng(4404)
+    Ts = list(np.exp(rng.uniform(np.log(0.01), np.log(10.0), len(w.points))))
+    Xs = [synth.random_channels(p.nq, FormFactors(p.shells).nff, seed=400 + i) for i, p in enumerate(w.points)]
+    d = ctx.rhs(Ts, _pack(ctx, Xs)).cpu()
+    for i in (0, 17, 63) + tuple(int(k) for k in rng.choice(64, 2, replace=False)):
+        p = w.points[i]
+        ff = FormFactors(p.shells)
+        qi = list(synth.sample_indices(p.nq, 3, seed=i)) + [p.nq - 1]
+        ref = orhs.rhs(p, Ts[i], Xs[i], ff, q_index=qi)
+        _normwise(ctx.view(d, i).numpy()[:, qi], ref, TOL, f"cfg4 pt{i} (Nff={ff.nff}, Lq={p.Lq})")
