@@ -146,6 +146,7 @@ typedef struct {
 } tufrg_flow_result;
 
 typedef struct tufrg_ctx tufrg_ctx;
+typedef struct tufrg_mlp tufrg_mlp;
 
 /* Build the scale-independent tables of every point (bonds, form-factor
  * coefficients, harmonic and projection index tables - the reusable part
@@ -205,12 +206,109 @@ tufrg_status tufrg_flop_count(const tufrg_ctx* ctx, double out[3]);
 tufrg_status tufrg_mu_from_filling(double t, double tp, double n, double T, int32_t L,
                                    double* mu);
 
+/* ---------------------------------------------------------------------
+ * Loop harmonics and the learned loop surrogate.
+ *
+ * With f_m(p) = sum_b c_mb exp(-i p.R_b), the loops of eqn. chis are
+ *   chi'_mn(q) = sum_{a,b} c_ma c_nb ghat(q, R_a + R_b),
+ *   ghat_X(q, S) = (1/N_k) sum_p dL^X/dT(eps(p+q/2), eps(p-q/2)) cos(p.S),
+ * real and even in S, so one value per (q, S) with S in the half set of
+ * bonds + bonds (S_x > 0, or S_x = 0 and S_y >= 0; N_S' = 1, 7, 13, 21, 35
+ * for shells 0..4) carries the loops of every form-factor pair.
+ *
+ * The surrogate (not part of the paper) predicts ghat from 9 features
+ *   (qx/pi, qy/pi, log10 T, mu/t, t'/t, R_a/2, R_b/2),
+ * (R_a, R_b) the canonical bond pair of S (the first pair in the bond
+ * order of the form-factor table with R_a + R_b = S), as 4 targets
+ *   (T (1 + 4T) ghat_pp, (1 + 4T^2) ghat_ph, 0, 0)
+ * (the last two: the imaginary parts, identically zero).
+ * ------------------------------------------------------------------- */
+
+/* Half-set harmonics of point `point`: *n receives N_S'; table (if not
+ * NULL, host [N_S'][6]) receives (S_x, S_y, R_a,x, R_a,y, R_b,x, R_b,y) per
+ * harmonic, the canonical pair included; *offset (if not NULL) the offset
+ * of the point in [sum_p Nq_p * 2 * N_S'_p] harmonic arrays. */
+tufrg_status tufrg_harmonics(const tufrg_ctx* ctx, int32_t point, int32_t* n, int32_t* table,
+                             int64_t* offset);
+
+/* ghat (device, [sum_p Nq_p][2][N_S'_p] per point block, channels pp, ph)
+ * at temperatures T_host[p], from the exact FP64 loop kernel.  FP64
+ * contexts only (EUNSUPPORTED otherwise). */
+tufrg_status tufrg_loop_harmonics(tufrg_ctx* ctx, const double* T_host, double* ghat);
+
+/* n training samples of the surrogate drawn uniformly over (point, q, S)
+ * with a counter-based hash of (seed, sample index), labels from the exact
+ * FP64 loop kernel at T_host[p]: x (device float [n][9]) features, y
+ * (device float [n][4]) targets, idx (device int32 [n][3] or NULL) the
+ * (point, q, harmonic) of each sample.  FP64 contexts only. */
+tufrg_status tufrg_surrogate_dataset(tufrg_ctx* ctx, const double* T_host, int64_t n, uint64_t seed,
+                                     float* x, float* y, int32_t* idx);
+
+/* Route the loops of tufrg_bubbles, tufrg_rhs and tufrg_flow through two
+ * surrogate networks (9 inputs, 4 outputs) with an exact fallback, or
+ * detach (a = b = NULL).  Per call, momentum q takes the exact loop kernel
+ * when the networks' predicted harmonics differ by more than
+ * tol * max_S |prediction at q|, when q = phase (mod check_stride) with the
+ * phase advancing by one per call, or while q is flagged; a checked q whose
+ * prediction misses the exact harmonics by more than tol * max_S |exact| is
+ * flagged together with its 8 neighbours, and a later passing check clears
+ * the flag.  Single-point FP64 contexts only (EUNSUPPORTED otherwise).  The
+ * networks must outlive the attachment and are used on the context's
+ * streams.  Allocates the surrogate's buffers. */
+tufrg_status tufrg_surrogate_attach(tufrg_ctx* ctx, tufrg_mlp* a, tufrg_mlp* b, double tol,
+                                    int32_t check_stride);
+
+/* Cumulative surrogate counters since the attachment: out[0] momenta
+ * evaluated exactly, out[1] momenta queried, out[2] failed checks.
+ * Synchronises the stream. */
+tufrg_status tufrg_surrogate_stats(tufrg_ctx* ctx, int64_t out[3]);
+
 /* Release everything tufrg_init allocated.  NULL is ignored. */
 void tufrg_free(tufrg_ctx* ctx);
 
 /* Message of the last failing call on ctx (or of the last failing
  * tufrg_init / host-only call when ctx is NULL).  Never NULL. */
 const char* tufrg_last_error(const tufrg_ctx* ctx);
+
+/* ---------------------------------------------------------------------
+ * Multilayer perceptron (the surrogate's network; not part of the paper).
+ *
+ * Layers l = 1..L: z_l = a_{l-1} W_l^T + b_l, a_l = silu(z_l) = z_l
+ * sigmoid(z_l) on hidden layers, a linear output.  Loss: mean over all
+ * rows and outputs of (a_L - y)^2.  Matrix products run on the matrix cores
+ * with FP32 accumulation: forward products with BF16 hi/lo split operands
+ * (about 16 mantissa bits), gradient products with plain BF16 operands;
+ * parameters and Adam moments are FP32.  Flat parameter layout: per layer
+ * W_l [out][in] row-major, then b_l [out].  All arrays are device memory,
+ * row-major [rows][width].  Calls are asynchronous on the network's stream
+ * unless stated otherwise.
+ * ------------------------------------------------------------------- */
+
+/* widths [nwidths] (input, hidden..., output), each 1..4096; max_rows: the
+ * largest batch of tufrg_mlp_gradient / tufrg_mlp_train and the chunk size
+ * of tufrg_mlp_forward.  Weights Glorot-uniform from a SplitMix64 counter
+ * hash of (seed, parameter index), biases zero.  Synchronises. */
+tufrg_status tufrg_mlp_create(const int32_t* widths, int32_t nwidths, int32_t max_rows, uint64_t seed,
+                              void* stream, tufrg_mlp** out);
+tufrg_status tufrg_mlp_nparams(const tufrg_mlp* net, int64_t* count);
+/* copy the FP32 parameters to / from a device array [nparams] */
+tufrg_status tufrg_mlp_get_params(tufrg_mlp* net, float* dst);
+tufrg_status tufrg_mlp_set_params(tufrg_mlp* net, const float* src);
+/* y [rows][out] = network(x [rows][in]) */
+tufrg_status tufrg_mlp_forward(tufrg_mlp* net, const float* x, float* y, int64_t rows);
+/* loss and gradient (device [nparams], may be NULL) of rows <= max_rows
+ * samples; *loss (host, may be NULL) synchronises. */
+tufrg_status tufrg_mlp_gradient(tufrg_mlp* net, const float* x, const float* y, int64_t rows,
+                                float* grad, double* loss);
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8; learning rate lr
+ * with cosine decay to lr/100 over the call) on minibatches of `batch`
+ * rows drawn with replacement from (x, y) [rows] by a counter hash of
+ * (seed, step, row); loss_hist (host [steps] or NULL) receives each step's
+ * minibatch loss.  Synchronises. */
+tufrg_status tufrg_mlp_train(tufrg_mlp* net, const float* x, const float* y, int64_t rows, int32_t steps,
+                             int32_t batch, float lr, uint64_t seed, double* loss_hist);
+void tufrg_mlp_free(tufrg_mlp* net);
+const char* tufrg_mlp_last_error(const tufrg_mlp* net);
 
 #ifdef __cplusplus
 }

@@ -6,8 +6,8 @@ include/tufrg.h; this module only marshals arguments.  PyTorch provides
 device memory and the stream.  Importing works without a GPU; creating a
 Context needs the built library and a GPU, and fails loudly otherwise.
 """
-from .binding import (Context, FlowOptions, FlowResult, TufrgError, library_path,  # noqa: F401
+from .binding import (MLP, Context, FlowOptions, FlowResult, TufrgError, library_path,  # noqa: F401
                       load_library, mu_from_filling, CHANNELS, IRREPS)
 
-__all__ = ["Context", "FlowOptions", "FlowResult", "TufrgError", "load_library",
+__all__ = ["Context", "MLP", "FlowOptions", "FlowResult", "TufrgError", "load_library",
            "library_path", "mu_from_filling", "CHANNELS", "IRREPS"]

@@ -21,7 +21,12 @@ LOOP_QUEUE = 4
 # every entry point declared in include/tufrg.h
 EXPORTS = ("tufrg_init", "tufrg_layout", "tufrg_geometry", "tufrg_bubbles", "tufrg_project",
            "tufrg_rhs", "tufrg_flow", "tufrg_sync", "tufrg_flop_count", "tufrg_mu_from_filling",
-           "tufrg_free", "tufrg_last_error")
+           "tufrg_harmonics", "tufrg_loop_harmonics", "tufrg_surrogate_dataset",
+           "tufrg_surrogate_attach", "tufrg_surrogate_stats",
+           "tufrg_mlp_create", "tufrg_mlp_nparams", "tufrg_mlp_get_params", "tufrg_mlp_set_params",
+           "tufrg_mlp_forward", "tufrg_mlp_gradient", "tufrg_mlp_train", "tufrg_mlp_free",
+           "tufrg_mlp_last_error", "tufrg_free", "tufrg_last_error")
+NO_STATUS = ("tufrg_free", "tufrg_last_error", "tufrg_mlp_free", "tufrg_mlp_last_error")
 
 
 class TufrgError(RuntimeError):
@@ -80,12 +85,29 @@ def load_library():
     lib.tufrg_sync.argtypes = [vp]
     lib.tufrg_flop_count.argtypes = [vp, dp]
     lib.tufrg_mu_from_filling.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, i32, dp]
+    u64, f32 = C.c_uint64, C.c_float
+    lib.tufrg_harmonics.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)]
+    lib.tufrg_loop_harmonics.argtypes = [vp, dp, vp]
+    lib.tufrg_surrogate_dataset.argtypes = [vp, dp, i64, u64, vp, vp, vp]
+    lib.tufrg_surrogate_attach.argtypes = [vp, vp, vp, C.c_double, i32]
+    lib.tufrg_surrogate_stats.argtypes = [vp, C.POINTER(i64)]
+    lib.tufrg_mlp_create.argtypes = [C.POINTER(i32), i32, i32, u64, vp, C.POINTER(vp)]
+    lib.tufrg_mlp_nparams.argtypes = [vp, C.POINTER(i64)]
+    lib.tufrg_mlp_get_params.argtypes = [vp, vp]
+    lib.tufrg_mlp_set_params.argtypes = [vp, vp]
+    lib.tufrg_mlp_forward.argtypes = [vp, vp, vp, i64]
+    lib.tufrg_mlp_gradient.argtypes = [vp, vp, vp, i64, vp, dp]
+    lib.tufrg_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, f32, u64, dp]
+    lib.tufrg_mlp_free.argtypes = [vp]
+    lib.tufrg_mlp_free.restype = None
+    lib.tufrg_mlp_last_error.argtypes = [vp]
+    lib.tufrg_mlp_last_error.restype = C.c_char_p
     lib.tufrg_free.argtypes = [vp]
     lib.tufrg_free.restype = None
     lib.tufrg_last_error.argtypes = [vp]
     lib.tufrg_last_error.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("tufrg_free", "tufrg_last_error"):
+        if name not in NO_STATUS:
             getattr(lib, name).restype = C.c_int
     _LIB = lib
     return lib
@@ -95,6 +117,100 @@ def _check(lib, ctx, status):
     if status != 0:
         msg = lib.tufrg_last_error(ctx).decode()
         raise TufrgError(f"{STATUS.get(status, status)}: {msg}")
+
+
+def _check_mlp(lib, net, status):
+    if status != 0:
+        msg = lib.tufrg_mlp_last_error(net).decode()
+        raise TufrgError(f"{STATUS.get(status, status)}: {msg}")
+
+
+def _dev_array(x, dtype, numel=None, what="array"):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dtype and x.is_contiguous()):
+        raise TufrgError(f"{what}: expected a contiguous {dtype} CUDA tensor")
+    if numel is not None and x.numel() != numel:
+        raise TufrgError(f"{what}: expected {numel} elements, got {x.numel()}")
+    return C.c_void_p(x.data_ptr())
+
+
+class MLP:
+    """Surrogate network (tufrg_mlp_*): SiLU MLP trained with the library's kernels."""
+
+    def __init__(self, widths: Sequence[int], max_rows: int = 65536, seed: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise TufrgError("a GPU is required (torch.cuda.is_available() is False)")
+        self._torch = torch
+        self.lib = load_library()
+        self.widths = [int(w) for w in widths]
+        self.max_rows = int(max_rows)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        arr = (C.c_int32 * len(self.widths))(*self.widths)
+        handle = C.c_void_p()
+        _check_mlp(self.lib, None, self.lib.tufrg_mlp_create(arr, len(self.widths), self.max_rows,
+                                                             C.c_uint64(seed),
+                                                             C.c_void_p(self.stream.cuda_stream),
+                                                             C.byref(handle)))
+        self.net = handle
+        n = C.c_int64()
+        _check_mlp(self.lib, self.net, self.lib.tufrg_mlp_nparams(self.net, C.byref(n)))
+        self.nparams = n.value
+
+    def params(self):
+        t = self._torch
+        out = t.empty(self.nparams, dtype=t.float32, device="cuda")
+        _check_mlp(self.lib, self.net, self.lib.tufrg_mlp_get_params(self.net, C.c_void_p(out.data_ptr())))
+        return out
+
+    def set_params(self, p):
+        _check_mlp(self.lib, self.net, self.lib.tufrg_mlp_set_params(
+            self.net, _dev_array(p, self._torch.float32, self.nparams, "params")))
+
+    def forward(self, x):
+        t = self._torch
+        rows = x.shape[0]
+        _dev_array(x, t.float32, rows * self.widths[0], "x")
+        y = t.empty((rows, self.widths[-1]), dtype=t.float32, device="cuda")
+        _check_mlp(self.lib, self.net, self.lib.tufrg_mlp_forward(self.net, C.c_void_p(x.data_ptr()),
+                                                                 C.c_void_p(y.data_ptr()), rows))
+        return y
+
+    def gradient(self, x, y):
+        t = self._torch
+        rows = x.shape[0]
+        _dev_array(x, t.float32, rows * self.widths[0], "x")
+        _dev_array(y, t.float32, rows * self.widths[-1], "y")
+        g = t.empty(self.nparams, dtype=t.float32, device="cuda")
+        loss = C.c_double()
+        _check_mlp(self.lib, self.net, self.lib.tufrg_mlp_gradient(
+            self.net, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), rows,
+            C.c_void_p(g.data_ptr()), C.byref(loss)))
+        return g, loss.value
+
+    def train(self, x, y, steps: int, batch: int, lr: float, seed: int = 0):
+        """Adam steps on minibatches of (x, y); returns the per-step losses."""
+        import numpy as np
+        t = self._torch
+        rows = x.shape[0]
+        _dev_array(x, t.float32, rows * self.widths[0], "x")
+        _dev_array(y, t.float32, rows * self.widths[-1], "y")
+        hist = (C.c_double * max(steps, 1))()
+        _check_mlp(self.lib, self.net, self.lib.tufrg_mlp_train(
+            self.net, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), rows, steps, batch,
+            C.c_float(lr), C.c_uint64(seed), hist))
+        return np.array(hist[:steps])
+
+    def close(self):
+        if getattr(self, "net", None):
+            self.lib.tufrg_mlp_free(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mu_from_filling(t: float, tp: float, n: float, T: float, L: int = 1024) -> float:
@@ -237,6 +353,53 @@ class Context:
                                   CHANNELS[r.channel] if div else None, r.q_index if div else None,
                                   IRREPS[r.irrep] if div else None, r.max_abs_X, r.n_rhs, r.n_steps))
         return out
+
+    # ------------------------------------------------------------- surrogate
+    def harmonics(self, point: int = 0):
+        """(N_S', table [N_S'][6] = (Sx, Sy, Ra_x, Ra_y, Rb_x, Rb_y), offset in harmonic arrays)."""
+        import numpy as np
+        n, off = C.c_int32(), C.c_int64()
+        _check(self.lib, self.ctx, self.lib.tufrg_harmonics(self.ctx, point, C.byref(n), None, C.byref(off)))
+        tab = (C.c_int32 * (6 * n.value))()
+        _check(self.lib, self.ctx, self.lib.tufrg_harmonics(self.ctx, point, C.byref(n), tab, None))
+        return n.value, np.array(tab[:], dtype=np.int32).reshape(n.value, 6), off.value
+
+    def harmonics_length(self) -> int:
+        total = 0
+        for i in range(self.npts):
+            n, _, _ = self.harmonics(i)
+            total += self.layouts[i][1] * 2 * n
+        return total
+
+    def loop_harmonics(self, T):
+        t = self._torch
+        out = t.empty(self.harmonics_length(), dtype=t.float64, device="cuda")
+        _check(self.lib, self.ctx, self.lib.tufrg_loop_harmonics(self.ctx, self._T(T),
+                                                                 C.c_void_p(out.data_ptr())))
+        return out
+
+    def surrogate_dataset(self, T, n: int, seed: int = 0, x=None, y=None, with_index: bool = False):
+        t = self._torch
+        x = t.empty((n, 9), dtype=t.float32, device="cuda") if x is None else x
+        y = t.empty((n, 4), dtype=t.float32, device="cuda") if y is None else y
+        idx = t.empty((n, 3), dtype=t.int32, device="cuda") if with_index else None
+        _check(self.lib, self.ctx, self.lib.tufrg_surrogate_dataset(
+            self.ctx, self._T(T), n, C.c_uint64(seed), _dev_array(x, t.float32, 9 * n, "x"),
+            _dev_array(y, t.float32, 4 * n, "y"), C.c_void_p(idx.data_ptr()) if with_index else None))
+        return (x, y, idx) if with_index else (x, y)
+
+    def attach_surrogate(self, a: "MLP", b: "MLP", tol: float = 1e-3, check_stride: int = 8):
+        self._surrogates = (a, b)      # keep the networks alive while attached
+        _check(self.lib, self.ctx, self.lib.tufrg_surrogate_attach(self.ctx, a.net, b.net, tol, check_stride))
+
+    def detach_surrogate(self):
+        _check(self.lib, self.ctx, self.lib.tufrg_surrogate_attach(self.ctx, None, None, 0.0, 0))
+        self._surrogates = None
+
+    def surrogate_stats(self):
+        out = (C.c_int64 * 3)()
+        _check(self.lib, self.ctx, self.lib.tufrg_surrogate_stats(self.ctx, out))
+        return {"exact_q": out[0], "queried_q": out[1], "failed_checks": out[2]}
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -214,7 +214,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   for (int p = 0; p < npts; ++p) add_point_items(ctx->dev[p], p, h, ctx->per_point[p]);
   int smax_max = 0, threads = 64;
   size_t lsm = 0, gsm = 0, bsm = 0, psm = 0;
-  int64_t dpart = 0;
+  int64_t dpart = 0, gh = 0, ghs = 0;
   for (int p = 0; p < npts; ++p) {
     DevTables& d = ctx->dev[p];
     smax_max = std::max(smax_max, d.smax);
@@ -226,7 +226,13 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
     psm = std::max(psm, sizeof(float) * 12 * (size_t)nff2);
     d.ws_dpart = dpart;
     if (d.nsplit > 1) dpart += (int64_t)d.nsplit * 2 * d.nq * nff2;
+    d.ws_gh = gh;
+    gh += (int64_t)d.nsplit * d.nq * 2 * d.nsh;
+    d.gh_off = ghs;
+    ghs += (int64_t)d.nq * 2 * d.nsh;
   }
+  ctx->ghat_len = gh;
+  ctx->ghat_sum_len = ghs;
   for (int p = 0; p < npts; ++p) lsm = std::max(lsm, loop_smem_of(ctx->dev[p], threads));
   int dev_smem = 0;
   hipDeviceGetAttribute(&dev_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
@@ -286,16 +292,57 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
 // T dX/dT (= dX/ds) when scale_T.  The loops depend on T only and run on the
 // side stream, concurrently with the X-dependent front end of the
 // projections; the back end (V and the products) joins both.
+// Loops through the attached surrogate (single-point context): predicted
+// harmonics, exact loop kernel on the momenta that need it, the check and
+// fallback bookkeeping, and chi' into dchi.
+void surrogate_loops(tufrg_ctx* ctx, const Launch& L, double* dchi, hipStream_t s) {
+  const DevTables& d = ctx->dev[0];
+  const int64_t rows = (int64_t)d.nq * d.nsh;
+  launch_surrogate_front(L, 0, d, ctx->sur_x, s);
+  mlp_forward_on(ctx->sur_a, ctx->sur_x, ctx->sur_ya, rows, s);
+  mlp_forward_on(ctx->sur_b, ctx->sur_x, ctx->sur_yb, rows, s);
+  launch_surrogate_decide(L, 0, d, ctx->sur_ya, ctx->sur_yb, ctx->sur, s);
+  Launch Lg = L;
+  Lg.b.ghat = ctx->ghat;
+  Lg.b.item_count = ctx->sur.count;
+  Lg.loop_items = ctx->sur.items;
+  ItemRange r;
+  r.n = d.nq * d.nsplit;
+  launch_loops(Lg, r, ctx->queue, false, s);
+  launch_surrogate_finish(Lg, 0, d, ctx->sur, dchi, s);
+}
+
 void rhs_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, const double* X, double* out,
                 bool scale_T, hipStream_t ms) {
   const bool mixed = mixed_of(ctx), cross = cross_of(ctx);
   hipEventRecord(ctx->ev_fork, ms);
   hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
-  launch_loops(L, r.loop, ctx->queue, mixed, ctx->side);
+  Launch Lb = L;
+  if (ctx->sur_a) {
+    surrogate_loops(ctx, L, L.b.dchi, ctx->side);
+    Lb.b.chi_final = 1;
+  } else {
+    launch_loops(L, r.loop, ctx->queue, mixed, ctx->side);
+  }
   hipEventRecord(ctx->ev_join, ctx->side);
   if (cross) launch_front(L, r, X, mixed, ms);
   hipStreamWaitEvent(ms, ctx->ev_join, 0);
-  launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms);
+  launch_back(Lb, r, X, out, 1, cross, scale_T, mixed, ms);
+}
+
+tufrg_status ensure_ghat(tufrg_ctx* ctx) {
+  if (ctx->ghat) return TUFRG_OK;
+  return dalloc(ctx, (size_t)std::max<int64_t>(ctx->ghat_len, 1), &ctx->ghat, ctx->allocations);
+}
+
+tufrg_status ensure_flow_buffers(tufrg_ctx* ctx) {
+  if (ctx->flow_ready) return TUFRG_OK;
+  const size_t s3 = 3 * (size_t)ctx->S;
+  ST_TRY(dalloc(ctx, s3, &ctx->stage, ctx->allocations));
+  ST_TRY(dalloc(ctx, s3, &ctx->ytmp, ctx->allocations));
+  for (int i = 0; i < 7; ++i) ST_TRY(dalloc(ctx, s3, &ctx->kk[i], ctx->allocations));
+  ctx->flow_ready = true;
+  return TUFRG_OK;
 }
 
 tufrg_status check_temperatures(tufrg_ctx* ctx, const double* T_host) {
@@ -498,12 +545,11 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
         (st = upload(ctx, t.cshift, &d.cshift, A)) || (st = upload(ctx, ehi, &d.eph_hi, A)) ||
         (st = upload(ctx, elo, &d.eph_lo, A)) || (st = upload(ctx, t.mrow, &d.mrow, A)) ||
         (st = upload(ctx, t.ment, &d.ment, A)) || (st = upload(ctx, hx, &d.hx, A)) ||
-        (st = upload(ctx, hy, &d.hy, A)))
+        (st = upload(ctx, hy, &d.hy, A)) || (st = upload(ctx, t.pairs, &d.pairs, A)))
       return bad(st);
   }
   // workspace, state buffers and control words
   Batch& B = ctx->L.b;
-  const size_t s3 = 3 * (size_t)S;
   tufrg_status st = TUFRG_OK;
   if (!st) st = dalloc(ctx, 2 * (size_t)S, &B.dchi, A);
   if (!st) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_xt, 1), &B.xt, A);
@@ -514,9 +560,6 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   if (!st) st = dalloc(ctx, (size_t)npts, &ctx->Tp, A);
   if (!st) st = dalloc(ctx, (size_t)npts, &ctx->frozen, A);
   if (!st) st = dalloc(ctx, 2, &ctx->queue, A);
-  if (!st) st = dalloc(ctx, s3, &ctx->stage, A);
-  if (!st) st = dalloc(ctx, s3, &ctx->ytmp, A);
-  for (int i = 0; i < 7 && !st; ++i) st = dalloc(ctx, s3, &ctx->kk[i], A);
   if (!st) st = dalloc(ctx, (size_t)npts, &ctx->umax, A);
   if (!st) st = dalloc(ctx, 1, &ctx->step, A);
   if (st) return bad(st);
@@ -572,8 +615,12 @@ tufrg_status tufrg_bubbles(tufrg_ctx* ctx, const double* T_host, double* dchi) {
   launch_set_T_values(ctx->Tp, T_host, (int)ctx->dev.size(), ctx->stream);
   Launch L = ctx->L;
   L.b.dchi = dchi;
-  launch_loops(L, ctx->all.loop, ctx->queue, mixed_of(ctx), ctx->stream);
-  launch_chi_sum(L, ctx->all.chi, dchi, ctx->stream);
+  if (ctx->sur_a) {
+    surrogate_loops(ctx, L, dchi, ctx->stream);
+  } else {
+    launch_loops(L, ctx->all.loop, ctx->queue, mixed_of(ctx), ctx->stream);
+    launch_chi_sum(L, ctx->all.chi, dchi, ctx->stream);
+  }
   HIP_TRY(ctx, hipGetLastError());
   return TUFRG_OK;
 }
@@ -597,6 +644,110 @@ tufrg_status tufrg_rhs(tufrg_ctx* ctx, const double* T_host, const double* X, do
   launch_set_T_values(ctx->Tp, T_host, (int)ctx->dev.size(), ctx->stream);
   rhs_launch(ctx, ctx->L, ctx->all, X, dXdT, false, ctx->stream);
   HIP_TRY(ctx, hipGetLastError());
+  return TUFRG_OK;
+}
+
+tufrg_status tufrg_harmonics(const tufrg_ctx* ctx, int32_t point, int32_t* n, int32_t* table,
+                             int64_t* offset) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  if (point < 0 || point >= (int)ctx->dev.size())
+    return fail(const_cast<tufrg_ctx*>(ctx), TUFRG_EINVAL, "point out of range");
+  const HostTables& t = ctx->host[point];
+  if (n) *n = t.nsh;
+  if (offset) *offset = ctx->dev[point].gh_off;
+  if (table)
+    for (int j = 0; j < t.nsh; ++j) {
+      table[6 * j + 0] = t.hx[j];
+      table[6 * j + 1] = t.hy[j];
+      for (int k = 0; k < 4; ++k) table[6 * j + 2 + k] = t.pairs[4 * j + k];
+    }
+  return TUFRG_OK;
+}
+
+tufrg_status tufrg_loop_harmonics(tufrg_ctx* ctx, const double* T_host, double* ghat) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  if (!T_host || !ghat) return fail(ctx, TUFRG_EINVAL, "NULL argument");
+  if (mixed_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "loop harmonics are computed in FP64 contexts");
+  ST_TRY(check_temperatures(ctx, T_host));
+  ST_TRY(ensure_ghat(ctx));
+  launch_set_T_values(ctx->Tp, T_host, (int)ctx->dev.size(), ctx->stream);
+  Launch L = ctx->L;
+  L.b.ghat = ctx->ghat;
+  launch_loops(L, ctx->all.loop, ctx->queue, false, ctx->stream);
+  for (size_t p = 0; p < ctx->dev.size(); ++p) launch_ghat_sum(L, (int)p, ctx->dev[p], ghat, ctx->stream);
+  HIP_TRY(ctx, hipGetLastError());
+  return TUFRG_OK;
+}
+
+tufrg_status tufrg_surrogate_dataset(tufrg_ctx* ctx, const double* T_host, int64_t n, uint64_t seed,
+                                     float* x, float* y, int32_t* idx) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  if (!T_host || !x || !y) return fail(ctx, TUFRG_EINVAL, "NULL argument");
+  if (n < 0) return fail(ctx, TUFRG_EINVAL, "n must be >= 0");
+  if (mixed_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "training labels come from FP64 contexts");
+  ST_TRY(check_temperatures(ctx, T_host));
+  ST_TRY(ensure_ghat(ctx));
+  launch_set_T_values(ctx->Tp, T_host, (int)ctx->dev.size(), ctx->stream);
+  Launch L = ctx->L;
+  L.b.ghat = ctx->ghat;
+  launch_loops(L, ctx->all.loop, ctx->queue, false, ctx->stream);
+  launch_sur_dataset(L, (int)ctx->dev.size(), n, seed, x, y, idx, ctx->stream);
+  HIP_TRY(ctx, hipGetLastError());
+  return TUFRG_OK;
+}
+
+tufrg_status tufrg_surrogate_attach(tufrg_ctx* ctx, tufrg_mlp* a, tufrg_mlp* b, double tol,
+                                    int32_t check_stride) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->side));
+  for (void* p : ctx->sur_allocations) hipFree(p);
+  ctx->sur_allocations.clear();
+  ctx->sur_a = ctx->sur_b = nullptr;
+  if (!a && !b) return TUFRG_OK;
+  if (!a || !b) return fail(ctx, TUFRG_EINVAL, "attach two networks (or none to detach)");
+  if (ctx->dev.size() != 1) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves single-point contexts");
+  if (mixed_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves FP64 contexts");
+  for (tufrg_mlp* m : {a, b})
+    if (mlp_width(m, 0) != 9 || mlp_width(m, -1) != 4)
+      return fail(ctx, TUFRG_EINVAL, "surrogate networks map 9 features to 4 targets");
+  if (!(tol > 0.0) || check_stride < 1) return fail(ctx, TUFRG_EINVAL, "need tol > 0 and check_stride >= 1");
+  ST_TRY(ensure_ghat(ctx));
+  const DevTables& d = ctx->dev[0];
+  const size_t rows = (size_t)d.nq * d.nsh, nh = (size_t)d.nq * 2 * d.nsh;
+  std::vector<void*>& g = ctx->sur_allocations;
+  SurState& st = ctx->sur;
+  st = SurState();
+  st.tol = tol;
+  st.stride = check_stride;
+  ST_TRY(dalloc(ctx, rows * 9, &ctx->sur_x, g));
+  ST_TRY(dalloc(ctx, rows * 4, &ctx->sur_ya, g));
+  ST_TRY(dalloc(ctx, rows * 4, &ctx->sur_yb, g));
+  ST_TRY(dalloc(ctx, 1, &st.phase, g));
+  ST_TRY(dalloc(ctx, (size_t)d.nq, &st.state, g));
+  ST_TRY(dalloc(ctx, (size_t)d.nq, &st.need, g));
+  ST_TRY(dalloc(ctx, (size_t)d.nq, &st.fail, g));
+  ST_TRY(dalloc(ctx, nh, &st.pred, g));
+  ST_TRY(dalloc(ctx, nh, &st.fin, g));
+  ST_TRY(dalloc(ctx, (size_t)d.nq * d.nsplit, &st.items, g));
+  ST_TRY(dalloc(ctx, 1, &st.count, g));
+  ST_TRY(dalloc(ctx, 3, &st.stats, g));
+  launch_fill_i32(st.phase, 1, 0, ctx->stream);
+  launch_fill_i32(st.state, d.nq, 0, ctx->stream);
+  launch_fill_u64(st.stats, 3, 0ull, ctx->stream);
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->sur_a = a;
+  ctx->sur_b = b;
+  return TUFRG_OK;
+}
+
+tufrg_status tufrg_surrogate_stats(tufrg_ctx* ctx, int64_t out[3]) {
+  if (!ctx || !out) return fail(ctx, TUFRG_EINVAL, "NULL argument");
+  if (!ctx->sur_a) return fail(ctx, TUFRG_EINVAL, "no surrogate attached");
+  unsigned long long v[3];
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  HIP_TRY(ctx, hipMemcpy(v, ctx->sur.stats, sizeof v, hipMemcpyDeviceToHost));
+  for (int i = 0; i < 3; ++i) out[i] = (int64_t)v[i];
   return TUFRG_OK;
 }
 
@@ -959,6 +1110,9 @@ tufrg_status tufrg_flow(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tuf
   if (!o || !X || !res) return fail(ctx, TUFRG_EINVAL, "NULL argument");
   if (!(o->T0 > 0.0) || !(o->Tmin > 0.0) || !(o->Tmin < o->T0) || !(o->Xmax > 0.0))
     return fail(ctx, TUFRG_EINVAL, "need T0 > Tmin > 0 and Xmax > 0");
+  if (o->scheme != TUFRG_RK4_LOG && o->scheme != TUFRG_DOPRI5_LOG)
+    return fail(ctx, TUFRG_EINVAL, "unknown scheme");
+  ST_TRY(ensure_flow_buffers(ctx));
   if (o->scheme == TUFRG_RK4_LOG) {
     if (o->nsteps <= 0) return fail(ctx, TUFRG_EINVAL, "nsteps must be > 0");
     ST_TRY(flow_rk4_all(ctx, o, X, res));
@@ -977,13 +1131,15 @@ tufrg_status tufrg_flow(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tuf
 
 void tufrg_free(tufrg_ctx* ctx) {
   if (!ctx) return;
-  if (!ctx->allocations.empty() || !ctx->geometry_allocations.empty()) hipDeviceSynchronize();
+  if (!ctx->allocations.empty() || !ctx->geometry_allocations.empty() || !ctx->sur_allocations.empty())
+    hipDeviceSynchronize();
   if (ctx->side) hipStreamDestroy(ctx->side);
   if (ctx->gs) hipStreamDestroy(ctx->gs);
   if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
   if (ctx->ev_gs) hipEventDestroy(ctx->ev_gs);
   if (ctx->umax_host) hipHostFree(ctx->umax_host);
+  for (void* p : ctx->sur_allocations) hipFree(p);
   for (void* p : ctx->geometry_allocations) hipFree(p);
   for (void* p : ctx->allocations) hipFree(p);
   delete ctx;

@@ -198,12 +198,20 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
     gh[o] = g;
   }
   __syncthreads();
-  // chi'_mn = sgn / (4 T^2 Nk) sum_j Ebub_{mn,j} ghat_j (pp carries the minus
-  // sign of dL^pp/dT = -Dh/(4T^2)).  With one slice the block writes chi'
-  // itself; otherwise its share goes to slice `split` of the point's
-  // [nsplit][2][Nq][nff^2] buffer and the consumer adds the slices in order.
+  // ghat_X(q, S_j) = sgn_X gh_j / (4 T^2 Nk) (pp carries the minus sign of
+  // dL^pp/dT = -Dh/(4T^2)); chi'_mn = sum_j Ebub_{mn,j} ghat(q, S_j).  With
+  // one slice the block writes chi' itself; otherwise its share goes to slice
+  // `split` of the point's [nsplit][2][Nq][nff^2] buffer and the consumer
+  // adds the slices in order.  In harmonics mode the block writes its slice
+  // of ghat instead.
   const int nff2 = d.nff * d.nff;
   const double base = 1.0 / (4.0 * T * T * (double)lk * (double)lk);
+  if (b.ghat != nullptr) {
+    for (int o = t; o < nout; o += blockDim.x)
+      b.ghat[d.ws_gh + ((size_t)split * d.nq + q) * nout + o] = gh[o] * (o < d.nsh ? -base : base);
+    __syncthreads();
+    return;
+  }
   for (int w = t; w < 2 * nff2; w += blockDim.x) {
     const int ch = w / nff2, mn = w % nff2;
     const double* e = d.ebub + (size_t)mn * d.nsh;
@@ -249,8 +257,9 @@ __global__ void __launch_bounds__(kLoopThreadsMax)
 k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ queue) {
   extern __shared__ double smem[];
   __shared__ int cur;
+  if (b.item_count != nullptr) nitems = min(nitems, *b.item_count);
   if (queue == nullptr) {
-    loop_dispatch<SMAX, MIXED>(b, items[blockIdx.x], smem);
+    if ((int)blockIdx.x < nitems) loop_dispatch<SMAX, MIXED>(b, items[blockIdx.x], smem);
     return;
   }
   const int t = threadIdx.x;
@@ -290,7 +299,7 @@ __device__ __forceinline__ void load_chi(const Batch& b, const DevTables& d, int
   const int nff2 = d.nff * d.nff, nq = d.nq;
   for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
     const int ch = w / nff2, mn = w % nff2;
-    if (d.nsplit == 1) {
+    if (d.nsplit == 1 || b.chi_final) {
       Ch[w] = b.dchi[(size_t)ch * b.S + d.off + (size_t)l * nff2 + mn];
     } else {
       double v = 0.0;
@@ -729,7 +738,7 @@ k_products_f32(Batch b, const int4* __restrict__ items, const double* __restrict
   for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
     const int ch = w / nff2, mn = w % nff2;
     double v;
-    if (d.nsplit == 1) {
+    if (d.nsplit == 1 || b.chi_final) {
       v = b.dchi[(size_t)ch * S + d.off + (size_t)l * nff2 + mn];
     } else {
       v = 0.0;

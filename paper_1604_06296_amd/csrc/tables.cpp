@@ -162,6 +162,22 @@ std::string build_tables(const tufrg_point& p, HostTables& t) {
     }
   t.nsh = (int)t.hx.size();
   t.ncol = 2 * t.nsh - 1;
+  // canonical bond pair of each half-set harmonic: the first (a, b) in bond
+  // order with R_a + R_b = S (the surrogate's encoding of S)
+  t.pairs.assign((size_t)4 * t.nsh, 0);
+  for (int j = 0; j < t.nsh; ++j) {
+    bool found = false;
+    for (int a = 0; a < nff && !found; ++a)
+      for (int b = 0; b < nff && !found; ++b)
+        if (t.bx[a] + t.bx[b] == t.hx[j] && t.by[a] + t.by[b] == t.hy[j]) {
+          t.pairs[4 * j + 0] = t.bx[a];
+          t.pairs[4 * j + 1] = t.by[a];
+          t.pairs[4 * j + 2] = t.bx[b];
+          t.pairs[4 * j + 3] = t.by[b];
+          found = true;
+        }
+    if (!found) return "internal error: harmonic without a bond pair";
+  }
   auto half_of = [&](int sx, int sy, int* conj) {
     bool neg = sx < 0 || (sx == 0 && sy < 0);
     *conj = neg ? 1 : 0;

@@ -10,6 +10,8 @@
 
 #include "../../include/tufrg.h"
 
+struct tufrg_mlp;
+
 namespace tufrg {
 
 using cplx = std::complex<double>;
@@ -31,6 +33,7 @@ struct HostTables {
   // harmonic set Hs = bonds + bonds (N_S vectors) and its half set Hh
   // (representatives with Sx > 0 or Sx == 0 && Sy >= 0; Hh[0] = (0,0))
   std::vector<int> hx, hy;        // half set [nsh]
+  std::vector<int32_t> pairs;     // canonical bond pair of each half-set harmonic [nsh][4]
   int nsh = 0;                    // N_S' = (N_S + 1)/2
   int ncol = 0;                   // 2 nsh - 1 real harmonic columns (cos, then sin without 0)
   // loops: chi_mn = sum_j Ebub[mn*nsh + j] ghat(S'_j)
@@ -75,6 +78,8 @@ struct DevTables {
   double t, tp, mu, U;
   int64_t off;            // element offset of the point inside one channel of [3][S] / [2][S]
   int64_t ws_xt, ws_yb, ws_g2, ws_dpart, ws_k;   // element offsets into the shared workspace
+  int64_t ws_gh;          // offset of the point's loop-harmonic slices [nsplit][nq][2][nsh]
+  int64_t gh_off;         // offset of the point's summed harmonics [nq][2][nsh]
   double* cre;            // [nff*nff]
   double* cim;
   int* shell_start;       // [nshell+1]
@@ -90,6 +95,7 @@ struct DevTables {
   int32_t* ment;
   int32_t* hx;            // half set [nsh]
   int32_t* hy;
+  int32_t* pairs;         // canonical bond pairs [nsh][4]
 };
 
 // Kernel-side view of one launch: tables, temperatures, stop flags, workspace.
@@ -104,6 +110,9 @@ struct Batch {
   double* yb;             // bond-basis transforms
   double* g2;             // inverse-transform coefficients
   float* kinv;            // inverse transforms (mixed precision)
+  double* ghat;           // loops: when set, write the loop harmonics here instead of chi'
+  const int* item_count;  // loops: when set, only the first *item_count items run
+  int chi_final;          // back ends: chi' is complete in dchi (no slices to add)
 };
 
 struct ItemRange {
@@ -133,6 +142,21 @@ struct Launch {
   size_t loop_smem, gather_smem, back_smem, prod_smem;
 };
 
+// Surrogate state of a single-point context (device pointers and settings).
+struct SurState {
+  double tol;                 // relative tolerance of the ensemble and residual checks
+  int stride;                 // one momentum in `stride` is checked per call, rotating
+  int* phase;                 // [1] current check phase
+  int* state;                 // [nq] fallback flags
+  int* need;                  // [nq] exact kernel this call
+  int* fail;                  // [nq] failed check this call
+  double* pred;               // [nq][2][nsh] predicted harmonics
+  double* fin;                // [nq][2][nsh] harmonics used this call
+  int4* items;                // [nq * nsplit] loop items of the exact momenta
+  int* count;                 // [1] number of those items
+  unsigned long long* stats;  // [3] exact momenta, momenta, failed checks (cumulative)
+};
+
 void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, hipStream_t s);
 void launch_chi_sum(const Launch& L, const ItemRange& r, double* dchi, hipStream_t s);
 void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s);
@@ -153,6 +177,18 @@ void launch_set_T_values(double* Tp, const double* T_host, int n, hipStream_t s)
 void launch_step_end(unsigned long long* words, int npts, int* frozen, double* hist, int* step,
                      int nsteps, double xmax, hipStream_t s);
 const void* loop_kernel_symbol(int smax_max, bool mixed);
+void launch_ghat_sum(const Launch& L, int p, const DevTables& d, double* out, hipStream_t s);
+void launch_sur_dataset(const Launch& L, int npts, int64_t n, uint64_t seed, float* x, float* y,
+                        int32_t* idx, hipStream_t s);
+void launch_surrogate_front(const Launch& L, int p, const DevTables& d, float* x, hipStream_t s);
+void launch_surrogate_decide(const Launch& L, int p, const DevTables& d, const float* ya, const float* yb,
+                             const SurState& st, hipStream_t s);
+void launch_surrogate_finish(const Launch& L, int p, const DevTables& d, const SurState& st, double* dchi,
+                             hipStream_t s);
+// forward pass of an MLP on stream s (rows in chunks of the net's max_rows)
+void mlp_forward_on(tufrg_mlp* net, const float* x, float* y, int64_t rows, hipStream_t s);
+int mlp_width(const tufrg_mlp* net, int i);   // widths[i]; i = -1: the last
+int mlp_max_rows(const tufrg_mlp* net);
 
 }  // namespace tufrg
 
@@ -173,6 +209,7 @@ struct tufrg_ctx {
   double* Tp = nullptr;                    // per-point temperatures
   int* frozen = nullptr;                   // per-point stop flags
   int* queue = nullptr;                    // loop-kernel work queue: next item, finished blocks
+  bool flow_ready = false;                 // flow state buffers allocated (first tufrg_flow)
   double* stage = nullptr;                 // RK stage state [3][S]
   double* kk[7] = {nullptr};               // RK slopes [3][S]
   double* ytmp = nullptr;                  // [3][S]
@@ -185,6 +222,16 @@ struct tufrg_ctx {
   int* step = nullptr;                     // device step counter
   int ttab_cap = 0;
   bool loop_persistent = false;            // launch form of the loop kernel
+  double* ghat = nullptr;                  // loop-harmonic slices (first harmonics call)
+  int64_t ghat_len = 0, ghat_sum_len = 0;  // slice and summed lengths over all points
+  // attached surrogate (single-point contexts)
+  tufrg_mlp* sur_a = nullptr;
+  tufrg_mlp* sur_b = nullptr;
+  tufrg::SurState sur{};
+  float* sur_x = nullptr;                  // [nq * nsh][9] features
+  float* sur_ya = nullptr;                 // [nq * nsh][4] predictions of each network
+  float* sur_yb = nullptr;
+  std::vector<void*> sur_allocations;
   std::vector<void*> allocations;          // freed by tufrg_free
   std::vector<void*> geometry_allocations; // item tables and slices; rebuilt by the autotuner
   std::string err;

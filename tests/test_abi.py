@@ -66,3 +66,20 @@ def test_workload_definitions():
     assert len(w4.points) == 64
     assert {p.Lk for p in w4.points} == {4 * p.Lq for p in w4.points}
     assert all(16 <= p.Lq <= 40 and p.Lq % 2 == 0 for p in w4.points)
+
+
+def test_mlp_and_surrogate_calls_validate_arguments(lib):
+    """Argument errors are reported before any device call."""
+    out = C.c_void_p()
+    w = (C.c_int32 * 3)(9, 0, 4)
+    assert lib.tufrg_mlp_create(w, 3, 64, 0, None, C.byref(out)) == -1
+    assert "widths" in lib.tufrg_mlp_last_error(None).decode()
+    w = (C.c_int32 * 1)(9)
+    assert lib.tufrg_mlp_create(w, 1, 64, 0, None, C.byref(out)) == -1
+    w = (C.c_int32 * 2)(9, 4)
+    assert lib.tufrg_mlp_create(w, 2, 0, 0, None, C.byref(out)) == -1
+    assert lib.tufrg_mlp_forward(None, None, None, 1) == -1
+    assert lib.tufrg_surrogate_attach(None, None, None, 1e-3, 8) == -1
+    assert lib.tufrg_loop_harmonics(None, None, None) == -1
+    n = C.c_int32()
+    assert lib.tufrg_harmonics(None, 0, C.byref(n), None, None) == -1
