@@ -2,9 +2,15 @@
 
 A step is one full right-hand side (loops, projections, products) of the
 t' = -0.25, n = 0.85, N_ff = 13, 24x24 transfer / 96x96 fine-grid workload
-with its inputs resident in HBM.  Prints one JSON line.
+with its inputs resident in HBM; `value` is right-hand sides per second.
+Further legs measure the other rows against the plain FP64 GPU path:
+  mixed      N_ff = 21, 48x48 / 128x128: FP64 vs mixed precision, per-result errors
+  batched    64 uneven points in one context: batched RK4 flow, eager vs graph
+  surrogate  N_ff = 21, 64x64 / 160x160: flow with and without the learned loops
+Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-flow] [--no-cpu]
+                    [--no-mixed] [--no-batched] [--no-surrogate]
 """
 from __future__ import annotations
 
@@ -29,7 +35,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-flow", action="store_true", help="skip the full-flow timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--train-steps", type=int, default=8000)
     return ap.parse_args()
 
 
@@ -39,8 +49,6 @@ def log(msg):
 
 def cpu_baseline(point, seconds):
     """The FP64 CPU oracle, untuned, on a bounded sample of the same workload."""
-    import numpy as np
-
     import synth
     from oracle.lattice import FormFactors
     from oracle.rhs import rhs as oracle_rhs
@@ -64,6 +72,157 @@ def cpu_baseline(point, seconds):
             "sample": f"{n} full right-hand sides of the same workload (oracle, FP64, numpy)"}
 
 
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def time_rhs(ctx, T, X, out, n=50):
+    for _ in range(5):
+        ctx.rhs(T, X, out)
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        ctx.rhs(T, X, out)
+    _sync()
+    return (time.perf_counter() - t0) / n
+
+
+def timed_flow(ctx, X, opts):
+    X.zero_()
+    _sync()
+    t0 = time.perf_counter()
+    res = ctx.flow(X, opts)
+    _sync()
+    return res, time.perf_counter() - t0
+
+
+def leg_mixed(tf, synth):
+    """cfg3: plain FP64 against the mixed-precision form, per result."""
+    import torch
+    w = synth.cfg3()
+    pt = w.points[0]
+    out = {"workload": w.name}
+    X = torch.from_numpy(synth.random_channels(pt.nq, pt.nff, seed=5).reshape(3, -1)).cuda()
+    ctxs = {p: tf.Context([pt], precision=p, autotune=True) for p in ("fp64", "mixed")}
+    opts = tf.FlowOptions(T0=w.T0, Tmin=w.Tmin, Xmax=w.Xmax, scheme="rk4", nsteps=w.nsteps, use_graph=True)
+    res = {}
+    for p, ctx in ctxs.items():
+        o = ctx.empty(3)
+        out[f"rhs_ms_{p}"] = 1e3 * time_rhs(ctx, 0.05, X, o)
+        Xf = ctx.empty(3)
+        r, el = timed_flow(ctx, Xf, opts)
+        V = ctx.project(Xf)
+        res[p] = (r[0], el, Xf, V)
+        out[f"flow_s_{p}"] = el
+        log(f"[mixed] {p}: rhs {out[f'rhs_ms_{p}']:.3f} ms, flow {el:.3f} s, {r[0]}")
+    # a diverging flow for the critical scale: the cfg2 point, RK4 in both precisions
+    w2 = synth.cfg2()
+    p2 = w2.points[0]
+    p2.mu = tf.mu_from_filling(p2.t, p2.tp, p2.filling, p2.mu_T, p2.mu_L)
+    o2 = tf.FlowOptions(T0=w2.T0, Tmin=w2.Tmin, Xmax=w2.Xmax, scheme="rk4", nsteps=400, use_graph=True)
+    c2 = {}
+    for p in ("fp64", "mixed"):
+        cx = tf.Context([p2], precision=p, autotune=True)
+        r, el = timed_flow(cx, cx.empty(3), o2)
+        c2[p] = (r[0], el)
+    a, b = c2["fp64"][0], c2["mixed"][0]
+    out["diverging_flow"] = {
+        "workload": w2.name + " (rk4, 400 steps)", "status": [a.status, b.status], "Tc": [a.Tc, b.Tc],
+        "Tc_rel_err": (abs(b.Tc / a.Tc - 1) if (a.Tc and b.Tc) else None),
+        "leading": [[a.channel, a.q_index, a.irrep], [b.channel, b.q_index, b.irrep]],
+        "flow_s": [c2["fp64"][1], c2["mixed"][1]]}
+    log(f"[mixed] cfg2 rk4: {out['diverging_flow']}")
+    r64, rmx = res["fp64"][0], res["mixed"][0]
+    maxV = [float(res[p][3].abs().max()) for p in ("fp64", "mixed")]
+    out.update({
+        "rhs_speedup": out["rhs_ms_fp64"] / out["rhs_ms_mixed"],
+        "flow_speedup": out["flow_s_fp64"] / out["flow_s_mixed"],
+        "status": [r64.status, rmx.status],
+        "Tc": [r64.Tc, rmx.Tc],
+        "Tc_rel_err": (abs(rmx.Tc / r64.Tc - 1) if (r64.Tc and rmx.Tc) else None),
+        "leading": [[r64.channel, r64.q_index, r64.irrep], [rmx.channel, rmx.q_index, rmx.irrep]],
+        "max_abs_X": [r64.max_abs_X, rmx.max_abs_X],
+        "max_abs_X_rel_err": abs(rmx.max_abs_X / r64.max_abs_X - 1),
+        "max_abs_V": maxV,
+        "max_abs_V_rel_err": abs(maxV[1] / maxV[0] - 1),
+        "X_end_rel_err": float((res["mixed"][2] - res["fp64"][2]).abs().max() / res["fp64"][2].abs().max()),
+    })
+    return out
+
+
+def leg_batched(tf, synth):
+    """cfg4: 64 uneven points, one context, RK4 flow eagerly and graph-replayed."""
+    w = synth.cfg4()
+    for p in w.points:
+        p.mu = tf.mu_from_filling(p.t, p.tp, p.filling, p.mu_T, p.mu_L)
+    ctx = tf.Context(w.points, autotune=True)
+    out = {"workload": w.name, "points": len(w.points), "S": ctx.S,
+           "loop_launch_form": "persistent queue" if ctx.geometry(0)[3] else "one block per item"}
+    X = ctx.empty(3)
+    Ts = [0.05] * len(w.points)
+    o = ctx.empty(3)
+    out["rhs_ms"] = 1e3 * time_rhs(ctx, Ts, X.zero_(), o, n=10)
+    opts = dict(T0=w.T0, Tmin=w.Tmin, Xmax=w.Xmax, scheme="rk4", nsteps=w.nsteps)
+    r_e, t_e = timed_flow(ctx, X, tf.FlowOptions(use_graph=False, **opts))
+    r_g, t_g = timed_flow(ctx, X, tf.FlowOptions(use_graph=True, **opts))
+    out.update({"flow_s_eager": t_e, "flow_s_graph": t_g, "graph_equals_eager": r_e == r_g,
+                "diverged": sum(r.status == "diverged" for r in r_g),
+                "rhs_total": sum(r.n_rhs for r in r_g)})
+    log(f"[batched] rhs {out['rhs_ms']:.3f} ms, flow eager {t_e:.2f} s, graph {t_g:.2f} s")
+    return out
+
+
+def leg_surrogate(tf, synth, train_steps):
+    """cfg5: surrogate trained on 2M exact samples; flow with and without it."""
+    import torch
+
+    from paper_1604_06296_amd import surrogate as sur
+    out = {}
+    pts = synth.surrogate_training_points(64)
+    temps = synth.surrogate_training_temperatures(64, 9)
+    t0 = time.perf_counter()
+    x, y = sur.make_training_set(pts, temps[:8], 262144, seed=500)
+    xv, yv = sur.make_training_set(pts, temps[8:], 65536, seed=900)
+    _sync()
+    out["data_s"] = time.perf_counter() - t0
+    out["train_samples"] = int(x.shape[0])
+    nets = sur.train_ensemble(x, y, steps=train_steps, batch=4096, lr=2e-3)
+    out["train_steps"] = train_steps
+    out["train_s"] = [t for _, _, t in nets]
+    out["final_loss"] = [float(h[-50:].mean()) for _, h, _ in nets]
+    out["validation"] = [sur.validation_error(n, xv, yv) for n, _, _ in nets]
+    log(f"[surrogate] data {out['data_s']:.2f} s, train {out['train_s']}, val {out['validation']}")
+    del x, y, xv, yv
+    w = synth.cfg5()
+    pt = w.points[0]
+    out["workload"] = w.name
+    opts = tf.FlowOptions(T0=w.T0, Tmin=w.Tmin, Xmax=w.Xmax, scheme="rk4", nsteps=w.nsteps, use_graph=True)
+    exact = tf.Context([pt], autotune=True)
+    Xe = exact.empty(3)
+    re, te = timed_flow(exact, Xe, opts)
+    ctx = tf.Context([pt], autotune=True)
+    ctx.attach_surrogate(nets[0][0], nets[1][0], tol=1e-3, check_stride=8)
+    Xs = ctx.empty(3)
+    rs, ts = timed_flow(ctx, Xs, opts)
+    st = ctx.surrogate_stats()
+    X = torch.from_numpy(synth.random_channels(pt.nq, pt.nff, seed=5).reshape(3, -1)).cuda()
+    o = exact.empty(3)
+    out.update({
+        "flow_s_exact": te, "flow_s_surrogate": ts, "flow_speedup": te / ts,
+        "rhs_ms_exact": 1e3 * time_rhs(exact, 0.05, X, o, n=20),
+        "rhs_ms_surrogate": 1e3 * time_rhs(ctx, 0.05, X, o, n=20),
+        "exact_fraction": st["exact_q"] / max(st["queried_q"], 1), "failed_checks": st["failed_checks"],
+        "status": [re[0].status, rs[0].status], "Tc": [re[0].Tc, rs[0].Tc],
+        "Tc_rel_err": (abs(rs[0].Tc / re[0].Tc - 1) if (re[0].Tc and rs[0].Tc) else None),
+        "leading": [[re[0].channel, re[0].q_index, re[0].irrep], [rs[0].channel, rs[0].q_index, rs[0].irrep]],
+        "max_abs_X": [re[0].max_abs_X, rs[0].max_abs_X],
+        "X_end_rel_err": float((Xs - Xe).abs().max() / Xe.abs().max()),
+    })
+    log(f"[surrogate] flow exact {te:.3f} s, surrogate {ts:.3f} s, exact fraction {out['exact_fraction']:.3f}")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -80,14 +239,15 @@ def main():
     w = synth.cfg2()
     pt = w.points[0]
     pt.mu = tf.mu_from_filling(pt.t, pt.tp, pt.filling, pt.mu_T, pt.mu_L)
-    ctx = tf.Context([pt])
-    nff = 13
+    ctx = tf.Context([pt], autotune=True)
+    nff = pt.nff
     X = torch.from_numpy(synth.random_channels(pt.nq, nff, seed=5, scale=1.0).reshape(3, -1)).cuda()
     out = ctx.empty(3)
     dchi = ctx.empty(2)
     # temperatures spread over the flow range
     Ts = [math.exp(math.log(10.0) + (math.log(1e-3) - math.log(10.0)) * i / 63) for i in range(64)]
-    log(f"[bench] workload {w.name}: Nq={pt.nq} Nk={pt.Lk ** 2} Nff={nff} mu={pt.mu:.6f}")
+    log(f"[bench] workload {w.name}: Nq={pt.nq} Nk={pt.Lk ** 2} Nff={nff} mu={pt.mu:.6f} "
+        f"loop geometry {ctx.geometry(0)}")
 
     for i in range(args.warmup):
         ctx.rhs(Ts[i % 64], X, out)
@@ -101,7 +261,9 @@ def main():
     ms = 1e3 * el / args.steps
     log(f"[bench] {args.steps} rhs in {el:.4f} s ({ms:.4f} ms each)")
 
-    # dominant kernel (loops): live HIP-event timing on the context's stream
+    # dominant kernel (loops): live HIP-event timing on the context's stream,
+    # which is torch's current stream; one bubbles call = the temperature
+    # upload kernel + the loop kernel (one slice per momentum after tuning)
     nb = max(args.steps, 20)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ctx.bubbles(Ts[0], dchi)
@@ -117,15 +279,22 @@ def main():
 
     flow_info = None
     if not args.no_flow:
-        Xf = ctx.empty(3).zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = ctx.flow(Xf, tf.FlowOptions(T0=w.T0, Tmin=w.Tmin, Xmax=w.Xmax, scheme="dopri5",
-                                        rtol=w.rtol, atol=w.atol))[0]
-        fl = time.perf_counter() - t0
+        Xf = ctx.empty(3)
+        r, fl = timed_flow(ctx, Xf, tf.FlowOptions(T0=w.T0, Tmin=w.Tmin, Xmax=w.Xmax, scheme="dopri5",
+                                                   rtol=w.rtol, atol=w.atol))
+        r = r[0]
         flow_info = {"flow_time_s": fl, "status": r.status, "Tc": r.Tc, "channel": r.channel,
                      "q_index": r.q_index, "irrep": r.irrep, "n_rhs": r.n_rhs, "n_steps": r.n_steps}
         log(f"[bench] flow {fl:.3f} s: {flow_info}")
+
+    legs = {}
+    for name, skip, fn in (("mixed", args.no_mixed, lambda: leg_mixed(tf, synth)),
+                           ("batched", args.no_batched, lambda: leg_batched(tf, synth)),
+                           ("surrogate", args.no_surrogate, lambda: leg_surrogate(tf, synth, args.train_steps))):
+        if not skip:
+            log(f"[bench] leg {name}")
+            legs[name] = fn()
+            torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu:
@@ -146,7 +315,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "Lq": pt.Lq, "Lk": pt.Lk, "nff": nff, "t": pt.t,
                    "tp": pt.tp, "filling": pt.filling, "mu": pt.mu, "U": pt.U,
-                   "flow": flow_info, "flops_per_rhs": flops},
+                   "loop_geometry": list(ctx.geometry(0)),
+                   "flow": flow_info, "flops_per_rhs": flops, **legs},
         "roofline": {"bound": "alu", "kernel": "k_loops", "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": None, "launch_us": loop_ms * 1e3},

@@ -97,6 +97,10 @@ enum {
                                named by the environment variable TUFRG_TUNE_CACHE
                                when it is set.  Results differ from the default
                                geometry only by summation order. */
+  TUFRG_NO_SYMMETRY = 1u << 3, /* integrate the loops at every transfer momentum
+                               instead of one representative per C4v orbit (a
+                               test seam: the point-group reduction is exact up
+                               to rounding) */
   TUFRG_LOOP_QUEUE = 1u << 2 /* run the loop kernel as persistent blocks that take
                                work items from a queue (default: one block per work
                                item, items ordered costliest first); bit-identical
@@ -106,7 +110,8 @@ enum {
 
 typedef struct {
   int32_t precision;       /* TUFRG_FP64 or TUFRG_MIXED */
-  uint32_t flags;          /* TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE */
+  uint32_t flags;          /* TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE |
+                              TUFRG_NO_SYMMETRY */
 } tufrg_options;
 
 enum { TUFRG_RK4_LOG = 0, TUFRG_DOPRI5_LOG = 1 };

@@ -17,6 +17,7 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 NO_CROSS = 1
 AUTOTUNE = 2
 LOOP_QUEUE = 4
+NO_SYMMETRY = 8
 
 # every entry point declared in include/tufrg.h
 EXPORTS = ("tufrg_init", "tufrg_layout", "tufrg_geometry", "tufrg_bubbles", "tufrg_project",
@@ -256,7 +257,8 @@ class Context:
     """
 
     def __init__(self, points: Sequence, precision: str = "fp64", no_cross: bool = False,
-                 stream=None, autotune: bool = False, loop_queue: bool = False):
+                 stream=None, autotune: bool = False, loop_queue: bool = False,
+                 no_symmetry: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise TufrgError("a GPU is required (torch.cuda.is_available() is False)")
@@ -270,7 +272,7 @@ class Context:
             arr[i] = _Point(p.t, p.tp, p.mu, p.U, p.Lq, p.Lk, p.shells, 0)
         opt = _Options(PRECISIONS[precision],
                        (NO_CROSS if no_cross else 0) | (AUTOTUNE if autotune else 0)
-                       | (LOOP_QUEUE if loop_queue else 0))
+                       | (LOOP_QUEUE if loop_queue else 0) | (NO_SYMMETRY if no_symmetry else 0))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = C.c_void_p()
         _check(self.lib, None, self.lib.tufrg_init(arr, n, C.byref(opt),

@@ -104,20 +104,21 @@ size_t loop_smem_of(const DevTables& d, int threads) {
          ((size_t)2 * nrmax + (size_t)nrmax * NH + (size_t)d.lk * 2 * NH + (size_t)nseg * nout);
 }
 
-// Default loop geometry: split the half fine grid of every transfer momentum
-// into row slices (separate work items) and row chunks (threads of one
-// column) until about 8 waves per SIMD are in flight, keeping at least 4 rows
-// per thread and at most kLoopThreadsMax threads per block.
+// Default loop geometry: split the half fine grid of every representative
+// transfer momentum into row chunks (threads of one column; at least 3 rows
+// each) and then row slices (separate work items; at least 2 rows per thread)
+// until about 8 waves per SIMD are in flight, with at most kLoopThreadsMax
+// threads per block.
 void default_geometry(DevTables& d) {
   const int rows = d.lk / 2 + 1;
   const int64_t target = (int64_t)256 * 4 * 8 * 64;
   int nsplit = 1, nchunk = 1;
   for (;;) {
-    const int64_t lanes = (int64_t)d.nq * d.lk * nsplit * nchunk;
+    const int64_t lanes = (int64_t)d.nirr * d.lk * nsplit * nchunk;
     if (lanes >= target) break;
-    if (d.lk * (nchunk + 1) <= kLoopThreadsMax && rows / (nsplit * (nchunk + 1)) >= 4) {
+    if (d.lk * (nchunk + 1) <= kLoopThreadsMax && rows / (nsplit * (nchunk + 1)) >= 3) {
       ++nchunk;
-    } else if (nsplit < 16 && rows / ((nsplit + 1) * nchunk) >= 4) {
+    } else if (nsplit < 16 && rows / ((nsplit + 1) * nchunk) >= 2) {
       ++nsplit;
     } else {
       break;
@@ -129,7 +130,7 @@ void default_geometry(DevTables& d) {
 
 // ------------------------------------------------------------ item tables
 struct HostItems {
-  std::vector<int4> loop, chi, fwd, fwd_mfma, basis, gather, inv_mfma, back, prod, seg;
+  std::vector<int4> loop, exp, fwd, fwd_mfma, basis, gather, inv_mfma, back, prod, seg;
 };
 
 template <class F>
@@ -143,9 +144,8 @@ void mark(std::vector<int4>& v, ItemRange& rg, F fill) {
 // point's ranges.  Item layouts are those documented at each kernel.
 void add_point_items(const DevTables& d, int p, HostItems& h, Ranges& r) {
   const int nff2 = d.nff * d.nff, nv = 2 * d.nsh - 1;
-  mark(h.chi, r.chi, [&](std::vector<int4>& v) {
-    if (d.nsplit > 1)
-      for (int b = 0; b < (2 * d.nq * nff2 + 255) / 256; ++b) v.push_back(make_int4(p, b, 0, 0));
+  mark(h.exp, r.exp, [&](std::vector<int4>& v) {
+    for (int q = 0; q < d.nq; ++q) v.push_back(make_int4(p, q, 0, 0));
   });
   mark(h.fwd, r.fwd, [&](std::vector<int4>& v) {
     for (int c = 0; c < (3 * nff2 + 63) / 64; ++c)
@@ -179,10 +179,10 @@ void add_point_items(const DevTables& d, int p, HostItems& h, Ranges& r) {
   });
 }
 
-// loop items of one point: one per (transfer momentum, row slice)
+// loop items of one point: one per (representative momentum, row slice)
 void add_loop_items(const DevTables& d, int p, std::vector<int4>& v, ItemRange& r) {
   mark(v, r, [&](std::vector<int4>& w) {
-    for (int b = 0; b < d.nq * d.nsplit; ++b) w.push_back(make_int4(p, b, 0, 0));
+    for (int b = 0; b < d.nirr * d.nsplit; ++b) w.push_back(make_int4(p, b, 0, 0));
   });
 }
 
@@ -214,7 +214,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   for (int p = 0; p < npts; ++p) add_point_items(ctx->dev[p], p, h, ctx->per_point[p]);
   int smax_max = 0, threads = 64;
   size_t lsm = 0, gsm = 0, bsm = 0, psm = 0;
-  int64_t dpart = 0, gh = 0, ghs = 0;
+  int64_t gh = 0, ghs = 0;
   for (int p = 0; p < npts; ++p) {
     DevTables& d = ctx->dev[p];
     smax_max = std::max(smax_max, d.smax);
@@ -224,10 +224,8 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
     bsm = std::max(bsm, sizeof(double) * ((size_t)d.lt * d.ncol + (size_t)d.lt * 3 * nff2 +
                                           9 * (size_t)nff2));
     psm = std::max(psm, sizeof(float) * 12 * (size_t)nff2);
-    d.ws_dpart = dpart;
-    if (d.nsplit > 1) dpart += (int64_t)d.nsplit * 2 * d.nq * nff2;
     d.ws_gh = gh;
-    gh += (int64_t)d.nsplit * d.nq * 2 * d.nsh;
+    gh += (int64_t)d.nsplit * d.nirr * 2 * d.nsh;
     d.gh_off = ghs;
     ghs += (int64_t)d.nq * 2 * d.nsh;
   }
@@ -244,7 +242,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
     return r;
   };
   Ranges& all = ctx->all;
-  all.loop = whole(h.loop); all.chi = whole(h.chi); all.fwd = whole(h.fwd);
+  all.loop = whole(h.loop); all.exp = whole(h.exp); all.fwd = whole(h.fwd);
   all.fwd_mfma = whole(h.fwd_mfma); all.basis = whole(h.basis); all.gather = whole(h.gather);
   all.inv_mfma = whole(h.inv_mfma); all.back = whole(h.back); all.prod = whole(h.prod);
   all.seg = whole(h.seg);
@@ -252,7 +250,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   std::vector<void*>& g = ctx->geometry_allocations;
   int4* t = nullptr;
   ST_TRY(upload(ctx, h.loop, &t, g)); L.loop_items = t;
-  ST_TRY(upload(ctx, h.chi, &t, g)); L.chi_items = t;
+  ST_TRY(upload(ctx, h.exp, &t, g)); L.exp_items = t;
   ST_TRY(upload(ctx, h.fwd, &t, g)); L.fwd_items = t;
   ST_TRY(upload(ctx, h.fwd_mfma, &t, g)); L.fwd_mfma_items = t;
   ST_TRY(upload(ctx, h.basis, &t, g)); L.basis_items = t;
@@ -261,8 +259,8 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   ST_TRY(upload(ctx, h.back, &t, g)); L.back_items = t;
   ST_TRY(upload(ctx, h.prod, &t, g)); L.prod_items = t;
   ST_TRY(upload(ctx, h.seg, &t, g)); L.seg_items = t;
-  L.b.dpart = nullptr;
-  if (dpart > 0) ST_TRY(dalloc(ctx, (size_t)dpart, &L.b.dpart, g));
+  ST_TRY(dalloc(ctx, (size_t)std::max<int64_t>(gh, 1), &L.b.ghat, g));
+  ctx->ghat = L.b.ghat;
   DevTables* dp = nullptr;
   ST_TRY(upload(ctx, ctx->dev, &dp, g));
   L.b.pts = dp;
@@ -293,23 +291,34 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
 // side stream, concurrently with the X-dependent front end of the
 // projections; the back end (V and the products) joins both.
 // Loops through the attached surrogate (single-point context): predicted
-// harmonics, exact loop kernel on the momenta that need it, the check and
-// fallback bookkeeping, and chi' into dchi.
+// harmonics of the representatives, exact loop kernel on those that need it,
+// the check and fallback bookkeeping, and chi' of every momentum into dchi.
 void surrogate_loops(tufrg_ctx* ctx, const Launch& L, double* dchi, hipStream_t s) {
   const DevTables& d = ctx->dev[0];
-  const int64_t rows = (int64_t)d.nq * d.nsh;
+  const int64_t rows = (int64_t)d.nirr * d.nsh;
   launch_surrogate_front(L, 0, d, ctx->sur_x, s);
   mlp_forward_on(ctx->sur_a, ctx->sur_x, ctx->sur_ya, rows, s);
   mlp_forward_on(ctx->sur_b, ctx->sur_x, ctx->sur_yb, rows, s);
   launch_surrogate_decide(L, 0, d, ctx->sur_ya, ctx->sur_yb, ctx->sur, s);
   Launch Lg = L;
-  Lg.b.ghat = ctx->ghat;
   Lg.b.item_count = ctx->sur.count;
   Lg.loop_items = ctx->sur.items;
   ItemRange r;
-  r.n = d.nq * d.nsplit;
+  r.n = d.nirr * d.nsplit;
   launch_loops(Lg, r, ctx->queue, false, s);
-  launch_surrogate_finish(Lg, 0, d, ctx->sur, dchi, s);
+  launch_surrogate_finish(L, 0, d, ctx->sur, s);
+  launch_chi_expand(L, ctx->all.exp, ctx->sur.fin, dchi, s);
+}
+
+// Loops of the ranges r into dchi: the loop kernel on the representatives,
+// then chi' of every momentum (or the surrogate path when attached).
+void loops_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, double* dchi, hipStream_t s) {
+  if (ctx->sur_a) {
+    surrogate_loops(ctx, L, dchi, s);
+    return;
+  }
+  launch_loops(L, r.loop, ctx->queue, mixed_of(ctx), s);
+  launch_chi_expand(L, r.exp, nullptr, dchi, s);
 }
 
 void rhs_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, const double* X, double* out,
@@ -317,22 +326,11 @@ void rhs_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, const double* 
   const bool mixed = mixed_of(ctx), cross = cross_of(ctx);
   hipEventRecord(ctx->ev_fork, ms);
   hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
-  Launch Lb = L;
-  if (ctx->sur_a) {
-    surrogate_loops(ctx, L, L.b.dchi, ctx->side);
-    Lb.b.chi_final = 1;
-  } else {
-    launch_loops(L, r.loop, ctx->queue, mixed, ctx->side);
-  }
+  loops_launch(ctx, L, r, L.b.dchi, ctx->side);
   hipEventRecord(ctx->ev_join, ctx->side);
   if (cross) launch_front(L, r, X, mixed, ms);
   hipStreamWaitEvent(ms, ctx->ev_join, 0);
-  launch_back(Lb, r, X, out, 1, cross, scale_T, mixed, ms);
-}
-
-tufrg_status ensure_ghat(tufrg_ctx* ctx) {
-  if (ctx->ghat) return TUFRG_OK;
-  return dalloc(ctx, (size_t)std::max<int64_t>(ctx->ghat_len, 1), &ctx->ghat, ctx->allocations);
+  launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms);
 }
 
 tufrg_status ensure_flow_buffers(tufrg_ctx* ctx) {
@@ -357,7 +355,7 @@ tufrg_status check_temperatures(tufrg_ctx* ctx, const double* T_host) {
 // distinct point shape in launches of that point alone and keeps the fastest.
 std::string tune_key(const DevTables& d, int precision) {
   char k[128];
-  std::snprintf(k, sizeof k, "gfx950_nq%d_lk%d_nff%d_prec%d", d.nq, d.lk, d.nff, precision);
+  std::snprintf(k, sizeof k, "gfx950_nq%d_nirr%d_lk%d_nff%d_prec%d", d.nq, d.nirr, d.lk, d.nff, precision);
   return k;
 }
 
@@ -384,7 +382,7 @@ tufrg_status autotune(tufrg_ctx* ctx) {
     DevTables& d = ctx->dev[p];
     const std::string key = tune_key(d, ctx->opt.precision);
     const int rows = d.lk / 2 + 1;
-    auto fits = [&](int ns, int nc) { return d.lk * nc <= kLoopThreadsMax && rows / (ns * nc) >= 3; };
+    auto fits = [&](int ns, int nc) { return d.lk * nc <= kLoopThreadsMax && rows / (ns * nc) >= 2; };
     std::pair<int, int> prior{0, 0};
     if (known.count(key)) prior = known[key];
     else if (fresh.count(key)) prior = fresh[key];
@@ -395,7 +393,7 @@ tufrg_status autotune(tufrg_ctx* ctx) {
     }
     double best = 1e300;
     int bs = d.nsplit, bc = d.nchunk;
-    for (int ns = 1; ns <= 8 && !st; ns *= 2)
+    for (int ns = 1; ns <= 16 && !st; ns *= 2)
       for (int nc = 1; nc <= 8 && !st; ++nc) {
         if (!fits(ns, nc)) continue;
         d.nsplit = ns;
@@ -465,7 +463,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   if (opt) o = *opt;
   if (o.precision != TUFRG_FP64 && o.precision != TUFRG_MIXED)
     return fail(nullptr, TUFRG_EINVAL, "precision must be TUFRG_FP64 or TUFRG_MIXED");
-  if (o.flags & ~(uint32_t)(TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE))
+  if (o.flags & ~(uint32_t)(TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE | TUFRG_NO_SYMMETRY))
     return fail(nullptr, TUFRG_EINVAL, "unknown flag bits");
   auto* ctx = new tufrg_ctx();
   ctx->opt = o;
@@ -476,7 +474,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   ctx->dev.assign(npts, DevTables());
   int64_t S = 0, ws_xt = 0, ws_yb = 0, ws_g2 = 0, ws_k = 0;
   for (int p = 0; p < npts; ++p) {
-    std::string e = build_tables(pts[p], ctx->host[p]);
+    std::string e = build_tables(pts[p], ctx->host[p], !(o.flags & TUFRG_NO_SYMMETRY));
     if (e.empty() && ctx->host[p].lk > kLoopThreadsMax)
       e = "Lk must be <= " + std::to_string(kLoopThreadsMax);
     if (!e.empty()) {
@@ -487,7 +485,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     DevTables& d = ctx->dev[p];
     std::memset(&d, 0, sizeof d);
     d.nff = t.nff; d.nq = t.nq; d.lq = t.p.Lq; d.lk = t.lk; d.nsh = t.nsh; d.ncol = t.ncol;
-    d.smax = t.smax; d.nshell = t.nshell;
+    d.smax = t.smax; d.nshell = t.nshell; d.nirr = t.nirr;
     d.t = t.p.t; d.tp = t.p.tp; d.mu = t.p.mu; d.U = t.p.U;
     default_geometry(d);
     // momenta per block of the FP64 back end: 2 on large grids while its LDS
@@ -545,7 +543,8 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
         (st = upload(ctx, t.cshift, &d.cshift, A)) || (st = upload(ctx, ehi, &d.eph_hi, A)) ||
         (st = upload(ctx, elo, &d.eph_lo, A)) || (st = upload(ctx, t.mrow, &d.mrow, A)) ||
         (st = upload(ctx, t.ment, &d.ment, A)) || (st = upload(ctx, hx, &d.hx, A)) ||
-        (st = upload(ctx, hy, &d.hy, A)) || (st = upload(ctx, t.pairs, &d.pairs, A)))
+        (st = upload(ctx, hy, &d.hy, A)) || (st = upload(ctx, t.pairs, &d.pairs, A)) ||
+        (st = upload(ctx, t.irr, &d.irr, A)) || (st = upload(ctx, t.symmap, &d.symmap, A)))
       return bad(st);
   }
   // workspace, state buffers and control words
@@ -613,14 +612,7 @@ tufrg_status tufrg_bubbles(tufrg_ctx* ctx, const double* T_host, double* dchi) {
   if (!T_host || !dchi) return fail(ctx, TUFRG_EINVAL, "NULL argument");
   ST_TRY(check_temperatures(ctx, T_host));
   launch_set_T_values(ctx->Tp, T_host, (int)ctx->dev.size(), ctx->stream);
-  Launch L = ctx->L;
-  L.b.dchi = dchi;
-  if (ctx->sur_a) {
-    surrogate_loops(ctx, L, dchi, ctx->stream);
-  } else {
-    launch_loops(L, ctx->all.loop, ctx->queue, mixed_of(ctx), ctx->stream);
-    launch_chi_sum(L, ctx->all.chi, dchi, ctx->stream);
-  }
+  loops_launch(ctx, ctx->L, ctx->all, dchi, ctx->stream);
   HIP_TRY(ctx, hipGetLastError());
   return TUFRG_OK;
 }
@@ -669,10 +661,8 @@ tufrg_status tufrg_loop_harmonics(tufrg_ctx* ctx, const double* T_host, double* 
   if (!T_host || !ghat) return fail(ctx, TUFRG_EINVAL, "NULL argument");
   if (mixed_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "loop harmonics are computed in FP64 contexts");
   ST_TRY(check_temperatures(ctx, T_host));
-  ST_TRY(ensure_ghat(ctx));
   launch_set_T_values(ctx->Tp, T_host, (int)ctx->dev.size(), ctx->stream);
-  Launch L = ctx->L;
-  L.b.ghat = ctx->ghat;
+  const Launch& L = ctx->L;
   launch_loops(L, ctx->all.loop, ctx->queue, false, ctx->stream);
   for (size_t p = 0; p < ctx->dev.size(); ++p) launch_ghat_sum(L, (int)p, ctx->dev[p], ghat, ctx->stream);
   HIP_TRY(ctx, hipGetLastError());
@@ -686,10 +676,8 @@ tufrg_status tufrg_surrogate_dataset(tufrg_ctx* ctx, const double* T_host, int64
   if (n < 0) return fail(ctx, TUFRG_EINVAL, "n must be >= 0");
   if (mixed_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "training labels come from FP64 contexts");
   ST_TRY(check_temperatures(ctx, T_host));
-  ST_TRY(ensure_ghat(ctx));
   launch_set_T_values(ctx->Tp, T_host, (int)ctx->dev.size(), ctx->stream);
-  Launch L = ctx->L;
-  L.b.ghat = ctx->ghat;
+  const Launch& L = ctx->L;
   launch_loops(L, ctx->all.loop, ctx->queue, false, ctx->stream);
   launch_sur_dataset(L, (int)ctx->dev.size(), n, seed, x, y, idx, ctx->stream);
   HIP_TRY(ctx, hipGetLastError());
@@ -712,9 +700,8 @@ tufrg_status tufrg_surrogate_attach(tufrg_ctx* ctx, tufrg_mlp* a, tufrg_mlp* b, 
     if (mlp_width(m, 0) != 9 || mlp_width(m, -1) != 4)
       return fail(ctx, TUFRG_EINVAL, "surrogate networks map 9 features to 4 targets");
   if (!(tol > 0.0) || check_stride < 1) return fail(ctx, TUFRG_EINVAL, "need tol > 0 and check_stride >= 1");
-  ST_TRY(ensure_ghat(ctx));
   const DevTables& d = ctx->dev[0];
-  const size_t rows = (size_t)d.nq * d.nsh, nh = (size_t)d.nq * 2 * d.nsh;
+  const size_t rows = (size_t)d.nirr * d.nsh, nh = (size_t)d.nirr * 2 * d.nsh;
   std::vector<void*>& g = ctx->sur_allocations;
   SurState& st = ctx->sur;
   st = SurState();
@@ -724,16 +711,16 @@ tufrg_status tufrg_surrogate_attach(tufrg_ctx* ctx, tufrg_mlp* a, tufrg_mlp* b, 
   ST_TRY(dalloc(ctx, rows * 4, &ctx->sur_ya, g));
   ST_TRY(dalloc(ctx, rows * 4, &ctx->sur_yb, g));
   ST_TRY(dalloc(ctx, 1, &st.phase, g));
-  ST_TRY(dalloc(ctx, (size_t)d.nq, &st.state, g));
-  ST_TRY(dalloc(ctx, (size_t)d.nq, &st.need, g));
-  ST_TRY(dalloc(ctx, (size_t)d.nq, &st.fail, g));
+  ST_TRY(dalloc(ctx, (size_t)d.nirr, &st.state, g));
+  ST_TRY(dalloc(ctx, (size_t)d.nirr, &st.need, g));
+  ST_TRY(dalloc(ctx, (size_t)d.nirr, &st.fail, g));
   ST_TRY(dalloc(ctx, nh, &st.pred, g));
   ST_TRY(dalloc(ctx, nh, &st.fin, g));
-  ST_TRY(dalloc(ctx, (size_t)d.nq * d.nsplit, &st.items, g));
+  ST_TRY(dalloc(ctx, (size_t)d.nirr * d.nsplit, &st.items, g));
   ST_TRY(dalloc(ctx, 1, &st.count, g));
   ST_TRY(dalloc(ctx, 3, &st.stats, g));
   launch_fill_i32(st.phase, 1, 0, ctx->stream);
-  launch_fill_i32(st.state, d.nq, 0, ctx->stream);
+  launch_fill_i32(st.state, d.nirr, 0, ctx->stream);
   launch_fill_u64(st.stats, 3, 0ull, ctx->stream);
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   ctx->sur_a = a;

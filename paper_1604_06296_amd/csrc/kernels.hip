@@ -44,14 +44,16 @@ __device__ __forceinline__ void neumaier_add(float& s, float& c, float v) {
 
 // ------------------------------------------------------------------ loops
 // Step ii.) of Sec. 2.4, eqn. chis, at the point's temperature.  Work item
-// (p, q * nsplit + split): one transfer momentum q and one slice of the rows
+// (p, slot * nsplit + split): one representative transfer momentum q =
+// irr[slot] (point-group orbits; every other momentum follows by symmetry in
+// the expansion kernel) and one slice of the rows
 // py in [0, Lk/2] of the fine grid (the loop weight is even in p: the
 // self-paired rows py = 0 and Lk/2 carry weight 1, the others weight 2).
 // Threads own one column px and a chunk of the slice's rows; they accumulate
 // row sums of the loop derivative against cos(n py) and sin(n py), n <= smax.
 // The block contracts the rows against cos(px Sx), sin(px Sx) into
 // ghat(q, S) = (1/Nk) sum_p L'(p) cos(p.S) for the half set of harmonics S in
-// bonds + bonds and applies chi'_mn(q) = sum_S Ebub_{mn,S} ghat(q, S).
+// bonds + bonds.
 // In the persistent form queue[0] is the next item and queue[1] counts
 // finished blocks; both are zero at entry, and the last block to finish sets
 // them back to zero for the next launch (device-scope atomics, valid across
@@ -66,7 +68,8 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
   constexpr int NH = 2 * SMAX + 1;
   const int t = threadIdx.x;
   const int nsplit = d.nsplit, nchunk = d.nchunk;
-  const int q = item_b / nsplit, split = item_b % nsplit;
+  const int slot = item_b / nsplit, split = item_b % nsplit;
+  const int q = d.irr[slot];
   const int lk = d.lk;
   const int rows = lk / 2 + 1;
   const int R0 = (int)((int64_t)rows * split / nsplit);
@@ -199,31 +202,12 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
   }
   __syncthreads();
   // ghat_X(q, S_j) = sgn_X gh_j / (4 T^2 Nk) (pp carries the minus sign of
-  // dL^pp/dT = -Dh/(4T^2)); chi'_mn = sum_j Ebub_{mn,j} ghat(q, S_j).  With
-  // one slice the block writes chi' itself; otherwise its share goes to slice
-  // `split` of the point's [nsplit][2][Nq][nff^2] buffer and the consumer
-  // adds the slices in order.  In harmonics mode the block writes its slice
-  // of ghat instead.
-  const int nff2 = d.nff * d.nff;
+  // dL^pp/dT = -Dh/(4T^2)), written to slice `split` of the representative's
+  // harmonics; chi'_mn = sum_j Ebub_{mn,j} ghat(q, S_j) follows in the
+  // expansion kernel.
   const double base = 1.0 / (4.0 * T * T * (double)lk * (double)lk);
-  if (b.ghat != nullptr) {
-    for (int o = t; o < nout; o += blockDim.x)
-      b.ghat[d.ws_gh + ((size_t)split * d.nq + q) * nout + o] = gh[o] * (o < d.nsh ? -base : base);
-    __syncthreads();
-    return;
-  }
-  for (int w = t; w < 2 * nff2; w += blockDim.x) {
-    const int ch = w / nff2, mn = w % nff2;
-    const double* e = d.ebub + (size_t)mn * d.nsh;
-    const double* g = gh + ch * d.nsh;
-    double v = 0.0;
-    for (int j = 0; j < d.nsh; ++j) v = fma(e[j], g[j], v);
-    v *= (ch == 0 ? -base : base);
-    if (nsplit == 1)
-      b.dchi[(size_t)ch * b.S + d.off + (size_t)q * nff2 + mn] = v;
-    else
-      b.dpart[d.ws_dpart + (((size_t)split * 2 + ch) * d.nq + q) * nff2 + mn] = v;
-  }
+  for (int o = t; o < nout; o += blockDim.x)
+    b.ghat[d.ws_gh + ((size_t)split * d.nirr + slot) * nout + o] = gh[o] * (o < d.nsh ? -base : base);
   __syncthreads();
 }
 
@@ -277,36 +261,49 @@ k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ q
   }
 }
 
-// chi' = sum of the slices in slice order; item (p, block)
+// chi'_mn(q) = sum_j Ebub_{mn,j} ghat(q, S_j) for every momentum, with
+// ghat(q, S_j) = sign ghat(r, S_j') of its representative (pack_sym entry of
+// the symmetry map); item (p, q).  The representative's harmonics are the sum
+// of its loop slices, or come from fin [nirr][2][nsh] (single point).
 __global__ void __launch_bounds__(256)
-k_chi_sum(Batch b, const int4* __restrict__ items, double* __restrict__ dchi) {
+k_chi_expand(Batch b, const int4* __restrict__ items, const double* __restrict__ fin,
+             double* __restrict__ dchi) {
+  __shared__ double g[2 * 64];
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
-  const int nff2 = d.nff * d.nff;
-  const int64_t n = (int64_t)2 * d.nq * nff2;
-  const int64_t i = (int64_t)item.y * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double v = 0.0;
-  for (int s = 0; s < d.nsplit; ++s) v += b.dpart[d.ws_dpart + (size_t)s * n + i];
-  const int64_t ch = i / ((int64_t)d.nq * nff2), r = i % ((int64_t)d.nq * nff2);
-  dchi[ch * b.S + d.off + r] = v;
+  const int q = item.y, nsh = d.nsh, nout = 2 * nsh, nff2 = d.nff * d.nff;
+  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+    const int ch = o / nsh, j = o % nsh;
+    const int32_t pk = d.symmap[(size_t)q * nsh + j];
+    const int slot = pk & 0xffff, j2 = (pk >> 16) & 0x7f;
+    const int oo = ch * nsh + j2;
+    double v = 0.0;
+    if (fin) {
+      v = fin[(size_t)slot * nout + oo];
+    } else {
+      for (int s = 0; s < d.nsplit; ++s) v += b.ghat[d.ws_gh + ((size_t)s * d.nirr + slot) * nout + oo];
+    }
+    g[o] = ((pk >> 24) & 1) ? -v : v;
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
+    const int ch = w / nff2, mn = w % nff2;
+    const double* e = d.ebub + (size_t)mn * nsh;
+    const double* gc = g + ch * nsh;
+    double v = 0.0;
+    for (int j = 0; j < nsh; ++j) v = fma(e[j], gc[j], v);
+    dchi[(size_t)ch * b.S + d.off + (size_t)q * nff2 + mn] = v;
+  }
 }
 
 // chi'(l) of one point into LDS (used by the FP64 back end)
 __device__ __forceinline__ void load_chi(const Batch& b, const DevTables& d, int l, double* Ch) {
-  const int nff2 = d.nff * d.nff, nq = d.nq;
+  const int nff2 = d.nff * d.nff;
   for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
     const int ch = w / nff2, mn = w % nff2;
-    if (d.nsplit == 1 || b.chi_final) {
-      Ch[w] = b.dchi[(size_t)ch * b.S + d.off + (size_t)l * nff2 + mn];
-    } else {
-      double v = 0.0;
-      for (int s = 0; s < d.nsplit; ++s)
-        v += b.dpart[d.ws_dpart + (((size_t)s * 2 + ch) * nq + l) * nff2 + mn];
-      Ch[w] = v;
-    }
+    Ch[w] = b.dchi[(size_t)ch * b.S + d.off + (size_t)l * nff2 + mn];
   }
 }
 
@@ -737,15 +734,7 @@ k_products_f32(Batch b, const int4* __restrict__ items, const double* __restrict
   }
   for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
     const int ch = w / nff2, mn = w % nff2;
-    double v;
-    if (d.nsplit == 1 || b.chi_final) {
-      v = b.dchi[(size_t)ch * S + d.off + (size_t)l * nff2 + mn];
-    } else {
-      v = 0.0;
-      for (int s2 = 0; s2 < d.nsplit; ++s2)
-        v += b.dpart[d.ws_dpart + (((size_t)s2 * 2 + ch) * nq + l) * nff2 + mn];
-    }
-    Ch[w] = (float)v;
+    Ch[w] = (float)b.dchi[(size_t)ch * S + d.off + (size_t)l * nff2 + mn];
   }
   __syncthreads();
   const float* VP = Vs;
@@ -944,9 +933,10 @@ void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, h
   }
 }
 
-void launch_chi_sum(const Launch& L, const ItemRange& r, double* dchi, hipStream_t s) {
+void launch_chi_expand(const Launch& L, const ItemRange& r, const double* fin, double* dchi,
+                       hipStream_t s) {
   if (r.n <= 0) return;
-  hipLaunchKernelGGL(k_chi_sum, dim3(r.n), dim3(256), 0, s, L.b, L.chi_items + r.begin, dchi);
+  hipLaunchKernelGGL(k_chi_expand, dim3(r.n), dim3(256), 0, s, L.b, L.exp_items + r.begin, fin, dchi);
 }
 
 void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s) {

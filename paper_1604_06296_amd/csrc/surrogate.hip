@@ -7,13 +7,15 @@
 //   (qx/pi, qy/pi, log10 T, mu/t, t'/t, R_a/2, R_b/2)
 // with (R_a, R_b) the canonical bond pair of S_j; targets (4):
 //   (T (1 + 4T) ghat_pp, (1 + 4T^2) ghat_ph, 0, 0).
-// Inference: two networks predict every query; a momentum q takes the exact
-// loop kernel when the networks disagree by more than tol relative to the
-// largest predicted harmonic at q, when it is in this call's check set
-// (q = phase mod stride, rotating per call), or when its fallback flag is
-// set.  Checked momenta compare prediction and exact harmonics; a failure
-// (relative residual above tol) flags the momentum and its 8 neighbours,
-// and a later passing check clears the flag.
+// Inference runs on the representatives of the transfer momenta (point-group
+// orbits; the expansion kernel serves the rest).  Two networks predict every
+// query; a representative takes the exact loop kernel when the networks
+// disagree by more than tol relative to its largest predicted harmonic, when
+// it is in this call's check set (slot = phase mod stride, rotating per
+// call), or when its fallback flag is set.  Checked representatives compare
+// prediction and exact harmonics; a failure (relative residual above tol)
+// flags it and the representatives of its 8 grid neighbours, and a later
+// passing check clears the flag.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -50,12 +52,20 @@ __device__ __forceinline__ void write_features(const DevTables& d, double T, int
   x[8] = 0.5f * (float)pr[3];
 }
 
-// exact harmonic o = ch * nsh + j of (p, q): the sum of the loop slices
-__device__ __forceinline__ double exact_harmonic(const Batch& b, const DevTables& d, int q, int o) {
+// harmonic o = ch * nsh + j of representative `slot`: the sum of its loop slices
+__device__ __forceinline__ double slot_harmonic(const Batch& b, const DevTables& d, int slot, int o) {
   const int nout = 2 * d.nsh;
   double v = 0.0;
-  for (int s = 0; s < d.nsplit; ++s) v += b.ghat[d.ws_gh + ((size_t)s * d.nq + q) * nout + o];
+  for (int s = 0; s < d.nsplit; ++s) v += b.ghat[d.ws_gh + ((size_t)s * d.nirr + slot) * nout + o];
   return v;
+}
+
+// exact harmonic o = ch * nsh + j of any momentum q, through the symmetry map
+__device__ __forceinline__ double exact_harmonic(const Batch& b, const DevTables& d, int q, int o) {
+  const int nsh = d.nsh, ch = o / nsh, j = o % nsh;
+  const int32_t pk = d.symmap[(size_t)q * nsh + j];
+  const double v = slot_harmonic(b, d, pk & 0xffff, ch * nsh + ((pk >> 16) & 0x7f));
+  return ((pk >> 24) & 1) ? -v : v;
 }
 
 // summed harmonics of point p: out[gh_off + q * 2 nsh + o]
@@ -93,12 +103,12 @@ __global__ void k_sur_dataset(Batch b, int npts, int64_t n, uint64_t seed, float
   }
 }
 
-// features of every query (q, j) of point p
+// features of every query (representative slot, j) of point p
 __global__ void k_sur_features(Batch b, int p, float* __restrict__ x) {
   const DevTables& d = b.pts[p];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)d.nq * d.nsh) return;
-  write_features(d, b.Tp[p], (int)(i / d.nsh), (int)(i % d.nsh), x + 9 * i);
+  if (i >= (int64_t)d.nirr * d.nsh) return;
+  write_features(d, b.Tp[p], d.irr[i / d.nsh], (int)(i % d.nsh), x + 9 * i);
 }
 
 __device__ __forceinline__ double block_max64(double v, double* red) {
@@ -113,8 +123,9 @@ __device__ __forceinline__ double block_max64(double v, double* red) {
   return r;
 }
 
-// one block of 64 threads per q: ensemble mean as the predicted harmonics,
-// disagreement test, and the momenta that take the exact kernel
+// one block of 64 threads per representative slot q: ensemble mean as the
+// predicted harmonics, disagreement test, and the momenta that take the
+// exact kernel
 __global__ void __launch_bounds__(64)
 k_sur_pred(Batch b, int p, const float* __restrict__ ya, const float* __restrict__ yb, SurState st) {
   __shared__ double red[64];
@@ -142,12 +153,13 @@ k_sur_pred(Batch b, int p, const float* __restrict__ ya, const float* __restrict
   }
 }
 
-// Items (p, q * nsplit + s) of the momenta that need the exact kernel, in
-// increasing q (one block, deterministic prefix sum); count = items.
+// Items (p, slot * nsplit + s) of the representatives that need the exact
+// kernel, in increasing slot (one block, deterministic prefix sum); count =
+// items.  Below, q always denotes a representative slot.
 __global__ void __launch_bounds__(1024) k_sur_compact(Batch b, int p, SurState st) {
   __shared__ int sums[1024];
   const DevTables& d = b.pts[p];
-  const int nq = d.nq, ns = d.nsplit;
+  const int nq = d.nirr, ns = d.nsplit;
   const int per = (nq + 1023) / 1024;
   const int q0 = threadIdx.x * per, q1 = min(nq, q0 + per);
   int c = 0;
@@ -186,7 +198,7 @@ __global__ void __launch_bounds__(64) k_sur_select(Batch b, int p, SurState st) 
     const size_t k = (size_t)q * nout + o;
     double v = st.pred[k];
     if (exact) {
-      const double e = exact_harmonic(b, d, q, o);
+      const double e = slot_harmonic(b, d, q, o);
       rmax = fmax(rmax, fabs(v - e));
       emax = fmax(emax, fabs(e));
       v = e;
@@ -203,41 +215,27 @@ __global__ void __launch_bounds__(64) k_sur_select(Batch b, int p, SurState st) 
   }
 }
 
-// fallback flags: checked momenta take their check result; a failure also
-// flags the 8 neighbours (periodic grid); then the check phase advances
+// fallback flags: checked representatives take their check result; a
+// failure also flags the representatives of the 8 grid neighbours (periodic
+// grid); then the check phase advances
 __global__ void k_sur_state(Batch b, int p, SurState st) {
   const DevTables& d = b.pts[p];
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= d.nq) return;
-  const int lq = d.lq, ix = q / lq, iy = q % lq;
-  const bool checked = q % st.stride == *st.phase;
-  int f = checked ? st.fail[q] : st.state[q];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= d.nirr) return;
+  const int lq = d.lq, q = d.irr[r], ix = q / lq, iy = q % lq;
+  const bool checked = r % st.stride == *st.phase;
+  int f = checked ? st.fail[r] : st.state[r];
   for (int dx = -1; dx <= 1; ++dx)
     for (int dy = -1; dy <= 1; ++dy) {
       if (dx == 0 && dy == 0) continue;
       const int nb = ((ix + dx + lq) % lq) * lq + (iy + dy + lq) % lq;
-      if (st.fail[nb]) f = 1;
+      if (st.fail[d.symmap[(size_t)nb * d.nsh] & 0xffff]) f = 1;
     }
-  st.state[q] = f;
+  st.state[r] = f;
 }
 
 __global__ void k_sur_advance(SurState st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *st.phase = (*st.phase + 1) % st.stride;
-}
-
-// chi'_mn(q) = sum_j Ebub_{mn,j} ghat(q, S_j), one block per q
-__global__ void __launch_bounds__(256)
-k_chi_from_ghat(Batch b, int p, const double* __restrict__ fin, double* __restrict__ dchi) {
-  const DevTables& d = b.pts[p];
-  const int q = blockIdx.x, nff2 = d.nff * d.nff, nsh = d.nsh;
-  for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
-    const int ch = w / nff2, mn = w % nff2;
-    const double* e = d.ebub + (size_t)mn * nsh;
-    const double* g = fin + ((size_t)q * 2 + ch) * nsh;
-    double v = 0.0;
-    for (int j = 0; j < nsh; ++j) v = fma(e[j], g[j], v);
-    dchi[(size_t)ch * b.S + d.off + (size_t)q * nff2 + mn] = v;
-  }
 }
 
 }  // namespace
@@ -258,23 +256,21 @@ void launch_sur_dataset(const Launch& L, int npts, int64_t n, uint64_t seed, flo
 }
 
 void launch_surrogate_front(const Launch& L, int p, const DevTables& d, float* x, hipStream_t s) {
-  const int64_t n = (int64_t)d.nq * d.nsh;
+  const int64_t n = (int64_t)d.nirr * d.nsh;
   hipLaunchKernelGGL(k_sur_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, L.b, p, x);
 }
 
 void launch_surrogate_decide(const Launch& L, int p, const DevTables& d, const float* ya, const float* yb,
                              const SurState& st, hipStream_t s) {
-  hipLaunchKernelGGL(k_sur_pred, dim3(d.nq), dim3(64), 0, s, L.b, p, ya, yb, st);
+  hipLaunchKernelGGL(k_sur_pred, dim3(d.nirr), dim3(64), 0, s, L.b, p, ya, yb, st);
   hipLaunchKernelGGL(k_sur_compact, dim3(1), dim3(1024), 0, s, L.b, p, st);
 }
 
-void launch_surrogate_finish(const Launch& L, int p, const DevTables& d, const SurState& st, double* dchi,
-                             hipStream_t s) {
+void launch_surrogate_finish(const Launch& L, int p, const DevTables& d, const SurState& st, hipStream_t s) {
   if (L.b.ghat == nullptr) return;
-  hipLaunchKernelGGL(k_sur_select, dim3(d.nq), dim3(64), 0, s, L.b, p, st);
-  hipLaunchKernelGGL(k_sur_state, dim3((d.nq + 255) / 256), dim3(256), 0, s, L.b, p, st);
+  hipLaunchKernelGGL(k_sur_select, dim3(d.nirr), dim3(64), 0, s, L.b, p, st);
+  hipLaunchKernelGGL(k_sur_state, dim3((d.nirr + 255) / 256), dim3(256), 0, s, L.b, p, st);
   hipLaunchKernelGGL(k_sur_advance, dim3(1), dim3(64), 0, s, st);
-  hipLaunchKernelGGL(k_chi_from_ghat, dim3(d.nq), dim3(256), 0, s, L.b, p, st.fin, dchi);
 }
 
 }  // namespace tufrg

@@ -85,7 +85,7 @@ int nff_of_shells(int shells) {
   return (shells >= 0 && shells <= 4) ? n[shells] : -1;
 }
 
-std::string build_tables(const tufrg_point& p, HostTables& t) {
+std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric) {
   char msg[256];
   if (!(p.t > 0.0) || !std::isfinite(p.t)) return "t must be finite and > 0";
   if (!std::isfinite(p.tp) || !std::isfinite(p.mu) || !std::isfinite(p.U))
@@ -106,6 +106,7 @@ std::string build_tables(const tufrg_point& p, HostTables& t) {
     return msg;
   }
   if ((int64_t)p.Lk * p.Lk > (int64_t)1 << 28) return "Lk too large";
+  if (p.Lq > 256) return "Lq must be <= 256";
   t.nq = p.Lq * p.Lq;
   t.lk = p.Lk;
   const int nff = t.nff;
@@ -184,6 +185,55 @@ std::string build_tables(const tufrg_point& p, HostTables& t) {
     if (neg) { sx = -sx; sy = -sy; }
     return half_index.at({sx, sy});
   };
+
+  // Point-group reduction of the transfer grid.  The dispersion and the
+  // unshifted fine grid are invariant under the 8 operations g of C4v, so the
+  // loop harmonics obey ghat(g q, g S) = ghat(q, S); shifting q by 2 pi e_x
+  // moves the fine grid by half a period and gives ghat(q + 2 pi e_x, S) =
+  // (-1)^{S_x} ghat(q, S) (Lk even).  Each q maps to the representative r of
+  // its orbit (smallest flat index) through an operation h with h q = r + G,
+  // G in {0, 2 pi}^2, so that ghat(q, S_j) = (-1)^{G.hS_j / 2 pi} ghat(r, +-h S_j)
+  // (ghat is even in S).  Without `symmetric` every q is its own representative.
+  {
+    static const int ops[8][4] = {{1, 0, 0, 1},  {-1, 0, 0, 1}, {1, 0, 0, -1}, {-1, 0, 0, -1},
+                                  {0, 1, 1, 0},  {0, -1, 1, 0}, {0, 1, -1, 0}, {0, -1, -1, 0}};
+    const int lq = p.Lq, half = lq / 2;
+    std::vector<int> rep(t.nq), op(t.nq), gx(t.nq), gy(t.nq);
+    for (int q = 0; q < t.nq; ++q) {
+      const int a = q / lq - half, b = q % lq - half;
+      int best = t.nq, bo = 0, bgx = 0, bgy = 0;
+      for (int o = 0; o < (symmetric ? 8 : 1); ++o) {
+        int a2 = ops[o][0] * a + ops[o][1] * b, b2 = ops[o][2] * a + ops[o][3] * b;
+        int sx = 0, sy = 0;
+        if (a2 >= half) { a2 -= lq; sx = 1; }     // components lie in [-half, half]
+        if (b2 >= half) { b2 -= lq; sy = 1; }
+        const int f = (a2 + half) * lq + (b2 + half);
+        if (f < best) { best = f; bo = o; bgx = sx; bgy = sy; }
+      }
+      rep[q] = best; op[q] = bo; gx[q] = bgx; gy[q] = bgy;
+    }
+    std::vector<int> slot_of(t.nq, -1);
+    t.irr.clear();
+    for (int q = 0; q < t.nq; ++q)
+      if (rep[q] == q) {
+        slot_of[q] = (int)t.irr.size();
+        t.irr.push_back(q);
+      }
+    t.nirr = (int)t.irr.size();
+    t.symmap.assign((size_t)t.nq * t.nsh, 0);
+    for (int q = 0; q < t.nq; ++q) {
+      const int* m = ops[op[q]];
+      const int slot = slot_of[rep[q]];
+      if (slot < 0) return "internal error: orbit representative";
+      for (int j = 0; j < t.nsh; ++j) {
+        const int s2x = m[0] * t.hx[j] + m[1] * t.hy[j], s2y = m[2] * t.hx[j] + m[3] * t.hy[j];
+        int conj;
+        const int j2 = half_of(s2x, s2y, &conj);
+        const int neg = (gx[q] * s2x + gy[q] * s2y) & 1;
+        t.symmap[(size_t)q * t.nsh + j] = pack_sym(slot, j2, neg);
+      }
+    }
+  }
 
   // loop epilogue: chi_mn = sum_{A,B} c_mA c_nB ghat(A+B), ghat even in S
   t.ebub.assign((size_t)nff * nff * t.nsh, 0.0);
@@ -332,12 +382,14 @@ std::string build_tables(const tufrg_point& p, HostTables& t) {
   // harmonic multiply-adds; per transfer momentum the contraction over px
   // (2 N_S' outputs x Lk columns x 2 multiply-adds) and the form-factor
   // epilogue (2 nff^2 N_S' multiply-adds).
+  // With the point-group reduction only the representatives of the transfer
+  // momenta are integrated; the epilogue runs for every momentum.
   const double nq = t.nq, f2 = (double)nff * nff, f3 = f2 * nff;
-  const double pairs = nq * (double)lk * (lk / 2 + 1);
+  const double pairs = (double)t.nirr * (double)lk * (lk / 2 + 1);
   const double c_pair = 162.0;
   const double c_acc = 2.0 * 2.0 * (2 * t.smax + 1);
-  t.flops_loops = (int64_t)(pairs * (c_pair + c_acc) +
-                            nq * (2.0 * t.nsh * lk * 4.0 + 2.0 * 2.0 * f2 * t.nsh));
+  t.flops_loops = (int64_t)(pairs * (c_pair + c_acc) + (double)t.nirr * 2.0 * t.nsh * lk * 4.0 +
+                            nq * 2.0 * 2.0 * f2 * t.nsh);
   // forward and inverse transforms (2 flops per real multiply-add), the bond
   // basis change of the transformed propagators and the gathered sums
   double bb = 0.0;

@@ -34,6 +34,11 @@ struct HostTables {
   // (representatives with Sx > 0 or Sx == 0 && Sy >= 0; Hh[0] = (0,0))
   std::vector<int> hx, hy;        // half set [nsh]
   std::vector<int32_t> pairs;     // canonical bond pair of each half-set harmonic [nsh][4]
+  // point-group reduction: representatives of the transfer momenta and, per
+  // (q, harmonic j), the representative's slot, harmonic and sign (pack_sym)
+  int nirr = 0;
+  std::vector<int32_t> irr;       // [nirr] flat q of each representative (increasing)
+  std::vector<int32_t> symmap;    // [nq][nsh]
   int nsh = 0;                    // N_S' = (N_S + 1)/2
   int ncol = 0;                   // 2 nsh - 1 real harmonic columns (cos, then sin without 0)
   // loops: chi_mn = sum_j Ebub[mn*nsh + j] ghat(S'_j)
@@ -61,7 +66,10 @@ inline int32_t pack_entry(int in, int b1, int b2, int v, int neg) {
   return in | (b1 << 2) | (b2 << 7) | (v << 12) | (neg << 19);
 }
 
-std::string build_tables(const tufrg_point& p, HostTables& t);   // "" on success
+// symmetry map entry: representative slot (16 bits), harmonic (7 bits), sign (1 bit)
+inline int32_t pack_sym(int slot, int j, int neg) { return slot | (j << 16) | (neg << 24); }
+
+std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric);   // "" on success
 int nff_of_shells(int shells);
 
 // ---------------------------------------------------------- device side
@@ -74,12 +82,12 @@ struct DevTables {
   int nff, nq, lq, lk, nsh, ncol, smax, nshell;
   int nsplit, nchunk;     // loop geometry: row slices per momentum, row chunks per column
   int lt;                 // momenta per block of the FP64 back end
-  int pad;
+  int nirr;               // representatives of the transfer momenta (point-group orbits)
   double t, tp, mu, U;
   int64_t off;            // element offset of the point inside one channel of [3][S] / [2][S]
-  int64_t ws_xt, ws_yb, ws_g2, ws_dpart, ws_k;   // element offsets into the shared workspace
-  int64_t ws_gh;          // offset of the point's loop-harmonic slices [nsplit][nq][2][nsh]
-  int64_t gh_off;         // offset of the point's summed harmonics [nq][2][nsh]
+  int64_t ws_xt, ws_yb, ws_g2, ws_k;   // element offsets into the shared workspace
+  int64_t ws_gh;          // offset of the point's loop-harmonic slices [nsplit][nirr][2][nsh]
+  int64_t gh_off;         // offset of the point's harmonics [nq][2][nsh] in harmonic outputs
   double* cre;            // [nff*nff]
   double* cim;
   int* shell_start;       // [nshell+1]
@@ -96,6 +104,8 @@ struct DevTables {
   int32_t* hx;            // half set [nsh]
   int32_t* hy;
   int32_t* pairs;         // canonical bond pairs [nsh][4]
+  int32_t* irr;           // [nirr] flat q of each representative
+  int32_t* symmap;        // [nq][nsh] pack_sym(slot, harmonic, sign)
 };
 
 // Kernel-side view of one launch: tables, temperatures, stop flags, workspace.
@@ -105,14 +115,12 @@ struct Batch {
   const double* Tp;       // per-point temperatures (device)
   const int* frozen;      // per-point stop flags (device) or null
   double* dchi;           // loops [2][S]
-  double* dpart;          // loop slices
   double* xt;             // forward transforms
   double* yb;             // bond-basis transforms
   double* g2;             // inverse-transform coefficients
   float* kinv;            // inverse transforms (mixed precision)
-  double* ghat;           // loops: when set, write the loop harmonics here instead of chi'
+  double* ghat;           // loop-harmonic slices (all points, at ws_gh)
   const int* item_count;  // loops: when set, only the first *item_count items run
-  int chi_final;          // back ends: chi' is complete in dchi (no slices to add)
 };
 
 struct ItemRange {
@@ -121,14 +129,14 @@ struct ItemRange {
 
 // Item ranges of one launch set (all points, or one point)
 struct Ranges {
-  ItemRange loop, chi, fwd, fwd_mfma, basis, gather, inv_mfma, back, prod, seg;
+  ItemRange loop, exp, fwd, fwd_mfma, basis, gather, inv_mfma, back, prod, seg;
 };
 
 // Device item tables and launch shapes shared by all launches of a context.
 struct Launch {
   Batch b;
   const int4* loop_items;
-  const int4* chi_items;
+  const int4* exp_items;
   const int4* fwd_items;
   const int4* fwd_mfma_items;
   const int4* basis_items;
@@ -147,18 +155,22 @@ struct SurState {
   double tol;                 // relative tolerance of the ensemble and residual checks
   int stride;                 // one momentum in `stride` is checked per call, rotating
   int* phase;                 // [1] current check phase
-  int* state;                 // [nq] fallback flags
-  int* need;                  // [nq] exact kernel this call
-  int* fail;                  // [nq] failed check this call
-  double* pred;               // [nq][2][nsh] predicted harmonics
-  double* fin;                // [nq][2][nsh] harmonics used this call
-  int4* items;                // [nq * nsplit] loop items of the exact momenta
+  int* state;                 // [nirr] fallback flags of the representatives
+  int* need;                  // [nirr] exact kernel this call
+  int* fail;                  // [nirr] failed check this call
+  double* pred;               // [nirr][2][nsh] predicted harmonics
+  double* fin;                // [nirr][2][nsh] harmonics used this call
+  int4* items;                // [nirr * nsplit] loop items of the exact representatives
   int* count;                 // [1] number of those items
-  unsigned long long* stats;  // [3] exact momenta, momenta, failed checks (cumulative)
+  unsigned long long* stats;  // [3] exact, queried representatives, failed checks (cumulative)
 };
 
 void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, hipStream_t s);
-void launch_chi_sum(const Launch& L, const ItemRange& r, double* dchi, hipStream_t s);
+// chi' of every momentum from the loop harmonics of the representatives:
+// from the slices in b.ghat (fin == null), or from fin [nirr][2][nsh] of a
+// single-point context
+void launch_chi_expand(const Launch& L, const ItemRange& r, const double* fin, double* dchi,
+                       hipStream_t s);
 void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s);
 void launch_back(const Launch& L, const Ranges& r, const double* X, double* out, int mode,
                  bool cross, bool scale_T, bool mixed, hipStream_t s);
@@ -183,8 +195,7 @@ void launch_sur_dataset(const Launch& L, int npts, int64_t n, uint64_t seed, flo
 void launch_surrogate_front(const Launch& L, int p, const DevTables& d, float* x, hipStream_t s);
 void launch_surrogate_decide(const Launch& L, int p, const DevTables& d, const float* ya, const float* yb,
                              const SurState& st, hipStream_t s);
-void launch_surrogate_finish(const Launch& L, int p, const DevTables& d, const SurState& st, double* dchi,
-                             hipStream_t s);
+void launch_surrogate_finish(const Launch& L, int p, const DevTables& d, const SurState& st, hipStream_t s);
 // forward pass of an MLP on stream s (rows in chunks of the net's max_rows)
 void mlp_forward_on(tufrg_mlp* net, const float* x, float* y, int64_t rows, hipStream_t s);
 int mlp_width(const tufrg_mlp* net, int i);   // widths[i]; i = -1: the last
@@ -222,7 +233,7 @@ struct tufrg_ctx {
   int* step = nullptr;                     // device step counter
   int ttab_cap = 0;
   bool loop_persistent = false;            // launch form of the loop kernel
-  double* ghat = nullptr;                  // loop-harmonic slices (first harmonics call)
+  double* ghat = nullptr;                  // loop-harmonic slices of the representatives
   int64_t ghat_len = 0, ghat_sum_len = 0;  // slice and summed lengths over all points
   // attached surrogate (single-point contexts)
   tufrg_mlp* sur_a = nullptr;

@@ -116,6 +116,25 @@ def cfg5() -> Workload:
                     Xmax=20.0, scheme="rk4", nsteps=200)
 
 
+def surrogate_training_points(npoints: int = 64) -> List[Point]:
+    """Seeded (t', mu) draws over the cfg2-cfg3 parameter ranges on the cfg5
+    grids (N_ff = 21, 64x64 transfer, 160x160 fine), for surrogate labels."""
+    rng = np.random.default_rng(BASE_SEED + 5)
+    pts = []
+    for _ in range(npoints):
+        tp = float(rng.uniform(-0.35, -0.2))
+        mu = float(rng.uniform(-1.2, 0.0))
+        pts.append(Point(t=1.0, tp=tp, U=3.0, Lq=64, Lk=160, shells=4, mu=mu))
+    return pts
+
+
+def surrogate_training_temperatures(npoints: int, rounds: int, seed: int = BASE_SEED + 55,
+                                    lo: float = 0.01, hi: float = 10.0) -> np.ndarray:
+    """[rounds][npoints] log-uniform temperatures of the flow range."""
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), (rounds, npoints)))
+
+
 def small_point(Lq=6, Lk=12, shells=1, t=1.0, tp=-0.2, mu=-0.3, U=2.5) -> Point:
     return Point(t=t, tp=tp, U=U, Lq=Lq, Lk=Lk, shells=shells, mu=mu)
 

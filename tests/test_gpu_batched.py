@@ -96,6 +96,24 @@ def test_loop_queue_form_identical(tf, precision):
         assert torch.equal(a.rhs(Ts, _pack(a, Xs)), b.rhs(Ts, _pack(b, Xs)))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_point_group_reduction_matches_full_grid(tf, precision):
+    """Loops on one representative per C4v orbit equal the loops at every
+    transfer momentum: 1e-12 normwise in FP64 (summation order only); in
+    mixed precision the two sides round their FP32 sums independently, so
+    twice the mixed loop bound of 2e-6."""
+    torch = _torch()
+    print(f"[batch] point-group reduction, {precision}", flush=True)
+    full = tf.Context(BATCH, precision=precision, no_symmetry=True)
+    red = tf.Context(BATCH, precision=precision)
+    Ts = [0.4, 0.05, 2.0, 0.011, 0.13, 0.9]
+    a, b = full.bubbles(Ts).cpu().numpy(), red.bubbles(Ts).cpu().numpy()
+    tol = 1e-12 if precision == "fp64" else 4e-6
+    for i in range(len(BATCH)):
+        _normwise(red.view(torch.from_numpy(b), i).numpy(), full.view(torch.from_numpy(a), i).numpy(), tol,
+                  f"pt{i}")
+
+
 def _flow_opts(tf, graph, nsteps=80):
     return tf.FlowOptions(T0=10.0, Tmin=0.01, Xmax=20.0, scheme="rk4", nsteps=nsteps, use_graph=graph)
 

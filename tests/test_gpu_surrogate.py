@@ -37,6 +37,22 @@ def _pt(shells, Lq, Lk, tp=-0.27, mu=-0.61, U=3.0):
     return synth.Point(t=1.0, tp=tp, U=U, Lq=Lq, Lk=Lk, shells=shells, mu=mu)
 
 
+def _orbits(Lq):
+    """Number of C4v orbits of the Lq x Lq transfer grid modulo the reciprocal
+    lattice (the surrogate works on one representative per orbit)."""
+    seen, n = set(), 0
+    for a in range(Lq):
+        for b in range(Lq):
+            if (a, b) in seen:
+                continue
+            n += 1
+            for x, y in ((a, b), (b, a)):
+                for sx in (1, -1):
+                    for sy in (1, -1):
+                        seen.add(((sx * x) % Lq, (sy * y) % Lq))
+    return n
+
+
 @pytest.mark.parametrize("shells,Lq,Lk", [(0, 6, 12), (1, 6, 14), (2, 8, 16), (3, 10, 20), (4, 10, 22)])
 def test_loop_harmonics_vs_oracle(tf, shells, Lq, Lk):
     pt = _pt(shells, Lq, Lk)
@@ -158,7 +174,7 @@ def test_surrogate_disagreeing_nets_fall_back_everywhere(tf):
         gb = ctx.bubbles(T).cpu().numpy()
         assert np.abs(gb - rb).max() <= 1e-12 * np.abs(rb).max()
     st = ctx.surrogate_stats()
-    assert st["exact_q"] == st["queried_q"] == 4 * pt.nq
+    assert st["exact_q"] == st["queried_q"] == 4 * _orbits(pt.Lq)
     ctx.detach_surrogate()
     assert torch.equal(ctx.bubbles(0.3), exact.bubbles(0.3))
 
@@ -178,12 +194,12 @@ def test_surrogate_rotating_check_flags_bad_predictions(tf):
     for _ in range(stride):
         ctx.bubbles(T)
     st = ctx.surrogate_stats()
-    assert st["failed_checks"] == pt.nq            # every momentum checked once, all failed
+    assert st["failed_checks"] == _orbits(pt.Lq)   # every representative checked once, all failed
     ref = exact.bubbles(T).cpu().numpy()
     got = ctx.bubbles(T).cpu().numpy()
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
     st2 = ctx.surrogate_stats()
-    assert st2["exact_q"] - st["exact_q"] == pt.nq
+    assert st2["exact_q"] - st["exact_q"] == _orbits(pt.Lq)
 
 
 def test_surrogate_flow_graph_equals_exact(tf):
