@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <numeric>
 #include <string>
@@ -130,7 +131,7 @@ void default_geometry(DevTables& d) {
 
 // ------------------------------------------------------------ item tables
 struct HostItems {
-  std::vector<int4> loop, exp, fwd, fwd_mfma, basis, gather, inv_mfma, back, prod, seg;
+  std::vector<int4> loop, exp, fwd, xtr, fwd_mfma, basis, gather, inv, inv_mfma, prod, seg;
 };
 
 template <class F>
@@ -145,11 +146,19 @@ void mark(std::vector<int4>& v, ItemRange& rg, F fill) {
 void add_point_items(const DevTables& d, int p, HostItems& h, Ranges& r) {
   const int nff2 = d.nff * d.nff, nv = 2 * d.nsh - 1;
   mark(h.exp, r.exp, [&](std::vector<int4>& v) {
-    for (int q = 0; q < d.nq; ++q) v.push_back(make_int4(p, q, 0, 0));
+    for (int rt = 0; rt < (2 * d.nq + 31) / 32; ++rt)
+      for (int ct = 0; ct < (nff2 + 63) / 64; ++ct) v.push_back(make_int4(p, rt, ct, 0));
   });
   mark(h.fwd, r.fwd, [&](std::vector<int4>& v) {
-    for (int c = 0; c < (3 * nff2 + 63) / 64; ++c)
-      for (int k = 0; k < (d.ncol + 3) / 4; ++k) v.push_back(make_int4(p, c, k, 0));
+    for (int sp = 0; sp < d.nsu; ++sp)
+      for (int c = 0; c < (3 * nff2 + 63) / 64; ++c) v.push_back(make_int4(p, c, sp, 0));
+  });
+  mark(h.xtr, r.xtr, [&](std::vector<int4>& v) {
+    for (int b = 0; b < (d.ncol * 3 * nff2 + 255) / 256; ++b) v.push_back(make_int4(p, b, 0, 0));
+  });
+  mark(h.inv, r.inv, [&](std::vector<int4>& v) {
+    for (int lt = 0; lt < (d.nq + 31) / 32; ++lt)
+      for (int c = 0; c < (3 * nff2 + 63) / 64; ++c) v.push_back(make_int4(p, lt, c, 0));
   });
   mark(h.fwd_mfma, r.fwd_mfma, [&](std::vector<int4>& v) {
     for (int m = 0; m < (d.ncol + 15) / 16; ++m)
@@ -165,9 +174,6 @@ void add_point_items(const DevTables& d, int p, HostItems& h, Ranges& r) {
   mark(h.inv_mfma, r.inv_mfma, [&](std::vector<int4>& v) {
     for (int m = 0; m < (d.nq + 15) / 16; ++m)
       for (int n = 0; n < (3 * nff2 + 63) / 64; ++n) v.push_back(make_int4(p, m, n, 0));
-  });
-  mark(h.back, r.back, [&](std::vector<int4>& v) {
-    for (int l0 = 0; l0 < d.nq; l0 += d.lt) v.push_back(make_int4(p, l0, std::min(d.lt, d.nq - l0), 0));
   });
   mark(h.prod, r.prod, [&](std::vector<int4>& v) {
     for (int l = 0; l < d.nq; ++l) v.push_back(make_int4(p, l, 0, 0));
@@ -213,7 +219,8 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   for (int p : order) add_loop_items(ctx->dev[p], p, h.loop, ctx->per_point[p].loop);
   for (int p = 0; p < npts; ++p) add_point_items(ctx->dev[p], p, h, ctx->per_point[p]);
   int smax_max = 0, threads = 64;
-  size_t lsm = 0, gsm = 0, bsm = 0, psm = 0;
+  size_t lsm = 0, gsm = 0, psm = 0;
+  int kpt = 4;
   int64_t gh = 0, ghs = 0;
   for (int p = 0; p < npts; ++p) {
     DevTables& d = ctx->dev[p];
@@ -221,9 +228,8 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
     threads = std::max(threads, round64(d.lk * d.nchunk));
     const int nff2 = d.nff * d.nff;
     gsm = std::max(gsm, sizeof(double) * 4 * (size_t)nff2);
-    bsm = std::max(bsm, sizeof(double) * ((size_t)d.lt * d.ncol + (size_t)d.lt * 3 * nff2 +
-                                          9 * (size_t)nff2));
-    psm = std::max(psm, sizeof(float) * 12 * (size_t)nff2);
+    psm = std::max(psm, sizeof(double) * 12 * (size_t)nff2);
+    kpt = std::max(kpt, (d.ncol + 3) / 4);
     d.ws_gh = gh;
     gh += (int64_t)d.nsplit * d.nirr * 2 * d.nsh;
     d.gh_off = ghs;
@@ -234,7 +240,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   for (int p = 0; p < npts; ++p) lsm = std::max(lsm, loop_smem_of(ctx->dev[p], threads));
   int dev_smem = 0;
   hipDeviceGetAttribute(&dev_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
-  if (dev_smem > 0 && (lsm > (size_t)dev_smem || bsm > (size_t)dev_smem))
+  if (dev_smem > 0 && (lsm > (size_t)dev_smem || psm > (size_t)dev_smem))
     return fail(ctx, TUFRG_EINVAL, "grids too large for the shared memory of one block");
   auto whole = [](const std::vector<int4>& v) {
     ItemRange r;
@@ -242,9 +248,9 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
     return r;
   };
   Ranges& all = ctx->all;
-  all.loop = whole(h.loop); all.exp = whole(h.exp); all.fwd = whole(h.fwd);
+  all.loop = whole(h.loop); all.exp = whole(h.exp); all.fwd = whole(h.fwd); all.xtr = whole(h.xtr);
   all.fwd_mfma = whole(h.fwd_mfma); all.basis = whole(h.basis); all.gather = whole(h.gather);
-  all.inv_mfma = whole(h.inv_mfma); all.back = whole(h.back); all.prod = whole(h.prod);
+  all.inv = whole(h.inv); all.inv_mfma = whole(h.inv_mfma); all.prod = whole(h.prod);
   all.seg = whole(h.seg);
   Launch& L = ctx->L;
   std::vector<void*>& g = ctx->geometry_allocations;
@@ -252,11 +258,12 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   ST_TRY(upload(ctx, h.loop, &t, g)); L.loop_items = t;
   ST_TRY(upload(ctx, h.exp, &t, g)); L.exp_items = t;
   ST_TRY(upload(ctx, h.fwd, &t, g)); L.fwd_items = t;
+  ST_TRY(upload(ctx, h.xtr, &t, g)); L.xtr_items = t;
+  ST_TRY(upload(ctx, h.inv, &t, g)); L.inv_items = t;
   ST_TRY(upload(ctx, h.fwd_mfma, &t, g)); L.fwd_mfma_items = t;
   ST_TRY(upload(ctx, h.basis, &t, g)); L.basis_items = t;
   ST_TRY(upload(ctx, h.gather, &t, g)); L.gather_items = t;
   ST_TRY(upload(ctx, h.inv_mfma, &t, g)); L.inv_mfma_items = t;
-  ST_TRY(upload(ctx, h.back, &t, g)); L.back_items = t;
   ST_TRY(upload(ctx, h.prod, &t, g)); L.prod_items = t;
   ST_TRY(upload(ctx, h.seg, &t, g)); L.seg_items = t;
   ST_TRY(dalloc(ctx, (size_t)std::max<int64_t>(gh, 1), &L.b.ghat, g));
@@ -271,8 +278,8 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   L.loop_threads = threads;
   L.loop_smem = lsm;
   L.gather_smem = gsm;
-  L.back_smem = bsm;
   L.prod_smem = psm;
+  L.fwd_kpt = kpt <= 4 ? 4 : (kpt <= 8 ? 8 : (kpt <= 12 ? 12 : 18));
   // persistent loop grid: every CU filled to the kernel's occupancy
   int per_cu = 0, cus = 0;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
@@ -321,11 +328,14 @@ void loops_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, double* dchi
   launch_chi_expand(L, r.exp, nullptr, dchi, s);
 }
 
+// The temperatures are set by set_T on the side stream, ahead of the loops
+// and off the projections' path; the back end reads them after the join.
 void rhs_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, const double* X, double* out,
-                bool scale_T, hipStream_t ms) {
+                bool scale_T, hipStream_t ms, const std::function<void(hipStream_t)>& set_T) {
   const bool mixed = mixed_of(ctx), cross = cross_of(ctx);
   hipEventRecord(ctx->ev_fork, ms);
   hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+  set_T(ctx->side);
   loops_launch(ctx, L, r, L.b.dchi, ctx->side);
   hipEventRecord(ctx->ev_join, ctx->side);
   if (cross) launch_front(L, r, X, mixed, ms);
@@ -472,7 +482,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   ctx->host.resize(npts);
   ctx->off.resize(npts);
   ctx->dev.assign(npts, DevTables());
-  int64_t S = 0, ws_xt = 0, ws_yb = 0, ws_g2 = 0, ws_k = 0;
+  int64_t S = 0, ws_xt = 0, ws_yb = 0, ws_g2 = 0, ws_k = 0, ws_xp = 0;
   for (int p = 0; p < npts; ++p) {
     std::string e = build_tables(pts[p], ctx->host[p], !(o.flags & TUFRG_NO_SYMMETRY));
     if (e.empty() && ctx->host[p].lk > kLoopThreadsMax)
@@ -488,14 +498,11 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     d.smax = t.smax; d.nshell = t.nshell; d.nirr = t.nirr;
     d.t = t.p.t; d.tp = t.p.tp; d.mu = t.p.mu; d.U = t.p.U;
     default_geometry(d);
-    // momenta per block of the FP64 back end: 2 on large grids while its LDS
-    // stays within 64 KiB
+    // splits of the transfer grid in the FP64 forward transform: about 512
+    // work items per point, at least 16 momenta per split
     const int nff2 = t.nff * t.nff;
-    auto back_bytes = [&](int l) {
-      return sizeof(double) * ((size_t)l * t.ncol + (size_t)l * 3 * nff2 + 9 * (size_t)nff2);
-    };
-    d.lt = t.nq >= 1024 ? 2 : 1;
-    while (d.lt > 1 && back_bytes(d.lt) > 65536) --d.lt;
+    const int ctiles = (3 * nff2 + 63) / 64;
+    d.nsu = std::max(1, std::min(512 / ctiles, t.nq / 16));
     d.off = S;
     ctx->off[p] = S;
     S += (int64_t)t.nq * nff2;
@@ -507,6 +514,8 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     ws_yb += (int64_t)2 * 3 * (2 * t.nsh - 1) * nff2;
     d.ws_k = ws_k;
     ws_k += (int64_t)3 * t.nq * nff2;
+    d.ws_xp = ws_xp;
+    ws_xp += (int64_t)d.nsu * t.ncol * 3 * nff2;
   }
   ctx->S = S;
   // first device call: every argument has been validated
@@ -535,11 +544,15 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     std::vector<int32_t> hx(t.hx.begin(), t.hx.end()), hy(t.hy.begin(), t.hy.end());
     std::vector<unsigned short> ehi, elo;
     split_table(t.eph, ehi, elo);
+    std::vector<double> ephp((size_t)t.nq * kEpad, 0.0);
+    for (int u = 0; u < t.nq; ++u)
+      for (int k = 0; k < t.ncol; ++k) ephp[(size_t)u * kEpad + k] = t.eph[(size_t)u * t.ncol + k];
     tufrg_status st;
     if ((st = upload(ctx, cre, &d.cre, A)) || (st = upload(ctx, cim, &d.cim, A)) ||
         (st = upload(ctx, ss, &d.shell_start, A)) || (st = upload(ctx, so, &d.shell_of, A)) ||
         (st = upload(ctx, t.ebub, &d.ebub, A)) || (st = upload(ctx, t.pxtab, &d.pxtab, A)) ||
         (st = upload(ctx, t.pytab, &d.pytab, A)) || (st = upload(ctx, t.eph, &d.eph, A)) ||
+        (st = upload(ctx, ephp, &d.ephp, A)) ||
         (st = upload(ctx, t.cshift, &d.cshift, A)) || (st = upload(ctx, ehi, &d.eph_hi, A)) ||
         (st = upload(ctx, elo, &d.eph_lo, A)) || (st = upload(ctx, t.mrow, &d.mrow, A)) ||
         (st = upload(ctx, t.ment, &d.ment, A)) || (st = upload(ctx, hx, &d.hx, A)) ||
@@ -556,6 +569,8 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   if (!st) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_g2, 1), &B.g2, A);
   B.kinv = nullptr;
   if (!st && o.precision == TUFRG_MIXED) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_k, 1), &B.kinv, A);
+  if (!st && o.precision != TUFRG_MIXED) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_k, 1), &B.kinv64, A);
+  if (!st && o.precision != TUFRG_MIXED) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_xp, 1), &B.xp, A);
   if (!st) st = dalloc(ctx, (size_t)npts, &ctx->Tp, A);
   if (!st) st = dalloc(ctx, (size_t)npts, &ctx->frozen, A);
   if (!st) st = dalloc(ctx, 2, &ctx->queue, A);
@@ -633,8 +648,9 @@ tufrg_status tufrg_rhs(tufrg_ctx* ctx, const double* T_host, const double* X, do
   if (!T_host || !X || !dXdT) return fail(ctx, TUFRG_EINVAL, "NULL argument");
   if (X == dXdT) return fail(ctx, TUFRG_EINVAL, "X and dXdT must not alias");
   ST_TRY(check_temperatures(ctx, T_host));
-  launch_set_T_values(ctx->Tp, T_host, (int)ctx->dev.size(), ctx->stream);
-  rhs_launch(ctx, ctx->L, ctx->all, X, dXdT, false, ctx->stream);
+  const int npts = (int)ctx->dev.size();
+  rhs_launch(ctx, ctx->L, ctx->all, X, dXdT, false, ctx->stream,
+             [&](hipStream_t s) { launch_set_T_values(ctx->Tp, T_host, npts, s); });
   HIP_TRY(ctx, hipGetLastError());
   return TUFRG_OK;
 }
@@ -874,17 +890,16 @@ void rk4_step(tufrg_ctx* ctx, const Launch& L, double* X, double h, double xmax,
   const double half[1] = {0.5}, one[1] = {1.0};
   const double fin[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
   const Ranges& r = ctx->all;
-  launch_set_T(ctx->Tp, npts, ctx->Ttab, ctx->step, 0, ms);
-  rhs_launch(ctx, L, r, X, k[0], true, ms);
+  auto stage_T = [&](int stage) {
+    return [=](hipStream_t s) { launch_set_T(ctx->Tp, npts, ctx->Ttab, ctx->step, stage, s); };
+  };
+  rhs_launch(ctx, L, r, X, k[0], true, ms, stage_T(0));
   launch_axpy(L, r.seg, X, &k[0], half, 1, h, ctx->stage, true, ms);
-  launch_set_T(ctx->Tp, npts, ctx->Ttab, ctx->step, 1, ms);
-  rhs_launch(ctx, L, r, ctx->stage, k[1], true, ms);
+  rhs_launch(ctx, L, r, ctx->stage, k[1], true, ms, stage_T(1));
   launch_axpy(L, r.seg, X, &k[1], half, 1, h, ctx->stage, true, ms);
-  launch_set_T(ctx->Tp, npts, ctx->Ttab, ctx->step, 2, ms);
-  rhs_launch(ctx, L, r, ctx->stage, k[2], true, ms);
+  rhs_launch(ctx, L, r, ctx->stage, k[2], true, ms, stage_T(2));
   launch_axpy(L, r.seg, X, &k[2], one, 1, h, ctx->stage, true, ms);
-  launch_set_T(ctx->Tp, npts, ctx->Ttab, ctx->step, 3, ms);
-  rhs_launch(ctx, L, r, ctx->stage, k[3], true, ms);
+  rhs_launch(ctx, L, r, ctx->stage, k[3], true, ms, stage_T(3));
   launch_axpy(L, r.seg, X, k, fin, 4, h, X, true, ms);
   launch_maxabs(L, r.seg, X, ctx->umax, ms);
   launch_step_end(ctx->umax, npts, ctx->frozen, ctx->hist, ctx->step, nsteps, xmax, ms);
@@ -1010,8 +1025,8 @@ const double kDpB4[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640, -9209
 
 // dX/ds of point p alone at temperature T
 void rhs_point(tufrg_ctx* ctx, int p, double T, const double* X, double* out) {
-  launch_set_T_values(ctx->Tp + p, &T, 1, ctx->stream);
-  rhs_launch(ctx, ctx->L, ctx->per_point[p], X, out, true, ctx->stream);
+  rhs_launch(ctx, ctx->L, ctx->per_point[p], X, out, true, ctx->stream,
+             [&](hipStream_t s) { launch_set_T_values(ctx->Tp + p, &T, 1, s); });
 }
 
 tufrg_status maxabs_point(tufrg_ctx* ctx, int p, const double* X, double* result) {

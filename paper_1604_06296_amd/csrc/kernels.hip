@@ -263,98 +263,126 @@ k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ q
 
 // chi'_mn(q) = sum_j Ebub_{mn,j} ghat(q, S_j) for every momentum, with
 // ghat(q, S_j) = sign ghat(r, S_j') of its representative (pack_sym entry of
-// the symmetry map); item (p, q).  The representative's harmonics are the sum
-// of its loop slices, or come from fin [nirr][2][nsh] (single point).
+// the symmetry map), as one contraction over j: rows (channel, q), columns
+// mn.  Item (p, row tile of 32, column tile of 64); the representatives'
+// harmonics are the sums of their loop slices, or come from fin
+// [nirr][2][nsh] (single point).  Each thread owns 2 rows x 4 columns.
+constexpr int kExpRows = 32, kExpCols = 64, kExpK = 36;
 __global__ void __launch_bounds__(256)
 k_chi_expand(Batch b, const int4* __restrict__ items, const double* __restrict__ fin,
              double* __restrict__ dchi) {
-  __shared__ double g[2 * 64];
+  __shared__ double As[kExpRows][kExpK];
+  __shared__ double Bs[kExpK][kExpCols];
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
-  const int q = item.y, nsh = d.nsh, nout = 2 * nsh, nff2 = d.nff * d.nff;
-  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
-    const int ch = o / nsh, j = o % nsh;
-    const int32_t pk = d.symmap[(size_t)q * nsh + j];
-    const int slot = pk & 0xffff, j2 = (pk >> 16) & 0x7f;
-    const int oo = ch * nsh + j2;
+  const int nq = d.nq, nsh = d.nsh, nout = 2 * nsh, nff2 = d.nff * d.nff;
+  const int r0 = item.y * kExpRows, c0 = item.z * kExpCols;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kExpRows * nsh; e += 256) {
+    const int rr = e / nsh, j = e % nsh, row = r0 + rr;
     double v = 0.0;
-    if (fin) {
-      v = fin[(size_t)slot * nout + oo];
-    } else {
-      for (int s = 0; s < d.nsplit; ++s) v += b.ghat[d.ws_gh + ((size_t)s * d.nirr + slot) * nout + oo];
+    if (row < 2 * nq) {
+      const int ch = row / nq, q = row % nq;
+      const int32_t pk = d.symmap[(size_t)q * nsh + j];
+      const int slot = pk & 0xffff, oo = ch * nsh + ((pk >> 16) & 0x7f);
+      if (fin) {
+        v = fin[(size_t)slot * nout + oo];
+      } else {
+        for (int sl = 0; sl < d.nsplit; ++sl) v += b.ghat[d.ws_gh + ((size_t)sl * d.nirr + slot) * nout + oo];
+      }
+      if ((pk >> 24) & 1) v = -v;
     }
-    g[o] = ((pk >> 24) & 1) ? -v : v;
+    As[rr][j] = v;
+  }
+  for (int e = tid; e < nsh * kExpCols; e += 256) {
+    const int j = e / kExpCols, c = e % kExpCols, mn = c0 + c;
+    Bs[j][c] = mn < nff2 ? d.ebub[(size_t)mn * nsh + j] : 0.0;
   }
   __syncthreads();
-  for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
-    const int ch = w / nff2, mn = w % nff2;
-    const double* e = d.ebub + (size_t)mn * nsh;
-    const double* gc = g + ch * nsh;
-    double v = 0.0;
-    for (int j = 0; j < nsh; ++j) v = fma(e[j], gc[j], v);
-    dchi[(size_t)ch * b.S + d.off + (size_t)q * nff2 + mn] = v;
+  const int rr = 2 * (tid >> 4), cc = 4 * (tid & 15);
+  double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  for (int j = 0; j < nsh; ++j) {
+    const double a0 = As[rr][j], a1 = As[rr + 1][j];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double bv = Bs[j][cc + c];
+      acc[0][c] = fma(a0, bv, acc[0][c]);
+      acc[1][c] = fma(a1, bv, acc[1][c]);
+    }
   }
-}
-
-// chi'(l) of one point into LDS (used by the FP64 back end)
-__device__ __forceinline__ void load_chi(const Batch& b, const DevTables& d, int l, double* Ch) {
-  const int nff2 = d.nff * d.nff;
-  for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
-    const int ch = w / nff2, mn = w % nff2;
-    Ch[w] = b.dchi[(size_t)ch * b.S + d.off + (size_t)l * nff2 + mn];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int row = r0 + rr + i;
+    if (row >= 2 * nq) continue;
+    const int ch = row / nq, q = row % nq;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int mn = c0 + cc + c;
+      if (mn < nff2) dchi[(size_t)ch * b.S + d.off + (size_t)q * nff2 + mn] = acc[i][c];
+    }
   }
 }
 
 // ------------------------------------------------------- projections
 // Forward transform: the partial Fourier sums over the transfer grid at the
 // half-integer frequencies S/2,
-//   xt[ch][k][mn] = (1/Nq) sum_u E[u][k] X[ch][u][mn],  E = (cos(u.S'/2) | sin(u.S'/2)).
-// Item (p, column tile, harmonic group): 64 consecutive columns (ch, mn) and
-// KG harmonic columns; the NW waves split the transfer grid and are added in
-// LDS in a fixed order.
-template <int KG, int NW>
-__global__ void __launch_bounds__(64 * NW)
-k_dft_fwd(Batch b, const int4* __restrict__ items, const double* __restrict__ X) {
-  __shared__ double red[NW][KG][64];
+//   xt[ch][k][mn] = (1/Nq) sum_u E[u][k] X[ch][u][mn],  E = (cos(u.S'/2) | sin(u.S'/2)),
+// as a contraction split over the transfer grid.  Item (p, column tile c,
+// transfer split s): 64 consecutive columns (ch, mn) against all harmonic
+// columns k (E read from its copy padded to kEpad columns, so no guards);
+// the 4 waves own KPT harmonic columns each.  Partial sums go to
+// xp[s][k][col]; k_xt_reduce adds the splits in order.
+template <int KPT>
+__global__ void __launch_bounds__(256)
+k_dft_fwd_part(Batch b, const int4* __restrict__ items, const double* __restrict__ X) {
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
-  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff;
+  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
   const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int col = item.y * 64 + lane;
-  const int k0 = item.z * KG;
-  const int kn = min(KG, ncol - k0);
-  const bool ok = col < 3 * nff2;
+  const int kg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int col = item.y * 64 + lane, split = item.z;
+  const bool ok = col < N;
   const int ch = ok ? col / nff2 : 0, mn = ok ? col % nff2 : 0;
+  const int u0 = (int)((int64_t)nq * split / d.nsu), u1 = (int)((int64_t)nq * (split + 1) / d.nsu);
+  const int k0 = kg * KPT;
   const double* xp = X + (size_t)ch * b.S + d.off + mn;
-  const int u0 = (int)((int64_t)nq * w / NW), u1 = (int)((int64_t)nq * (w + 1) / NW);
-  double acc[KG];
+  const double* ep = d.ephp + k0;
+  double acc[KPT];
 #pragma unroll
-  for (int i = 0; i < KG; ++i) acc[i] = 0.0;
-#pragma unroll 4
+  for (int i = 0; i < KPT; ++i) acc[i] = 0.0;
+#pragma unroll 2
   for (int u = u0; u < u1; ++u) {
     const double x = ok ? xp[(size_t)u * nff2] : 0.0;
-    const double* e = d.eph + (size_t)u * ncol + k0;
+    const double* e = ep + (size_t)u * kEpad;
 #pragma unroll
-    for (int i = 0; i < KG; ++i)
-      if (i < kn) acc[i] = fma(e[i], x, acc[i]);
+    for (int i = 0; i < KPT; ++i) acc[i] = fma(e[i], x, acc[i]);
   }
+  if (!ok) return;
+  double* out = b.xp + d.ws_xp + (size_t)split * ncol * N + col;
 #pragma unroll
-  for (int i = 0; i < KG; ++i) red[w][i][lane] = acc[i];
-  __syncthreads();
-  if (w == 0 && ok) {
-    const double inv = 1.0 / (double)nq;
-    double* xt = b.xt + d.ws_xt;
-    for (int i = 0; i < kn; ++i) {
-      double v = 0.0;
-      for (int ww = 0; ww < NW; ++ww) v += red[ww][i][lane];
-      xt[((size_t)ch * ncol + k0 + i) * nff2 + mn] = v * inv;
-    }
-  }
+  for (int i = 0; i < KPT; ++i)
+    if (k0 + i < ncol) out[(size_t)(k0 + i) * N] = acc[i];
+}
+
+// xt[ch][k][mn] = (1/Nq) sum_s xp[s][k][col] (splits in order); item (p, block)
+__global__ void __launch_bounds__(256) k_xt_reduce(Batch b, const int4* __restrict__ items) {
+  const int4 item = items[blockIdx.x];
+  const int p = item.x;
+  if (skip_point(b, p)) return;
+  const DevTables& d = b.pts[p];
+  const int nff2 = d.nff * d.nff, N = 3 * nff2, ncol = d.ncol;
+  const int64_t i = (int64_t)item.y * 256 + threadIdx.x;
+  if (i >= (int64_t)ncol * N) return;
+  const int k = (int)(i / N), col = (int)(i % N);
+  const double* src = b.xp + d.ws_xp + i;
+  double v = 0.0;
+  for (int sp = 0; sp < d.nsu; ++sp) v += src[(size_t)sp * ncol * N];
+  const int ch = col / nff2, mn = col % nff2;
+  b.xt[d.ws_xt + ((size_t)ch * ncol + k) * nff2 + mn] = v * (1.0 / (double)d.nq);
 }
 
 // Bond basis of the transformed propagators, for every harmonic of the full
@@ -471,102 +499,59 @@ k_gather_g2(Batch b, const int4* __restrict__ items) {
   }
 }
 
-// Inverse transform fused with the assembly of eqns. proj_VP/VC/VD and, in
-// mode 1, with the products of eqns. matmul-P/C/D.  Item (p, l0, nl): nl
-// consecutive momenta of point p starting at l0.
-//   K^X_mn(l) = sum_k E[l][k] g2[X][k][mn]
-//   V^P = U e0e0 - P + K^P,  V^C = U e0e0 + C + K^C,  V^D = U e0e0 + D + K^D
-//   dP = V^P chi'pp V^P, dC = -V^C chi'ph V^C,
-//   dD = (W chi'ph W - V^C chi'ph V^C)/2 with W = 2 V^D - V^C (the SU(2) form
-//   of eqn. matmul-D: 2 dD - dC = W chi'ph W).
-// mode 1 writes scale * dX/dT with scale = T (dX/ds, s = ln T) if scale_T, else 1.
-__global__ void __launch_bounds__(256)
-k_proj_back(Batch b, const int4* __restrict__ items, const double* __restrict__ X,
-            double* __restrict__ out, int mode, int cross, int scale_T) {
+// Inverse transform K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn] in FP64, as a
+// tiled contraction: item (p, tile of 32 momenta l, tile of 64 columns (ch,
+// mn)); k in chunks of 16 through LDS; each thread owns 2 momenta x 4
+// columns.
+__global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict__ items) {
+  __shared__ double Es[32][17];
+  __shared__ double Gs[16][64];
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
-  const int nff = d.nff, nff2 = nff * nff, ncol = d.ncol;
-  const int l0 = item.y, nl = item.z, lt = d.lt;
-  const double scale = scale_T ? b.Tp[p] : 1.0;
+  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
+  const int l0 = item.y * 32, c0 = item.z * 64, tid = threadIdx.x;
   const double* g2 = b.g2 + d.ws_g2;
-  const size_t S = (size_t)b.S;
-  extern __shared__ double sm[];
-  double* Et = sm;                         // [lt][ncol]
-  double* Vs = Et + lt * ncol;             // [lt][3][nff2]
-  double* T1 = Vs + lt * 3 * nff2;         // [3][nff2]
-  double* T2 = T1 + 3 * nff2;              // [3][nff2]
-  double* Ch = T2 + 3 * nff2;              // [2][nff2]
-  double* Wm = Ch + 2 * nff2;              // [nff2]
-  for (int i = threadIdx.x; i < nl * ncol; i += blockDim.x)
-    Et[i] = d.eph[(size_t)(l0 + i / ncol) * ncol + i % ncol];
-  __syncthreads();
-  for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
-    const int ch = w / nff2, mn = w % nff2;
-    double acc[kMaxLT];
+  const int lr = 2 * (tid >> 4), cc = 4 * (tid & 15);
+  double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  for (int k0 = 0; k0 < ncol; k0 += 16) {
+    for (int e = tid; e < 32 * 16; e += 256) {
+      const int r = e >> 4, kk = e & 15, l = l0 + r, k = k0 + kk;
+      Es[r][kk] = (l < nq && k < ncol) ? d.eph[(size_t)l * ncol + k] : 0.0;
+    }
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int kk = e >> 6, c = e & 63, col = c0 + c, k = k0 + kk;
+      double v = 0.0;
+      if (col < N && k < ncol) {
+        const int ch = col / nff2, mn = col % nff2;
+        v = g2[((size_t)ch * ncol + k) * nff2 + mn];
+      }
+      Gs[kk][c] = v;
+    }
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kMaxLT; ++i) acc[i] = 0.0;
-    if (cross) {
-      const double* g = g2 + (size_t)ch * ncol * nff2 + mn;
-#pragma unroll 8
-      for (int k = 0; k < ncol; ++k) {
-        const double gv = g[(size_t)k * nff2];
+    for (int kk = 0; kk < 16; ++kk) {
+      const double a0 = Es[lr][kk], a1 = Es[lr + 1][kk];
 #pragma unroll
-        for (int i = 0; i < kMaxLT; ++i)
-          if (i < nl) acc[i] = fma(Et[i * ncol + k], gv, acc[i]);
+      for (int c = 0; c < 4; ++c) {
+        const double bv = Gs[kk][cc + c];
+        acc[0][c] = fma(a0, bv, acc[0][c]);
+        acc[1][c] = fma(a1, bv, acc[1][c]);
       }
     }
-    const double bare = (mn == 0) ? d.U : 0.0;
-    const double sgn = (ch == 0) ? -1.0 : 1.0;
-    for (int i = 0; i < nl; ++i) {
-      const double own = X[ch * S + d.off + (size_t)(l0 + i) * nff2 + mn];
-      Vs[(i * 3 + ch) * nff2 + mn] = bare + sgn * own + acc[i];
-    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (mode == 0) {
-    for (int w = threadIdx.x; w < nl * 3 * nff2; w += blockDim.x) {
-      const int i = w / (3 * nff2), r = w % (3 * nff2), ch = r / nff2, mn = r % nff2;
-      out[ch * S + d.off + (size_t)(l0 + i) * nff2 + mn] = Vs[w];
+  double* K = b.kinv64 + d.ws_k;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int l = l0 + lr + i;
+    if (l >= nq) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int col = c0 + cc + c;
+      if (col < N) K[((size_t)(col / nff2) * nq + l) * nff2 + col % nff2] = acc[i][c];
     }
-    return;
-  }
-  for (int i = 0; i < nl; ++i) {
-    const int l = l0 + i;
-    const double* VP = Vs + (i * 3 + 0) * nff2;
-    const double* VC = Vs + (i * 3 + 1) * nff2;
-    const double* VD = Vs + (i * 3 + 2) * nff2;
-    load_chi(b, d, l, Ch);
-    for (int w = threadIdx.x; w < nff2; w += blockDim.x) Wm[w] = 2.0 * VD[w] - VC[w];
-    __syncthreads();
-    // T1 = chi'pp V^P, chi'ph V^C, chi'ph W
-    for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
-      const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
-      const double* A = Ch + (which == 0 ? 0 : nff2) + m * nff;
-      const double* B = which == 0 ? VP : (which == 1 ? VC : Wm);
-      double v = 0.0;
-      for (int k = 0; k < nff; ++k) v = fma(A[k], B[k * nff + n], v);
-      T1[w] = v;
-    }
-    __syncthreads();
-    // T2 = V^P T1p, V^C T1c, W T1w
-    for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
-      const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
-      const double* A = (which == 0 ? VP : (which == 1 ? VC : Wm)) + m * nff;
-      const double* B = T1 + which * nff2;
-      double v = 0.0;
-      for (int k = 0; k < nff; ++k) v = fma(A[k], B[k * nff + n], v);
-      T2[w] = v;
-    }
-    __syncthreads();
-    for (int w = threadIdx.x; w < nff2; w += blockDim.x) {
-      const size_t o = d.off + (size_t)l * nff2 + w;
-      out[o] = scale * T2[w];
-      out[S + o] = -scale * T2[nff2 + w];
-      out[2 * S + o] = 0.5 * scale * (T2[2 * nff2 + w] - T2[nff2 + w]);
-    }
-    __syncthreads();
   }
 }
 
@@ -698,12 +683,19 @@ k_dft_inv_mfma(Batch b, const int4* __restrict__ items) {
   }
 }
 
-// Assembly of V and the products in FP32; item (p, l).  Inputs: the inverse
-// transform K (FP32; unused without cross terms), X and the loops (FP64);
-// output scale * dX/dT (mode 1) or V (mode 0) in FP64.
+// Assembly of eqns. proj_VP/VC/VD and the products of eqns. matmul-P/C/D in
+// precision R (double, or float for the mixed form); item (p, l):
+//   V^P = U e0e0 - P + K^P,  V^C = U e0e0 + C + K^C,  V^D = U e0e0 + D + K^D
+//   dP = V^P chi'pp V^P, dC = -V^C chi'ph V^C,
+//   dD = (W chi'ph W - V^C chi'ph V^C)/2 with W = 2 V^D - V^C (the SU(2) form
+//   of eqn. matmul-D: 2 dD - dC = W chi'ph W).
+// K is the inverse transform (unused without cross terms); X and the loops
+// are FP64; the output is scale * dX/dT (mode 1; scale = T, i.e. dX/ds with
+// s = ln T, if scale_T, else 1) or V (mode 0), in FP64.
+template <typename R>
 __global__ void __launch_bounds__(256)
-k_products_f32(Batch b, const int4* __restrict__ items, const double* __restrict__ X,
-               double* __restrict__ out, int mode, int cross, int scale_T) {
+k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X, const R* __restrict__ Kall,
+           double* __restrict__ out, int mode, int cross, int scale_T) {
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
@@ -712,18 +704,18 @@ k_products_f32(Batch b, const int4* __restrict__ items, const double* __restrict
   const int l = item.y;
   const double scale = scale_T ? b.Tp[p] : 1.0;
   const size_t S = (size_t)b.S;
-  const float* K = b.kinv + d.ws_k;
-  extern __shared__ float fsm[];
-  float* Vs = fsm;              // [3][nff2]
-  float* Ch = Vs + 3 * nff2;    // [2][nff2]
-  float* Wm = Ch + 2 * nff2;    // [nff2]
-  float* T1 = Wm + nff2;        // [3][nff2]
-  float* T2 = T1 + 3 * nff2;    // [3][nff2]
+  const R* K = Kall + d.ws_k;
+  extern __shared__ double smem_prod[];
+  R* Vs = reinterpret_cast<R*>(smem_prod);   // [3][nff2]
+  R* Ch = Vs + 3 * nff2;                    // [2][nff2]
+  R* Wm = Ch + 2 * nff2;                    // [nff2]
+  R* T1 = Wm + nff2;                        // [3][nff2]
+  R* T2 = T1 + 3 * nff2;                    // [3][nff2]
   for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
     const int ch = w / nff2, mn = w % nff2;
-    const float bare = (mn == 0) ? (float)d.U : 0.0f;
-    const float own = (float)X[ch * S + d.off + (size_t)l * nff2 + mn];
-    const float kk = cross ? K[((size_t)ch * nq + l) * nff2 + mn] : 0.0f;
+    const R bare = (mn == 0) ? (R)d.U : (R)0;
+    const R own = (R)X[ch * S + d.off + (size_t)l * nff2 + mn];
+    const R kk = cross ? K[((size_t)ch * nq + l) * nff2 + mn] : (R)0;
     Vs[w] = bare + (ch == 0 ? -own : own) + kk;
   }
   if (mode == 0) {
@@ -734,29 +726,29 @@ k_products_f32(Batch b, const int4* __restrict__ items, const double* __restrict
   }
   for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
     const int ch = w / nff2, mn = w % nff2;
-    Ch[w] = (float)b.dchi[(size_t)ch * S + d.off + (size_t)l * nff2 + mn];
+    Ch[w] = (R)b.dchi[(size_t)ch * S + d.off + (size_t)l * nff2 + mn];
   }
   __syncthreads();
-  const float* VP = Vs;
-  const float* VC = Vs + nff2;
-  const float* VD = Vs + 2 * nff2;
-  for (int w = threadIdx.x; w < nff2; w += blockDim.x) Wm[w] = 2.0f * VD[w] - VC[w];
+  const R* VP = Vs;
+  const R* VC = Vs + nff2;
+  const R* VD = Vs + 2 * nff2;
+  for (int w = threadIdx.x; w < nff2; w += blockDim.x) Wm[w] = (R)2 * VD[w] - VC[w];
   __syncthreads();
   for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
     const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
-    const float* A = Ch + (which == 0 ? 0 : nff2) + m * nff;
-    const float* B = which == 0 ? VP : (which == 1 ? VC : Wm);
-    float v = 0.0f;
-    for (int k = 0; k < nff; ++k) v = fmaf(A[k], B[k * nff + n], v);
+    const R* A = Ch + (which == 0 ? 0 : nff2) + m * nff;
+    const R* B = which == 0 ? VP : (which == 1 ? VC : Wm);
+    R v = 0;
+    for (int k = 0; k < nff; ++k) v = fma(A[k], B[k * nff + n], v);
     T1[w] = v;
   }
   __syncthreads();
   for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
     const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
-    const float* A = (which == 0 ? VP : (which == 1 ? VC : Wm)) + m * nff;
-    const float* B = T1 + which * nff2;
-    float v = 0.0f;
-    for (int k = 0; k < nff; ++k) v = fmaf(A[k], B[k * nff + n], v);
+    const R* A = (which == 0 ? VP : (which == 1 ? VC : Wm)) + m * nff;
+    const R* B = T1 + which * nff2;
+    R v = 0;
+    for (int k = 0; k < nff; ++k) v = fma(A[k], B[k * nff + n], v);
     T2[w] = v;
   }
   __syncthreads();
@@ -945,8 +937,15 @@ void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed,
       hipLaunchKernelGGL(k_dft_fwd_mfma, dim3(r.fwd_mfma.n), dim3(256), 0, s, L.b,
                          L.fwd_mfma_items + r.fwd_mfma.begin, X);
   } else if (r.fwd.n > 0) {
-    hipLaunchKernelGGL((k_dft_fwd<4, 16>), dim3(r.fwd.n), dim3(1024), 0, s, L.b,
-                       L.fwd_items + r.fwd.begin, X);
+    const int4* it = L.fwd_items + r.fwd.begin;
+    switch (L.fwd_kpt) {
+      case 4: hipLaunchKernelGGL(k_dft_fwd_part<4>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
+      case 8: hipLaunchKernelGGL(k_dft_fwd_part<8>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
+      case 12: hipLaunchKernelGGL(k_dft_fwd_part<12>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
+      default: hipLaunchKernelGGL(k_dft_fwd_part<18>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
+    }
+    if (r.xtr.n > 0)
+      hipLaunchKernelGGL(k_xt_reduce, dim3(r.xtr.n), dim3(256), 0, s, L.b, L.xtr_items + r.xtr.begin);
   }
   if (r.basis.n > 0)
     hipLaunchKernelGGL(k_bond_basis, dim3(r.basis.n), dim3(256), 0, s, L.b,
@@ -954,22 +953,25 @@ void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed,
   if (r.gather.n > 0)
     hipLaunchKernelGGL(k_gather_g2, dim3(r.gather.n), dim3(256), L.gather_smem, s, L.b,
                        L.gather_items + r.gather.begin);
-  if (mixed && r.inv_mfma.n > 0)
-    hipLaunchKernelGGL(k_dft_inv_mfma, dim3(r.inv_mfma.n), dim3(256), 0, s, L.b,
-                       L.inv_mfma_items + r.inv_mfma.begin);
+  if (mixed) {
+    if (r.inv_mfma.n > 0)
+      hipLaunchKernelGGL(k_dft_inv_mfma, dim3(r.inv_mfma.n), dim3(256), 0, s, L.b,
+                         L.inv_mfma_items + r.inv_mfma.begin);
+  } else if (r.inv.n > 0) {
+    hipLaunchKernelGGL(k_dft_inv, dim3(r.inv.n), dim3(256), 0, s, L.b, L.inv_items + r.inv.begin);
+  }
 }
 
 void launch_back(const Launch& L, const Ranges& r, const double* X, double* out, int mode,
                  bool cross, bool scale_T, bool mixed, hipStream_t s) {
-  if (mixed) {
-    if (r.prod.n > 0)
-      hipLaunchKernelGGL(k_products_f32, dim3(r.prod.n), dim3(256), L.prod_smem, s, L.b,
-                         L.prod_items + r.prod.begin, X, out, mode, cross ? 1 : 0, scale_T ? 1 : 0);
-    return;
-  }
-  if (r.back.n > 0)
-    hipLaunchKernelGGL(k_proj_back, dim3(r.back.n), dim3(256), L.back_smem, s, L.b,
-                       L.back_items + r.back.begin, X, out, mode, cross ? 1 : 0, scale_T ? 1 : 0);
+  if (r.prod.n <= 0) return;
+  const int4* it = L.prod_items + r.prod.begin;
+  if (mixed)
+    hipLaunchKernelGGL(k_products<float>, dim3(r.prod.n), dim3(256), L.prod_smem / 2, s, L.b, it, X,
+                       (const float*)L.b.kinv, out, mode, cross ? 1 : 0, scale_T ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_products<double>, dim3(r.prod.n), dim3(256), L.prod_smem, s, L.b, it, X,
+                       (const double*)L.b.kinv64, out, mode, cross ? 1 : 0, scale_T ? 1 : 0);
 }
 
 void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const double* const* k,

@@ -76,16 +76,18 @@ int nff_of_shells(int shells);
 constexpr int kLoopThreadsMax = 512;   // loop kernel block size bound
 constexpr int kMaxLT = 4;              // momenta per block of the FP64 back end
 constexpr int kSeg = 4096;             // elements per ODE segment item
+constexpr int kEpad = 72;              // padded row length of the phase table copy (ncol <= 69)
 
 // Per-point tables and launch parameters as seen by the kernels (device array).
 struct DevTables {
   int nff, nq, lq, lk, nsh, ncol, smax, nshell;
   int nsplit, nchunk;     // loop geometry: row slices per momentum, row chunks per column
-  int lt;                 // momenta per block of the FP64 back end
+  int nsu;                // splits of the transfer grid in the FP64 forward transform
   int nirr;               // representatives of the transfer momenta (point-group orbits)
   double t, tp, mu, U;
   int64_t off;            // element offset of the point inside one channel of [3][S] / [2][S]
   int64_t ws_xt, ws_yb, ws_g2, ws_k;   // element offsets into the shared workspace
+  int64_t ws_xp;          // offset of the forward-transform partial sums [nsu][ncol][3 nff^2]
   int64_t ws_gh;          // offset of the point's loop-harmonic slices [nsplit][nirr][2][nsh]
   int64_t gh_off;         // offset of the point's harmonics [nq][2][nsh] in harmonic outputs
   double* cre;            // [nff*nff]
@@ -97,6 +99,7 @@ struct DevTables {
   double* pytab;          // [lk/2+1][2 smax + 1]
   double* cshift;         // [lq][lk][2]: cos(p_j + q_i/2), cos(p_j - q_i/2) per axis
   double* eph;            // [nq][ncol]
+  double* ephp;           // [nq][kEpad]: eph padded with zero columns
   unsigned short* eph_hi; // BF16 split of eph (mixed precision): eph ~ hi + lo
   unsigned short* eph_lo;
   int32_t* mrow;
@@ -115,10 +118,12 @@ struct Batch {
   const double* Tp;       // per-point temperatures (device)
   const int* frozen;      // per-point stop flags (device) or null
   double* dchi;           // loops [2][S]
+  double* xp;             // forward-transform partial sums
   double* xt;             // forward transforms
   double* yb;             // bond-basis transforms
   double* g2;             // inverse-transform coefficients
   float* kinv;            // inverse transforms (mixed precision)
+  double* kinv64;         // inverse transforms (FP64)
   double* ghat;           // loop-harmonic slices (all points, at ws_gh)
   const int* item_count;  // loops: when set, only the first *item_count items run
 };
@@ -129,7 +134,7 @@ struct ItemRange {
 
 // Item ranges of one launch set (all points, or one point)
 struct Ranges {
-  ItemRange loop, exp, fwd, fwd_mfma, basis, gather, inv_mfma, back, prod, seg;
+  ItemRange loop, exp, fwd, xtr, fwd_mfma, basis, gather, inv, inv_mfma, prod, seg;
 };
 
 // Device item tables and launch shapes shared by all launches of a context.
@@ -138,16 +143,18 @@ struct Launch {
   const int4* loop_items;
   const int4* exp_items;
   const int4* fwd_items;
+  const int4* xtr_items;
+  const int4* inv_items;
   const int4* fwd_mfma_items;
   const int4* basis_items;
   const int4* gather_items;
   const int4* inv_mfma_items;
-  const int4* back_items;
   const int4* prod_items;
   const int4* seg_items;
   int loop_threads, loop_blocks, smax_max;
+  int fwd_kpt;            // harmonic columns per wave of the FP64 forward transform (4, 8, 12, 18)
   bool loop_persistent;   // loop kernel: persistent work queue, or one block per item
-  size_t loop_smem, gather_smem, back_smem, prod_smem;
+  size_t loop_smem, gather_smem, prod_smem;
 };
 
 // Surrogate state of a single-point context (device pointers and settings).
