@@ -131,7 +131,7 @@ void default_geometry(DevTables& d) {
 
 // ------------------------------------------------------------ item tables
 struct HostItems {
-  std::vector<int4> loop, exp, fwd, xtr, fwd_mfma, basis, gather, inv, inv_mfma, prod, seg;
+  std::vector<int4> loop, exp, fwd, fwd_mfma, basis, gather, inv, inv_mfma, prod, seg;
 };
 
 template <class F>
@@ -153,9 +153,6 @@ void add_point_items(const DevTables& d, int p, HostItems& h, Ranges& r) {
     for (int sp = 0; sp < d.nsu; ++sp)
       for (int c = 0; c < (3 * nff2 + 63) / 64; ++c) v.push_back(make_int4(p, c, sp, 0));
   });
-  mark(h.xtr, r.xtr, [&](std::vector<int4>& v) {
-    for (int b = 0; b < (d.ncol * 3 * nff2 + 255) / 256; ++b) v.push_back(make_int4(p, b, 0, 0));
-  });
   mark(h.inv, r.inv, [&](std::vector<int4>& v) {
     for (int lt = 0; lt < (d.nq + 31) / 32; ++lt)
       for (int c = 0; c < (3 * nff2 + 63) / 64; ++c) v.push_back(make_int4(p, lt, c, 0));
@@ -165,7 +162,7 @@ void add_point_items(const DevTables& d, int p, HostItems& h, Ranges& r) {
       for (int n = 0; n < (3 * nff2 + 15) / 16; ++n) v.push_back(make_int4(p, m, n, 0));
   });
   mark(h.basis, r.basis, [&](std::vector<int4>& v) {
-    for (int b = 0; b < (3 * nv * nff2 + 255) / 256; ++b) v.push_back(make_int4(p, b, 0, 0));
+    for (int b = 0; b < 3 * nv; ++b) v.push_back(make_int4(p, b, 0, 0));
   });
   mark(h.gather, r.gather, [&](std::vector<int4>& v) {
     for (int j = 0; j < d.nsh; ++j)
@@ -220,16 +217,17 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   for (int p = 0; p < npts; ++p) add_point_items(ctx->dev[p], p, h, ctx->per_point[p]);
   int smax_max = 0, threads = 64;
   size_t lsm = 0, gsm = 0, psm = 0;
-  int kpt = 4;
+  int kpt = 2, ncol_max = 1;
   int64_t gh = 0, ghs = 0;
   for (int p = 0; p < npts; ++p) {
     DevTables& d = ctx->dev[p];
     smax_max = std::max(smax_max, d.smax);
     threads = std::max(threads, round64(d.lk * d.nchunk));
     const int nff2 = d.nff * d.nff;
-    gsm = std::max(gsm, sizeof(double) * 4 * (size_t)nff2);
+    gsm = std::max(gsm, sizeof(double) * 6 * (size_t)nff2);
     psm = std::max(psm, sizeof(double) * 12 * (size_t)nff2);
-    kpt = std::max(kpt, (d.ncol + 3) / 4);
+    kpt = std::max(kpt, (d.ncol + 7) / 8);
+    ncol_max = std::max(ncol_max, d.ncol);
     d.ws_gh = gh;
     gh += (int64_t)d.nsplit * d.nirr * 2 * d.nsh;
     d.gh_off = ghs;
@@ -248,7 +246,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
     return r;
   };
   Ranges& all = ctx->all;
-  all.loop = whole(h.loop); all.exp = whole(h.exp); all.fwd = whole(h.fwd); all.xtr = whole(h.xtr);
+  all.loop = whole(h.loop); all.exp = whole(h.exp); all.fwd = whole(h.fwd);
   all.fwd_mfma = whole(h.fwd_mfma); all.basis = whole(h.basis); all.gather = whole(h.gather);
   all.inv = whole(h.inv); all.inv_mfma = whole(h.inv_mfma); all.prod = whole(h.prod);
   all.seg = whole(h.seg);
@@ -258,7 +256,6 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   ST_TRY(upload(ctx, h.loop, &t, g)); L.loop_items = t;
   ST_TRY(upload(ctx, h.exp, &t, g)); L.exp_items = t;
   ST_TRY(upload(ctx, h.fwd, &t, g)); L.fwd_items = t;
-  ST_TRY(upload(ctx, h.xtr, &t, g)); L.xtr_items = t;
   ST_TRY(upload(ctx, h.inv, &t, g)); L.inv_items = t;
   ST_TRY(upload(ctx, h.fwd_mfma, &t, g)); L.fwd_mfma_items = t;
   ST_TRY(upload(ctx, h.basis, &t, g)); L.basis_items = t;
@@ -279,7 +276,8 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   L.loop_smem = lsm;
   L.gather_smem = gsm;
   L.prod_smem = psm;
-  L.fwd_kpt = kpt <= 4 ? 4 : (kpt <= 8 ? 8 : (kpt <= 12 ? 12 : 18));
+  L.fwd_tkg = kpt <= 2 ? 2 : (kpt <= 4 ? 4 : (kpt <= 6 ? 6 : 9));
+  L.inv_kc = ncol_max <= 16 ? 16 : (ncol_max <= 48 ? 48 : 24);
   // persistent loop grid: every CU filled to the kernel's occupancy
   int per_cu = 0, cus = 0;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
@@ -498,11 +496,11 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     d.smax = t.smax; d.nshell = t.nshell; d.nirr = t.nirr;
     d.t = t.p.t; d.tp = t.p.tp; d.mu = t.p.mu; d.U = t.p.U;
     default_geometry(d);
-    // splits of the transfer grid in the FP64 forward transform: about 512
-    // work items per point, at least 16 momenta per split
+    // splits of the transfer grid in the FP64 forward transform: about 256
+    // work items per point, at least 32 momenta per split
     const int nff2 = t.nff * t.nff;
     const int ctiles = (3 * nff2 + 63) / 64;
-    d.nsu = std::max(1, std::min(512 / ctiles, t.nq / 16));
+    d.nsu = std::max(1, std::min(256 / ctiles, t.nq / 32));
     d.off = S;
     ctx->off[p] = S;
     S += (int64_t)t.nq * nff2;
@@ -1024,9 +1022,10 @@ const double kDpB4[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640, -9209
                          187.0 / 2100, 1.0 / 40};
 
 // dX/ds of point p alone at temperature T
-void rhs_point(tufrg_ctx* ctx, int p, double T, const double* X, double* out) {
+tufrg_status rhs_point(tufrg_ctx* ctx, int p, double T, const double* X, double* out) {
   rhs_launch(ctx, ctx->L, ctx->per_point[p], X, out, true, ctx->stream,
              [&](hipStream_t s) { launch_set_T_values(ctx->Tp + p, &T, 1, s); });
+  return TUFRG_OK;
 }
 
 tufrg_status maxabs_point(tufrg_ctx* ctx, int p, const double* X, double* result) {
@@ -1059,7 +1058,7 @@ tufrg_status flow_dopri5_point(tufrg_ctx* ctx, int p, const tufrg_flow_opts* o, 
   double m, mprev, sprev = s;
   ST_TRY(maxabs_point(ctx, p, X, &m));
   mprev = m;
-  rhs_point(ctx, p, std::exp(s), X, k[0]);
+  ST_TRY(rhs_point(ctx, p, std::exp(s), X, k[0]));
   int64_t n_rhs = 1, n_acc = 0;
   std::vector<double> red(seg.n);
   double e[7];
@@ -1069,7 +1068,7 @@ tufrg_status flow_dopri5_point(tufrg_ctx* ctx, int p, const tufrg_flow_opts* o, 
     if (s + h < s_end) h = s_end - s;
     for (int i = 1; i < 7; ++i) {
       launch_axpy(ctx->L, seg, X, k, kDpA[i], i, h, stage, false, ms);
-      rhs_point(ctx, p, std::exp(s + kDpC[i] * h), stage, k[i]);
+      ST_TRY(rhs_point(ctx, p, std::exp(s + kDpC[i] * h), stage, k[i]));
     }
     n_rhs += 6;
     launch_axpy(ctx->L, seg, X, k, kDpB5, 7, h, y5, false, ms);

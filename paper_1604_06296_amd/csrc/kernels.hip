@@ -329,60 +329,65 @@ k_chi_expand(Batch b, const int4* __restrict__ items, const double* __restrict__
 // Forward transform: the partial Fourier sums over the transfer grid at the
 // half-integer frequencies S/2,
 //   xt[ch][k][mn] = (1/Nq) sum_u E[u][k] X[ch][u][mn],  E = (cos(u.S'/2) | sin(u.S'/2)),
-// as a contraction split over the transfer grid.  Item (p, column tile c,
-// transfer split s): 64 consecutive columns (ch, mn) against all harmonic
-// columns k (E read from its copy padded to kEpad columns, so no guards);
-// the 4 waves own KPT harmonic columns each.  Partial sums go to
-// xp[s][k][col]; k_xt_reduce adds the splits in order.
-template <int KPT>
+// as an LDS-tiled contraction split over the transfer grid.  Item (p, column
+// tile c, transfer split s): 64 consecutive columns (ch, mn) against 8 TKG
+// harmonic columns k >= ncol (E from its copy padded with zero columns);
+// chunks of 32 momenta u pass through LDS; thread (k group of TKG, column
+// pair) holds TKG x 2 sums.  Partial sums go to xp[s][k][col]; the bond-basis
+// kernel adds the splits in order.
+template <int TKG>
 __global__ void __launch_bounds__(256)
 k_dft_fwd_part(Batch b, const int4* __restrict__ items, const double* __restrict__ X) {
+  constexpr int TK = 8 * TKG;
+  __shared__ double Es[32][TK + 1];
+  __shared__ double Xs[32][64];
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
   const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
-  const int lane = threadIdx.x & 63;
-  const int kg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int col = item.y * 64 + lane, split = item.z;
-  const bool ok = col < N;
-  const int ch = ok ? col / nff2 : 0, mn = ok ? col % nff2 : 0;
+  const int c0 = item.y * 64, split = item.z;
   const int u0 = (int)((int64_t)nq * split / d.nsu), u1 = (int)((int64_t)nq * (split + 1) / d.nsu);
-  const int k0 = kg * KPT;
-  const double* xp = X + (size_t)ch * b.S + d.off + mn;
-  const double* ep = d.ephp + k0;
-  double acc[KPT];
+  const int tid = threadIdx.x, kg = tid >> 5, cx = tid & 31;
+  const double* Xp = X + d.off;
+  double acc[TKG][2];
 #pragma unroll
-  for (int i = 0; i < KPT; ++i) acc[i] = 0.0;
-#pragma unroll 2
-  for (int u = u0; u < u1; ++u) {
-    const double x = ok ? xp[(size_t)u * nff2] : 0.0;
-    const double* e = ep + (size_t)u * kEpad;
+  for (int i = 0; i < TKG; ++i) acc[i][0] = acc[i][1] = 0.0;
+  for (int ub = u0; ub < u1; ub += 32) {
+    for (int e = tid; e < 32 * TK; e += 256) {
+      const int uu = e / TK, k = e % TK, u = ub + uu;
+      Es[uu][k] = u < u1 ? d.ephp[(size_t)u * kEpad + k] : 0.0;
+    }
+    for (int e = tid; e < 32 * 64; e += 256) {
+      const int uu = e >> 6, c = e & 63, u = ub + uu, col = c0 + c;
+      double v = 0.0;
+      if (u < u1 && col < N) {
+        const int ch = col / nff2, mn = col % nff2;
+        v = Xp[(size_t)ch * b.S + (size_t)u * nff2 + mn];
+      }
+      Xs[uu][c] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int uu = 0; uu < 32; ++uu) {
+      const double x0 = Xs[uu][cx], x1 = Xs[uu][cx + 32];
 #pragma unroll
-    for (int i = 0; i < KPT; ++i) acc[i] = fma(e[i], x, acc[i]);
+      for (int i = 0; i < TKG; ++i) {
+        const double e = Es[uu][kg * TKG + i];
+        acc[i][0] = fma(e, x0, acc[i][0]);
+        acc[i][1] = fma(e, x1, acc[i][1]);
+      }
+    }
+    __syncthreads();
   }
-  if (!ok) return;
-  double* out = b.xp + d.ws_xp + (size_t)split * ncol * N + col;
+  double* out = b.xp + d.ws_xp + (size_t)split * ncol * N;
 #pragma unroll
-  for (int i = 0; i < KPT; ++i)
-    if (k0 + i < ncol) out[(size_t)(k0 + i) * N] = acc[i];
-}
-
-// xt[ch][k][mn] = (1/Nq) sum_s xp[s][k][col] (splits in order); item (p, block)
-__global__ void __launch_bounds__(256) k_xt_reduce(Batch b, const int4* __restrict__ items) {
-  const int4 item = items[blockIdx.x];
-  const int p = item.x;
-  if (skip_point(b, p)) return;
-  const DevTables& d = b.pts[p];
-  const int nff2 = d.nff * d.nff, N = 3 * nff2, ncol = d.ncol;
-  const int64_t i = (int64_t)item.y * 256 + threadIdx.x;
-  if (i >= (int64_t)ncol * N) return;
-  const int k = (int)(i / N), col = (int)(i % N);
-  const double* src = b.xp + d.ws_xp + i;
-  double v = 0.0;
-  for (int sp = 0; sp < d.nsu; ++sp) v += src[(size_t)sp * ncol * N];
-  const int ch = col / nff2, mn = col % nff2;
-  b.xt[d.ws_xt + ((size_t)ch * ncol + k) * nff2 + mn] = v * (1.0 / (double)d.nq);
+  for (int i = 0; i < TKG; ++i) {
+    const int k = kg * TKG + i;
+    if (k >= ncol) continue;
+    if (c0 + cx < N) out[(size_t)k * N + c0 + cx] = acc[i][0];
+    if (c0 + cx + 32 < N) out[(size_t)k * N + c0 + cx + 32] = acc[i][1];
+  }
 }
 
 // Bond basis of the transformed propagators, for every harmonic of the full
@@ -390,7 +395,10 @@ __global__ void __launch_bounds__(256) k_xt_reduce(Batch b, const int4* __restri
 //   yb[in][v][b1 b2] = sum_{m' in shell(b1), n' in shell(b2)} c_{m'b1} c_{n'b2} xt^{in}_{m'n'}(v)
 // with xt(-S') = conj(xt(S')).  These are the bond-space Fourier coefficients
 // Yhat_{R1R2}(W) of the propagators at frequency 2W - R1 - R2 = v.
-// Item (p, block of 256 outputs).
+// Item (p, in * nv + v): the harmonic's transform and the coefficients are
+// staged in LDS; threads own bond pairs (b1, b2).  In FP64 contexts the
+// transform is the in-order sum of the forward-transform splits (xp), taken
+// here; the mixed form reads xt.
 __global__ void __launch_bounds__(256)
 k_bond_basis(Batch b, const int4* __restrict__ items) {
   const int4 item = items[blockIdx.x];
@@ -399,40 +407,63 @@ k_bond_basis(Batch b, const int4* __restrict__ items) {
   const DevTables& d = b.pts[p];
   const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol, nv = 2 * nsh - 1;
   const int total = 3 * nv * nff2;
+  const int in = item.y / nv, v = item.y % nv;
+  const int j = v < nsh ? v : v - nsh + 1;
+  const double sim = v < nsh ? 1.0 : -1.0;
   __shared__ double cs[2 * 441];
+  __shared__ double xs[2 * 441];
+  const double* xt = b.xt + d.ws_xt;
+  const double* xr = xt + ((size_t)in * ncol + j) * nff2;
+  const double* xi = xt + ((size_t)in * ncol + (nsh - 1 + j)) * nff2;
+  if (b.xp != nullptr) {
+    const int N = 3 * nff2;
+    const size_t sstride = (size_t)ncol * N;
+    const double* pr = b.xp + d.ws_xp + (size_t)j * N + (size_t)in * nff2;
+    const double* pi = b.xp + d.ws_xp + (size_t)(nsh - 1 + j) * N + (size_t)in * nff2;
+    const double inv = 1.0 / (double)d.nq;
+    for (int i = threadIdx.x; i < nff2; i += blockDim.x) {
+      double vr = 0.0, vi = 0.0;
+#pragma unroll 4
+      for (int sp = 0; sp < d.nsu; ++sp) {
+        vr += pr[sp * sstride + i];
+        if (j > 0) vi += pi[sp * sstride + i];
+      }
+      xs[i] = vr * inv;
+      xs[nff2 + i] = sim * vi * inv;
+    }
+  } else {
+    for (int i = threadIdx.x; i < nff2; i += blockDim.x) {
+      xs[i] = xr[i];
+      xs[nff2 + i] = j > 0 ? sim * xi[i] : 0.0;
+    }
+  }
   for (int i = threadIdx.x; i < nff2; i += blockDim.x) {
     cs[i] = d.cre[i];
     cs[nff2 + i] = d.cim[i];
   }
   __syncthreads();
-  const int idx = item.y * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int in = idx / (nv * nff2), v = (idx / nff2) % nv, bb = idx % nff2;
-  const int b1 = bb / nff, b2 = bb % nff;
-  const int j = v < nsh ? v : v - nsh + 1;
-  const double sim = v < nsh ? 1.0 : -1.0;
-  const double* xt = b.xt + d.ws_xt;
-  const double* xr = xt + ((size_t)in * ncol + j) * nff2;
-  const double* xi = xt + ((size_t)in * ncol + (nsh - 1 + j)) * nff2;
-  const int s1 = d.shell_of[b1], s2 = d.shell_of[b2];
-  const int m0 = d.shell_start[s1], m1 = d.shell_start[s1 + 1];
-  const int n0 = d.shell_start[s2], n1 = d.shell_start[s2 + 1];
-  double yr = 0.0, yi = 0.0;
-  for (int mp = m0; mp < m1; ++mp) {
-    const double c1r = cs[mp * nff + b1], c1i = cs[nff2 + mp * nff + b1];
-#pragma unroll 4
-    for (int np = n0; np < n1; ++np) {
-      const double c2r = cs[np * nff + b2], c2i = cs[nff2 + np * nff + b2];
-      const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
-      const double ar = xr[mp * nff + np];
-      const double ai = j > 0 ? sim * xi[mp * nff + np] : 0.0;
-      yr = fma(wr, ar, fma(-wi, ai, yr));
-      yi = fma(wr, ai, fma(wi, ar, yi));
-    }
-  }
   double* yb = b.yb + d.ws_yb;
-  yb[idx] = yr;
-  yb[(size_t)total + idx] = yi;
+  for (int bb = threadIdx.x; bb < nff2; bb += blockDim.x) {
+    const int b1 = bb / nff, b2 = bb % nff;
+    const int s1 = d.shell_of[b1], s2 = d.shell_of[b2];
+    const int m0 = d.shell_start[s1], m1 = d.shell_start[s1 + 1];
+    const int n0 = d.shell_start[s2], n1 = d.shell_start[s2 + 1];
+    double yr = 0.0, yi = 0.0;
+    for (int mp = m0; mp < m1; ++mp) {
+      const double c1r = cs[mp * nff + b1], c1i = cs[nff2 + mp * nff + b1];
+#pragma unroll 4
+      for (int np = n0; np < n1; ++np) {
+        const double c2r = cs[np * nff + b2], c2i = cs[nff2 + np * nff + b2];
+        const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
+        const double ar = xs[mp * nff + np], ai = xs[nff2 + mp * nff + np];
+        yr = fma(wr, ar, fma(-wi, ai, yr));
+        yi = fma(wr, ai, fma(wi, ar, yi));
+      }
+    }
+    const size_t idx = ((size_t)in * nv + v) * nff2 + bb;
+    yb[idx] = yr;
+    yb[(size_t)total + idx] = yi;
+  }
 }
 
 // Gather and basis change, independent of the transfer momentum.  Item
@@ -457,18 +488,39 @@ k_gather_g2(Batch b, const int4* __restrict__ items) {
   extern __shared__ double sm[];
   double* Mre = sm;                  // [2][nff2]
   double* Mim = Mre + 2 * nff2;
+  double* cr = Mim + 2 * nff2;       // coefficients c_{m,b} [nff2]
+  double* ci = cr + nff2;
+  for (int i = threadIdx.x; i < nff2; i += blockDim.x) {
+    cr[i] = d.cre[i];
+    ci[i] = d.cim[i];
+  }
   for (int w = threadIdx.x; w < nvl * nff2; w += blockDim.x) {
     const int vi = w / nff2, ab = w % nff2;
     const int vf = (vi == 0) ? j : (nsh - 1 + j);
     const size_t row = ((size_t)X * nv + vf) * nff2 + ab;
     double re = 0.0, im = 0.0;
-    for (int e = d.mrow[row]; e < d.mrow[row + 1]; ++e) {
-      const int32_t pk = d.ment[e];
-      const int in = pk & 3, b1 = (pk >> 2) & 31, b2 = (pk >> 7) & 31, v = (pk >> 12) & 127;
-      const int neg = (pk >> 19) & 1;
-      const size_t o = ((size_t)in * nv + v) * nff2 + b1 * nff + b2;
-      const double yr = yb[o], yi = yb[ybim + o];
-      if (neg) { re -= yr; im -= yi; } else { re += yr; im += yi; }
+    const int e0 = d.mrow[row], e1 = d.mrow[row + 1];
+    for (int e = e0; e < e1; e += 4) {
+      // entries four at a time: independent loads, then the sums in order
+      int32_t pk[4];
+      double yr[4], yi[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pk[u] = e + u < e1 ? d.ment[e + u] : -1;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        yr[u] = yi[u] = 0.0;
+        if (pk[u] >= 0) {
+          const int in = pk[u] & 3, b1 = (pk[u] >> 2) & 31, b2 = (pk[u] >> 7) & 31, v = (pk[u] >> 12) & 127;
+          const size_t o = ((size_t)in * nv + v) * nff2 + b1 * nff + b2;
+          yr[u] = yb[o];
+          yi[u] = yb[ybim + o];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (pk[u] < 0) continue;
+        if ((pk[u] >> 19) & 1) { re -= yr[u]; im -= yi[u]; } else { re += yr[u]; im += yi[u]; }
+      }
     }
     Mre[vi * nff2 + ab] = re;
     Mim[vi * nff2 + ab] = im;
@@ -479,9 +531,9 @@ k_gather_g2(Batch b, const int4* __restrict__ items) {
     const int sm_ = d.shell_of[m], sn = d.shell_of[n];
     double nr[2] = {0.0, 0.0}, ni[2] = {0.0, 0.0};
     for (int a = d.shell_start[sm_]; a < d.shell_start[sm_ + 1]; ++a) {
-      const double c1r = d.cre[m * nff + a], c1i = d.cim[m * nff + a];
+      const double c1r = cr[m * nff + a], c1i = ci[m * nff + a];
       for (int bb = d.shell_start[sn]; bb < d.shell_start[sn + 1]; ++bb) {
-        const double c2r = d.cre[n * nff + bb], c2i = d.cim[n * nff + bb];
+        const double c2r = cr[n * nff + bb], c2i = ci[n * nff + bb];
         const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
         for (int vi = 0; vi < nvl; ++vi) {
           const double mr = Mre[vi * nff2 + a * nff + bb], mi = Mim[vi * nff2 + a * nff + bb];
@@ -501,11 +553,12 @@ k_gather_g2(Batch b, const int4* __restrict__ items) {
 
 // Inverse transform K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn] in FP64, as a
 // tiled contraction: item (p, tile of 32 momenta l, tile of 64 columns (ch,
-// mn)); k in chunks of 16 through LDS; each thread owns 2 momenta x 4
-// columns.
+// mn)); k in chunks of KC through LDS (one chunk when ncol <= KC); each
+// thread owns 2 momenta x 4 columns.
+template <int KC>
 __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict__ items) {
-  __shared__ double Es[32][17];
-  __shared__ double Gs[16][64];
+  __shared__ double Es[32][KC + 1];
+  __shared__ double Gs[KC][64];
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
@@ -515,12 +568,12 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
   const double* g2 = b.g2 + d.ws_g2;
   const int lr = 2 * (tid >> 4), cc = 4 * (tid & 15);
   double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-  for (int k0 = 0; k0 < ncol; k0 += 16) {
-    for (int e = tid; e < 32 * 16; e += 256) {
-      const int r = e >> 4, kk = e & 15, l = l0 + r, k = k0 + kk;
+  for (int k0 = 0; k0 < ncol; k0 += KC) {
+    for (int e = tid; e < 32 * KC; e += 256) {
+      const int r = e / KC, kk = e % KC, l = l0 + r, k = k0 + kk;
       Es[r][kk] = (l < nq && k < ncol) ? d.eph[(size_t)l * ncol + k] : 0.0;
     }
-    for (int e = tid; e < 16 * 64; e += 256) {
+    for (int e = tid; e < KC * 64; e += 256) {
       const int kk = e >> 6, c = e & 63, col = c0 + c, k = k0 + kk;
       double v = 0.0;
       if (col < N && k < ncol) {
@@ -530,8 +583,8 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
       Gs[kk][c] = v;
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
+#pragma unroll 8
+    for (int kk = 0; kk < KC; ++kk) {
       const double a0 = Es[lr][kk], a1 = Es[lr + 1][kk];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -938,14 +991,12 @@ void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed,
                          L.fwd_mfma_items + r.fwd_mfma.begin, X);
   } else if (r.fwd.n > 0) {
     const int4* it = L.fwd_items + r.fwd.begin;
-    switch (L.fwd_kpt) {
+    switch (L.fwd_tkg) {
+      case 2: hipLaunchKernelGGL(k_dft_fwd_part<2>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
       case 4: hipLaunchKernelGGL(k_dft_fwd_part<4>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
-      case 8: hipLaunchKernelGGL(k_dft_fwd_part<8>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
-      case 12: hipLaunchKernelGGL(k_dft_fwd_part<12>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
-      default: hipLaunchKernelGGL(k_dft_fwd_part<18>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
+      case 6: hipLaunchKernelGGL(k_dft_fwd_part<6>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
+      default: hipLaunchKernelGGL(k_dft_fwd_part<9>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
     }
-    if (r.xtr.n > 0)
-      hipLaunchKernelGGL(k_xt_reduce, dim3(r.xtr.n), dim3(256), 0, s, L.b, L.xtr_items + r.xtr.begin);
   }
   if (r.basis.n > 0)
     hipLaunchKernelGGL(k_bond_basis, dim3(r.basis.n), dim3(256), 0, s, L.b,
@@ -958,7 +1009,13 @@ void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed,
       hipLaunchKernelGGL(k_dft_inv_mfma, dim3(r.inv_mfma.n), dim3(256), 0, s, L.b,
                          L.inv_mfma_items + r.inv_mfma.begin);
   } else if (r.inv.n > 0) {
-    hipLaunchKernelGGL(k_dft_inv, dim3(r.inv.n), dim3(256), 0, s, L.b, L.inv_items + r.inv.begin);
+    const int4* it = L.inv_items + r.inv.begin;
+    if (L.inv_kc == 16)
+      hipLaunchKernelGGL(k_dft_inv<16>, dim3(r.inv.n), dim3(256), 0, s, L.b, it);
+    else if (L.inv_kc == 48)
+      hipLaunchKernelGGL(k_dft_inv<48>, dim3(r.inv.n), dim3(256), 0, s, L.b, it);
+    else
+      hipLaunchKernelGGL(k_dft_inv<24>, dim3(r.inv.n), dim3(256), 0, s, L.b, it);
   }
 }
 

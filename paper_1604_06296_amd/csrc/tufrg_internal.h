@@ -134,7 +134,7 @@ struct ItemRange {
 
 // Item ranges of one launch set (all points, or one point)
 struct Ranges {
-  ItemRange loop, exp, fwd, xtr, fwd_mfma, basis, gather, inv, inv_mfma, prod, seg;
+  ItemRange loop, exp, fwd, fwd_mfma, basis, gather, inv, inv_mfma, prod, seg;
 };
 
 // Device item tables and launch shapes shared by all launches of a context.
@@ -143,7 +143,6 @@ struct Launch {
   const int4* loop_items;
   const int4* exp_items;
   const int4* fwd_items;
-  const int4* xtr_items;
   const int4* inv_items;
   const int4* fwd_mfma_items;
   const int4* basis_items;
@@ -152,7 +151,8 @@ struct Launch {
   const int4* prod_items;
   const int4* seg_items;
   int loop_threads, loop_blocks, smax_max;
-  int fwd_kpt;            // harmonic columns per wave of the FP64 forward transform (4, 8, 12, 18)
+  int fwd_tkg;            // FP64 forward transform: harmonic columns per thread group (2, 4, 6, 9)
+  int inv_kc;             // FP64 inverse transform: harmonic chunk (16, 48, or 24 beyond 48)
   bool loop_persistent;   // loop kernel: persistent work queue, or one block per item
   size_t loop_smem, gather_smem, prod_smem;
 };
