@@ -15,6 +15,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -26,6 +27,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "flow-RHS evals/sec and full-flow time vs plain FP64 GPU at Λ_c err ≤1%"
 PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CUs x 64 lanes x 2 flops x 2.4 GHz)
+
+# HBM bytes per launch of the loop kernel at the headline workload (default
+# geometry), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by
+# the counters of a plain 64 MiB device copy; valid only for the kernel
+# sources they were taken with (profiles/loop_kernel_traffic_*.md).
+LOOP_TRAFFIC = {"sources_sha256": None, "bytes": None}
+
+
+def loop_kernel_sources_sha():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "loop_math.h"):
+        with open(os.path.join(ROOT, "paper_1604_06296_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -40,7 +55,33 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--train-steps", type=int, default=8000)
+    ap.add_argument("--probe-loops", type=int, default=0,
+                    help="counter probe only: one 64 MiB device copy (calibration), then this many "
+                         "loop steps of the headline workload; prints no JSON")
     return ap.parse_args()
+
+
+def probe_loops(n):
+    """Fixed kernel sequence for hardware-counter runs (rocprofv3 --pmc)."""
+    import torch
+
+    import paper_1604_06296_amd as tf
+    import synth
+    words = 64 * 1024 * 1024 // 8
+    a = torch.ones(words, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)                                    # 64 MiB read + 64 MiB written
+    torch.cuda.synchronize()
+    w = synth.cfg2()
+    pt = w.points[0]
+    pt.mu = tf.mu_from_filling(pt.t, pt.tp, pt.filling, pt.mu_T, pt.mu_L)
+    ctx = tf.Context([pt])
+    d = ctx.empty(2)
+    for _ in range(n):
+        ctx.bubbles(0.05, d)
+    torch.cuda.synchronize()
+    log(f"[probe] copy of {2 * words * 8} bytes, {n} loop steps, geometry {ctx.geometry(0)}")
 
 
 def log(msg):
@@ -225,6 +266,9 @@ def leg_surrogate(tf, synth, train_steps):
 
 def main():
     args = parse()
+    if args.probe_loops > 0:
+        probe_loops(args.probe_loops)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the right-hand side would shard over transfer momenta; see DESIGN.md)",
@@ -239,11 +283,10 @@ def main():
     w = synth.cfg2()
     pt = w.points[0]
     pt.mu = tf.mu_from_filling(pt.t, pt.tp, pt.filling, pt.mu_T, pt.mu_L)
-    ctx = tf.Context([pt], autotune=True)
+    ctx = tf.Context([pt])          # default (deterministic) loop geometry
     nff = pt.nff
     X = torch.from_numpy(synth.random_channels(pt.nq, nff, seed=5, scale=1.0).reshape(3, -1)).cuda()
     out = ctx.empty(3)
-    dchi = ctx.empty(2)
     # temperatures spread over the flow range
     Ts = [math.exp(math.log(10.0) + (math.log(1e-3) - math.log(10.0)) * i / 63) for i in range(64)]
     log(f"[bench] workload {w.name}: Nq={pt.nq} Nk={pt.Lk ** 2} Nff={nff} mu={pt.mu:.6f} "
@@ -261,21 +304,13 @@ def main():
     ms = 1e3 * el / args.steps
     log(f"[bench] {args.steps} rhs in {el:.4f} s ({ms:.4f} ms each)")
 
-    # dominant kernel (loops): live HIP-event timing on the context's stream,
-    # which is torch's current stream; one bubbles call = the temperature
-    # upload kernel + the loop kernel (one slice per momentum after tuning)
-    nb = max(args.steps, 20)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ctx.bubbles(Ts[0], dchi)
-    ev0.record()
-    for i in range(nb):
-        ctx.bubbles(Ts[i % 64], dchi)
-    ev1.record()
-    torch.cuda.synchronize()
-    loop_ms = ev0.elapsed_time(ev1) / nb
+    # dominant kernel (the loop kernel): HIP events recorded by the library on
+    # the context's stream around back-to-back launches of that kernel alone
+    loop_us, loop_flops = ctx.loop_kernel_time(0.05, reps=max(args.steps, 20))
+    achieved = loop_flops / (loop_us * 1e-6) / 1e12
     flops = ctx.flop_count()
-    achieved = flops["loops"] / (loop_ms * 1e-3) / 1e12
-    log(f"[bench] loop kernel {loop_ms * 1e3:.2f} us/launch, {achieved:.2f} TFLOP/s")
+    log(f"[bench] loop kernel {loop_us:.2f} us/launch, {achieved:.2f} TFLOP/s")
+    traffic = LOOP_TRAFFIC["bytes"] if LOOP_TRAFFIC["sources_sha256"] == loop_kernel_sources_sha() else None
 
     flow_info = None
     if not args.no_flow:
@@ -319,7 +354,7 @@ def main():
                    "flow": flow_info, "flops_per_rhs": flops, **legs},
         "roofline": {"bound": "alu", "kernel": "k_loops", "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": None, "launch_us": loop_ms * 1e3},
+                     "traffic": traffic, "launch_us": loop_us, "flops_per_launch": loop_flops},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -204,6 +204,15 @@ tufrg_status tufrg_sync(tufrg_ctx* ctx);
  * projections, out[2] products.  Host-only. */
 tufrg_status tufrg_flop_count(const tufrg_ctx* ctx, double out[3]);
 
+/* Diagnostic: average duration in microseconds (*us) of the loop kernel
+ * alone, from HIP events recorded on the context's stream around `reps`
+ * back-to-back launches at temperatures T_host[p] (after one warm-up
+ * launch), and its algorithmic flop count per launch (*flops, may be NULL;
+ * the loop part of tufrg_flop_count without the chi' expansion).
+ * Synchronises the stream. */
+tufrg_status tufrg_loop_kernel_time(tufrg_ctx* ctx, const double* T_host, int32_t reps, double* us,
+                                    double* flops);
+
 /* Chemical potential for electron density n (both spins) at temperature T:
  * n = (2/L^2) sum_k n_F(eps_k) on the unshifted L x L grid, by bisection to
  * |dmu| < 1e-13.  Host-only; no context needed.  EINVAL for n outside (0, 2),

@@ -21,7 +21,8 @@ NO_SYMMETRY = 8
 
 # every entry point declared in include/tufrg.h
 EXPORTS = ("tufrg_init", "tufrg_layout", "tufrg_geometry", "tufrg_bubbles", "tufrg_project",
-           "tufrg_rhs", "tufrg_flow", "tufrg_sync", "tufrg_flop_count", "tufrg_mu_from_filling",
+           "tufrg_rhs", "tufrg_flow", "tufrg_sync", "tufrg_flop_count", "tufrg_loop_kernel_time",
+           "tufrg_mu_from_filling",
            "tufrg_harmonics", "tufrg_loop_harmonics", "tufrg_surrogate_dataset",
            "tufrg_surrogate_attach", "tufrg_surrogate_stats",
            "tufrg_mlp_create", "tufrg_mlp_nparams", "tufrg_mlp_get_params", "tufrg_mlp_set_params",
@@ -85,6 +86,7 @@ def load_library():
     lib.tufrg_flow.argtypes = [vp, C.POINTER(_FlowOpts), vp, C.POINTER(_FlowResult)]
     lib.tufrg_sync.argtypes = [vp]
     lib.tufrg_flop_count.argtypes = [vp, dp]
+    lib.tufrg_loop_kernel_time.argtypes = [vp, dp, i32, dp, dp]
     lib.tufrg_mu_from_filling.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, i32, dp]
     u64, f32 = C.c_uint64, C.c_float
     lib.tufrg_harmonics.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)]
@@ -340,6 +342,13 @@ class Context:
         out = (C.c_double * 3)()
         _check(self.lib, self.ctx, self.lib.tufrg_flop_count(self.ctx, out))
         return {"loops": out[0], "projections": out[1], "products": out[2]}
+
+    def loop_kernel_time(self, T, reps: int = 50):
+        """(average microseconds of the loop kernel alone, its flops per launch)."""
+        us, fl = C.c_double(), C.c_double()
+        _check(self.lib, self.ctx, self.lib.tufrg_loop_kernel_time(self.ctx, self._T(T), reps, C.byref(us),
+                                                                   C.byref(fl)))
+        return us.value, fl.value
 
     def flow(self, X, opts: FlowOptions, raise_nonfinite: bool = False) -> List[FlowResult]:
         o = _FlowOpts(opts.T0, opts.Tmin, opts.Xmax, SCHEMES[opts.scheme], opts.nsteps, opts.rtol,

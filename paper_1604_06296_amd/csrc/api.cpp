@@ -752,6 +752,34 @@ tufrg_status tufrg_surrogate_stats(tufrg_ctx* ctx, int64_t out[3]) {
   return TUFRG_OK;
 }
 
+tufrg_status tufrg_loop_kernel_time(tufrg_ctx* ctx, const double* T_host, int32_t reps, double* us,
+                                    double* flops) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  if (!T_host || !us || reps < 1) return fail(ctx, TUFRG_EINVAL, "need T_host, us and reps >= 1");
+  ST_TRY(check_temperatures(ctx, T_host));
+  launch_set_T_values(ctx->Tp, T_host, (int)ctx->dev.size(), ctx->stream);
+  const bool mixed = mixed_of(ctx);
+  launch_loops(ctx->L, ctx->all.loop, ctx->queue, mixed, ctx->stream);   // warm-up
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  hipError_t e = hipEventRecord(e0, ctx->stream);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) launch_loops(ctx->L, ctx->all.loop, ctx->queue, mixed, ctx->stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(ctx, TUFRG_EHIP, std::string("loop kernel timing: ") + hipGetErrorString(e));
+  *us = 1e3 * (double)ms / reps;
+  if (flops) {
+    *flops = 0.0;
+    for (const HostTables& t : ctx->host) *flops += (double)t.flops_loop_kernel;
+  }
+  return TUFRG_OK;
+}
+
 tufrg_status tufrg_sync(tufrg_ctx* ctx) {
   if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

@@ -388,8 +388,8 @@ std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric) {
   const double pairs = (double)t.nirr * (double)lk * (lk / 2 + 1);
   const double c_pair = 162.0;
   const double c_acc = 2.0 * 2.0 * (2 * t.smax + 1);
-  t.flops_loops = (int64_t)(pairs * (c_pair + c_acc) + (double)t.nirr * 2.0 * t.nsh * lk * 4.0 +
-                            nq * 2.0 * 2.0 * f2 * t.nsh);
+  t.flops_loop_kernel = (int64_t)(pairs * (c_pair + c_acc) + (double)t.nirr * 2.0 * t.nsh * lk * 4.0);
+  t.flops_loops = t.flops_loop_kernel + (int64_t)(nq * 2.0 * 2.0 * f2 * t.nsh);
   // forward and inverse transforms (2 flops per real multiply-add), the bond
   // basis change of the transformed propagators and the gathered sums
   double bb = 0.0;

@@ -57,6 +57,7 @@ struct HostTables {
   std::vector<int32_t> mrow;      // CSR row pointers [rows + 1]
   std::vector<int32_t> ment;      // packed entries (see pack_entry)
   int64_t flops_loops = 0, flops_proj = 0, flops_prod = 0;
+  int64_t flops_loop_kernel = 0;  // the loop kernel alone (flops_loops adds the chi' expansion)
 };
 
 // packed gather entry: input channel (2 bits), bonds b1, b2 (5 bits each),
