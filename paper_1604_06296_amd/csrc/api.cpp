@@ -154,7 +154,7 @@ void add_point_items(const DevTables& d, int p, HostItems& h, Ranges& r) {
       for (int c = 0; c < (3 * nff2 + 63) / 64; ++c) v.push_back(make_int4(p, c, sp, 0));
   });
   mark(h.inv, r.inv, [&](std::vector<int4>& v) {
-    for (int lt = 0; lt < (d.nq + 31) / 32; ++lt)
+    for (int lt = 0; lt < (d.nq + 63) / 64; ++lt)
       for (int c = 0; c < (3 * nff2 + 63) / 64; ++c) v.push_back(make_int4(p, lt, c, 0));
   });
   mark(h.fwd_mfma, r.fwd_mfma, [&](std::vector<int4>& v) {
@@ -217,7 +217,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   for (int p = 0; p < npts; ++p) add_point_items(ctx->dev[p], p, h, ctx->per_point[p]);
   int smax_max = 0, threads = 64;
   size_t lsm = 0, gsm = 0, psm = 0;
-  int kpt = 2, ncol_max = 1;
+  int kpt = 1;
   int64_t gh = 0, ghs = 0;
   for (int p = 0; p < npts; ++p) {
     DevTables& d = ctx->dev[p];
@@ -226,8 +226,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
     const int nff2 = d.nff * d.nff;
     gsm = std::max(gsm, sizeof(double) * 6 * (size_t)nff2);
     psm = std::max(psm, sizeof(double) * 12 * (size_t)nff2);
-    kpt = std::max(kpt, (d.ncol + 7) / 8);
-    ncol_max = std::max(ncol_max, d.ncol);
+    kpt = std::max(kpt, (d.ncol + 15) / 16);
     d.ws_gh = gh;
     gh += (int64_t)d.nsplit * d.nirr * 2 * d.nsh;
     d.gh_off = ghs;
@@ -276,8 +275,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   L.loop_smem = lsm;
   L.gather_smem = gsm;
   L.prod_smem = psm;
-  L.fwd_tkg = kpt <= 2 ? 2 : (kpt <= 4 ? 4 : (kpt <= 6 ? 6 : 9));
-  L.inv_kc = ncol_max <= 16 ? 16 : (ncol_max <= 48 ? 48 : 24);
+  L.fwd_kt = kpt <= 3 ? kpt : 5;
   // persistent loop grid: every CU filled to the kernel's occupancy
   int per_cu = 0, cus = 0;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
@@ -496,11 +494,11 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     d.smax = t.smax; d.nshell = t.nshell; d.nirr = t.nirr;
     d.t = t.p.t; d.tp = t.p.tp; d.mu = t.p.mu; d.U = t.p.U;
     default_geometry(d);
-    // splits of the transfer grid in the FP64 forward transform: about 256
-    // work items per point, at least 32 momenta per split
+    // splits of the transfer grid in the FP64 forward transform: about 512
+    // work items per point, at least 64 momenta per split
     const int nff2 = t.nff * t.nff;
     const int ctiles = (3 * nff2 + 63) / 64;
-    d.nsu = std::max(1, std::min(256 / ctiles, t.nq / 32));
+    d.nsu = std::max(1, std::min(512 / ctiles, t.nq / 64));
     d.off = S;
     ctx->off[p] = S;
     S += (int64_t)t.nq * nff2;

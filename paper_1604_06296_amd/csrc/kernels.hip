@@ -329,18 +329,20 @@ k_chi_expand(Batch b, const int4* __restrict__ items, const double* __restrict__
 // Forward transform: the partial Fourier sums over the transfer grid at the
 // half-integer frequencies S/2,
 //   xt[ch][k][mn] = (1/Nq) sum_u E[u][k] X[ch][u][mn],  E = (cos(u.S'/2) | sin(u.S'/2)),
-// as an LDS-tiled contraction split over the transfer grid.  Item (p, column
-// tile c, transfer split s): 64 consecutive columns (ch, mn) against 8 TKG
-// harmonic columns k >= ncol (E from its copy padded with zero columns);
-// chunks of 32 momenta u pass through LDS; thread (k group of TKG, column
-// pair) holds TKG x 2 sums.  Partial sums go to xp[s][k][col]; the bond-basis
-// kernel adds the splits in order.
-template <int TKG>
+// as a contraction on the FP64 matrix cores, split over the transfer grid.
+// Item (p, column tile c, transfer split s): 64 consecutive columns (ch, mn)
+// against KT tiles of 16 harmonic rows k (E from its copy padded with zero
+// columns to kEpad).  Chunks of 32 momenta u pass through LDS; wave w owns
+// 16 columns and KT accumulator tiles of v_mfma_f64_16x16x4f64 (lane l holds
+// A[l%16][l/16], B[l/16][l%16] and, in register j, D[4j+l/16][l%16]).  Partial sums go to
+// xp[s][k][col]; the bond-basis kernel adds the splits in order.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <int KT>
 __global__ void __launch_bounds__(256)
 k_dft_fwd_part(Batch b, const int4* __restrict__ items, const double* __restrict__ X) {
-  constexpr int TK = 8 * TKG;
-  __shared__ double Es[32][TK + 1];
-  __shared__ double Xs[32][64];
+  constexpr int TK = 16 * KT;
+  __shared__ double Es[32][TK + 2];
+  __shared__ double Xs[32][64 + 2];
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
@@ -348,11 +350,12 @@ k_dft_fwd_part(Batch b, const int4* __restrict__ items, const double* __restrict
   const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
   const int c0 = item.y * 64, split = item.z;
   const int u0 = (int)((int64_t)nq * split / d.nsu), u1 = (int)((int64_t)nq * (split + 1) / d.nsu);
-  const int tid = threadIdx.x, kg = tid >> 5, cx = tid & 31;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, k4 = lane >> 4;
   const double* Xp = X + d.off;
-  double acc[TKG][2];
+  f64x4 acc[KT];
 #pragma unroll
-  for (int i = 0; i < TKG; ++i) acc[i][0] = acc[i][1] = 0.0;
+  for (int t = 0; t < KT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
   for (int ub = u0; ub < u1; ub += 32) {
     for (int e = tid; e < 32 * TK; e += 256) {
       const int uu = e / TK, k = e % TK, u = ub + uu;
@@ -368,26 +371,25 @@ k_dft_fwd_part(Batch b, const int4* __restrict__ items, const double* __restrict
       Xs[uu][c] = v;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int uu = 0; uu < 32; ++uu) {
-      const double x0 = Xs[uu][cx], x1 = Xs[uu][cx + 32];
 #pragma unroll
-      for (int i = 0; i < TKG; ++i) {
-        const double e = Es[uu][kg * TKG + i];
-        acc[i][0] = fma(e, x0, acc[i][0]);
-        acc[i][1] = fma(e, x1, acc[i][1]);
-      }
+    for (int uk = 0; uk < 32; uk += 4) {
+      const double bv = Xs[uk + k4][16 * w + r16];
+#pragma unroll
+      for (int t = 0; t < KT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Es[uk + k4][16 * t + r16], bv, acc[t], 0, 0, 0);
     }
     __syncthreads();
   }
   double* out = b.xp + d.ws_xp + (size_t)split * ncol * N;
+  const int col = c0 + 16 * w + r16;
+  if (col >= N) return;
 #pragma unroll
-  for (int i = 0; i < TKG; ++i) {
-    const int k = kg * TKG + i;
-    if (k >= ncol) continue;
-    if (c0 + cx < N) out[(size_t)k * N + c0 + cx] = acc[i][0];
-    if (c0 + cx + 32 < N) out[(size_t)k * N + c0 + cx + 32] = acc[i][1];
-  }
+  for (int t = 0; t < KT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = 16 * t + 4 * j + k4;
+      if (k < ncol) out[(size_t)k * N + col] = acc[t][j];
+    }
 }
 
 // Bond basis of the transformed propagators, for every harmonic of the full
@@ -551,29 +553,31 @@ k_gather_g2(Batch b, const int4* __restrict__ items) {
   }
 }
 
-// Inverse transform K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn] in FP64, as a
-// tiled contraction: item (p, tile of 32 momenta l, tile of 64 columns (ch,
-// mn)); k in chunks of KC through LDS (one chunk when ncol <= KC); each
-// thread owns 2 momenta x 4 columns.
-template <int KC>
+// Inverse transform K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn] in FP64 on the
+// matrix cores: item (p, tile of 64 momenta l, tile of 64 columns (ch, mn));
+// harmonics k in chunks of 16 through LDS; wave w owns 16 columns and 4
+// accumulator tiles of v_mfma_f64_16x16x4f64 (16 momenta each; lane layout
+// as in the forward transform).
 __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict__ items) {
-  __shared__ double Es[32][KC + 1];
-  __shared__ double Gs[KC][64];
+  __shared__ double Es[16][64 + 2];   // [k][l]
+  __shared__ double Gs[16][64 + 2];   // [k][col]
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
   const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
-  const int l0 = item.y * 32, c0 = item.z * 64, tid = threadIdx.x;
+  const int l0 = item.y * 64, c0 = item.z * 64, tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, r16 = lane & 15, k4 = lane >> 4;
   const double* g2 = b.g2 + d.ws_g2;
-  const int lr = 2 * (tid >> 4), cc = 4 * (tid & 15);
-  double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-  for (int k0 = 0; k0 < ncol; k0 += KC) {
-    for (int e = tid; e < 32 * KC; e += 256) {
-      const int r = e / KC, kk = e % KC, l = l0 + r, k = k0 + kk;
-      Es[r][kk] = (l < nq && k < ncol) ? d.eph[(size_t)l * ncol + k] : 0.0;
+  f64x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < ncol; k0 += 16) {
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int r = e & 63, kk = e >> 6, l = l0 + r, k = k0 + kk;
+      Es[kk][r] = (l < nq && k < ncol) ? d.eph[(size_t)l * ncol + k] : 0.0;
     }
-    for (int e = tid; e < KC * 64; e += 256) {
+    for (int e = tid; e < 16 * 64; e += 256) {
       const int kk = e >> 6, c = e & 63, col = c0 + c, k = k0 + kk;
       double v = 0.0;
       if (col < N && k < ncol) {
@@ -583,29 +587,26 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
       Gs[kk][c] = v;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < KC; ++kk) {
-      const double a0 = Es[lr][kk], a1 = Es[lr + 1][kk];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const double bv = Gs[kk][cc + c];
-        acc[0][c] = fma(a0, bv, acc[0][c]);
-        acc[1][c] = fma(a1, bv, acc[1][c]);
-      }
+    for (int kk = 0; kk < 16; kk += 4) {
+      const double bv = Gs[kk + k4][16 * w + r16];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Es[kk + k4][16 * t + r16], bv, acc[t], 0, 0, 0);
     }
     __syncthreads();
   }
   double* K = b.kinv64 + d.ws_k;
+  const int col = c0 + 16 * w + r16;
+  if (col >= N) return;
+  const int ch = col / nff2, mn = col % nff2;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int l = l0 + lr + i;
-    if (l >= nq) continue;
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int col = c0 + cc + c;
-      if (col < N) K[((size_t)(col / nff2) * nq + l) * nff2 + col % nff2] = acc[i][c];
+    for (int j = 0; j < 4; ++j) {
+      const int l = l0 + 16 * t + 4 * j + k4;
+      if (l < nq) K[((size_t)ch * nq + l) * nff2 + mn] = acc[t][j];
     }
-  }
 }
 
 // ======================================================= mixed precision
@@ -991,11 +992,11 @@ void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed,
                          L.fwd_mfma_items + r.fwd_mfma.begin, X);
   } else if (r.fwd.n > 0) {
     const int4* it = L.fwd_items + r.fwd.begin;
-    switch (L.fwd_tkg) {
+    switch (L.fwd_kt) {
+      case 1: hipLaunchKernelGGL(k_dft_fwd_part<1>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
       case 2: hipLaunchKernelGGL(k_dft_fwd_part<2>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
-      case 4: hipLaunchKernelGGL(k_dft_fwd_part<4>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
-      case 6: hipLaunchKernelGGL(k_dft_fwd_part<6>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
-      default: hipLaunchKernelGGL(k_dft_fwd_part<9>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
+      case 3: hipLaunchKernelGGL(k_dft_fwd_part<3>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
+      default: hipLaunchKernelGGL(k_dft_fwd_part<5>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
     }
   }
   if (r.basis.n > 0)
@@ -1009,13 +1010,7 @@ void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed,
       hipLaunchKernelGGL(k_dft_inv_mfma, dim3(r.inv_mfma.n), dim3(256), 0, s, L.b,
                          L.inv_mfma_items + r.inv_mfma.begin);
   } else if (r.inv.n > 0) {
-    const int4* it = L.inv_items + r.inv.begin;
-    if (L.inv_kc == 16)
-      hipLaunchKernelGGL(k_dft_inv<16>, dim3(r.inv.n), dim3(256), 0, s, L.b, it);
-    else if (L.inv_kc == 48)
-      hipLaunchKernelGGL(k_dft_inv<48>, dim3(r.inv.n), dim3(256), 0, s, L.b, it);
-    else
-      hipLaunchKernelGGL(k_dft_inv<24>, dim3(r.inv.n), dim3(256), 0, s, L.b, it);
+    hipLaunchKernelGGL(k_dft_inv, dim3(r.inv.n), dim3(256), 0, s, L.b, L.inv_items + r.inv.begin);
   }
 }
 

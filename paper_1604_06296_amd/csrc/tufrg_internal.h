@@ -77,7 +77,7 @@ int nff_of_shells(int shells);
 constexpr int kLoopThreadsMax = 512;   // loop kernel block size bound
 constexpr int kMaxLT = 4;              // momenta per block of the FP64 back end
 constexpr int kSeg = 4096;             // elements per ODE segment item
-constexpr int kEpad = 72;              // padded row length of the phase table copy (ncol <= 69)
+constexpr int kEpad = 80;              // padded row length of the phase table copy (ncol <= 69)
 
 // Per-point tables and launch parameters as seen by the kernels (device array).
 struct DevTables {
@@ -152,8 +152,7 @@ struct Launch {
   const int4* prod_items;
   const int4* seg_items;
   int loop_threads, loop_blocks, smax_max;
-  int fwd_tkg;            // FP64 forward transform: harmonic columns per thread group (2, 4, 6, 9)
-  int inv_kc;             // FP64 inverse transform: harmonic chunk (16, 48, or 24 beyond 48)
+  int fwd_kt;             // FP64 forward transform: 16-row harmonic tiles (1, 2, 3 or 5)
   bool loop_persistent;   // loop kernel: persistent work queue, or one block per item
   size_t loop_smem, gather_smem, prod_smem;
 };
