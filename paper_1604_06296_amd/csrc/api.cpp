@@ -131,7 +131,7 @@ void default_geometry(DevTables& d) {
 
 // ------------------------------------------------------------ item tables
 struct HostItems {
-  std::vector<int4> loop, exp, fwd, fwd_mfma, basis, gather, inv, inv_mfma, prod, seg;
+  std::vector<int4> loop, exp, fwd, basis, gather, inv, prod, seg;
 };
 
 template <class F>
@@ -157,20 +157,12 @@ void add_point_items(const DevTables& d, int p, HostItems& h, Ranges& r) {
     for (int lt = 0; lt < (d.nq + 63) / 64; ++lt)
       for (int c = 0; c < (3 * nff2 + 63) / 64; ++c) v.push_back(make_int4(p, lt, c, 0));
   });
-  mark(h.fwd_mfma, r.fwd_mfma, [&](std::vector<int4>& v) {
-    for (int m = 0; m < (d.ncol + 15) / 16; ++m)
-      for (int n = 0; n < (3 * nff2 + 15) / 16; ++n) v.push_back(make_int4(p, m, n, 0));
-  });
   mark(h.basis, r.basis, [&](std::vector<int4>& v) {
     for (int b = 0; b < 3 * nv; ++b) v.push_back(make_int4(p, b, 0, 0));
   });
   mark(h.gather, r.gather, [&](std::vector<int4>& v) {
     for (int j = 0; j < d.nsh; ++j)
       for (int X = 0; X < 3; ++X) v.push_back(make_int4(p, j, X, 0));
-  });
-  mark(h.inv_mfma, r.inv_mfma, [&](std::vector<int4>& v) {
-    for (int m = 0; m < (d.nq + 15) / 16; ++m)
-      for (int n = 0; n < (3 * nff2 + 63) / 64; ++n) v.push_back(make_int4(p, m, n, 0));
   });
   mark(h.prod, r.prod, [&](std::vector<int4>& v) {
     for (int l = 0; l < d.nq; ++l) v.push_back(make_int4(p, l, 0, 0));
@@ -246,8 +238,8 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   };
   Ranges& all = ctx->all;
   all.loop = whole(h.loop); all.exp = whole(h.exp); all.fwd = whole(h.fwd);
-  all.fwd_mfma = whole(h.fwd_mfma); all.basis = whole(h.basis); all.gather = whole(h.gather);
-  all.inv = whole(h.inv); all.inv_mfma = whole(h.inv_mfma); all.prod = whole(h.prod);
+  all.basis = whole(h.basis); all.gather = whole(h.gather);
+  all.inv = whole(h.inv); all.prod = whole(h.prod);
   all.seg = whole(h.seg);
   Launch& L = ctx->L;
   std::vector<void*>& g = ctx->geometry_allocations;
@@ -256,10 +248,8 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   ST_TRY(upload(ctx, h.exp, &t, g)); L.exp_items = t;
   ST_TRY(upload(ctx, h.fwd, &t, g)); L.fwd_items = t;
   ST_TRY(upload(ctx, h.inv, &t, g)); L.inv_items = t;
-  ST_TRY(upload(ctx, h.fwd_mfma, &t, g)); L.fwd_mfma_items = t;
   ST_TRY(upload(ctx, h.basis, &t, g)); L.basis_items = t;
   ST_TRY(upload(ctx, h.gather, &t, g)); L.gather_items = t;
-  ST_TRY(upload(ctx, h.inv_mfma, &t, g)); L.inv_mfma_items = t;
   ST_TRY(upload(ctx, h.prod, &t, g)); L.prod_items = t;
   ST_TRY(upload(ctx, h.seg, &t, g)); L.seg_items = t;
   ST_TRY(dalloc(ctx, (size_t)std::max<int64_t>(gh, 1), &L.b.ghat, g));
@@ -478,7 +468,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   ctx->host.resize(npts);
   ctx->off.resize(npts);
   ctx->dev.assign(npts, DevTables());
-  int64_t S = 0, ws_xt = 0, ws_yb = 0, ws_g2 = 0, ws_k = 0, ws_xp = 0;
+  int64_t S = 0, ws_yb = 0, ws_g2 = 0, ws_k = 0, ws_xp = 0;
   for (int p = 0; p < npts; ++p) {
     std::string e = build_tables(pts[p], ctx->host[p], !(o.flags & TUFRG_NO_SYMMETRY));
     if (e.empty() && ctx->host[p].lk > kLoopThreadsMax)
@@ -494,16 +484,14 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     d.smax = t.smax; d.nshell = t.nshell; d.nirr = t.nirr;
     d.t = t.p.t; d.tp = t.p.tp; d.mu = t.p.mu; d.U = t.p.U;
     default_geometry(d);
-    // splits of the transfer grid in the FP64 forward transform: about 512
-    // work items per point, at least 64 momenta per split
+    // splits of the transfer grid in the forward transform: about 512 work
+    // items per point, at least 64 momenta per split
     const int nff2 = t.nff * t.nff;
     const int ctiles = (3 * nff2 + 63) / 64;
     d.nsu = std::max(1, std::min(512 / ctiles, t.nq / 64));
     d.off = S;
     ctx->off[p] = S;
     S += (int64_t)t.nq * nff2;
-    d.ws_xt = ws_xt;
-    ws_xt += (int64_t)3 * t.ncol * nff2;
     d.ws_g2 = ws_g2;
     ws_g2 += (int64_t)3 * t.ncol * nff2;
     d.ws_yb = ws_yb;
@@ -538,19 +526,32 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     for (int s = 0; s < t.nshell; ++s)
       for (int m = t.shell_start[s]; m < t.shell_start[s + 1]; ++m) so[m] = s;
     std::vector<int32_t> hx(t.hx.begin(), t.hx.end()), hy(t.hy.begin(), t.hy.end());
-    std::vector<unsigned short> ehi, elo;
-    split_table(t.eph, ehi, elo);
     std::vector<double> ephp((size_t)t.nq * kEpad, 0.0);
     for (int u = 0; u < t.nq; ++u)
       for (int k = 0; k < t.ncol; ++k) ephp[(size_t)u * kEpad + k] = t.eph[(size_t)u * t.ncol + k];
+    // BF16 splits of the phase table in the two layouts of the mixed transforms
+    std::vector<unsigned short> ehi, elo;
+    split_table(ephp, ehi, elo);
+    const size_t nq16 = (size_t)(t.nq + 15) / 16 * 16, nq64 = (size_t)(t.nq + 63) / 64 * 64;
+    std::vector<unsigned short> qhi(nq16 * kEpad, 0), qlo(nq16 * kEpad, 0);
+    std::vector<unsigned short> rhi(nq64 * kEpad, 0), rlo(nq64 * kEpad, 0);
+    for (int u = 0; u < t.nq; ++u)
+      for (int k = 0; k < kEpad; ++k) {
+        const size_t src = (size_t)u * kEpad + k, q = ((size_t)(u / 4) * kEpad + k) * 4 + u % 4;
+        qhi[q] = ehi[src];
+        qlo[q] = elo[src];
+        rhi[src] = ehi[src];
+        rlo[src] = elo[src];
+      }
     tufrg_status st;
     if ((st = upload(ctx, cre, &d.cre, A)) || (st = upload(ctx, cim, &d.cim, A)) ||
         (st = upload(ctx, ss, &d.shell_start, A)) || (st = upload(ctx, so, &d.shell_of, A)) ||
         (st = upload(ctx, t.ebub, &d.ebub, A)) || (st = upload(ctx, t.pxtab, &d.pxtab, A)) ||
         (st = upload(ctx, t.pytab, &d.pytab, A)) || (st = upload(ctx, t.eph, &d.eph, A)) ||
         (st = upload(ctx, ephp, &d.ephp, A)) ||
-        (st = upload(ctx, t.cshift, &d.cshift, A)) || (st = upload(ctx, ehi, &d.eph_hi, A)) ||
-        (st = upload(ctx, elo, &d.eph_lo, A)) || (st = upload(ctx, t.mrow, &d.mrow, A)) ||
+        (st = upload(ctx, t.cshift, &d.cshift, A)) || (st = upload(ctx, qhi, &d.ephq_hi, A)) ||
+        (st = upload(ctx, qlo, &d.ephq_lo, A)) || (st = upload(ctx, rhi, &d.ephr_hi, A)) ||
+        (st = upload(ctx, rlo, &d.ephr_lo, A)) || (st = upload(ctx, t.mrow, &d.mrow, A)) ||
         (st = upload(ctx, t.ment, &d.ment, A)) || (st = upload(ctx, hx, &d.hx, A)) ||
         (st = upload(ctx, hy, &d.hy, A)) || (st = upload(ctx, t.pairs, &d.pairs, A)) ||
         (st = upload(ctx, t.irr, &d.irr, A)) || (st = upload(ctx, t.symmap, &d.symmap, A)))
@@ -560,13 +561,12 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   Batch& B = ctx->L.b;
   tufrg_status st = TUFRG_OK;
   if (!st) st = dalloc(ctx, 2 * (size_t)S, &B.dchi, A);
-  if (!st) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_xt, 1), &B.xt, A);
   if (!st) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_yb, 1), &B.yb, A);
   if (!st) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_g2, 1), &B.g2, A);
   B.kinv = nullptr;
   if (!st && o.precision == TUFRG_MIXED) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_k, 1), &B.kinv, A);
   if (!st && o.precision != TUFRG_MIXED) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_k, 1), &B.kinv64, A);
-  if (!st && o.precision != TUFRG_MIXED) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_xp, 1), &B.xp, A);
+  if (!st) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_xp, 1), &B.xp, A);
   if (!st) st = dalloc(ctx, (size_t)npts, &ctx->Tp, A);
   if (!st) st = dalloc(ctx, (size_t)npts, &ctx->frozen, A);
   if (!st) st = dalloc(ctx, 2, &ctx->queue, A);

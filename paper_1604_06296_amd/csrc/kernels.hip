@@ -398,9 +398,8 @@ k_dft_fwd_part(Batch b, const int4* __restrict__ items, const double* __restrict
 // with xt(-S') = conj(xt(S')).  These are the bond-space Fourier coefficients
 // Yhat_{R1R2}(W) of the propagators at frequency 2W - R1 - R2 = v.
 // Item (p, in * nv + v): the harmonic's transform and the coefficients are
-// staged in LDS; threads own bond pairs (b1, b2).  In FP64 contexts the
-// transform is the in-order sum of the forward-transform splits (xp), taken
-// here; the mixed form reads xt.
+// staged in LDS; threads own bond pairs (b1, b2).  The transform is the
+// in-order FP64 sum of the forward-transform splits (xp), taken here.
 __global__ void __launch_bounds__(256)
 k_bond_basis(Batch b, const int4* __restrict__ items) {
   const int4 item = items[blockIdx.x];
@@ -414,10 +413,7 @@ k_bond_basis(Batch b, const int4* __restrict__ items) {
   const double sim = v < nsh ? 1.0 : -1.0;
   __shared__ double cs[2 * 441];
   __shared__ double xs[2 * 441];
-  const double* xt = b.xt + d.ws_xt;
-  const double* xr = xt + ((size_t)in * ncol + j) * nff2;
-  const double* xi = xt + ((size_t)in * ncol + (nsh - 1 + j)) * nff2;
-  if (b.xp != nullptr) {
+  {
     const int N = 3 * nff2;
     const size_t sstride = (size_t)ncol * N;
     const double* pr = b.xp + d.ws_xp + (size_t)j * N + (size_t)in * nff2;
@@ -432,11 +428,6 @@ k_bond_basis(Batch b, const int4* __restrict__ items) {
       }
       xs[i] = vr * inv;
       xs[nff2 + i] = sim * vi * inv;
-    }
-  } else {
-    for (int i = threadIdx.x; i < nff2; i += blockDim.x) {
-      xs[i] = xr[i];
-      xs[nff2 + i] = j > 0 ? sim * xi[i] : 0.0;
     }
   }
   for (int i = threadIdx.x; i < nff2; i += blockDim.x) {
@@ -631,110 +622,120 @@ __device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigne
   lo = bf16_rne(f - bf16_to_f32(hi));
 }
 
-// Forward transform on the matrix cores: xt = (1/Nq) E^T X as
-// C[M=ncol][N=3 nff^2] with A = E (pre-split, [Nq][ncol]) and B = X (split on
-// the fly).  Item (p, M tile, N tile): one 16x16 output tile; the 4 waves split
-// the transfer grid and are added in LDS in a fixed order.
+// Forward transform in split precision: the same contraction and output as
+// the FP64 form (partial sums over transfer splits in xp, added in order by
+// the bond-basis kernel), with products hi*hi + hi*lo + lo*hi of the BF16
+// splits accumulated in FP32 over one split.  Item (p, column tile c, split
+// s); splits start on multiples of 16 momenta.  Wave w owns 16 columns; per
+// step of 16 momenta each lane loads its 4 values of X (split on the fly) and,
+// for each of the KT harmonic tiles, one quad of the pre-split phase table
+// laid out [u/4][kEpad][4] (zero beyond Nq), straight from the cache: there
+// is no reuse across waves worth an LDS pass.
+template <int KT>
 __global__ void __launch_bounds__(256)
-k_dft_fwd_mfma(Batch b, const int4* __restrict__ items, const double* __restrict__ X) {
-  __shared__ float red[4][256];
+k_dft_fwd_mix(Batch b, const int4* __restrict__ items, const double* __restrict__ X) {
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
-  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff;
+  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
+  const int split = item.z, nq16 = (nq + 15) >> 4;
+  const int u0 = 16 * (int)((int64_t)nq16 * split / d.nsu);
+  const int u1 = 16 * (int)((int64_t)nq16 * (split + 1) / d.nsu);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = item.y * 16, n0 = item.z * 16;
-  const int ml = m0 + (lane & 15), nl = n0 + (lane & 15), kq = 4 * (lane >> 4);
-  const bool mok = ml < ncol, nok = nl < 3 * nff2;
-  const int ch = nok ? nl / nff2 : 0, mn = nok ? nl % nff2 : 0;
-  const double* xp = X + (size_t)ch * b.S + d.off + mn;
-  const unsigned short* eh = d.eph_hi;
-  const unsigned short* el = d.eph_lo;
-  const int nsteps = (nq + 15) / 16;
-  const int s0 = nsteps * w / 4, s1 = nsteps * (w + 1) / 4;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int st = s0; st < s1; ++st) {
-    bf16x4 ah, al, bh, bl;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  const int col = item.y * 64 + 16 * w + r16;
+  const bool cok = col < N;
+  const int ch = cok ? col / nff2 : 0, mn = cok ? col % nff2 : 0;
+  const double* xc = X + d.off + (size_t)ch * b.S + mn;
+  const bf16x4* eh = reinterpret_cast<const bf16x4*>(d.ephq_hi);
+  const bf16x4* el = reinterpret_cast<const bf16x4*>(d.ephq_lo);
+  f32x4 acc[KT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int ub = u0; ub < u1; ub += 16) {
+    bf16x4 bh, bl;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int u = st * 16 + kq + j;
-      const bool ok = u < nq;
-      ah[j] = (short)((ok && mok) ? eh[(size_t)u * ncol + ml] : 0);
-      al[j] = (short)((ok && mok) ? el[(size_t)u * ncol + ml] : 0);
+      const int u = ub + 4 * k4 + j;
       unsigned short h = 0, l = 0;
-      if (ok && nok) split_bf16(xp[(size_t)u * nff2], h, l);
+      if (cok && u < nq) split_bf16(xc[(size_t)u * nff2], h, l);
       bh[j] = (short)h;
       bl[j] = (short)l;
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
-  }
+    const size_t qrow = (size_t)((ub >> 2) + k4) * kEpad;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) red[w][lane * 4 + j] = acc[j];
-  __syncthreads();
-  if (w == 0) {
-    const double inv = 1.0 / (double)nq;
-    double* xt = b.xt + d.ws_xt;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const double v = ((double)red[0][lane * 4 + j] + (double)red[1][lane * 4 + j]) +
-                       ((double)red[2][lane * 4 + j] + (double)red[3][lane * 4 + j]);
-      const int m = m0 + kq + j, n = n0 + (lane & 15);
-      if (m < ncol && n < 3 * nff2) {
-        const int c2 = n / nff2, mn2 = n % nff2;
-        xt[((size_t)c2 * ncol + m) * nff2 + mn2] = v * inv;
-      }
+    for (int t = 0; t < KT; ++t) {
+      const bf16x4 ah = eh[qrow + 16 * t + r16], al = el[qrow + 16 * t + r16];
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[t], 0, 0, 0);
     }
   }
+  if (!cok) return;
+  double* out = b.xp + d.ws_xp + (size_t)split * ncol * N;
+#pragma unroll
+  for (int t = 0; t < KT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = 16 * t + 4 * k4 + j;
+      if (k < ncol) out[(size_t)k * N + col] = (double)acc[t][j];
+    }
 }
 
-// Inverse transform on the matrix cores: K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn]
-// as C[M=Nq][N=3 nff^2] with A = E (pre-split) and B = g2 (split on the fly).
-// Item (p, M tile, N tile group): each wave owns one 16x16 output tile.
+// Inverse transform in split precision: K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn]
+// with FP32 accumulation of the three BF16 split products, stored in FP32.
+// Item (p, tile of 64 momenta l, tile of 64 columns); wave w owns 16 columns
+// and 4 accumulator tiles of 16 momenta.  The pre-split phase table is laid
+// out [l][kEpad] (zero beyond Nq, rows padded to a multiple of 64), so a
+// lane's 4 consecutive harmonics are one 8-byte load; g2 is split on the fly.
 __global__ void __launch_bounds__(256)
-k_dft_inv_mfma(Batch b, const int4* __restrict__ items) {
+k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
-  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff;
+  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = item.y * 16, n0 = (item.z * 4 + w) * 16;
-  const int ml = m0 + (lane & 15), nl = n0 + (lane & 15), kq = 4 * (lane >> 4);
-  const bool mok = ml < nq, nok = nl < 3 * nff2;
-  const int ch = nok ? nl / nff2 : 0, mn = nok ? nl % nff2 : 0;
-  const unsigned short* eh = d.eph_hi;
-  const unsigned short* el = d.eph_lo;
-  const double* g2 = b.g2 + d.ws_g2;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int r16 = lane & 15, k4 = lane >> 4;
+  const int l0 = item.y * 64, col = item.z * 64 + 16 * w + r16;
+  const bool cok = col < N;
+  const int ch = cok ? col / nff2 : 0, mn = cok ? col % nff2 : 0;
+  const double* gc = b.g2 + d.ws_g2 + (size_t)ch * ncol * nff2 + mn;
+  const bf16x4* eh = reinterpret_cast<const bf16x4*>(d.ephr_hi);
+  const bf16x4* el = reinterpret_cast<const bf16x4*>(d.ephr_lo);
+  constexpr int QR = kEpad / 4;
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < ncol; k0 += 16) {
-    bf16x4 ah, al, bh, bl;
+    bf16x4 bh, bl;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int k = k0 + kq + j;
-      const bool ok = k < ncol;
-      ah[j] = (short)((ok && mok) ? eh[(size_t)ml * ncol + k] : 0);
-      al[j] = (short)((ok && mok) ? el[(size_t)ml * ncol + k] : 0);
+      const int k = k0 + 4 * k4 + j;
       unsigned short h = 0, l = 0;
-      if (ok && nok) split_bf16(g2[((size_t)ch * ncol + k) * nff2 + mn], h, l);
+      if (cok && k < ncol) split_bf16(gc[(size_t)k * nff2], h, l);
       bh[j] = (short)h;
       bl[j] = (short)l;
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
-  }
-  float* K = b.kinv + d.ws_k;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int m = m0 + kq + j, n = n0 + (lane & 15);
-    if (m < nq && n < 3 * nff2) {
-      const int c2 = n / nff2, mn2 = n % nff2;
-      K[((size_t)c2 * nq + m) * nff2 + mn2] = acc[j];
+    for (int t = 0; t < 4; ++t) {
+      const size_t a = (size_t)(l0 + 16 * t + r16) * QR + (k0 >> 2) + k4;
+      const bf16x4 ah = eh[a], al = el[a];
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[t], 0, 0, 0);
     }
   }
+  if (!cok) return;
+  float* K = b.kinv + d.ws_k;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int l = l0 + 16 * t + 4 * k4 + j;
+      if (l < nq) K[((size_t)ch * nq + l) * nff2 + mn] = acc[t][j];
+    }
 }
 
 // Assembly of eqns. proj_VP/VC/VD and the products of eqns. matmul-P/C/D in
@@ -986,17 +987,23 @@ void launch_chi_expand(const Launch& L, const ItemRange& r, const double* fin, d
 }
 
 void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s) {
-  if (mixed) {
-    if (r.fwd_mfma.n > 0)
-      hipLaunchKernelGGL(k_dft_fwd_mfma, dim3(r.fwd_mfma.n), dim3(256), 0, s, L.b,
-                         L.fwd_mfma_items + r.fwd_mfma.begin, X);
-  } else if (r.fwd.n > 0) {
+  if (r.fwd.n > 0) {
     const int4* it = L.fwd_items + r.fwd.begin;
-    switch (L.fwd_kt) {
-      case 1: hipLaunchKernelGGL(k_dft_fwd_part<1>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
-      case 2: hipLaunchKernelGGL(k_dft_fwd_part<2>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
-      case 3: hipLaunchKernelGGL(k_dft_fwd_part<3>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
-      default: hipLaunchKernelGGL(k_dft_fwd_part<5>, dim3(r.fwd.n), dim3(256), 0, s, L.b, it, X); break;
+    const dim3 g(r.fwd.n), blk(256);
+    if (mixed) {
+      switch (L.fwd_kt) {
+        case 1: hipLaunchKernelGGL(k_dft_fwd_mix<1>, g, blk, 0, s, L.b, it, X); break;
+        case 2: hipLaunchKernelGGL(k_dft_fwd_mix<2>, g, blk, 0, s, L.b, it, X); break;
+        case 3: hipLaunchKernelGGL(k_dft_fwd_mix<3>, g, blk, 0, s, L.b, it, X); break;
+        default: hipLaunchKernelGGL(k_dft_fwd_mix<5>, g, blk, 0, s, L.b, it, X); break;
+      }
+    } else {
+      switch (L.fwd_kt) {
+        case 1: hipLaunchKernelGGL(k_dft_fwd_part<1>, g, blk, 0, s, L.b, it, X); break;
+        case 2: hipLaunchKernelGGL(k_dft_fwd_part<2>, g, blk, 0, s, L.b, it, X); break;
+        case 3: hipLaunchKernelGGL(k_dft_fwd_part<3>, g, blk, 0, s, L.b, it, X); break;
+        default: hipLaunchKernelGGL(k_dft_fwd_part<5>, g, blk, 0, s, L.b, it, X); break;
+      }
     }
   }
   if (r.basis.n > 0)
@@ -1005,12 +1012,11 @@ void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed,
   if (r.gather.n > 0)
     hipLaunchKernelGGL(k_gather_g2, dim3(r.gather.n), dim3(256), L.gather_smem, s, L.b,
                        L.gather_items + r.gather.begin);
-  if (mixed) {
-    if (r.inv_mfma.n > 0)
-      hipLaunchKernelGGL(k_dft_inv_mfma, dim3(r.inv_mfma.n), dim3(256), 0, s, L.b,
-                         L.inv_mfma_items + r.inv_mfma.begin);
-  } else if (r.inv.n > 0) {
-    hipLaunchKernelGGL(k_dft_inv, dim3(r.inv.n), dim3(256), 0, s, L.b, L.inv_items + r.inv.begin);
+  if (r.inv.n > 0) {
+    if (mixed)
+      hipLaunchKernelGGL(k_dft_inv_mix, dim3(r.inv.n), dim3(256), 0, s, L.b, L.inv_items + r.inv.begin);
+    else
+      hipLaunchKernelGGL(k_dft_inv, dim3(r.inv.n), dim3(256), 0, s, L.b, L.inv_items + r.inv.begin);
   }
 }
 

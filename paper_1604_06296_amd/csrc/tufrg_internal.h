@@ -87,7 +87,7 @@ struct DevTables {
   int nirr;               // representatives of the transfer momenta (point-group orbits)
   double t, tp, mu, U;
   int64_t off;            // element offset of the point inside one channel of [3][S] / [2][S]
-  int64_t ws_xt, ws_yb, ws_g2, ws_k;   // element offsets into the shared workspace
+  int64_t ws_yb, ws_g2, ws_k;   // element offsets into the shared workspace
   int64_t ws_xp;          // offset of the forward-transform partial sums [nsu][ncol][3 nff^2]
   int64_t ws_gh;          // offset of the point's loop-harmonic slices [nsplit][nirr][2][nsh]
   int64_t gh_off;         // offset of the point's harmonics [nq][2][nsh] in harmonic outputs
@@ -101,8 +101,11 @@ struct DevTables {
   double* cshift;         // [lq][lk][2]: cos(p_j + q_i/2), cos(p_j - q_i/2) per axis
   double* eph;            // [nq][ncol]
   double* ephp;           // [nq][kEpad]: eph padded with zero columns
-  unsigned short* eph_hi; // BF16 split of eph (mixed precision): eph ~ hi + lo
-  unsigned short* eph_lo;
+  // BF16 splits of the phase table (mixed precision: E ~ hi + lo), zero-padded
+  unsigned short* ephq_hi; // forward transform: [ceil(nq/16)*4][kEpad][4], quads of momenta
+  unsigned short* ephq_lo;
+  unsigned short* ephr_hi; // inverse transform: [ceil(nq/64)*64][kEpad]
+  unsigned short* ephr_lo;
   int32_t* mrow;
   int32_t* ment;
   int32_t* hx;            // half set [nsh]
@@ -120,7 +123,6 @@ struct Batch {
   const int* frozen;      // per-point stop flags (device) or null
   double* dchi;           // loops [2][S]
   double* xp;             // forward-transform partial sums
-  double* xt;             // forward transforms
   double* yb;             // bond-basis transforms
   double* g2;             // inverse-transform coefficients
   float* kinv;            // inverse transforms (mixed precision)
@@ -135,7 +137,7 @@ struct ItemRange {
 
 // Item ranges of one launch set (all points, or one point)
 struct Ranges {
-  ItemRange loop, exp, fwd, fwd_mfma, basis, gather, inv, inv_mfma, prod, seg;
+  ItemRange loop, exp, fwd, basis, gather, inv, prod, seg;
 };
 
 // Device item tables and launch shapes shared by all launches of a context.
@@ -145,14 +147,12 @@ struct Launch {
   const int4* exp_items;
   const int4* fwd_items;
   const int4* inv_items;
-  const int4* fwd_mfma_items;
   const int4* basis_items;
   const int4* gather_items;
-  const int4* inv_mfma_items;
   const int4* prod_items;
   const int4* seg_items;
   int loop_threads, loop_blocks, smax_max;
-  int fwd_kt;             // FP64 forward transform: 16-row harmonic tiles (1, 2, 3 or 5)
+  int fwd_kt;             // forward transform: 16-row harmonic tiles (1, 2, 3 or 5)
   bool loop_persistent;   // loop kernel: persistent work queue, or one block per item
   size_t loop_smem, gather_smem, prod_smem;
 };
