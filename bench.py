@@ -37,7 +37,7 @@ LOOP_TRAFFIC = {"sources_sha256": None, "bytes": None}
 
 def loop_kernel_sources_sha():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "loop_math.h"):
+    for f in ("loops.hip", "loop_math.h"):
         with open(os.path.join(ROOT, "paper_1604_06296_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

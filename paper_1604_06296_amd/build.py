@@ -18,7 +18,7 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libtufrg.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["tables.cpp", "api.cpp", "kernels.hip", "mlp.hip", "surrogate.hip"]
+SOURCES = ["tables.cpp", "api.cpp", "loops.hip", "kernels.hip", "mlp.hip", "surrogate.hip"]
 
 # Device code: CDNA4 only; packed FP32 instructions disabled (they have given
 # wrong results on these machines).

@@ -102,29 +102,24 @@ size_t loop_smem_of(const DevTables& d, int threads) {
   int nseg = threads / nout;
   if (nseg < 1) nseg = 1;
   return sizeof(double) *
-         ((size_t)2 * nrmax + (size_t)nrmax * NH + (size_t)d.lk * 2 * NH + (size_t)nseg * nout);
+         ((size_t)2 * nrmax + (size_t)nrmax * NH + (size_t)d.lk * 3 * NH + (size_t)nseg * nout);
 }
 
-// Default loop geometry: split the half fine grid of every representative
-// transfer momentum into row chunks (threads of one column; at least 3 rows
-// each) and then row slices (separate work items; at least 2 rows per thread)
-// until about 8 waves per SIMD are in flight, with at most kLoopThreadsMax
-// threads per block.
+// Default loop geometry: two row slices (separate work items) per
+// representative transfer momentum when the half fine grid has at least 16
+// rows, then the fewest row chunks (threads of one column) that put about two
+// waves per SIMD in flight and leave at most 16 rows per thread, with at most
+// kLoopThreadsMax threads per block and at least 2 rows per thread.  (Fitted
+// to the autotuner's choices; TUFRG_AUTOTUNE searches the full range.)
 void default_geometry(DevTables& d) {
   const int rows = d.lk / 2 + 1;
-  const int64_t target = (int64_t)256 * 4 * 8 * 64;
-  int nsplit = 1, nchunk = 1;
-  for (;;) {
-    const int64_t lanes = (int64_t)d.nirr * d.lk * nsplit * nchunk;
-    if (lanes >= target) break;
-    if (d.lk * (nchunk + 1) <= kLoopThreadsMax && rows / (nsplit * (nchunk + 1)) >= 3) {
-      ++nchunk;
-    } else if (nsplit < 16 && rows / ((nsplit + 1) * nchunk) >= 2) {
-      ++nsplit;
-    } else {
-      break;
-    }
-  }
+  const int64_t target_waves = (int64_t)256 * 4 * 2;
+  const int nsplit = rows >= 16 ? 2 : 1;
+  auto waves = [&](int nc) { return (int64_t)d.nirr * nsplit * ((d.lk * nc + 63) / 64); };
+  int nchunk = 1;
+  while (d.lk * (nchunk + 1) <= kLoopThreadsMax && rows / (nsplit * (nchunk + 1)) >= 2 &&
+         (waves(nchunk) < target_waves || rows / (nsplit * nchunk) > 16))
+    ++nchunk;
   d.nsplit = nsplit;
   d.nchunk = nchunk;
 }
@@ -143,7 +138,7 @@ void mark(std::vector<int4>& v, ItemRange& rg, F fill) {
 
 // The work items of point p for every kernel, appended to h; r receives the
 // point's ranges.  Item layouts are those documented at each kernel.
-void add_point_items(const DevTables& d, int p, HostItems& h, Ranges& r) {
+void add_point_items(const DevTables& d, int p, int inv_lt, HostItems& h, Ranges& r) {
   const int nff2 = d.nff * d.nff, nv = 2 * d.nsh - 1;
   mark(h.exp, r.exp, [&](std::vector<int4>& v) {
     for (int rt = 0; rt < (2 * d.nq + 31) / 32; ++rt)
@@ -154,15 +149,16 @@ void add_point_items(const DevTables& d, int p, HostItems& h, Ranges& r) {
       for (int c = 0; c < (3 * nff2 + 63) / 64; ++c) v.push_back(make_int4(p, c, sp, 0));
   });
   mark(h.inv, r.inv, [&](std::vector<int4>& v) {
-    for (int lt = 0; lt < (d.nq + 63) / 64; ++lt)
+    for (int lt = 0; lt < (d.nq + 16 * inv_lt - 1) / (16 * inv_lt); ++lt)
       for (int c = 0; c < (3 * nff2 + 63) / 64; ++c) v.push_back(make_int4(p, lt, c, 0));
   });
   mark(h.basis, r.basis, [&](std::vector<int4>& v) {
     for (int b = 0; b < 3 * nv; ++b) v.push_back(make_int4(p, b, 0, 0));
   });
   mark(h.gather, r.gather, [&](std::vector<int4>& v) {
+    const int ns = d.nshell;
     for (int j = 0; j < d.nsh; ++j)
-      for (int X = 0; X < 3; ++X) v.push_back(make_int4(p, j, X, 0));
+      for (int x = 0; x < 3 * ns * ns; ++x) v.push_back(make_int4(p, j, x, 0));
   });
   mark(h.prod, r.prod, [&](std::vector<int4>& v) {
     for (int l = 0; l < d.nq; ++l) v.push_back(make_int4(p, l, 0, 0));
@@ -206,9 +202,16 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
   for (int p : order) add_loop_items(ctx->dev[p], p, h.loop, ctx->per_point[p].loop);
-  for (int p = 0; p < npts; ++p) add_point_items(ctx->dev[p], p, h, ctx->per_point[p]);
+  // inverse-transform momentum tile: the largest of 64, 32, 16 that still
+  // gives the launch 512 items
+  int64_t inv_items[3] = {0, 0, 0};
+  for (const DevTables& d : ctx->dev)
+    for (int i = 0; i < 3; ++i)
+      inv_items[i] += (int64_t)((d.nq + (16 << i) - 1) / (16 << i)) * ((3 * d.nff * d.nff + 63) / 64);
+  const int inv_lt = inv_items[2] >= 512 ? 4 : (inv_items[1] >= 512 ? 2 : 1);
+  for (int p = 0; p < npts; ++p) add_point_items(ctx->dev[p], p, inv_lt, h, ctx->per_point[p]);
   int smax_max = 0, threads = 64;
-  size_t lsm = 0, gsm = 0, psm = 0;
+  size_t lsm = 0, psm = 0;
   int kpt = 1;
   int64_t gh = 0, ghs = 0;
   for (int p = 0; p < npts; ++p) {
@@ -216,7 +219,6 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
     smax_max = std::max(smax_max, d.smax);
     threads = std::max(threads, round64(d.lk * d.nchunk));
     const int nff2 = d.nff * d.nff;
-    gsm = std::max(gsm, sizeof(double) * 6 * (size_t)nff2);
     psm = std::max(psm, sizeof(double) * 12 * (size_t)nff2);
     kpt = std::max(kpt, (d.ncol + 15) / 16);
     d.ws_gh = gh;
@@ -263,9 +265,9 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   L.smax_max = smax_max;
   L.loop_threads = threads;
   L.loop_smem = lsm;
-  L.gather_smem = gsm;
   L.prod_smem = psm;
   L.fwd_kt = kpt <= 3 ? kpt : 5;
+  L.inv_lt = inv_lt;
   // persistent loop grid: every CU filled to the kernel's occupancy
   int per_cu = 0, cus = 0;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
@@ -473,6 +475,9 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     std::string e = build_tables(pts[p], ctx->host[p], !(o.flags & TUFRG_NO_SYMMETRY));
     if (e.empty() && ctx->host[p].lk > kLoopThreadsMax)
       e = "Lk must be <= " + std::to_string(kLoopThreadsMax);
+    for (int sh = 0; e.empty() && sh < ctx->host[p].nshell; ++sh)
+      if (ctx->host[p].shell_start[sh + 1] - ctx->host[p].shell_start[sh] > kShellMax)
+        e = "form-factor shell larger than " + std::to_string(kShellMax);
     if (!e.empty()) {
       delete ctx;
       return fail(nullptr, TUFRG_EINVAL, "point " + std::to_string(p) + ": " + e);
@@ -485,10 +490,10 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     d.t = t.p.t; d.tp = t.p.tp; d.mu = t.p.mu; d.U = t.p.U;
     default_geometry(d);
     // splits of the transfer grid in the forward transform: about 512 work
-    // items per point, at least 64 momenta per split
+    // items per point, at least 32 momenta per split
     const int nff2 = t.nff * t.nff;
     const int ctiles = (3 * nff2 + 63) / 64;
-    d.nsu = std::max(1, std::min(512 / ctiles, t.nq / 64));
+    d.nsu = std::max(1, std::min(512 / ctiles, t.nq / 32));
     d.off = S;
     ctx->off[p] = S;
     S += (int64_t)t.nq * nff2;

@@ -1,5 +1,6 @@
-// HIP kernels for gfx950 (CDNA4): loops, projections, products and ODE helpers
-// of the TUfRG flow right-hand side.
+// HIP kernels for gfx950 (CDNA4): loop expansion, projections, products and
+// ODE helpers of the TUfRG flow right-hand side (the loop kernel itself is in
+// loops.hip).
 //
 // Every kernel is driven by a table of work items (point, a, b, c): one launch
 // covers any set of points with uneven grids and truncations, a single point
@@ -12,7 +13,6 @@
 #include <algorithm>
 #include <cstdint>
 
-#include "loop_math.h"
 #include "tufrg_internal.h"
 
 namespace tufrg {
@@ -20,245 +20,6 @@ namespace {
 
 __device__ __forceinline__ bool skip_point(const Batch& b, int p) {
   return b.frozen != nullptr && b.frozen[p] != 0;
-}
-
-struct DevRcp {
-  __device__ double operator()(double x) const {
-    double r = __builtin_amdgcn_rcp(x);       // hardware estimate, refined by Newton steps
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-  }
-};
-struct Exp2F { __device__ float operator()(float x) const { return __builtin_amdgcn_exp2f(x); } };
-struct RcpF { __device__ float operator()(float x) const { return __builtin_amdgcn_rcpf(x); } };
-
-__device__ __forceinline__ void neumaier_add(float& s, float& c, float v) {
-  const float t = s + v;
-  const bool sbig = fabsf(s) >= fabsf(v);
-  const float big = sbig ? s : v, small = sbig ? v : s;
-  c += (big - t) + small;
-  s = t;
-}
-
-// ------------------------------------------------------------------ loops
-// Step ii.) of Sec. 2.4, eqn. chis, at the point's temperature.  Work item
-// (p, slot * nsplit + split): one representative transfer momentum q =
-// irr[slot] (point-group orbits; every other momentum follows by symmetry in
-// the expansion kernel) and one slice of the rows
-// py in [0, Lk/2] of the fine grid (the loop weight is even in p: the
-// self-paired rows py = 0 and Lk/2 carry weight 1, the others weight 2).
-// Threads own one column px and a chunk of the slice's rows; they accumulate
-// row sums of the loop derivative against cos(n py) and sin(n py), n <= smax.
-// The block contracts the rows against cos(px Sx), sin(px Sx) into
-// ghat(q, S) = (1/Nk) sum_p L'(p) cos(p.S) for the half set of harmonics S in
-// bonds + bonds.
-// In the persistent form queue[0] is the next item and queue[1] counts
-// finished blocks; both are zero at entry, and the last block to finish sets
-// them back to zero for the next launch (device-scope atomics, valid across
-// XCDs).  MIXED selects the FP32 pair math with blocked Neumaier-compensated
-// FP32 row sums; otherwise everything is FP64.
-//
-// One loop work item with the point's exact harmonic count NH = 2 smax + 1
-// (compile-time, so the per-row harmonic loops carry no guards).
-template <int SMAX, bool MIXED>
-__device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, int p, int item_b,
-                                          double* smem) {
-  constexpr int NH = 2 * SMAX + 1;
-  const int t = threadIdx.x;
-  const int nsplit = d.nsplit, nchunk = d.nchunk;
-  const int slot = item_b / nsplit, split = item_b % nsplit;
-  const int q = d.irr[slot];
-  const int lk = d.lk;
-  const int rows = lk / 2 + 1;
-  const int R0 = (int)((int64_t)rows * split / nsplit);
-  const int R1 = (int)((int64_t)rows * (split + 1) / nsplit);
-  const int nr = R1 - R0;
-  const int lq = d.lq;
-  const int ix = q / lq, iy = q % lq;
-  const double T = b.Tp[p];
-  const double inv2T = 0.5 / T;
-
-  double* y1 = smem;                        // cos(py + qy/2)        [nr]
-  double* y2 = y1 + nr;                     // cos(py - qy/2)        [nr]
-  double* pyt = y2 + nr;                    // weighted py harmonics [nr][NH]
-  double* rs = pyt + nr * NH;               // row sums              [lk][2][NH]
-  double* gh = rs + lk * 2 * NH;            // harmonic partials     [nseg][2 nsh]
-  for (int j = t; j < nr; j += blockDim.x) {
-    const double* c = d.cshift + ((size_t)iy * lk + (R0 + j)) * 2;
-    y1[j] = c[0];
-    y2[j] = c[1];
-  }
-  for (int j = t; j < nr * NH; j += blockDim.x) pyt[j] = d.pytab[R0 * NH + j];
-  for (int j = t; j < lk * 2 * NH; j += blockDim.x) rs[j] = 0.0;
-  __syncthreads();
-
-  const bool active = t < lk * nchunk;
-  const int px = t % lk, c = t / lk;
-  double acc[2][NH];
-#pragma unroll
-  for (int n = 0; n < NH; ++n) acc[0][n] = acc[1][n] = 0.0;
-  if (active) {
-    const double cx1 = d.cshift[((size_t)ix * lk + px) * 2];       // cos(px + qx/2)
-    const double cx2 = d.cshift[((size_t)ix * lk + px) * 2 + 1];   // cos(px - qx/2)
-    // alpha = eps(p + q/2)/(2T) = A1 + B1 cos(py + qy/2); beta likewise
-    const double A1 = (-2.0 * d.t * cx1 - d.mu) * inv2T;
-    const double B1 = (-2.0 * d.t - 4.0 * d.tp * cx1) * inv2T;
-    const double A2 = (-2.0 * d.t * cx2 - d.mu) * inv2T;
-    const double B2 = (-2.0 * d.t - 4.0 * d.tp * cx2) * inv2T;
-    const int r0 = (int)((int64_t)nr * c / nchunk);
-    const int r1 = (int)((int64_t)nr * (c + 1) / nchunk);
-    if constexpr (!MIXED) {
-#pragma unroll 2
-      for (int r = r0; r < r1; ++r) {
-        const double al = fma(B1, y1[r], A1);
-        const double be = fma(B2, y2[r], A2);
-        double dph, dpp;
-        loop_dot_pair_t(al, be, dph, dpp, DevRcp());
-        const double* w = pyt + r * NH;
-#pragma unroll
-        for (int n = 0; n < NH; ++n) {
-          acc[0][n] = fma(dpp, w[n], acc[0][n]);
-          acc[1][n] = fma(dph, w[n], acc[1][n]);
-        }
-      }
-    } else {
-      // FP32 pair math from FP64 energies; rows blocked by 8 in FP32 and
-      // added into Neumaier-compensated FP32 running sums
-      constexpr int RB = 8;
-      float sum[2][NH], cmp[2][NH];
-#pragma unroll
-      for (int n = 0; n < NH; ++n) sum[0][n] = sum[1][n] = cmp[0][n] = cmp[1][n] = 0.0f;
-      for (int rb = r0; rb < r1; rb += RB) {
-        float blk[2][NH];
-#pragma unroll
-        for (int n = 0; n < NH; ++n) blk[0][n] = blk[1][n] = 0.0f;
-        const int re = min(rb + RB, r1);
-        for (int r = rb; r < re; ++r) {
-          const double al = fma(B1, y1[r], A1);
-          const double be = fma(B2, y2[r], A2);
-          float dph, dpp;
-          loop_dot_pair_f32((float)al, (float)be, (float)(al - be), (float)(al + be), dph, dpp,
-                            Exp2F(), RcpF());
-          const double* w = pyt + r * NH;
-#pragma unroll
-          for (int n = 0; n < NH; ++n) {
-            const float wf = (float)w[n];
-            blk[0][n] = fmaf(dpp, wf, blk[0][n]);
-            blk[1][n] = fmaf(dph, wf, blk[1][n]);
-          }
-        }
-#pragma unroll
-        for (int n = 0; n < NH; ++n) {
-          neumaier_add(sum[0][n], cmp[0][n], blk[0][n]);
-          neumaier_add(sum[1][n], cmp[1][n], blk[1][n]);
-        }
-      }
-#pragma unroll
-      for (int n = 0; n < NH; ++n) {
-        acc[0][n] = (double)sum[0][n] + (double)cmp[0][n];
-        acc[1][n] = (double)sum[1][n] + (double)cmp[1][n];
-      }
-    }
-  }
-  // add the chunks into the row sums one after another (fixed order)
-  for (int cc = 0; cc < nchunk; ++cc) {
-    if (active && c == cc) {
-      double* dst = rs + px * 2 * NH;
-#pragma unroll
-      for (int n = 0; n < NH; ++n) {
-        dst[n] += acc[0][n];
-        dst[NH + n] += acc[1][n];
-      }
-    }
-    __syncthreads();
-  }
-  // contraction over px into the half-set harmonics, split into segments
-  const int nout = 2 * d.nsh;
-  int nseg = (int)blockDim.x / nout;
-  if (nseg < 1) nseg = 1;
-  for (int w = t; w < nout * nseg; w += blockDim.x) {
-    const int o = w % nout, seg = w / nout;
-    const int ch = o / d.nsh, j = o % d.nsh;
-    const int sx = d.hx[j], sy = d.hy[j];          // sx >= 0
-    const int ay = sy < 0 ? -sy : sy;
-    const double sg = sy < 0 ? -1.0 : 1.0;
-    double g = 0.0;
-    for (int x = seg; x < lk; x += nseg) {
-      const double* r = rs + x * 2 * NH + ch * NH;
-      // cos(px sx + py sy) = cos(px sx) cos(py |sy|) - sin(px sx) sgn(sy) sin(py |sy|)
-      double v = d.pxtab[x * NH + sx] * r[ay];
-      if (sx > 0 && ay > 0) v = fma(-sg * d.pxtab[x * NH + SMAX + sx], r[SMAX + ay], v);
-      g += v;
-    }
-    gh[seg * nout + o] = g;
-  }
-  __syncthreads();
-  for (int o = t; o < nout; o += blockDim.x) {
-    double g = 0.0;
-    for (int s = 0; s < nseg; ++s) g += gh[s * nout + o];
-    gh[o] = g;
-  }
-  __syncthreads();
-  // ghat_X(q, S_j) = sgn_X gh_j / (4 T^2 Nk) (pp carries the minus sign of
-  // dL^pp/dT = -Dh/(4T^2)), written to slice `split` of the representative's
-  // harmonics; chi'_mn = sum_j Ebub_{mn,j} ghat(q, S_j) follows in the
-  // expansion kernel.
-  const double base = 1.0 / (4.0 * T * T * (double)lk * (double)lk);
-  for (int o = t; o < nout; o += blockDim.x)
-    b.ghat[d.ws_gh + ((size_t)split * d.nirr + slot) * nout + o] = gh[o] * (o < d.nsh ? -base : base);
-  __syncthreads();
-}
-
-template <int SMAX, bool MIXED>
-__device__ __forceinline__ void loop_dispatch(const Batch& b, const int4 item, double* smem) {
-  const int p = item.x;
-  if (skip_point(b, p)) return;
-  const DevTables& d = b.pts[p];
-  if constexpr (SMAX >= 4) {
-    if (d.smax == 4) {
-      loop_item<4, MIXED>(b, d, p, item.y, smem);
-      return;
-    }
-  }
-  if constexpr (SMAX >= 2) {
-    if (d.smax == 2) {
-      loop_item<2, MIXED>(b, d, p, item.y, smem);
-      return;
-    }
-  }
-  loop_item<0, MIXED>(b, d, p, item.y, smem);
-}
-
-// Loop kernel over work items (p, q * nsplit + split); SMAX is the largest
-// smax of the batch, and each item runs the body compiled for its own smax.
-// Without a queue every block runs item blockIdx.x (the hardware dispatcher
-// balances the load, items being ordered costliest first); with a queue the
-// kernel is persistent and blocks take items until the queue is empty.
-template <int SMAX, bool MIXED>
-__global__ void __launch_bounds__(kLoopThreadsMax)
-k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ queue) {
-  extern __shared__ double smem[];
-  __shared__ int cur;
-  if (b.item_count != nullptr) nitems = min(nitems, *b.item_count);
-  if (queue == nullptr) {
-    if ((int)blockIdx.x < nitems) loop_dispatch<SMAX, MIXED>(b, items[blockIdx.x], smem);
-    return;
-  }
-  const int t = threadIdx.x;
-  for (;;) {
-    if (t == 0) cur = atomicAdd(queue, 1);
-    __syncthreads();
-    const int it = cur;
-    __syncthreads();
-    if (it >= nitems) break;
-    loop_dispatch<SMAX, MIXED>(b, items[it], smem);
-  }
-  if (t == 0 && atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {
-    atomicExch(queue, 0);
-    atomicExch(queue + 1, 0);
-  }
 }
 
 // chi'_mn(q) = sum_j Ebub_{mn,j} ghat(q, S_j) for every momentum, with
@@ -280,21 +41,47 @@ k_chi_expand(Batch b, const int4* __restrict__ items, const double* __restrict__
   const int nq = d.nq, nsh = d.nsh, nout = 2 * nsh, nff2 = d.nff * d.nff;
   const int r0 = item.y * kExpRows, c0 = item.z * kExpCols;
   const int tid = threadIdx.x;
-  for (int e = tid; e < kExpRows * nsh; e += 256) {
-    const int rr = e / nsh, j = e % nsh, row = r0 + rr;
-    double v = 0.0;
-    if (row < 2 * nq) {
-      const int ch = row / nq, q = row % nq;
-      const int32_t pk = d.symmap[(size_t)q * nsh + j];
-      const int slot = pk & 0xffff, oo = ch * nsh + ((pk >> 16) & 0x7f);
-      if (fin) {
-        v = fin[(size_t)slot * nout + oo];
-      } else {
-        for (int sl = 0; sl < d.nsplit; ++sl) v += b.ghat[d.ws_gh + ((size_t)sl * d.nirr + slot) * nout + oo];
+  {
+    // the thread's (up to 5) entries of the row tile, the loop slices of each
+    // loaded 4 at a time and added in slice order
+    constexpr int kPer = (kExpRows * kExpK + 255) / 256;
+    const double* src[kPer];
+    bool ok[kPer], neg[kPer];
+    double v[kPer];
+#pragma unroll
+    for (int s5 = 0; s5 < kPer; ++s5) {
+      const int e = tid + 256 * s5, rr = e / nsh, j = e % nsh, row = r0 + rr;
+      ok[s5] = e < kExpRows * nsh && row < 2 * nq;
+      neg[s5] = false;
+      src[s5] = fin;
+      v[s5] = 0.0;
+      if (ok[s5]) {
+        const int ch = row / nq, q = row % nq;
+        const int32_t pk = d.symmap[(size_t)q * nsh + j];
+        const int slot = pk & 0xffff, oo = ch * nsh + ((pk >> 16) & 0x7f);
+        neg[s5] = (pk >> 24) & 1;
+        src[s5] = fin ? fin + (size_t)slot * nout + oo : b.ghat + d.ws_gh + (size_t)slot * nout + oo;
       }
-      if ((pk >> 24) & 1) v = -v;
     }
-    As[rr][j] = v;
+    const int nsl = fin ? 1 : d.nsplit;
+    const size_t sstride = (size_t)d.nirr * nout;
+    for (int sl0 = 0; sl0 < nsl; sl0 += 4) {
+      double t[kPer][4];
+#pragma unroll
+      for (int s5 = 0; s5 < kPer; ++s5)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          t[s5][u] = (ok[s5] && sl0 + u < nsl) ? src[s5][(size_t)(sl0 + u) * sstride] : 0.0;
+#pragma unroll
+      for (int s5 = 0; s5 < kPer; ++s5)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[s5] += t[s5][u];
+    }
+#pragma unroll
+    for (int s5 = 0; s5 < kPer; ++s5) {
+      const int e = tid + 256 * s5;
+      if (e < kExpRows * nsh) As[e / nsh][e % nsh] = neg[s5] ? -v[s5] : v[s5];
+    }
   }
   for (int e = tid; e < nsh * kExpCols; e += 256) {
     const int j = e / kExpCols, c = e % kExpCols, mn = c0 + c;
@@ -414,20 +201,41 @@ k_bond_basis(Batch b, const int4* __restrict__ items) {
   __shared__ double cs[2 * 441];
   __shared__ double xs[2 * 441];
   {
-    const int N = 3 * nff2;
+    // 2 nff^2 sums of nsu terms; each thread keeps up to 4 sums and 8 splits
+    // of each in flight, then adds them in split order
+    const int N = 3 * nff2, nel = 2 * nff2;
     const size_t sstride = (size_t)ncol * N;
-    const double* pr = b.xp + d.ws_xp + (size_t)j * N + (size_t)in * nff2;
-    const double* pi = b.xp + d.ws_xp + (size_t)(nsh - 1 + j) * N + (size_t)in * nff2;
+    const double* base = b.xp + d.ws_xp + (size_t)in * nff2;
     const double inv = 1.0 / (double)d.nq;
-    for (int i = threadIdx.x; i < nff2; i += blockDim.x) {
-      double vr = 0.0, vi = 0.0;
-#pragma unroll 4
-      for (int sp = 0; sp < d.nsu; ++sp) {
-        vr += pr[sp * sstride + i];
-        if (j > 0) vi += pi[sp * sstride + i];
+    for (int e0 = threadIdx.x; e0 < nel; e0 += 4 * 256) {
+      const double* src[4];
+      bool ok[4];
+      double acc[4];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int e = e0 + 256 * s4;
+        const bool im = e >= nff2;
+        ok[s4] = e < nel && (!im || j > 0);
+        src[s4] = base + (size_t)(im ? nsh - 1 + j : j) * N + (im ? e - nff2 : e);
+        acc[s4] = 0.0;
       }
-      xs[i] = vr * inv;
-      xs[nff2 + i] = sim * vi * inv;
+      for (int sp0 = 0; sp0 < d.nsu; sp0 += 8) {
+        double v[4][8];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            v[s4][u] = (ok[s4] && sp0 + u < d.nsu) ? src[s4][(size_t)(sp0 + u) * sstride] : 0.0;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[s4] += v[s4][u];
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int e = e0 + 256 * s4;
+        if (e < nel) xs[e] = (e < nff2 ? 1.0 : sim) * acc[s4] * inv;
+      }
     }
   }
   for (int i = threadIdx.x; i < nff2; i += blockDim.x) {
@@ -459,38 +267,35 @@ k_bond_basis(Batch b, const int4* __restrict__ items) {
   }
 }
 
-// Gather and basis change, independent of the transfer momentum.  Item
-// (p, half-set harmonic j, output channel X).  For V = +S'_j and V = -S'_j:
+// Gather and basis change, independent of the transfer momentum.  For
+// V = +S'_j and V = -S'_j:
 //   M^X_AB(V) = sum_entries (+-) yb^{in}_{b1 b2}(v)          (eqn. proj_pos in bonds)
 //   N^X(V) = C M^X(V) C^T                                  (back to form factors)
 // and the real coefficients of cos(l.V/2), sin(l.V/2) for the inverse transform:
 //   Re[e^{-il.V/2} N(V) + e^{+il.V/2} N(-V)] = cos (ReN+ + ReN-) + sin (ImN+ - ImN-).
-__global__ void __launch_bounds__(256)
+// C is block diagonal over shells, so the item is (p, half-set harmonic j,
+// (X, shell of m, shell of n)): one wave gathers the shell block of M (at
+// most kShellMax^2 bond pairs per harmonic) into LDS and transforms it.
+__global__ void __launch_bounds__(64)
 k_gather_g2(Batch b, const int4* __restrict__ items) {
+  __shared__ double Mre[2][kShellMax * kShellMax];
+  __shared__ double Mim[2][kShellMax * kShellMax];
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
-  const int j = item.y, X = item.z;
-  const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol;
-  const int nv = 2 * nsh - 1;
+  const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol, ns = d.nshell;
+  const int j = item.y, X = item.z / (ns * ns), sm = item.z / ns % ns, sn = item.z % ns;
+  const int a0 = d.shell_start[sm], na = d.shell_start[sm + 1] - a0;
+  const int b0 = d.shell_start[sn], nb = d.shell_start[sn + 1] - b0;
+  const int nv = 2 * nsh - 1, nab = na * nb;
   const int nvl = (j == 0) ? 1 : 2;
   const size_t ybim = (size_t)3 * nv * nff2;
   const double* yb = b.yb + d.ws_yb;
-  double* g2 = b.g2 + d.ws_g2;
-  extern __shared__ double sm[];
-  double* Mre = sm;                  // [2][nff2]
-  double* Mim = Mre + 2 * nff2;
-  double* cr = Mim + 2 * nff2;       // coefficients c_{m,b} [nff2]
-  double* ci = cr + nff2;
-  for (int i = threadIdx.x; i < nff2; i += blockDim.x) {
-    cr[i] = d.cre[i];
-    ci[i] = d.cim[i];
-  }
-  for (int w = threadIdx.x; w < nvl * nff2; w += blockDim.x) {
-    const int vi = w / nff2, ab = w % nff2;
+  for (int w = threadIdx.x; w < nvl * nab; w += 64) {
+    const int vi = w / nab, r = w % nab;
     const int vf = (vi == 0) ? j : (nsh - 1 + j);
-    const size_t row = ((size_t)X * nv + vf) * nff2 + ab;
+    const size_t row = ((size_t)X * nv + vf) * nff2 + (size_t)(a0 + r / nb) * nff + b0 + r % nb;
     double re = 0.0, im = 0.0;
     const int e0 = d.mrow[row], e1 = d.mrow[row + 1];
     for (int e = e0; e < e1; e += 4) {
@@ -515,21 +320,21 @@ k_gather_g2(Batch b, const int4* __restrict__ items) {
         if ((pk[u] >> 19) & 1) { re -= yr[u]; im -= yi[u]; } else { re += yr[u]; im += yi[u]; }
       }
     }
-    Mre[vi * nff2 + ab] = re;
-    Mim[vi * nff2 + ab] = im;
+    Mre[vi][r] = re;
+    Mim[vi][r] = im;
   }
   __syncthreads();
-  for (int mn = threadIdx.x; mn < nff2; mn += blockDim.x) {
-    const int m = mn / nff, n = mn % nff;
-    const int sm_ = d.shell_of[m], sn = d.shell_of[n];
+  double* g2 = b.g2 + d.ws_g2;
+  for (int w = threadIdx.x; w < nab; w += 64) {
+    const int m = a0 + w / nb, n = b0 + w % nb, mn = m * nff + n;
     double nr[2] = {0.0, 0.0}, ni[2] = {0.0, 0.0};
-    for (int a = d.shell_start[sm_]; a < d.shell_start[sm_ + 1]; ++a) {
-      const double c1r = cr[m * nff + a], c1i = ci[m * nff + a];
-      for (int bb = d.shell_start[sn]; bb < d.shell_start[sn + 1]; ++bb) {
-        const double c2r = cr[n * nff + bb], c2i = ci[n * nff + bb];
+    for (int a = 0; a < na; ++a) {
+      const double c1r = d.cre[m * nff + a0 + a], c1i = d.cim[m * nff + a0 + a];
+      for (int bb = 0; bb < nb; ++bb) {
+        const double c2r = d.cre[n * nff + b0 + bb], c2i = d.cim[n * nff + b0 + bb];
         const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
         for (int vi = 0; vi < nvl; ++vi) {
-          const double mr = Mre[vi * nff2 + a * nff + bb], mi = Mim[vi * nff2 + a * nff + bb];
+          const double mr = Mre[vi][a * nb + bb], mi = Mim[vi][a * nb + bb];
           nr[vi] += wr * mr - wi * mi;
           ni[vi] += wr * mi + wi * mr;
         }
@@ -545,27 +350,30 @@ k_gather_g2(Batch b, const int4* __restrict__ items) {
 }
 
 // Inverse transform K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn] in FP64 on the
-// matrix cores: item (p, tile of 64 momenta l, tile of 64 columns (ch, mn));
-// harmonics k in chunks of 16 through LDS; wave w owns 16 columns and 4
+// matrix cores: item (p, tile of 16 LT momenta l, tile of 64 columns (ch, mn));
+// harmonics k in chunks of 16 through LDS; wave w owns 16 columns and LT
 // accumulator tiles of v_mfma_f64_16x16x4f64 (16 momenta each; lane layout
-// as in the forward transform).
+// as in the forward transform).  LT is the largest of 4, 2, 1 that still gives
+// the launch enough items.
+template <int LT>
 __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict__ items) {
-  __shared__ double Es[16][64 + 2];   // [k][l]
+  constexpr int TL = 16 * LT;
+  __shared__ double Es[16][TL + 2];   // [k][l]
   __shared__ double Gs[16][64 + 2];   // [k][col]
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
   const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
-  const int l0 = item.y * 64, c0 = item.z * 64, tid = threadIdx.x;
+  const int l0 = item.y * TL, c0 = item.z * 64, tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, r16 = lane & 15, k4 = lane >> 4;
   const double* g2 = b.g2 + d.ws_g2;
-  f64x4 acc[4];
+  f64x4 acc[LT];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < LT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < ncol; k0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int r = e & 63, kk = e >> 6, l = l0 + r, k = k0 + kk;
+    for (int e = tid; e < 16 * TL; e += 256) {
+      const int r = e % TL, kk = e / TL, l = l0 + r, k = k0 + kk;
       Es[kk][r] = (l < nq && k < ncol) ? d.eph[(size_t)l * ncol + k] : 0.0;
     }
     for (int e = tid; e < 16 * 64; e += 256) {
@@ -582,7 +390,7 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
     for (int kk = 0; kk < 16; kk += 4) {
       const double bv = Gs[kk + k4][16 * w + r16];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < LT; ++t)
         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Es[kk + k4][16 * t + r16], bv, acc[t], 0, 0, 0);
     }
     __syncthreads();
@@ -592,7 +400,7 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
   if (col >= N) return;
   const int ch = col / nff2, mn = col % nff2;
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < LT; ++t)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int l = l0 + 16 * t + 4 * j + k4;
@@ -685,10 +493,11 @@ k_dft_fwd_mix(Batch b, const int4* __restrict__ items, const double* __restrict_
 
 // Inverse transform in split precision: K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn]
 // with FP32 accumulation of the three BF16 split products, stored in FP32.
-// Item (p, tile of 64 momenta l, tile of 64 columns); wave w owns 16 columns
-// and 4 accumulator tiles of 16 momenta.  The pre-split phase table is laid
-// out [l][kEpad] (zero beyond Nq, rows padded to a multiple of 64), so a
-// lane's 4 consecutive harmonics are one 8-byte load; g2 is split on the fly.
+// Item (p, tile of 16 LT momenta l, tile of 64 columns); wave w owns 16
+// columns and LT accumulator tiles of 16 momenta.  The pre-split phase table
+// is laid out [l][kEpad] (zero beyond Nq, rows padded to a multiple of 64), so
+// a lane's 4 consecutive harmonics are one 8-byte load; g2 is split on the fly.
+template <int LT>
 __global__ void __launch_bounds__(256)
 k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
   const int4 item = items[blockIdx.x];
@@ -698,16 +507,16 @@ k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
   const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r16 = lane & 15, k4 = lane >> 4;
-  const int l0 = item.y * 64, col = item.z * 64 + 16 * w + r16;
+  const int l0 = item.y * 16 * LT, col = item.z * 64 + 16 * w + r16;
   const bool cok = col < N;
   const int ch = cok ? col / nff2 : 0, mn = cok ? col % nff2 : 0;
   const double* gc = b.g2 + d.ws_g2 + (size_t)ch * ncol * nff2 + mn;
   const bf16x4* eh = reinterpret_cast<const bf16x4*>(d.ephr_hi);
   const bf16x4* el = reinterpret_cast<const bf16x4*>(d.ephr_lo);
   constexpr int QR = kEpad / 4;
-  f32x4 acc[4];
+  f32x4 acc[LT];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < LT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < ncol; k0 += 16) {
     bf16x4 bh, bl;
 #pragma unroll
@@ -719,7 +528,7 @@ k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
       bl[j] = (short)l;
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < LT; ++t) {
       const size_t a = (size_t)(l0 + 16 * t + r16) * QR + (k0 >> 2) + k4;
       const bf16x4 ah = eh[a], al = el[a];
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
@@ -730,7 +539,7 @@ k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
   if (!cok) return;
   float* K = b.kinv + d.ws_k;
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < LT; ++t)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int l = l0 + 16 * t + 4 * k4 + j;
@@ -957,29 +766,6 @@ __global__ void k_step_end(unsigned long long* words, int npts, int* frozen, dou
 }  // namespace
 
 // ============================================================== launchers
-void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, hipStream_t s) {
-  if (r.n <= 0) return;
-  if (!L.loop_persistent) queue = nullptr;
-  const int grid = L.loop_persistent ? std::min(r.n, L.loop_blocks) : r.n;
-  const dim3 blk(L.loop_threads);
-  const size_t sm = L.loop_smem;
-  const int4* it = L.loop_items + r.begin;
-  switch (L.smax_max) {
-    case 0:
-      if (mixed) hipLaunchKernelGGL((k_loops<0, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
-      else hipLaunchKernelGGL((k_loops<0, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
-      break;
-    case 2:
-      if (mixed) hipLaunchKernelGGL((k_loops<2, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
-      else hipLaunchKernelGGL((k_loops<2, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
-      break;
-    default:
-      if (mixed) hipLaunchKernelGGL((k_loops<4, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
-      else hipLaunchKernelGGL((k_loops<4, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
-      break;
-  }
-}
-
 void launch_chi_expand(const Launch& L, const ItemRange& r, const double* fin, double* dchi,
                        hipStream_t s) {
   if (r.n <= 0) return;
@@ -1010,13 +796,23 @@ void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed,
     hipLaunchKernelGGL(k_bond_basis, dim3(r.basis.n), dim3(256), 0, s, L.b,
                        L.basis_items + r.basis.begin);
   if (r.gather.n > 0)
-    hipLaunchKernelGGL(k_gather_g2, dim3(r.gather.n), dim3(256), L.gather_smem, s, L.b,
-                       L.gather_items + r.gather.begin);
+    hipLaunchKernelGGL(k_gather_g2, dim3(r.gather.n), dim3(64), 0, s, L.b, L.gather_items + r.gather.begin);
   if (r.inv.n > 0) {
-    if (mixed)
-      hipLaunchKernelGGL(k_dft_inv_mix, dim3(r.inv.n), dim3(256), 0, s, L.b, L.inv_items + r.inv.begin);
-    else
-      hipLaunchKernelGGL(k_dft_inv, dim3(r.inv.n), dim3(256), 0, s, L.b, L.inv_items + r.inv.begin);
+    const int4* it = L.inv_items + r.inv.begin;
+    const dim3 g(r.inv.n), blk(256);
+    if (mixed) {
+      switch (L.inv_lt) {
+        case 1: hipLaunchKernelGGL(k_dft_inv_mix<1>, g, blk, 0, s, L.b, it); break;
+        case 2: hipLaunchKernelGGL(k_dft_inv_mix<2>, g, blk, 0, s, L.b, it); break;
+        default: hipLaunchKernelGGL(k_dft_inv_mix<4>, g, blk, 0, s, L.b, it); break;
+      }
+    } else {
+      switch (L.inv_lt) {
+        case 1: hipLaunchKernelGGL(k_dft_inv<1>, g, blk, 0, s, L.b, it); break;
+        case 2: hipLaunchKernelGGL(k_dft_inv<2>, g, blk, 0, s, L.b, it); break;
+        default: hipLaunchKernelGGL(k_dft_inv<4>, g, blk, 0, s, L.b, it); break;
+      }
+    }
   }
 }
 
@@ -1089,14 +885,6 @@ void launch_step_end(unsigned long long* words, int npts, int* frozen, double* h
                      int nsteps, double xmax, hipStream_t s) {
   hipLaunchKernelGGL(k_step_end, dim3(1), dim3(256), 0, s, words, npts, frozen, hist, step, nsteps,
                      xmax);
-}
-
-const void* loop_kernel_symbol(int smax_max, bool mixed) {
-  switch (smax_max) {
-    case 0: return mixed ? (const void*)k_loops<0, true> : (const void*)k_loops<0, false>;
-    case 2: return mixed ? (const void*)k_loops<2, true> : (const void*)k_loops<2, false>;
-    default: return mixed ? (const void*)k_loops<4, true> : (const void*)k_loops<4, false>;
-  }
 }
 
 }  // namespace tufrg

@@ -1,0 +1,298 @@
+// HIP loop kernel for gfx950 (CDNA4): the temperature-flow loops of the TUfRG
+// right-hand side on the fine momentum grid.
+//
+// Driven by a table of work items (point, a, b, c) like every kernel of the
+// library: one launch covers any set of points with uneven grids and
+// truncations.  Temperatures are read from a per-point device array (so that a
+// captured HIP graph can be replayed with new temperatures), and points whose
+// flow has stopped are skipped through a per-point device flag.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "loop_math.h"
+#include "tufrg_internal.h"
+
+namespace tufrg {
+namespace {
+
+__device__ __forceinline__ bool skip_point(const Batch& b, int p) {
+  return b.frozen != nullptr && b.frozen[p] != 0;
+}
+
+struct DevRcp {
+  __device__ double operator()(double x) const {
+    double r = __builtin_amdgcn_rcp(x);       // hardware estimate, refined by Newton steps
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+  }
+};
+struct Exp2F { __device__ float operator()(float x) const { return __builtin_amdgcn_exp2f(x); } };
+struct RcpF { __device__ float operator()(float x) const { return __builtin_amdgcn_rcpf(x); } };
+
+__device__ __forceinline__ void neumaier_add(float& s, float& c, float v) {
+  const float t = s + v;
+  const bool sbig = fabsf(s) >= fabsf(v);
+  const float big = sbig ? s : v, small = sbig ? v : s;
+  c += (big - t) + small;
+  s = t;
+}
+
+// ------------------------------------------------------------------ loops
+// Step ii.) of Sec. 2.4, eqn. chis, at the point's temperature.  Work item
+// (p, slot * nsplit + split): one representative transfer momentum q =
+// irr[slot] (point-group orbits; every other momentum follows by symmetry in
+// the expansion kernel) and one slice of the rows
+// py in [0, Lk/2] of the fine grid (the loop weight is even in p: the
+// self-paired rows py = 0 and Lk/2 carry weight 1, the others weight 2).
+// Threads own one column px and a chunk of the slice's rows; they accumulate
+// row sums of the loop derivative against cos(n py) and sin(n py), n <= smax.
+// The block contracts the rows against cos(px Sx), sin(px Sx) into
+// ghat(q, S) = (1/Nk) sum_p L'(p) cos(p.S) for the half set of harmonics S in
+// bonds + bonds.
+// In the persistent form queue[0] is the next item and queue[1] counts
+// finished blocks; both are zero at entry, and the last block to finish sets
+// them back to zero for the next launch (device-scope atomics, valid across
+// XCDs).  MIXED selects the FP32 pair math with blocked Neumaier-compensated
+// FP32 row sums; otherwise everything is FP64.
+//
+// One loop work item with the point's exact harmonic count NH = 2 smax + 1
+// (compile-time, so the per-row harmonic loops carry no guards).
+template <int SMAX, bool MIXED>
+__device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, int p, int item_b,
+                                          double* smem) {
+  constexpr int NH = 2 * SMAX + 1;
+  const int t = threadIdx.x;
+  const int nsplit = d.nsplit, nchunk = d.nchunk;
+  const int slot = item_b / nsplit, split = item_b % nsplit;
+  const int q = d.irr[slot];
+  const int lk = d.lk;
+  const int rows = lk / 2 + 1;
+  const int R0 = (int)((int64_t)rows * split / nsplit);
+  const int R1 = (int)((int64_t)rows * (split + 1) / nsplit);
+  const int nr = R1 - R0;
+  const int lq = d.lq;
+  const int ix = q / lq, iy = q % lq;
+  const double T = b.Tp[p];
+  const double inv2T = 0.5 / T;
+
+  double* y1 = smem;                        // cos(py + qy/2)        [nr]
+  double* y2 = y1 + nr;                     // cos(py - qy/2)        [nr]
+  double* pyt = y2 + nr;                    // weighted py harmonics [nr][NH]
+  double* rs = pyt + nr * NH;               // row sums              [lk][2][NH]
+  double* pxs = rs + lk * 2 * NH;           // px harmonics          [lk][NH]
+  double* gh = pxs + lk * NH;               // harmonic partials     [nseg][2 nsh]
+  for (int j = t; j < nr; j += blockDim.x) {
+    const double* c = d.cshift + ((size_t)iy * lk + (R0 + j)) * 2;
+    y1[j] = c[0];
+    y2[j] = c[1];
+  }
+  for (int j = t; j < nr * NH; j += blockDim.x) pyt[j] = d.pytab[R0 * NH + j];
+  for (int j = t; j < lk * 2 * NH; j += blockDim.x) rs[j] = 0.0;
+  for (int j = t; j < lk * NH; j += blockDim.x) pxs[j] = d.pxtab[j];
+  __syncthreads();
+
+  const bool active = t < lk * nchunk;
+  const int px = t % lk, c = t / lk;
+  double acc[2][NH];
+#pragma unroll
+  for (int n = 0; n < NH; ++n) acc[0][n] = acc[1][n] = 0.0;
+  if (active) {
+    const double cx1 = d.cshift[((size_t)ix * lk + px) * 2];       // cos(px + qx/2)
+    const double cx2 = d.cshift[((size_t)ix * lk + px) * 2 + 1];   // cos(px - qx/2)
+    // alpha = eps(p + q/2)/(2T) = A1 + B1 cos(py + qy/2); beta likewise
+    const double A1 = (-2.0 * d.t * cx1 - d.mu) * inv2T;
+    const double B1 = (-2.0 * d.t - 4.0 * d.tp * cx1) * inv2T;
+    const double A2 = (-2.0 * d.t * cx2 - d.mu) * inv2T;
+    const double B2 = (-2.0 * d.t - 4.0 * d.tp * cx2) * inv2T;
+    const int r0 = (int)((int64_t)nr * c / nchunk);
+    const int r1 = (int)((int64_t)nr * (c + 1) / nchunk);
+    if constexpr (!MIXED) {
+#pragma unroll 2
+      for (int r = r0; r < r1; ++r) {
+        const double al = fma(B1, y1[r], A1);
+        const double be = fma(B2, y2[r], A2);
+        double dph, dpp;
+        loop_dot_pair_t(al, be, dph, dpp, DevRcp());
+        const double* w = pyt + r * NH;
+#pragma unroll
+        for (int n = 0; n < NH; ++n) {
+          acc[0][n] = fma(dpp, w[n], acc[0][n]);
+          acc[1][n] = fma(dph, w[n], acc[1][n]);
+        }
+      }
+    } else {
+      // FP32 pair math from FP64 energies; rows blocked by 8 in FP32 and
+      // added into Neumaier-compensated FP32 running sums
+      constexpr int RB = 8;
+      float sum[2][NH], cmp[2][NH];
+#pragma unroll
+      for (int n = 0; n < NH; ++n) sum[0][n] = sum[1][n] = cmp[0][n] = cmp[1][n] = 0.0f;
+      for (int rb = r0; rb < r1; rb += RB) {
+        float blk[2][NH];
+#pragma unroll
+        for (int n = 0; n < NH; ++n) blk[0][n] = blk[1][n] = 0.0f;
+        const int re = min(rb + RB, r1);
+        for (int r = rb; r < re; ++r) {
+          const double al = fma(B1, y1[r], A1);
+          const double be = fma(B2, y2[r], A2);
+          float dph, dpp;
+          loop_dot_pair_f32((float)al, (float)be, (float)(al - be), (float)(al + be), dph, dpp,
+                            Exp2F(), RcpF());
+          const double* w = pyt + r * NH;
+#pragma unroll
+          for (int n = 0; n < NH; ++n) {
+            const float wf = (float)w[n];
+            blk[0][n] = fmaf(dpp, wf, blk[0][n]);
+            blk[1][n] = fmaf(dph, wf, blk[1][n]);
+          }
+        }
+#pragma unroll
+        for (int n = 0; n < NH; ++n) {
+          neumaier_add(sum[0][n], cmp[0][n], blk[0][n]);
+          neumaier_add(sum[1][n], cmp[1][n], blk[1][n]);
+        }
+      }
+#pragma unroll
+      for (int n = 0; n < NH; ++n) {
+        acc[0][n] = (double)sum[0][n] + (double)cmp[0][n];
+        acc[1][n] = (double)sum[1][n] + (double)cmp[1][n];
+      }
+    }
+  }
+  // add the chunks into the row sums one after another (fixed order)
+  for (int cc = 0; cc < nchunk; ++cc) {
+    if (active && c == cc) {
+      double* dst = rs + px * 2 * NH;
+#pragma unroll
+      for (int n = 0; n < NH; ++n) {
+        dst[n] += acc[0][n];
+        dst[NH + n] += acc[1][n];
+      }
+    }
+    __syncthreads();
+  }
+  // contraction over px into the half-set harmonics, split into segments
+  const int nout = 2 * d.nsh;
+  int nseg = (int)blockDim.x / nout;
+  if (nseg < 1) nseg = 1;
+  for (int w = t; w < nout * nseg; w += blockDim.x) {
+    const int o = w % nout, seg = w / nout;
+    const int ch = o / d.nsh, j = o % d.nsh;
+    const int sx = d.hx[j], sy = d.hy[j];          // sx >= 0
+    const int ay = sy < 0 ? -sy : sy;
+    const double sg = sy < 0 ? -1.0 : 1.0;
+    double g = 0.0;
+    for (int x = seg; x < lk; x += nseg) {
+      const double* r = rs + x * 2 * NH + ch * NH;
+      // cos(px sx + py sy) = cos(px sx) cos(py |sy|) - sin(px sx) sgn(sy) sin(py |sy|)
+      double v = pxs[x * NH + sx] * r[ay];
+      if (sx > 0 && ay > 0) v = fma(-sg * pxs[x * NH + SMAX + sx], r[SMAX + ay], v);
+      g += v;
+    }
+    gh[seg * nout + o] = g;
+  }
+  __syncthreads();
+  for (int o = t; o < nout; o += blockDim.x) {
+    double g = 0.0;
+    for (int s = 0; s < nseg; ++s) g += gh[s * nout + o];
+    gh[o] = g;
+  }
+  __syncthreads();
+  // ghat_X(q, S_j) = sgn_X gh_j / (4 T^2 Nk) (pp carries the minus sign of
+  // dL^pp/dT = -Dh/(4T^2)), written to slice `split` of the representative's
+  // harmonics; chi'_mn = sum_j Ebub_{mn,j} ghat(q, S_j) follows in the
+  // expansion kernel.
+  const double base = 1.0 / (4.0 * T * T * (double)lk * (double)lk);
+  for (int o = t; o < nout; o += blockDim.x)
+    b.ghat[d.ws_gh + ((size_t)split * d.nirr + slot) * nout + o] = gh[o] * (o < d.nsh ? -base : base);
+  __syncthreads();
+}
+
+template <int SMAX, bool MIXED>
+__device__ __forceinline__ void loop_dispatch(const Batch& b, const int4 item, double* smem) {
+  const int p = item.x;
+  if (skip_point(b, p)) return;
+  const DevTables& d = b.pts[p];
+  if constexpr (SMAX >= 4) {
+    if (d.smax == 4) {
+      loop_item<4, MIXED>(b, d, p, item.y, smem);
+      return;
+    }
+  }
+  if constexpr (SMAX >= 2) {
+    if (d.smax == 2) {
+      loop_item<2, MIXED>(b, d, p, item.y, smem);
+      return;
+    }
+  }
+  loop_item<0, MIXED>(b, d, p, item.y, smem);
+}
+
+// Loop kernel over work items (p, q * nsplit + split); SMAX is the largest
+// smax of the batch, and each item runs the body compiled for its own smax.
+// Without a queue every block runs item blockIdx.x (the hardware dispatcher
+// balances the load, items being ordered costliest first); with a queue the
+// kernel is persistent and blocks take items until the queue is empty.
+template <int SMAX, bool MIXED>
+__global__ void __launch_bounds__(kLoopThreadsMax)
+k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ queue) {
+  extern __shared__ double smem[];
+  __shared__ int cur;
+  if (b.item_count != nullptr) nitems = min(nitems, *b.item_count);
+  if (queue == nullptr) {
+    if ((int)blockIdx.x < nitems) loop_dispatch<SMAX, MIXED>(b, items[blockIdx.x], smem);
+    return;
+  }
+  const int t = threadIdx.x;
+  for (;;) {
+    if (t == 0) cur = atomicAdd(queue, 1);
+    __syncthreads();
+    const int it = cur;
+    __syncthreads();
+    if (it >= nitems) break;
+    loop_dispatch<SMAX, MIXED>(b, items[it], smem);
+  }
+  if (t == 0 && atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {
+    atomicExch(queue, 0);
+    atomicExch(queue + 1, 0);
+  }
+}
+
+}  // namespace
+
+void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, hipStream_t s) {
+  if (r.n <= 0) return;
+  if (!L.loop_persistent) queue = nullptr;
+  const int grid = L.loop_persistent ? std::min(r.n, L.loop_blocks) : r.n;
+  const dim3 blk(L.loop_threads);
+  const size_t sm = L.loop_smem;
+  const int4* it = L.loop_items + r.begin;
+  switch (L.smax_max) {
+    case 0:
+      if (mixed) hipLaunchKernelGGL((k_loops<0, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
+      else hipLaunchKernelGGL((k_loops<0, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
+      break;
+    case 2:
+      if (mixed) hipLaunchKernelGGL((k_loops<2, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
+      else hipLaunchKernelGGL((k_loops<2, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
+      break;
+    default:
+      if (mixed) hipLaunchKernelGGL((k_loops<4, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
+      else hipLaunchKernelGGL((k_loops<4, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
+      break;
+  }
+}
+
+const void* loop_kernel_symbol(int smax_max, bool mixed) {
+  switch (smax_max) {
+    case 0: return mixed ? (const void*)k_loops<0, true> : (const void*)k_loops<0, false>;
+    case 2: return mixed ? (const void*)k_loops<2, true> : (const void*)k_loops<2, false>;
+    default: return mixed ? (const void*)k_loops<4, true> : (const void*)k_loops<4, false>;
+  }
+}
+
+}  // namespace tufrg

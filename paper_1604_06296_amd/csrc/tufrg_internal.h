@@ -77,6 +77,7 @@ int nff_of_shells(int shells);
 constexpr int kLoopThreadsMax = 512;   // loop kernel block size bound
 constexpr int kMaxLT = 4;              // momenta per block of the FP64 back end
 constexpr int kSeg = 4096;             // elements per ODE segment item
+constexpr int kShellMax = 8;           // largest form-factor shell (bonds up to |R|^2 = 5)
 constexpr int kEpad = 80;              // padded row length of the phase table copy (ncol <= 69)
 
 // Per-point tables and launch parameters as seen by the kernels (device array).
@@ -153,8 +154,9 @@ struct Launch {
   const int4* seg_items;
   int loop_threads, loop_blocks, smax_max;
   int fwd_kt;             // forward transform: 16-row harmonic tiles (1, 2, 3 or 5)
+  int inv_lt;             // inverse transform: 16-momentum tiles per item (1, 2 or 4)
   bool loop_persistent;   // loop kernel: persistent work queue, or one block per item
-  size_t loop_smem, gather_smem, prod_smem;
+  size_t loop_smem, prod_smem;
 };
 
 // Surrogate state of a single-point context (device pointers and settings).
