@@ -101,17 +101,26 @@ enum {
                                instead of one representative per C4v orbit (a
                                test seam: the point-group reduction is exact up
                                to rounding) */
-  TUFRG_LOOP_QUEUE = 1u << 2 /* run the loop kernel as persistent blocks that take
+  TUFRG_LOOP_QUEUE = 1u << 2, /* run the loop kernel as persistent blocks that take
                                work items from a queue (default: one block per work
                                item, items ordered costliest first); bit-identical
                                results.  TUFRG_AUTOTUNE times both forms and keeps
                                the faster, whatever this bit says. */
+  TUFRG_NO_FUSE = 1u << 4  /* never run the right-hand side in fused launches.  By
+                               default a context whose channel state (sum of
+                               Nq Nff^2 over its points) is at most 2^18 runs the
+                               loops and the projections in shared launches on one
+                               stream (small problems are bound by launch and
+                               synchronisation cost); larger ones, and every
+                               context with this bit, the surrogate or the loop
+                               queue, run the loops on a second stream alongside
+                               the projections.  Bit-identical results. */
 };
 
 typedef struct {
   int32_t precision;       /* TUFRG_FP64 or TUFRG_MIXED */
   uint32_t flags;          /* TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE |
-                              TUFRG_NO_SYMMETRY */
+                              TUFRG_NO_SYMMETRY | TUFRG_NO_FUSE */
 } tufrg_options;
 
 enum { TUFRG_RK4_LOG = 0, TUFRG_DOPRI5_LOG = 1 };

@@ -18,6 +18,7 @@ NO_CROSS = 1
 AUTOTUNE = 2
 LOOP_QUEUE = 4
 NO_SYMMETRY = 8
+NO_FUSE = 16
 
 # every entry point declared in include/tufrg.h
 EXPORTS = ("tufrg_init", "tufrg_layout", "tufrg_geometry", "tufrg_bubbles", "tufrg_project",
@@ -260,7 +261,7 @@ class Context:
 
     def __init__(self, points: Sequence, precision: str = "fp64", no_cross: bool = False,
                  stream=None, autotune: bool = False, loop_queue: bool = False,
-                 no_symmetry: bool = False):
+                 no_symmetry: bool = False, fuse: bool = True):
         import torch
         if not torch.cuda.is_available():
             raise TufrgError("a GPU is required (torch.cuda.is_available() is False)")
@@ -274,7 +275,8 @@ class Context:
             arr[i] = _Point(p.t, p.tp, p.mu, p.U, p.Lq, p.Lk, p.shells, 0)
         opt = _Options(PRECISIONS[precision],
                        (NO_CROSS if no_cross else 0) | (AUTOTUNE if autotune else 0)
-                       | (LOOP_QUEUE if loop_queue else 0) | (NO_SYMMETRY if no_symmetry else 0))
+                       | (LOOP_QUEUE if loop_queue else 0) | (NO_SYMMETRY if no_symmetry else 0)
+                       | (0 if fuse else NO_FUSE))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = C.c_void_p()
         _check(self.lib, None, self.lib.tufrg_init(arr, n, C.byref(opt),

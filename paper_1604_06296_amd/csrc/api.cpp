@@ -138,7 +138,7 @@ void mark(std::vector<int4>& v, ItemRange& rg, F fill) {
 
 // The work items of point p for every kernel, appended to h; r receives the
 // point's ranges.  Item layouts are those documented at each kernel.
-void add_point_items(const DevTables& d, int p, int inv_lt, HostItems& h, Ranges& r) {
+void add_point_items(const DevTables& d, int p, int inv_lt, int fwd_cols, HostItems& h, Ranges& r) {
   const int nff2 = d.nff * d.nff, nv = 2 * d.nsh - 1;
   mark(h.exp, r.exp, [&](std::vector<int4>& v) {
     for (int rt = 0; rt < (2 * d.nq + 31) / 32; ++rt)
@@ -146,7 +146,7 @@ void add_point_items(const DevTables& d, int p, int inv_lt, HostItems& h, Ranges
   });
   mark(h.fwd, r.fwd, [&](std::vector<int4>& v) {
     for (int sp = 0; sp < d.nsu; ++sp)
-      for (int c = 0; c < (3 * nff2 + 63) / 64; ++c) v.push_back(make_int4(p, c, sp, 0));
+      for (int c = 0; c < (3 * nff2 + fwd_cols - 1) / fwd_cols; ++c) v.push_back(make_int4(p, c, sp, 0));
   });
   mark(h.inv, r.inv, [&](std::vector<int4>& v) {
     for (int lt = 0; lt < (d.nq + 16 * inv_lt - 1) / (16 * inv_lt); ++lt)
@@ -209,15 +209,23 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
     for (int i = 0; i < 3; ++i)
       inv_items[i] += (int64_t)((d.nq + (16 << i) - 1) / (16 << i)) * ((3 * d.nff * d.nff + 63) / 64);
   const int inv_lt = inv_items[2] >= 512 ? 4 : (inv_items[1] >= 512 ? 2 : 1);
-  for (int p = 0; p < npts; ++p) add_point_items(ctx->dev[p], p, inv_lt, h, ctx->per_point[p]);
-  int smax_max = 0, threads = 64;
+  // loop block (the largest point's loop geometry).  Small problems are
+  // bound by launch and synchronisation cost: there the loops share launches
+  // with the projections on one stream (the forward transform then runs in
+  // blocks of the loops' size, 16 columns per wave); larger ones overlap the
+  // two on two streams.
+  int threads = 64;
+  for (const DevTables& d : ctx->dev) threads = std::max(threads, round64(d.lk * d.nchunk));
+  const bool fused = ctx->S <= kFuseMaxState && !ctx->loop_persistent && !(ctx->opt.flags & TUFRG_NO_FUSE);
+  const int front_threads = fused ? std::max(threads, 256) : 256, fwd_cols = 16 * (front_threads / 64);
+  for (int p = 0; p < npts; ++p) add_point_items(ctx->dev[p], p, inv_lt, fwd_cols, h, ctx->per_point[p]);
+  int smax_max = 0;
   size_t lsm = 0, psm = 0;
   int kpt = 1;
   int64_t gh = 0, ghs = 0;
   for (int p = 0; p < npts; ++p) {
     DevTables& d = ctx->dev[p];
     smax_max = std::max(smax_max, d.smax);
-    threads = std::max(threads, round64(d.lk * d.nchunk));
     const int nff2 = d.nff * d.nff;
     psm = std::max(psm, sizeof(double) * 12 * (size_t)nff2);
     kpt = std::max(kpt, (d.ncol + 15) / 16);
@@ -229,9 +237,11 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   ctx->ghat_len = gh;
   ctx->ghat_sum_len = ghs;
   for (int p = 0; p < npts; ++p) lsm = std::max(lsm, loop_smem_of(ctx->dev[p], threads));
+  const int fwd_kt = kpt <= 3 ? kpt : 5;
+  const size_t fsm = mixed ? 0 : sizeof(double) * 32 * ((size_t)(16 * fwd_kt + 2) + (size_t)(fwd_cols + 2));
   int dev_smem = 0;
   hipDeviceGetAttribute(&dev_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
-  if (dev_smem > 0 && (lsm > (size_t)dev_smem || psm > (size_t)dev_smem))
+  if (dev_smem > 0 && (lsm > (size_t)dev_smem || psm > (size_t)dev_smem || fsm > (size_t)dev_smem))
     return fail(ctx, TUFRG_EINVAL, "grids too large for the shared memory of one block");
   auto whole = [](const std::vector<int4>& v) {
     ItemRange r;
@@ -266,8 +276,13 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   L.loop_threads = threads;
   L.loop_smem = lsm;
   L.prod_smem = psm;
-  L.fwd_kt = kpt <= 3 ? kpt : 5;
+  L.fwd_kt = fwd_kt;
   L.inv_lt = inv_lt;
+  L.front_threads = front_threads;
+  L.fused = fused;
+  L.fwd_smem = fsm;
+  L.front_smem = std::max(lsm, fsm);
+  L.b.loop_threads = threads;
   // persistent loop grid: every CU filled to the kernel's occupancy
   int per_cu = 0, cus = 0;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
@@ -316,11 +331,24 @@ void loops_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, double* dchi
   launch_chi_expand(L, r.exp, nullptr, dchi, s);
 }
 
-// The temperatures are set by set_T on the side stream, ahead of the loops
-// and off the projections' path; the back end reads them after the join.
+// One right-hand side on stream ms.  The loops and the projections are
+// independent until the products, so they share launches on one stream:
+// (loops + forward transform), (loop expansion + bond basis), gather,
+// inverse transform, products, when the context is small enough for launch
+// costs to dominate (Launch::fused).  Otherwise, and with the surrogate, the
+// loops run on the side stream (fork and join by events) alongside the
+// whole projection chain.
 void rhs_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, const double* X, double* out,
                 bool scale_T, hipStream_t ms, const std::function<void(hipStream_t)>& set_T) {
   const bool mixed = mixed_of(ctx), cross = cross_of(ctx);
+  if (!ctx->sur_a && L.fused) {
+    set_T(ms);
+    launch_loops_fwd(L, r, X, mixed, cross, ms);
+    launch_expand_basis(L, r, L.b.dchi, cross, ms);
+    if (cross) launch_gather_inv(L, r, mixed, ms);
+    launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms);
+    return;
+  }
   hipEventRecord(ctx->ev_fork, ms);
   hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
   set_T(ctx->side);
@@ -461,7 +489,8 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   if (opt) o = *opt;
   if (o.precision != TUFRG_FP64 && o.precision != TUFRG_MIXED)
     return fail(nullptr, TUFRG_EINVAL, "precision must be TUFRG_FP64 or TUFRG_MIXED");
-  if (o.flags & ~(uint32_t)(TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE | TUFRG_NO_SYMMETRY))
+  if (o.flags & ~(uint32_t)(TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE | TUFRG_NO_SYMMETRY |
+                            TUFRG_NO_FUSE))
     return fail(nullptr, TUFRG_EINVAL, "unknown flag bits");
   auto* ctx = new tufrg_ctx();
   ctx->opt = o;

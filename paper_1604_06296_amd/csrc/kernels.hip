@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "transforms.h"
 #include "tufrg_internal.h"
 
 namespace tufrg {
@@ -29,15 +30,17 @@ __device__ __forceinline__ bool skip_point(const Batch& b, int p) {
 // harmonics are the sums of their loop slices, or come from fin
 // [nirr][2][nsh] (single point).  Each thread owns 2 rows x 4 columns.
 constexpr int kExpRows = 32, kExpCols = 64, kExpK = 36;
-__global__ void __launch_bounds__(256)
-k_chi_expand(Batch b, const int4* __restrict__ items, const double* __restrict__ fin,
-             double* __restrict__ dchi) {
-  __shared__ double As[kExpRows][kExpK];
-  __shared__ double Bs[kExpK][kExpCols];
-  const int4 item = items[blockIdx.x];
+struct alignas(16) ExpandShared {
+  double As[kExpRows][kExpK];
+  double Bs[kExpK][kExpCols];
+};
+__device__ __forceinline__ void expand_body(const Batch& b, const int4 item, const double* __restrict__ fin,
+                                            double* __restrict__ dchi, ExpandShared& sh) {
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
+  auto& As = sh.As;
+  auto& Bs = sh.Bs;
   const int nq = d.nq, nsh = d.nsh, nout = 2 * nsh, nff2 = d.nff * d.nff;
   const int r0 = item.y * kExpRows, c0 = item.z * kExpCols;
   const int tid = threadIdx.x;
@@ -112,71 +115,23 @@ k_chi_expand(Batch b, const int4* __restrict__ items, const double* __restrict__
   }
 }
 
-// ------------------------------------------------------- projections
-// Forward transform: the partial Fourier sums over the transfer grid at the
-// half-integer frequencies S/2,
-//   xt[ch][k][mn] = (1/Nq) sum_u E[u][k] X[ch][u][mn],  E = (cos(u.S'/2) | sin(u.S'/2)),
-// as a contraction on the FP64 matrix cores, split over the transfer grid.
-// Item (p, column tile c, transfer split s): 64 consecutive columns (ch, mn)
-// against KT tiles of 16 harmonic rows k (E from its copy padded with zero
-// columns to kEpad).  Chunks of 32 momenta u pass through LDS; wave w owns
-// 16 columns and KT accumulator tiles of v_mfma_f64_16x16x4f64 (lane l holds
-// A[l%16][l/16], B[l/16][l%16] and, in register j, D[4j+l/16][l%16]).  Partial sums go to
-// xp[s][k][col]; the bond-basis kernel adds the splits in order.
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-template <int KT>
 __global__ void __launch_bounds__(256)
+k_chi_expand(Batch b, const int4* __restrict__ items, const double* __restrict__ fin,
+             double* __restrict__ dchi) {
+  __shared__ ExpandShared sh;
+  expand_body(b, items[blockIdx.x], fin, dchi, sh);
+}
+
+// ------------------------------------------------------- projections
+// Forward transform (bodies and layout in transforms.h): FP64 on the matrix
+// cores, with the LDS staging in dynamic shared memory.
+template <int KT>
+__global__ void __launch_bounds__(kLoopThreadsMax)
 k_dft_fwd_part(Batch b, const int4* __restrict__ items, const double* __restrict__ X) {
-  constexpr int TK = 16 * KT;
-  __shared__ double Es[32][TK + 2];
-  __shared__ double Xs[32][64 + 2];
+  extern __shared__ double smem_fwd[];
   const int4 item = items[blockIdx.x];
-  const int p = item.x;
-  if (skip_point(b, p)) return;
-  const DevTables& d = b.pts[p];
-  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
-  const int c0 = item.y * 64, split = item.z;
-  const int u0 = (int)((int64_t)nq * split / d.nsu), u1 = (int)((int64_t)nq * (split + 1) / d.nsu);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int r16 = lane & 15, k4 = lane >> 4;
-  const double* Xp = X + d.off;
-  f64x4 acc[KT];
-#pragma unroll
-  for (int t = 0; t < KT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int ub = u0; ub < u1; ub += 32) {
-    for (int e = tid; e < 32 * TK; e += 256) {
-      const int uu = e / TK, k = e % TK, u = ub + uu;
-      Es[uu][k] = u < u1 ? d.ephp[(size_t)u * kEpad + k] : 0.0;
-    }
-    for (int e = tid; e < 32 * 64; e += 256) {
-      const int uu = e >> 6, c = e & 63, u = ub + uu, col = c0 + c;
-      double v = 0.0;
-      if (u < u1 && col < N) {
-        const int ch = col / nff2, mn = col % nff2;
-        v = Xp[(size_t)ch * b.S + (size_t)u * nff2 + mn];
-      }
-      Xs[uu][c] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int uk = 0; uk < 32; uk += 4) {
-      const double bv = Xs[uk + k4][16 * w + r16];
-#pragma unroll
-      for (int t = 0; t < KT; ++t)
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Es[uk + k4][16 * t + r16], bv, acc[t], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-  double* out = b.xp + d.ws_xp + (size_t)split * ncol * N;
-  const int col = c0 + 16 * w + r16;
-  if (col >= N) return;
-#pragma unroll
-  for (int t = 0; t < KT; ++t)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = 16 * t + 4 * j + k4;
-      if (k < ncol) out[(size_t)k * N + col] = acc[t][j];
-    }
+  if (skip_point(b, item.x)) return;
+  fwd_part_body<KT>(b, b.pts[item.x], item, X, smem_fwd);
 }
 
 // Bond basis of the transformed propagators, for every harmonic of the full
@@ -187,9 +142,11 @@ k_dft_fwd_part(Batch b, const int4* __restrict__ items, const double* __restrict
 // Item (p, in * nv + v): the harmonic's transform and the coefficients are
 // staged in LDS; threads own bond pairs (b1, b2).  The transform is the
 // in-order FP64 sum of the forward-transform splits (xp), taken here.
-__global__ void __launch_bounds__(256)
-k_bond_basis(Batch b, const int4* __restrict__ items) {
-  const int4 item = items[blockIdx.x];
+struct alignas(16) BasisShared {
+  double cs[2 * 441];
+  double xs[2 * 441];
+};
+__device__ __forceinline__ void basis_body(const Batch& b, const int4 item, BasisShared& sh) {
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
@@ -198,8 +155,8 @@ k_bond_basis(Batch b, const int4* __restrict__ items) {
   const int in = item.y / nv, v = item.y % nv;
   const int j = v < nsh ? v : v - nsh + 1;
   const double sim = v < nsh ? 1.0 : -1.0;
-  __shared__ double cs[2 * 441];
-  __shared__ double xs[2 * 441];
+  double* cs = sh.cs;
+  double* xs = sh.xs;
   {
     // 2 nff^2 sums of nsu terms; each thread keeps up to 4 sums and 8 splits
     // of each in flight, then adds them in split order
@@ -265,6 +222,26 @@ k_bond_basis(Batch b, const int4* __restrict__ items) {
     yb[idx] = yr;
     yb[(size_t)total + idx] = yi;
   }
+}
+
+__global__ void __launch_bounds__(256)
+k_bond_basis(Batch b, const int4* __restrict__ items) {
+  __shared__ BasisShared sh;
+  basis_body(b, items[blockIdx.x], sh);
+}
+
+// The loop expansion and the bond basis in one launch (they are independent:
+// the expansion reads the loop kernel's harmonics, the basis the forward
+// transform's partial sums): blocks below nexp expand, the others transform.
+__global__ void __launch_bounds__(256)
+k_expand_basis(Batch b, const int4* __restrict__ exp_items, int nexp, const int4* __restrict__ basis_items,
+               double* __restrict__ dchi) {
+  __shared__ union {
+    ExpandShared e;
+    BasisShared s;
+  } sh;
+  if ((int)blockIdx.x < nexp) expand_body(b, exp_items[blockIdx.x], nullptr, dchi, sh.e);
+  else basis_body(b, basis_items[blockIdx.x - nexp], sh.s);
 }
 
 // Gather and basis change, independent of the transfer momentum.  For
@@ -409,86 +386,14 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
 }
 
 // ======================================================= mixed precision
-// BF16 hi/lo split with round to nearest even: x ~ hi + lo (about 16 mantissa
-// bits); products hi*hi + hi*lo + lo*hi accumulate in FP32 on the matrix cores.
-// v_mfma_f32_16x16x16bf16_1k operand layout: lane l holds A[l%16][4(l/16)+j],
-// B[4(l/16)+j][l%16] (j = 0..3) and D[4(l/16)+j][l%16].
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ unsigned short bf16_rne(float f) {
-  unsigned int u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
-  return __uint_as_float(((unsigned int)h) << 16);
-}
-__device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigned short& lo) {
-  const float f = (float)x;
-  hi = bf16_rne(f);
-  lo = bf16_rne(f - bf16_to_f32(hi));
-}
-
-// Forward transform in split precision: the same contraction and output as
-// the FP64 form (partial sums over transfer splits in xp, added in order by
-// the bond-basis kernel), with products hi*hi + hi*lo + lo*hi of the BF16
-// splits accumulated in FP32 over one split.  Item (p, column tile c, split
-// s); splits start on multiples of 16 momenta.  Wave w owns 16 columns; per
-// step of 16 momenta each lane loads its 4 values of X (split on the fly) and,
-// for each of the KT harmonic tiles, one quad of the pre-split phase table
-// laid out [u/4][kEpad][4] (zero beyond Nq), straight from the cache: there
-// is no reuse across waves worth an LDS pass.
+// (BF16 hi/lo split helpers and the split-precision forward body in
+// transforms.h.)
 template <int KT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kLoopThreadsMax)
 k_dft_fwd_mix(Batch b, const int4* __restrict__ items, const double* __restrict__ X) {
   const int4 item = items[blockIdx.x];
-  const int p = item.x;
-  if (skip_point(b, p)) return;
-  const DevTables& d = b.pts[p];
-  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
-  const int split = item.z, nq16 = (nq + 15) >> 4;
-  const int u0 = 16 * (int)((int64_t)nq16 * split / d.nsu);
-  const int u1 = 16 * (int)((int64_t)nq16 * (split + 1) / d.nsu);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r16 = lane & 15, k4 = lane >> 4;
-  const int col = item.y * 64 + 16 * w + r16;
-  const bool cok = col < N;
-  const int ch = cok ? col / nff2 : 0, mn = cok ? col % nff2 : 0;
-  const double* xc = X + d.off + (size_t)ch * b.S + mn;
-  const bf16x4* eh = reinterpret_cast<const bf16x4*>(d.ephq_hi);
-  const bf16x4* el = reinterpret_cast<const bf16x4*>(d.ephq_lo);
-  f32x4 acc[KT];
-#pragma unroll
-  for (int t = 0; t < KT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int ub = u0; ub < u1; ub += 16) {
-    bf16x4 bh, bl;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int u = ub + 4 * k4 + j;
-      unsigned short h = 0, l = 0;
-      if (cok && u < nq) split_bf16(xc[(size_t)u * nff2], h, l);
-      bh[j] = (short)h;
-      bl[j] = (short)l;
-    }
-    const size_t qrow = (size_t)((ub >> 2) + k4) * kEpad;
-#pragma unroll
-    for (int t = 0; t < KT; ++t) {
-      const bf16x4 ah = eh[qrow + 16 * t + r16], al = el[qrow + 16 * t + r16];
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[t], 0, 0, 0);
-    }
-  }
-  if (!cok) return;
-  double* out = b.xp + d.ws_xp + (size_t)split * ncol * N;
-#pragma unroll
-  for (int t = 0; t < KT; ++t)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = 16 * t + 4 * k4 + j;
-      if (k < ncol) out[(size_t)k * N + col] = (double)acc[t][j];
-    }
+  if (skip_point(b, item.x)) return;
+  fwd_mix_body<KT>(b, b.pts[item.x], item, X);
 }
 
 // Inverse transform in split precision: K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn]
@@ -772,29 +677,29 @@ void launch_chi_expand(const Launch& L, const ItemRange& r, const double* fin, d
   hipLaunchKernelGGL(k_chi_expand, dim3(r.n), dim3(256), 0, s, L.b, L.exp_items + r.begin, fin, dchi);
 }
 
-void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s) {
-  if (r.fwd.n > 0) {
-    const int4* it = L.fwd_items + r.fwd.begin;
-    const dim3 g(r.fwd.n), blk(256);
-    if (mixed) {
-      switch (L.fwd_kt) {
-        case 1: hipLaunchKernelGGL(k_dft_fwd_mix<1>, g, blk, 0, s, L.b, it, X); break;
-        case 2: hipLaunchKernelGGL(k_dft_fwd_mix<2>, g, blk, 0, s, L.b, it, X); break;
-        case 3: hipLaunchKernelGGL(k_dft_fwd_mix<3>, g, blk, 0, s, L.b, it, X); break;
-        default: hipLaunchKernelGGL(k_dft_fwd_mix<5>, g, blk, 0, s, L.b, it, X); break;
-      }
-    } else {
-      switch (L.fwd_kt) {
-        case 1: hipLaunchKernelGGL(k_dft_fwd_part<1>, g, blk, 0, s, L.b, it, X); break;
-        case 2: hipLaunchKernelGGL(k_dft_fwd_part<2>, g, blk, 0, s, L.b, it, X); break;
-        case 3: hipLaunchKernelGGL(k_dft_fwd_part<3>, g, blk, 0, s, L.b, it, X); break;
-        default: hipLaunchKernelGGL(k_dft_fwd_part<5>, g, blk, 0, s, L.b, it, X); break;
-      }
+void launch_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s) {
+  if (r.fwd.n <= 0) return;
+  const int4* it = L.fwd_items + r.fwd.begin;
+  const dim3 g(r.fwd.n), blk(L.front_threads);
+  if (mixed) {
+    switch (L.fwd_kt) {
+      case 1: hipLaunchKernelGGL(k_dft_fwd_mix<1>, g, blk, 0, s, L.b, it, X); break;
+      case 2: hipLaunchKernelGGL(k_dft_fwd_mix<2>, g, blk, 0, s, L.b, it, X); break;
+      case 3: hipLaunchKernelGGL(k_dft_fwd_mix<3>, g, blk, 0, s, L.b, it, X); break;
+      default: hipLaunchKernelGGL(k_dft_fwd_mix<5>, g, blk, 0, s, L.b, it, X); break;
+    }
+  } else {
+    const size_t sm = L.fwd_smem;
+    switch (L.fwd_kt) {
+      case 1: hipLaunchKernelGGL(k_dft_fwd_part<1>, g, blk, sm, s, L.b, it, X); break;
+      case 2: hipLaunchKernelGGL(k_dft_fwd_part<2>, g, blk, sm, s, L.b, it, X); break;
+      case 3: hipLaunchKernelGGL(k_dft_fwd_part<3>, g, blk, sm, s, L.b, it, X); break;
+      default: hipLaunchKernelGGL(k_dft_fwd_part<5>, g, blk, sm, s, L.b, it, X); break;
     }
   }
-  if (r.basis.n > 0)
-    hipLaunchKernelGGL(k_bond_basis, dim3(r.basis.n), dim3(256), 0, s, L.b,
-                       L.basis_items + r.basis.begin);
+}
+
+void launch_gather_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t s) {
   if (r.gather.n > 0)
     hipLaunchKernelGGL(k_gather_g2, dim3(r.gather.n), dim3(64), 0, s, L.b, L.gather_items + r.gather.begin);
   if (r.inv.n > 0) {
@@ -814,6 +719,20 @@ void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed,
       }
     }
   }
+}
+
+void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s) {
+  launch_fwd(L, r, X, mixed, s);
+  if (r.basis.n > 0)
+    hipLaunchKernelGGL(k_bond_basis, dim3(r.basis.n), dim3(256), 0, s, L.b, L.basis_items + r.basis.begin);
+  launch_gather_inv(L, r, mixed, s);
+}
+
+void launch_expand_basis(const Launch& L, const Ranges& r, double* dchi, bool cross, hipStream_t s) {
+  const int nb = cross ? r.basis.n : 0;
+  if (r.exp.n + nb <= 0) return;
+  hipLaunchKernelGGL(k_expand_basis, dim3(r.exp.n + nb), dim3(256), 0, s, L.b, L.exp_items + r.exp.begin,
+                     r.exp.n, L.basis_items + r.basis.begin, dchi);
 }
 
 void launch_back(const Launch& L, const Ranges& r, const double* X, double* out, int mode,

@@ -12,6 +12,7 @@
 #include <cstdint>
 
 #include "loop_math.h"
+#include "transforms.h"
 #include "tufrg_internal.h"
 
 namespace tufrg {
@@ -176,8 +177,10 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
     __syncthreads();
   }
   // contraction over px into the half-set harmonics, split into segments
+  // (the segment count follows the launch's loop geometry, not the block
+  // size, so that every launch form sums in the same order)
   const int nout = 2 * d.nsh;
-  int nseg = (int)blockDim.x / nout;
+  int nseg = b.loop_threads / nout;
   if (nseg < 1) nseg = 1;
   for (int w = t; w < nout * nseg; w += blockDim.x) {
     const int o = w % nout, seg = w / nout;
@@ -262,6 +265,41 @@ k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ q
   }
 }
 
+// The loops and the forward transform of the projections in one launch (they
+// are independent: the loops read only the temperature, the transform only
+// the couplings): blocks below nloop run loop items, the others forward-
+// transform items, so that both fill the machine together without a second
+// stream.  Dynamic shared memory holds the larger of the two layouts.
+template <int SMAX, bool MIXED, int KT>
+__global__ void __launch_bounds__(kLoopThreadsMax)
+k_loops_fwd(Batch b, const int4* __restrict__ loop_items, int nloop, const int4* __restrict__ fwd_items,
+            const double* __restrict__ X) {
+  extern __shared__ double smem[];
+  if ((int)blockIdx.x < nloop) {
+    loop_dispatch<SMAX, MIXED>(b, loop_items[blockIdx.x], smem);
+    return;
+  }
+  const int4 item = fwd_items[blockIdx.x - nloop];
+  if (skip_point(b, item.x)) return;
+  if constexpr (MIXED) fwd_mix_body<KT>(b, b.pts[item.x], item, X);
+  else fwd_part_body<KT>(b, b.pts[item.x], item, X, smem);
+}
+
+template <int SMAX, bool MIXED>
+void launch_loops_fwd_kt(const Launch& L, const Ranges& r, const double* X, bool cross, hipStream_t s) {
+  const int nf = cross ? r.fwd.n : 0;
+  const dim3 g(r.loop.n + nf), blk(L.front_threads);
+  const size_t sm = L.front_smem;
+  const int4* li = L.loop_items + r.loop.begin;
+  const int4* fi = L.fwd_items + r.fwd.begin;
+  switch (L.fwd_kt) {
+    case 1: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 1>), g, blk, sm, s, L.b, li, r.loop.n, fi, X); break;
+    case 2: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 2>), g, blk, sm, s, L.b, li, r.loop.n, fi, X); break;
+    case 3: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 3>), g, blk, sm, s, L.b, li, r.loop.n, fi, X); break;
+    default: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 5>), g, blk, sm, s, L.b, li, r.loop.n, fi, X); break;
+  }
+}
+
 }  // namespace
 
 void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, hipStream_t s) {
@@ -283,6 +321,25 @@ void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, h
     default:
       if (mixed) hipLaunchKernelGGL((k_loops<4, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
       else hipLaunchKernelGGL((k_loops<4, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
+      break;
+  }
+}
+
+void launch_loops_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, bool cross,
+                      hipStream_t s) {
+  if (r.loop.n + (cross ? r.fwd.n : 0) <= 0) return;
+  switch (L.smax_max) {
+    case 0:
+      if (mixed) launch_loops_fwd_kt<0, true>(L, r, X, cross, s);
+      else launch_loops_fwd_kt<0, false>(L, r, X, cross, s);
+      break;
+    case 2:
+      if (mixed) launch_loops_fwd_kt<2, true>(L, r, X, cross, s);
+      else launch_loops_fwd_kt<2, false>(L, r, X, cross, s);
+      break;
+    default:
+      if (mixed) launch_loops_fwd_kt<4, true>(L, r, X, cross, s);
+      else launch_loops_fwd_kt<4, false>(L, r, X, cross, s);
       break;
   }
 }

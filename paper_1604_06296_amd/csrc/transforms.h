@@ -1,0 +1,160 @@
+// Device bodies of the forward transform of the projections (Sec. 2.4,
+// eqns. proj_VP/VC/VD: the Fourier sums of the channel couplings over the
+// transfer grid), shared by the stand-alone forward-transform kernels and by
+// the combined loop + forward-transform launch of the right-hand side.
+//
+// The transforms are the partial sums over one split of the transfer grid at
+// the half-integer frequencies S/2,
+//   xp[s][k][ch mn] = sum_{u in split s} E[u][k] X[ch][u][mn],
+//   E = (cos(u.S'/2) | sin(u.S'/2)),
+// with the splits added in order (and divided by Nq) by the bond-basis
+// kernel.  A block of nw = blockDim.x / 64 waves owns 16 nw consecutive
+// columns (ch, mn); wave w owns 16 of them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "tufrg_internal.h"
+
+namespace tufrg {
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+// BF16 hi/lo split with round to nearest even: x ~ hi + lo (about 16 mantissa
+// bits); products hi*hi + hi*lo + lo*hi accumulate in FP32 on the matrix cores.
+// v_mfma_f32_16x16x16bf16_1k operand layout: lane l holds A[l%16][4(l/16)+j],
+// B[4(l/16)+j][l%16] (j = 0..3) and D[4(l/16)+j][l%16].
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+  return __uint_as_float(((unsigned int)h) << 16);
+}
+__device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigned short& lo) {
+  const float f = (float)x;
+  hi = bf16_rne(f);
+  lo = bf16_rne(f - bf16_to_f32(hi));
+}
+
+// FP64 on the matrix cores.  Item (p, column tile c, transfer split s): the
+// block's columns against KT tiles of 16 harmonic rows k (E from its copy
+// padded with zero columns to kEpad).  Chunks of 32 momenta u pass through
+// LDS (smem holds fwd_smem_bytes(KT, 16 nw)); wave w accumulates KT tiles of
+// v_mfma_f64_16x16x4f64 (lane l holds A[l%16][l/16], B[l/16][l%16] and, in
+// register j, D[4j+l/16][l%16]).
+template <int KT>
+__device__ __forceinline__ void fwd_part_body(const Batch& b, const DevTables& d, const int4 item,
+                                              const double* __restrict__ X, double* smem) {
+  constexpr int TK = 16 * KT, ES = TK + 2;
+  const int nw = (int)blockDim.x >> 6, CW = 16 * nw, XS = CW + 2;
+  double* Es = smem;             // [32][ES]
+  double* Xs = smem + 32 * ES;   // [32][XS]
+  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
+  const int c0 = item.y * CW, split = item.z;
+  const int u0 = (int)((int64_t)nq * split / d.nsu), u1 = (int)((int64_t)nq * (split + 1) / d.nsu);
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  const double* Xp = X + d.off;
+  f64x4 acc[KT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int ub = u0; ub < u1; ub += 32) {
+    for (int e = tid; e < 32 * TK; e += nt) {
+      const int uu = e / TK, k = e % TK, u = ub + uu;
+      Es[uu * ES + k] = u < u1 ? d.ephp[(size_t)u * kEpad + k] : 0.0;
+    }
+    for (int e = tid; e < 32 * CW; e += nt) {
+      const int uu = e / CW, c = e % CW, u = ub + uu, col = c0 + c;
+      double v = 0.0;
+      if (u < u1 && col < N) {
+        const int ch = col / nff2, mn = col % nff2;
+        v = Xp[(size_t)ch * b.S + (size_t)u * nff2 + mn];
+      }
+      Xs[uu * XS + c] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int uk = 0; uk < 32; uk += 4) {
+      const double bv = Xs[(uk + k4) * XS + 16 * w + r16];
+#pragma unroll
+      for (int t = 0; t < KT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Es[(uk + k4) * ES + 16 * t + r16], bv, acc[t], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* out = b.xp + d.ws_xp + (size_t)split * ncol * N;
+  const int col = c0 + 16 * w + r16;
+  if (col >= N) return;
+#pragma unroll
+  for (int t = 0; t < KT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = 16 * t + 4 * j + k4;
+      if (k < ncol) out[(size_t)k * N + col] = acc[t][j];
+    }
+}
+
+// Split precision: the same contraction and output, with products
+// hi*hi + hi*lo + lo*hi of the BF16 splits accumulated in FP32 over one
+// split; splits start on multiples of 16 momenta.  Per step of 16 momenta
+// each lane loads its 4 values of X (split on the fly) and, for each of the
+// KT harmonic tiles, one quad of the pre-split phase table laid out
+// [u/4][kEpad][4] (zero beyond Nq), straight from the cache: there is no
+// reuse across waves worth an LDS pass.
+template <int KT>
+__device__ __forceinline__ void fwd_mix_body(const Batch& b, const DevTables& d, const int4 item,
+                                             const double* __restrict__ X) {
+  const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
+  const int split = item.z, nq16 = (nq + 15) >> 4;
+  const int u0 = 16 * (int)((int64_t)nq16 * split / d.nsu);
+  const int u1 = 16 * (int)((int64_t)nq16 * (split + 1) / d.nsu);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  const int col = item.y * 16 * ((int)blockDim.x >> 6) + 16 * w + r16;
+  const bool cok = col < N;
+  const int ch = cok ? col / nff2 : 0, mn = cok ? col % nff2 : 0;
+  const double* xc = X + d.off + (size_t)ch * b.S + mn;
+  const bf16x4* eh = reinterpret_cast<const bf16x4*>(d.ephq_hi);
+  const bf16x4* el = reinterpret_cast<const bf16x4*>(d.ephq_lo);
+  f32x4 acc[KT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int ub = u0; ub < u1; ub += 16) {
+    bf16x4 bh, bl;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int u = ub + 4 * k4 + j;
+      unsigned short h = 0, l = 0;
+      if (cok && u < nq) split_bf16(xc[(size_t)u * nff2], h, l);
+      bh[j] = (short)h;
+      bl[j] = (short)l;
+    }
+    const size_t qrow = (size_t)((ub >> 2) + k4) * kEpad;
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      const bf16x4 ah = eh[qrow + 16 * t + r16], al = el[qrow + 16 * t + r16];
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[t], 0, 0, 0);
+    }
+  }
+  if (!cok) return;
+  double* out = b.xp + d.ws_xp + (size_t)split * ncol * N;
+#pragma unroll
+  for (int t = 0; t < KT; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = 16 * t + 4 * k4 + j;
+      if (k < ncol) out[(size_t)k * N + col] = (double)acc[t][j];
+    }
+}
+
+}  // namespace
+}  // namespace tufrg

@@ -75,6 +75,7 @@ int nff_of_shells(int shells);
 
 // ---------------------------------------------------------- device side
 constexpr int kLoopThreadsMax = 512;   // loop kernel block size bound
+constexpr int64_t kFuseMaxState = 1 << 18;  // largest channel state (sum of Nq Nff^2) run in fused launches
 constexpr int kMaxLT = 4;              // momenta per block of the FP64 back end
 constexpr int kSeg = 4096;             // elements per ODE segment item
 constexpr int kShellMax = 8;           // largest form-factor shell (bonds up to |R|^2 = 5)
@@ -130,6 +131,7 @@ struct Batch {
   double* kinv64;         // inverse transforms (FP64)
   double* ghat;           // loop-harmonic slices (all points, at ws_gh)
   const int* item_count;  // loops: when set, only the first *item_count items run
+  int loop_threads;       // threads of the loop geometry (fixes the loops' summation order)
 };
 
 struct ItemRange {
@@ -155,6 +157,10 @@ struct Launch {
   int loop_threads, loop_blocks, smax_max;
   int fwd_kt;             // forward transform: 16-row harmonic tiles (1, 2, 3 or 5)
   int inv_lt;             // inverse transform: 16-momentum tiles per item (1, 2 or 4)
+  int front_threads;      // block of the forward transform and of the loops + transform launch
+  bool fused;             // right-hand side in fused launches on one stream (small contexts)
+  size_t fwd_smem;        // FP64 forward transform: dynamic LDS
+  size_t front_smem;      // loops + transform launch: dynamic LDS
   bool loop_persistent;   // loop kernel: persistent work queue, or one block per item
   size_t loop_smem, prod_smem;
 };
@@ -181,6 +187,11 @@ void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, h
 void launch_chi_expand(const Launch& L, const ItemRange& r, const double* fin, double* dchi,
                        hipStream_t s);
 void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s);
+void launch_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s);
+void launch_gather_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t s);
+void launch_loops_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, bool cross,
+                      hipStream_t s);
+void launch_expand_basis(const Launch& L, const Ranges& r, double* dchi, bool cross, hipStream_t s);
 void launch_back(const Launch& L, const Ranges& r, const double* X, double* out, int mode,
                  bool cross, bool scale_T, bool mixed, hipStream_t s);
 void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const double* const* k,

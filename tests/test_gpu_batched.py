@@ -97,6 +97,29 @@ def test_loop_queue_form_identical(tf, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_and_two_stream_forms_identical(tf, precision):
+    """A small context runs the right-hand side in fused launches on one stream
+    (loops with the forward transform, loop expansion with the bond basis);
+    with fuse=False the loops run on a second stream beside the projection
+    chain.  Same bits, for right-hand sides and for a graph-replayed RK4 flow."""
+    print(f"[batch] fused vs two-stream, {precision}", flush=True)
+    torch = _torch()
+    a = tf.Context(BATCH, precision=precision)
+    b = tf.Context(BATCH, precision=precision, fuse=False)
+    assert a.S <= 1 << 18
+    Ts = [0.4, 0.05, 2.0, 0.011, 0.13, 0.9]
+    Xs = [synth.random_channels(p.nq, FormFactors(p.shells).nff, seed=90 + i) for i, p in enumerate(BATCH)]
+    for rep in range(2):
+        assert torch.equal(a.rhs(Ts, _pack(a, Xs)), b.rhs(Ts, _pack(b, Xs)))
+    assert torch.equal(a.project(_pack(a, Xs)), b.project(_pack(b, Xs)))
+    opts = tf.FlowOptions(T0=10.0, Tmin=0.05, Xmax=20.0, scheme="rk4", nsteps=30, use_graph=True)
+    Xa, Xb = a.empty(3).zero_(), b.empty(3).zero_()
+    ra, rb = a.flow(Xa, opts), b.flow(Xb, opts)
+    assert ra == rb
+    assert torch.equal(Xa, Xb)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_point_group_reduction_matches_full_grid(tf, precision):
     """Loops on one representative per C4v orbit equal the loops at every
     transfer momentum: 1e-12 normwise in FP64 (summation order only); in
