@@ -203,6 +203,30 @@ def test_flow_cfg1_rk4(tf):
     _assert_normwise(_host(ctx, X), ref.X, tol=1e-8, what="X at stop")
 
 
+def test_flow_cfg2_dopri5_against_oracle_golden(tf):
+    """The headline workload's adaptive flow (24x24 / 96x96, N_ff = 13, T 10 -> 1e-3):
+    critical scale within 1e-3 of the oracle's (stored by tests/golden/make_flow_cfg2.py;
+    inside the 1% bar, and loose enough for a step sequence that differs by rounding)
+    and the same leading instability."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "flow_cfg2_dopri5_oracle.json")) as fh:
+        ref = json.load(fh)
+    w = synth.cfg2()
+    pt = w.points[0]
+    pt.mu = tf.mu_from_filling(pt.t, pt.tp, pt.filling, pt.mu_T, pt.mu_L)
+    assert abs(pt.mu - ref["point"]["mu"]) < 1e-12
+    print(f"[flow] cfg2 dopri5 vs oracle golden Tc={ref['Tc']}", flush=True)
+    ctx = tf.Context([pt])
+    X = ctx.empty(3).zero_()
+    r = ctx.flow(X, tf.FlowOptions(T0=w.T0, Tmin=w.Tmin, Xmax=w.Xmax, scheme="dopri5",
+                                   rtol=w.rtol, atol=w.atol))[0]
+    print("gpu", r, flush=True)
+    assert r.status == ref["status"] == "diverged"
+    assert abs(r.Tc / ref["Tc"] - 1) < 1e-3
+    assert (r.channel, r.q_index, r.irrep) == (ref["channel"], ref["q_index"], ref["irrep"])
+
+
 def test_flow_dopri5_small(tf):
     pt = _pt(1, 6, 16, tp=0.0, mu=0.0, U=3.0)
     ctx = tf.Context([pt])
