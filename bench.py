@@ -59,6 +59,10 @@ def parse():
     ap.add_argument("--probe-loops", type=int, default=0,
                     help="counter probe only: one 64 MiB device copy (calibration), then this many "
                          "loop steps of the headline workload; prints no JSON")
+    ap.add_argument("--probe-projections", type=int, default=0,
+                    help="counter probe only: this many projection steps (tufrg_project) of the "
+                         "headline workload (FP64) and of the N_ff=21, 48x48 workload (FP64, then "
+                         "mixed); prints no JSON")
     return ap.parse_args()
 
 
@@ -83,6 +87,26 @@ def probe_loops(n):
         ctx.bubbles(0.05, d)
     torch.cuda.synchronize()
     log(f"[probe] copy of {2 * words * 8} bytes, {n} loop steps, geometry {ctx.geometry(0)}")
+
+
+def probe_projections(n):
+    """Fixed projection sequence for hardware-counter runs (rocprofv3 --pmc)."""
+    import torch
+
+    import paper_1604_06296_amd as tf
+    import synth
+    for w, prec in ((synth.cfg2(), "fp64"), (synth.cfg3(), "fp64"), (synth.cfg3(), "mixed")):
+        pt = w.points[0]
+        if pt.mu is None:
+            pt.mu = tf.mu_from_filling(pt.t, pt.tp, pt.filling, pt.mu_T, pt.mu_L)
+        ctx = tf.Context([pt], precision=prec)
+        X = torch.from_numpy(synth.random_channels(pt.nq, pt.nff, seed=5).reshape(3, -1)).cuda()
+        V = ctx.empty(3)
+        for _ in range(n):
+            ctx.project(X, V)
+        torch.cuda.synchronize()
+        log(f"[probe] {w.name} {prec}: {n} projection steps")
+        ctx.close()
 
 
 def log(msg):
@@ -267,8 +291,11 @@ def leg_surrogate(tf, synth, train_steps):
 
 def main():
     args = parse()
-    if args.probe_loops > 0:
-        probe_loops(args.probe_loops)
+    if args.probe_loops > 0 or args.probe_projections > 0:
+        if args.probe_loops > 0:
+            probe_loops(args.probe_loops)
+        if args.probe_projections > 0:
+            probe_projections(args.probe_projections)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
