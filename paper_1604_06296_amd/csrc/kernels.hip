@@ -86,9 +86,20 @@ __device__ __forceinline__ void expand_body(const Batch& b, const int4 item, con
       if (e < kExpRows * nsh) As[e / nsh][e % nsh] = neg[s5] ? -v[s5] : v[s5];
     }
   }
-  for (int e = tid; e < nsh * kExpCols; e += 256) {
-    const int j = e / kExpCols, c = e % kExpCols, mn = c0 + c;
-    Bs[j][c] = mn < nff2 ? d.ebub[(size_t)mn * nsh + j] : 0.0;
+  {
+    // the coefficient tile, all of the thread's loads in flight together
+    constexpr int kB = kExpK * kExpCols / 256;
+    double bv[kB];
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      const int e = tid + 256 * i, j = e / kExpCols, mn = c0 + e % kExpCols;
+      bv[i] = (j < nsh && mn < nff2) ? d.ebub[(size_t)mn * nsh + j] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      const int e = tid + 256 * i;
+      Bs[e / kExpCols][e % kExpCols] = bv[i];
+    }
   }
   __syncthreads();
   const int rr = 2 * (tid >> 4), cc = 4 * (tid & 15);
@@ -344,24 +355,34 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
   const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
   const int l0 = item.y * TL, c0 = item.z * 64, tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, r16 = lane & 15, k4 = lane >> 4;
-  const double* g2 = b.g2 + d.ws_g2;
+  // staging: each chunk's loads are issued together into registers before
+  // they go to LDS; a thread stages LT entries of E (16 consecutive harmonics
+  // of one momentum per 16 threads) and one column of g2 (rows gk + 4 i)
+  const int gc = tid & 63, gk = tid >> 6, gcol = c0 + gc;
+  const bool gok = gcol < N;
+  const double* gsrc = b.g2 + d.ws_g2 + (gok ? (size_t)(gcol / nff2) * ncol * nff2 + gcol % nff2 : 0);
   f64x4 acc[LT];
 #pragma unroll
   for (int t = 0; t < LT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < ncol; k0 += 16) {
-    for (int e = tid; e < 16 * TL; e += 256) {
-      const int r = e % TL, kk = e / TL, l = l0 + r, k = k0 + kk;
-      Es[kk][r] = (l < nq && k < ncol) ? d.eph[(size_t)l * ncol + k] : 0.0;
+    double ev[LT], gv[4];
+#pragma unroll
+    for (int i = 0; i < LT; ++i) {
+      const int e = tid + 256 * i, l = l0 + (e >> 4), k = k0 + (e & 15);
+      ev[i] = (l < nq && k < ncol) ? d.eph[(size_t)l * ncol + k] : 0.0;
     }
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int kk = e >> 6, c = e & 63, col = c0 + c, k = k0 + kk;
-      double v = 0.0;
-      if (col < N && k < ncol) {
-        const int ch = col / nff2, mn = col % nff2;
-        v = g2[((size_t)ch * ncol + k) * nff2 + mn];
-      }
-      Gs[kk][c] = v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = k0 + gk + 4 * i;
+      gv[i] = (gok && k < ncol) ? gsrc[(size_t)k * nff2] : 0.0;
     }
+#pragma unroll
+    for (int i = 0; i < LT; ++i) {
+      const int e = tid + 256 * i;
+      Es[e & 15][e >> 4] = ev[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Gs[gk + 4 * i][gc] = gv[i];
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4) {
@@ -480,29 +501,48 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
   R* Wm = Ch + 2 * nff2;                    // [nff2]
   R* T1 = Wm + nff2;                        // [3][nff2]
   R* T2 = T1 + 3 * nff2;                    // [3][nff2]
-  for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
-    const int ch = w / nff2, mn = w % nff2;
+  // the thread's entries mn = tid + 256 h (h < 2; 256 threads, nff^2 <= 441):
+  // all of their loads in flight together, then V (and W, the loops) to LDS
+  double xv[2][3], kv[2][3], cv[2][2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int mn = threadIdx.x + 256 * h;
+    const bool ok = mn < nff2;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      xv[h][ch] = ok ? X[ch * S + d.off + (size_t)l * nff2 + mn] : 0.0;
+      kv[h][ch] = (ok && cross) ? (double)K[((size_t)ch * nq + l) * nff2 + mn] : 0.0;
+    }
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch)
+      cv[h][ch] = (ok && mode != 0) ? b.dchi[(size_t)ch * S + d.off + (size_t)l * nff2 + mn] : 0.0;
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int mn = threadIdx.x + 256 * h;
+    if (mn >= nff2) continue;
     const R bare = (mn == 0) ? (R)d.U : (R)0;
-    const R own = (R)X[ch * S + d.off + (size_t)l * nff2 + mn];
-    const R kk = cross ? K[((size_t)ch * nq + l) * nff2 + mn] : (R)0;
-    Vs[w] = bare + (ch == 0 ? -own : own) + kk;
+    R v[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const R own = (R)xv[h][ch];
+      v[ch] = bare + (ch == 0 ? -own : own) + (R)kv[h][ch];
+    }
+    if (mode == 0) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) out[(size_t)ch * S + d.off + (size_t)l * nff2 + mn] = (double)v[ch];
+      continue;
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) Vs[ch * nff2 + mn] = v[ch];
+    Wm[mn] = (R)2 * v[2] - v[1];
+    Ch[mn] = (R)cv[h][0];
+    Ch[nff2 + mn] = (R)cv[h][1];
   }
-  if (mode == 0) {
-    __syncthreads();
-    for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x)
-      out[(size_t)(w / nff2) * S + d.off + (size_t)l * nff2 + w % nff2] = (double)Vs[w];
-    return;
-  }
-  for (int w = threadIdx.x; w < 2 * nff2; w += blockDim.x) {
-    const int ch = w / nff2, mn = w % nff2;
-    Ch[w] = (R)b.dchi[(size_t)ch * S + d.off + (size_t)l * nff2 + mn];
-  }
+  if (mode == 0) return;
   __syncthreads();
   const R* VP = Vs;
   const R* VC = Vs + nff2;
-  const R* VD = Vs + 2 * nff2;
-  for (int w = threadIdx.x; w < nff2; w += blockDim.x) Wm[w] = (R)2 * VD[w] - VC[w];
-  __syncthreads();
   for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
     const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
     const R* A = Ch + (which == 0 ? 0 : nff2) + m * nff;

@@ -46,7 +46,7 @@ __device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigne
 // FP64 on the matrix cores.  Item (p, column tile c, transfer split s): the
 // block's columns against KT tiles of 16 harmonic rows k (E from its copy
 // padded with zero columns to kEpad).  Chunks of 32 momenta u pass through
-// LDS (smem holds fwd_smem_bytes(KT, 16 nw)); wave w accumulates KT tiles of
+// LDS (32 (16 KT + 2) + 32 (16 nw + 2) doubles); wave w accumulates KT tiles of
 // v_mfma_f64_16x16x4f64 (lane l holds A[l%16][l/16], B[l/16][l%16] and, in
 // register j, D[4j+l/16][l%16]).
 template <int KT>
@@ -61,24 +61,35 @@ __device__ __forceinline__ void fwd_part_body(const Batch& b, const DevTables& d
   const int u0 = (int)((int64_t)nq * split / d.nsu), u1 = (int)((int64_t)nq * (split + 1) / d.nsu);
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, k4 = lane >> 4;
-  const double* Xp = X + d.off;
+  // staging: each chunk's loads are issued together into registers before
+  // they go to LDS.  A thread stages one column of X (the block has 4 CW
+  // threads: rows tid / CW + 4 i, i < 8) and up to EPT entries of E.
+  constexpr int EPT = (32 * TK + 255) / 256;
+  const int xc = tid % CW, xr = tid / CW, xcol = c0 + xc;
+  const bool xok = xcol < N;
+  const double* xsrc = X + d.off + (xok ? (size_t)(xcol / nff2) * b.S + xcol % nff2 : 0);
   f64x4 acc[KT];
 #pragma unroll
   for (int t = 0; t < KT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
   for (int ub = u0; ub < u1; ub += 32) {
-    for (int e = tid; e < 32 * TK; e += nt) {
-      const int uu = e / TK, k = e % TK, u = ub + uu;
-      Es[uu * ES + k] = u < u1 ? d.ephp[(size_t)u * kEpad + k] : 0.0;
+    double ev[EPT], xv[8];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * nt, uu = e / TK, k = e % TK, u = ub + uu;
+      ev[i] = (e < 32 * TK && u < u1) ? d.ephp[(size_t)u * kEpad + k] : 0.0;
     }
-    for (int e = tid; e < 32 * CW; e += nt) {
-      const int uu = e / CW, c = e % CW, u = ub + uu, col = c0 + c;
-      double v = 0.0;
-      if (u < u1 && col < N) {
-        const int ch = col / nff2, mn = col % nff2;
-        v = Xp[(size_t)ch * b.S + (size_t)u * nff2 + mn];
-      }
-      Xs[uu * XS + c] = v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int u = ub + xr + 4 * i;
+      xv[i] = (xok && u < u1) ? xsrc[(size_t)u * nff2] : 0.0;
     }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * nt;
+      if (e < 32 * TK) Es[(e / TK) * ES + e % TK] = ev[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) Xs[(xr + 4 * i) * XS + xc] = xv[i];
     __syncthreads();
 #pragma unroll
     for (int uk = 0; uk < 32; uk += 4) {
