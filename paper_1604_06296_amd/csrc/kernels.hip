@@ -268,6 +268,8 @@ __global__ void __launch_bounds__(64)
 k_gather_g2(Batch b, const int4* __restrict__ items) {
   __shared__ double Mre[2][kShellMax * kShellMax];
   __shared__ double Mim[2][kShellMax * kShellMax];
+  __shared__ double C1[2][kShellMax * kShellMax];   // c_{m a}, m and a in shell sm (re, im)
+  __shared__ double C2[2][kShellMax * kShellMax];   // c_{n b}, n and b in shell sn
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
@@ -311,15 +313,25 @@ k_gather_g2(Batch b, const int4* __restrict__ items) {
     Mre[vi][r] = re;
     Mim[vi][r] = im;
   }
+  if ((int)threadIdx.x < na * na) {
+    const int i = threadIdx.x, c = (a0 + i / na) * nff + a0 + i % na;
+    C1[0][i] = d.cre[c];
+    C1[1][i] = d.cim[c];
+  }
+  if ((int)threadIdx.x < nb * nb) {
+    const int i = threadIdx.x, c = (b0 + i / nb) * nff + b0 + i % nb;
+    C2[0][i] = d.cre[c];
+    C2[1][i] = d.cim[c];
+  }
   __syncthreads();
   double* g2 = b.g2 + d.ws_g2;
   for (int w = threadIdx.x; w < nab; w += 64) {
     const int m = a0 + w / nb, n = b0 + w % nb, mn = m * nff + n;
     double nr[2] = {0.0, 0.0}, ni[2] = {0.0, 0.0};
     for (int a = 0; a < na; ++a) {
-      const double c1r = d.cre[m * nff + a0 + a], c1i = d.cim[m * nff + a0 + a];
+      const double c1r = C1[0][(m - a0) * na + a], c1i = C1[1][(m - a0) * na + a];
       for (int bb = 0; bb < nb; ++bb) {
-        const double c2r = d.cre[n * nff + b0 + bb], c2i = d.cim[n * nff + b0 + bb];
+        const double c2r = C2[0][(n - b0) * nb + bb], c2i = C2[1][(n - b0) * nb + bb];
         const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
         for (int vi = 0; vi < nvl; ++vi) {
           const double mr = Mre[vi][a * nb + bb], mi = Mim[vi][a * nb + bb];
