@@ -238,7 +238,10 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   ctx->ghat_sum_len = ghs;
   for (int p = 0; p < npts; ++p) lsm = std::max(lsm, loop_smem_of(ctx->dev[p], threads));
   const int fwd_kt = kpt <= 3 ? kpt : 5;
-  const size_t fsm = mixed ? 0 : sizeof(double) * 32 * ((size_t)(16 * fwd_kt + 2) + (size_t)(fwd_cols + 2));
+  // forward transform LDS: FP64 chunks of 32 momenta [32][16 KT + 2] + [32][cols + 2];
+  // split precision: hi and lo quads [8][16 KT] + [8][cols] (8 bytes each)
+  const size_t fsm = mixed ? (size_t)16 * 8 * (16 * fwd_kt + fwd_cols)
+                           : sizeof(double) * 32 * ((size_t)(16 * fwd_kt + 2) + (size_t)(fwd_cols + 2));
   int dev_smem = 0;
   hipDeviceGetAttribute(&dev_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
   if (dev_smem > 0 && (lsm > (size_t)dev_smem || psm > (size_t)dev_smem || fsm > (size_t)dev_smem))

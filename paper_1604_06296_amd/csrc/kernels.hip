@@ -424,57 +424,98 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
 template <int KT>
 __global__ void __launch_bounds__(kLoopThreadsMax)
 k_dft_fwd_mix(Batch b, const int4* __restrict__ items, const double* __restrict__ X) {
+  extern __shared__ double smem_fwd[];
   const int4 item = items[blockIdx.x];
   if (skip_point(b, item.x)) return;
-  fwd_mix_body<KT>(b, b.pts[item.x], item, X);
+  fwd_mix_body<KT>(b, b.pts[item.x], item, X, smem_fwd);
 }
 
 // Inverse transform in split precision: K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn]
 // with FP32 accumulation of the three BF16 split products, stored in FP32.
 // Item (p, tile of 16 LT momenta l, tile of 64 columns); wave w owns 16
-// columns and LT accumulator tiles of 16 momenta.  The pre-split phase table
-// is laid out [l][kEpad] (zero beyond Nq, rows padded to a multiple of 64), so
-// a lane's 4 consecutive harmonics are one 8-byte load; g2 is split on the fly.
+// columns and LT accumulator tiles of 16 momenta.  The whole harmonic range
+// (at most 20 quads of 4) is staged in LDS at once, with all loads in flight
+// together: the block's rows of the pre-split phase table (laid out [l][kEpad],
+// zero beyond Nq, rows padded to a multiple of 64) as hi and lo quads, and its
+// columns of g2, split to hi and lo quads as they are staged.
 template <int LT>
 __global__ void __launch_bounds__(256)
 k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
+  constexpr int TL = 16 * LT, QR = kEpad / 4;
+  __shared__ bf16x4 Eh[TL][QR + 1], El[TL][QR + 1];
+  __shared__ bf16x4 Gh[QR][64 + 1], Gl[QR][64 + 1];
   const int4 item = items[blockIdx.x];
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
   const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, k4 = lane >> 4;
-  const int l0 = item.y * 16 * LT, col = item.z * 64 + 16 * w + r16;
-  const bool cok = col < N;
-  const int ch = cok ? col / nff2 : 0, mn = cok ? col % nff2 : 0;
-  const double* gc = b.g2 + d.ws_g2 + (size_t)ch * ncol * nff2 + mn;
-  const bf16x4* eh = reinterpret_cast<const bf16x4*>(d.ephr_hi);
-  const bf16x4* el = reinterpret_cast<const bf16x4*>(d.ephr_lo);
-  constexpr int QR = kEpad / 4;
+  const int l0 = item.y * TL, c0 = item.z * 64;
+  const int nk = (ncol + 15) / 16 * 4;   // quads in use
+  // staging: E entries tid + 256 i of [TL][QR]; g2 column gc, quads gq + 4 i
+  constexpr int EPT = (TL * QR + 255) / 256;
+  const bf16x4* ehq = reinterpret_cast<const bf16x4*>(d.ephr_hi);
+  const bf16x4* elq = reinterpret_cast<const bf16x4*>(d.ephr_lo);
+  bf16x4 eh[EPT], el[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + 256 * i, r = e / QR, q = e % QR;
+    const bool ok = e < TL * QR && q < nk;
+    const size_t src = (size_t)(l0 + r) * QR + q;
+    eh[i] = ok ? ehq[src] : bf16x4{0, 0, 0, 0};
+    el[i] = ok ? elq[src] : bf16x4{0, 0, 0, 0};
+  }
+  const int gc = tid & 63, gq = tid >> 6, gcol = c0 + gc;
+  const bool gok = gcol < N;
+  const double* gsrc = b.g2 + d.ws_g2 + (gok ? (size_t)(gcol / nff2) * ncol * nff2 + gcol % nff2 : 0);
+  double gv[QR / 4][4];
+#pragma unroll
+  for (int i = 0; i < QR / 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = 4 * (gq + 4 * i) + j;
+      gv[i][j] = (gok && k < ncol) ? gsrc[(size_t)k * nff2] : 0.0;
+    }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + 256 * i;
+    if (e < TL * QR) {
+      Eh[e / QR][e % QR] = eh[i];
+      El[e / QR][e % QR] = el[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < QR / 4; ++i) {
+    bf16x4 qh, ql;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      unsigned short hi, lo;
+      split_bf16(gv[i][j], hi, lo);
+      qh[j] = (short)hi;
+      ql[j] = (short)lo;
+    }
+    Gh[gq + 4 * i][gc] = qh;
+    Gl[gq + 4 * i][gc] = ql;
+  }
+  __syncthreads();
   f32x4 acc[LT];
 #pragma unroll
   for (int t = 0; t < LT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < ncol; k0 += 16) {
-    bf16x4 bh, bl;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = k0 + 4 * k4 + j;
-      unsigned short h = 0, l = 0;
-      if (cok && k < ncol) split_bf16(gc[(size_t)k * nff2], h, l);
-      bh[j] = (short)h;
-      bl[j] = (short)l;
-    }
+  for (int q0 = 0; q0 < nk; q0 += 4) {
+    const int q = q0 + k4;
+    const bf16x4 bh = Gh[q][16 * w + r16], bl = Gl[q][16 * w + r16];
 #pragma unroll
     for (int t = 0; t < LT; ++t) {
-      const size_t a = (size_t)(l0 + 16 * t + r16) * QR + (k0 >> 2) + k4;
-      const bf16x4 ah = eh[a], al = el[a];
+      const bf16x4 ah = Eh[16 * t + r16][q], al = El[16 * t + r16][q];
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[t], 0, 0, 0);
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[t], 0, 0, 0);
     }
   }
-  if (!cok) return;
+  const int col = c0 + 16 * w + r16;
+  if (col >= N) return;
+  const int ch = col / nff2, mn = col % nff2;
   float* K = b.kinv + d.ws_k;
 #pragma unroll
   for (int t = 0; t < LT; ++t)
@@ -734,11 +775,12 @@ void launch_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, h
   const int4* it = L.fwd_items + r.fwd.begin;
   const dim3 g(r.fwd.n), blk(L.front_threads);
   if (mixed) {
+    const size_t sm = L.fwd_smem;
     switch (L.fwd_kt) {
-      case 1: hipLaunchKernelGGL(k_dft_fwd_mix<1>, g, blk, 0, s, L.b, it, X); break;
-      case 2: hipLaunchKernelGGL(k_dft_fwd_mix<2>, g, blk, 0, s, L.b, it, X); break;
-      case 3: hipLaunchKernelGGL(k_dft_fwd_mix<3>, g, blk, 0, s, L.b, it, X); break;
-      default: hipLaunchKernelGGL(k_dft_fwd_mix<5>, g, blk, 0, s, L.b, it, X); break;
+      case 1: hipLaunchKernelGGL(k_dft_fwd_mix<1>, g, blk, sm, s, L.b, it, X); break;
+      case 2: hipLaunchKernelGGL(k_dft_fwd_mix<2>, g, blk, sm, s, L.b, it, X); break;
+      case 3: hipLaunchKernelGGL(k_dft_fwd_mix<3>, g, blk, sm, s, L.b, it, X); break;
+      default: hipLaunchKernelGGL(k_dft_fwd_mix<5>, g, blk, sm, s, L.b, it, X); break;
     }
   } else {
     const size_t sm = L.fwd_smem;

@@ -281,7 +281,7 @@ k_loops_fwd(Batch b, const int4* __restrict__ loop_items, int nloop, const int4*
   }
   const int4 item = fwd_items[blockIdx.x - nloop];
   if (skip_point(b, item.x)) return;
-  if constexpr (MIXED) fwd_mix_body<KT>(b, b.pts[item.x], item, X);
+  if constexpr (MIXED) fwd_mix_body<KT>(b, b.pts[item.x], item, X, smem);
   else fwd_part_body<KT>(b, b.pts[item.x], item, X, smem);
 }
 

@@ -114,49 +114,95 @@ __device__ __forceinline__ void fwd_part_body(const Batch& b, const DevTables& d
 
 // Split precision: the same contraction and output, with products
 // hi*hi + hi*lo + lo*hi of the BF16 splits accumulated in FP32 over one
-// split; splits start on multiples of 16 momenta.  Per step of 16 momenta
-// each lane loads its 4 values of X (split on the fly) and, for each of the
-// KT harmonic tiles, one quad of the pre-split phase table laid out
-// [u/4][kEpad][4] (zero beyond Nq), straight from the cache: there is no
-// reuse across waves worth an LDS pass.
+// split; splits start on multiples of 16 momenta.  Chunks of 32 momenta (8
+// quads of 4) pass through LDS: the pre-split phase table (laid out
+// [u/4][kEpad][4], zero beyond Nq) as hi and lo quads for the KT harmonic
+// tiles, and the block's columns of X, split to hi and lo quads as they are
+// staged (each thread stages two (quad, column) pairs: 8 loads in flight).
+// Each wave then reads its operand quads from LDS for 2 steps of 16 momenta.
 template <int KT>
 __device__ __forceinline__ void fwd_mix_body(const Batch& b, const DevTables& d, const int4 item,
-                                             const double* __restrict__ X) {
+                                             const double* __restrict__ X, double* smem) {
+  constexpr int TK = 16 * KT;
+  const int nw = (int)blockDim.x >> 6, CW = 16 * nw, nt = blockDim.x;
+  bf16x4* Eh = reinterpret_cast<bf16x4*>(smem);   // [8][TK]
+  bf16x4* El = Eh + 8 * TK;
+  bf16x4* Xh = El + 8 * TK;                        // [8][CW]
+  bf16x4* Xl = Xh + 8 * CW;
   const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
   const int split = item.z, nq16 = (nq + 15) >> 4;
   const int u0 = 16 * (int)((int64_t)nq16 * split / d.nsu);
   const int u1 = 16 * (int)((int64_t)nq16 * (split + 1) / d.nsu);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, k4 = lane >> 4;
-  const int col = item.y * 16 * ((int)blockDim.x >> 6) + 16 * w + r16;
-  const bool cok = col < N;
-  const int ch = cok ? col / nff2 : 0, mn = cok ? col % nff2 : 0;
-  const double* xc = X + d.off + (size_t)ch * b.S + mn;
-  const bf16x4* eh = reinterpret_cast<const bf16x4*>(d.ephq_hi);
-  const bf16x4* el = reinterpret_cast<const bf16x4*>(d.ephq_lo);
+  const int c0 = item.y * CW;
+  // staging roles: X column xc (constant), quads xq and xq + 4; E entries
+  // tid + i nt of the [8][TK] quad tile (hi and lo)
+  constexpr int EPT = (8 * TK + 255) / 256;
+  const int xc = tid % CW, xq = tid / CW, xcol = c0 + xc;
+  const bool xok = xcol < N;
+  const double* xsrc = X + d.off + (xok ? (size_t)(xcol / nff2) * b.S + xcol % nff2 : 0);
+  const bf16x4* ehq = reinterpret_cast<const bf16x4*>(d.ephq_hi);
+  const bf16x4* elq = reinterpret_cast<const bf16x4*>(d.ephq_lo);
   f32x4 acc[KT];
 #pragma unroll
   for (int t = 0; t < KT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int ub = u0; ub < u1; ub += 16) {
-    bf16x4 bh, bl;
+  for (int ub = u0; ub < u1; ub += 32) {
+    const int nst = min(32, u1 - ub) >> 4;   // steps of 16 in this chunk (1 or 2)
+    bf16x4 eh[EPT], el[EPT];
+    double xv[2][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int u = ub + 4 * k4 + j;
-      unsigned short h = 0, l = 0;
-      if (cok && u < nq) split_bf16(xc[(size_t)u * nff2], h, l);
-      bh[j] = (short)h;
-      bl[j] = (short)l;
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * nt, q = e / TK, k = e % TK;
+      const size_t src = (size_t)((ub >> 2) + q) * kEpad + k;
+      const bool ok = e < 8 * TK && q < 4 * nst;
+      eh[i] = ok ? ehq[src] : bf16x4{0, 0, 0, 0};
+      el[i] = ok ? elq[src] : bf16x4{0, 0, 0, 0};
     }
-    const size_t qrow = (size_t)((ub >> 2) + k4) * kEpad;
 #pragma unroll
-    for (int t = 0; t < KT; ++t) {
-      const bf16x4 ah = eh[qrow + 16 * t + r16], al = el[qrow + 16 * t + r16];
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[t], 0, 0, 0);
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int u = ub + 4 * (xq + 4 * h) + j;
+        xv[h][j] = (xok && u < nq && u < u1) ? xsrc[(size_t)u * nff2] : 0.0;
+      }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * nt;
+      if (e < 8 * TK) {
+        Eh[e] = eh[i];
+        El[e] = el[i];
+      }
     }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      bf16x4 qh, ql;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        unsigned short hi, lo;
+        split_bf16(xv[h][j], hi, lo);
+        qh[j] = (short)hi;
+        ql[j] = (short)lo;
+      }
+      Xh[(xq + 4 * h) * CW + xc] = qh;
+      Xl[(xq + 4 * h) * CW + xc] = ql;
+    }
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+      const int q = 4 * st + k4;
+      const bf16x4 bh = Xh[q * CW + 16 * w + r16], bl = Xl[q * CW + 16 * w + r16];
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        const bf16x4 ah = Eh[q * TK + 16 * t + r16], al = El[q * TK + 16 * t + r16];
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
   }
-  if (!cok) return;
+  const int col = c0 + 16 * w + r16;
+  if (col >= N) return;
   double* out = b.xp + d.ws_xp + (size_t)split * ncol * N;
 #pragma unroll
   for (int t = 0; t < KT; ++t)

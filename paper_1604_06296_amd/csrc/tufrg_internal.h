@@ -159,7 +159,7 @@ struct Launch {
   int inv_lt;             // inverse transform: 16-momentum tiles per item (1, 2 or 4)
   int front_threads;      // block of the forward transform and of the loops + transform launch
   bool fused;             // right-hand side in fused launches on one stream (small contexts)
-  size_t fwd_smem;        // FP64 forward transform: dynamic LDS
+  size_t fwd_smem;        // forward transform: dynamic LDS
   size_t front_smem;      // loops + transform launch: dynamic LDS
   bool loop_persistent;   // loop kernel: persistent work queue, or one block per item
   size_t loop_smem, prod_smem;
