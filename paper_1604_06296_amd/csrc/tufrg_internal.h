@@ -76,7 +76,6 @@ int nff_of_shells(int shells);
 // ---------------------------------------------------------- device side
 constexpr int kLoopThreadsMax = 512;   // loop kernel block size bound
 constexpr int64_t kFuseMaxState = 1 << 18;  // largest channel state (sum of Nq Nff^2) run in fused launches
-constexpr int kMaxLT = 4;              // momenta per block of the FP64 back end
 constexpr int kSeg = 4096;             // elements per ODE segment item
 constexpr int kShellMax = 8;           // largest form-factor shell (bonds up to |R|^2 = 5)
 constexpr int kEpad = 80;              // padded row length of the phase table copy (ncol <= 69)
