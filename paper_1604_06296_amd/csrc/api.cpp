@@ -10,7 +10,6 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
-#include <functional>
 #include <map>
 #include <numeric>
 #include <string>
@@ -341,12 +340,44 @@ void loops_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, double* dchi
 // costs to dominate (Launch::fused).  Otherwise, and with the surrogate, the
 // loops run on the side stream (fork and join by events) alongside the
 // whole projection chain.
+// The temperatures of one right-hand side: host values for points p0 .. p0+n-1,
+// or (host == nullptr) the RK4 stage temperature Ttab[4 step + stage] of every
+// point, read on the device.
+struct TSource {
+  const double* host;
+  int p0, n;
+  int stage;
+};
+
+// Stores the temperatures into the per-point array on stream s.
+void set_T_launch(tufrg_ctx* ctx, const TSource& ts, hipStream_t s) {
+  if (ts.host) launch_set_T_values(ctx->Tp + ts.p0, ts.host, ts.n, s);
+  else launch_set_T(ctx->Tp, (int)ctx->dev.size(), ctx->Ttab, ctx->step, ts.stage, s);
+}
+
 void rhs_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, const double* X, double* out,
-                bool scale_T, hipStream_t ms, const std::function<void(hipStream_t)>& set_T) {
+                bool scale_T, hipStream_t ms, const TSource& ts) {
   const bool mixed = mixed_of(ctx), cross = cross_of(ctx);
   if (!ctx->sur_a && L.fused) {
-    set_T(ms);
-    launch_loops_fwd(L, r, X, mixed, cross, ms);
+    // the fused launch takes the temperatures itself (and stores them for the
+    // products), except for host values of more than 64 points
+    TArg ta{};
+    ta.Tp = ctx->Tp;
+    ta.npts = (int)ctx->dev.size();
+    if (ts.host && ts.n <= 64) {
+      ta.mode = 1;
+      ta.p0 = ts.p0;
+      ta.n = ts.n;
+      for (int i = 0; i < ts.n; ++i) ta.v[i] = ts.host[i];
+    } else if (!ts.host) {
+      ta.mode = 2;
+      ta.Ttab = ctx->Ttab;
+      ta.step = ctx->step;
+      ta.stage = ts.stage;
+    } else {
+      set_T_launch(ctx, ts, ms);
+    }
+    launch_loops_fwd(L, r, X, mixed, cross, ta, ms);
     launch_expand_basis(L, r, L.b.dchi, cross, ms);
     if (cross) launch_gather_inv(L, r, mixed, ms);
     launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms);
@@ -354,7 +385,7 @@ void rhs_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, const double* 
   }
   hipEventRecord(ctx->ev_fork, ms);
   hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
-  set_T(ctx->side);
+  set_T_launch(ctx, ts, ctx->side);
   loops_launch(ctx, L, r, L.b.dchi, ctx->side);
   hipEventRecord(ctx->ev_join, ctx->side);
   if (cross) launch_front(L, r, X, mixed, ms);
@@ -681,9 +712,8 @@ tufrg_status tufrg_rhs(tufrg_ctx* ctx, const double* T_host, const double* X, do
   if (!T_host || !X || !dXdT) return fail(ctx, TUFRG_EINVAL, "NULL argument");
   if (X == dXdT) return fail(ctx, TUFRG_EINVAL, "X and dXdT must not alias");
   ST_TRY(check_temperatures(ctx, T_host));
-  const int npts = (int)ctx->dev.size();
   rhs_launch(ctx, ctx->L, ctx->all, X, dXdT, false, ctx->stream,
-             [&](hipStream_t s) { launch_set_T_values(ctx->Tp, T_host, npts, s); });
+             TSource{T_host, 0, (int)ctx->dev.size(), 0});
   HIP_TRY(ctx, hipGetLastError());
   return TUFRG_OK;
 }
@@ -951,9 +981,7 @@ void rk4_step(tufrg_ctx* ctx, const Launch& L, double* X, double h, double xmax,
   const double half[1] = {0.5}, one[1] = {1.0};
   const double fin[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
   const Ranges& r = ctx->all;
-  auto stage_T = [&](int stage) {
-    return [=](hipStream_t s) { launch_set_T(ctx->Tp, npts, ctx->Ttab, ctx->step, stage, s); };
-  };
+  auto stage_T = [](int stage) { return TSource{nullptr, 0, 0, stage}; };
   rhs_launch(ctx, L, r, X, k[0], true, ms, stage_T(0));
   launch_axpy(L, r.seg, X, &k[0], half, 1, h, ctx->stage, true, ms);
   rhs_launch(ctx, L, r, ctx->stage, k[1], true, ms, stage_T(1));
@@ -1086,8 +1114,7 @@ const double kDpB4[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640, -9209
 
 // dX/ds of point p alone at temperature T
 tufrg_status rhs_point(tufrg_ctx* ctx, int p, double T, const double* X, double* out) {
-  rhs_launch(ctx, ctx->L, ctx->per_point[p], X, out, true, ctx->stream,
-             [&](hipStream_t s) { launch_set_T_values(ctx->Tp + p, &T, 1, s); });
+  rhs_launch(ctx, ctx->L, ctx->per_point[p], X, out, true, ctx->stream, TSource{&T, p, 1, 0});
   return TUFRG_OK;
 }
 

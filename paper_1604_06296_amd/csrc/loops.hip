@@ -64,7 +64,7 @@ __device__ __forceinline__ void neumaier_add(float& s, float& c, float v) {
 // (compile-time, so the per-row harmonic loops carry no guards).
 template <int SMAX, bool MIXED>
 __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, int p, int item_b,
-                                          double* smem) {
+                                          double T, double* smem) {
   constexpr int NH = 2 * SMAX + 1;
   const int t = threadIdx.x;
   const int nsplit = d.nsplit, nchunk = d.nchunk;
@@ -77,7 +77,6 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
   const int nr = R1 - R0;
   const int lq = d.lq;
   const int ix = q / lq, iy = q % lq;
-  const double T = b.Tp[p];
   const double inv2T = 0.5 / T;
 
   double* y1 = smem;                        // cos(py + qy/2)        [nr]
@@ -215,24 +214,36 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
   __syncthreads();
 }
 
+// The point's temperature: from the launch's TArg when there is one (fused
+// launches), else from the per-point array.
+__device__ __forceinline__ double point_T(const Batch& b, const TArg* ta, int p) {
+  if (ta != nullptr) {
+    if (ta->mode == 1 && p >= ta->p0 && p < ta->p0 + ta->n) return ta->v[p - ta->p0];
+    if (ta->mode == 2) return ta->Ttab[4 * ta->step[0] + ta->stage];
+  }
+  return b.Tp[p];
+}
+
 template <int SMAX, bool MIXED>
-__device__ __forceinline__ void loop_dispatch(const Batch& b, const int4 item, double* smem) {
+__device__ __forceinline__ void loop_dispatch(const Batch& b, const int4 item, double* smem,
+                                              const TArg* ta = nullptr) {
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
+  const double T = point_T(b, ta, p);
   if constexpr (SMAX >= 4) {
     if (d.smax == 4) {
-      loop_item<4, MIXED>(b, d, p, item.y, smem);
+      loop_item<4, MIXED>(b, d, p, item.y, T, smem);
       return;
     }
   }
   if constexpr (SMAX >= 2) {
     if (d.smax == 2) {
-      loop_item<2, MIXED>(b, d, p, item.y, smem);
+      loop_item<2, MIXED>(b, d, p, item.y, T, smem);
       return;
     }
   }
-  loop_item<0, MIXED>(b, d, p, item.y, smem);
+  loop_item<0, MIXED>(b, d, p, item.y, T, smem);
 }
 
 // Loop kernel over work items (p, q * nsplit + split); SMAX is the largest
@@ -273,10 +284,20 @@ k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ q
 template <int SMAX, bool MIXED, int KT>
 __global__ void __launch_bounds__(kLoopThreadsMax)
 k_loops_fwd(Batch b, const int4* __restrict__ loop_items, int nloop, const int4* __restrict__ fwd_items,
-            const double* __restrict__ X) {
+            const double* __restrict__ X, TArg ta) {
   extern __shared__ double smem[];
+  if (blockIdx.x == 0) {
+    // the temperatures, stored for the kernels after this launch (the loop
+    // blocks of this launch take them from ta)
+    if (ta.mode == 1) {
+      for (int i = threadIdx.x; i < ta.n; i += blockDim.x) ta.Tp[ta.p0 + i] = ta.v[i];
+    } else if (ta.mode == 2) {
+      const double T = ta.Ttab[4 * ta.step[0] + ta.stage];
+      for (int i = threadIdx.x; i < ta.npts; i += blockDim.x) ta.Tp[i] = T;
+    }
+  }
   if ((int)blockIdx.x < nloop) {
-    loop_dispatch<SMAX, MIXED>(b, loop_items[blockIdx.x], smem);
+    loop_dispatch<SMAX, MIXED>(b, loop_items[blockIdx.x], smem, &ta);
     return;
   }
   const int4 item = fwd_items[blockIdx.x - nloop];
@@ -286,17 +307,18 @@ k_loops_fwd(Batch b, const int4* __restrict__ loop_items, int nloop, const int4*
 }
 
 template <int SMAX, bool MIXED>
-void launch_loops_fwd_kt(const Launch& L, const Ranges& r, const double* X, bool cross, hipStream_t s) {
+void launch_loops_fwd_kt(const Launch& L, const Ranges& r, const double* X, bool cross, const TArg& ta,
+                         hipStream_t s) {
   const int nf = cross ? r.fwd.n : 0;
   const dim3 g(r.loop.n + nf), blk(L.front_threads);
   const size_t sm = L.front_smem;
   const int4* li = L.loop_items + r.loop.begin;
   const int4* fi = L.fwd_items + r.fwd.begin;
   switch (L.fwd_kt) {
-    case 1: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 1>), g, blk, sm, s, L.b, li, r.loop.n, fi, X); break;
-    case 2: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 2>), g, blk, sm, s, L.b, li, r.loop.n, fi, X); break;
-    case 3: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 3>), g, blk, sm, s, L.b, li, r.loop.n, fi, X); break;
-    default: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 5>), g, blk, sm, s, L.b, li, r.loop.n, fi, X); break;
+    case 1: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 1>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
+    case 2: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 2>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
+    case 3: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 3>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
+    default: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 5>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
   }
 }
 
@@ -326,20 +348,20 @@ void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, h
 }
 
 void launch_loops_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, bool cross,
-                      hipStream_t s) {
+                      const TArg& ta, hipStream_t s) {
   if (r.loop.n + (cross ? r.fwd.n : 0) <= 0) return;
   switch (L.smax_max) {
     case 0:
-      if (mixed) launch_loops_fwd_kt<0, true>(L, r, X, cross, s);
-      else launch_loops_fwd_kt<0, false>(L, r, X, cross, s);
+      if (mixed) launch_loops_fwd_kt<0, true>(L, r, X, cross, ta, s);
+      else launch_loops_fwd_kt<0, false>(L, r, X, cross, ta, s);
       break;
     case 2:
-      if (mixed) launch_loops_fwd_kt<2, true>(L, r, X, cross, s);
-      else launch_loops_fwd_kt<2, false>(L, r, X, cross, s);
+      if (mixed) launch_loops_fwd_kt<2, true>(L, r, X, cross, ta, s);
+      else launch_loops_fwd_kt<2, false>(L, r, X, cross, ta, s);
       break;
     default:
-      if (mixed) launch_loops_fwd_kt<4, true>(L, r, X, cross, s);
-      else launch_loops_fwd_kt<4, false>(L, r, X, cross, s);
+      if (mixed) launch_loops_fwd_kt<4, true>(L, r, X, cross, ta, s);
+      else launch_loops_fwd_kt<4, false>(L, r, X, cross, ta, s);
       break;
   }
 }

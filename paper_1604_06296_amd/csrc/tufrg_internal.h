@@ -142,6 +142,20 @@ struct Ranges {
   ItemRange loop, exp, fwd, basis, gather, inv, prod, seg;
 };
 
+// Where a fused loops + transform launch takes the temperatures of its
+// points: mode 0 reads the per-point array as set before the launch; mode 1
+// uses the values v[i] for points p0 + i (i < n <= 64); mode 2 takes the RK4
+// stage temperature Ttab[4 step + stage] for every point.  Block 0 of the
+// launch also stores them into the per-point array Tp for later kernels.
+struct TArg {
+  int mode, p0, n, npts;
+  double* Tp;
+  const double* Ttab;
+  const int* step;
+  int stage;
+  double v[64];
+};
+
 // Device item tables and launch shapes shared by all launches of a context.
 struct Launch {
   Batch b;
@@ -189,7 +203,7 @@ void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed,
 void launch_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s);
 void launch_gather_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t s);
 void launch_loops_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, bool cross,
-                      hipStream_t s);
+                      const TArg& ta, hipStream_t s);
 void launch_expand_basis(const Launch& L, const Ranges& r, double* dchi, bool cross, hipStream_t s);
 void launch_back(const Launch& L, const Ranges& r, const double* X, double* out, int mode,
                  bool cross, bool scale_T, bool mixed, hipStream_t s);
