@@ -32,8 +32,8 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CUs x 64 lanes x 2 fl
 # geometry), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by
 # the counters of a plain 64 MiB device copy; valid only for the kernel
 # sources they were taken with (profiles/loop_kernel_traffic_*.md).
-LOOP_TRAFFIC = {"sources_sha256": "af537ae14eedfbf59afc6e3b40be3c0317ace5d10f3a9405c6a09211cd485132",
-                "bytes": 561811}
+LOOP_TRAFFIC = {"sources_sha256": "02671ca1fac00e18242ed7b0f877df576578cce6fad103a566dda8d961a298d6",
+                "bytes": 571726}
 
 
 def loop_kernel_sources_sha():
