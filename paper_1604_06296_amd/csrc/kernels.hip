@@ -596,22 +596,63 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
   __syncthreads();
   const R* VP = Vs;
   const R* VC = Vs + nff2;
-  for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
-    const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
-    const R* A = Ch + (which == 0 ? 0 : nff2) + m * nff;
-    const R* B = which == 0 ? VP : (which == 1 ? VC : Wm);
-    R v = 0;
-    for (int k = 0; k < nff; ++k) v = fma(A[k], B[k * nff + n], v);
-    T1[w] = v;
+  // the six N_ff x N_ff products; in 3x3 register tiles each A and B entry is
+  // read from LDS once per tile.  Every output sums k in order either way.
+  const int nt = (nff + 2) / 3;
+  auto product = [&](const R* A, const R* B, R* C, int ti, int tj) {
+    const int m0 = 3 * ti, n0 = 3 * tj;
+    R c[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) c[i][j] = 0;
+    for (int k = 0; k < nff; ++k) {
+      R a[3], bb[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) a[i] = m0 + i < nff ? A[(m0 + i) * nff + k] : (R)0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) bb[j] = n0 + j < nff ? B[k * nff + n0 + j] : (R)0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) c[i][j] = fma(a[i], bb[j], c[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        if (m0 + i < nff && n0 + j < nff) C[(m0 + i) * nff + n0 + j] = c[i][j];
+  };
+  // one output per thread while the block holds every output in a round or
+  // two (N_ff <= 13); 3x3 tiles beyond
+  const bool tiled = nff > 13;
+  const int nw = tiled ? 3 * nt * nt : 3 * nff2;
+  for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+    if (tiled) {
+      const int which = w / (nt * nt), ti = w / nt % nt, tj = w % nt;
+      product(Ch + (which == 0 ? 0 : nff2), which == 0 ? VP : (which == 1 ? VC : Wm), T1 + which * nff2, ti, tj);
+    } else {
+      const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
+      const R* A = Ch + (which == 0 ? 0 : nff2) + m * nff;
+      const R* B = which == 0 ? VP : (which == 1 ? VC : Wm);
+      R v = 0;
+      for (int k = 0; k < nff; ++k) v = fma(A[k], B[k * nff + n], v);
+      T1[w] = v;
+    }
   }
   __syncthreads();
-  for (int w = threadIdx.x; w < 3 * nff2; w += blockDim.x) {
-    const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
-    const R* A = (which == 0 ? VP : (which == 1 ? VC : Wm)) + m * nff;
-    const R* B = T1 + which * nff2;
-    R v = 0;
-    for (int k = 0; k < nff; ++k) v = fma(A[k], B[k * nff + n], v);
-    T2[w] = v;
+  for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+    if (tiled) {
+      const int which = w / (nt * nt), ti = w / nt % nt, tj = w % nt;
+      product(which == 0 ? VP : (which == 1 ? VC : Wm), T1 + which * nff2, T2 + which * nff2, ti, tj);
+    } else {
+      const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
+      const R* A = (which == 0 ? VP : (which == 1 ? VC : Wm)) + m * nff;
+      const R* B = T1 + which * nff2;
+      R v = 0;
+      for (int k = 0; k < nff; ++k) v = fma(A[k], B[k * nff + n], v);
+      T2[w] = v;
+    }
   }
   __syncthreads();
   for (int w = threadIdx.x; w < nff2; w += blockDim.x) {
