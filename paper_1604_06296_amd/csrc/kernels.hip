@@ -376,8 +376,9 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
   f64x4 acc[LT];
 #pragma unroll
   for (int t = 0; t < LT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < ncol; k0 += 16) {
-    double ev[LT], gv[4];
+  // software pipeline: chunk c + 1's loads are in flight during chunk c's MFMAs
+  double ev[LT], gv[4];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < LT; ++i) {
       const int e = tid + 256 * i, l = l0 + (e >> 4), k = k0 + (e & 15);
@@ -388,6 +389,9 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
       const int k = k0 + gk + 4 * i;
       gv[i] = (gok && k < ncol) ? gsrc[(size_t)k * nff2] : 0.0;
     }
+  };
+  load(0);
+  for (int k0 = 0; k0 < ncol; k0 += 16) {
 #pragma unroll
     for (int i = 0; i < LT; ++i) {
       const int e = tid + 256 * i;
@@ -396,6 +400,7 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
 #pragma unroll
     for (int i = 0; i < 4; ++i) Gs[gk + 4 * i][gc] = gv[i];
     __syncthreads();
+    if (k0 + 16 < ncol) load(k0 + 16);
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4) {
       const double bv = Gs[kk + k4][16 * w + r16];

@@ -71,8 +71,9 @@ __device__ __forceinline__ void fwd_part_body(const Batch& b, const DevTables& d
   f64x4 acc[KT];
 #pragma unroll
   for (int t = 0; t < KT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int ub = u0; ub < u1; ub += 32) {
-    double ev[EPT], xv[8];
+  // software pipeline: chunk c + 1's loads are in flight during chunk c's MFMAs
+  double ev[EPT], xv[8];
+  auto load = [&](int ub) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * nt, uu = e / TK, k = e % TK, u = ub + uu;
@@ -83,6 +84,9 @@ __device__ __forceinline__ void fwd_part_body(const Batch& b, const DevTables& d
       const int u = ub + xr + 4 * i;
       xv[i] = (xok && u < u1) ? xsrc[(size_t)u * nff2] : 0.0;
     }
+  };
+  if (u0 < u1) load(u0);
+  for (int ub = u0; ub < u1; ub += 32) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * nt;
@@ -91,6 +95,7 @@ __device__ __forceinline__ void fwd_part_body(const Batch& b, const DevTables& d
 #pragma unroll
     for (int i = 0; i < 8; ++i) Xs[(xr + 4 * i) * XS + xc] = xv[i];
     __syncthreads();
+    if (ub + 32 < u1) load(ub + 32);
 #pragma unroll
     for (int uk = 0; uk < 32; uk += 4) {
       const double bv = Xs[(uk + k4) * XS + 16 * w + r16];
