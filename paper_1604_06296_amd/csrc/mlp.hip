@@ -74,19 +74,18 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kb; k0 < ke; k0 += kKC) {
+  // software pipeline: the next K chunk's operands are loaded into registers
+  // while the current chunk is in the matrix cores, then split and staged
+  float av[8], bv[8];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int e = tid + 256 * i;
       const int m = g.transA ? e % kTM : e / kKC;
       const int k = g.transA ? e / kTM : e % kKC;
       const int gm = m0 + m, gk = k0 + k;
-      float v = 0.f;
-      if (gm < g.M && gk < ke)
-        v = g.transA ? g.A[(size_t)gk * g.lda + gm] : g.A[(size_t)gm * g.lda + gk];
-      const unsigned short h = bf16_rne(v);
-      Ah[m * kLDK + k] = h;
-      if constexpr (PASSES == 3) Al[m * kLDK + k] = bf16_rne(v - bf16_value(h));
+      av[i] = (gm < g.M && gk < ke) ? (g.transA ? g.A[(size_t)gk * g.lda + gm] : g.A[(size_t)gm * g.lda + gk])
+                                    : 0.f;
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -94,14 +93,32 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       const int n = g.transB ? e / kKC : e % kTN;
       const int k = g.transB ? e % kKC : e / kTN;
       const int gn = n0 + n, gk = k0 + k;
-      float v = 0.f;
-      if (gn < g.N && gk < ke)
-        v = g.transB ? g.B[(size_t)gn * g.ldb + gk] : g.B[(size_t)gk * g.ldb + gn];
-      const unsigned short h = bf16_rne(v);
+      bv[i] = (gn < g.N && gk < ke) ? (g.transB ? g.B[(size_t)gn * g.ldb + gk] : g.B[(size_t)gk * g.ldb + gn])
+                                    : 0.f;
+    }
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += kKC) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid + 256 * i;
+      const int m = g.transA ? e % kTM : e / kKC;
+      const int k = g.transA ? e / kTM : e % kKC;
+      const unsigned short h = bf16_rne(av[i]);
+      Ah[m * kLDK + k] = h;
+      if constexpr (PASSES == 3) Al[m * kLDK + k] = bf16_rne(av[i] - bf16_value(h));
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid + 256 * i;
+      const int n = g.transB ? e / kKC : e % kTN;
+      const int k = g.transB ? e % kKC : e / kTN;
+      const unsigned short h = bf16_rne(bv[i]);
       Bh[n * kLDK + k] = h;
-      if constexpr (PASSES == 3) Bl[n * kLDK + k] = bf16_rne(v - bf16_value(h));
+      if constexpr (PASSES == 3) Bl[n * kLDK + k] = bf16_rne(bv[i] - bf16_value(h));
     }
     __syncthreads();
+    if (k0 + kKC < ke) load(k0 + kKC);
 #pragma unroll
     for (int kk = 0; kk < kKC; kk += 16) {
       const int kq = kk + 4 * (lane >> 4);
