@@ -59,7 +59,10 @@ constexpr int kTM = 64, kTN = 64, kKC = 32, kLDK = kKC + 8;   // LDS row stride 
 // C tile 64 x 64 per block of 4 waves; each wave owns a 32 x 32 quarter as
 // 2 x 2 tiles of v_mfma_f32_16x16x16bf16_1k.  Operands are read as FP32,
 // rounded to BF16 (and split hi/lo when PASSES == 3) into LDS, K chunk 32.
-template <int PASSES>
+// VEC: op(A) = A and op(B) = B^T with rows of K contiguous and 16-byte
+// aligned (lda, ldb multiples of 4): each thread stages two 4-wide K quads of
+// A and of B with one 16-byte load each and one 8-byte LDS store per BF16 quad.
+template <int PASSES, bool VEC>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) unsigned short Ah[kTM * kLDK];
   __shared__ __attribute__((aligned(16))) unsigned short Bh[kTN * kLDK];
@@ -77,45 +80,87 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   // software pipeline: the next K chunk's operands are loaded into registers
   // while the current chunk is in the matrix cores, then split and staged
   float av[8], bv[8];
+  const int vr = tid >> 3, vk = 4 * (tid & 7);   // VEC: rows vr + 32 i, K quad vk
+  auto quad = [&](const float* row, bool ok, int gk, float* dst) {
+    if (ok && gk + 4 <= ke) {
+      const float4 q = *reinterpret_cast<const float4*>(row + gk);
+      dst[0] = q.x;
+      dst[1] = q.y;
+      dst[2] = q.z;
+      dst[3] = q.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dst[j] = (ok && gk + j < ke) ? row[gk + j] : 0.f;
+    }
+  };
   auto load = [&](int k0) {
+    if constexpr (VEC) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = tid + 256 * i;
-      const int m = g.transA ? e % kTM : e / kKC;
-      const int k = g.transA ? e / kTM : e % kKC;
-      const int gm = m0 + m, gk = k0 + k;
-      av[i] = (gm < g.M && gk < ke) ? (g.transA ? g.A[(size_t)gk * g.lda + gm] : g.A[(size_t)gm * g.lda + gk])
-                                    : 0.f;
-    }
+      for (int i = 0; i < 2; ++i) {
+        const int gm = m0 + vr + 32 * i, gn = n0 + vr + 32 * i;
+        quad(g.A + (size_t)(gm < g.M ? gm : 0) * g.lda, gm < g.M, k0 + vk, av + 4 * i);
+        quad(g.B + (size_t)(gn < g.N ? gn : 0) * g.ldb, gn < g.N, k0 + vk, bv + 4 * i);
+      }
+    } else {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = tid + 256 * i;
-      const int n = g.transB ? e / kKC : e % kTN;
-      const int k = g.transB ? e % kKC : e / kTN;
-      const int gn = n0 + n, gk = k0 + k;
-      bv[i] = (gn < g.N && gk < ke) ? (g.transB ? g.B[(size_t)gn * g.ldb + gk] : g.B[(size_t)gk * g.ldb + gn])
-                                    : 0.f;
+      for (int i = 0; i < 8; ++i) {
+        const int e = tid + 256 * i;
+        const int m = g.transA ? e % kTM : e / kKC;
+        const int k = g.transA ? e / kTM : e % kKC;
+        const int gm = m0 + m, gk = k0 + k;
+        av[i] = (gm < g.M && gk < ke) ? (g.transA ? g.A[(size_t)gk * g.lda + gm] : g.A[(size_t)gm * g.lda + gk])
+                                      : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = tid + 256 * i;
+        const int n = g.transB ? e / kKC : e % kTN;
+        const int k = g.transB ? e % kKC : e / kTN;
+        const int gn = n0 + n, gk = k0 + k;
+        bv[i] = (gn < g.N && gk < ke) ? (g.transB ? g.B[(size_t)gn * g.ldb + gk] : g.B[(size_t)gk * g.ldb + gn])
+                                      : 0.f;
+      }
     }
+  };
+  auto store_quad = [&](const float* v, unsigned short* hi, unsigned short* lo) {
+    bf16x4 qh, ql;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const unsigned short h = bf16_rne(v[j]);
+      qh[j] = (short)h;
+      ql[j] = (short)bf16_rne(v[j] - bf16_value(h));
+    }
+    *reinterpret_cast<bf16x4*>(hi) = qh;
+    if constexpr (PASSES == 3) *reinterpret_cast<bf16x4*>(lo) = ql;
   };
   if (kb < ke) load(kb);
   for (int k0 = kb; k0 < ke; k0 += kKC) {
+    if constexpr (VEC) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = tid + 256 * i;
-      const int m = g.transA ? e % kTM : e / kKC;
-      const int k = g.transA ? e / kTM : e % kKC;
-      const unsigned short h = bf16_rne(av[i]);
-      Ah[m * kLDK + k] = h;
-      if constexpr (PASSES == 3) Al[m * kLDK + k] = bf16_rne(av[i] - bf16_value(h));
-    }
+      for (int i = 0; i < 2; ++i) {
+        const int r = vr + 32 * i;
+        store_quad(av + 4 * i, &Ah[r * kLDK + vk], &Al[PASSES == 3 ? r * kLDK + vk : 0]);
+        store_quad(bv + 4 * i, &Bh[r * kLDK + vk], &Bl[PASSES == 3 ? r * kLDK + vk : 0]);
+      }
+    } else {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = tid + 256 * i;
-      const int n = g.transB ? e / kKC : e % kTN;
-      const int k = g.transB ? e % kKC : e / kTN;
-      const unsigned short h = bf16_rne(bv[i]);
-      Bh[n * kLDK + k] = h;
-      if constexpr (PASSES == 3) Bl[n * kLDK + k] = bf16_rne(bv[i] - bf16_value(h));
+      for (int i = 0; i < 8; ++i) {
+        const int e = tid + 256 * i;
+        const int m = g.transA ? e % kTM : e / kKC;
+        const int k = g.transA ? e / kTM : e % kKC;
+        const unsigned short h = bf16_rne(av[i]);
+        Ah[m * kLDK + k] = h;
+        if constexpr (PASSES == 3) Al[m * kLDK + k] = bf16_rne(av[i] - bf16_value(h));
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = tid + 256 * i;
+        const int n = g.transB ? e / kKC : e % kTN;
+        const int k = g.transB ? e % kKC : e / kTN;
+        const unsigned short h = bf16_rne(bv[i]);
+        Bh[n * kLDK + k] = h;
+        if constexpr (PASSES == 3) Bl[n * kLDK + k] = bf16_rne(bv[i] - bf16_value(h));
+      }
     }
     __syncthreads();
     if (k0 + kKC < ke) load(k0 + kKC);
@@ -317,10 +362,15 @@ tufrg_status malloc_dev(tufrg_mlp* n, size_t count, T** out) {
 
 void gemm(hipStream_t s, int passes, const GemmArgs& a, int splits) {
   const dim3 grid((a.N + kTN - 1) / kTN, (a.M + kTM - 1) / kTM, splits);
-  if (passes == 3)
-    hipLaunchKernelGGL(k_gemm<3>, grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_gemm<1>, grid, dim3(256), 0, s, a);
+  const bool vec = !a.transA && a.transB && a.lda % 4 == 0 && a.ldb % 4 == 0 &&
+                   reinterpret_cast<uintptr_t>(a.A) % 16 == 0 && reinterpret_cast<uintptr_t>(a.B) % 16 == 0;
+  if (passes == 3) {
+    if (vec) hipLaunchKernelGGL((k_gemm<3, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_gemm<3, false>), grid, dim3(256), 0, s, a);
+  } else {
+    if (vec) hipLaunchKernelGGL((k_gemm<1, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_gemm<1, false>), grid, dim3(256), 0, s, a);
+  }
 }
 
 GemmArgs base_args() {
