@@ -594,6 +594,9 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     for (int s = 0; s < t.nshell; ++s)
       for (int m = t.shell_start[s]; m < t.shell_start[s + 1]; ++m) so[m] = s;
     std::vector<int32_t> hx(t.hx.begin(), t.hx.end()), hy(t.hy.begin(), t.hy.end());
+    std::vector<double> ebub_t(t.ebub.size());
+    for (int mn = 0; mn < t.nff * t.nff; ++mn)
+      for (int j = 0; j < t.nsh; ++j) ebub_t[(size_t)j * t.nff * t.nff + mn] = t.ebub[(size_t)mn * t.nsh + j];
     std::vector<double> ephp((size_t)t.nq * kEpad, 0.0);
     for (int u = 0; u < t.nq; ++u)
       for (int k = 0; k < t.ncol; ++k) ephp[(size_t)u * kEpad + k] = t.eph[(size_t)u * t.ncol + k];
@@ -614,7 +617,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     tufrg_status st;
     if ((st = upload(ctx, cre, &d.cre, A)) || (st = upload(ctx, cim, &d.cim, A)) ||
         (st = upload(ctx, ss, &d.shell_start, A)) || (st = upload(ctx, so, &d.shell_of, A)) ||
-        (st = upload(ctx, t.ebub, &d.ebub, A)) || (st = upload(ctx, t.pxtab, &d.pxtab, A)) ||
+        (st = upload(ctx, ebub_t, &d.ebub, A)) || (st = upload(ctx, t.pxtab, &d.pxtab, A)) ||
         (st = upload(ctx, t.pytab, &d.pytab, A)) || (st = upload(ctx, t.eph, &d.eph, A)) ||
         (st = upload(ctx, ephp, &d.ephp, A)) ||
         (st = upload(ctx, t.cshift, &d.cshift, A)) || (st = upload(ctx, qhi, &d.ephq_hi, A)) ||

@@ -93,7 +93,7 @@ __device__ __forceinline__ void expand_body(const Batch& b, const int4 item, con
 #pragma unroll
     for (int i = 0; i < kB; ++i) {
       const int e = tid + 256 * i, j = e / kExpCols, mn = c0 + e % kExpCols;
-      bv[i] = (j < nsh && mn < nff2) ? d.ebub[(size_t)mn * nsh + j] : 0.0;
+      bv[i] = (j < nsh && mn < nff2) ? d.ebub[(size_t)j * nff2 + mn] : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < kB; ++i) {

@@ -96,7 +96,7 @@ struct DevTables {
   double* cim;
   int* shell_start;       // [nshell+1]
   int* shell_of;          // [nff]
-  double* ebub;           // [nff*nff*nsh]
+  double* ebub;           // [nsh][nff*nff] (the host table transposed: coalesced over mn)
   double* pxtab;          // [lk][2 smax + 1]
   double* pytab;          // [lk/2+1][2 smax + 1]
   double* cshift;         // [lq][lk][2]: cos(p_j + q_i/2), cos(p_j - q_i/2) per axis
