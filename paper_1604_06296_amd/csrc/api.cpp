@@ -333,13 +333,6 @@ void loops_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, double* dchi
   launch_chi_expand(L, r.exp, nullptr, dchi, s);
 }
 
-// One right-hand side on stream ms.  The loops and the projections are
-// independent until the products, so they share launches on one stream:
-// (loops + forward transform), (loop expansion + bond basis), gather,
-// inverse transform, products, when the context is small enough for launch
-// costs to dominate (Launch::fused).  Otherwise, and with the surrogate, the
-// loops run on the side stream (fork and join by events) alongside the
-// whole projection chain.
 // The temperatures of one right-hand side: host values for points p0 .. p0+n-1,
 // or (host == nullptr) the RK4 stage temperature Ttab[4 step + stage] of every
 // point, read on the device.
@@ -355,6 +348,13 @@ void set_T_launch(tufrg_ctx* ctx, const TSource& ts, hipStream_t s) {
   else launch_set_T(ctx->Tp, (int)ctx->dev.size(), ctx->Ttab, ctx->step, ts.stage, s);
 }
 
+// One right-hand side on stream ms.  The loops and the projections are
+// independent until the products, so they share launches on one stream:
+// (loops + forward transform), (loop expansion + bond basis), gather,
+// inverse transform, products, when the context is small enough for launch
+// costs to dominate (Launch::fused).  Otherwise, and with the surrogate, the
+// loops run on the side stream (fork and join by events) alongside the
+// whole projection chain.
 void rhs_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, const double* X, double* out,
                 bool scale_T, hipStream_t ms, const TSource& ts) {
   const bool mixed = mixed_of(ctx), cross = cross_of(ctx);

@@ -119,6 +119,29 @@ def test_fused_and_two_stream_forms_identical(tf, precision):
     assert torch.equal(Xa, Xb)
 
 
+def test_fused_form_with_more_points_than_passed_by_value(tf):
+    """A small context of 70 points runs fused, but its temperatures (one per
+    point) are more than the fused launch takes by value: they are stored by a
+    separate launch first.  Same bits as the two-stream form, and every point
+    keeps its own temperature."""
+    print("[batch] fused, 70 points", flush=True)
+    torch = _torch()
+    pts = [synth.Point(t=1.0, tp=-0.05 * (i % 5), U=2.0 + 0.02 * i, Lq=6, Lk=12 + 4 * (i % 3), shells=i % 2,
+                       mu=-0.1 * (i % 7)) for i in range(70)]
+    a = tf.Context(pts)
+    b = tf.Context(pts, fuse=False)
+    assert a.S <= 1 << 18
+    Ts = [0.05 + 0.01 * i for i in range(70)]
+    Xs = [synth.random_channels(p.nq, FormFactors(p.shells).nff, seed=300 + i) for i, p in enumerate(pts)]
+    ra = a.rhs(Ts, _pack(a, Xs))
+    assert torch.equal(ra, b.rhs(Ts, _pack(b, Xs)))
+    for i in (0, 37, 69):
+        one = tf.Context([pts[i]])
+        ref = one.view(one.rhs(Ts[i], _pack(one, [Xs[i]]))).cpu().numpy()
+        _normwise(a.view(ra, i).cpu().numpy(), ref, 1e-12, f"pt{i} batch vs single")
+        one.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_point_group_reduction_matches_full_grid(tf, precision):
     """Loops on one representative per C4v orbit equal the loops at every
