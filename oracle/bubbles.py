@@ -1,4 +1,4 @@
-"""Form-factor projected fermionic loops chi^pp, chi^ph and their T-derivatives.
+"""Form-factor projected fermionic loops chi^pp, chi^ph and their scale derivatives.
 
 TEST INFRASTRUCTURE ONLY (plain FP64 CPU oracle; never used by the GPU path).
 
@@ -26,6 +26,19 @@ with x = (a-b)/2 (ph) or (a+b)/2 (pp) and x coth x = 1 at x = 0.
 L is evaluated in the log domain so that no intermediate overflows; the
 bracket is split into its exact linear part and small one-signed tails, so
 that exponentially small derivatives keep their relative accuracy.
+
+Omega-cutoff regulator (regulator="omega"; Sec. 4 runs its flows with the
+Omega-cutoff of Husemann and Salmhofer, self-energy neglected): at T = 0
+    G(i w, eps) = chi(w) / (i w - eps),   chi(w) = w^2 / (w^2 + Om^2),
+the Matsubara sum becomes int dw/2pi and the dot of the flow is d/dOm (the
+scale argument of these functions is then Om).  Writing
+1/((iw-a)(iw-b)) = [1/(iw-a) - 1/(iw-b)]/(a-b) and keeping the part of
+1/(iw-a) that is even in w, -a/(w^2+a^2),
+    L^ph = -(I(eps1) - I(eps2))/(eps1 - eps2),
+    L^pp = +(I(eps1) + I(eps2))/(eps1 + eps2),
+    I(a) = int dw/2pi chi(w)^2 a/(w^2+a^2) = a (Om + 2|a|) / (4 (Om + |a|)^2)
+(partial fractions in w^2), and the flow derivative replaces I by
+dI/dOm = -a (Om + 3|a|) / (4 (Om + |a|)^3).
 """
 from __future__ import annotations
 
@@ -105,16 +118,70 @@ def loop_dot(eps1, eps2, T, channel: str):
     return loop(eps1, eps2, T, channel) * bracket / T
 
 
+# ------------------------------------------------------------ Omega cutoff
+def omega_I(a, Om, dot: bool = False):
+    """I(a) = int dw/2pi chi(w)^2 a/(w^2+a^2), or dI/dOm (dot=True); odd in a."""
+    a = np.asarray(a, dtype=float)
+    u = Om + np.abs(a)
+    if dot:
+        return -a * (Om + 3.0 * np.abs(a)) / (4.0 * u ** 3)
+    return a * (Om + 2.0 * np.abs(a)) / (4.0 * u * u)
+
+
+def _omega_divided_difference(a, b, Om, dot: bool):
+    """(I(a) - I(b)) / (a - b) (or of dI/dOm) without cancellation.
+
+    I(a) = sgn(a) G(|a|) with G rational in u = Om + |a|:
+        G      = 1/2 - 3 Om/(4u) + Om^2/(4u^2),
+        dG/dOm = -3/(4u) + 5 Om/(4u^2) - Om^2/(2u^3),
+    so for a, b of one sign (u, v = Om + |a|, Om + |b|) the difference
+    quotient is the exact rational expression below; for opposite signs
+    I(a) and I(b) have opposite signs and the plain quotient does not cancel.
+    """
+    a = np.asarray(a, dtype=float)
+    b = np.asarray(b, dtype=float)
+    u, v = Om + np.abs(a), Om + np.abs(b)
+    if dot:
+        same = 3.0 / (4.0 * u * v) - 5.0 * Om * (u + v) / (4.0 * u * u * v * v) \
+            + Om * Om * (u * u + u * v + v * v) / (2.0 * u ** 3 * v ** 3)
+    else:
+        same = 3.0 * Om / (4.0 * u * v) - Om * Om * (u + v) / (4.0 * u * u * v * v)
+    one_sign = a * b >= 0
+    d = np.where(one_sign, 1.0, a - b)
+    opposite = (omega_I(a, Om, dot) - omega_I(b, Om, dot)) / d
+    return np.where(one_sign, same, opposite)
+
+
+def loop_omega(eps1, eps2, Om, channel: str, dot: bool = False):
+    """L^X at T = 0 with the Omega cutoff (dot=True: dL^X/dOm at fixed energies)."""
+    if channel == "ph":
+        return -_omega_divided_difference(eps1, eps2, Om, dot)
+    if channel == "pp":
+        return _omega_divided_difference(eps1, -np.asarray(eps2, dtype=float), Om, dot)
+    raise ValueError(channel)
+
+
+def loop_omega_dot(eps1, eps2, Om, channel: str):
+    return loop_omega(eps1, eps2, Om, channel, dot=True)
+
+
+REGULATORS = ("T", "omega")
+
+
 def bubbles(point, T: float, which: str = "dot", ff: FormFactors | None = None,
-            q_index=None):
-    """chi (which='value') or d chi/dT (which='dot') on the transfer grid.
+            q_index=None, regulator: str = "T"):
+    """chi (which='value') or its scale derivative (which='dot') on the transfer grid.
 
     Returns an array [2][nq_sel][nff][nff] ordered (pp, ph).  The loop
     integral is the literal pairwise grid average
         chi_mn(q) = (1/N_k) sum_p L(eps(p+q/2), eps(p-q/2)) f_m(p) f_n(p)
     (discretised eqn. chis: p on the unshifted fine grid, energies taken at
-    p +- q/2, form factors at p).
+    p +- q/2, form factors at p).  regulator="T": the scale T is the
+    temperature (d/dT); regulator="omega": T = 0 and the scale is the
+    Omega cutoff (d/dOm).
     """
+    if regulator not in REGULATORS:
+        raise ValueError(regulator)
     ff = ff or FormFactors(point.shells)
     qx, qy = q_grid(point.Lq)
     if q_index is not None:
@@ -122,7 +189,10 @@ def bubbles(point, T: float, which: str = "dot", ff: FormFactors | None = None,
     px, py = k_grid(point.Lk)
     F = ff.values(px, py)                         # [nff, Nk]
     Nk = px.size
-    fn = loop_dot if which == "dot" else loop
+    if regulator == "omega":
+        fn = loop_omega_dot if which == "dot" else loop_omega
+    else:
+        fn = loop_dot if which == "dot" else loop
     out = np.empty((2, qx.size, ff.nff, ff.nff))
     for i in range(qx.size):
         e1 = dispersion(px + 0.5 * qx[i], py + 0.5 * qy[i], point.t, point.tp, point.mu)

@@ -7,7 +7,8 @@ Paper Sec. 3 (an explicit ODE solver integrates the increments) and Sec. 4
 exceeds a threshold; classify by channel, ordering vector and form-factor
 symmetry).  Readings used here:
   * the flow variable is s = ln T, dX/ds = T dX/dT, integrated downwards
-    from T0 with X(T0) = 0;
+    from T0 with X(T0) = 0 (with regulator="omega" the scale T is the Omega
+    cutoff at zero temperature, and T_c is the critical Omega);
   * fixed-step RK4 uses uniform steps in s;
   * adaptive stepping is Dormand-Prince 5(4) with its embedded error
     estimate, RMS error norm with atol + rtol max(|y|,|y_new|), step factor
@@ -87,10 +88,10 @@ def _finish(status, s_hist, m_hist, Xmax, X, ff, n_rhs, n_steps):
 
 def flow_rk4(point, T0: float, Tmin: float, nsteps: int, Xmax: float,
              X0: Optional[np.ndarray] = None, no_cross: bool = False,
-             rhs_fn: Optional[Callable] = None) -> FlowResult:
+             rhs_fn: Optional[Callable] = None, regulator: str = "T") -> FlowResult:
     """Classical RK4 with nsteps uniform steps in s = ln T from T0 to Tmin."""
     ff = FormFactors(point.shells)
-    f = rhs_fn or (lambda T, X: rhs(point, T, X, ff, no_cross=no_cross))
+    f = rhs_fn or (lambda T, X: rhs(point, T, X, ff, no_cross=no_cross, regulator=regulator))
     X = np.zeros((3, point.Lq ** 2, ff.nff, ff.nff)) if X0 is None else X0.copy()
     s, h = math.log(T0), (math.log(Tmin) - math.log(T0)) / nsteps
 
@@ -136,10 +137,10 @@ DP_B4 = [5179 / 57600, 0.0, 7571 / 16695, 393 / 640, -92097 / 339200, 187 / 2100
 def flow_dopri5(point, T0: float, Tmin: float, Xmax: float, rtol: float = 1e-7,
                 atol: float = 1e-9, h0: Optional[float] = None, max_steps: int = 100000,
                 X0: Optional[np.ndarray] = None, no_cross: bool = False,
-                rhs_fn: Optional[Callable] = None) -> FlowResult:
+                rhs_fn: Optional[Callable] = None, regulator: str = "T") -> FlowResult:
     """Adaptive Dormand-Prince 5(4) in s = ln T (FSAL), from T0 down to Tmin."""
     ff = FormFactors(point.shells)
-    f = rhs_fn or (lambda T, X: rhs(point, T, X, ff, no_cross=no_cross))
+    f = rhs_fn or (lambda T, X: rhs(point, T, X, ff, no_cross=no_cross, regulator=regulator))
     X = np.zeros((3, point.Lq ** 2, ff.nff, ff.nff)) if X0 is None else X0.copy()
     s, s_end = math.log(T0), math.log(Tmin)
     h = h0 if h0 is not None else (s_end - s) / 200.0
