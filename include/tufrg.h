@@ -13,9 +13,14 @@
  * and integrates the flow with an explicit ODE solver (Sec. 3) until the
  * largest exchange propagator exceeds a threshold (Sec. 4).
  *
- * The regulator is the temperature T: loops are T * sum over Matsubara
- * frequencies of G G with G(i w, eps) = 1/(i w - eps), and every
- * derivative is d/dT.  Transfer momenta live on a uniform Lq x Lq grid
+ * The regulator is the temperature T by default: loops are T * sum over
+ * Matsubara frequencies of G G with G(i w, eps) = 1/(i w - eps), and every
+ * derivative is d/dT.  With TUFRG_OMEGA_CUTOFF it is the Omega cutoff at
+ * zero temperature (the regulator the paper's Sec. 3 names for its runs):
+ * G(i w, eps) = chi(w)/(i w - eps) with chi(w) = w^2/(w^2 + Omega^2), loops
+ * are integrals over real frequencies, every derivative is d/dOmega, and
+ * every argument named T below (temperatures, T0, Tmin, Tc) is Omega.
+ * Transfer momenta live on a uniform Lq x Lq grid
  * q_i = 2 pi (i - Lq/2)/Lq per axis (flat index ix*Lq + iy); loops are
  * plain averages over the unshifted uniform Lk x Lk grid p_j = 2 pi j/Lk.
  *
@@ -106,6 +111,11 @@ enum {
                                item, items ordered costliest first); bit-identical
                                results.  TUFRG_AUTOTUNE times both forms and keeps
                                the faster, whatever this bit says. */
+  TUFRG_OMEGA_CUTOFF = 1u << 5, /* the flow's scale is the Omega cutoff at T = 0
+                               instead of the temperature (see the top of this
+                               file); only the loops change.  Not available with
+                               a surrogate (tufrg_surrogate_attach returns
+                               EUNSUPPORTED). */
   TUFRG_NO_FUSE = 1u << 4  /* never run the right-hand side in fused launches.  By
                                default a context whose channel state (sum of
                                Nq Nff^2 over its points) is at most 2^18 runs the
@@ -120,7 +130,7 @@ enum {
 typedef struct {
   int32_t precision;       /* TUFRG_FP64 or TUFRG_MIXED */
   uint32_t flags;          /* TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE |
-                              TUFRG_NO_SYMMETRY | TUFRG_NO_FUSE */
+                              TUFRG_NO_SYMMETRY | TUFRG_NO_FUSE | TUFRG_OMEGA_CUTOFF */
 } tufrg_options;
 
 enum { TUFRG_RK4_LOG = 0, TUFRG_DOPRI5_LOG = 1 };

@@ -19,6 +19,8 @@ AUTOTUNE = 2
 LOOP_QUEUE = 4
 NO_SYMMETRY = 8
 NO_FUSE = 16
+OMEGA_CUTOFF = 32
+REGULATORS = {"T": 0, "omega": OMEGA_CUTOFF}
 
 # every entry point declared in include/tufrg.h
 EXPORTS = ("tufrg_init", "tufrg_layout", "tufrg_geometry", "tufrg_bubbles", "tufrg_project",
@@ -257,11 +259,13 @@ class Context:
     points: objects with attributes t, tp, mu, U, Lq, Lk, shells.
     Arrays are torch float64 CUDA tensors laid out [channels][S]
     (channel-major, then point blocks [Nq][Nff][Nff]).
+    regulator: "T" (temperature flow) or "omega" (Omega cutoff at zero
+    temperature; every scale argument named T is then Omega).
     """
 
     def __init__(self, points: Sequence, precision: str = "fp64", no_cross: bool = False,
                  stream=None, autotune: bool = False, loop_queue: bool = False,
-                 no_symmetry: bool = False, fuse: bool = True):
+                 no_symmetry: bool = False, fuse: bool = True, regulator: str = "T"):
         import torch
         if not torch.cuda.is_available():
             raise TufrgError("a GPU is required (torch.cuda.is_available() is False)")
@@ -276,7 +280,7 @@ class Context:
         opt = _Options(PRECISIONS[precision],
                        (NO_CROSS if no_cross else 0) | (AUTOTUNE if autotune else 0)
                        | (LOOP_QUEUE if loop_queue else 0) | (NO_SYMMETRY if no_symmetry else 0)
-                       | (0 if fuse else NO_FUSE))
+                       | (0 if fuse else NO_FUSE) | REGULATORS[regulator])
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = C.c_void_p()
         _check(self.lib, None, self.lib.tufrg_init(arr, n, C.byref(opt),

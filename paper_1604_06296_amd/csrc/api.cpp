@@ -178,6 +178,7 @@ void add_loop_items(const DevTables& d, int p, std::vector<int4>& v, ItemRange& 
 
 bool mixed_of(const tufrg_ctx* ctx) { return ctx->opt.precision == TUFRG_MIXED; }
 bool cross_of(const tufrg_ctx* ctx) { return !(ctx->opt.flags & TUFRG_NO_CROSS); }
+bool omega_of(const tufrg_ctx* ctx) { return (ctx->opt.flags & TUFRG_OMEGA_CUTOFF) != 0; }
 
 // Item tables, slice buffers, launch shapes and the device table array from
 // the current per-point geometry (replaces those of an earlier build).
@@ -285,10 +286,11 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   L.fwd_smem = fsm;
   L.front_smem = std::max(lsm, fsm);
   L.b.loop_threads = threads;
+  L.omega = omega_of(ctx);
   // persistent loop grid: every CU filled to the kernel's occupancy
   int per_cu = 0, cus = 0;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop_kernel_symbol(smax_max, mixed),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop_kernel_symbol(smax_max, mixed, omega_of(ctx)),
                                                    threads, lsm) != hipSuccess || per_cu < 1)
     per_cu = 1;
   if (cus < 1) cus = 1;
@@ -524,7 +526,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   if (o.precision != TUFRG_FP64 && o.precision != TUFRG_MIXED)
     return fail(nullptr, TUFRG_EINVAL, "precision must be TUFRG_FP64 or TUFRG_MIXED");
   if (o.flags & ~(uint32_t)(TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE | TUFRG_NO_SYMMETRY |
-                            TUFRG_NO_FUSE))
+                            TUFRG_NO_FUSE | TUFRG_OMEGA_CUTOFF))
     return fail(nullptr, TUFRG_EINVAL, "unknown flag bits");
   auto* ctx = new tufrg_ctx();
   ctx->opt = o;
@@ -535,7 +537,8 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   ctx->dev.assign(npts, DevTables());
   int64_t S = 0, ws_yb = 0, ws_g2 = 0, ws_k = 0, ws_xp = 0;
   for (int p = 0; p < npts; ++p) {
-    std::string e = build_tables(pts[p], ctx->host[p], !(o.flags & TUFRG_NO_SYMMETRY));
+    std::string e = build_tables(pts[p], ctx->host[p], !(o.flags & TUFRG_NO_SYMMETRY),
+                                 (o.flags & TUFRG_OMEGA_CUTOFF) != 0);
     if (e.empty() && ctx->host[p].lk > kLoopThreadsMax)
       e = "Lk must be <= " + std::to_string(kLoopThreadsMax);
     for (int sh = 0; e.empty() && sh < ctx->host[p].nshell; ++sh)
@@ -757,6 +760,7 @@ tufrg_status tufrg_surrogate_dataset(tufrg_ctx* ctx, const double* T_host, int64
   if (!T_host || !x || !y) return fail(ctx, TUFRG_EINVAL, "NULL argument");
   if (n < 0) return fail(ctx, TUFRG_EINVAL, "n must be >= 0");
   if (mixed_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "training labels come from FP64 contexts");
+  if (omega_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves the temperature flow");
   ST_TRY(check_temperatures(ctx, T_host));
   launch_set_T_values(ctx->Tp, T_host, (int)ctx->dev.size(), ctx->stream);
   const Launch& L = ctx->L;
@@ -778,6 +782,7 @@ tufrg_status tufrg_surrogate_attach(tufrg_ctx* ctx, tufrg_mlp* a, tufrg_mlp* b, 
   if (!a || !b) return fail(ctx, TUFRG_EINVAL, "attach two networks (or none to detach)");
   if (ctx->dev.size() != 1) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves single-point contexts");
   if (mixed_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves FP64 contexts");
+  if (omega_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves the temperature flow");
   for (tufrg_mlp* m : {a, b})
     if (mlp_width(m, 0) != 9 || mlp_width(m, -1) != 4)
       return fail(ctx, TUFRG_EINVAL, "surrogate networks map 9 features to 4 targets");
@@ -1165,7 +1170,7 @@ tufrg_status flow_dopri5_point(tufrg_ctx* ctx, int p, const tufrg_flow_opts* o, 
     }
     n_rhs += 6;
     launch_axpy(ctx->L, seg, X, k, kDpB5, 7, h, y5, false, ms);
-    launch_errnorm(ctx->L, seg, X, y5, k, e, 7, h, o->rtol, o->atol, ctx->red, ms);
+    launch_errnorm(ctx->L, seg, X, y5, k, e, h, o->rtol, o->atol, ctx->red, ms);
     HIP_TRY(ctx, hipMemcpyAsync(red.data(), ctx->red, sizeof(double) * seg.n, hipMemcpyDeviceToHost, ms));
     HIP_TRY(ctx, hipStreamSynchronize(ms));
     double sum = 0.0;

@@ -1,4 +1,5 @@
-// Loop derivative of one (q, p) pair in the temperature flow.
+// Loop derivative of one (q, p) pair: temperature flow (below) and Omega
+// cutoff at zero temperature (at the end of this file).
 //
 // With alpha = eps(p + q/2)/(2T), beta = eps(p - q/2)/(2T) and
 // h(y) = y sech^2(y), the T-derivatives of the Matsubara-summed loops of
@@ -138,6 +139,55 @@ __host__ __device__ inline void loop_dot_pair_f32(float a, float b, float dm, fl
   const float near_pp = fmaf(-sab * (ta - tb), sinhc1(dp), s2b);
   dph = fabsf(dm) < 1.0f ? near_ph : far_ph;
   dpp = fabsf(dp) < 1.0f ? near_pp : far_pp;
+}
+
+}  // namespace tufrg
+
+namespace tufrg {
+
+// ------------------------------------------------- Omega cutoff at T = 0
+// With the regulated propagator G = chi(w)/(i w - eps), chi(w) = w^2/(w^2 +
+// Om^2), the loops are integrals over real frequencies, and their
+// Omega-derivatives are divided differences of one odd function: with
+// x = eps1/Om, y = eps2/Om,
+//   dL^ph/dOm = +Df(x, y)  / (4 Om^2),
+//   dL^pp/dOm = -Df(x, -y) / (4 Om^2),
+//   f(v) = v (1 + 3|v|) / (1 + |v|)^3,   Df(x, y) = (f(x) - f(y))/(x - y),
+// the structure of the temperature flow with h -> f and eps/(2T) -> eps/Om.
+// With u = 1/(1+|x|), w = 1/(1+|y|), a = |x| u, b = |y| w (all in [0, 1]):
+//   x, y of one sign:       Df = u w (1 + a + b - 2 (a^2 + a b + b^2))
+//     (an exact rational identity: f(x) - f(y) never cancels),
+//   x, y of opposite signs: Df = (a u (3 - 2u) + b w (3 - 2w)) / (|x| + |y|)
+//     (a weighted mean of bounded terms; f(|x|) = a u (3 - 2u)).
+// Both channels share u, w, a and b: ph takes the one-sign form when
+// x y >= 0, pp (y -> -y) when x y <= 0.
+template <class Rcp>
+__host__ __device__ inline void omega_dot_pair_t(double x, double y, double& dph, double& dpp,
+                                                 Rcp rcp) {
+  const double ax = fabs(x), ay = fabs(y);
+  const double u = rcp(1.0 + ax), w = rcp(1.0 + ay);
+  const double a = ax * u, b = ay * w;
+  const double one = u * w * (1.0 + a + b - 2.0 * (a * a + a * b + b * b));
+  const double den = ax + ay;
+  const double opp = (a * u * (3.0 - 2.0 * u) + b * w * (3.0 - 2.0 * w)) * rcp(den > 0.0 ? den : 1.0);
+  const double xy = x * y;
+  dph = xy >= 0.0 ? one : opp;
+  dpp = xy <= 0.0 ? one : opp;
+}
+
+// The same in single precision (mixed-precision loops); x and y are formed
+// in FP64 and rounded.
+template <class Rcp>
+__host__ __device__ inline void omega_dot_pair_f32(float x, float y, float& dph, float& dpp, Rcp rcp) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float u = rcp(1.0f + ax), w = rcp(1.0f + ay);
+  const float a = ax * u, b = ay * w;
+  const float one = u * w * (1.0f + a + b - 2.0f * (a * a + a * b + b * b));
+  const float den = ax + ay;
+  const float opp = (a * u * (3.0f - 2.0f * u) + b * w * (3.0f - 2.0f * w)) * rcp(den > 0.0f ? den : 1.0f);
+  const float xy = x * y;
+  dph = xy >= 0.0f ? one : opp;
+  dpp = xy <= 0.0f ? one : opp;
 }
 
 }  // namespace tufrg

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "loop_math.h"
 #include "transforms.h"
@@ -62,7 +63,7 @@ __device__ __forceinline__ void neumaier_add(float& s, float& c, float v) {
 //
 // One loop work item with the point's exact harmonic count NH = 2 smax + 1
 // (compile-time, so the per-row harmonic loops carry no guards).
-template <int SMAX, bool MIXED>
+template <int SMAX, bool MIXED, bool OMEGA>
 __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, int p, int item_b,
                                           double T, double* smem) {
   constexpr int NH = 2 * SMAX + 1;
@@ -77,7 +78,8 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
   const int nr = R1 - R0;
   const int lq = d.lq;
   const int ix = q / lq, iy = q % lq;
-  const double inv2T = 0.5 / T;
+  // loop arguments: eps/(2T) for the temperature flow, eps/Om for the Omega cutoff
+  const double inv_s = OMEGA ? 1.0 / T : 0.5 / T;
 
   double* y1 = smem;                        // cos(py + qy/2)        [nr]
   double* y2 = y1 + nr;                     // cos(py - qy/2)        [nr]
@@ -103,11 +105,11 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
   if (active) {
     const double cx1 = d.cshift[((size_t)ix * lk + px) * 2];       // cos(px + qx/2)
     const double cx2 = d.cshift[((size_t)ix * lk + px) * 2 + 1];   // cos(px - qx/2)
-    // alpha = eps(p + q/2)/(2T) = A1 + B1 cos(py + qy/2); beta likewise
-    const double A1 = (-2.0 * d.t * cx1 - d.mu) * inv2T;
-    const double B1 = (-2.0 * d.t - 4.0 * d.tp * cx1) * inv2T;
-    const double A2 = (-2.0 * d.t * cx2 - d.mu) * inv2T;
-    const double B2 = (-2.0 * d.t - 4.0 * d.tp * cx2) * inv2T;
+    // alpha = eps(p + q/2) inv_s = A1 + B1 cos(py + qy/2); beta likewise
+    const double A1 = (-2.0 * d.t * cx1 - d.mu) * inv_s;
+    const double B1 = (-2.0 * d.t - 4.0 * d.tp * cx1) * inv_s;
+    const double A2 = (-2.0 * d.t * cx2 - d.mu) * inv_s;
+    const double B2 = (-2.0 * d.t - 4.0 * d.tp * cx2) * inv_s;
     const int r0 = (int)((int64_t)nr * c / nchunk);
     const int r1 = (int)((int64_t)nr * (c + 1) / nchunk);
     if constexpr (!MIXED) {
@@ -116,7 +118,8 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
         const double al = fma(B1, y1[r], A1);
         const double be = fma(B2, y2[r], A2);
         double dph, dpp;
-        loop_dot_pair_t(al, be, dph, dpp, DevRcp());
+        if constexpr (OMEGA) omega_dot_pair_t(al, be, dph, dpp, DevRcp());
+        else loop_dot_pair_t(al, be, dph, dpp, DevRcp());
         const double* w = pyt + r * NH;
 #pragma unroll
         for (int n = 0; n < NH; ++n) {
@@ -140,8 +143,9 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
           const double al = fma(B1, y1[r], A1);
           const double be = fma(B2, y2[r], A2);
           float dph, dpp;
-          loop_dot_pair_f32((float)al, (float)be, (float)(al - be), (float)(al + be), dph, dpp,
-                            Exp2F(), RcpF());
+          if constexpr (OMEGA) omega_dot_pair_f32((float)al, (float)be, dph, dpp, RcpF());
+          else loop_dot_pair_f32((float)al, (float)be, (float)(al - be), (float)(al + be), dph, dpp,
+                                 Exp2F(), RcpF());
           const double* w = pyt + r * NH;
 #pragma unroll
           for (int n = 0; n < NH; ++n) {
@@ -205,7 +209,8 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
   }
   __syncthreads();
   // ghat_X(q, S_j) = sgn_X gh_j / (4 T^2 Nk) (pp carries the minus sign of
-  // dL^pp/dT = -Dh/(4T^2)), written to slice `split` of the representative's
+  // dL^pp/dT = -Dh/(4T^2); with the Omega cutoff T is Om and h is f), written
+  // to slice `split` of the representative's
   // harmonics; chi'_mn = sum_j Ebub_{mn,j} ghat(q, S_j) follows in the
   // expansion kernel.
   const double base = 1.0 / (4.0 * T * T * (double)lk * (double)lk);
@@ -224,41 +229,48 @@ __device__ __forceinline__ double point_T(const Batch& b, const TArg* ta, int p)
   return b.Tp[p];
 }
 
-template <int SMAX, bool MIXED>
-__device__ __forceinline__ void loop_dispatch(const Batch& b, const int4 item, double* smem,
-                                              const TArg* ta = nullptr) {
-  const int p = item.x;
-  if (skip_point(b, p)) return;
-  const DevTables& d = b.pts[p];
-  const double T = point_T(b, ta, p);
+// Runs the body compiled for the item's own smax.
+template <int SMAX, bool MIXED, bool OMEGA>
+__device__ __forceinline__ void loop_smax(const Batch& b, const DevTables& d, int p, int item_b, double T,
+                                          double* smem) {
   if constexpr (SMAX >= 4) {
     if (d.smax == 4) {
-      loop_item<4, MIXED>(b, d, p, item.y, T, smem);
+      loop_item<4, MIXED, OMEGA>(b, d, p, item_b, T, smem);
       return;
     }
   }
   if constexpr (SMAX >= 2) {
     if (d.smax == 2) {
-      loop_item<2, MIXED>(b, d, p, item.y, T, smem);
+      loop_item<2, MIXED, OMEGA>(b, d, p, item_b, T, smem);
       return;
     }
   }
-  loop_item<0, MIXED>(b, d, p, item.y, T, smem);
+  loop_item<0, MIXED, OMEGA>(b, d, p, item_b, T, smem);
+}
+
+template <int SMAX, bool MIXED, bool OMEGA>
+__device__ __forceinline__ void loop_dispatch(const Batch& b, const int4 item, double* smem,
+                                              const TArg* ta = nullptr) {
+  const int p = item.x;
+  if (skip_point(b, p)) return;
+  const DevTables& d = b.pts[p];
+  loop_smax<SMAX, MIXED, OMEGA>(b, d, p, item.y, point_T(b, ta, p), smem);
 }
 
 // Loop kernel over work items (p, q * nsplit + split); SMAX is the largest
-// smax of the batch, and each item runs the body compiled for its own smax.
+// smax of the batch, and each item runs the body compiled for its own smax;
+// OMEGA selects the regulator (Omega cutoff at T = 0, else temperature).
 // Without a queue every block runs item blockIdx.x (the hardware dispatcher
 // balances the load, items being ordered costliest first); with a queue the
 // kernel is persistent and blocks take items until the queue is empty.
-template <int SMAX, bool MIXED>
+template <int SMAX, bool MIXED, bool OMEGA>
 __global__ void __launch_bounds__(kLoopThreadsMax)
 k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ queue) {
   extern __shared__ double smem[];
   __shared__ int cur;
   if (b.item_count != nullptr) nitems = min(nitems, *b.item_count);
   if (queue == nullptr) {
-    if ((int)blockIdx.x < nitems) loop_dispatch<SMAX, MIXED>(b, items[blockIdx.x], smem);
+    if ((int)blockIdx.x < nitems) loop_dispatch<SMAX, MIXED, OMEGA>(b, items[blockIdx.x], smem);
     return;
   }
   const int t = threadIdx.x;
@@ -268,7 +280,7 @@ k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ q
     const int it = cur;
     __syncthreads();
     if (it >= nitems) break;
-    loop_dispatch<SMAX, MIXED>(b, items[it], smem);
+    loop_dispatch<SMAX, MIXED, OMEGA>(b, items[it], smem);
   }
   if (t == 0 && atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {
     atomicExch(queue, 0);
@@ -281,7 +293,7 @@ k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ q
 // the couplings): blocks below nloop run loop items, the others forward-
 // transform items, so that both fill the machine together without a second
 // stream.  Dynamic shared memory holds the larger of the two layouts.
-template <int SMAX, bool MIXED, int KT>
+template <int SMAX, bool MIXED, int KT, bool OMEGA>
 __global__ void __launch_bounds__(kLoopThreadsMax)
 k_loops_fwd(Batch b, const int4* __restrict__ loop_items, int nloop, const int4* __restrict__ fwd_items,
             const double* __restrict__ X, TArg ta) {
@@ -297,7 +309,7 @@ k_loops_fwd(Batch b, const int4* __restrict__ loop_items, int nloop, const int4*
     }
   }
   if ((int)blockIdx.x < nloop) {
-    loop_dispatch<SMAX, MIXED>(b, loop_items[blockIdx.x], smem, &ta);
+    loop_dispatch<SMAX, MIXED, OMEGA>(b, loop_items[blockIdx.x], smem, &ta);
     return;
   }
   const int4 item = fwd_items[blockIdx.x - nloop];
@@ -306,19 +318,21 @@ k_loops_fwd(Batch b, const int4* __restrict__ loop_items, int nloop, const int4*
   else fwd_part_body<KT>(b, b.pts[item.x], item, X, smem);
 }
 
-template <int SMAX, bool MIXED>
-void launch_loops_fwd_kt(const Launch& L, const Ranges& r, const double* X, bool cross, const TArg& ta,
-                         hipStream_t s) {
-  const int nf = cross ? r.fwd.n : 0;
-  const dim3 g(r.loop.n + nf), blk(L.front_threads);
-  const size_t sm = L.front_smem;
-  const int4* li = L.loop_items + r.loop.begin;
-  const int4* fi = L.fwd_items + r.fwd.begin;
-  switch (L.fwd_kt) {
-    case 1: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 1>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
-    case 2: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 2>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
-    case 3: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 3>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
-    default: hipLaunchKernelGGL((k_loops_fwd<SMAX, MIXED, 5>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
+// Calls f(smax, mixed, omega) with the runtime values as compile-time constants.
+template <class F>
+void with_loop_variant(int smax_max, bool mixed, bool omega, F&& f) {
+  auto by_reg = [&](auto sm, auto mx) {
+    if (omega) f(sm, mx, std::true_type{});
+    else f(sm, mx, std::false_type{});
+  };
+  auto by_prec = [&](auto sm) {
+    if (mixed) by_reg(sm, std::true_type{});
+    else by_reg(sm, std::false_type{});
+  };
+  switch (smax_max) {
+    case 0: by_prec(std::integral_constant<int, 0>{}); break;
+    case 2: by_prec(std::integral_constant<int, 2>{}); break;
+    default: by_prec(std::integral_constant<int, 4>{}); break;
   }
 }
 
@@ -331,47 +345,38 @@ void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, h
   const dim3 blk(L.loop_threads);
   const size_t sm = L.loop_smem;
   const int4* it = L.loop_items + r.begin;
-  switch (L.smax_max) {
-    case 0:
-      if (mixed) hipLaunchKernelGGL((k_loops<0, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
-      else hipLaunchKernelGGL((k_loops<0, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
-      break;
-    case 2:
-      if (mixed) hipLaunchKernelGGL((k_loops<2, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
-      else hipLaunchKernelGGL((k_loops<2, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
-      break;
-    default:
-      if (mixed) hipLaunchKernelGGL((k_loops<4, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
-      else hipLaunchKernelGGL((k_loops<4, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
-      break;
-  }
+  with_loop_variant(L.smax_max, mixed, L.omega, [&](auto S, auto M, auto O) {
+    hipLaunchKernelGGL((k_loops<decltype(S)::value, decltype(M)::value, decltype(O)::value>), dim3(grid),
+                       blk, sm, s, L.b, it, r.n, queue);
+  });
 }
 
 void launch_loops_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, bool cross,
                       const TArg& ta, hipStream_t s) {
-  if (r.loop.n + (cross ? r.fwd.n : 0) <= 0) return;
-  switch (L.smax_max) {
-    case 0:
-      if (mixed) launch_loops_fwd_kt<0, true>(L, r, X, cross, ta, s);
-      else launch_loops_fwd_kt<0, false>(L, r, X, cross, ta, s);
-      break;
-    case 2:
-      if (mixed) launch_loops_fwd_kt<2, true>(L, r, X, cross, ta, s);
-      else launch_loops_fwd_kt<2, false>(L, r, X, cross, ta, s);
-      break;
-    default:
-      if (mixed) launch_loops_fwd_kt<4, true>(L, r, X, cross, ta, s);
-      else launch_loops_fwd_kt<4, false>(L, r, X, cross, ta, s);
-      break;
-  }
+  const int nf = cross ? r.fwd.n : 0;
+  if (r.loop.n + nf <= 0) return;
+  const dim3 g(r.loop.n + nf), blk(L.front_threads);
+  const size_t sm = L.front_smem;
+  const int4* li = L.loop_items + r.loop.begin;
+  const int4* fi = L.fwd_items + r.fwd.begin;
+  with_loop_variant(L.smax_max, mixed, L.omega, [&](auto S, auto M, auto O) {
+    constexpr int SM = decltype(S)::value;
+    constexpr bool MX = decltype(M)::value, OM = decltype(O)::value;
+    switch (L.fwd_kt) {
+      case 1: hipLaunchKernelGGL((k_loops_fwd<SM, MX, 1, OM>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
+      case 2: hipLaunchKernelGGL((k_loops_fwd<SM, MX, 2, OM>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
+      case 3: hipLaunchKernelGGL((k_loops_fwd<SM, MX, 3, OM>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
+      default: hipLaunchKernelGGL((k_loops_fwd<SM, MX, 5, OM>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
+    }
+  });
 }
 
-const void* loop_kernel_symbol(int smax_max, bool mixed) {
-  switch (smax_max) {
-    case 0: return mixed ? (const void*)k_loops<0, true> : (const void*)k_loops<0, false>;
-    case 2: return mixed ? (const void*)k_loops<2, true> : (const void*)k_loops<2, false>;
-    default: return mixed ? (const void*)k_loops<4, true> : (const void*)k_loops<4, false>;
-  }
+const void* loop_kernel_symbol(int smax_max, bool mixed, bool omega) {
+  const void* k = nullptr;
+  with_loop_variant(smax_max, mixed, omega, [&](auto S, auto M, auto O) {
+    k = (const void*)k_loops<decltype(S)::value, decltype(M)::value, decltype(O)::value>;
+  });
+  return k;
 }
 
 }  // namespace tufrg

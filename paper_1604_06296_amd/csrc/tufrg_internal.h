@@ -70,13 +70,14 @@ inline int32_t pack_entry(int in, int b1, int b2, int v, int neg) {
 // symmetry map entry: representative slot (16 bits), harmonic (7 bits), sign (1 bit)
 inline int32_t pack_sym(int slot, int j, int neg) { return slot | (j << 16) | (neg << 24); }
 
-std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric);   // "" on success
+std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric,
+                         bool omega);   // "" on success
 int nff_of_shells(int shells);
 
 // ---------------------------------------------------------- device side
 constexpr int kLoopThreadsMax = 512;   // loop kernel block size bound
 constexpr int64_t kFuseMaxState = 1 << 18;  // largest channel state (sum of Nq Nff^2) run in fused launches
-constexpr int kSeg = 4096;             // elements per ODE segment item
+constexpr int kSeg = 1024;             // elements per ODE segment item (4 per thread of 256)
 constexpr int kShellMax = 8;           // largest form-factor shell (bonds up to |R|^2 = 5)
 constexpr int kEpad = 80;              // padded row length of the phase table copy (ncol <= 69)
 
@@ -176,6 +177,7 @@ struct Launch {
   size_t front_smem;      // loops + transform launch: dynamic LDS
   bool loop_persistent;   // loop kernel: persistent work queue, or one block per item
   size_t loop_smem, prod_smem;
+  bool omega = false;     // the scale is the Omega cutoff at T = 0 (temperatures hold Om)
 };
 
 // Surrogate state of a single-point context (device pointers and settings).
@@ -211,9 +213,10 @@ void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const dou
                  const double* coef, int nk, double h, double* out, bool skip_frozen, hipStream_t s);
 void launch_maxabs(const Launch& L, const ItemRange& r, const double* X, unsigned long long* words,
                    hipStream_t s);
+// the embedded Dormand-Prince error: seven slopes k, weights e
 void launch_errnorm(const Launch& L, const ItemRange& r, const double* y0, const double* y5,
-                    const double* const* k, const double* e, int nk, double h, double rtol,
-                    double atol, double* red, hipStream_t s);
+                    const double* const* k, const double* e, double h, double rtol, double atol,
+                    double* red, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
 void launch_fill_i32(int* p, int n, int v, hipStream_t s);
 void launch_set_T(double* Tp, int npts, const double* Ttab, const int* step, int stage,
@@ -221,7 +224,7 @@ void launch_set_T(double* Tp, int npts, const double* Ttab, const int* step, int
 void launch_set_T_values(double* Tp, const double* T_host, int n, hipStream_t s);
 void launch_step_end(unsigned long long* words, int npts, int* frozen, double* hist, int* step,
                      int nsteps, double xmax, hipStream_t s);
-const void* loop_kernel_symbol(int smax_max, bool mixed);
+const void* loop_kernel_symbol(int smax_max, bool mixed, bool omega);
 void launch_ghat_sum(const Launch& L, int p, const DevTables& d, double* out, hipStream_t s);
 void launch_sur_dataset(const Launch& L, int npts, int64_t n, uint64_t seed, float* x, float* y,
                         int32_t* idx, hipStream_t s);

@@ -65,6 +65,7 @@ class Workload:
     rtol: float = 1e-7
     atol: float = 1e-9
     precision: str = "fp64"
+    regulator: str = "T"   # "T": temperature flow; "omega": Omega cutoff at T = 0
 
 
 def cfg1() -> Workload:
@@ -80,6 +81,15 @@ def cfg2() -> Workload:
               mu_T=1e-3)
     return Workload("hubbard_tp-0.25_n0.85_nff13_q24_k96_dopri5", [p], T0=10.0,
                     Tmin=1e-3, Xmax=20.0, scheme="dopri5")
+
+
+def cfg2_omega() -> Workload:
+    """cfg2's point flowed with the Omega cutoff at zero temperature: Omega from
+    800 (two orders of magnitude above the bandwidth 8t) down to 1e-3, stopping
+    at max|X| > 80 (one order of magnitude above the bandwidth)."""
+    w = cfg2()
+    return Workload("hubbard_tp-0.25_n0.85_nff13_q24_k96_omega_dopri5", w.points, T0=800.0,
+                    Tmin=1e-3, Xmax=80.0, scheme="dopri5", regulator="omega")
 
 
 def cfg3() -> Workload:

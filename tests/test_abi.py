@@ -83,3 +83,25 @@ def test_mlp_and_surrogate_calls_validate_arguments(lib):
     assert lib.tufrg_loop_harmonics(None, None, None) == -1
     n = C.c_int32()
     assert lib.tufrg_harmonics(None, 0, C.byref(n), None, None) == -1
+
+
+def test_flag_values_match_header(lib):
+    """The binding's flag bits are the header's, and unknown bits are rejected."""
+    import paper_1604_06296_amd.binding as b
+    from paper_1604_06296_amd.binding import _Options, _Point
+    hdr = open(os.path.join(ROOT, "include", "tufrg.h")).read()
+    bits = {m.group(1): 1 << int(m.group(2)) for m in re.finditer(r"TUFRG_([A-Z_]+)\s*=\s*1u\s*<<\s*(\d+)", hdr)}
+    for name in ("NO_CROSS", "AUTOTUNE", "NO_SYMMETRY", "LOOP_QUEUE", "NO_FUSE", "OMEGA_CUTOFF"):
+        assert getattr(b, name) == bits[name], name
+    assert b.REGULATORS == {"T": 0, "omega": bits["OMEGA_CUTOFF"]}
+    arr = (_Point * 1)(_Point(1.0, -0.2, -0.3, 3.0, 10, 16, 1, 0))
+    h = C.c_void_p()
+    assert lib.tufrg_init(arr, 1, C.byref(_Options(0, 1 << 6)), None, C.byref(h)) == -1
+    assert "flag" in lib.tufrg_last_error(None).decode()
+
+
+def test_omega_workload_definition():
+    w, w2 = synth.cfg2_omega(), synth.cfg2()
+    assert w.regulator == "omega" and w2.regulator == "T"
+    assert w.points[0] == w2.points[0]
+    assert w.T0 == 100 * 8.0 and w.Xmax == 10 * 8.0    # bandwidth 8t, t = 1
