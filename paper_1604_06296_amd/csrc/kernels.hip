@@ -686,20 +686,35 @@ __device__ __forceinline__ bool seg_range(const Batch& b, const int4& it, size_t
   return true;
 }
 
-// out = X + h sum_j coef_j k_j; frozen points untouched when skip_frozen
+// out = X + h sum_j coef_j k_j; frozen points untouched when skip_frozen.
+// Every thread holds kSeg / 256 elements of the segment and issues all their
+// loads (X and the NK slopes) before the arithmetic.
+constexpr int kSegPer = kSeg / 256;
+template <int NK>
 __global__ void __launch_bounds__(256)
-k_axpy(Batch b, const int4* __restrict__ items, const double* __restrict__ X, SlopeSet ks, int nk,
-       double h, double* __restrict__ out, int skip_frozen) {
+k_axpy(Batch b, const int4* __restrict__ items, const double* __restrict__ X, SlopeSet ks, double h,
+       double* __restrict__ out, int skip_frozen) {
   const int4 it = items[blockIdx.x];
   if (skip_frozen && skip_point(b, it.x)) return;
   size_t base;
   int n;
   if (!seg_range(b, it, base, n)) return;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const size_t e = base + i;
+  double xv[kSegPer], kv[kSegPer][NK];
+#pragma unroll
+  for (int u = 0; u < kSegPer; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    const size_t e = base + (i < n ? i : 0);
+    xv[u] = X[e];
+#pragma unroll
+    for (int j = 0; j < NK; ++j) kv[u][j] = ks.k[j][e];
+  }
+#pragma unroll
+  for (int u = 0; u < kSegPer; ++u) {
+    const int i = threadIdx.x + 256 * u;
     double acc = 0.0;
-    for (int j = 0; j < nk; ++j) acc = fma(ks.coef[j], ks.k[j][e], acc);
-    out[e] = fma(h, acc, X[e]);
+#pragma unroll
+    for (int j = 0; j < NK; ++j) acc = fma(ks.coef[j], kv[u][j], acc);
+    if (i < n) out[base + i] = fma(h, acc, xv[u]);
   }
 }
 
@@ -732,10 +747,12 @@ k_maxabs(Batch b, const int4* __restrict__ items, const double* __restrict__ X,
 }
 
 // Partial sums of ((h sum_j e_j k_j) / (atol + rtol max(|y0|,|y5|)))^2 per
-// segment, in a fixed tree order (deterministic).
+// segment, in a fixed order (each thread's elements in turn, then a tree):
+// deterministic.  Loads issued together as in k_axpy.
+template <int NK>
 __global__ void __launch_bounds__(256)
 k_errnorm(Batch b, const int4* __restrict__ items, const double* __restrict__ y0,
-          const double* __restrict__ y5, SlopeSet ks, int nk, double h, double rtol, double atol,
+          const double* __restrict__ y5, SlopeSet ks, double h, double rtol, double atol,
           double* __restrict__ red_out) {
   __shared__ double red[256];
   const int4 it = items[blockIdx.x];
@@ -743,14 +760,25 @@ k_errnorm(Batch b, const int4* __restrict__ items, const double* __restrict__ y0
   size_t base;
   int n;
   if (seg_range(b, it, base, n)) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const size_t e = base + i;
+    double av[kSegPer], bv[kSegPer], kv[kSegPer][NK];
+#pragma unroll
+    for (int u = 0; u < kSegPer; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      const size_t e = base + (i < n ? i : 0);
+      av[u] = y0[e];
+      bv[u] = y5[e];
+#pragma unroll
+      for (int j = 0; j < NK; ++j) kv[u][j] = ks.k[j][e];
+    }
+#pragma unroll
+    for (int u = 0; u < kSegPer; ++u) {
       double er = 0.0;
-      for (int j = 0; j < nk; ++j) er = fma(ks.coef[j], ks.k[j][e], er);
+#pragma unroll
+      for (int j = 0; j < NK; ++j) er = fma(ks.coef[j], kv[u][j], er);
       er *= h;
-      const double sc = atol + rtol * fmax(fabs(y0[e]), fabs(y5[e]));
+      const double sc = atol + rtol * fmax(fabs(av[u]), fabs(bv[u]));
       const double r = er / sc;
-      acc = fma(r, r, acc);
+      if ((int)threadIdx.x + 256 * u < n) acc = fma(r, r, acc);
     }
   }
   red[threadIdx.x] = acc;
@@ -895,8 +923,18 @@ void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const dou
     ks.k[j] = k[j];
     ks.coef[j] = coef[j];
   }
-  hipLaunchKernelGGL(k_axpy, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, X, ks, nk, h,
-                     out, skip_frozen ? 1 : 0);
+  const dim3 g(r.n), blk(256);
+  const int4* it = L.seg_items + r.begin;
+  const int sf = skip_frozen ? 1 : 0;
+  switch (nk) {
+    case 1: hipLaunchKernelGGL(k_axpy<1>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
+    case 2: hipLaunchKernelGGL(k_axpy<2>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
+    case 3: hipLaunchKernelGGL(k_axpy<3>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
+    case 4: hipLaunchKernelGGL(k_axpy<4>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
+    case 5: hipLaunchKernelGGL(k_axpy<5>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
+    case 6: hipLaunchKernelGGL(k_axpy<6>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
+    default: hipLaunchKernelGGL(k_axpy<7>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
+  }
 }
 
 void launch_maxabs(const Launch& L, const ItemRange& r, const double* X, unsigned long long* words,
@@ -906,16 +944,16 @@ void launch_maxabs(const Launch& L, const ItemRange& r, const double* X, unsigne
 }
 
 void launch_errnorm(const Launch& L, const ItemRange& r, const double* y0, const double* y5,
-                    const double* const* k, const double* e, int nk, double h, double rtol,
-                    double atol, double* red, hipStream_t s) {
+                    const double* const* k, const double* e, double h, double rtol, double atol,
+                    double* red, hipStream_t s) {
   if (r.n <= 0) return;
   SlopeSet ks{};
-  for (int j = 0; j < nk; ++j) {
+  for (int j = 0; j < 7; ++j) {
     ks.k[j] = k[j];
     ks.coef[j] = e[j];
   }
-  hipLaunchKernelGGL(k_errnorm, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, y0, y5, ks,
-                     nk, h, rtol, atol, red);
+  hipLaunchKernelGGL(k_errnorm<7>, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, y0, y5, ks,
+                     h, rtol, atol, red);
 }
 
 void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s) {
