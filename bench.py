@@ -32,8 +32,8 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CUs x 64 lanes x 2 fl
 # geometry), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by
 # the counters of a plain 64 MiB device copy; valid only for the kernel
 # sources they were taken with (profiles/loop_kernel_traffic_*.md).
-LOOP_TRAFFIC = {"sources_sha256": "02671ca1fac00e18242ed7b0f877df576578cce6fad103a566dda8d961a298d6",
-                "bytes": 571726}
+LOOP_TRAFFIC = {"sources_sha256": "b8de7a3fb2d3a83dba500a469080d79a93e7c8a558363ffbcbc922f2528dc357",
+                "bytes": 554529}
 
 
 def loop_kernel_sources_sha():
@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-omega", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--train-steps", type=int, default=8000)
     ap.add_argument("--probe-loops", type=int, default=0,
@@ -239,6 +240,41 @@ def leg_batched(tf, synth):
     return out
 
 
+def leg_omega(tf, synth, steps):
+    """The benchmark point with the Omega cutoff at zero temperature: right-hand
+    sides over the flow's range of Omega, the loop kernel alone, and the
+    adaptive flow (Omega 800 -> 1e-3, stop at max|X| > 80) to its critical Omega."""
+    import torch
+    w = synth.cfg2_omega()
+    pt = w.points[0]
+    pt.mu = tf.mu_from_filling(pt.t, pt.tp, pt.filling, pt.mu_T, pt.mu_L)
+    ctx = tf.Context([pt], regulator="omega")
+    X = torch.from_numpy(synth.random_channels(pt.nq, pt.nff, seed=5, scale=1.0).reshape(3, -1)).cuda()
+    o = ctx.empty(3)
+    Oms = [math.exp(math.log(w.T0) + (math.log(w.Tmin) - math.log(w.T0)) * i / 63) for i in range(64)]
+    for i in range(20):
+        ctx.rhs(Oms[i % 64], X, o)
+    _sync()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ctx.rhs(Oms[i % 64], X, o)
+    _sync()
+    el = time.perf_counter() - t0
+    loop_us, loop_flops = ctx.loop_kernel_time(0.05, reps=max(steps, 20))
+    tflops = loop_flops / (loop_us * 1e-6) / 1e12
+    r, fl = timed_flow(ctx, ctx.empty(3), tf.FlowOptions(T0=w.T0, Tmin=w.Tmin, Xmax=w.Xmax, scheme="dopri5",
+                                                         rtol=w.rtol, atol=w.atol))
+    r = r[0]
+    out = {"workload": w.name, "regulator": "omega", "rhs_per_s": steps / el, "ms_per_rhs": 1e3 * el / steps,
+           "loop_kernel_us": loop_us, "loop_kernel_flops": loop_flops, "loop_kernel_tflops": tflops,
+           "loop_kernel_frac_fp64_peak": tflops / PEAK_FP64_TFLOPS,
+           "flow": {"flow_time_s": fl, "status": r.status, "Omega_c": r.Tc, "channel": r.channel,
+                    "q_index": r.q_index, "irrep": r.irrep, "n_rhs": r.n_rhs, "n_steps": r.n_steps}}
+    log(f"[omega] rhs {out['ms_per_rhs']:.4f} ms, loop kernel {loop_us:.2f} us ({tflops:.2f} TFLOP/s), "
+        f"flow {fl:.3f} s: {out['flow']}")
+    return out
+
+
 def leg_surrogate(tf, synth, train_steps):
     """cfg5: surrogate trained on 2M exact samples; flow with and without it."""
     import torch
@@ -351,7 +387,8 @@ def main():
         log(f"[bench] flow {fl:.3f} s: {flow_info}")
 
     legs = {}
-    for name, skip, fn in (("mixed", args.no_mixed, lambda: leg_mixed(tf, synth)),
+    for name, skip, fn in (("omega", args.no_omega, lambda: leg_omega(tf, synth, args.steps)),
+                           ("mixed", args.no_mixed, lambda: leg_mixed(tf, synth)),
                            ("batched", args.no_batched, lambda: leg_batched(tf, synth)),
                            ("surrogate", args.no_surrogate, lambda: leg_surrogate(tf, synth, args.train_steps))):
         if not skip:

@@ -27,8 +27,9 @@ L is evaluated in the log domain so that no intermediate overflows; the
 bracket is split into its exact linear part and small one-signed tails, so
 that exponentially small derivatives keep their relative accuracy.
 
-Omega-cutoff regulator (regulator="omega"; Sec. 4 runs its flows with the
-Omega-cutoff of Husemann and Salmhofer, self-energy neglected): at T = 0
+Omega-cutoff regulator (regulator="omega"; Sec. 3 names the Omega cutoff of
+Husemann and Salmhofer, with the self-energy neglected, as the regulator of
+its runs): at T = 0
     G(i w, eps) = chi(w) / (i w - eps),   chi(w) = w^2 / (w^2 + Om^2),
 the Matsubara sum becomes int dw/2pi and the dot of the flow is d/dOm (the
 scale argument of these functions is then Om).  Writing

@@ -1,4 +1,4 @@
-"""Pins of the oracle's Omega-cutoff loops and flow (Sec. 4's regulator, T = 0).
+"""Pins of the oracle's Omega-cutoff loops and flow (the regulator named in Sec. 3, T = 0).
 
 The closed forms of the oracle are checked against what does not use them:
 direct numerical quadrature of the frequency integrals of the regulated
