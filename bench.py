@@ -32,8 +32,8 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CUs x 64 lanes x 2 fl
 # geometry), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by
 # the counters of a plain 64 MiB device copy; valid only for the kernel
 # sources they were taken with (profiles/loop_kernel_traffic_*.md).
-LOOP_TRAFFIC = {"sources_sha256": "b8de7a3fb2d3a83dba500a469080d79a93e7c8a558363ffbcbc922f2528dc357",
-                "bytes": 554529}
+LOOP_TRAFFIC = {"sources_sha256": "7d5aba3f78f1e447128ff058ec812976db31d4b37cae2ed2e4607cd362197bc9",
+                "bytes": 564010}
 
 
 def loop_kernel_sources_sha():

@@ -169,10 +169,11 @@ void add_point_items(const DevTables& d, int p, int inv_lt, int fwd_cols, HostIt
   });
 }
 
-// loop items of one point: one per (representative momentum, row slice)
-void add_loop_items(const DevTables& d, int p, std::vector<int4>& v, ItemRange& r) {
+// loop items of one point: one per (representative momentum, row slice),
+// (p, slot * nsplit + split, flat q of the representative)
+void add_loop_items(const DevTables& d, const HostTables& t, int p, std::vector<int4>& v, ItemRange& r) {
   mark(v, r, [&](std::vector<int4>& w) {
-    for (int b = 0; b < d.nirr * d.nsplit; ++b) w.push_back(make_int4(p, b, 0, 0));
+    for (int b = 0; b < d.nirr * d.nsplit; ++b) w.push_back(make_int4(p, b, t.irr[b / d.nsplit], 0));
   });
 }
 
@@ -201,7 +202,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
     return (double)d.lk * (d.lk / 2 + 1) / d.nsplit * (2 * d.smax + 5);
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
-  for (int p : order) add_loop_items(ctx->dev[p], p, h.loop, ctx->per_point[p].loop);
+  for (int p : order) add_loop_items(ctx->dev[p], ctx->host[p], p, h.loop, ctx->per_point[p].loop);
   // inverse-transform momentum tile: the largest of 64, 32, 16 that still
   // gives the launch 512 items
   int64_t inv_items[3] = {0, 0, 0};
@@ -1169,10 +1170,14 @@ tufrg_status flow_dopri5_point(tufrg_ctx* ctx, int p, const tufrg_flow_opts* o, 
       ST_TRY(rhs_point(ctx, p, std::exp(s + kDpC[i] * h), stage, k[i]));
     }
     n_rhs += 6;
-    launch_axpy(ctx->L, seg, X, k, kDpB5, 7, h, y5, false, ms);
-    launch_errnorm(ctx->L, seg, X, y5, k, e, h, o->rtol, o->atol, ctx->red, ms);
+    // y5, the error norm's partial sums and max|y5| in one pass, read with one sync
+    launch_fill_u64(ctx->umax + p, 1, 0ull, ms);
+    launch_dp_final(ctx->L, seg, X, k, kDpB5, e, h, o->rtol, o->atol, y5, ctx->red, ctx->umax, ms);
     HIP_TRY(ctx, hipMemcpyAsync(red.data(), ctx->red, sizeof(double) * seg.n, hipMemcpyDeviceToHost, ms));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->umax_host + p, ctx->umax + p, sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, ms));
     HIP_TRY(ctx, hipStreamSynchronize(ms));
+    const double m5 = word_to_double(ctx->umax_host[p]);
     double sum = 0.0;
     for (double v : red) sum += v;
     const double err = std::sqrt(sum / (3.0 * (double)n));
@@ -1187,7 +1192,7 @@ tufrg_status flow_dopri5_point(tufrg_ctx* ctx, int p, const tufrg_flow_opts* o, 
                                     n * sizeof(double), hipMemcpyDeviceToDevice, ms));
       std::swap(k[0], k[6]);  // first-same-as-last: the slope at the new state
       ++n_acc;
-      ST_TRY(maxabs_point(ctx, p, X, &m));
+      m = m5;
       if (m > o->Xmax)
         return finish_point(ctx, p, X, TUFRG_FLOW_DIVERGED, sprev, s, mprev, m, o->Xmax, n_rhs, n_acc, ms, r);
       if (s <= s_end + 1e-15)

@@ -729,11 +729,17 @@ k_maxabs(Batch b, const int4* __restrict__ items, const double* __restrict__ X,
   size_t base;
   int n;
   if (!skip_point(b, it.x) && seg_range(b, it, base, n)) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const double x = X[base + i];
-      unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(x));
-      if (x != x) bits = 0x7ff8000000000000ull;
-      m = bits > m ? bits : m;
+    double xv[kSegPer];
+#pragma unroll
+    for (int u = 0; u < kSegPer; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      xv[u] = X[base + (i < n ? i : 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < kSegPer; ++u) {
+      unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(xv[u]));
+      if (xv[u] != xv[u]) bits = 0x7ff8000000000000ull;
+      if ((int)threadIdx.x + 256 * u < n) m = bits > m ? bits : m;
     }
   }
   red[threadIdx.x] = m;
@@ -746,48 +752,70 @@ k_maxabs(Batch b, const int4* __restrict__ items, const double* __restrict__ X,
   if (threadIdx.x == 0 && red[0] != 0ull) atomicMax(words + it.x, red[0]);
 }
 
-// Partial sums of ((h sum_j e_j k_j) / (atol + rtol max(|y0|,|y5|)))^2 per
-// segment, in a fixed order (each thread's elements in turn, then a tree):
-// deterministic.  Loads issued together as in k_axpy.
-template <int NK>
+// The last stage of a Dormand-Prince step in one pass: y5 = y0 + h sum_j b5_j k_j
+// (as k_axpy<7>); per segment the partial sum of ((h sum_j e_j k_j) / (atol +
+// rtol max(|y0|,|y5|)))^2 in a fixed order (each thread's elements in turn,
+// then a tree: deterministic); and the point's max |y5| (as k_maxabs, into
+// word p of max_out).
+struct Coef7 {
+  double c[7];
+};
 __global__ void __launch_bounds__(256)
-k_errnorm(Batch b, const int4* __restrict__ items, const double* __restrict__ y0,
-          const double* __restrict__ y5, SlopeSet ks, double h, double rtol, double atol,
-          double* __restrict__ red_out) {
+k_dp_final(Batch b, const int4* __restrict__ items, const double* __restrict__ y0, SlopeSet ks, Coef7 e,
+           double h, double rtol, double atol, double* __restrict__ y5, double* __restrict__ red_out,
+           unsigned long long* __restrict__ max_out) {
   __shared__ double red[256];
+  __shared__ unsigned long long mred[256];
   const int4 it = items[blockIdx.x];
   double acc = 0.0;
+  unsigned long long m = 0ull;
   size_t base;
   int n;
   if (seg_range(b, it, base, n)) {
-    double av[kSegPer], bv[kSegPer], kv[kSegPer][NK];
+    double av[kSegPer], kv[kSegPer][7];
 #pragma unroll
     for (int u = 0; u < kSegPer; ++u) {
       const int i = threadIdx.x + 256 * u;
-      const size_t e = base + (i < n ? i : 0);
-      av[u] = y0[e];
-      bv[u] = y5[e];
+      const size_t idx = base + (i < n ? i : 0);
+      av[u] = y0[idx];
 #pragma unroll
-      for (int j = 0; j < NK; ++j) kv[u][j] = ks.k[j][e];
+      for (int j = 0; j < 7; ++j) kv[u][j] = ks.k[j][idx];
     }
 #pragma unroll
     for (int u = 0; u < kSegPer; ++u) {
-      double er = 0.0;
+      const int i = threadIdx.x + 256 * u;
+      double a5 = 0.0, er = 0.0;
 #pragma unroll
-      for (int j = 0; j < NK; ++j) er = fma(ks.coef[j], kv[u][j], er);
+      for (int j = 0; j < 7; ++j) a5 = fma(ks.coef[j], kv[u][j], a5);
+#pragma unroll
+      for (int j = 0; j < 7; ++j) er = fma(e.c[j], kv[u][j], er);
+      const double x5 = fma(h, a5, av[u]);
       er *= h;
-      const double sc = atol + rtol * fmax(fabs(av[u]), fabs(bv[u]));
+      const double sc = atol + rtol * fmax(fabs(av[u]), fabs(x5));
       const double r = er / sc;
-      if ((int)threadIdx.x + 256 * u < n) acc = fma(r, r, acc);
+      unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(x5));
+      if (x5 != x5) bits = 0x7ff8000000000000ull;
+      if (i < n) {
+        y5[base + i] = x5;
+        acc = fma(r, r, acc);
+        m = bits > m ? bits : m;
+      }
     }
   }
   red[threadIdx.x] = acc;
+  mred[threadIdx.x] = m;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if ((int)threadIdx.x < s) {
+      red[threadIdx.x] += red[threadIdx.x + s];
+      if (mred[threadIdx.x + s] > mred[threadIdx.x]) mred[threadIdx.x] = mred[threadIdx.x + s];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) red_out[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) {
+    red_out[blockIdx.x] = red[0];
+    if (mred[0] != 0ull) atomicMax(max_out + it.x, mred[0]);
+  }
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
@@ -943,17 +971,19 @@ void launch_maxabs(const Launch& L, const ItemRange& r, const double* X, unsigne
   hipLaunchKernelGGL(k_maxabs, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, X, words);
 }
 
-void launch_errnorm(const Launch& L, const ItemRange& r, const double* y0, const double* y5,
-                    const double* const* k, const double* e, double h, double rtol, double atol,
-                    double* red, hipStream_t s) {
+void launch_dp_final(const Launch& L, const ItemRange& r, const double* y0, const double* const* k,
+                     const double* b5, const double* e, double h, double rtol, double atol, double* y5,
+                     double* red, unsigned long long* max_words, hipStream_t s) {
   if (r.n <= 0) return;
   SlopeSet ks{};
+  Coef7 ec{};
   for (int j = 0; j < 7; ++j) {
     ks.k[j] = k[j];
-    ks.coef[j] = e[j];
+    ks.coef[j] = b5[j];
+    ec.c[j] = e[j];
   }
-  hipLaunchKernelGGL(k_errnorm<7>, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, y0, y5, ks,
-                     h, rtol, atol, red);
+  hipLaunchKernelGGL(k_dp_final, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, y0, ks, ec, h,
+                     rtol, atol, y5, red, max_words);
 }
 
 void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s) {

@@ -45,9 +45,10 @@ __device__ __forceinline__ void neumaier_add(float& s, float& c, float v) {
 
 // ------------------------------------------------------------------ loops
 // Step ii.) of Sec. 2.4, eqn. chis, at the point's temperature.  Work item
-// (p, slot * nsplit + split): one representative transfer momentum q =
+// (p, slot * nsplit + split, q): one representative transfer momentum q =
 // irr[slot] (point-group orbits; every other momentum follows by symmetry in
-// the expansion kernel) and one slice of the rows
+// the expansion kernel; q travels in the item, which saves the kernel a
+// dependent load) and one slice of the rows
 // py in [0, Lk/2] of the fine grid (the loop weight is even in p: the
 // self-paired rows py = 0 and Lk/2 carry weight 1, the others weight 2).
 // Threads own one column px and a chunk of the slice's rows; they accumulate
@@ -64,13 +65,12 @@ __device__ __forceinline__ void neumaier_add(float& s, float& c, float v) {
 // One loop work item with the point's exact harmonic count NH = 2 smax + 1
 // (compile-time, so the per-row harmonic loops carry no guards).
 template <int SMAX, bool MIXED, bool OMEGA>
-__device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, int p, int item_b,
+__device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, int p, int item_b, int q,
                                           double T, double* smem) {
   constexpr int NH = 2 * SMAX + 1;
   const int t = threadIdx.x;
   const int nsplit = d.nsplit, nchunk = d.nchunk;
   const int slot = item_b / nsplit, split = item_b % nsplit;
-  const int q = d.irr[slot];
   const int lk = d.lk;
   const int rows = lk / 2 + 1;
   const int R0 = (int)((int64_t)rows * split / nsplit);
@@ -191,12 +191,33 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
     const int sx = d.hx[j], sy = d.hy[j];          // sx >= 0
     const int ay = sy < 0 ? -sy : sy;
     const double sg = sy < 0 ? -1.0 : 1.0;
+    // cos(px sx + py sy) = cos(px sx) cos(py |sy|) - sin(px sx) sgn(sy) sin(py |sy|);
+    // four columns' operands are loaded before their terms are added in order
+    const bool two = sx > 0 && ay > 0;
     double g = 0.0;
-    for (int x = seg; x < lk; x += nseg) {
+    int x = seg;
+    for (; x + 3 * nseg < lk; x += 4 * nseg) {
+      double c[4], rc[4], sn[4], rsn[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int xx = x + u * nseg;
+        const double* r = rs + xx * 2 * NH + ch * NH;
+        c[u] = pxs[xx * NH + sx];
+        rc[u] = r[ay];
+        sn[u] = two ? pxs[xx * NH + SMAX + sx] : 0.0;
+        rsn[u] = two ? r[SMAX + ay] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double v = c[u] * rc[u];
+        if (two) v = fma(-sg * sn[u], rsn[u], v);
+        g += v;
+      }
+    }
+    for (; x < lk; x += nseg) {
       const double* r = rs + x * 2 * NH + ch * NH;
-      // cos(px sx + py sy) = cos(px sx) cos(py |sy|) - sin(px sx) sgn(sy) sin(py |sy|)
       double v = pxs[x * NH + sx] * r[ay];
-      if (sx > 0 && ay > 0) v = fma(-sg * pxs[x * NH + SMAX + sx], r[SMAX + ay], v);
+      if (two) v = fma(-sg * pxs[x * NH + SMAX + sx], r[SMAX + ay], v);
       g += v;
     }
     gh[seg * nout + o] = g;
@@ -204,7 +225,15 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
   __syncthreads();
   for (int o = t; o < nout; o += blockDim.x) {
     double g = 0.0;
-    for (int s = 0; s < nseg; ++s) g += gh[s * nout + o];
+    int s = 0;
+    for (; s + 3 < nseg; s += 4) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = gh[(s + u) * nout + o];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) g += v[u];
+    }
+    for (; s < nseg; ++s) g += gh[s * nout + o];
     gh[o] = g;
   }
   __syncthreads();
@@ -231,21 +260,21 @@ __device__ __forceinline__ double point_T(const Batch& b, const TArg* ta, int p)
 
 // Runs the body compiled for the item's own smax.
 template <int SMAX, bool MIXED, bool OMEGA>
-__device__ __forceinline__ void loop_smax(const Batch& b, const DevTables& d, int p, int item_b, double T,
-                                          double* smem) {
+__device__ __forceinline__ void loop_smax(const Batch& b, const DevTables& d, int p, int item_b, int q,
+                                          double T, double* smem) {
   if constexpr (SMAX >= 4) {
     if (d.smax == 4) {
-      loop_item<4, MIXED, OMEGA>(b, d, p, item_b, T, smem);
+      loop_item<4, MIXED, OMEGA>(b, d, p, item_b, q, T, smem);
       return;
     }
   }
   if constexpr (SMAX >= 2) {
     if (d.smax == 2) {
-      loop_item<2, MIXED, OMEGA>(b, d, p, item_b, T, smem);
+      loop_item<2, MIXED, OMEGA>(b, d, p, item_b, q, T, smem);
       return;
     }
   }
-  loop_item<0, MIXED, OMEGA>(b, d, p, item_b, T, smem);
+  loop_item<0, MIXED, OMEGA>(b, d, p, item_b, q, T, smem);
 }
 
 template <int SMAX, bool MIXED, bool OMEGA>
@@ -254,7 +283,7 @@ __device__ __forceinline__ void loop_dispatch(const Batch& b, const int4 item, d
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
-  loop_smax<SMAX, MIXED, OMEGA>(b, d, p, item.y, point_T(b, ta, p), smem);
+  loop_smax<SMAX, MIXED, OMEGA>(b, d, p, item.y, item.z, point_T(b, ta, p), smem);
 }
 
 // Loop kernel over work items (p, q * nsplit + split); SMAX is the largest

@@ -153,9 +153,10 @@ k_sur_pred(Batch b, int p, const float* __restrict__ ya, const float* __restrict
   }
 }
 
-// Items (p, slot * nsplit + s) of the representatives that need the exact
-// kernel, in increasing slot (one block, deterministic prefix sum); count =
-// items.  Below, q always denotes a representative slot.
+// Loop items (p, slot * nsplit + s, flat momentum of the representative) of
+// the representatives that need the exact kernel, in increasing slot (one
+// block, deterministic prefix sum); count = items.  Below, q always denotes a
+// representative slot.
 __global__ void __launch_bounds__(1024) k_sur_compact(Batch b, int p, SurState st) {
   __shared__ int sums[1024];
   const DevTables& d = b.pts[p];
@@ -175,7 +176,7 @@ __global__ void __launch_bounds__(1024) k_sur_compact(Batch b, int p, SurState s
   int pos = sums[threadIdx.x] - c;     // exclusive prefix: first slot of this thread
   for (int q = q0; q < q1; ++q)
     if (st.need[q]) {
-      for (int s = 0; s < ns; ++s) st.items[(size_t)pos * ns + s] = make_int4(p, q * ns + s, 0, 0);
+      for (int s = 0; s < ns; ++s) st.items[(size_t)pos * ns + s] = make_int4(p, q * ns + s, d.irr[q], 0);
       ++pos;
     }
   if (threadIdx.x == 1023) {

@@ -213,10 +213,10 @@ void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const dou
                  const double* coef, int nk, double h, double* out, bool skip_frozen, hipStream_t s);
 void launch_maxabs(const Launch& L, const ItemRange& r, const double* X, unsigned long long* words,
                    hipStream_t s);
-// the embedded Dormand-Prince error: seven slopes k, weights e
-void launch_errnorm(const Launch& L, const ItemRange& r, const double* y0, const double* y5,
-                    const double* const* k, const double* e, double h, double rtol, double atol,
-                    double* red, hipStream_t s);
+// the last Dormand-Prince stage: y5, the error partial sums and max|y5| per point
+void launch_dp_final(const Launch& L, const ItemRange& r, const double* y0, const double* const* k,
+                     const double* b5, const double* e, double h, double rtol, double atol, double* y5,
+                     double* red, unsigned long long* max_words, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
 void launch_fill_i32(int* p, int n, int v, hipStream_t s);
 void launch_set_T(double* Tp, int npts, const double* Ttab, const int* step, int stage,
