@@ -1148,6 +1148,10 @@ tufrg_status flow_dopri5_point(tufrg_ctx* ctx, int p, const tufrg_flow_opts* o, 
   const int64_t n = (int64_t)t.nq * t.nff * t.nff;
   if (ctx->nred < seg.n) {
     ST_TRY(dalloc(ctx, (size_t)seg.n, &ctx->red, ctx->allocations));
+    if (ctx->red_host) hipHostFree(ctx->red_host);
+    ctx->red_host = nullptr;
+    if (hipHostMalloc((void**)&ctx->red_host, sizeof(double) * seg.n, 0) != hipSuccess)
+      return fail(ctx, TUFRG_ENOMEM, "pinned host buffer for the error norm");
     ctx->nred = seg.n;
   }
   double s = std::log(o->T0);
@@ -1159,49 +1163,61 @@ tufrg_status flow_dopri5_point(tufrg_ctx* ctx, int p, const tufrg_flow_opts* o, 
   mprev = m;
   ST_TRY(rhs_point(ctx, p, std::exp(s), X, k[0]));
   int64_t n_rhs = 1, n_acc = 0;
-  std::vector<double> red(seg.n);
+  const double* red = ctx->red_host;
   double e[7];
   for (int j = 0; j < 7; ++j) e[j] = kDpB5[j] - kDpB4[j];
   const hipStream_t ms = ctx->stream;
+  // the accepted state lives in the caller's X or in the scratch buffer (no
+  // copy per accepted step); it is moved to X once, before returning
+  double* cur = X;
+  double* nxt = y5;
+  auto settle = [&]() -> tufrg_status {
+    if (cur != X)
+      for (int c = 0; c < 3; ++c)
+        HIP_TRY(ctx, hipMemcpyAsync(X + c * ctx->S + ctx->off[p], cur + c * ctx->S + ctx->off[p],
+                                    n * sizeof(double), hipMemcpyDeviceToDevice, ms));
+    return TUFRG_OK;
+  };
   for (int it = 0; it < max_steps; ++it) {
     if (s + h < s_end) h = s_end - s;
     for (int i = 1; i < 7; ++i) {
-      launch_axpy(ctx->L, seg, X, k, kDpA[i], i, h, stage, false, ms);
+      launch_axpy(ctx->L, seg, cur, k, kDpA[i], i, h, stage, false, ms);
       ST_TRY(rhs_point(ctx, p, std::exp(s + kDpC[i] * h), stage, k[i]));
     }
     n_rhs += 6;
     // y5, the error norm's partial sums and max|y5| in one pass, read with one sync
     launch_fill_u64(ctx->umax + p, 1, 0ull, ms);
-    launch_dp_final(ctx->L, seg, X, k, kDpB5, e, h, o->rtol, o->atol, y5, ctx->red, ctx->umax, ms);
-    HIP_TRY(ctx, hipMemcpyAsync(red.data(), ctx->red, sizeof(double) * seg.n, hipMemcpyDeviceToHost, ms));
+    launch_dp_final(ctx->L, seg, cur, k, kDpB5, e, h, o->rtol, o->atol, nxt, ctx->red, ctx->umax, ms);
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->red_host, ctx->red, sizeof(double) * seg.n, hipMemcpyDeviceToHost, ms));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->umax_host + p, ctx->umax + p, sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, ms));
     HIP_TRY(ctx, hipStreamSynchronize(ms));
     const double m5 = word_to_double(ctx->umax_host[p]);
     double sum = 0.0;
-    for (double v : red) sum += v;
+    for (int i = 0; i < seg.n; ++i) sum += red[i];
     const double err = std::sqrt(sum / (3.0 * (double)n));
-    if (!std::isfinite(err))
-      return finish_point(ctx, p, y5, TUFRG_FLOW_NONFINITE, s, s + h, m, NAN, o->Xmax, n_rhs, n_acc, ms, r);
+    if (!std::isfinite(err)) {
+      ST_TRY(settle());
+      return finish_point(ctx, p, nxt, TUFRG_FLOW_NONFINITE, s, s + h, m, NAN, o->Xmax, n_rhs, n_acc, ms, r);
+    }
     if (err <= 1.0) {
       sprev = s;
       mprev = m;
       s = s + h;
-      for (int c = 0; c < 3; ++c)
-        HIP_TRY(ctx, hipMemcpyAsync(X + c * ctx->S + ctx->off[p], y5 + c * ctx->S + ctx->off[p],
-                                    n * sizeof(double), hipMemcpyDeviceToDevice, ms));
+      std::swap(cur, nxt);
       std::swap(k[0], k[6]);  // first-same-as-last: the slope at the new state
       ++n_acc;
       m = m5;
-      if (m > o->Xmax)
-        return finish_point(ctx, p, X, TUFRG_FLOW_DIVERGED, sprev, s, mprev, m, o->Xmax, n_rhs, n_acc, ms, r);
-      if (s <= s_end + 1e-15)
-        return finish_point(ctx, p, X, TUFRG_FLOW_REACHED_TMIN, sprev, s, mprev, m, o->Xmax, n_rhs, n_acc,
-                            ms, r);
+      if (m > o->Xmax || s <= s_end + 1e-15) {
+        ST_TRY(settle());
+        return finish_point(ctx, p, X, m > o->Xmax ? TUFRG_FLOW_DIVERGED : TUFRG_FLOW_REACHED_TMIN, sprev, s,
+                            mprev, m, o->Xmax, n_rhs, n_acc, ms, r);
+      }
     }
     const double fac = err == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.9 * std::pow(err, -0.2)));
     h *= fac;
   }
+  ST_TRY(settle());
   return finish_point(ctx, p, X, TUFRG_FLOW_REACHED_TMIN, sprev, s, mprev, m, o->Xmax, n_rhs, n_acc, ms, r);
 }
 
@@ -1243,6 +1259,7 @@ void tufrg_free(tufrg_ctx* ctx) {
   if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
   if (ctx->ev_gs) hipEventDestroy(ctx->ev_gs);
   if (ctx->umax_host) hipHostFree(ctx->umax_host);
+  if (ctx->red_host) hipHostFree(ctx->red_host);
   for (void* p : ctx->sur_allocations) hipFree(p);
   for (void* p : ctx->geometry_allocations) hipFree(p);
   for (void* p : ctx->allocations) hipFree(p);

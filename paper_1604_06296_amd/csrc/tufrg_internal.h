@@ -261,6 +261,7 @@ struct tufrg_ctx {
   double* kk[7] = {nullptr};               // RK slopes [3][S]
   double* ytmp = nullptr;                  // [3][S]
   double* red = nullptr;                   // reduction scratch
+  double* red_host = nullptr;              // pinned copy of red
   int nred = 0;
   unsigned long long* umax = nullptr;      // per-point max words
   unsigned long long* umax_host = nullptr; // pinned

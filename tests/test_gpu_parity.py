@@ -239,6 +239,24 @@ def test_flow_dopri5_small(tf):
     assert (r.channel, r.q_index, r.irrep) == (ref.channel, ref.q_index, ref.irrep)
 
 
+@pytest.mark.parametrize("Tmin", [0.6, 0.45, 0.33])
+def test_flow_dopri5_state_matches_oracle(tf, Tmin):
+    """Adaptive flow that reaches Tmin: the same accepted steps as the oracle and
+    the final state in the caller's array (whichever buffer held the last
+    accepted state) equal to the oracle's at rounding level."""
+    pt = _pt(2, 8, 16, tp=-0.2, mu=-0.5, U=1.5)
+    print(f"[flow] dopri5 state, Tmin={Tmin}", flush=True)
+    ff = FormFactors(pt.shells)
+    ctx = tf.Context([pt])
+    X = ctx.empty(3).zero_()
+    r = ctx.flow(X, tf.FlowOptions(T0=10.0, Tmin=Tmin, Xmax=1e9, scheme="dopri5", rtol=1e-8, atol=1e-10))[0]
+    ref = oflow.flow_dopri5(pt, 10.0, Tmin, 1e9, rtol=1e-8, atol=1e-10)
+    print("gpu", r.status, r.n_steps, r.n_rhs, "oracle", ref.n_steps, ref.n_rhs, flush=True)
+    assert r.status == "reached_tmin" and ref.status == oflow.STATUS_REACHED_TMIN
+    assert (r.n_steps, r.n_rhs) == (ref.n_steps, ref.n_rhs)
+    _assert_normwise(_host(ctx, X), ref.X, tol=1e-9, what="X at Tmin")
+
+
 def test_flow_no_cross_is_rpa(tf):
     pt = _pt(0, 6, 16, tp=-0.1, mu=-0.2, U=2.0)
     ctx = tf.Context([pt], no_cross=True)
