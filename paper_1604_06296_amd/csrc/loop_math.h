@@ -72,28 +72,38 @@ __host__ __device__ inline double sinhc_small(double d) {
 
 constexpr double kNearDiag = 0.25;
 
-// Dh(a, b) and Dh(a, -b) (the ph and pp divided differences)
+// Dh(a, b) and Dh(a, -b) (the ph and pp divided differences).  Two refined
+// reciprocals per pair: 1/(1+qa) and 1/(1+qb) come from the reciprocal of
+// their product (in [1, 4]), and the two far-branch divisors from the
+// reciprocal of theirs (a divisor the near form replaces counts as 1, so the
+// product lies in [1/16, ~1e8] for |eps/T| up to ~1e4).  The near form is a
+// branch of its own: a wave runs it only when one of its pairs needs it.
 template <class Rcp>
 __host__ __device__ inline void loop_dot_pair_t(double a, double b, double& dph, double& dpp,
                                                 Rcp rcp) {
   const double ea = exp_neg(fabs(a)), eb = exp_neg(fabs(b));   // e^{-|a|}, e^{-|b|}
   const double qa = ea * ea, qb = eb * eb;
-  const double ra = rcp(1.0 + qa), rb = rcp(1.0 + qb);
+  const double pa = 1.0 + qa, pb = 1.0 + qb;
+  const double rab = rcp(pa * pb);
+  const double ra = rab * pb, rb = rab * pa;                   // 1/(1+qa), 1/(1+qb)
   const double sa = 2.0 * ea * ra, sb = 2.0 * eb * rb;        // sech
   const double ta = copysign((1.0 - qa) * ra, a);              // tanh
   const double tb = copysign((1.0 - qb) * rb, b);
   const double s2b = sb * sb;
   const double ha = a * sa * sa, hb = b * s2b;                 // h = y sech^2 y
-  const double dm = a - b, dp = a + b;
   const double sab = a * sa * sb;
+  const double dm = a - b, dp = a + b;
+  const bool near_m = fabs(dm) < kNearDiag, near_p = fabs(dp) < kNearDiag;
   // far from the diagonal: plain divided differences
-  const double far_ph = (ha - hb) * rcp(dm);
-  const double far_pp = (ha + hb) * rcp(dp);
+  const double gm = near_m ? 1.0 : dm, gp = near_p ? 1.0 : dp;
+  const double rmp = rcp(gm * gp);
+  dph = (ha - hb) * (gp * rmp);
+  dpp = (ha + hb) * (gm * rmp);
   // near the diagonal: bounded identity
-  const double near_ph = fma(-sab * (ta + tb), sinhc_small(dm), s2b);
-  const double near_pp = fma(-sab * (ta - tb), sinhc_small(dp), s2b);
-  dph = fabs(dm) < kNearDiag ? near_ph : far_ph;
-  dpp = fabs(dp) < kNearDiag ? near_pp : far_pp;
+  if (near_m || near_p) {
+    if (near_m) dph = fma(-sab * (ta + tb), sinhc_small(dm), s2b);
+    if (near_p) dpp = fma(-sab * (ta - tb), sinhc_small(dp), s2b);
+  }
 }
 
 }  // namespace tufrg

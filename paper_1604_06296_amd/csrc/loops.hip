@@ -113,7 +113,6 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
     const int r0 = (int)((int64_t)nr * c / nchunk);
     const int r1 = (int)((int64_t)nr * (c + 1) / nchunk);
     if constexpr (!MIXED) {
-#pragma unroll 2
       for (int r = r0; r < r1; ++r) {
         const double al = fma(B1, y1[r], A1);
         const double be = fma(B2, y2[r], A2);
