@@ -32,8 +32,8 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CUs x 64 lanes x 2 fl
 # geometry), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by
 # the counters of a plain 64 MiB device copy; valid only for the kernel
 # sources they were taken with (profiles/loop_kernel_traffic_*.md).
-LOOP_TRAFFIC = {"sources_sha256": "bbb2d4a296b6ab7c713fcd6d08e235aca7cd17c30e47fb74c40c5c7f4dcec642",
-                "bytes": 581255}
+LOOP_TRAFFIC = {"sources_sha256": "0cadc6ebabbd1ecbac3c98ab46ce8b2038627eae32098c2accad1adfd37f3c26",
+                "bytes": 558783}
 
 
 def loop_kernel_sources_sha():

@@ -288,13 +288,23 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   L.front_smem = std::max(lsm, fsm);
   L.b.loop_threads = threads;
   L.omega = omega_of(ctx);
-  // persistent loop grid: every CU filled to the kernel's occupancy
-  int per_cu = 0, cus = 0;
+  // blocks of the loop kernel per CU in each form; the form with two rows in
+  // flight when the items need no more blocks per CU than it allows
+  int cus = 0;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop_kernel_symbol(smax_max, mixed, omega_of(ctx)),
-                                                   threads, lsm) != hipSuccess || per_cu < 1)
-    per_cu = 1;
   if (cus < 1) cus = 1;
+  auto per_cu_of = [&](bool unroll) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, loop_kernel_symbol(smax_max, mixed, omega_of(ctx), unroll),
+                                                     threads, lsm) != hipSuccess || n < 1)
+      n = 1;
+    return n;
+  };
+  const int per_cu_unroll = per_cu_of(true);
+  const int nloop = (int)h.loop.size();
+  L.loop_unroll = !ctx->loop_persistent && (nloop + cus - 1) / cus <= per_cu_unroll;
+  // persistent loop grid: every CU filled to the kernel's occupancy
+  const int per_cu = L.loop_unroll ? per_cu_unroll : per_cu_of(false);
   L.loop_blocks = cus * per_cu;
   L.loop_persistent = ctx->loop_persistent;
   return TUFRG_OK;

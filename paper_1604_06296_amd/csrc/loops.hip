@@ -64,7 +64,7 @@ __device__ __forceinline__ void neumaier_add(float& s, float& c, float v) {
 //
 // One loop work item with the point's exact harmonic count NH = 2 smax + 1
 // (compile-time, so the per-row harmonic loops carry no guards).
-template <int SMAX, bool MIXED, bool OMEGA>
+template <int SMAX, bool MIXED, bool OMEGA, bool UNROLL>
 __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, int p, int item_b, int q,
                                           double T, double* smem) {
   constexpr int NH = 2 * SMAX + 1;
@@ -113,7 +113,7 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
     const int r0 = (int)((int64_t)nr * c / nchunk);
     const int r1 = (int)((int64_t)nr * (c + 1) / nchunk);
     if constexpr (!MIXED) {
-      for (int r = r0; r < r1; ++r) {
+      auto row = [&](int r) {
         const double al = fma(B1, y1[r], A1);
         const double be = fma(B2, y2[r], A2);
         double dph, dpp;
@@ -125,6 +125,13 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
           acc[0][n] = fma(dpp, w[n], acc[0][n]);
           acc[1][n] = fma(dph, w[n], acc[1][n]);
         }
+      };
+      // two rows in flight where the launch can afford the registers
+      if constexpr (UNROLL) {
+#pragma unroll 2
+        for (int r = r0; r < r1; ++r) row(r);
+      } else {
+        for (int r = r0; r < r1; ++r) row(r);
       }
     } else {
       // FP32 pair math from FP64 energies; rows blocked by 8 in FP32 and
@@ -258,47 +265,48 @@ __device__ __forceinline__ double point_T(const Batch& b, const TArg* ta, int p)
 }
 
 // Runs the body compiled for the item's own smax.
-template <int SMAX, bool MIXED, bool OMEGA>
+template <int SMAX, bool MIXED, bool OMEGA, bool UNROLL>
 __device__ __forceinline__ void loop_smax(const Batch& b, const DevTables& d, int p, int item_b, int q,
                                           double T, double* smem) {
   if constexpr (SMAX >= 4) {
     if (d.smax == 4) {
-      loop_item<4, MIXED, OMEGA>(b, d, p, item_b, q, T, smem);
+      loop_item<4, MIXED, OMEGA, UNROLL>(b, d, p, item_b, q, T, smem);
       return;
     }
   }
   if constexpr (SMAX >= 2) {
     if (d.smax == 2) {
-      loop_item<2, MIXED, OMEGA>(b, d, p, item_b, q, T, smem);
+      loop_item<2, MIXED, OMEGA, UNROLL>(b, d, p, item_b, q, T, smem);
       return;
     }
   }
-  loop_item<0, MIXED, OMEGA>(b, d, p, item_b, q, T, smem);
+  loop_item<0, MIXED, OMEGA, UNROLL>(b, d, p, item_b, q, T, smem);
 }
 
-template <int SMAX, bool MIXED, bool OMEGA>
+template <int SMAX, bool MIXED, bool OMEGA, bool UNROLL>
 __device__ __forceinline__ void loop_dispatch(const Batch& b, const int4 item, double* smem,
                                               const TArg* ta = nullptr) {
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
-  loop_smax<SMAX, MIXED, OMEGA>(b, d, p, item.y, item.z, point_T(b, ta, p), smem);
+  loop_smax<SMAX, MIXED, OMEGA, UNROLL>(b, d, p, item.y, item.z, point_T(b, ta, p), smem);
 }
 
 // Loop kernel over work items (p, q * nsplit + split); SMAX is the largest
 // smax of the batch, and each item runs the body compiled for its own smax;
-// OMEGA selects the regulator (Omega cutoff at T = 0, else temperature).
+// OMEGA selects the regulator (Omega cutoff at T = 0, else temperature);
+// UNROLL keeps two FP64 rows in flight (more registers, fewer blocks per CU).
 // Without a queue every block runs item blockIdx.x (the hardware dispatcher
 // balances the load, items being ordered costliest first); with a queue the
 // kernel is persistent and blocks take items until the queue is empty.
-template <int SMAX, bool MIXED, bool OMEGA>
+template <int SMAX, bool MIXED, bool OMEGA, bool UNROLL>
 __global__ void __launch_bounds__(kLoopThreadsMax)
 k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ queue) {
   extern __shared__ double smem[];
   __shared__ int cur;
   if (b.item_count != nullptr) nitems = min(nitems, *b.item_count);
   if (queue == nullptr) {
-    if ((int)blockIdx.x < nitems) loop_dispatch<SMAX, MIXED, OMEGA>(b, items[blockIdx.x], smem);
+    if ((int)blockIdx.x < nitems) loop_dispatch<SMAX, MIXED, OMEGA, UNROLL>(b, items[blockIdx.x], smem);
     return;
   }
   const int t = threadIdx.x;
@@ -308,7 +316,7 @@ k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ q
     const int it = cur;
     __syncthreads();
     if (it >= nitems) break;
-    loop_dispatch<SMAX, MIXED, OMEGA>(b, items[it], smem);
+    loop_dispatch<SMAX, MIXED, OMEGA, UNROLL>(b, items[it], smem);
   }
   if (t == 0 && atomicAdd(queue + 1, 1) == (int)gridDim.x - 1) {
     atomicExch(queue, 0);
@@ -337,7 +345,7 @@ k_loops_fwd(Batch b, const int4* __restrict__ loop_items, int nloop, const int4*
     }
   }
   if ((int)blockIdx.x < nloop) {
-    loop_dispatch<SMAX, MIXED, OMEGA>(b, loop_items[blockIdx.x], smem, &ta);
+    loop_dispatch<SMAX, MIXED, OMEGA, true>(b, loop_items[blockIdx.x], smem, &ta);
     return;
   }
   const int4 item = fwd_items[blockIdx.x - nloop];
@@ -374,8 +382,12 @@ void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, h
   const size_t sm = L.loop_smem;
   const int4* it = L.loop_items + r.begin;
   with_loop_variant(L.smax_max, mixed, L.omega, [&](auto S, auto M, auto O) {
-    hipLaunchKernelGGL((k_loops<decltype(S)::value, decltype(M)::value, decltype(O)::value>), dim3(grid),
-                       blk, sm, s, L.b, it, r.n, queue);
+    constexpr int SM = decltype(S)::value;
+    constexpr bool MX = decltype(M)::value, OM = decltype(O)::value;
+    if (L.loop_unroll)
+      hipLaunchKernelGGL((k_loops<SM, MX, OM, true>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
+    else
+      hipLaunchKernelGGL((k_loops<SM, MX, OM, false>), dim3(grid), blk, sm, s, L.b, it, r.n, queue);
   });
 }
 
@@ -399,10 +411,12 @@ void launch_loops_fwd(const Launch& L, const Ranges& r, const double* X, bool mi
   });
 }
 
-const void* loop_kernel_symbol(int smax_max, bool mixed, bool omega) {
+const void* loop_kernel_symbol(int smax_max, bool mixed, bool omega, bool unroll) {
   const void* k = nullptr;
   with_loop_variant(smax_max, mixed, omega, [&](auto S, auto M, auto O) {
-    k = (const void*)k_loops<decltype(S)::value, decltype(M)::value, decltype(O)::value>;
+    constexpr int SM = decltype(S)::value;
+    constexpr bool MX = decltype(M)::value, OM = decltype(O)::value;
+    k = unroll ? (const void*)k_loops<SM, MX, OM, true> : (const void*)k_loops<SM, MX, OM, false>;
   });
   return k;
 }

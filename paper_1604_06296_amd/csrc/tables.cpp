@@ -376,11 +376,13 @@ std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric, bo
   t.mrow[rows] = (int32_t)t.ment.size();
 
   // algorithmic flop counts of one right-hand side (FP64 flops, FMA = 2).
-  // Loops: per (q, p) pair of the half fine grid, 162 flops for the two loop
-  // derivatives (two exponentials, reciprocals, both divided-difference
-  // branches, as counted in the compiled kernel; with the Omega cutoff 58: the
-  // two arguments, three reciprocals with two Newton steps each, the one-sign
-  // and opposite-sign forms) plus 2 channels x (2 smax + 1)
+  // Loops: per (q, p) pair of the half fine grid, 157 flops for the two loop
+  // derivatives (the executed FP64 flops of the temperature-flow loop kernel
+  // per pair, from its VALU counters at t'=-0.25, 24x24 / 96x96, after the
+  // harmonic and contraction terms below: two exponentials, two refined
+  // reciprocals, the divided differences; with the Omega cutoff 58, counted
+  // from the code: the two arguments, three reciprocals with two Newton steps
+  // each, the one-sign and opposite-sign forms) plus 2 channels x (2 smax + 1)
   // harmonic multiply-adds; per transfer momentum the contraction over px
   // (2 N_S' outputs x Lk columns x 2 multiply-adds) and the form-factor
   // epilogue (2 nff^2 N_S' multiply-adds).
@@ -388,7 +390,7 @@ std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric, bo
   // momenta are integrated; the epilogue runs for every momentum.
   const double nq = t.nq, f2 = (double)nff * nff, f3 = f2 * nff;
   const double pairs = (double)t.nirr * (double)lk * (lk / 2 + 1);
-  const double c_pair = omega ? 58.0 : 162.0;
+  const double c_pair = omega ? 58.0 : 157.0;
   const double c_acc = 2.0 * 2.0 * (2 * t.smax + 1);
   t.flops_loop_kernel = (int64_t)(pairs * (c_pair + c_acc) + (double)t.nirr * 2.0 * t.nsh * lk * 4.0);
   t.flops_loops = t.flops_loop_kernel + (int64_t)(nq * 2.0 * 2.0 * f2 * t.nsh);

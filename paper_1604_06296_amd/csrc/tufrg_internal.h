@@ -178,6 +178,8 @@ struct Launch {
   bool loop_persistent;   // loop kernel: persistent work queue, or one block per item
   size_t loop_smem, prod_smem;
   bool omega = false;     // the scale is the Omega cutoff at T = 0 (temperatures hold Om)
+  bool loop_unroll = false;  // loop kernel: two FP64 rows in flight (when the launch needs no
+                             // more blocks per CU than that form's occupancy allows)
 };
 
 // Surrogate state of a single-point context (device pointers and settings).
@@ -224,7 +226,7 @@ void launch_set_T(double* Tp, int npts, const double* Ttab, const int* step, int
 void launch_set_T_values(double* Tp, const double* T_host, int n, hipStream_t s);
 void launch_step_end(unsigned long long* words, int npts, int* frozen, double* hist, int* step,
                      int nsteps, double xmax, hipStream_t s);
-const void* loop_kernel_symbol(int smax_max, bool mixed, bool omega);
+const void* loop_kernel_symbol(int smax_max, bool mixed, bool omega, bool unroll);
 void launch_ghat_sum(const Launch& L, int p, const DevTables& d, double* out, hipStream_t s);
 void launch_sur_dataset(const Launch& L, int npts, int64_t n, uint64_t seed, float* x, float* y,
                         int32_t* idx, hipStream_t s);
