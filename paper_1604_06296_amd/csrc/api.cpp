@@ -188,7 +188,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   const bool mixed = mixed_of(ctx);
   if (!ctx->geometry_allocations.empty()) {
     HIP_TRY(ctx, hipDeviceSynchronize());
-    for (void* p : ctx->geometry_allocations) hipFree(p);
+    for (void* p : ctx->geometry_allocations) (void)hipFree(p);
     ctx->geometry_allocations.clear();
   }
   HostItems h;
@@ -244,7 +244,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   const size_t fsm = mixed ? (size_t)16 * 8 * (16 * fwd_kt + fwd_cols)
                            : sizeof(double) * 32 * ((size_t)(16 * fwd_kt + 2) + (size_t)(fwd_cols + 2));
   int dev_smem = 0;
-  hipDeviceGetAttribute(&dev_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
+  (void)hipDeviceGetAttribute(&dev_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
   if (dev_smem > 0 && (lsm > (size_t)dev_smem || psm > (size_t)dev_smem || fsm > (size_t)dev_smem))
     return fail(ctx, TUFRG_EINVAL, "grids too large for the shared memory of one block");
   auto whole = [](const std::vector<int4>& v) {
@@ -291,7 +291,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   // blocks of the loop kernel per CU in each form; the form with two rows in
   // flight when the items need no more blocks per CU than it allows
   int cus = 0;
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
   if (cus < 1) cus = 1;
   auto per_cu_of = [&](bool unroll) {
     int n = 0;
@@ -396,13 +396,14 @@ void rhs_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, const double* 
     launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms);
     return;
   }
-  hipEventRecord(ctx->ev_fork, ms);
-  hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+  // fork and join: errors of these calls are read with hipGetLastError by every caller
+  (void)hipEventRecord(ctx->ev_fork, ms);
+  (void)hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
   set_T_launch(ctx, ts, ctx->side);
   loops_launch(ctx, L, r, L.b.dchi, ctx->side);
-  hipEventRecord(ctx->ev_join, ctx->side);
+  (void)hipEventRecord(ctx->ev_join, ctx->side);
   if (cross) launch_front(L, r, X, mixed, ms);
-  hipStreamWaitEvent(ms, ctx->ev_join, 0);
+  (void)hipStreamWaitEvent(ms, ctx->ev_join, 0);
   launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms);
 }
 
@@ -511,8 +512,8 @@ tufrg_status autotune(tufrg_ctx* ctx) {
     form_ms[f] = ms;
   }
   ctx->loop_persistent = !st && form_ms[1] < form_ms[0];
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st) return st;
   if (path && !fresh.empty()) {
     std::ofstream out(path, std::ios::app);
@@ -786,7 +787,7 @@ tufrg_status tufrg_surrogate_attach(tufrg_ctx* ctx, tufrg_mlp* a, tufrg_mlp* b, 
   if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->side));
-  for (void* p : ctx->sur_allocations) hipFree(p);
+  for (void* p : ctx->sur_allocations) (void)hipFree(p);
   ctx->sur_allocations.clear();
   ctx->sur_a = ctx->sur_b = nullptr;
   if (!a && !b) return TUFRG_OK;
@@ -853,8 +854,8 @@ tufrg_status tufrg_loop_kernel_time(tufrg_ctx* ctx, const double* T_host, int32_
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (e != hipSuccess) return fail(ctx, TUFRG_EHIP, std::string("loop kernel timing: ") + hipGetErrorString(e));
   *us = 1e3 * (double)ms / reps;
   if (flops) {
@@ -1058,8 +1059,8 @@ tufrg_status flow_rk4_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, t
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   auto cleanup = [&]() {
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
   };
   if (o->use_graph) {
     HIP_TRY(ctx, hipStreamBeginCapture(ms, hipStreamCaptureModeThreadLocal));
@@ -1134,6 +1135,7 @@ const double kDpB4[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640, -9209
 // dX/ds of point p alone at temperature T
 tufrg_status rhs_point(tufrg_ctx* ctx, int p, double T, const double* X, double* out) {
   rhs_launch(ctx, ctx->L, ctx->per_point[p], X, out, true, ctx->stream, TSource{&T, p, 1, 0});
+  HIP_TRY(ctx, hipGetLastError());
   return TUFRG_OK;
 }
 
@@ -1158,7 +1160,7 @@ tufrg_status flow_dopri5_point(tufrg_ctx* ctx, int p, const tufrg_flow_opts* o, 
   const int64_t n = (int64_t)t.nq * t.nff * t.nff;
   if (ctx->nred < seg.n) {
     ST_TRY(dalloc(ctx, (size_t)seg.n, &ctx->red, ctx->allocations));
-    if (ctx->red_host) hipHostFree(ctx->red_host);
+    if (ctx->red_host) (void)hipHostFree(ctx->red_host);
     ctx->red_host = nullptr;
     if (hipHostMalloc((void**)&ctx->red_host, sizeof(double) * seg.n, 0) != hipSuccess)
       return fail(ctx, TUFRG_ENOMEM, "pinned host buffer for the error norm");
@@ -1262,17 +1264,17 @@ tufrg_status tufrg_flow(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tuf
 void tufrg_free(tufrg_ctx* ctx) {
   if (!ctx) return;
   if (!ctx->allocations.empty() || !ctx->geometry_allocations.empty() || !ctx->sur_allocations.empty())
-    hipDeviceSynchronize();
-  if (ctx->side) hipStreamDestroy(ctx->side);
-  if (ctx->gs) hipStreamDestroy(ctx->gs);
-  if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
-  if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
-  if (ctx->ev_gs) hipEventDestroy(ctx->ev_gs);
-  if (ctx->umax_host) hipHostFree(ctx->umax_host);
-  if (ctx->red_host) hipHostFree(ctx->red_host);
-  for (void* p : ctx->sur_allocations) hipFree(p);
-  for (void* p : ctx->geometry_allocations) hipFree(p);
-  for (void* p : ctx->allocations) hipFree(p);
+    (void)hipDeviceSynchronize();
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  if (ctx->gs) (void)hipStreamDestroy(ctx->gs);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->ev_gs) (void)hipEventDestroy(ctx->ev_gs);
+  if (ctx->umax_host) (void)hipHostFree(ctx->umax_host);
+  if (ctx->red_host) (void)hipHostFree(ctx->red_host);
+  for (void* p : ctx->sur_allocations) (void)hipFree(p);
+  for (void* p : ctx->geometry_allocations) (void)hipFree(p);
+  for (void* p : ctx->allocations) (void)hipFree(p);
   delete ctx;
 }
 

@@ -637,8 +637,8 @@ tufrg_status tufrg_mlp_train(tufrg_mlp* n, const float* x, const float* y, int64
 
 void tufrg_mlp_free(tufrg_mlp* n) {
   if (!n) return;
-  if (!n->allocations.empty()) hipDeviceSynchronize();
-  for (void* p : n->allocations) hipFree(p);
+  if (!n->allocations.empty()) (void)hipDeviceSynchronize();
+  for (void* p : n->allocations) (void)hipFree(p);
   delete n;
 }
 
