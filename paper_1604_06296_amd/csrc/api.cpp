@@ -494,6 +494,52 @@ tufrg_status autotune(tufrg_ctx* ctx) {
     d.nchunk = bc;
     fresh[key] = {bs, bc};
   }
+  // Batches: the shapes were timed alone (latency); with many items in flight
+  // fewer, longer blocks can serve the whole launch better.  Time every
+  // point's row slices divided by 1, 2, 4, 8 on the whole batch and keep the
+  // fastest (cached under the batch's multiset of shapes).
+  if (!st && npts > 1) {
+    std::vector<std::string> shapes;
+    for (int p = 0; p < npts; ++p) shapes.push_back(tune_key(ctx->dev[p], ctx->opt.precision));
+    std::sort(shapes.begin(), shapes.end());
+    uint64_t hsh = 1469598103934665603ull;   // FNV-1a over the sorted shape keys
+    for (const std::string& k : shapes)
+      for (unsigned char c : k + ";") hsh = (hsh ^ c) * 1099511628211ull;
+    char bk[64];
+    std::snprintf(bk, sizeof bk, "batch_%016llx", (unsigned long long)hsh);
+    std::vector<int> ns0(npts);
+    for (int p = 0; p < npts; ++p) ns0[p] = ctx->dev[p].nsplit;
+    auto apply = [&](int f) {
+      for (int p = 0; p < npts; ++p) ctx->dev[p].nsplit = std::max(1, ns0[p] / f);
+    };
+    int best_f = 1;
+    if (known.count(bk)) {
+      best_f = known[bk].first;
+    } else {
+      double best = 1e300;
+      for (int f = 1; f <= 8 && !st; f *= 2) {
+        if (f > 1 && std::all_of(ns0.begin(), ns0.end(), [&](int n) { return n / (f / 2) <= 1; })) break;
+        apply(f);
+        if ((st = build_launch(ctx))) break;
+        for (int w = 0; w < 2; ++w) launch_loops(ctx->L, ctx->all.loop, ctx->queue, mixed, ctx->stream);
+        const int reps = 5;
+        float ms = 0.f;
+        if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = fail(ctx, TUFRG_EHIP, "event"); break; }
+        for (int w = 0; w < reps; ++w) launch_loops(ctx->L, ctx->all.loop, ctx->queue, mixed, ctx->stream);
+        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          st = fail(ctx, TUFRG_EHIP, "autotuner timing failed");
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          best_f = f;
+        }
+      }
+      fresh[bk] = {best_f, 1};
+    }
+    apply(best_f);
+  }
   // launch form of the whole batch: one block per item, or the persistent queue
   if (!st) st = build_launch(ctx);
   double form_ms[2] = {0.0, 0.0};

@@ -223,7 +223,9 @@ def test_autotune_geometry_and_cache(tf, tmp_path):
         tuned = tf.Context(pts, autotune=True)
         plain = tf.Context(pts)
         lines = cache.read_text().split()
-        assert len(lines) == 3 * len({(p.nq, p.Lk, FormFactors(p.shells).nff) for p in pts})
+        # one line per distinct point shape, and one for the batch's row-slice factor
+        assert len(lines) == 3 * (len({(p.nq, p.Lk, FormFactors(p.shells).nff) for p in pts}) + 1)
+        assert sum(1 for w in lines if w.startswith("batch_")) == 1
         for i, p in enumerate(pts):
             ns, nc, th, _ = tuned.geometry(i)
             assert ns >= 1 and nc >= 1 and p.Lk * nc <= th <= 512
