@@ -96,12 +96,15 @@ enum {
                                seam for closed forms, not part of the method) */
   TUFRG_AUTOTUNE = 1u << 1, /* time candidate loop-kernel geometries (row slices per
                                momentum x row chunks per column) for every distinct
-                               point shape, then both launch forms of the whole
-                               batch, during tufrg_init and keep the fastest;
-                               choices are read from and appended to the text file
-                               named by the environment variable TUFRG_TUNE_CACHE
-                               when it is set.  Results differ from the default
-                               geometry only by summation order. */
+                               point shape alone; with several points, then the
+                               slice counts of all points divided by 1, 2, 4, 8 on
+                               the whole batch; then both launch forms of the whole
+                               batch; during tufrg_init, keeping the fastest.
+                               Choices (per shape and per batch of shapes) are read
+                               from and appended to the text file named by the
+                               environment variable TUFRG_TUNE_CACHE when it is set.
+                               Results differ from the default geometry only by
+                               summation order. */
   TUFRG_NO_SYMMETRY = 1u << 3, /* integrate the loops at every transfer momentum
                                instead of one representative per C4v orbit (a
                                test seam: the point-group reduction is exact up
