@@ -219,7 +219,17 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   for (const DevTables& d : ctx->dev) threads = std::max(threads, round64(d.lk * d.nchunk));
   const bool fused = ctx->S <= kFuseMaxState && !ctx->loop_persistent && !(ctx->opt.flags & TUFRG_NO_FUSE);
   const int front_threads = fused ? std::max(threads, 256) : 256, fwd_cols = 16 * (front_threads / 64);
-  for (int p = 0; p < npts; ++p) add_point_items(ctx->dev[p], p, inv_lt, fwd_cols, h, ctx->per_point[p]);
+  // points in decreasing N_ff, so that the product items of one N_ff are contiguous
+  std::vector<int> by_nff(npts);
+  std::iota(by_nff.begin(), by_nff.end(), 0);
+  std::stable_sort(by_nff.begin(), by_nff.end(), [&](int x, int y) { return ctx->dev[x].nff > ctx->dev[y].nff; });
+  for (int p : by_nff) {
+    Ranges& rp = ctx->per_point[p];
+    add_point_items(ctx->dev[p], p, inv_lt, fwd_cols, h, rp);
+    rp.nprod_cls = 1;
+    rp.prod_cls[0] = rp.prod;
+    rp.prod_cls_nff[0] = ctx->dev[p].nff;
+  }
   int smax_max = 0;
   size_t lsm = 0, psm = 0;
   int kpt = 1;
@@ -257,6 +267,18 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   all.basis = whole(h.basis); all.gather = whole(h.gather);
   all.inv = whole(h.inv); all.prod = whole(h.prod);
   all.seg = whole(h.seg);
+  all.nprod_cls = 0;
+  for (int p : by_nff) {
+    const ItemRange& pr = ctx->per_point[p].prod;
+    const int nff = ctx->dev[p].nff;
+    if (all.nprod_cls > 0 && all.prod_cls_nff[all.nprod_cls - 1] == nff) {
+      all.prod_cls[all.nprod_cls - 1].n = pr.begin + pr.n - all.prod_cls[all.nprod_cls - 1].begin;
+    } else {
+      all.prod_cls[all.nprod_cls] = pr;
+      all.prod_cls_nff[all.nprod_cls] = nff;
+      ++all.nprod_cls;
+    }
+  }
   Launch& L = ctx->L;
   std::vector<void*>& g = ctx->geometry_allocations;
   int4* t = nullptr;

@@ -934,13 +934,23 @@ void launch_expand_basis(const Launch& L, const Ranges& r, double* dchi, bool cr
 void launch_back(const Launch& L, const Ranges& r, const double* X, double* out, int mode,
                  bool cross, bool scale_T, bool mixed, hipStream_t s) {
   if (r.prod.n <= 0) return;
-  const int4* it = L.prod_items + r.prod.begin;
-  if (mixed)
-    hipLaunchKernelGGL(k_products<float>, dim3(r.prod.n), dim3(256), L.prod_smem / 2, s, L.b, it, X,
-                       (const float*)L.b.kinv, out, mode, cross ? 1 : 0, scale_T ? 1 : 0);
-  else
-    hipLaunchKernelGGL(k_products<double>, dim3(r.prod.n), dim3(256), L.prod_smem, s, L.b, it, X,
-                       (const double*)L.b.kinv64, out, mode, cross ? 1 : 0, scale_T ? 1 : 0);
+  auto launch = [&](const ItemRange& ir, size_t smem64) {
+    if (ir.n <= 0) return;
+    const int4* it = L.prod_items + ir.begin;
+    if (mixed)
+      hipLaunchKernelGGL(k_products<float>, dim3(ir.n), dim3(256), smem64 / 2, s, L.b, it, X,
+                         (const float*)L.b.kinv, out, mode, cross ? 1 : 0, scale_T ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_products<double>, dim3(ir.n), dim3(256), smem64, s, L.b, it, X,
+                         (const double*)L.b.kinv64, out, mode, cross ? 1 : 0, scale_T ? 1 : 0);
+  };
+  if (r.nprod_cls == 0) {
+    launch(r.prod, L.prod_smem);
+    return;
+  }
+  // one launch per N_ff, each with the [12][N_ff^2] shared memory of its own matrices
+  for (int c = 0; c < r.nprod_cls; ++c)
+    launch(r.prod_cls[c], sizeof(double) * 12 * (size_t)r.prod_cls_nff[c] * r.prod_cls_nff[c]);
 }
 
 void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const double* const* k,

@@ -141,6 +141,12 @@ struct ItemRange {
 // Item ranges of one launch set (all points, or one point)
 struct Ranges {
   ItemRange loop, exp, fwd, basis, gather, inv, prod, seg;
+  // the product items by N_ff (contiguous runs of prod): one launch each, with
+  // the shared memory of its own N_ff, so that small matrices are not held to
+  // the occupancy of the largest
+  int nprod_cls = 0;
+  ItemRange prod_cls[5];
+  int prod_cls_nff[5];
 };
 
 // Where a fused loops + transform launch takes the temperatures of its
