@@ -169,6 +169,13 @@ void add_point_items(const DevTables& d, int p, int inv_lt, int fwd_cols, HostIt
   });
 }
 
+// harmonic tiles of 16 rows the forward transform of point d needs (the
+// kernel is compiled for 1, 2, 3 and 5)
+int fwd_kt_of(const DevTables& d) {
+  const int k = (d.ncol + 15) / 16;
+  return k <= 3 ? k : 5;
+}
+
 // loop items of one point: one per (representative momentum, row slice),
 // (p, slot * nsplit + split, flat q of the representative)
 void add_loop_items(const DevTables& d, const HostTables& t, int p, std::vector<int4>& v, ItemRange& r) {
@@ -229,6 +236,9 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
     rp.nprod_cls = 1;
     rp.prod_cls[0] = rp.prod;
     rp.prod_cls_nff[0] = ctx->dev[p].nff;
+    rp.nfwd_cls = 1;
+    rp.fwd_cls[0] = rp.fwd;
+    rp.fwd_cls_kt[0] = fwd_kt_of(ctx->dev[p]);
   }
   int smax_max = 0;
   size_t lsm = 0, psm = 0;
@@ -248,7 +258,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   ctx->ghat_len = gh;
   ctx->ghat_sum_len = ghs;
   for (int p = 0; p < npts; ++p) lsm = std::max(lsm, loop_smem_of(ctx->dev[p], threads));
-  const int fwd_kt = kpt <= 3 ? kpt : 5;
+  const int fwd_kt = kpt <= 3 ? kpt : 5;   // the largest fwd_kt_of over the points
   // forward transform LDS: FP64 chunks of 32 momenta [32][16 KT + 2] + [32][cols + 2];
   // split precision: hi and lo quads [8][16 KT] + [8][cols] (8 bytes each)
   const size_t fsm = mixed ? (size_t)16 * 8 * (16 * fwd_kt + fwd_cols)
@@ -267,6 +277,18 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   all.basis = whole(h.basis); all.gather = whole(h.gather);
   all.inv = whole(h.inv); all.prod = whole(h.prod);
   all.seg = whole(h.seg);
+  all.nfwd_cls = 0;
+  for (int p : by_nff) {
+    const ItemRange& fr = ctx->per_point[p].fwd;
+    const int kt = fwd_kt_of(ctx->dev[p]);
+    if (all.nfwd_cls > 0 && all.fwd_cls_kt[all.nfwd_cls - 1] == kt) {
+      all.fwd_cls[all.nfwd_cls - 1].n = fr.begin + fr.n - all.fwd_cls[all.nfwd_cls - 1].begin;
+    } else {
+      all.fwd_cls[all.nfwd_cls] = fr;
+      all.fwd_cls_kt[all.nfwd_cls] = kt;
+      ++all.nfwd_cls;
+    }
+  }
   all.nprod_cls = 0;
   for (int p : by_nff) {
     const ItemRange& pr = ctx->per_point[p].prod;

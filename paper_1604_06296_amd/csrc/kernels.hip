@@ -874,24 +874,39 @@ void launch_chi_expand(const Launch& L, const ItemRange& r, const double* fin, d
 
 void launch_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s) {
   if (r.fwd.n <= 0) return;
-  const int4* it = L.fwd_items + r.fwd.begin;
-  const dim3 g(r.fwd.n), blk(L.front_threads);
-  if (mixed) {
-    const size_t sm = L.fwd_smem;
-    switch (L.fwd_kt) {
-      case 1: hipLaunchKernelGGL(k_dft_fwd_mix<1>, g, blk, sm, s, L.b, it, X); break;
-      case 2: hipLaunchKernelGGL(k_dft_fwd_mix<2>, g, blk, sm, s, L.b, it, X); break;
-      case 3: hipLaunchKernelGGL(k_dft_fwd_mix<3>, g, blk, sm, s, L.b, it, X); break;
-      default: hipLaunchKernelGGL(k_dft_fwd_mix<5>, g, blk, sm, s, L.b, it, X); break;
+  const int cols = 16 * ((int)L.front_threads / 64);
+  auto launch = [&](const ItemRange& ir, int kt, size_t sm) {
+    if (ir.n <= 0) return;
+    const int4* it = L.fwd_items + ir.begin;
+    const dim3 g(ir.n), blk(L.front_threads);
+    if (mixed) {
+      switch (kt) {
+        case 1: hipLaunchKernelGGL(k_dft_fwd_mix<1>, g, blk, sm, s, L.b, it, X); break;
+        case 2: hipLaunchKernelGGL(k_dft_fwd_mix<2>, g, blk, sm, s, L.b, it, X); break;
+        case 3: hipLaunchKernelGGL(k_dft_fwd_mix<3>, g, blk, sm, s, L.b, it, X); break;
+        default: hipLaunchKernelGGL(k_dft_fwd_mix<5>, g, blk, sm, s, L.b, it, X); break;
+      }
+    } else {
+      switch (kt) {
+        case 1: hipLaunchKernelGGL(k_dft_fwd_part<1>, g, blk, sm, s, L.b, it, X); break;
+        case 2: hipLaunchKernelGGL(k_dft_fwd_part<2>, g, blk, sm, s, L.b, it, X); break;
+        case 3: hipLaunchKernelGGL(k_dft_fwd_part<3>, g, blk, sm, s, L.b, it, X); break;
+        default: hipLaunchKernelGGL(k_dft_fwd_part<5>, g, blk, sm, s, L.b, it, X); break;
+      }
     }
-  } else {
-    const size_t sm = L.fwd_smem;
-    switch (L.fwd_kt) {
-      case 1: hipLaunchKernelGGL(k_dft_fwd_part<1>, g, blk, sm, s, L.b, it, X); break;
-      case 2: hipLaunchKernelGGL(k_dft_fwd_part<2>, g, blk, sm, s, L.b, it, X); break;
-      case 3: hipLaunchKernelGGL(k_dft_fwd_part<3>, g, blk, sm, s, L.b, it, X); break;
-      default: hipLaunchKernelGGL(k_dft_fwd_part<5>, g, blk, sm, s, L.b, it, X); break;
-    }
+  };
+  if (r.nfwd_cls == 0) {
+    launch(r.fwd, L.fwd_kt, L.fwd_smem);
+    return;
+  }
+  // one launch per harmonic tile count, each with the LDS of its own tiles:
+  // FP64 chunks of 32 momenta [32][16 KT + 2] + [32][cols + 2]; split precision
+  // hi and lo quads [8][16 KT] + [8][cols]
+  for (int c = 0; c < r.nfwd_cls; ++c) {
+    const int kt = r.fwd_cls_kt[c];
+    const size_t sm = mixed ? (size_t)16 * 8 * (16 * kt + cols)
+                            : sizeof(double) * 32 * ((size_t)(16 * kt + 2) + (size_t)(cols + 2));
+    launch(r.fwd_cls[c], kt, sm);
   }
 }
 

@@ -147,6 +147,11 @@ struct Ranges {
   int nprod_cls = 0;
   ItemRange prod_cls[5];
   int prod_cls_nff[5];
+  // the forward-transform items by harmonic tile count KT (contiguous runs of
+  // fwd): one launch each, compiled for that KT
+  int nfwd_cls = 0;
+  ItemRange fwd_cls[5];
+  int fwd_cls_kt[5];
 };
 
 // Where a fused loops + transform launch takes the temperatures of its
