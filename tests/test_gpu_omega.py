@@ -97,6 +97,24 @@ def test_omega_cfg2_full(tf):
     _assert_normwise(_host(ctx, ctx.rhs(Om, Xd)), ref_rhs, what="cfg2 omega rhs")
 
 
+@pytest.mark.parametrize("which", ["cfg3", "cfg5"])
+def test_omega_full_size_sampled(tf, which):
+    """N_ff = 21 at 48x48/128x128 and 64x64/160x160 with the Omega cutoff: loops and
+    right-hand sides on sampled momenta."""
+    w = synth.cfg3() if which == "cfg3" else synth.cfg5()
+    pt = w.points[0]
+    print(f"[omega] {which} sampled", flush=True)
+    ff = FormFactors(pt.shells)
+    ctx = tf.Context([pt], regulator="omega")
+    X = synth.random_channels(pt.nq, ff.nff, seed=14, scale=1.0)
+    qi = list(synth.sample_indices(pt.nq, 4, seed=19)) + [0, pt.nq - 1]
+    Om = 0.023
+    ref_rhs, _, ref_chi = orhs.rhs(pt, Om, X, ff, return_parts=True, q_index=qi, regulator="omega")
+    Xd = _to_dev(ctx, X)
+    _assert_normwise(_host(ctx, ctx.bubbles(Om))[:, qi], ref_chi, what=f"{which} omega bubbles")
+    _assert_normwise(_host(ctx, ctx.rhs(Om, Xd))[:, qi], ref_rhs, what=f"{which} omega rhs")
+
+
 def test_omega_multi_point_and_full_grid(tf):
     """Uneven points in one context, and the point-group reduction off: same results."""
     pts = [_pt(1, 8, 20), _pt(3, 10, 24, tp=-0.1, mu=-0.3), _pt(0, 6, 12, tp=0.0, mu=0.0)]
