@@ -658,10 +658,12 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     d.t = t.p.t; d.tp = t.p.tp; d.mu = t.p.mu; d.U = t.p.U;
     default_geometry(d);
     // splits of the transfer grid in the forward transform: about 512 work
-    // items per point, at least 32 momenta per split
+    // items per point, at least 64 momenta per split (every split writes a
+    // full partial sum that the next kernel reads again, so fewer, longer
+    // splits where the point is small)
     const int nff2 = t.nff * t.nff;
     const int ctiles = (3 * nff2 + 63) / 64;
-    d.nsu = std::max(1, std::min(512 / ctiles, t.nq / 32));
+    d.nsu = std::max(1, std::min(512 / ctiles, t.nq / 64));
     d.off = S;
     ctx->off[p] = S;
     S += (int64_t)t.nq * nff2;
