@@ -11,10 +11,11 @@ Modules:
   projections  V^P, V^C, V^D (eqns. proj_VP/VC/VD via eqn. proj_pos)
   rhs          products (eqns. matmul-P/C/D) and the full increment
   flow         RK4 / Dormand-Prince flow in ln T, critical scale, classification
+  symmetry     C4v covariance law of the exchange propagators, symmetrisation
   surrogate    loop harmonics ghat(q, S), surrogate features/targets, FP64 MLP
 
 Parity status: every function is pinned by tests under tests/ against
 closed forms, brute force or invariants, except the coupled flow at
 N_ff >= 5, which is pinned only through its parts (tests/test_oracle_rhs.py).
 """
-from . import bubbles, flow, lattice, projections, rhs, surrogate  # noqa: F401
+from . import bubbles, flow, lattice, projections, rhs, surrogate, symmetry  # noqa: F401
