@@ -119,6 +119,22 @@ enum {
                                file); only the loops change.  Not available with
                                a surrogate (tufrg_surrogate_attach returns
                                EUNSUPPORTED). */
+  TUFRG_SYMMETRIC_STATE = 1u << 6, /* the caller's states are C4v-symmetric:
+                               X(q) = T X(q') T^T whenever an operation h of C4v
+                               gives h q = q' + G (G in {0, 2 pi}^2, the zone
+                               edge), T being the signed permutation of the form
+                               factors with f_m(h^-1 (k - G/2)) = sum_n T_mn f_n(k)
+                               (Sec. 3: the lattice symmetries; every state of a
+                               flow started at zero is symmetric, and the
+                               increment of a symmetric state is).  The inverse
+                               transform and the products then run at one
+                               transfer momentum per orbit and the results are
+                               copied to the rest of the orbit with that law:
+                               every member is an exact signed copy of its
+                               representative.  For a state that is not
+                               symmetric the results are its representatives'
+                               increments copied by the law (no error is
+                               raised). */
   TUFRG_NO_FUSE = 1u << 4  /* never run the right-hand side in fused launches.  By
                                default a context whose channel state (sum of
                                Nq Nff^2 over its points) is at most 2^18 runs the
@@ -133,7 +149,8 @@ enum {
 typedef struct {
   int32_t precision;       /* TUFRG_FP64 or TUFRG_MIXED */
   uint32_t flags;          /* TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE |
-                              TUFRG_NO_SYMMETRY | TUFRG_NO_FUSE | TUFRG_OMEGA_CUTOFF */
+                              TUFRG_NO_SYMMETRY | TUFRG_NO_FUSE | TUFRG_OMEGA_CUTOFF |
+                              TUFRG_SYMMETRIC_STATE */
 } tufrg_options;
 
 enum { TUFRG_RK4_LOG = 0, TUFRG_DOPRI5_LOG = 1 };

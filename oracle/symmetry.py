@@ -54,6 +54,11 @@ def ff_transform(ff: FormFactors, h: np.ndarray, g) -> np.ndarray:
     T = A @ B.T / kx.size
     if np.abs(A - T @ B).max() > 1e-12:
         raise ValueError("form-factor span not closed under the operation")
+    # the overlaps are integers (each form factor maps to +- another): take
+    # them exactly, so that T X T^T only moves and negates entries
+    Ti = np.round(T)
+    if np.abs(T - Ti).max() < 1e-12:
+        T = Ti
     return T
 
 

@@ -20,6 +20,7 @@ LOOP_QUEUE = 4
 NO_SYMMETRY = 8
 NO_FUSE = 16
 OMEGA_CUTOFF = 32
+SYMMETRIC_STATE = 64
 REGULATORS = {"T": 0, "omega": OMEGA_CUTOFF}
 
 # every entry point declared in include/tufrg.h
@@ -261,11 +262,16 @@ class Context:
     (channel-major, then point blocks [Nq][Nff][Nff]).
     regulator: "T" (temperature flow) or "omega" (Omega cutoff at zero
     temperature; every scale argument named T is then Omega).
+    symmetric_state: the states passed in are C4v-symmetric (every state of
+    a flow started at zero is); the inverse transform and the products then
+    run at one transfer momentum per point-group orbit and the results are
+    copied to the rest of the orbit by the form factors' signed permutations.
     """
 
     def __init__(self, points: Sequence, precision: str = "fp64", no_cross: bool = False,
                  stream=None, autotune: bool = False, loop_queue: bool = False,
-                 no_symmetry: bool = False, fuse: bool = True, regulator: str = "T"):
+                 no_symmetry: bool = False, fuse: bool = True, regulator: str = "T",
+                 symmetric_state: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise TufrgError("a GPU is required (torch.cuda.is_available() is False)")
@@ -280,7 +286,8 @@ class Context:
         opt = _Options(PRECISIONS[precision],
                        (NO_CROSS if no_cross else 0) | (AUTOTUNE if autotune else 0)
                        | (LOOP_QUEUE if loop_queue else 0) | (NO_SYMMETRY if no_symmetry else 0)
-                       | (0 if fuse else NO_FUSE) | REGULATORS[regulator])
+                       | (0 if fuse else NO_FUSE) | REGULATORS[regulator]
+                       | (SYMMETRIC_STATE if symmetric_state else 0))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = C.c_void_p()
         _check(self.lib, None, self.lib.tufrg_init(arr, n, C.byref(opt),

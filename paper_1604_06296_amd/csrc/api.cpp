@@ -137,8 +137,14 @@ void mark(std::vector<int4>& v, ItemRange& rg, F fill) {
 
 // The work items of point p for every kernel, appended to h; r receives the
 // point's ranges.  Item layouts are those documented at each kernel.
-void add_point_items(const DevTables& d, int p, int inv_lt, int fwd_cols, HostItems& h, Ranges& r) {
+// Inverse-transform rows and product items: every momentum, or with symmetric
+// states (wedge) one representative per orbit (items carry its slot).
+int inv_rows_of(const DevTables& d, bool wedge) { return wedge ? d.nirr : d.nq; }
+
+void add_point_items(const DevTables& d, const HostTables& t, int p, int inv_lt, int fwd_cols, bool wedge,
+                     HostItems& h, Ranges& r) {
   const int nff2 = d.nff * d.nff, nv = 2 * d.nsh - 1;
+  const int nrow = inv_rows_of(d, wedge);
   mark(h.exp, r.exp, [&](std::vector<int4>& v) {
     for (int rt = 0; rt < (2 * d.nq + 31) / 32; ++rt)
       for (int ct = 0; ct < (nff2 + 63) / 64; ++ct) v.push_back(make_int4(p, rt, ct, 0));
@@ -148,7 +154,7 @@ void add_point_items(const DevTables& d, int p, int inv_lt, int fwd_cols, HostIt
       for (int c = 0; c < (3 * nff2 + fwd_cols - 1) / fwd_cols; ++c) v.push_back(make_int4(p, c, sp, 0));
   });
   mark(h.inv, r.inv, [&](std::vector<int4>& v) {
-    for (int lt = 0; lt < (d.nq + 16 * inv_lt - 1) / (16 * inv_lt); ++lt)
+    for (int lt = 0; lt < (nrow + 16 * inv_lt - 1) / (16 * inv_lt); ++lt)
       for (int c = 0; c < (3 * nff2 + 63) / 64; ++c) v.push_back(make_int4(p, lt, c, 0));
   });
   mark(h.basis, r.basis, [&](std::vector<int4>& v) {
@@ -160,7 +166,10 @@ void add_point_items(const DevTables& d, int p, int inv_lt, int fwd_cols, HostIt
       for (int x = 0; x < 3 * ns * ns; ++x) v.push_back(make_int4(p, j, x, 0));
   });
   mark(h.prod, r.prod, [&](std::vector<int4>& v) {
-    for (int l = 0; l < d.nq; ++l) v.push_back(make_int4(p, l, 0, 0));
+    if (wedge)
+      for (int sl = 0; sl < d.nirr; ++sl) v.push_back(make_int4(p, t.irr[(size_t)sl], sl, 0));
+    else
+      for (int l = 0; l < d.nq; ++l) v.push_back(make_int4(p, l, 0, 0));
   });
   mark(h.seg, r.seg, [&](std::vector<int4>& v) {
     const int chunks = (d.nq * nff2 + kSeg - 1) / kSeg;
@@ -210,12 +219,13 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
   for (int p : order) add_loop_items(ctx->dev[p], ctx->host[p], p, h.loop, ctx->per_point[p].loop);
+  const bool wedge = (ctx->opt.flags & TUFRG_SYMMETRIC_STATE) != 0;
   // inverse-transform momentum tile: the largest of 64, 32, 16 that still
   // gives the launch 512 items
   int64_t inv_items[3] = {0, 0, 0};
   for (const DevTables& d : ctx->dev)
     for (int i = 0; i < 3; ++i)
-      inv_items[i] += (int64_t)((d.nq + (16 << i) - 1) / (16 << i)) * ((3 * d.nff * d.nff + 63) / 64);
+      inv_items[i] += (int64_t)((inv_rows_of(d, wedge) + (16 << i) - 1) / (16 << i)) * ((3 * d.nff * d.nff + 63) / 64);
   const int inv_lt = inv_items[2] >= 512 ? 4 : (inv_items[1] >= 512 ? 2 : 1);
   // loop block (the largest point's loop geometry).  Small problems are
   // bound by launch and synchronisation cost: there the loops share launches
@@ -232,7 +242,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   std::stable_sort(by_nff.begin(), by_nff.end(), [&](int x, int y) { return ctx->dev[x].nff > ctx->dev[y].nff; });
   for (int p : by_nff) {
     Ranges& rp = ctx->per_point[p];
-    add_point_items(ctx->dev[p], p, inv_lt, fwd_cols, h, rp);
+    add_point_items(ctx->dev[p], ctx->host[p], p, inv_lt, fwd_cols, wedge, h, rp);
     rp.nprod_cls = 1;
     rp.prod_cls[0] = rp.prod;
     rp.prod_cls_nff[0] = ctx->dev[p].nff;
@@ -331,6 +341,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   L.fwd_smem = fsm;
   L.front_smem = std::max(lsm, fsm);
   L.b.loop_threads = threads;
+  L.b.wedge = wedge ? 1 : 0;
   L.omega = omega_of(ctx);
   // blocks of the loop kernel per CU in each form; the form with two rows in
   // flight when the items need no more blocks per CU than it allows
@@ -628,7 +639,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   if (o.precision != TUFRG_FP64 && o.precision != TUFRG_MIXED)
     return fail(nullptr, TUFRG_EINVAL, "precision must be TUFRG_FP64 or TUFRG_MIXED");
   if (o.flags & ~(uint32_t)(TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE | TUFRG_NO_SYMMETRY |
-                            TUFRG_NO_FUSE | TUFRG_OMEGA_CUTOFF))
+                            TUFRG_NO_FUSE | TUFRG_OMEGA_CUTOFF | TUFRG_SYMMETRIC_STATE))
     return fail(nullptr, TUFRG_EINVAL, "unknown flag bits");
   auto* ctx = new tufrg_ctx();
   ctx->opt = o;
@@ -732,7 +743,9 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
         (st = upload(ctx, rlo, &d.ephr_lo, A)) || (st = upload(ctx, t.mrow, &d.mrow, A)) ||
         (st = upload(ctx, t.ment, &d.ment, A)) || (st = upload(ctx, hx, &d.hx, A)) ||
         (st = upload(ctx, hy, &d.hy, A)) || (st = upload(ctx, t.pairs, &d.pairs, A)) ||
-        (st = upload(ctx, t.irr, &d.irr, A)) || (st = upload(ctx, t.symmap, &d.symmap, A)))
+        (st = upload(ctx, t.irr, &d.irr, A)) || (st = upload(ctx, t.symmap, &d.symmap, A)) ||
+        (st = upload(ctx, t.tperm, &d.tperm, A)) || (st = upload(ctx, t.orb_start, &d.orb_start, A)) ||
+        (st = upload(ctx, t.orb_q, &d.orb_q, A)) || (st = upload(ctx, t.orb_tr, &d.orb_tr, A)))
       return bad(st);
   }
   // workspace, state buffers and control words

@@ -354,7 +354,8 @@ k_gather_g2(Batch b, const int4* __restrict__ items) {
 // harmonics k in chunks of 16 through LDS; wave w owns 16 columns and LT
 // accumulator tiles of v_mfma_f64_16x16x4f64 (16 momenta each; lane layout
 // as in the forward transform).  LT is the largest of 4, 2, 1 that still gives
-// the launch enough items.
+// the launch enough items.  With symmetric states (b.wedge) the rows are the
+// orbit representatives irr[r] only.
 template <int LT>
 __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict__ items) {
   constexpr int TL = 16 * LT;
@@ -376,13 +377,20 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
   f64x4 acc[LT];
 #pragma unroll
   for (int t = 0; t < LT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int nrow = b.wedge ? d.nirr : nq;
+  int lrow[LT];   // momentum of each staged row (-1 beyond the rows)
+#pragma unroll
+  for (int i = 0; i < LT; ++i) {
+    const int r = l0 + ((tid + 256 * i) >> 4);
+    lrow[i] = r < nrow ? (b.wedge ? d.irr[r] : r) : -1;
+  }
   // software pipeline: chunk c + 1's loads are in flight during chunk c's MFMAs
   double ev[LT], gv[4];
   auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < LT; ++i) {
-      const int e = tid + 256 * i, l = l0 + (e >> 4), k = k0 + (e & 15);
-      ev[i] = (l < nq && k < ncol) ? d.eph[(size_t)l * ncol + k] : 0.0;
+      const int k = k0 + ((tid + 256 * i) & 15);
+      ev[i] = (lrow[i] >= 0 && k < ncol) ? d.eph[(size_t)lrow[i] * ncol + k] : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -418,8 +426,8 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
   for (int t = 0; t < LT; ++t)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int l = l0 + 16 * t + 4 * j + k4;
-      if (l < nq) K[((size_t)ch * nq + l) * nff2 + mn] = acc[t][j];
+      const int r = l0 + 16 * t + 4 * j + k4;
+      if (r < nrow) K[((size_t)ch * nq + (b.wedge ? d.irr[r] : r)) * nff2 + mn] = acc[t][j];
     }
 }
 
@@ -465,9 +473,11 @@ k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
   bf16x4 eh[EPT], el[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = tid + 256 * i, r = e / QR, q = e % QR;
-    const bool ok = e < TL * QR && q < nk;
-    const size_t src = (size_t)(l0 + r) * QR + q;
+    const int e = tid + 256 * i, r = e / QR, q = e % QR, rr = l0 + r;
+    // with symmetric states (b.wedge) the rows are the orbit representatives
+    const int lsrc = b.wedge ? (rr < d.nirr && e < TL * QR ? d.irr[rr] : -1) : rr;
+    const bool ok = e < TL * QR && q < nk && lsrc >= 0;
+    const size_t src = (size_t)(ok ? lsrc : 0) * QR + q;
     eh[i] = ok ? ehq[src] : bf16x4{0, 0, 0, 0};
     el[i] = ok ? elq[src] : bf16x4{0, 0, 0, 0};
   }
@@ -526,8 +536,8 @@ k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
   for (int t = 0; t < LT; ++t)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int l = l0 + 16 * t + 4 * k4 + j;
-      if (l < nq) K[((size_t)ch * nq + l) * nff2 + mn] = acc[t][j];
+      const int r = l0 + 16 * t + 4 * k4 + j;
+      if (r < (b.wedge ? d.nirr : nq)) K[((size_t)ch * nq + (b.wedge ? d.irr[r] : r)) * nff2 + mn] = acc[t][j];
     }
 }
 
@@ -539,7 +549,10 @@ k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
 //   of eqn. matmul-D: 2 dD - dC = W chi'ph W).
 // K is the inverse transform (unused without cross terms); X and the loops
 // are FP64; the output is scale * dX/dT (mode 1; scale = T, i.e. dX/ds with
-// s = ln T, if scale_T, else 1) or V (mode 0), in FP64.
+// s = ln T, if scale_T, else 1) or V (mode 0), in FP64.  With symmetric
+// states (b.wedge) the item is (p, representative l, its slot) and the result
+// goes to every member q of the orbit as Y(q)_mn = s_m s_n Y(l)_{pi(m) pi(n)}
+// (the point-group law of the form factors; exact sign copies).
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X, const R* __restrict__ Kall,
@@ -586,7 +599,7 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
       const R own = (R)xv[h][ch];
       v[ch] = bare + (ch == 0 ? -own : own) + (R)kv[h][ch];
     }
-    if (mode == 0) {
+    if (mode == 0 && !b.wedge) {
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) out[(size_t)ch * S + d.off + (size_t)l * nff2 + mn] = (double)v[ch];
       continue;
@@ -597,8 +610,26 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
     Ch[mn] = (R)cv[h][0];
     Ch[nff2 + mn] = (R)cv[h][1];
   }
-  if (mode == 0) return;
+  if (mode == 0 && !b.wedge) return;
   __syncthreads();
+  // the orbit of the representative: members e0..e1 with their transforms
+  auto orbit = [&](auto&& value) {
+    const int e0 = d.orb_start[item.z], n = d.orb_start[item.z + 1] - e0;
+    for (int w = threadIdx.x; w < n * nff2; w += blockDim.x) {
+      const int e = e0 + w / nff2, mn = w % nff2;
+      const int32_t* tp = d.tperm + (size_t)d.orb_tr[e] * nff;
+      const int a = tp[mn / nff], c = tp[mn % nff];
+      const double sg = ((a ^ c) >> 8) & 1 ? -1.0 : 1.0;
+      value(d.off + (size_t)d.orb_q[e] * nff2 + mn, (a & 0xff) * nff + (c & 0xff), sg);
+    }
+  };
+  if (mode == 0) {
+    orbit([&](size_t o, int src, double sg) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) out[(size_t)ch * S + o] = sg * (double)Vs[ch * nff2 + src];
+    });
+    return;
+  }
   const R* VP = Vs;
   const R* VC = Vs + nff2;
   // the six N_ff x N_ff products; in 3x3 register tiles each A and B entry is
@@ -660,6 +691,14 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
     }
   }
   __syncthreads();
+  if (b.wedge) {
+    orbit([&](size_t o, int w, double sg) {
+      out[o] = sg * (scale * (double)T2[w]);
+      out[S + o] = sg * (-scale * (double)T2[nff2 + w]);
+      out[2 * S + o] = sg * (0.5 * scale * ((double)T2[2 * nff2 + w] - (double)T2[nff2 + w]));
+    });
+    return;
+  }
   for (int w = threadIdx.x; w < nff2; w += blockDim.x) {
     const size_t o = d.off + (size_t)l * nff2 + w;
     out[o] = scale * (double)T2[w];

@@ -233,6 +233,65 @@ std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric, bo
         t.symmap[(size_t)q * t.nsh + j] = pack_sym(slot, j2, neg);
       }
     }
+    // Orbits for symmetric states.  In the grid sum of the loops (form
+    // factors at p, energies at p +- q/2) the substitution p = h^-1 (p' - G/2)
+    // with h q = r + G gives X(q) = T X(r) T^T, T_mn from
+    // f_m(h^-1 (k - G/2)) = sum_n T_mn f_n(k).  Expanded in bonds,
+    // f_m(h^-1 (k - G/2)) = sum_b c_mb (-1)^{G.(h R_b)/2pi} exp(-i k.(h R_b)),
+    // so row m of T is found by matching these coefficients against +-c_n.
+    // For this basis every T is a signed permutation (checked here).
+    std::map<std::pair<int, int>, int> bond_of;
+    for (int b = 0; b < nff; ++b) bond_of[{t.bx[b], t.by[b]}] = b;
+    std::map<int, int> tr_index;    // key o * 4 + 2 gx + gy
+    t.tperm.clear();
+    auto transform_of = [&](int o, int sx, int sy) -> int {
+      const int key = o * 4 + 2 * sx + sy;
+      auto it = tr_index.find(key);
+      if (it != tr_index.end()) return it->second;
+      const int* m = ops[o];
+      std::vector<cplx> cp((size_t)nff);
+      std::vector<int32_t> row((size_t)nff);
+      for (int a = 0; a < nff; ++a) {
+        std::fill(cp.begin(), cp.end(), cplx(0, 0));
+        for (int b = 0; b < nff; ++b) {
+          const int rx = m[0] * t.bx[b] + m[1] * t.by[b], ry = m[2] * t.bx[b] + m[3] * t.by[b];
+          auto f = bond_of.find({rx, ry});
+          if (f == bond_of.end()) return -1;
+          const double sg = ((sx * rx + sy * ry) & 1) ? -1.0 : 1.0;
+          cp[(size_t)f->second] = sg * t.c[(size_t)a * nff + b];
+        }
+        int found = -1, neg = 0;
+        for (int n = 0; n < nff && found < 0; ++n) {
+          double dp = 0.0, dm = 0.0;
+          for (int b = 0; b < nff; ++b) {
+            dp = std::max(dp, std::abs(cp[(size_t)b] - t.c[(size_t)n * nff + b]));
+            dm = std::max(dm, std::abs(cp[(size_t)b] + t.c[(size_t)n * nff + b]));
+          }
+          if (dp < 1e-9) found = n;
+          else if (dm < 1e-9) { found = n; neg = 1; }
+        }
+        if (found < 0) return -1;
+        row[(size_t)a] = pack_perm(found, neg);
+      }
+      const int idx = (int)(t.tperm.size() / (size_t)nff);
+      t.tperm.insert(t.tperm.end(), row.begin(), row.end());
+      tr_index[key] = idx;
+      return idx;
+    };
+    t.orb_start.assign((size_t)t.nirr + 1, 0);
+    for (int q = 0; q < t.nq; ++q) ++t.orb_start[(size_t)slot_of[rep[q]] + 1];
+    for (int s2 = 0; s2 < t.nirr; ++s2) t.orb_start[(size_t)s2 + 1] += t.orb_start[(size_t)s2];
+    t.orb_q.assign((size_t)t.nq, 0);
+    t.orb_tr.assign((size_t)t.nq, 0);
+    std::vector<int32_t> fill(t.orb_start.begin(), t.orb_start.end() - 1);
+    for (int q = 0; q < t.nq; ++q) {
+      const int tr = transform_of(op[q], gx[q], gy[q]);
+      if (tr < 0) return "internal error: form factors not closed under the point group";
+      const int32_t e = fill[(size_t)slot_of[rep[q]]]++;
+      t.orb_q[(size_t)e] = q;
+      t.orb_tr[(size_t)e] = tr;
+    }
+    t.ntr = (int)(t.tperm.size() / (size_t)nff);
   }
 
   // loop epilogue: chi_mn = sum_{A,B} c_mA c_nB ghat(A+B), ghat even in S

@@ -39,6 +39,14 @@ struct HostTables {
   int nirr = 0;
   std::vector<int32_t> irr;       // [nirr] flat q of each representative (increasing)
   std::vector<int32_t> symmap;    // [nq][nsh]
+  // orbits for symmetric states: X(q) = T X(r) T^T with T a signed permutation
+  // of the form factors (pack_perm entries of transform tr, [ntr][nff]);
+  // members of representative slot s: orb_q/orb_tr[orb_start[s] .. orb_start[s+1])
+  int ntr = 0;
+  std::vector<int32_t> tperm;     // [ntr][nff]
+  std::vector<int32_t> orb_start; // [nirr + 1]
+  std::vector<int32_t> orb_q;     // [nq]
+  std::vector<int32_t> orb_tr;    // [nq]
   int nsh = 0;                    // N_S' = (N_S + 1)/2
   int ncol = 0;                   // 2 nsh - 1 real harmonic columns (cos, then sin without 0)
   // loops: chi_mn = sum_j Ebub[mn*nsh + j] ghat(S'_j)
@@ -66,6 +74,9 @@ struct HostTables {
 inline int32_t pack_entry(int in, int b1, int b2, int v, int neg) {
   return in | (b1 << 2) | (b2 << 7) | (v << 12) | (neg << 19);
 }
+
+// form-factor permutation entry: source form factor (8 bits), negative sign (bit 8)
+inline int32_t pack_perm(int n, int neg) { return n | (neg << 8); }
 
 // symmetry map entry: representative slot (16 bits), harmonic (7 bits), sign (1 bit)
 inline int32_t pack_sym(int slot, int j, int neg) { return slot | (j << 16) | (neg << 24); }
@@ -115,6 +126,10 @@ struct DevTables {
   int32_t* pairs;         // canonical bond pairs [nsh][4]
   int32_t* irr;           // [nirr] flat q of each representative
   int32_t* symmap;        // [nq][nsh] pack_sym(slot, harmonic, sign)
+  int32_t* tperm;         // [ntr][nff] pack_perm(source, sign): X(q)_mn = s_m s_n X(r)_{pi(m) pi(n)}
+  int32_t* orb_start;     // [nirr + 1] orbit members of each representative slot
+  int32_t* orb_q;         // [nq] flat q of each member
+  int32_t* orb_tr;        // [nq] its transform
 };
 
 // Kernel-side view of one launch: tables, temperatures, stop flags, workspace.
@@ -132,6 +147,8 @@ struct Batch {
   double* ghat;           // loop-harmonic slices (all points, at ws_gh)
   const int* item_count;  // loops: when set, only the first *item_count items run
   int loop_threads;       // threads of the loop geometry (fixes the loops' summation order)
+  int wedge;              // symmetric states: inverse transform and products at the orbit
+                          // representatives, the increments copied to every orbit member
 };
 
 struct ItemRange {
