@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-omega", action="store_true")
+    ap.add_argument("--no-wedge", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--train-steps", type=int, default=8000)
     ap.add_argument("--probe-loops", type=int, default=0,
@@ -275,6 +276,49 @@ def leg_omega(tf, synth, steps):
     return out
 
 
+def leg_wedge(tf, synth, steps, Tc_ref):
+    """Symmetric states (one momentum per C4v orbit in the inverse transform and the
+    products): the benchmark point's adaptive flow from zero and right-hand sides of
+    its end state over the flow's temperatures; the 48x48 / 128x128, N_ff = 21
+    point's right-hand side at the flow's start (X = 0) against the per-momentum path."""
+    import torch
+    w = synth.cfg2()
+    pt = w.points[0]
+    pt.mu = tf.mu_from_filling(pt.t, pt.tp, pt.filling, pt.mu_T, pt.mu_L)
+    ctx = tf.Context([pt], symmetric_state=True)
+    X = ctx.empty(3)
+    r, fl = timed_flow(ctx, X, tf.FlowOptions(T0=w.T0, Tmin=w.Tmin, Xmax=w.Xmax, scheme="dopri5",
+                                              rtol=w.rtol, atol=w.atol))
+    r = r[0]
+    o = ctx.empty(3)
+    Ts = [math.exp(math.log(10.0) + (math.log(1e-3) - math.log(10.0)) * i / 63) for i in range(64)]
+    for i in range(20):
+        ctx.rhs(Ts[i % 64], X, o)
+    _sync()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ctx.rhs(Ts[i % 64], X, o)
+    _sync()
+    el = time.perf_counter() - t0
+    out = {"workload": w.name + "_symmetric_state", "rhs_per_s": steps / el, "ms_per_rhs": 1e3 * el / steps,
+           "flow": {"flow_time_s": fl, "status": r.status, "Tc": r.Tc, "channel": r.channel,
+                    "q_index": r.q_index, "irrep": r.irrep, "n_rhs": r.n_rhs, "n_steps": r.n_steps},
+           "Tc_rel_vs_per_momentum": (abs(r.Tc / Tc_ref - 1) if (r.Tc and Tc_ref) else None)}
+    w3 = synth.cfg3()
+    p3 = w3.points[0]
+    big = {"workload": w3.name}
+    for prec in ("fp64", "mixed"):
+        for sym in (False, True):
+            c3 = tf.Context([p3], precision=prec, symmetric_state=sym)
+            X3 = c3.empty(3).zero_()
+            big[f"rhs_ms_{prec}_{'wedge' if sym else 'per_momentum'}"] = 1e3 * time_rhs(c3, 0.05, X3, c3.empty(3))
+            c3.close()
+            torch.cuda.empty_cache()
+    out["large"] = big
+    log(f"[wedge] rhs {out['ms_per_rhs']:.4f} ms, flow {fl:.3f} s: {out['flow']}; 48x48: {big}")
+    return out
+
+
 def leg_surrogate(tf, synth, train_steps):
     """cfg5: surrogate trained on 2M exact samples; flow with and without it."""
     import torch
@@ -387,7 +431,9 @@ def main():
         log(f"[bench] flow {fl:.3f} s: {flow_info}")
 
     legs = {}
+    Tc_ref = flow_info["Tc"] if flow_info else None
     for name, skip, fn in (("omega", args.no_omega, lambda: leg_omega(tf, synth, args.steps)),
+                           ("wedge", args.no_wedge, lambda: leg_wedge(tf, synth, args.steps, Tc_ref)),
                            ("mixed", args.no_mixed, lambda: leg_mixed(tf, synth)),
                            ("batched", args.no_batched, lambda: leg_batched(tf, synth)),
                            ("surrogate", args.no_surrogate, lambda: leg_surrogate(tf, synth, args.train_steps))):

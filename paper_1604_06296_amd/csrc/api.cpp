@@ -125,7 +125,7 @@ void default_geometry(DevTables& d) {
 
 // ------------------------------------------------------------ item tables
 struct HostItems {
-  std::vector<int4> loop, exp, fwd, basis, gather, inv, prod, seg;
+  std::vector<int4> loop, exp, expw, fwd, basis, gather, inv, prod, seg;
 };
 
 template <class F>
@@ -149,6 +149,13 @@ void add_point_items(const DevTables& d, const HostTables& t, int p, int inv_lt,
     for (int rt = 0; rt < (2 * d.nq + 31) / 32; ++rt)
       for (int ct = 0; ct < (nff2 + 63) / 64; ++ct) v.push_back(make_int4(p, rt, ct, 0));
   });
+  // symmetric states: chi' at the representatives only (rows (channel, slot),
+  // item.w = 1), which is all the products read
+  if (wedge)
+    mark(h.expw, r.exp_w, [&](std::vector<int4>& v) {
+      for (int rt = 0; rt < (2 * d.nirr + 31) / 32; ++rt)
+        for (int ct = 0; ct < (nff2 + 63) / 64; ++ct) v.push_back(make_int4(p, rt, ct, 1));
+    });
   mark(h.fwd, r.fwd, [&](std::vector<int4>& v) {
     for (int sp = 0; sp < d.nsu; ++sp)
       for (int c = 0; c < (3 * nff2 + fwd_cols - 1) / fwd_cols; ++c) v.push_back(make_int4(p, c, sp, 0));
@@ -283,7 +290,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
     return r;
   };
   Ranges& all = ctx->all;
-  all.loop = whole(h.loop); all.exp = whole(h.exp); all.fwd = whole(h.fwd);
+  all.loop = whole(h.loop); all.exp = whole(h.exp); all.exp_w = whole(h.expw); all.fwd = whole(h.fwd);
   all.basis = whole(h.basis); all.gather = whole(h.gather);
   all.inv = whole(h.inv); all.prod = whole(h.prod);
   all.seg = whole(h.seg);
@@ -316,6 +323,11 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   int4* t = nullptr;
   ST_TRY(upload(ctx, h.loop, &t, g)); L.loop_items = t;
   ST_TRY(upload(ctx, h.exp, &t, g)); L.exp_items = t;
+  L.expw_items = nullptr;
+  if (!h.expw.empty()) {
+    ST_TRY(upload(ctx, h.expw, &t, g));
+    L.expw_items = t;
+  }
   ST_TRY(upload(ctx, h.fwd, &t, g)); L.fwd_items = t;
   ST_TRY(upload(ctx, h.inv, &t, g)); L.inv_items = t;
   ST_TRY(upload(ctx, h.basis, &t, g)); L.basis_items = t;
@@ -423,9 +435,16 @@ void set_T_launch(tufrg_ctx* ctx, const TSource& ts, hipStream_t s) {
 // costs to dominate (Launch::fused).  Otherwise, and with the surrogate, the
 // loops run on the side stream (fork and join by events) alongside the
 // whole projection chain.
-void rhs_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, const double* X, double* out,
+void rhs_launch(tufrg_ctx* ctx, const Launch& L0, const Ranges& r0, const double* X, double* out,
                 bool scale_T, hipStream_t ms, const TSource& ts) {
   const bool mixed = mixed_of(ctx), cross = cross_of(ctx);
+  // symmetric states: the loop expansion at the representatives only
+  Launch L = L0;
+  Ranges r = r0;
+  if (L0.b.wedge && L0.expw_items) {
+    L.exp_items = L0.expw_items;
+    r.exp = r0.exp_w;
+  }
   if (!ctx->sur_a && L.fused) {
     // the fused launch takes the temperatures itself (and stores them for the
     // products), except for host values of more than 64 points

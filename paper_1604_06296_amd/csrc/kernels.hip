@@ -28,7 +28,9 @@ __device__ __forceinline__ bool skip_point(const Batch& b, int p) {
 // the symmetry map), as one contraction over j: rows (channel, q), columns
 // mn.  Item (p, row tile of 32, column tile of 64); the representatives'
 // harmonics are the sums of their loop slices, or come from fin
-// [nirr][2][nsh] (single point).  Each thread owns 2 rows x 4 columns.
+// [nirr][2][nsh] (single point).  Each thread owns 2 rows x 4 columns.  Items
+// with w = 1 take the rows (channel, representative slot) instead: chi' at the
+// orbit representatives only (symmetric states).
 constexpr int kExpRows = 32, kExpCols = 64, kExpK = 36;
 struct alignas(16) ExpandShared {
   double As[kExpRows][kExpK];
@@ -43,6 +45,8 @@ __device__ __forceinline__ void expand_body(const Batch& b, const int4 item, con
   auto& Bs = sh.Bs;
   const int nq = d.nq, nsh = d.nsh, nout = 2 * nsh, nff2 = d.nff * d.nff;
   const int r0 = item.y * kExpRows, c0 = item.z * kExpCols;
+  const bool reps = item.w != 0;
+  const int nrow = reps ? d.nirr : nq;   // rows per channel
   const int tid = threadIdx.x;
   {
     // the thread's (up to 5) entries of the row tile, the loop slices of each
@@ -54,12 +58,12 @@ __device__ __forceinline__ void expand_body(const Batch& b, const int4 item, con
 #pragma unroll
     for (int s5 = 0; s5 < kPer; ++s5) {
       const int e = tid + 256 * s5, rr = e / nsh, j = e % nsh, row = r0 + rr;
-      ok[s5] = e < kExpRows * nsh && row < 2 * nq;
+      ok[s5] = e < kExpRows * nsh && row < 2 * nrow;
       neg[s5] = false;
       src[s5] = fin;
       v[s5] = 0.0;
       if (ok[s5]) {
-        const int ch = row / nq, q = row % nq;
+        const int ch = row / nrow, q = reps ? d.irr[row % nrow] : row % nrow;
         const int32_t pk = d.symmap[(size_t)q * nsh + j];
         const int slot = pk & 0xffff, oo = ch * nsh + ((pk >> 16) & 0x7f);
         neg[s5] = (pk >> 24) & 1;
@@ -116,8 +120,8 @@ __device__ __forceinline__ void expand_body(const Batch& b, const int4 item, con
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int row = r0 + rr + i;
-    if (row >= 2 * nq) continue;
-    const int ch = row / nq, q = row % nq;
+    if (row >= 2 * nrow) continue;
+    const int ch = row / nrow, q = reps ? d.irr[row % nrow] : row % nrow;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int mn = c0 + cc + c;

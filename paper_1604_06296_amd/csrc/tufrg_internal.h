@@ -158,6 +158,7 @@ struct ItemRange {
 // Item ranges of one launch set (all points, or one point)
 struct Ranges {
   ItemRange loop, exp, fwd, basis, gather, inv, prod, seg;
+  ItemRange exp_w;   // loop expansion at the orbit representatives (symmetric states)
   // the product items by N_ff (contiguous runs of prod): one launch each, with
   // the shared memory of its own N_ff, so that small matrices are not held to
   // the occupancy of the largest
@@ -190,6 +191,7 @@ struct Launch {
   Batch b;
   const int4* loop_items;
   const int4* exp_items;
+  const int4* expw_items; // loop expansion at the representatives (symmetric states) or null
   const int4* fwd_items;
   const int4* inv_items;
   const int4* basis_items;

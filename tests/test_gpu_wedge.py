@@ -213,3 +213,14 @@ def test_batch_of_uneven_points(tf):
         single = tf.Context([p])
         ref = _host(single, single.rhs(0.08, _to_dev(single, s)))
         _assert_normwise(_host(ctx, out, i), ref, tol=1e-11, what=f"point {i}")
+
+
+def test_bubbles_entry_point_still_covers_every_momentum(tf):
+    """The right-hand side expands the loops at the representatives only; the
+    loops entry point still returns chi' of every momentum, bit for bit."""
+    pt = _pt(3, 10, 24)
+    a = tf.Context([pt], symmetric_state=True)
+    b = tf.Context([pt])
+    ga = _host(a, a.bubbles(0.09))
+    gb = _host(b, b.bubbles(0.09))
+    np.testing.assert_array_equal(ga, gb)
