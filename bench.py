@@ -65,6 +65,10 @@ def parse():
                     help="counter probe only: this many projection steps (tufrg_project) of the "
                          "headline workload (FP64) and of the N_ff=21, 48x48 workload (FP64, then "
                          "mixed); prints no JSON")
+    ap.add_argument("--probe-wedge", type=int, default=0,
+                    help="trace probe only: this many right-hand sides of the N_ff=21, 48x48 workload "
+                         "(FP64) per momentum, one fill kernel as a marker, then as many with "
+                         "symmetric states; prints no JSON")
     return ap.parse_args()
 
 
@@ -109,6 +113,27 @@ def probe_projections(n):
         torch.cuda.synchronize()
         log(f"[probe] {w.name} {prec}: {n} projection steps")
         ctx.close()
+
+
+def probe_wedge(n):
+    """Fixed right-hand-side sequence for a kernel trace of the symmetric-state mode."""
+    import torch
+
+    import paper_1604_06296_amd as tf
+    import synth
+    pt = synth.cfg3().points[0]
+    for sym in (False, True):
+        ctx = tf.Context([pt], symmetric_state=sym)
+        X = ctx.empty(3).zero_()
+        out = ctx.empty(3)
+        for _ in range(n):
+            ctx.rhs(0.05, X, out)
+        torch.cuda.synchronize()
+        log(f"[probe] {n} right-hand sides, symmetric_state={sym}")
+        ctx.close()
+        if not sym:
+            torch.zeros(1, device="cuda").fill_(1.0)    # marker between the two runs
+            torch.cuda.synchronize()
 
 
 def log(msg):
@@ -371,7 +396,9 @@ def leg_surrogate(tf, synth, train_steps):
 
 def main():
     args = parse()
-    if args.probe_loops > 0 or args.probe_projections > 0:
+    if args.probe_loops > 0 or args.probe_projections > 0 or args.probe_wedge > 0:
+        if args.probe_wedge > 0:
+            probe_wedge(args.probe_wedge)
         if args.probe_loops > 0:
             probe_loops(args.probe_loops)
         if args.probe_projections > 0:

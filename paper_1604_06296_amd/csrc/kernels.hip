@@ -576,6 +576,20 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
   R* Wm = Ch + 2 * nff2;                    // [nff2]
   R* T1 = Wm + nff2;                        // [3][nff2]
   R* T2 = T1 + 3 * nff2;                    // [3][nff2]
+  // symmetric states: the representative's orbit (at most 8 members), each
+  // member's q and form-factor permutation, staged with the block's loads
+  __shared__ int orb_q_s[8];
+  __shared__ int32_t orb_p_s[8][32];
+  int orb_n = 0;
+  if (b.wedge) {
+    const int e0 = d.orb_start[item.z];
+    orb_n = d.orb_start[item.z + 1] - e0;
+    for (int i = threadIdx.x; i < orb_n * nff; i += blockDim.x) {
+      const int e = i / nff, m = i % nff;
+      orb_p_s[e][m] = d.tperm[(size_t)d.orb_tr[e0 + e] * nff + m];
+    }
+    if ((int)threadIdx.x < orb_n) orb_q_s[threadIdx.x] = d.orb_q[e0 + threadIdx.x];
+  }
   // the thread's entries mn = tid + 256 h (h < 2; 256 threads, nff^2 <= 441):
   // all of their loads in flight together, then V (and W, the loops) to LDS
   double xv[2][3], kv[2][3], cv[2][2];
@@ -616,15 +630,14 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
   }
   if (mode == 0 && !b.wedge) return;
   __syncthreads();
-  // the orbit of the representative: members e0..e1 with their transforms
+  // the orbit of the representative (staged above; the barrier above or in
+  // the products has made it visible)
   auto orbit = [&](auto&& value) {
-    const int e0 = d.orb_start[item.z], n = d.orb_start[item.z + 1] - e0;
-    for (int w = threadIdx.x; w < n * nff2; w += blockDim.x) {
-      const int e = e0 + w / nff2, mn = w % nff2;
-      const int32_t* tp = d.tperm + (size_t)d.orb_tr[e] * nff;
-      const int a = tp[mn / nff], c = tp[mn % nff];
+    for (int w = threadIdx.x; w < orb_n * nff2; w += blockDim.x) {
+      const int e = w / nff2, mn = w % nff2;
+      const int a = orb_p_s[e][mn / nff], c = orb_p_s[e][mn % nff];
       const double sg = ((a ^ c) >> 8) & 1 ? -1.0 : 1.0;
-      value(d.off + (size_t)d.orb_q[e] * nff2 + mn, (a & 0xff) * nff + (c & 0xff), sg);
+      value(d.off + (size_t)orb_q_s[e] * nff2 + mn, (a & 0xff) * nff + (c & 0xff), sg);
     }
   };
   if (mode == 0) {
