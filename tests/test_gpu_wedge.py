@@ -224,3 +224,36 @@ def test_bubbles_entry_point_still_covers_every_momentum(tf):
     ga = _host(a, a.bubbles(0.09))
     gb = _host(b, b.bubbles(0.09))
     np.testing.assert_array_equal(ga, gb)
+
+
+def _rep_of(Lq, q):
+    return min(osym.image(Lq, h, q)[0] for h in osym.C4V_OPS)
+
+
+def test_batched_rk4_flow_graph_and_eager(tf):
+    """A batch of uneven points flowed from zero with symmetric states: the HIP-graph
+    replay equals the eager flow bit for bit, and every point matches the
+    per-momentum batch (critical scale 1e-8, same steps and channel, the ordering
+    vector in the same orbit: members of an orbit are exact copies here, so the
+    classification's first maximum may be another member)."""
+    import torch
+    pts = [_pt(1, 8, 16, tp=-0.1, mu=-0.2, U=3.0), _pt(2, 10, 20, tp=-0.3, mu=-1.0, U=2.5),
+           _pt(3, 12, 24, tp=-0.2, mu=-0.6, U=2.8), _pt(0, 6, 12, tp=0.0, mu=0.0, U=3.2)]
+    opts = lambda g: tf.FlowOptions(T0=10.0, Tmin=0.01, Xmax=20.0, scheme="rk4", nsteps=60, use_graph=g)
+    print("[wedge] batched rk4 flow, graph vs eager", flush=True)
+    ctx = tf.Context(pts, symmetric_state=True, loop_queue=True)
+    Xa, Xb = ctx.empty(3).zero_(), ctx.empty(3).zero_()
+    ra = ctx.flow(Xa, opts(False))
+    rb = ctx.flow(Xb, opts(True))
+    assert ra == rb and torch.equal(Xa, Xb)
+    ref = tf.Context(pts, loop_queue=True)
+    Xr = ref.empty(3).zero_()
+    rr = ref.flow(Xr, opts(False))
+    for i, (a, r) in enumerate(zip(ra, rr)):
+        print(f"  pt{i}: {a.status} Tc={a.Tc} {a.channel} q={a.q_index} {a.irrep} / {r.Tc} q={r.q_index}",
+              flush=True)
+        assert a.status == r.status and a.n_steps == r.n_steps and a.channel == r.channel
+        if a.status == "diverged":
+            assert abs(a.Tc / r.Tc - 1) < 1e-8
+            assert _rep_of(pts[i].Lq, a.q_index) == _rep_of(pts[i].Lq, r.q_index)
+        _assert_normwise(_host(ctx, Xa, i), _host(ref, Xr, i), tol=1e-8, what=f"pt{i} X at stop")
