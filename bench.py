@@ -263,6 +263,18 @@ def leg_batched(tf, synth):
                 "diverged": sum(r.status == "diverged" for r in r_g),
                 "rhs_total": sum(r.n_rhs for r in r_g)})
     log(f"[batched] rhs {out['rhs_ms']:.3f} ms, flow eager {t_e:.2f} s, graph {t_g:.2f} s")
+    ctx.close()
+    # the same batch with symmetric states (every flow starts at zero): one
+    # momentum per orbit in the loop expansion, inverse transform and products
+    sym = tf.Context(w.points, autotune=True, symmetric_state=True)
+    Xs, os_ = sym.empty(3), sym.empty(3)
+    rhs_ms = 1e3 * time_rhs(sym, Ts, Xs.zero_(), os_, n=10)
+    r_s, t_s = timed_flow(sym, Xs, tf.FlowOptions(use_graph=True, **opts))
+    same = all(a.status == b.status and a.n_steps == b.n_steps and a.channel == b.channel and a.irrep == b.irrep
+               and (a.Tc is None or abs(a.Tc / b.Tc - 1) < 1e-8) for a, b in zip(r_s, r_g))
+    out["symmetric_state"] = {"rhs_ms": rhs_ms, "flow_s_graph": t_s, "same_outcomes": same}
+    log(f"[batched] symmetric states: rhs {rhs_ms:.3f} ms, flow graph {t_s:.2f} s, same outcomes {same}")
+    sym.close()
     return out
 
 
