@@ -20,6 +20,9 @@
  * G(i w, eps) = chi(w)/(i w - eps) with chi(w) = w^2/(w^2 + Omega^2), loops
  * are integrals over real frequencies, every derivative is d/dOmega, and
  * every argument named T below (temperatures, T0, Tmin, Tc) is Omega.
+ * With TUFRG_SYMMETRIC_STATE the states are taken to be C4v-symmetric (as
+ * every state of a flow started at zero is) and part of the work runs at one
+ * transfer momentum per point-group orbit; see the flag.
  * Transfer momenta live on a uniform Lq x Lq grid
  * q_i = 2 pi (i - Lq/2)/Lq per axis (flat index ix*Lq + iy); loops are
  * plain averages over the unshifted uniform Lk x Lk grid p_j = 2 pi j/Lk.
