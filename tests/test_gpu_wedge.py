@@ -257,3 +257,32 @@ def test_batched_rk4_flow_graph_and_eager(tf):
             assert abs(a.Tc / r.Tc - 1) < 1e-8
             assert _rep_of(pts[i].Lq, a.q_index) == _rep_of(pts[i].Lq, r.q_index)
         _assert_normwise(_host(ctx, Xa, i), _host(ref, Xr, i), tol=1e-8, what=f"pt{i} X at stop")
+
+
+def test_singleton_orbits_give_the_per_momentum_bits(tf):
+    """With the point-group reduction off every momentum is its own representative:
+    the symmetric-state path is then the per-momentum path, bit for bit."""
+    pt = _pt(3, 10, 24)
+    ff = FormFactors(3)
+    X = synth.random_channels(100, ff.nff, seed=12)
+    a = tf.Context([pt], no_symmetry=True, symmetric_state=True)
+    b = tf.Context([pt], no_symmetry=True)
+    np.testing.assert_array_equal(_host(a, a.rhs(0.06, _to_dev(a, X))), _host(b, b.rhs(0.06, _to_dev(b, X))))
+    np.testing.assert_array_equal(_host(a, a.project(_to_dev(a, X))), _host(b, b.project(_to_dev(b, X))))
+
+
+def test_mixed_precision_flow(tf):
+    """Mixed precision along a whole RK4 flow from zero: the same outcome as the
+    per-momentum mixed flow (critical scale within the mixed form's 1e-5)."""
+    w = synth.cfg1()
+    pt = w.points[0]
+    opts = tf.FlowOptions(T0=w.T0, Tmin=w.Tmin, Xmax=w.Xmax, scheme="rk4", nsteps=w.nsteps)
+    a = tf.Context([pt], precision="mixed", symmetric_state=True)
+    b = tf.Context([pt], precision="mixed")
+    ra = a.flow(a.empty(3).zero_(), opts)[0]
+    rb = b.flow(b.empty(3).zero_(), opts)[0]
+    print("wedge", ra, "per momentum", rb, flush=True)
+    assert ra.status == rb.status == "diverged" and ra.n_steps == rb.n_steps
+    assert abs(ra.Tc / rb.Tc - 1) < 1e-5
+    assert ra.channel == rb.channel and ra.irrep == rb.irrep
+    assert _rep_of(pt.Lq, ra.q_index) == _rep_of(pt.Lq, rb.q_index)
