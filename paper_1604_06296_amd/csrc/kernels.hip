@@ -649,62 +649,86 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
   }
   const R* VP = Vs;
   const R* VC = Vs + nff2;
-  // the six N_ff x N_ff products; in 3x3 register tiles each A and B entry is
-  // read from LDS once per tile.  Every output sums k in order either way.
-  const int nt = (nff + 2) / 3;
-  auto product = [&](const R* A, const R* B, R* C, int ti, int tj) {
-    const int m0 = 3 * ti, n0 = 3 * tj;
-    R c[3][3];
+  // N_ff <= 16: the six products on the matrix cores, one 16 x 16 tile of
+  // the zero-padded matrices per wave (v_mfma_f64_16x16x4f64, or
+  // v_mfma_f32_16x16x4f32 for the FP32 form; lane l holds A[l%16][k0 + l/16]
+  // and B[k0 + l/16][l%16]).  Beyond, padding to 32 would triple the work
+  // (the FP64 matrix and vector peaks are equal), so 3x3 register tiles.
+  if (nff <= 16) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    const int r16 = lane & 15, k4 = lane >> 4;
+    auto mm_tile = [&](const R* A, const R* B, R* C) {
+      if constexpr (sizeof(R) == 8) {
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < 16; k0 += 4) {
+          const int k = k0 + k4;
+          const double av = (r16 < nff && k < nff) ? (double)A[r16 * nff + k] : 0.0;
+          const double bv = (k < nff && r16 < nff) ? (double)B[k * nff + r16] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 4; ++j) {
+          const int r = 4 * j + k4;   // f64 result layout: D[4j + l/16][l%16]
+          if (r < nff && r16 < nff) C[r * nff + r16] = (R)acc[j];
+        }
+      } else {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < 16; k0 += 4) {
+          const int k = k0 + k4;
+          const float av = (r16 < nff && k < nff) ? (float)A[r16 * nff + k] : 0.f;
+          const float bv = (k < nff && r16 < nff) ? (float)B[k * nff + r16] : 0.f;
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        }
 #pragma unroll
-      for (int j = 0; j < 3; ++j) c[i][j] = 0;
-    for (int k = 0; k < nff; ++k) {
-      R a[3], bb[3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) a[i] = m0 + i < nff ? A[(m0 + i) * nff + k] : (R)0;
-#pragma unroll
-      for (int j = 0; j < 3; ++j) bb[j] = n0 + j < nff ? B[k * nff + n0 + j] : (R)0;
+        for (int j = 0; j < 4; ++j) {
+          const int r = 4 * k4 + j;   // f32 result layout: D[4(l/16) + j][l%16]
+          if (r < nff && r16 < nff) C[r * nff + r16] = (R)acc[j];
+        }
+      }
+    };
+    // round 1: T1 = (chi'pp VP, chi'ph VC, chi'ph W); round 2: T2 = (VP T1_0, VC T1_1, W T1_2)
+    for (int which = wv; which < 3; which += nwv)
+      mm_tile(Ch + (which == 0 ? 0 : nff2), which == 0 ? VP : (which == 1 ? VC : Wm), T1 + which * nff2);
+    __syncthreads();
+    for (int which = wv; which < 3; which += nwv)
+      mm_tile(which == 0 ? VP : (which == 1 ? VC : Wm), T1 + which * nff2, T2 + which * nff2);
+  } else {
+    // 3x3 register tiles: each A and B entry is read from LDS once per tile,
+    // and every output sums k in order
+    const int nt = (nff + 2) / 3;
+    auto product = [&](const R* A, const R* B, R* C, int ti, int tj) {
+      const int m0 = 3 * ti, n0 = 3 * tj;
+      R c[3][3];
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) c[i][j] = fma(a[i], bb[j], c[i][j]);
-    }
+        for (int j = 0; j < 3; ++j) c[i][j] = 0;
+      for (int k = 0; k < nff; ++k) {
+        R a[3], bb[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i) a[i] = m0 + i < nff ? A[(m0 + i) * nff + k] : (R)0;
 #pragma unroll
-      for (int j = 0; j < 3; ++j)
-        if (m0 + i < nff && n0 + j < nff) C[(m0 + i) * nff + n0 + j] = c[i][j];
-  };
-  // one output per thread while the block holds every output in a round or
-  // two (N_ff <= 13); 3x3 tiles beyond
-  const bool tiled = nff > 13;
-  const int nw = tiled ? 3 * nt * nt : 3 * nff2;
-  for (int w = threadIdx.x; w < nw; w += blockDim.x) {
-    if (tiled) {
+        for (int j = 0; j < 3; ++j) bb[j] = n0 + j < nff ? B[k * nff + n0 + j] : (R)0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) c[i][j] = fma(a[i], bb[j], c[i][j]);
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          if (m0 + i < nff && n0 + j < nff) C[(m0 + i) * nff + n0 + j] = c[i][j];
+    };
+    const int nw = 3 * nt * nt;
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) {
       const int which = w / (nt * nt), ti = w / nt % nt, tj = w % nt;
       product(Ch + (which == 0 ? 0 : nff2), which == 0 ? VP : (which == 1 ? VC : Wm), T1 + which * nff2, ti, tj);
-    } else {
-      const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
-      const R* A = Ch + (which == 0 ? 0 : nff2) + m * nff;
-      const R* B = which == 0 ? VP : (which == 1 ? VC : Wm);
-      R v = 0;
-      for (int k = 0; k < nff; ++k) v = fma(A[k], B[k * nff + n], v);
-      T1[w] = v;
     }
-  }
-  __syncthreads();
-  for (int w = threadIdx.x; w < nw; w += blockDim.x) {
-    if (tiled) {
+    __syncthreads();
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) {
       const int which = w / (nt * nt), ti = w / nt % nt, tj = w % nt;
       product(which == 0 ? VP : (which == 1 ? VC : Wm), T1 + which * nff2, T2 + which * nff2, ti, tj);
-    } else {
-      const int which = w / nff2, m = (w % nff2) / nff, n = w % nff;
-      const R* A = (which == 0 ? VP : (which == 1 ? VC : Wm)) + m * nff;
-      const R* B = T1 + which * nff2;
-      R v = 0;
-      for (int k = 0; k < nff; ++k) v = fma(A[k], B[k * nff + n], v);
-      T2[w] = v;
     }
   }
   __syncthreads();
