@@ -126,6 +126,7 @@ void default_geometry(DevTables& d) {
 // ------------------------------------------------------------ item tables
 struct HostItems {
   std::vector<int4> loop, exp, expw, fwd, basis, gather, inv, prod, seg;
+  std::vector<int2> gent;   // gather rows' entries, gather_cap per row
 };
 
 template <class F>
@@ -142,7 +143,7 @@ void mark(std::vector<int4>& v, ItemRange& rg, F fill) {
 int inv_rows_of(const DevTables& d, bool wedge) { return wedge ? d.nirr : d.nq; }
 
 void add_point_items(const DevTables& d, const HostTables& t, int p, int inv_lt, int fwd_cols, bool wedge,
-                     HostItems& h, Ranges& r) {
+                     int gcap, HostItems& h, Ranges& r) {
   const int nff2 = d.nff * d.nff, nv = 2 * d.nsh - 1;
   const int nrow = inv_rows_of(d, wedge);
   mark(h.exp, r.exp, [&](std::vector<int4>& v) {
@@ -167,10 +168,34 @@ void add_point_items(const DevTables& d, const HostTables& t, int p, int inv_lt,
   mark(h.basis, r.basis, [&](std::vector<int4>& v) {
     for (int b = 0; b < 3 * nv; ++b) v.push_back(make_int4(p, b, 0, 0));
   });
+  // gather items (p, packed block, -, first entry): the block's harmonic j,
+  // output channel X and shell pair (start and size of each) packed into y,
+  // and its rows' entries (gcap per row, in the entry lists' order) as
+  // absolute offsets into yb, so that the kernel reaches yb in two loads
   mark(h.gather, r.gather, [&](std::vector<int4>& v) {
-    const int ns = d.nshell;
+    const int ns = d.nshell, nv2 = 2 * d.nsh - 1, ybim = 3 * nv2 * nff2;
     for (int j = 0; j < d.nsh; ++j)
-      for (int x = 0; x < 3 * ns * ns; ++x) v.push_back(make_int4(p, j, x, 0));
+      for (int x = 0; x < 3 * ns * ns; ++x) {
+        const int X = x / (ns * ns), sm = x / ns % ns, sn = x % ns;
+        const int a0 = t.shell_start[sm], na = t.shell_start[sm + 1] - a0;
+        const int b0 = t.shell_start[sn], nb = t.shell_start[sn + 1] - b0;
+        const int nvl = j == 0 ? 1 : 2, nab = na * nb;
+        const int packed = j | (X << 8) | (na << 10) | (nb << 14) | (a0 << 18) | (b0 << 23);
+        v.push_back(make_int4(p, packed, 0, (int)h.gent.size()));
+        for (int w = 0; w < nvl * nab; ++w) {
+          const int vi = w / nab, rr = w % nab, vf = vi == 0 ? j : d.nsh - 1 + j;
+          const size_t row = ((size_t)X * nv2 + vf) * nff2 + (size_t)(a0 + rr / nb) * d.nff + b0 + rr % nb;
+          int k = 0;
+          for (int e = t.mrow[row]; e < t.mrow[row + 1]; ++e, ++k) {
+            const int32_t pk = t.ment[(size_t)e];
+            const int in = pk & 3, b1 = (pk >> 2) & 31, b2 = (pk >> 7) & 31, vv = (pk >> 12) & 127;
+            const int o = (int)d.ws_yb + ((in * nv2 + vv) * nff2 + b1 * d.nff + b2);
+            const int im = o + ybim;
+            h.gent.push_back(make_int2(o, ((pk >> 19) & 1) ? -(im + 1) : im));
+          }
+          for (; k < gcap; ++k) h.gent.push_back(make_int2(-1, 0));
+        }
+      }
   });
   mark(h.prod, r.prod, [&](std::vector<int4>& v) {
     if (wedge)
@@ -227,6 +252,13 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
   for (int p : order) add_loop_items(ctx->dev[p], ctx->host[p], p, h.loop, ctx->per_point[p].loop);
   const bool wedge = (ctx->opt.flags & TUFRG_SYMMETRIC_STATE) != 0;
+  // entries per gather row: the longest row of any point
+  int gcap = 1;
+  for (const HostTables& t : ctx->host)
+    for (size_t r = 0; r + 1 < t.mrow.size(); ++r) gcap = std::max(gcap, t.mrow[r + 1] - t.mrow[r]);
+  for (const DevTables& d : ctx->dev)   // gather entries hold yb offsets as int
+    if (d.ws_yb + (int64_t)6 * (2 * d.nsh - 1) * d.nff * d.nff > (int64_t)INT32_MAX)
+      return fail(ctx, TUFRG_EINVAL, "bond-basis workspace beyond 2^31 elements");
   // inverse-transform momentum tile: the largest of 64, 32, 16 that still
   // gives the launch 512 items
   int64_t inv_items[3] = {0, 0, 0};
@@ -249,7 +281,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   std::stable_sort(by_nff.begin(), by_nff.end(), [&](int x, int y) { return ctx->dev[x].nff > ctx->dev[y].nff; });
   for (int p : by_nff) {
     Ranges& rp = ctx->per_point[p];
-    add_point_items(ctx->dev[p], ctx->host[p], p, inv_lt, fwd_cols, wedge, h, rp);
+    add_point_items(ctx->dev[p], ctx->host[p], p, inv_lt, fwd_cols, wedge, gcap, h, rp);
     rp.nprod_cls = 1;
     rp.prod_cls[0] = rp.prod;
     rp.prod_cls_nff[0] = ctx->dev[p].nff;
@@ -332,6 +364,12 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   ST_TRY(upload(ctx, h.inv, &t, g)); L.inv_items = t;
   ST_TRY(upload(ctx, h.basis, &t, g)); L.basis_items = t;
   ST_TRY(upload(ctx, h.gather, &t, g)); L.gather_items = t;
+  {
+    int2* ge = nullptr;
+    ST_TRY(upload(ctx, h.gent, &ge, g));
+    L.gather_ent = ge;
+    L.gather_cap = gcap;
+  }
   ST_TRY(upload(ctx, h.prod, &t, g)); L.prod_items = t;
   ST_TRY(upload(ctx, h.seg, &t, g)); L.seg_items = t;
   ST_TRY(dalloc(ctx, (size_t)std::max<int64_t>(gh, 1), &L.b.ghat, g));

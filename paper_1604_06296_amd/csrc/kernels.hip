@@ -267,56 +267,52 @@ k_expand_basis(Batch b, const int4* __restrict__ exp_items, int nexp, const int4
 //   Re[e^{-il.V/2} N(V) + e^{+il.V/2} N(-V)] = cos (ReN+ + ReN-) + sin (ImN+ - ImN-).
 // C is block diagonal over shells, so the item is (p, half-set harmonic j,
 // (X, shell of m, shell of n)): one wave gathers the shell block of M (at
-// most kShellMax^2 bond pairs per harmonic) into LDS and transforms it.
+// most kShellMax^2 bond pairs per harmonic) into LDS and transforms it.  The
+// item packs j, X and both shells' start and size (y) and the index of its
+// rows' entries (w: cap per row, absolute yb offsets of the real and
+// imaginary parts, a negative imaginary offset for a negated entry, a
+// negative real offset for padding), so that the yb loads wait for two loads
+// only; the entries of a row are added in the order of the entry lists.
 __global__ void __launch_bounds__(64)
-k_gather_g2(Batch b, const int4* __restrict__ items) {
+k_gather_g2(Batch b, const int4* __restrict__ items, const int2* __restrict__ gent, int cap) {
   __shared__ double Mre[2][kShellMax * kShellMax];
   __shared__ double Mim[2][kShellMax * kShellMax];
   __shared__ double C1[2][kShellMax * kShellMax];   // c_{m a}, m and a in shell sm (re, im)
   __shared__ double C2[2][kShellMax * kShellMax];   // c_{n b}, n and b in shell sn
   const int4 item = items[blockIdx.x];
   const int p = item.x;
+  const int j = item.y & 0xff, X = (item.y >> 8) & 3, na = (item.y >> 10) & 15, nb = (item.y >> 14) & 15;
+  const int a0 = (item.y >> 18) & 31, b0 = (item.y >> 23) & 31;
+  const int nab = na * nb, nvl = j == 0 ? 1 : 2;
   if (skip_point(b, p)) return;
-  const DevTables& d = b.pts[p];
-  const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol, ns = d.nshell;
-  const int j = item.y, X = item.z / (ns * ns), sm = item.z / ns % ns, sn = item.z % ns;
-  const int a0 = d.shell_start[sm], na = d.shell_start[sm + 1] - a0;
-  const int b0 = d.shell_start[sn], nb = d.shell_start[sn + 1] - b0;
-  const int nv = 2 * nsh - 1, nab = na * nb;
-  const int nvl = (j == 0) ? 1 : 2;
-  const size_t ybim = (size_t)3 * nv * nff2;
-  const double* yb = b.yb + d.ws_yb;
+  // the rows' entries and their yb values first: they depend on the item only
   for (int w = threadIdx.x; w < nvl * nab; w += 64) {
-    const int vi = w / nab, r = w % nab;
-    const int vf = (vi == 0) ? j : (nsh - 1 + j);
-    const size_t row = ((size_t)X * nv + vf) * nff2 + (size_t)(a0 + r / nb) * nff + b0 + r % nb;
+    const int2* en = gent + item.w + (size_t)w * cap;
     double re = 0.0, im = 0.0;
-    const int e0 = d.mrow[row], e1 = d.mrow[row + 1];
-    for (int e = e0; e < e1; e += 4) {
-      // entries four at a time: independent loads, then the sums in order
-      int32_t pk[4];
+    for (int e = 0; e < cap; e += 4) {
+      int2 pk[4];
       double yr[4], yi[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) pk[u] = e + u < e1 ? d.ment[e + u] : -1;
+      for (int u = 0; u < 4; ++u) pk[u] = e + u < cap ? en[e + u] : make_int2(-1, 0);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         yr[u] = yi[u] = 0.0;
-        if (pk[u] >= 0) {
-          const int in = pk[u] & 3, b1 = (pk[u] >> 2) & 31, b2 = (pk[u] >> 7) & 31, v = (pk[u] >> 12) & 127;
-          const size_t o = ((size_t)in * nv + v) * nff2 + b1 * nff + b2;
-          yr[u] = yb[o];
-          yi[u] = yb[ybim + o];
+        if (pk[u].x >= 0) {
+          yr[u] = b.yb[pk[u].x];
+          yi[u] = b.yb[pk[u].y >= 0 ? pk[u].y : -pk[u].y - 1];
         }
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (pk[u] < 0) continue;
-        if ((pk[u] >> 19) & 1) { re -= yr[u]; im -= yi[u]; } else { re += yr[u]; im += yi[u]; }
+        if (pk[u].x < 0) continue;
+        if (pk[u].y < 0) { re -= yr[u]; im -= yi[u]; } else { re += yr[u]; im += yi[u]; }
       }
     }
-    Mre[vi][r] = re;
-    Mim[vi][r] = im;
+    Mre[w / nab][w % nab] = re;
+    Mim[w / nab][w % nab] = im;
   }
+  const DevTables& d = b.pts[p];
+  const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol;
   if ((int)threadIdx.x < na * na) {
     const int i = threadIdx.x, c = (a0 + i / na) * nff + a0 + i % na;
     C1[0][i] = d.cre[c];
@@ -992,7 +988,8 @@ void launch_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, h
 
 void launch_gather_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t s) {
   if (r.gather.n > 0)
-    hipLaunchKernelGGL(k_gather_g2, dim3(r.gather.n), dim3(64), 0, s, L.b, L.gather_items + r.gather.begin);
+    hipLaunchKernelGGL(k_gather_g2, dim3(r.gather.n), dim3(64), 0, s, L.b, L.gather_items + r.gather.begin,
+                       L.gather_ent, L.gather_cap);
   if (r.inv.n > 0) {
     const int4* it = L.inv_items + r.inv.begin;
     const dim3 g(r.inv.n), blk(256);

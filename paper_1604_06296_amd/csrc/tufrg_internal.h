@@ -196,6 +196,8 @@ struct Launch {
   const int4* inv_items;
   const int4* basis_items;
   const int4* gather_items;
+  const int2* gather_ent;  // gather rows' entries: absolute yb offsets (re, im; im < 0 negates)
+  int gather_cap;          // entries per gather row (padded with re = -1)
   const int4* prod_items;
   const int4* seg_items;
   int loop_threads, loop_blocks, smax_max;
