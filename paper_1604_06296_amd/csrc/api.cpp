@@ -392,6 +392,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   L.front_smem = std::max(lsm, fsm);
   L.b.loop_threads = threads;
   L.b.wedge = wedge ? 1 : 0;
+  L.one_point = npts == 1;
   L.omega = omega_of(ctx);
   // blocks of the loop kernel per CU in each form; the form with two rows in
   // flight when the items need no more blocks per CU than it allows

@@ -36,9 +36,12 @@ struct alignas(16) ExpandShared {
   double As[kExpRows][kExpK];
   double Bs[kExpK][kExpCols];
 };
+// ONE: the launch covers a single point (p = 0), so its descriptor loads need
+// not wait for the item's
+template <bool ONE>
 __device__ __forceinline__ void expand_body(const Batch& b, const int4 item, const double* __restrict__ fin,
                                             double* __restrict__ dchi, ExpandShared& sh) {
-  const int p = item.x;
+  const int p = ONE ? 0 : item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
   auto& As = sh.As;
@@ -134,7 +137,7 @@ __global__ void __launch_bounds__(256)
 k_chi_expand(Batch b, const int4* __restrict__ items, const double* __restrict__ fin,
              double* __restrict__ dchi) {
   __shared__ ExpandShared sh;
-  expand_body(b, items[blockIdx.x], fin, dchi, sh);
+  expand_body<false>(b, items[blockIdx.x], fin, dchi, sh);
 }
 
 // ------------------------------------------------------- projections
@@ -161,8 +164,9 @@ struct alignas(16) BasisShared {
   double cs[2 * 441];
   double xs[2 * 441];
 };
+template <bool ONE>
 __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, BasisShared& sh) {
-  const int p = item.x;
+  const int p = ONE ? 0 : item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
   const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol, nv = 2 * nsh - 1;
@@ -242,12 +246,13 @@ __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, Basi
 __global__ void __launch_bounds__(256)
 k_bond_basis(Batch b, const int4* __restrict__ items) {
   __shared__ BasisShared sh;
-  basis_body(b, items[blockIdx.x], sh);
+  basis_body<false>(b, items[blockIdx.x], sh);
 }
 
 // The loop expansion and the bond basis in one launch (they are independent:
 // the expansion reads the loop kernel's harmonics, the basis the forward
 // transform's partial sums): blocks below nexp expand, the others transform.
+template <bool ONE>
 __global__ void __launch_bounds__(256)
 k_expand_basis(Batch b, const int4* __restrict__ exp_items, int nexp, const int4* __restrict__ basis_items,
                double* __restrict__ dchi) {
@@ -255,8 +260,8 @@ k_expand_basis(Batch b, const int4* __restrict__ exp_items, int nexp, const int4
     ExpandShared e;
     BasisShared s;
   } sh;
-  if ((int)blockIdx.x < nexp) expand_body(b, exp_items[blockIdx.x], nullptr, dchi, sh.e);
-  else basis_body(b, basis_items[blockIdx.x - nexp], sh.s);
+  if ((int)blockIdx.x < nexp) expand_body<ONE>(b, exp_items[blockIdx.x], nullptr, dchi, sh.e);
+  else basis_body<ONE>(b, basis_items[blockIdx.x - nexp], sh.s);
 }
 
 // Gather and basis change, independent of the transfer momentum.  For
@@ -356,13 +361,13 @@ k_gather_g2(Batch b, const int4* __restrict__ items, const int2* __restrict__ ge
 // as in the forward transform).  LT is the largest of 4, 2, 1 that still gives
 // the launch enough items.  With symmetric states (b.wedge) the rows are the
 // orbit representatives irr[r] only.
-template <int LT>
+template <int LT, bool ONE>
 __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict__ items) {
   constexpr int TL = 16 * LT;
   __shared__ double Es[16][TL + 2];   // [k][l]
   __shared__ double Gs[16][64 + 2];   // [k][col]
   const int4 item = items[blockIdx.x];
-  const int p = item.x;
+  const int p = ONE ? 0 : item.x;   // ONE: a single-point launch
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
   const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
@@ -451,14 +456,14 @@ k_dft_fwd_mix(Batch b, const int4* __restrict__ items, const double* __restrict_
 // together: the block's rows of the pre-split phase table (laid out [l][kEpad],
 // zero beyond Nq, rows padded to a multiple of 64) as hi and lo quads, and its
 // columns of g2, split to hi and lo quads as they are staged.
-template <int LT>
+template <int LT, bool ONE>
 __global__ void __launch_bounds__(256)
 k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
   constexpr int TL = 16 * LT, QR = kEpad / 4;
   __shared__ bf16x4 Eh[TL][QR + 1], El[TL][QR + 1];
   __shared__ bf16x4 Gh[QR][64 + 1], Gl[QR][64 + 1];
   const int4 item = items[blockIdx.x];
-  const int p = item.x;
+  const int p = ONE ? 0 : item.x;   // ONE: a single-point launch
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
   const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
@@ -553,12 +558,12 @@ k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
 // states (b.wedge) the item is (p, representative l, its slot) and the result
 // goes to every member q of the orbit as Y(q)_mn = s_m s_n Y(l)_{pi(m) pi(n)}
 // (the point-group law of the form factors; exact sign copies).
-template <typename R>
+template <typename R, bool ONE>
 __global__ void __launch_bounds__(256)
 k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X, const R* __restrict__ Kall,
            double* __restrict__ out, int mode, int cross, int scale_T) {
   const int4 item = items[blockIdx.x];
-  const int p = item.x;
+  const int p = ONE ? 0 : item.x;   // ONE: a single-point launch
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
   const int nff = d.nff, nff2 = nff * nff, nq = d.nq;
@@ -993,17 +998,30 @@ void launch_gather_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t
   if (r.inv.n > 0) {
     const int4* it = L.inv_items + r.inv.begin;
     const dim3 g(r.inv.n), blk(256);
+    const bool one = L.one_point;
     if (mixed) {
       switch (L.inv_lt) {
-        case 1: hipLaunchKernelGGL(k_dft_inv_mix<1>, g, blk, 0, s, L.b, it); break;
-        case 2: hipLaunchKernelGGL(k_dft_inv_mix<2>, g, blk, 0, s, L.b, it); break;
-        default: hipLaunchKernelGGL(k_dft_inv_mix<4>, g, blk, 0, s, L.b, it); break;
+        case 1: if (one) hipLaunchKernelGGL((k_dft_inv_mix<1, true>), g, blk, 0, s, L.b, it);
+          else hipLaunchKernelGGL((k_dft_inv_mix<1, false>), g, blk, 0, s, L.b, it);
+          break;
+        case 2: if (one) hipLaunchKernelGGL((k_dft_inv_mix<2, true>), g, blk, 0, s, L.b, it);
+          else hipLaunchKernelGGL((k_dft_inv_mix<2, false>), g, blk, 0, s, L.b, it);
+          break;
+        default: if (one) hipLaunchKernelGGL((k_dft_inv_mix<4, true>), g, blk, 0, s, L.b, it);
+          else hipLaunchKernelGGL((k_dft_inv_mix<4, false>), g, blk, 0, s, L.b, it);
+          break;
       }
     } else {
       switch (L.inv_lt) {
-        case 1: hipLaunchKernelGGL(k_dft_inv<1>, g, blk, 0, s, L.b, it); break;
-        case 2: hipLaunchKernelGGL(k_dft_inv<2>, g, blk, 0, s, L.b, it); break;
-        default: hipLaunchKernelGGL(k_dft_inv<4>, g, blk, 0, s, L.b, it); break;
+        case 1: if (one) hipLaunchKernelGGL((k_dft_inv<1, true>), g, blk, 0, s, L.b, it);
+          else hipLaunchKernelGGL((k_dft_inv<1, false>), g, blk, 0, s, L.b, it);
+          break;
+        case 2: if (one) hipLaunchKernelGGL((k_dft_inv<2, true>), g, blk, 0, s, L.b, it);
+          else hipLaunchKernelGGL((k_dft_inv<2, false>), g, blk, 0, s, L.b, it);
+          break;
+        default: if (one) hipLaunchKernelGGL((k_dft_inv<4, true>), g, blk, 0, s, L.b, it);
+          else hipLaunchKernelGGL((k_dft_inv<4, false>), g, blk, 0, s, L.b, it);
+          break;
       }
     }
   }
@@ -1019,8 +1037,12 @@ void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed,
 void launch_expand_basis(const Launch& L, const Ranges& r, double* dchi, bool cross, hipStream_t s) {
   const int nb = cross ? r.basis.n : 0;
   if (r.exp.n + nb <= 0) return;
-  hipLaunchKernelGGL(k_expand_basis, dim3(r.exp.n + nb), dim3(256), 0, s, L.b, L.exp_items + r.exp.begin,
-                     r.exp.n, L.basis_items + r.basis.begin, dchi);
+  if (L.one_point)
+    hipLaunchKernelGGL(k_expand_basis<true>, dim3(r.exp.n + nb), dim3(256), 0, s, L.b, L.exp_items + r.exp.begin,
+                       r.exp.n, L.basis_items + r.basis.begin, dchi);
+  else
+    hipLaunchKernelGGL(k_expand_basis<false>, dim3(r.exp.n + nb), dim3(256), 0, s, L.b, L.exp_items + r.exp.begin,
+                       r.exp.n, L.basis_items + r.basis.begin, dchi);
 }
 
 void launch_back(const Launch& L, const Ranges& r, const double* X, double* out, int mode,
@@ -1029,12 +1051,21 @@ void launch_back(const Launch& L, const Ranges& r, const double* X, double* out,
   auto launch = [&](const ItemRange& ir, size_t smem64) {
     if (ir.n <= 0) return;
     const int4* it = L.prod_items + ir.begin;
-    if (mixed)
-      hipLaunchKernelGGL(k_products<float>, dim3(ir.n), dim3(256), smem64 / 2, s, L.b, it, X,
-                         (const float*)L.b.kinv, out, mode, cross ? 1 : 0, scale_T ? 1 : 0);
+    const int c = cross ? 1 : 0, st = scale_T ? 1 : 0;
+    const float* k32 = (const float*)L.b.kinv;
+    const double* k64 = (const double*)L.b.kinv64;
+    if (mixed && L.one_point)
+      hipLaunchKernelGGL((k_products<float, true>), dim3(ir.n), dim3(256), smem64 / 2, s, L.b, it, X, k32, out,
+                         mode, c, st);
+    else if (mixed)
+      hipLaunchKernelGGL((k_products<float, false>), dim3(ir.n), dim3(256), smem64 / 2, s, L.b, it, X, k32, out,
+                         mode, c, st);
+    else if (L.one_point)
+      hipLaunchKernelGGL((k_products<double, true>), dim3(ir.n), dim3(256), smem64, s, L.b, it, X, k64, out,
+                         mode, c, st);
     else
-      hipLaunchKernelGGL(k_products<double>, dim3(ir.n), dim3(256), smem64, s, L.b, it, X,
-                         (const double*)L.b.kinv64, out, mode, cross ? 1 : 0, scale_T ? 1 : 0);
+      hipLaunchKernelGGL((k_products<double, false>), dim3(ir.n), dim3(256), smem64, s, L.b, it, X, k64, out,
+                         mode, c, st);
   };
   if (r.nprod_cls == 0) {
     launch(r.prod, L.prod_smem);

@@ -210,6 +210,7 @@ struct Launch {
   bool loop_persistent;   // loop kernel: persistent work queue, or one block per item
   size_t loop_smem, prod_smem;
   bool omega = false;     // the scale is the Omega cutoff at T = 0 (temperatures hold Om)
+  bool one_point = false; // the context has one point: kernels take p = 0 without the item's
   bool loop_unroll = false;  // loop kernel: two FP64 rows in flight (when the launch needs no
                              // more blocks per CU than that form's occupancy allows)
 };
