@@ -52,6 +52,22 @@ __device__ __forceinline__ void expand_body(const Batch& b, const int4 item, con
   const int nrow = reps ? d.nirr : nq;   // rows per channel
   const int tid = threadIdx.x;
   {
+    // the coefficient tile first (its loads need the descriptor only), all of
+    // the thread's loads in flight together
+    constexpr int kB = kExpK * kExpCols / 256;
+    double bv[kB];
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      const int e = tid + 256 * i, j = e / kExpCols, mn = c0 + e % kExpCols;
+      bv[i] = (j < nsh && mn < nff2) ? d.ebub[(size_t)j * nff2 + mn] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      const int e = tid + 256 * i;
+      Bs[e / kExpCols][e % kExpCols] = bv[i];
+    }
+  }
+  {
     // the thread's (up to 5) entries of the row tile, the loop slices of each
     // loaded 4 at a time and added in slice order
     constexpr int kPer = (kExpRows * kExpK + 255) / 256;
@@ -91,21 +107,6 @@ __device__ __forceinline__ void expand_body(const Batch& b, const int4 item, con
     for (int s5 = 0; s5 < kPer; ++s5) {
       const int e = tid + 256 * s5;
       if (e < kExpRows * nsh) As[e / nsh][e % nsh] = neg[s5] ? -v[s5] : v[s5];
-    }
-  }
-  {
-    // the coefficient tile, all of the thread's loads in flight together
-    constexpr int kB = kExpK * kExpCols / 256;
-    double bv[kB];
-#pragma unroll
-    for (int i = 0; i < kB; ++i) {
-      const int e = tid + 256 * i, j = e / kExpCols, mn = c0 + e % kExpCols;
-      bv[i] = (j < nsh && mn < nff2) ? d.ebub[(size_t)j * nff2 + mn] : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < kB; ++i) {
-      const int e = tid + 256 * i;
-      Bs[e / kExpCols][e % kExpCols] = bv[i];
     }
   }
   __syncthreads();
