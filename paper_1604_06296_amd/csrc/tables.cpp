@@ -280,7 +280,11 @@ std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric, bo
     };
     t.orb_start.assign((size_t)t.nirr + 1, 0);
     for (int q = 0; q < t.nq; ++q) ++t.orb_start[(size_t)slot_of[rep[q]] + 1];
-    for (int s2 = 0; s2 < t.nirr; ++s2) t.orb_start[(size_t)s2 + 1] += t.orb_start[(size_t)s2];
+    for (int s2 = 0; s2 < t.nirr; ++s2) {
+      if (t.orb_start[(size_t)s2 + 1] > 8)   // an orbit of C4v has at most 8 members
+        return "internal error: orbit larger than the point group";
+      t.orb_start[(size_t)s2 + 1] += t.orb_start[(size_t)s2];
+    }
     t.orb_q.assign((size_t)t.nq, 0);
     t.orb_tr.assign((size_t)t.nq, 0);
     std::vector<int32_t> fill(t.orb_start.begin(), t.orb_start.end() - 1);
