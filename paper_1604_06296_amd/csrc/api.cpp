@@ -798,8 +798,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
         (st = upload(ctx, ephp, &d.ephp, A)) ||
         (st = upload(ctx, t.cshift, &d.cshift, A)) || (st = upload(ctx, qhi, &d.ephq_hi, A)) ||
         (st = upload(ctx, qlo, &d.ephq_lo, A)) || (st = upload(ctx, rhi, &d.ephr_hi, A)) ||
-        (st = upload(ctx, rlo, &d.ephr_lo, A)) || (st = upload(ctx, t.mrow, &d.mrow, A)) ||
-        (st = upload(ctx, t.ment, &d.ment, A)) || (st = upload(ctx, hx, &d.hx, A)) ||
+        (st = upload(ctx, rlo, &d.ephr_lo, A)) || (st = upload(ctx, hx, &d.hx, A)) ||
         (st = upload(ctx, hy, &d.hy, A)) || (st = upload(ctx, t.pairs, &d.pairs, A)) ||
         (st = upload(ctx, t.irr, &d.irr, A)) || (st = upload(ctx, t.symmap, &d.symmap, A)) ||
         (st = upload(ctx, t.tperm, &d.tperm, A)) || (st = upload(ctx, t.orb_start, &d.orb_start, A)) ||

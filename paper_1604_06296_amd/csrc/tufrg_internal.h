@@ -119,8 +119,6 @@ struct DevTables {
   unsigned short* ephq_lo;
   unsigned short* ephr_hi; // inverse transform: [ceil(nq/64)*64][kEpad]
   unsigned short* ephr_lo;
-  int32_t* mrow;
-  int32_t* ment;
   int32_t* hx;            // half set [nsh]
   int32_t* hy;
   int32_t* pairs;         // canonical bond pairs [nsh][4]
