@@ -166,7 +166,8 @@ typedef struct {
                               TUFRG_DOPRI5_LOG: Dormand-Prince 5(4), RMS error norm
                               with atol + rtol*max(|y|,|y_new|), step factor
                               0.9 err^(-1/5) in [0.2, 5], first step h0 (0: (ln Tmin
-                              - ln T0)/200) */
+                              - ln T0)/200; otherwise it must be negative, pointing
+                              from T0 towards Tmin, else EINVAL) */
   int32_t nsteps;
   double rtol, atol, h0;
   int32_t max_steps;       /* DOPRI5 step budget (0: 100000) */
@@ -178,7 +179,10 @@ typedef struct {
                               the first step with max|X| > Xmax. */
 } tufrg_flow_opts;
 
-enum { TUFRG_FLOW_DIVERGED = 1, TUFRG_FLOW_REACHED_TMIN = 2, TUFRG_FLOW_NONFINITE = 3 };
+/* MAX_STEPS: a DOPRI5 flow used up max_steps attempted steps before it
+ * diverged or reached Tmin (the state is the last accepted one). */
+enum { TUFRG_FLOW_DIVERGED = 1, TUFRG_FLOW_REACHED_TMIN = 2, TUFRG_FLOW_NONFINITE = 3,
+       TUFRG_FLOW_MAX_STEPS = 4 };
 
 /* Per-point flow result.  Tc: linear interpolation of ln max|X| in s to
  * ln Xmax between the last two accepted steps (only when DIVERGED).

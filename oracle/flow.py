@@ -13,6 +13,8 @@ symmetry).  Readings used here:
   * adaptive stepping is Dormand-Prince 5(4) with its embedded error
     estimate, RMS error norm with atol + rtol max(|y|,|y_new|), step factor
     0.9 err^(-1/5) clipped to [0.2, 5];
+  * a DOPRI5 flow that uses up its step budget before diverging or reaching
+    Tmin ends with its own status (max steps);
   * divergence: max |X| over channels, momenta and form factors exceeds
     Xmax after an accepted step (a non-finite state also stops the flow);
   * T_c: linear interpolation of ln max|X| in s between the last two
@@ -33,7 +35,7 @@ from .lattice import FormFactors
 from .rhs import rhs
 
 CHANNELS = ("P", "C", "D")
-STATUS_DIVERGED, STATUS_REACHED_TMIN, STATUS_NONFINITE = 1, 2, 3
+STATUS_DIVERGED, STATUS_REACHED_TMIN, STATUS_NONFINITE, STATUS_MAX_STEPS = 1, 2, 3, 4
 
 
 @dataclasses.dataclass
@@ -134,15 +136,43 @@ DP_B5 = [35 / 384, 0.0, 500 / 1113, 125 / 192, -2187 / 6784, 11 / 84, 0.0]
 DP_B4 = [5179 / 57600, 0.0, 7571 / 16695, 393 / 640, -92097 / 339200, 187 / 2100, 1 / 40]
 
 
+def dopri5_step(g: Callable, s: float, X: np.ndarray, h: float, k0: np.ndarray):
+    """One Dormand-Prince 5(4) step of dX/ds = g(s, X) from (s, X) with slope
+    k0 = g(s, X): returns (X5, err_vec, k) with X5 the fifth-order solution,
+    err_vec = X5 - X4 the embedded error estimate (X4 the fourth-order
+    solution) and k the seven stage slopes (k[6] = g(s + h, X5), first same as
+    last)."""
+    k = [None] * 7
+    k[0] = k0
+    for i in range(1, 7):
+        Xi = X.copy()
+        for j, a in enumerate(DP_A[i]):
+            if a != 0.0:
+                Xi = Xi + h * a * k[j]
+        k[i] = g(s + DP_C[i] * h, Xi)
+    X5 = X.copy()
+    for j in range(7):
+        if DP_B5[j] != 0.0:
+            X5 = X5 + h * DP_B5[j] * k[j]
+    err_vec = sum(h * (DP_B5[j] - DP_B4[j]) * k[j] for j in range(7))
+    return X5, err_vec, k
+
+
 def flow_dopri5(point, T0: float, Tmin: float, Xmax: float, rtol: float = 1e-7,
                 atol: float = 1e-9, h0: Optional[float] = None, max_steps: int = 100000,
                 X0: Optional[np.ndarray] = None, no_cross: bool = False,
                 rhs_fn: Optional[Callable] = None, regulator: str = "T") -> FlowResult:
-    """Adaptive Dormand-Prince 5(4) in s = ln T (FSAL), from T0 down to Tmin."""
+    """Adaptive Dormand-Prince 5(4) in s = ln T (FSAL), from T0 down to Tmin.
+
+    A first step h0 must point from T0 towards Tmin (h0 < 0); max_steps bounds
+    the attempted steps, and a flow that uses them up before reaching Tmin or
+    diverging ends with STATUS_MAX_STEPS."""
     ff = FormFactors(point.shells)
     f = rhs_fn or (lambda T, X: rhs(point, T, X, ff, no_cross=no_cross, regulator=regulator))
     X = np.zeros((3, point.Lq ** 2, ff.nff, ff.nff)) if X0 is None else X0.copy()
     s, s_end = math.log(T0), math.log(Tmin)
+    if h0 is not None and not h0 * (s_end - s) > 0.0:
+        raise ValueError("h0 must point from T0 towards Tmin")
     h = h0 if h0 is not None else (s_end - s) / 200.0
 
     def g(sv, Xv):
@@ -150,24 +180,13 @@ def flow_dopri5(point, T0: float, Tmin: float, Xmax: float, rtol: float = 1e-7,
         return T * f(T, Xv)
 
     s_hist, m_hist = [s], [_max_abs(X)]
-    k = [None] * 7
-    k[0] = g(s, X)
+    k0 = g(s, X)
     n_rhs, n_acc = 1, 0
     for _ in range(max_steps):
         if s + h < s_end:
             h = s_end - s
-        for i in range(1, 7):
-            Xi = X.copy()
-            for j, a in enumerate(DP_A[i]):
-                if a != 0.0:
-                    Xi = Xi + h * a * k[j]
-            k[i] = g(s + DP_C[i] * h, Xi)
+        X5, err_vec, k = dopri5_step(g, s, X, h, k0)
         n_rhs += 6
-        X5 = X.copy()
-        for j in range(7):
-            if DP_B5[j] != 0.0:
-                X5 = X5 + h * DP_B5[j] * k[j]
-        err_vec = sum(h * (DP_B5[j] - DP_B4[j]) * k[j] for j in range(7))
         sc = atol + rtol * np.maximum(np.abs(X), np.abs(X5))
         err = float(np.sqrt(np.mean((err_vec / sc) ** 2)))
         if not np.isfinite(err):
@@ -177,7 +196,7 @@ def flow_dopri5(point, T0: float, Tmin: float, Xmax: float, rtol: float = 1e-7,
         if err <= 1.0:
             s = s + h
             X = X5
-            k[0] = k[6]
+            k0 = k[6]
             n_acc += 1
             m = _max_abs(X)
             s_hist.append(s)
@@ -188,4 +207,4 @@ def flow_dopri5(point, T0: float, Tmin: float, Xmax: float, rtol: float = 1e-7,
                 return _finish(STATUS_REACHED_TMIN, s_hist, m_hist, Xmax, X, ff, n_rhs, n_acc)
         fac = 5.0 if err == 0.0 else min(5.0, max(0.2, 0.9 * err ** (-0.2)))
         h = h * fac
-    return _finish(STATUS_REACHED_TMIN, s_hist, m_hist, Xmax, X, ff, n_rhs, n_acc)
+    return _finish(STATUS_MAX_STEPS, s_hist, m_hist, Xmax, X, ff, n_rhs, n_acc)

@@ -11,7 +11,7 @@ CHANNELS = ("P", "C", "D")
 IRREPS = ("A1", "B1", "B2", "A2", "E")
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONFINITE", -5: "EUNSUPPORTED"}
-FLOW_STATUS = {1: "diverged", 2: "reached_tmin", 3: "nonfinite"}
+FLOW_STATUS = {1: "diverged", 2: "reached_tmin", 3: "nonfinite", 4: "max_steps"}
 SCHEMES = {"rk4": 0, "dopri5": 1}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 NO_CROSS = 1

@@ -1392,7 +1392,7 @@ tufrg_status flow_dopri5_point(tufrg_ctx* ctx, int p, const tufrg_flow_opts* o, 
     h *= fac;
   }
   ST_TRY(settle());
-  return finish_point(ctx, p, X, TUFRG_FLOW_REACHED_TMIN, sprev, s, mprev, m, o->Xmax, n_rhs, n_acc, ms, r);
+  return finish_point(ctx, p, X, TUFRG_FLOW_MAX_STEPS, sprev, s, mprev, m, o->Xmax, n_rhs, n_acc, ms, r);
 }
 
 }  // namespace
@@ -1412,6 +1412,8 @@ tufrg_status tufrg_flow(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tuf
     ST_TRY(flow_rk4_all(ctx, o, X, res));
   } else if (o->scheme == TUFRG_DOPRI5_LOG) {
     if (!(o->rtol > 0.0) || !(o->atol > 0.0)) return fail(ctx, TUFRG_EINVAL, "rtol, atol must be > 0");
+    if (!(o->h0 <= 0.0)) return fail(ctx, TUFRG_EINVAL, "h0 must be 0 (default) or negative (towards Tmin)");
+    if (o->max_steps < 0) return fail(ctx, TUFRG_EINVAL, "max_steps must be >= 0");
     for (size_t p = 0; p < ctx->dev.size(); ++p) ST_TRY(flow_dopri5_point(ctx, (int)p, o, X, &res[p]));
   } else {
     return fail(ctx, TUFRG_EINVAL, "unknown scheme");

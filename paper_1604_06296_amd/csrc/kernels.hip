@@ -770,12 +770,14 @@ __device__ __forceinline__ bool seg_range(const Batch& b, const int4& it, size_t
 
 // out = X + h sum_j coef_j k_j; frozen points untouched when skip_frozen.
 // Every thread holds kSeg / 256 elements of the segment and issues all their
-// loads (X and the NK slopes) before the arithmetic.
+// loads (X and the NK slopes) before the arithmetic.  out may be X (the RK4
+// update writes in place: each element is read and written by one thread), so
+// neither carries __restrict__.
 constexpr int kSegPer = kSeg / 256;
 template <int NK>
 __global__ void __launch_bounds__(256)
-k_axpy(Batch b, const int4* __restrict__ items, const double* __restrict__ X, SlopeSet ks, double h,
-       double* __restrict__ out, int skip_frozen) {
+k_axpy(Batch b, const int4* __restrict__ items, const double* X, SlopeSet ks, double h,
+       double* out, int skip_frozen) {
   const int4 it = items[blockIdx.x];
   if (skip_frozen && skip_point(b, it.x)) return;
   size_t base;

@@ -75,12 +75,13 @@ class TrigPropagator:
         ly = np.asarray(ly, dtype=float)
         W = np.array(self.Ws, dtype=float)
         eW = np.exp(-1j * (lx[..., None] * W[:, 0] + ly[..., None] * W[:, 1]))   # [..., nW]
-        XB = np.einsum("...w,wab->...ab", eW, self.Y)
+        nb = self.Y.shape[1]
+        XB = (eW @ self.Y.reshape(len(self.Ws), nb * nb)).reshape(eW.shape[:-1] + (nb, nb))
         gx = 0.5 * (self.B[:, None, 0] + self.B[None, :, 0])
         gy = 0.5 * (self.B[:, None, 1] + self.B[None, :, 1])
         XB = XB * np.exp(1j * (lx[..., None, None] * gx + ly[..., None, None] * gy))
         cc = np.conj(self.ff.c)
-        Xmn = np.einsum("ma,...ab,nb->...mn", cc, XB, cc)
+        Xmn = cc @ XB @ cc.T
         assert np.abs(Xmn.imag).max() < 1e-12 * max(1.0, np.abs(Xmn).max())
         return Xmn.real
 

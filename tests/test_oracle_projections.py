@@ -19,7 +19,8 @@ def _state(ff, Lq, wmax, seed):
 
 
 @pytest.mark.parametrize("shells,Lq,wmax,Lf,nl", [(0, 4, 1, 6, 16), (1, 6, 2, 10, 6),
-                                                   (2, 6, 2, 10, 4), (3, 10, 2, 12, 2)])
+                                                   (2, 6, 2, 10, 4), (3, 10, 2, 12, 2),
+                                                   (4, 10, 2, 12, 2)])
 def test_cross_projections_equal_double_momentum_sums(shells, Lq, wmax, Lf, nl):
     """Each of the six cross projections equals the literal double integral of
     the projection rule applied to the channel decomposition."""

@@ -133,3 +133,74 @@ def test_classify_picks_argmax_and_irrep():
     X[0, 2, 2, 2] = -30.0          # d_x2-y2 pairing (form factor 2, irrep B1)
     X[1, 1, 0, 0] = 10.0
     assert classify(X, ff) == ("P", 2, "B1")
+
+
+def _dopri5_local_errors(hs):
+    """Local errors of one Dormand-Prince step of y' = y cos(s) (exact solution
+    y = exp(sin s - sin s0)) for each step size: fifth-order solution, the
+    fourth-order solution X5 - err, and the embedded estimate itself."""
+    import oracle.flow as oflow
+    s0 = 0.3
+    g = lambda s, y: y * math.cos(s)
+    y0 = np.array([1.0])
+    out = []
+    for h in hs:
+        y5, err, _ = oflow.dopri5_step(g, s0, y0, h, g(s0, y0))
+        exact = math.exp(math.sin(s0 + h) - math.sin(s0))
+        out.append((abs(y5[0] - exact), abs(y5[0] - err[0] - exact), abs(err[0])))
+    return np.array(out)
+
+
+def _orders(errs):
+    return np.log2(errs[:-1] / errs[1:])
+
+
+def test_dopri5_step_orders():
+    """The embedded pair has local errors O(h^6) (fifth-order solution) and
+    O(h^5) (fourth-order solution), so the error estimate scales as h^5."""
+    e = _dopri5_local_errors([0.2, 0.1, 0.05, 0.025])
+    o5, o4, oe = (_orders(e[:, i]) for i in range(3))
+    assert np.all(o5 > 5.6), o5          # -> 6
+    assert np.all(np.abs(o4 - 5.0) < 0.35), o4
+    assert np.all(np.abs(oe - 5.0) < 0.35), oe
+
+
+def test_dopri5_order_pin_catches_a_wrong_weight(monkeypatch):
+    """A planted mistake in one fourth-order weight (the oracle's tableau)
+    breaks the order of the error estimate."""
+    import oracle.flow as oflow
+    bad = list(oflow.DP_B4)
+    bad[3] = 393 / 641
+    monkeypatch.setattr(oflow, "DP_B4", bad)
+    e = _dopri5_local_errors([0.2, 0.1, 0.05, 0.025])
+    assert not np.all(np.abs(_orders(e[:, 2]) - 5.0) < 0.35)
+
+
+def test_dopri5_decoupled_flow_is_rpa_ladder():
+    """The adaptive flow at tight tolerances reproduces the closed-form RPA
+    ladders of the decoupled channels (independently of RK4)."""
+    pt = synth.Point(t=1.0, tp=-0.1, U=2.0, Lq=6, Lk=16, shells=0, mu=-0.2)
+    T0, T1 = 10.0, 0.3
+    r = flow_dopri5(pt, T0, T1, Xmax=1e9, rtol=1e-11, atol=1e-13, no_cross=True)
+    assert r.status == STATUS_REACHED_TMIN
+    P, C, D = r.X[:, :, 0, 0]
+    VP, VC, W = _rpa(pt, T0, T1, 2.0)
+    np.testing.assert_allclose(2.0 - P, VP, rtol=1e-8)
+    np.testing.assert_allclose(2.0 + C, VC, rtol=1e-8)
+    np.testing.assert_allclose(2 * (2.0 + D) - (2.0 + C), W, rtol=1e-8)
+    # the error scales with the tolerance
+    loose = flow_dopri5(pt, T0, T1, Xmax=1e9, rtol=1e-6, atol=1e-8, no_cross=True)
+    e_tight = np.abs(2.0 + C - VC).max()
+    e_loose = np.abs(2.0 + loose.X[1, :, 0, 0] - VC).max()
+    assert e_loose > 10 * e_tight and e_loose < 1e-4
+
+
+def test_dopri5_step_budget_and_step_sign():
+    """A flow that uses up max_steps reports it (not 'reached Tmin'), and a
+    first step pointing away from Tmin is rejected."""
+    import oracle.flow as oflow
+    pt = synth.small_point(Lq=6, Lk=8, shells=0)
+    r = flow_dopri5(pt, 10.0, 0.01, 1e9, max_steps=3)
+    assert r.status == oflow.STATUS_MAX_STEPS and r.n_steps <= 3
+    with pytest.raises(ValueError):
+        flow_dopri5(pt, 10.0, 0.01, 1e9, h0=0.1)
