@@ -140,29 +140,72 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(point, seconds):
-    """The FP64 CPU oracle, untuned, on a bounded sample of the same workload."""
-    import synth
+def _cpu_chunk(args):
+    """One worker's share of an oracle right-hand side: the momenta of one chunk."""
+    point, T, X, q_index = args
     from oracle.lattice import FormFactors
     from oracle.rhs import rhs as oracle_rhs
+    return oracle_rhs(point, T, X, FormFactors(point.shells), q_index=q_index)
+
+
+def _cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = 1
-    ff = FormFactors(point.shells)
-    X = synth.random_channels(point.nq, ff.nff, seed=7, scale=1.0)
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(point, seconds):
+    """The FP64 CPU oracle, untuned, on a bounded sample of the same workload.
+
+    The oracle's right-hand side is evaluated per transfer momentum (its
+    q_index argument), so one right-hand side is split into one chunk of
+    momenta per worker process (one process per core this process may run
+    on, BLAS limited to one thread each) and the chunks are put back
+    together in order.  Runs before the GPU is touched: the workers are
+    fresh interpreters started by the spawn method."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import synth
+    from oracle.lattice import mu_from_filling
+    if point.mu is None:
+        point.mu = mu_from_filling(point.filling, point.t, point.tp, point.mu_T, point.mu_L)
+    cores = len(os.sched_getaffinity(0))
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    X = synth.random_channels(point.nq, point.nff, seed=7, scale=1.0)
+    chunks = [c for c in np.array_split(np.arange(point.nq), cores) if c.size]
     Ts = [0.5, 0.05, 0.01, 0.2]
-    n, t0 = 0, time.perf_counter()
-    while True:
-        oracle_rhs(point, Ts[n % len(Ts)], X, ff)
-        n += 1
-        el = time.perf_counter() - t0
-        log(f"[cpu] oracle rhs {n} done, {el:.1f} s")
-        if el >= seconds or n >= 50:
-            break
-    return {"value": n / el, "unit": "RHS evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} full right-hand sides of the same workload (oracle, FP64, numpy)"}
+    try:
+        with mp.get_context("spawn").Pool(processes=len(chunks)) as pool:
+            pool.map(_cpu_chunk, [(point, Ts[0], X, c) for c in chunks[:1]])   # start-up of every worker
+            n, t0 = 0, time.perf_counter()
+            while True:
+                parts = pool.map(_cpu_chunk, [(point, Ts[n % len(Ts)], X, c) for c in chunks])
+                dX = np.concatenate(parts, axis=1)
+                assert dX.shape == X.shape
+                n += 1
+                el = time.perf_counter() - t0
+                log(f"[cpu] oracle rhs {n} done, {el:.1f} s")
+                if el >= seconds or n >= 200:
+                    break
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return {"value": n / el, "unit": "RHS evals/s", "cores": len(chunks), "kind": "oracle",
+            "cpu_model": _cpu_model(), "cores_available": cores, "blas_threads_per_worker": 1,
+            "sample": f"{n} full right-hand sides of the same workload (oracle, FP64, numpy), each split "
+                      f"over {len(chunks)} worker processes by transfer momentum"}
 
 
 def _sync():
@@ -421,11 +464,18 @@ def main():
               "(the right-hand side would shard over transfer momenta; see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+    import synth
+
+    # the oracle's baseline first, before the native library is loaded or
+    # anything touches the GPU (its workers are fresh interpreters); the
+    # oracle solves the workload's mu(n) itself
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(synth.cfg2().points[0], args.cpu_seconds)
+
     import torch
 
     import paper_1604_06296_amd as tf
-    import synth
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = synth.cfg2()
     pt = w.points[0]
@@ -480,10 +530,6 @@ def main():
             log(f"[bench] leg {name}")
             legs[name] = fn()
             torch.cuda.empty_cache()
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(pt, args.cpu_seconds)
 
     line = {
         "metric": METRIC,
