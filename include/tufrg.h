@@ -234,6 +234,19 @@ tufrg_status tufrg_project(tufrg_ctx* ctx, const double* X, double* V);
  * T_host[p] (eqns. matmul-P/C/D).  X, dXdT: device pointers (no alias). */
 tufrg_status tufrg_rhs(tufrg_ctx* ctx, const double* T_host, const double* X, double* dXdT);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * right-hand side as tufrg_rhs (same kernels, same bits), with its
+ * workspace (loops, transforms, bond basis, loop harmonics) in a 32 MiB
+ * static device array of the library instead of the context's workspace.
+ * The call allocates nothing.  EINVAL when the context's workspace exceeds
+ * 32 MiB (the message gives the size: at N_ff = 13 on 24x24 it is about
+ * 6 MB); EUNSUPPORTED with a surrogate attached.  The array is shared by
+ * every context on a device and holds the last call's workspace: calls that
+ * overlap on one device (other streams, other host threads) race.  Nothing in
+ * it needs to start at zero. */
+tufrg_status tufrg_rhs_noalloc(tufrg_ctx* ctx, const double* T_host, const double* X, double* dXdT);
+
 /* Integrate the flow for every point; X (device, [3][S]) holds X(T0) on
  * entry and the state at the stop on return.  res: host array [npts].
  * Synchronises the stream.  Returns ENONFINITE if any point's state became

@@ -25,7 +25,7 @@ REGULATORS = {"T": 0, "omega": OMEGA_CUTOFF}
 
 # every entry point declared in include/tufrg.h
 EXPORTS = ("tufrg_init", "tufrg_layout", "tufrg_geometry", "tufrg_bubbles", "tufrg_project",
-           "tufrg_rhs", "tufrg_flow", "tufrg_sync", "tufrg_flop_count", "tufrg_loop_kernel_time",
+           "tufrg_rhs", "tufrg_rhs_noalloc", "tufrg_flow", "tufrg_sync", "tufrg_flop_count", "tufrg_loop_kernel_time",
            "tufrg_mu_from_filling",
            "tufrg_harmonics", "tufrg_loop_harmonics", "tufrg_surrogate_dataset",
            "tufrg_surrogate_attach", "tufrg_surrogate_stats",
@@ -87,6 +87,7 @@ def load_library():
     lib.tufrg_bubbles.argtypes = [vp, dp, vp]
     lib.tufrg_project.argtypes = [vp, vp, vp]
     lib.tufrg_rhs.argtypes = [vp, dp, vp, vp]
+    lib.tufrg_rhs_noalloc.argtypes = [vp, dp, vp, vp]
     lib.tufrg_flow.argtypes = [vp, C.POINTER(_FlowOpts), vp, C.POINTER(_FlowResult)]
     lib.tufrg_sync.argtypes = [vp]
     lib.tufrg_flop_count.argtypes = [vp, dp]
@@ -346,6 +347,12 @@ class Context:
         out = self.empty(3) if out is None else out
         _check(self.lib, self.ctx, self.lib.tufrg_rhs(self.ctx, self._T(T), self._dev(X, 3),
                                                       self._dev(out, 3)))
+        return out
+
+    def rhs_noalloc(self, T, X, out):
+        """tufrg_rhs_noalloc: the right-hand side with the library's static workspace."""
+        _check(self.lib, self.ctx, self.lib.tufrg_rhs_noalloc(self.ctx, self._T(T), self._dev(X, 3),
+                                                              self._dev(out, 3)))
         return out
 
     def sync(self):

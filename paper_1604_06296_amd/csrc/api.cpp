@@ -11,6 +11,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -18,6 +19,14 @@
 #include "tufrg_internal.h"
 
 using namespace tufrg;
+
+// Static device scratch of the allocation-free right-hand side
+// (tufrg_rhs_noalloc): its workspace lives here instead of in the context's
+// allocations.  Each device the library runs on holds its own copy until the
+// process ends.  In host code `scratch` only names the symbol: its device
+// address on the current device comes from hipGetSymbolAddress.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
 
 namespace {
 
@@ -83,6 +92,25 @@ void split_table(const std::vector<double>& x, std::vector<unsigned short>& hi,
     hi[i] = bf16_bits(f);
     lo[i] = bf16_bits(f - bf16_value(hi[i]));
   }
+}
+
+// Device address of `scratch` on device dev (the current device), resolved
+// once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+hipError_t resolve_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 double word_to_double(unsigned long long w) {
@@ -751,6 +779,18 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     delete ctx;
     return fail(nullptr, TUFRG_EHIP, "no HIP device");
   }
+  ctx->ws_total_xp = ws_xp;
+  ctx->ws_total_yb = ws_yb;
+  ctx->ws_total_g2 = ws_g2;
+  ctx->ws_total_k = ws_k;
+  {
+    // the static scratch of this device (used by tufrg_rhs_noalloc only)
+    const hipError_t e = resolve_scratch(ctx->device, &ctx->scratch);
+    if (e != hipSuccess) {
+      delete ctx;
+      return fail(nullptr, TUFRG_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+  }
   auto bad = [&](tufrg_status st) {
     std::string m = ctx->err;
     tufrg_free(ctx);
@@ -894,6 +934,48 @@ tufrg_status tufrg_rhs(tufrg_ctx* ctx, const double* T_host, const double* X, do
   ST_TRY(check_temperatures(ctx, T_host));
   rhs_launch(ctx, ctx->L, ctx->all, X, dXdT, false, ctx->stream,
              TSource{T_host, 0, (int)ctx->dev.size(), 0});
+  HIP_TRY(ctx, hipGetLastError());
+  return TUFRG_OK;
+}
+
+tufrg_status tufrg_rhs_noalloc(tufrg_ctx* ctx, const double* T_host, const double* X, double* dXdT) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  if (!T_host || !X || !dXdT) return fail(ctx, TUFRG_EINVAL, "NULL argument");
+  if (X == dXdT) return fail(ctx, TUFRG_EINVAL, "X and dXdT must not alias");
+  if (ctx->sur_a) return fail(ctx, TUFRG_EUNSUPPORTED, "the allocation-free right-hand side has no surrogate path");
+  if (!ctx->scratch) return fail(ctx, TUFRG_EHIP, "static scratch not resolved on this device");
+  ST_TRY(check_temperatures(ctx, T_host));
+  // workspace regions inside the static scratch (doubles, 256-byte aligned):
+  // loops, forward-transform splits, bond basis, inverse-transform
+  // coefficients, inverse transforms (FP32 in mixed precision), loop harmonics
+  auto up = [](int64_t n) { return (n + 31) / 32 * 32; };
+  const bool mixed = mixed_of(ctx);
+  const int64_t n_k = mixed ? (ctx->ws_total_k + 1) / 2 : ctx->ws_total_k;
+  const int64_t parts[6] = {2 * ctx->S, ctx->ws_total_xp, ctx->ws_total_yb, ctx->ws_total_g2, n_k, ctx->ghat_len};
+  int64_t off[6], need = 0;
+  for (int i = 0; i < 6; ++i) {
+    off[i] = need;
+    need += up(std::max<int64_t>(parts[i], 1));
+  }
+  const int64_t cap = (int64_t)(kScratchBytes / sizeof(double));
+  if (need > cap)
+    return fail(ctx, TUFRG_EINVAL, "workspace of " + std::to_string(need * 8) + " bytes exceeds the " +
+                                       std::to_string(kScratchBytes) + "-byte static scratch");
+  double* base = static_cast<double*>(ctx->scratch);
+  Launch L = ctx->L;
+  L.b.dchi = base + off[0];
+  L.b.xp = base + off[1];
+  L.b.yb = base + off[2];
+  L.b.g2 = base + off[3];
+  if (mixed) {
+    L.b.kinv = reinterpret_cast<float*>(base + off[4]);
+    L.b.kinv64 = nullptr;
+  } else {
+    L.b.kinv = nullptr;
+    L.b.kinv64 = base + off[4];
+  }
+  L.b.ghat = base + off[5];
+  rhs_launch(ctx, L, ctx->all, X, dXdT, false, ctx->stream, TSource{T_host, 0, (int)ctx->dev.size(), 0});
   HIP_TRY(ctx, hipGetLastError());
   return TUFRG_OK;
 }

@@ -317,4 +317,7 @@ struct tufrg_ctx {
   std::vector<void*> geometry_allocations; // item tables and slices; rebuilt by the autotuner
   std::string err;
   int device = 0;
+  // workspace totals (elements) of the step calls, for the no-allocation entry point
+  int64_t ws_total_xp = 0, ws_total_yb = 0, ws_total_g2 = 0, ws_total_k = 0;
+  void* scratch = nullptr;                 // device address of the static scratch on ctx->device
 };
