@@ -135,9 +135,11 @@ enum {
                                copied to the rest of the orbit with that law:
                                every member is an exact signed copy of its
                                representative.  For a state that is not
-                               symmetric the results are its representatives'
-                               increments copied by the law (no error is
-                               raised). */
+                               symmetric the step calls return its
+                               representatives' increments copied by the law:
+                               validate states with tufrg_symmetry_defect;
+                               tufrg_flow checks its initial state and returns
+                               EINVAL when its relative defect exceeds 1e-12. */
   TUFRG_NO_FUSE = 1u << 4  /* never run the right-hand side in fused launches.  By
                                default a context whose channel state (sum of
                                Nq Nff^2 over its points) is at most 2^18 runs the
@@ -254,6 +256,14 @@ tufrg_status tufrg_rhs_noalloc(tufrg_ctx* ctx, const double* T_host, const doubl
  * not an error. */
 tufrg_status tufrg_flow(tufrg_ctx* ctx, const tufrg_flow_opts* opts, double* X,
                         tufrg_flow_result* res);
+
+/* Largest relative deviation of X (device, [3][S]) from the C4v covariance
+ * law of TUFRG_SYMMETRIC_STATE (Sec. 3, the lattice symmetries):
+ * *rel = max over points of max|X(q)_mn - s_m s_n X(r)_{pi(m) pi(n)}| / max|X|,
+ * the maximum over channels, orbit members q of their representative r and
+ * (m, n); 0 for X = 0, NaN for a non-finite state.  A state with *rel below
+ * about 1e-12 is symmetric up to rounding.  Synchronises the stream. */
+tufrg_status tufrg_symmetry_defect(tufrg_ctx* ctx, const double* X, double* rel);
 
 /* Wait for all work issued on the context's stream; reports kernel faults. */
 tufrg_status tufrg_sync(tufrg_ctx* ctx);

@@ -25,7 +25,7 @@ REGULATORS = {"T": 0, "omega": OMEGA_CUTOFF}
 
 # every entry point declared in include/tufrg.h
 EXPORTS = ("tufrg_init", "tufrg_layout", "tufrg_geometry", "tufrg_bubbles", "tufrg_project",
-           "tufrg_rhs", "tufrg_rhs_noalloc", "tufrg_flow", "tufrg_sync", "tufrg_flop_count", "tufrg_loop_kernel_time",
+           "tufrg_rhs", "tufrg_rhs_noalloc", "tufrg_flow", "tufrg_symmetry_defect", "tufrg_sync", "tufrg_flop_count", "tufrg_loop_kernel_time",
            "tufrg_mu_from_filling",
            "tufrg_harmonics", "tufrg_loop_harmonics", "tufrg_surrogate_dataset",
            "tufrg_surrogate_attach", "tufrg_surrogate_stats",
@@ -90,6 +90,7 @@ def load_library():
     lib.tufrg_rhs_noalloc.argtypes = [vp, dp, vp, vp]
     lib.tufrg_flow.argtypes = [vp, C.POINTER(_FlowOpts), vp, C.POINTER(_FlowResult)]
     lib.tufrg_sync.argtypes = [vp]
+    lib.tufrg_symmetry_defect.argtypes = [vp, vp, dp]
     lib.tufrg_flop_count.argtypes = [vp, dp]
     lib.tufrg_loop_kernel_time.argtypes = [vp, dp, i32, dp, dp]
     lib.tufrg_mu_from_filling.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, i32, dp]
@@ -357,6 +358,12 @@ class Context:
 
     def sync(self):
         _check(self.lib, self.ctx, self.lib.tufrg_sync(self.ctx))
+
+    def symmetry_defect(self, X) -> float:
+        """Largest relative deviation of X from the C4v covariance law."""
+        out = C.c_double()
+        _check(self.lib, self.ctx, self.lib.tufrg_symmetry_defect(self.ctx, self._dev(X, 3), C.byref(out)))
+        return out.value
 
     def flop_count(self):
         out = (C.c_double * 3)()

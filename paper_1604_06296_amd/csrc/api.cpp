@@ -113,6 +113,8 @@ hipError_t resolve_scratch(int dev, void** out) {
   return hipSuccess;
 }
 
+constexpr double kSymmetryTol = 1e-12;   // relative covariance defect accepted as symmetric
+
 double word_to_double(unsigned long long w) {
   double d;
   std::memcpy(&d, &w, sizeof d);
@@ -444,6 +446,31 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   return TUFRG_OK;
 }
 
+// Largest relative deviation of X from the C4v covariance law over the
+// points (max|X(q) - T X(r) T^T| / max|X| per point; 0 for X = 0).
+// Synchronises the stream.
+tufrg_status symmetry_defect(tufrg_ctx* ctx, const double* X, double* rel) {
+  const int npts = (int)ctx->dev.size();
+  launch_fill_u64(ctx->sym_words, npts, 0ull, ctx->stream);
+  launch_fill_u64(ctx->umax, npts, 0ull, ctx->stream);
+  launch_sym_defect(ctx->L, ctx->sym_items, ctx->n_sym_items, X, ctx->sym_words, ctx->stream);
+  launch_maxabs(ctx->L, ctx->all.seg, X, ctx->umax, ctx->stream);
+  std::vector<unsigned long long> dw(npts), mw(npts);
+  HIP_TRY(ctx, hipMemcpyAsync(dw.data(), ctx->sym_words, sizeof(unsigned long long) * npts, hipMemcpyDeviceToHost,
+                              ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(mw.data(), ctx->umax, sizeof(unsigned long long) * npts, hipMemcpyDeviceToHost,
+                              ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  double worst = 0.0;
+  for (int p = 0; p < npts; ++p) {
+    const double dv = word_to_double(dw[p]), mv = word_to_double(mw[p]);
+    const double r = (dv == 0.0) ? 0.0 : dv / mv;
+    if (!(r <= worst)) worst = r;   // NaN propagates
+  }
+  *rel = worst;
+  return TUFRG_OK;
+}
+
 // ------------------------------------------------------------ RHS driver
 // One right-hand side over the item ranges r on stream ms: out = dX/dT, or
 // T dX/dT (= dX/ds) when scale_T.  The loops depend on T only and run on the
@@ -483,15 +510,21 @@ void loops_launch(tufrg_ctx* ctx, const Launch& L, const Ranges& r, double* dchi
 // The temperatures of one right-hand side: host values for points p0 .. p0+n-1,
 // or (host == nullptr) the RK4 stage temperature Ttab[4 step + stage] of every
 // point, read on the device.
+// With sh set: T = exp(s[p] + c h[p]) of the adaptive flow's device state
+// (stage c of every point's current step).
 struct TSource {
   const double* host;
   int p0, n;
   int stage;
+  const double* s = nullptr;
+  const double* h = nullptr;
+  double c = 0.0;
 };
 
 // Stores the temperatures into the per-point array on stream s.
 void set_T_launch(tufrg_ctx* ctx, const TSource& ts, hipStream_t s) {
   if (ts.host) launch_set_T_values(ctx->Tp + ts.p0, ts.host, ts.n, s);
+  else if (ts.s) launch_set_T_sh(ctx->Tp, (int)ctx->dev.size(), ts.s, ts.h, ts.c, s);
   else launch_set_T(ctx->Tp, (int)ctx->dev.size(), ctx->Ttab, ctx->step, ts.stage, s);
 }
 
@@ -523,6 +556,11 @@ void rhs_launch(tufrg_ctx* ctx, const Launch& L0, const Ranges& r0, const double
       ta.p0 = ts.p0;
       ta.n = ts.n;
       for (int i = 0; i < ts.n; ++i) ta.v[i] = ts.host[i];
+    } else if (!ts.host && ts.s) {
+      ta.mode = 3;
+      ta.s = ts.s;
+      ta.h = ts.h;
+      ta.c = ts.c;
     } else if (!ts.host) {
       ta.mode = 2;
       ta.Ttab = ctx->Ttab;
@@ -860,6 +898,14 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   if (!st) st = dalloc(ctx, 2, &ctx->queue, A);
   if (!st) st = dalloc(ctx, (size_t)npts, &ctx->umax, A);
   if (!st) st = dalloc(ctx, 1, &ctx->step, A);
+  if (!st) st = dalloc(ctx, (size_t)npts, &ctx->sym_words, A);
+  if (!st) {
+    std::vector<int2> si;
+    for (int p = 0; p < npts; ++p)
+      for (int sl = 0; sl < ctx->host[p].nirr; ++sl) si.push_back(make_int2(p, sl));
+    ctx->n_sym_items = (int)si.size();
+    st = upload(ctx, si, &ctx->sym_items, A);
+  }
   if (st) return bad(st);
   if (hipHostMalloc((void**)&ctx->umax_host, sizeof(unsigned long long) * npts, 0) != hipSuccess)
     return bad(fail(ctx, TUFRG_ENOMEM, "pinned host allocation failed"));
@@ -1107,6 +1153,12 @@ tufrg_status tufrg_loop_kernel_time(tufrg_ctx* ctx, const double* T_host, int32_
     for (const HostTables& t : ctx->host) *flops += (double)t.flops_loop_kernel;
   }
   return TUFRG_OK;
+}
+
+tufrg_status tufrg_symmetry_defect(tufrg_ctx* ctx, const double* X, double* rel) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  if (!X || !rel) return fail(ctx, TUFRG_EINVAL, "NULL argument");
+  return symmetry_defect(ctx, X, rel);
 }
 
 tufrg_status tufrg_sync(tufrg_ctx* ctx) {
@@ -1376,105 +1428,164 @@ const double kDpB5[7] = {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6
 const double kDpB4[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200,
                          187.0 / 2100, 1.0 / 40};
 
-// dX/ds of point p alone at temperature T
-tufrg_status rhs_point(tufrg_ctx* ctx, int p, double T, const double* X, double* out) {
-  rhs_launch(ctx, ctx->L, ctx->per_point[p], X, out, true, ctx->stream, TSource{&T, p, 1, 0});
-  HIP_TRY(ctx, hipGetLastError());
-  return TUFRG_OK;
-}
-
-tufrg_status maxabs_point(tufrg_ctx* ctx, int p, const double* X, double* result) {
-  launch_fill_u64(ctx->umax + p, 1, 0ull, ctx->stream);
-  launch_maxabs(ctx->L, ctx->per_point[p].seg, X, ctx->umax, ctx->stream);
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->umax_host + p, ctx->umax + p, sizeof(unsigned long long),
-                              hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  *result = word_to_double(ctx->umax_host[p]);
-  return TUFRG_OK;
-}
-
-tufrg_status flow_dopri5_point(tufrg_ctx* ctx, int p, const tufrg_flow_opts* o, double* X,
-                               tufrg_flow_result* r) {
+// The adaptive flow of every point at once, with the step control on the
+// device (Dormand-Prince 5(4) in s = ln T, the rules of the flow options, the
+// oracle's): one attempted step of all points is six stage combinations and
+// right-hand sides, the fifth-order state with the error norm's partial sums
+// and max|y5|, the control kernel (accept or reject, next step, stop) and the
+// acceptance copy (y = y5, k0 = k6).  Each point has its own s and h in device
+// memory; the kernels read them, so the attempt can be captured in a HIP
+// graph and replayed.  A point that has stopped is skipped by every kernel.
+// The host checks the stop flags only between batches of attempts.
+tufrg_status flow_dopri5_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tufrg_flow_result* res) {
+  const int npts = (int)ctx->dev.size();
   double* k[7];
   for (int i = 0; i < 7; ++i) k[i] = ctx->kk[i];
   double* stage = ctx->stage;
   double* y5 = ctx->ytmp;
-  const ItemRange seg = ctx->per_point[p].seg;
-  const HostTables& t = ctx->host[p];
-  const int64_t n = (int64_t)t.nq * t.nff * t.nff;
-  if (ctx->nred < seg.n) {
-    ST_TRY(dalloc(ctx, (size_t)seg.n, &ctx->red, ctx->allocations));
-    if (ctx->red_host) (void)hipHostFree(ctx->red_host);
-    ctx->red_host = nullptr;
-    if (hipHostMalloc((void**)&ctx->red_host, sizeof(double) * seg.n, 0) != hipSuccess)
-      return fail(ctx, TUFRG_ENOMEM, "pinned host buffer for the error norm");
-    ctx->nred = seg.n;
+  const Ranges& r = ctx->all;
+  if (ctx->nred < r.seg.n) {
+    ST_TRY(dalloc(ctx, (size_t)r.seg.n, &ctx->red, ctx->allocations));
+    ctx->nred = r.seg.n;
   }
-  double s = std::log(o->T0);
-  const double s_end = std::log(o->Tmin);
-  double h = (o->h0 != 0.0) ? o->h0 : (s_end - s) / 200.0;
+  if (!ctx->dp_state) {
+    ST_TRY(dalloc(ctx, (size_t)npts, &ctx->dp_state, ctx->allocations));
+    ST_TRY(dalloc(ctx, (size_t)2 * npts, &ctx->dp_sh, ctx->allocations));
+    std::vector<int2> seg(npts);
+    std::vector<double> nel(npts);
+    for (int p = 0; p < npts; ++p) {
+      seg[p] = make_int2(ctx->per_point[p].seg.begin, ctx->per_point[p].seg.n);
+      nel[p] = 3.0 * (double)ctx->host[p].nq * ctx->host[p].nff * ctx->host[p].nff;
+    }
+    ST_TRY(upload(ctx, seg, &ctx->dp_seg, ctx->allocations));
+    ST_TRY(upload(ctx, nel, &ctx->dp_nel, ctx->allocations));
+  }
+  const double s0 = std::log(o->T0), s_end = std::log(o->Tmin);
+  const double h0 = (o->h0 != 0.0) ? o->h0 : (s_end - s0) / 200.0;
   const int max_steps = o->max_steps > 0 ? o->max_steps : 100000;
-  double m, mprev, sprev = s;
-  ST_TRY(maxabs_point(ctx, p, X, &m));
-  mprev = m;
-  ST_TRY(rhs_point(ctx, p, std::exp(s), X, k[0]));
-  int64_t n_rhs = 1, n_acc = 0;
-  const double* red = ctx->red_host;
+  hipStream_t ms = ctx->stream;
+  if (o->use_graph) {
+    ms = ctx->gs;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_gs, ctx->stream));
+    HIP_TRY(ctx, hipStreamWaitEvent(ms, ctx->ev_gs, 0));
+  }
+  // initial state: max|X| of every point, s, h (clipped) and the first slope
+  launch_fill_i32(ctx->frozen, npts, 0, ms);
+  launch_fill_u64(ctx->umax, npts, 0ull, ms);
+  launch_maxabs(ctx->L, r.seg, X, ctx->umax, ms);
+  std::vector<unsigned long long> mw(npts);
+  HIP_TRY(ctx, hipMemcpyAsync(mw.data(), ctx->umax, sizeof(unsigned long long) * npts, hipMemcpyDeviceToHost, ms));
+  launch_fill_u64(ctx->umax, npts, 0ull, ms);
+  HIP_TRY(ctx, hipStreamSynchronize(ms));
+  std::vector<DpState> st0(npts);
+  std::vector<double> sh(2 * (size_t)npts);
+  for (int p = 0; p < npts; ++p) {
+    DpState& q = st0[p];
+    std::memset(&q, 0, sizeof q);
+    q.s = s0;
+    q.h = (s0 + h0 < s_end) ? s_end - s0 : h0;
+    q.s0 = q.s1 = s0;
+    q.m0 = q.m1 = word_to_double(mw[p]);
+    sh[p] = q.s;
+    sh[npts + p] = q.h;
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->dp_state, st0.data(), sizeof(DpState) * npts, hipMemcpyHostToDevice, ms));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->dp_sh, sh.data(), sizeof(double) * 2 * npts, hipMemcpyHostToDevice, ms));
+  double* s_arr = ctx->dp_sh;
+  double* h_arr = ctx->dp_sh + npts;
+  Launch Lf = ctx->L;
+  Lf.b.frozen = ctx->frozen;
+  auto stage_T = [&](double c) {
+    TSource ts{nullptr, 0, 0, 0};
+    ts.s = s_arr;
+    ts.h = h_arr;
+    ts.c = c;
+    return ts;
+  };
+  rhs_launch(ctx, Lf, r, X, k[0], true, ms, stage_T(0.0));
   double e[7];
   for (int j = 0; j < 7; ++j) e[j] = kDpB5[j] - kDpB4[j];
-  const hipStream_t ms = ctx->stream;
-  // the accepted state lives in the caller's X or in the scratch buffer (no
-  // copy per accepted step); it is moved to X once, before returning
-  double* cur = X;
-  double* nxt = y5;
-  auto settle = [&]() -> tufrg_status {
-    if (cur != X)
-      for (int c = 0; c < 3; ++c)
-        HIP_TRY(ctx, hipMemcpyAsync(X + c * ctx->S + ctx->off[p], cur + c * ctx->S + ctx->off[p],
-                                    n * sizeof(double), hipMemcpyDeviceToDevice, ms));
-    return TUFRG_OK;
-  };
-  for (int it = 0; it < max_steps; ++it) {
-    if (s + h < s_end) h = s_end - s;
+  DpControl dc{};
+  dc.st = ctx->dp_state;
+  dc.frozen = ctx->frozen;
+  dc.seg = ctx->dp_seg;
+  dc.n_el = ctx->dp_nel;
+  dc.red = ctx->red;
+  dc.max_words = ctx->umax;
+  dc.s_arr = s_arr;
+  dc.h_arr = h_arr;
+  dc.s_end = s_end;
+  dc.xmax = o->Xmax;
+  dc.max_steps = max_steps;
+  dc.npts = npts;
+  auto attempt = [&]() {
     for (int i = 1; i < 7; ++i) {
-      launch_axpy(ctx->L, seg, cur, k, kDpA[i], i, h, stage, false, ms);
-      ST_TRY(rhs_point(ctx, p, std::exp(s + kDpC[i] * h), stage, k[i]));
+      launch_axpy(Lf, r.seg, X, k, kDpA[i], i, 0.0, stage, true, ms, h_arr);
+      rhs_launch(ctx, Lf, r, stage, k[i], true, ms, stage_T(kDpC[i]));
     }
-    n_rhs += 6;
-    // y5, the error norm's partial sums and max|y5| in one pass, read with one sync
-    launch_fill_u64(ctx->umax + p, 1, 0ull, ms);
-    launch_dp_final(ctx->L, seg, cur, k, kDpB5, e, h, o->rtol, o->atol, nxt, ctx->red, ctx->umax, ms);
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->red_host, ctx->red, sizeof(double) * seg.n, hipMemcpyDeviceToHost, ms));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->umax_host + p, ctx->umax + p, sizeof(unsigned long long),
-                                hipMemcpyDeviceToHost, ms));
-    HIP_TRY(ctx, hipStreamSynchronize(ms));
-    const double m5 = word_to_double(ctx->umax_host[p]);
-    double sum = 0.0;
-    for (int i = 0; i < seg.n; ++i) sum += red[i];
-    const double err = std::sqrt(sum / (3.0 * (double)n));
-    if (!std::isfinite(err)) {
-      ST_TRY(settle());
-      return finish_point(ctx, p, nxt, TUFRG_FLOW_NONFINITE, s, s + h, m, NAN, o->Xmax, n_rhs, n_acc, ms, r);
+    launch_dp_final(Lf, r.seg, X, k, kDpB5, e, 0.0, o->rtol, o->atol, y5, ctx->red, ctx->umax, ms, h_arr);
+    launch_dp_control(dc, ms);
+    launch_dp_accept(Lf, r.seg, ctx->dp_state, y5, k[6], X, k[0], ms);
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  };
+  if (o->use_graph) {
+    HIP_TRY(ctx, hipStreamBeginCapture(ms, hipStreamCaptureModeThreadLocal));
+    attempt();
+    hipError_t ge = hipStreamEndCapture(ms, &graph);
+    if (ge == hipSuccess) ge = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ge != hipSuccess) {
+      cleanup();
+      return fail(ctx, TUFRG_EHIP, std::string("graph capture of the adaptive step: ") + hipGetErrorString(ge));
     }
-    if (err <= 1.0) {
-      sprev = s;
-      mprev = m;
-      s = s + h;
-      std::swap(cur, nxt);
-      std::swap(k[0], k[6]);  // first-same-as-last: the slope at the new state
-      ++n_acc;
-      m = m5;
-      if (m > o->Xmax || s <= s_end + 1e-15) {
-        ST_TRY(settle());
-        return finish_point(ctx, p, X, m > o->Xmax ? TUFRG_FLOW_DIVERGED : TUFRG_FLOW_REACHED_TMIN, sprev, s,
-                            mprev, m, o->Xmax, n_rhs, n_acc, ms, r);
+  }
+  // attempts in batches; the host reads the points' states between batches
+  // (a batch is sized by the remaining distance of the slowest point)
+  std::vector<DpState> stv(npts);
+  int attempted = 0, batch = 4;
+  for (;;) {
+    for (int i = 0; i < batch; ++i) {
+      if (exec) {
+        const hipError_t ge = hipGraphLaunch(exec, ms);
+        if (ge != hipSuccess) {
+          cleanup();
+          return fail(ctx, TUFRG_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(ge));
+        }
+      } else {
+        attempt();
       }
     }
-    const double fac = err == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.9 * std::pow(err, -0.2)));
-    h *= fac;
+    attempted += batch;
+    hipError_t ge = hipMemcpyAsync(stv.data(), ctx->dp_state, sizeof(DpState) * npts, hipMemcpyDeviceToHost, ms);
+    if (ge == hipSuccess) ge = hipStreamSynchronize(ms);
+    if (ge == hipSuccess) ge = hipGetLastError();
+    if (ge != hipSuccess) {
+      cleanup();
+      return fail(ctx, TUFRG_EHIP, std::string("adaptive flow: ") + hipGetErrorString(ge));
+    }
+    bool all_done = true, near = false;
+    double steps_left = 1.0;
+    for (const DpState& q : stv)
+      if (q.status == 0) {
+        all_done = false;
+        steps_left = std::max(steps_left, std::ceil((q.s - s_end) / std::max(std::fabs(q.h), 1e-300)));
+        near = near || q.m1 > 0.25 * o->Xmax;   // close to the stop rule: check after every attempt
+      }
+    if (all_done || attempted > max_steps + 1) break;
+    batch = near ? 1 : (int)std::min(8.0, std::max(1.0, steps_left));
   }
-  ST_TRY(settle());
-  return finish_point(ctx, p, X, TUFRG_FLOW_MAX_STEPS, sprev, s, mprev, m, o->Xmax, n_rhs, n_acc, ms, r);
+  cleanup();
+  for (int p = 0; p < npts; ++p) {
+    const DpState& q = stv[p];
+    const int status = q.status != 0 ? q.status : TUFRG_FLOW_MAX_STEPS;
+    ST_TRY(finish_point(ctx, p, X, status, q.s0, q.s1, q.m0, q.m1, o->Xmax, 1 + 6 * (int64_t)q.n_att, q.n_acc,
+                        ms, &res[p]));
+  }
+  return TUFRG_OK;
 }
 
 }  // namespace
@@ -1488,6 +1599,13 @@ tufrg_status tufrg_flow(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tuf
     return fail(ctx, TUFRG_EINVAL, "need T0 > Tmin > 0 and Xmax > 0");
   if (o->scheme != TUFRG_RK4_LOG && o->scheme != TUFRG_DOPRI5_LOG)
     return fail(ctx, TUFRG_EINVAL, "unknown scheme");
+  if (ctx->opt.flags & TUFRG_SYMMETRIC_STATE) {
+    double rel = 0.0;
+    ST_TRY(symmetry_defect(ctx, X, &rel));
+    if (!(rel <= kSymmetryTol))
+      return fail(ctx, TUFRG_EINVAL, "initial state is not C4v-symmetric (relative defect " + std::to_string(rel) +
+                                         "); symmetric-state contexts need symmetric states");
+  }
   ST_TRY(ensure_flow_buffers(ctx));
   if (o->scheme == TUFRG_RK4_LOG) {
     if (o->nsteps <= 0) return fail(ctx, TUFRG_EINVAL, "nsteps must be > 0");
@@ -1496,7 +1614,7 @@ tufrg_status tufrg_flow(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tuf
     if (!(o->rtol > 0.0) || !(o->atol > 0.0)) return fail(ctx, TUFRG_EINVAL, "rtol, atol must be > 0");
     if (!(o->h0 <= 0.0)) return fail(ctx, TUFRG_EINVAL, "h0 must be 0 (default) or negative (towards Tmin)");
     if (o->max_steps < 0) return fail(ctx, TUFRG_EINVAL, "max_steps must be >= 0");
-    for (size_t p = 0; p < ctx->dev.size(); ++p) ST_TRY(flow_dopri5_point(ctx, (int)p, o, X, &res[p]));
+    ST_TRY(flow_dopri5_all(ctx, o, X, res));
   } else {
     return fail(ctx, TUFRG_EINVAL, "unknown scheme");
   }

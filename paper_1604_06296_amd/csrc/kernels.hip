@@ -13,15 +13,12 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "proj_bodies.h"
 #include "transforms.h"
 #include "tufrg_internal.h"
 
 namespace tufrg {
 namespace {
-
-__device__ __forceinline__ bool skip_point(const Batch& b, int p) {
-  return b.frozen != nullptr && b.frozen[p] != 0;
-}
 
 // chi'_mn(q) = sum_j Ebub_{mn,j} ghat(q, S_j) for every momentum, with
 // ghat(q, S_j) = sign ghat(r, S_j') of its representative (pack_sym entry of
@@ -153,97 +150,6 @@ k_dft_fwd_part(Batch b, const int4* __restrict__ items, const double* __restrict
   fwd_part_body<KT>(b, b.pts[item.x], item, X, smem_fwd);
 }
 
-// Bond basis of the transformed propagators, for every harmonic of the full
-// list v (+S'_j for v < nsh, -S'_{v-nsh+1} otherwise):
-//   yb[in][v][b1 b2] = sum_{m' in shell(b1), n' in shell(b2)} c_{m'b1} c_{n'b2} xt^{in}_{m'n'}(v)
-// with xt(-S') = conj(xt(S')).  These are the bond-space Fourier coefficients
-// Yhat_{R1R2}(W) of the propagators at frequency 2W - R1 - R2 = v.
-// Item (p, in * nv + v): the harmonic's transform and the coefficients are
-// staged in LDS; threads own bond pairs (b1, b2).  The transform is the
-// in-order FP64 sum of the forward-transform splits (xp), taken here.
-struct alignas(16) BasisShared {
-  double cs[2 * 441];
-  double xs[2 * 441];
-};
-template <bool ONE>
-__device__ __forceinline__ void basis_body(const Batch& b, const int4 item, BasisShared& sh) {
-  const int p = ONE ? 0 : item.x;
-  if (skip_point(b, p)) return;
-  const DevTables& d = b.pts[p];
-  const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol, nv = 2 * nsh - 1;
-  const int total = 3 * nv * nff2;
-  const int in = item.y / nv, v = item.y % nv;
-  const int j = v < nsh ? v : v - nsh + 1;
-  const double sim = v < nsh ? 1.0 : -1.0;
-  double* cs = sh.cs;
-  double* xs = sh.xs;
-  {
-    // 2 nff^2 sums of nsu terms; each thread keeps up to 4 sums and 8 splits
-    // of each in flight, then adds them in split order
-    const int N = 3 * nff2, nel = 2 * nff2;
-    const size_t sstride = (size_t)ncol * N;
-    const double* base = b.xp + d.ws_xp + (size_t)in * nff2;
-    const double inv = 1.0 / (double)d.nq;
-    for (int e0 = threadIdx.x; e0 < nel; e0 += 4 * 256) {
-      const double* src[4];
-      bool ok[4];
-      double acc[4];
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        const int e = e0 + 256 * s4;
-        const bool im = e >= nff2;
-        ok[s4] = e < nel && (!im || j > 0);
-        src[s4] = base + (size_t)(im ? nsh - 1 + j : j) * N + (im ? e - nff2 : e);
-        acc[s4] = 0.0;
-      }
-      for (int sp0 = 0; sp0 < d.nsu; sp0 += 8) {
-        double v[4][8];
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            v[s4][u] = (ok[s4] && sp0 + u < d.nsu) ? src[s4][(size_t)(sp0 + u) * sstride] : 0.0;
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-          for (int u = 0; u < 8; ++u) acc[s4] += v[s4][u];
-      }
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        const int e = e0 + 256 * s4;
-        if (e < nel) xs[e] = (e < nff2 ? 1.0 : sim) * acc[s4] * inv;
-      }
-    }
-  }
-  for (int i = threadIdx.x; i < nff2; i += blockDim.x) {
-    cs[i] = d.cre[i];
-    cs[nff2 + i] = d.cim[i];
-  }
-  __syncthreads();
-  double* yb = b.yb + d.ws_yb;
-  for (int bb = threadIdx.x; bb < nff2; bb += blockDim.x) {
-    const int b1 = bb / nff, b2 = bb % nff;
-    const int s1 = d.shell_of[b1], s2 = d.shell_of[b2];
-    const int m0 = d.shell_start[s1], m1 = d.shell_start[s1 + 1];
-    const int n0 = d.shell_start[s2], n1 = d.shell_start[s2 + 1];
-    double yr = 0.0, yi = 0.0;
-    for (int mp = m0; mp < m1; ++mp) {
-      const double c1r = cs[mp * nff + b1], c1i = cs[nff2 + mp * nff + b1];
-#pragma unroll 4
-      for (int np = n0; np < n1; ++np) {
-        const double c2r = cs[np * nff + b2], c2i = cs[nff2 + np * nff + b2];
-        const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
-        const double ar = xs[mp * nff + np], ai = xs[nff2 + mp * nff + np];
-        yr = fma(wr, ar, fma(-wi, ai, yr));
-        yi = fma(wr, ai, fma(wi, ar, yi));
-      }
-    }
-    const size_t idx = ((size_t)in * nv + v) * nff2 + bb;
-    yb[idx] = yr;
-    yb[(size_t)total + idx] = yi;
-  }
-}
-
 __global__ void __launch_bounds__(256)
 k_bond_basis(Batch b, const int4* __restrict__ items) {
   __shared__ BasisShared sh;
@@ -265,94 +171,14 @@ k_expand_basis(Batch b, const int4* __restrict__ exp_items, int nexp, const int4
   else basis_body<ONE>(b, basis_items[blockIdx.x - nexp], sh.s);
 }
 
-// Gather and basis change, independent of the transfer momentum.  For
-// V = +S'_j and V = -S'_j:
-//   M^X_AB(V) = sum_entries (+-) yb^{in}_{b1 b2}(v)          (eqn. proj_pos in bonds)
-//   N^X(V) = C M^X(V) C^T                                  (back to form factors)
-// and the real coefficients of cos(l.V/2), sin(l.V/2) for the inverse transform:
-//   Re[e^{-il.V/2} N(V) + e^{+il.V/2} N(-V)] = cos (ReN+ + ReN-) + sin (ImN+ - ImN-).
-// C is block diagonal over shells, so the item is (p, half-set harmonic j,
-// (X, shell of m, shell of n)): one wave gathers the shell block of M (at
-// most kShellMax^2 bond pairs per harmonic) into LDS and transforms it.  The
-// item packs j, X and both shells' start and size (y) and the index of its
-// rows' entries (w: cap per row, absolute yb offsets of the real and
-// imaginary parts, a negative imaginary offset for a negated entry, a
-// negative real offset for padding), so that the yb loads wait for two loads
-// only; the entries of a row are added in the order of the entry lists.
 __global__ void __launch_bounds__(64)
 k_gather_g2(Batch b, const int4* __restrict__ items, const int2* __restrict__ gent, int cap) {
-  __shared__ double Mre[2][kShellMax * kShellMax];
-  __shared__ double Mim[2][kShellMax * kShellMax];
-  __shared__ double C1[2][kShellMax * kShellMax];   // c_{m a}, m and a in shell sm (re, im)
-  __shared__ double C2[2][kShellMax * kShellMax];   // c_{n b}, n and b in shell sn
+  __shared__ GatherShared sh;
   const int4 item = items[blockIdx.x];
-  const int p = item.x;
-  const int j = item.y & 0xff, X = (item.y >> 8) & 3, na = (item.y >> 10) & 15, nb = (item.y >> 14) & 15;
-  const int a0 = (item.y >> 18) & 31, b0 = (item.y >> 23) & 31;
-  const int nab = na * nb, nvl = j == 0 ? 1 : 2;
-  if (skip_point(b, p)) return;
-  // the rows' entries and their yb values first: they depend on the item only
-  for (int w = threadIdx.x; w < nvl * nab; w += 64) {
-    const int2* en = gent + item.w + (size_t)w * cap;
-    double re = 0.0, im = 0.0;
-    for (int e = 0; e < cap; e += 4) {
-      int2 pk[4];
-      double yr[4], yi[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) pk[u] = e + u < cap ? en[e + u] : make_int2(-1, 0);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        yr[u] = yi[u] = 0.0;
-        if (pk[u].x >= 0) {
-          yr[u] = b.yb[pk[u].x];
-          yi[u] = b.yb[pk[u].y >= 0 ? pk[u].y : -pk[u].y - 1];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (pk[u].x < 0) continue;
-        if (pk[u].y < 0) { re -= yr[u]; im -= yi[u]; } else { re += yr[u]; im += yi[u]; }
-      }
-    }
-    Mre[w / nab][w % nab] = re;
-    Mim[w / nab][w % nab] = im;
-  }
-  const DevTables& d = b.pts[p];
-  const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol;
-  if ((int)threadIdx.x < na * na) {
-    const int i = threadIdx.x, c = (a0 + i / na) * nff + a0 + i % na;
-    C1[0][i] = d.cre[c];
-    C1[1][i] = d.cim[c];
-  }
-  if ((int)threadIdx.x < nb * nb) {
-    const int i = threadIdx.x, c = (b0 + i / nb) * nff + b0 + i % nb;
-    C2[0][i] = d.cre[c];
-    C2[1][i] = d.cim[c];
-  }
+  if (skip_point(b, item.x)) return;
+  gather_load(b, item, gent, cap, threadIdx.x, sh);
   __syncthreads();
-  double* g2 = b.g2 + d.ws_g2;
-  for (int w = threadIdx.x; w < nab; w += 64) {
-    const int m = a0 + w / nb, n = b0 + w % nb, mn = m * nff + n;
-    double nr[2] = {0.0, 0.0}, ni[2] = {0.0, 0.0};
-    for (int a = 0; a < na; ++a) {
-      const double c1r = C1[0][(m - a0) * na + a], c1i = C1[1][(m - a0) * na + a];
-      for (int bb = 0; bb < nb; ++bb) {
-        const double c2r = C2[0][(n - b0) * nb + bb], c2i = C2[1][(n - b0) * nb + bb];
-        const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
-        for (int vi = 0; vi < nvl; ++vi) {
-          const double mr = Mre[vi][a * nb + bb], mi = Mim[vi][a * nb + bb];
-          nr[vi] += wr * mr - wi * mi;
-          ni[vi] += wr * mi + wi * mr;
-        }
-      }
-    }
-    if (j == 0) {
-      g2[((size_t)X * ncol + 0) * nff2 + mn] = nr[0];
-    } else {
-      g2[((size_t)X * ncol + j) * nff2 + mn] = nr[0] + nr[1];
-      g2[((size_t)X * ncol + nsh - 1 + j) * nff2 + mn] = ni[0] - ni[1];
-    }
-  }
+  gather_store(b, item, threadIdx.x, sh);
 }
 
 // Inverse transform K[ch][l][mn] = sum_k E[l][k] g2[ch][k][mn] in FP64 on the
@@ -777,9 +603,10 @@ constexpr int kSegPer = kSeg / 256;
 template <int NK>
 __global__ void __launch_bounds__(256)
 k_axpy(Batch b, const int4* __restrict__ items, const double* X, SlopeSet ks, double h,
-       double* out, int skip_frozen) {
+       double* out, int skip_frozen, const double* __restrict__ hp) {
   const int4 it = items[blockIdx.x];
   if (skip_frozen && skip_point(b, it.x)) return;
+  if (hp != nullptr) h = hp[it.x];
   size_t base;
   int n;
   if (!seg_range(b, it, base, n)) return;
@@ -847,10 +674,15 @@ struct Coef7 {
 __global__ void __launch_bounds__(256)
 k_dp_final(Batch b, const int4* __restrict__ items, const double* __restrict__ y0, SlopeSet ks, Coef7 e,
            double h, double rtol, double atol, double* __restrict__ y5, double* __restrict__ red_out,
-           unsigned long long* __restrict__ max_out) {
+           unsigned long long* __restrict__ max_out, const double* __restrict__ hp) {
   __shared__ double red[256];
   __shared__ unsigned long long mred[256];
   const int4 it = items[blockIdx.x];
+  if (skip_point(b, it.x)) {
+    if (threadIdx.x == 0) red_out[blockIdx.x] = 0.0;
+    return;
+  }
+  if (hp != nullptr) h = hp[it.x];
   double acc = 0.0;
   unsigned long long m = 0ull;
   size_t base;
@@ -900,6 +732,140 @@ k_dp_final(Batch b, const int4* __restrict__ items, const double* __restrict__ y
     red_out[blockIdx.x] = red[0];
     if (mred[0] != 0ull) atomicMax(max_out + it.x, mred[0]);
   }
+}
+
+// Step control of the adaptive flow, one block per point (the Dormand-Prince
+// 5(4) rules of the flow options: RMS error norm of the attempt, accepted
+// when <= 1; step factor 0.9 err^(-1/5) in [0.2, 5]; stop after an accepted
+// step with max|X| > xmax, at s_end, on a non-finite error, or when
+// max_steps attempts are used up).  The error partial sums of the point's
+// segments are added in a fixed order: thread i sums partials i, i + 256, ...
+// in turn, then a fixed tree over the threads.  The next attempt's step is
+// clipped so that it does not pass s_end.
+__global__ void __launch_bounds__(256) k_dp_control(DpControl c) {
+  __shared__ double red[256];
+  const int p = blockIdx.x;
+  const int status = c.st[p].status;
+  if (status != 0) {
+    if (threadIdx.x == 0) {
+      c.max_words[p] = 0ull;
+      c.st[p].accept = 0;   // the stopping step's state was taken by the last acceptance
+    }
+    return;
+  }
+  const int2 sg = c.seg[p];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < sg.y; i += 256) acc += c.red[sg.x + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  DpState st = c.st[p];
+  const unsigned long long mw = c.max_words[p];
+  c.max_words[p] = 0ull;
+  const double err = sqrt(red[0] / c.n_el[p]);
+  st.err = err;
+  st.accept = 0;
+  ++st.n_att;
+  if (!isfinite(err)) {
+    st.status = TUFRG_FLOW_NONFINITE;
+    st.s0 = st.s;
+    st.m0 = st.m1;
+    st.s1 = st.s + st.h;
+    st.m1 = __longlong_as_double(0x7ff8000000000000ll);
+  } else {
+    if (err <= 1.0) {
+      st.accept = 1;
+      ++st.n_acc;
+      st.s0 = st.s1;
+      st.m0 = st.m1;
+      st.s = st.s + st.h;
+      st.s1 = st.s;
+      st.m1 = __longlong_as_double((long long)mw);
+      if (st.m1 > c.xmax) st.status = TUFRG_FLOW_DIVERGED;
+      else if (st.s <= c.s_end + 1e-15) st.status = TUFRG_FLOW_REACHED_TMIN;
+    }
+    const double fac = err == 0.0 ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(err, -0.2)));
+    st.h *= fac;
+    if (st.status == 0 && st.n_att >= c.max_steps) st.status = TUFRG_FLOW_MAX_STEPS;
+    if (st.s + st.h < c.s_end) st.h = c.s_end - st.s;
+  }
+  if (st.status != 0) c.frozen[p] = 1;
+  c.s_arr[p] = st.s;
+  c.h_arr[p] = st.h;
+  c.st[p] = st;
+}
+
+// y = y5 and k0 = k6 (first same as last) for the points whose attempt was
+// accepted; segment items as k_axpy
+__global__ void __launch_bounds__(256)
+k_dp_accept(Batch b, const int4* __restrict__ items, const DpState* __restrict__ st, const double* __restrict__ y5,
+            const double* __restrict__ k6, double* __restrict__ y, double* __restrict__ k0) {
+  const int4 it = items[blockIdx.x];
+  if (!st[it.x].accept) return;
+  size_t base;
+  int n;
+  if (!seg_range(b, it, base, n)) return;
+  double yv[kSegPer], kv[kSegPer];
+#pragma unroll
+  for (int u = 0; u < kSegPer; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    const size_t e = base + (i < n ? i : 0);
+    yv[u] = y5[e];
+    kv[u] = k6[e];
+  }
+#pragma unroll
+  for (int u = 0; u < kSegPer; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    if (i < n) {
+      y[base + i] = yv[u];
+      k0[base + i] = kv[u];
+    }
+  }
+}
+
+// Tp[p] = exp(s[p] + c h[p]) (stage temperatures of the adaptive flow)
+__global__ void k_set_T_sh(double* Tp, int npts, const double* __restrict__ s_arr, const double* __restrict__ h_arr,
+                           double c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < npts) Tp[i] = exp(fma(c, h_arr[i], s_arr[i]));
+}
+
+// Largest deviation of a state from the C4v covariance law, per point:
+// max over channels, orbit members q of representative r and (m, n) of
+// |X(q)_mn - s_m s_n X(r)_{pi(m) pi(n)}| as an ordered bit pattern (NaN sorts
+// above +inf), into words[p].  Item (p, representative slot).
+__global__ void __launch_bounds__(256)
+k_sym_defect(Batch b, const int2* __restrict__ items, const double* __restrict__ X,
+             unsigned long long* __restrict__ words) {
+  __shared__ unsigned long long red[256];
+  const int2 it = items[blockIdx.x];
+  const DevTables& d = b.pts[it.x];
+  const int nff = d.nff, nff2 = nff * nff, slot = it.y, r = d.irr[slot];
+  const int e0 = d.orb_start[slot], ne = d.orb_start[slot + 1] - e0;
+  const size_t S = (size_t)b.S;
+  unsigned long long m = 0ull;
+  for (int w = threadIdx.x; w < 3 * ne * nff2; w += blockDim.x) {
+    const int ch = w / (ne * nff2), rem = w % (ne * nff2), e = rem / nff2, mn = rem % nff2;
+    const int q = d.orb_q[e0 + e], tr = d.orb_tr[e0 + e];
+    const int pa = d.tperm[(size_t)tr * nff + mn / nff], pc = d.tperm[(size_t)tr * nff + mn % nff];
+    const double sg = ((pa ^ pc) >> 8) & 1 ? -1.0 : 1.0;
+    const double* Xc = X + ch * S + d.off;
+    const double v = Xc[(size_t)q * nff2 + mn] - sg * Xc[(size_t)r * nff2 + (pa & 0xff) * nff + (pc & 0xff)];
+    unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(v));
+    if (v != v) bits = 0x7ff8000000000000ull;
+    m = bits > m ? bits : m;
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s && red[threadIdx.x + s] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] != 0ull) atomicMax(words + it.x, red[0]);
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
@@ -1080,7 +1046,8 @@ void launch_back(const Launch& L, const Ranges& r, const double* X, double* out,
 }
 
 void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const double* const* k,
-                 const double* coef, int nk, double h, double* out, bool skip_frozen, hipStream_t s) {
+                 const double* coef, int nk, double h, double* out, bool skip_frozen, hipStream_t s,
+                 const double* hp) {
   if (r.n <= 0) return;
   SlopeSet ks{};
   for (int j = 0; j < nk; ++j) {
@@ -1091,13 +1058,13 @@ void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const dou
   const int4* it = L.seg_items + r.begin;
   const int sf = skip_frozen ? 1 : 0;
   switch (nk) {
-    case 1: hipLaunchKernelGGL(k_axpy<1>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
-    case 2: hipLaunchKernelGGL(k_axpy<2>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
-    case 3: hipLaunchKernelGGL(k_axpy<3>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
-    case 4: hipLaunchKernelGGL(k_axpy<4>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
-    case 5: hipLaunchKernelGGL(k_axpy<5>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
-    case 6: hipLaunchKernelGGL(k_axpy<6>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
-    default: hipLaunchKernelGGL(k_axpy<7>, g, blk, 0, s, L.b, it, X, ks, h, out, sf); break;
+    case 1: hipLaunchKernelGGL(k_axpy<1>, g, blk, 0, s, L.b, it, X, ks, h, out, sf, hp); break;
+    case 2: hipLaunchKernelGGL(k_axpy<2>, g, blk, 0, s, L.b, it, X, ks, h, out, sf, hp); break;
+    case 3: hipLaunchKernelGGL(k_axpy<3>, g, blk, 0, s, L.b, it, X, ks, h, out, sf, hp); break;
+    case 4: hipLaunchKernelGGL(k_axpy<4>, g, blk, 0, s, L.b, it, X, ks, h, out, sf, hp); break;
+    case 5: hipLaunchKernelGGL(k_axpy<5>, g, blk, 0, s, L.b, it, X, ks, h, out, sf, hp); break;
+    case 6: hipLaunchKernelGGL(k_axpy<6>, g, blk, 0, s, L.b, it, X, ks, h, out, sf, hp); break;
+    default: hipLaunchKernelGGL(k_axpy<7>, g, blk, 0, s, L.b, it, X, ks, h, out, sf, hp); break;
   }
 }
 
@@ -1109,7 +1076,7 @@ void launch_maxabs(const Launch& L, const ItemRange& r, const double* X, unsigne
 
 void launch_dp_final(const Launch& L, const ItemRange& r, const double* y0, const double* const* k,
                      const double* b5, const double* e, double h, double rtol, double atol, double* y5,
-                     double* red, unsigned long long* max_words, hipStream_t s) {
+                     double* red, unsigned long long* max_words, hipStream_t s, const double* hp) {
   if (r.n <= 0) return;
   SlopeSet ks{};
   Coef7 ec{};
@@ -1119,7 +1086,27 @@ void launch_dp_final(const Launch& L, const ItemRange& r, const double* y0, cons
     ec.c[j] = e[j];
   }
   hipLaunchKernelGGL(k_dp_final, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, y0, ks, ec, h,
-                     rtol, atol, y5, red, max_words);
+                     rtol, atol, y5, red, max_words, hp);
+}
+
+void launch_dp_control(const DpControl& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_dp_control, dim3(c.npts), dim3(256), 0, s, c);
+}
+
+void launch_dp_accept(const Launch& L, const ItemRange& r, const DpState* st, const double* y5, const double* k6,
+                      double* y, double* k0, hipStream_t s) {
+  if (r.n <= 0) return;
+  hipLaunchKernelGGL(k_dp_accept, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, st, y5, k6, y, k0);
+}
+
+void launch_set_T_sh(double* Tp, int npts, const double* s_arr, const double* h_arr, double c, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_T_sh, dim3((npts + 255) / 256), dim3(256), 0, s, Tp, npts, s_arr, h_arr, c);
+}
+
+void launch_sym_defect(const Launch& L, const int2* items, int n, const double* X, unsigned long long* words,
+                       hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_sym_defect, dim3(n), dim3(256), 0, s, L.b, items, X, words);
 }
 
 void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s) {

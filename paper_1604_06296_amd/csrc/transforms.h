@@ -21,6 +21,10 @@
 namespace tufrg {
 namespace {
 
+__device__ __forceinline__ bool skip_point(const Batch& b, int p) {
+  return b.frozen != nullptr && b.frozen[p] != 0;
+}
+
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 // BF16 hi/lo split with round to nearest even: x ~ hi + lo (about 16 mantissa
 // bits); products hi*hi + hi*lo + lo*hi accumulate in FP32 on the matrix cores.

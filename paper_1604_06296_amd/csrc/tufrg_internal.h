@@ -175,13 +175,28 @@ struct Ranges {
 // uses the values v[i] for points p0 + i (i < n <= 64); mode 2 takes the RK4
 // stage temperature Ttab[4 step + stage] for every point.  Block 0 of the
 // launch also stores them into the per-point array Tp for later kernels.
+// Mode 3 takes T = exp(s[p] + c h[p]) from the device arrays of the adaptive
+// flow (stage c of the point's current step).
 struct TArg {
   int mode, p0, n, npts;
   double* Tp;
   const double* Ttab;
   const int* step;
   int stage;
+  const double* s;
+  const double* h;
+  double c;
   double v[64];
+};
+
+// Device state of the adaptive (Dormand-Prince) flow, one entry per point.
+struct DpState {
+  double s, h;            // current scale s = ln T and the step of the next attempt
+  double s0, m0, s1, m1;  // the last two accepted (s, max|X|)
+  double err;             // error norm of the last attempt
+  int status;             // 0 while flowing, else a TUFRG_FLOW_* status
+  int n_acc, n_att;       // accepted and attempted steps
+  int accept;             // the last attempt was accepted
 };
 
 // Device item tables and launch shapes shared by all launches of a context.
@@ -242,15 +257,39 @@ void launch_loops_fwd(const Launch& L, const Ranges& r, const double* X, bool mi
 void launch_expand_basis(const Launch& L, const Ranges& r, double* dchi, bool cross, hipStream_t s);
 void launch_back(const Launch& L, const Ranges& r, const double* X, double* out, int mode,
                  bool cross, bool scale_T, bool mixed, hipStream_t s);
+// hp (device, per point) or null: the step of point p is hp[p] (the adaptive
+// flow) instead of h
 void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const double* const* k,
-                 const double* coef, int nk, double h, double* out, bool skip_frozen, hipStream_t s);
+                 const double* coef, int nk, double h, double* out, bool skip_frozen, hipStream_t s,
+                 const double* hp = nullptr);
 void launch_maxabs(const Launch& L, const ItemRange& r, const double* X, unsigned long long* words,
                    hipStream_t s);
 // the last Dormand-Prince stage: y5, the error partial sums and max|y5| per point
 void launch_dp_final(const Launch& L, const ItemRange& r, const double* y0, const double* const* k,
                      const double* b5, const double* e, double h, double rtol, double atol, double* y5,
-                     double* red, unsigned long long* max_words, hipStream_t s);
+                     double* red, unsigned long long* max_words, hipStream_t s, const double* hp = nullptr);
+// the adaptive flow's step control of every point (one block per point) and
+// the acceptance of its new state (y = y5 and k0 = k6 where accepted)
+struct DpControl {
+  DpState* st;
+  int* frozen;
+  const int2* seg;        // per point: first error partial sum and their count
+  const double* n_el;     // per point: elements of the state (3 Nq Nff^2)
+  const double* red;      // error partial sums of the attempt
+  unsigned long long* max_words;
+  double* s_arr;          // per point s and h, read by the next attempt's kernels
+  double* h_arr;
+  double s_end, xmax;
+  int max_steps, npts;
+};
+void launch_dp_control(const DpControl& c, hipStream_t s);
+void launch_dp_accept(const Launch& L, const ItemRange& r, const DpState* st, const double* y5, const double* k6,
+                      double* y, double* k0, hipStream_t s);
+void launch_set_T_sh(double* Tp, int npts, const double* s_arr, const double* h_arr, double c, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
+// per-point largest deviation of X from the C4v covariance law (items (p, slot))
+void launch_sym_defect(const Launch& L, const int2* items, int n, const double* X, unsigned long long* words,
+                       hipStream_t s);
 void launch_fill_i32(int* p, int n, int v, hipStream_t s);
 void launch_set_T(double* Tp, int npts, const double* Ttab, const int* step, int stage,
                   hipStream_t s);
@@ -320,4 +359,11 @@ struct tufrg_ctx {
   // workspace totals (elements) of the step calls, for the no-allocation entry point
   int64_t ws_total_xp = 0, ws_total_yb = 0, ws_total_g2 = 0, ws_total_k = 0;
   void* scratch = nullptr;                 // device address of the static scratch on ctx->device
+  tufrg::DpState* dp_state = nullptr;             // adaptive flow: per-point state (device)
+  double* dp_sh = nullptr;                 // [2][npts] s and h of every point (device)
+  int2* dp_seg = nullptr;                  // [npts] first error partial sum and count
+  double* dp_nel = nullptr;                // [npts] state elements 3 Nq Nff^2
+  int2* sym_items = nullptr;               // (point, representative slot) of every orbit
+  int n_sym_items = 0;
+  unsigned long long* sym_words = nullptr; // per-point covariance defect words
 };

@@ -261,3 +261,43 @@ def test_cfg4_full_batch_sampled(tf):
         qi = list(synth.sample_indices(p.nq, 3, seed=i)) + [p.nq - 1]
         ref = orhs.rhs(p, Ts[i], Xs[i], ff, q_index=qi)
         _normwise(ctx.view(d, i).numpy()[:, qi], ref, TOL, f"cfg4 pt{i} (Nff={ff.nff}, Lq={p.Lq})")
+
+
+def test_batched_dopri5_equals_single_point_flows(tf):
+    """The adaptive flow of a batch of uneven points (each with its own step
+    size and stop on the device) gives every point its single-point flow:
+    same status and instability, critical scale and state within the flow's
+    tolerances (the batch sums the loops in the batch's block order, so the
+    step sequence may differ by rounding); graph-replayed = eager bit for bit."""
+    import torch
+    pts = BATCH[:4]
+    print("[batch] dopri5 batch vs single points", flush=True)
+    opts = dict(T0=10.0, Tmin=0.01, Xmax=20.0, scheme="dopri5", rtol=1e-7, atol=1e-9)
+    ctx = tf.Context(pts)
+    Xg, Xe = ctx.empty(3).zero_(), ctx.empty(3).zero_()
+    rg = ctx.flow(Xg, tf.FlowOptions(use_graph=True, **opts))
+    re = ctx.flow(Xe, tf.FlowOptions(use_graph=False, **opts))
+    assert rg == re and torch.equal(Xg, Xe)
+    for i, p in enumerate(pts):
+        one = tf.Context([p])
+        X1 = one.empty(3).zero_()
+        r1 = one.flow(X1, tf.FlowOptions(**opts))[0]
+        a = rg[i]
+        assert (a.status, a.channel, a.q_index, a.irrep) == (r1.status, r1.channel, r1.q_index, r1.irrep), (i, a, r1)
+        assert abs(a.n_steps - r1.n_steps) <= 1, (i, a, r1)
+        if r1.Tc:
+            assert abs(a.Tc / r1.Tc - 1) < 1e-5
+        _normwise(ctx.view(Xg, i).cpu().numpy(), one.view(X1).cpu().numpy(), 1e-5, f"point {i}")
+
+
+def test_dopri5_step_budget_and_step_sign(tf):
+    """A flow that uses up max_steps says so; a first step pointing away from
+    Tmin is rejected."""
+    from paper_1604_06296_amd.binding import TufrgError
+    ctx = tf.Context([BATCH[1]])
+    r = ctx.flow(ctx.empty(3).zero_(), tf.FlowOptions(T0=10.0, Tmin=0.01, Xmax=20.0, scheme="dopri5",
+                                                      rtol=1e-7, atol=1e-9, max_steps=3))[0]
+    assert r.status == "max_steps" and r.n_steps <= 3 and r.n_rhs == 1 + 6 * 3
+    with pytest.raises(TufrgError, match="h0"):
+        ctx.flow(ctx.empty(3).zero_(), tf.FlowOptions(T0=10.0, Tmin=0.01, Xmax=20.0, scheme="dopri5",
+                                                      rtol=1e-7, atol=1e-9, h0=0.05))

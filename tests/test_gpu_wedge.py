@@ -286,3 +286,26 @@ def test_mixed_precision_flow(tf):
     assert abs(ra.Tc / rb.Tc - 1) < 1e-5
     assert ra.channel == rb.channel and ra.irrep == rb.irrep
     assert _rep_of(pt.Lq, ra.q_index) == _rep_of(pt.Lq, rb.q_index)
+
+
+def test_symmetry_defect_detects_non_symmetric_states(tf):
+    """tufrg_symmetry_defect: ~0 for a symmetrised state (and its flow
+    increment), O(1) for a random state; a symmetric-state flow rejects a
+    non-symmetric initial state with EINVAL instead of a silent answer."""
+    import torch
+    from paper_1604_06296_amd.binding import TufrgError
+    pt = synth.Point(t=1.0, tp=-0.25, U=3.0, Lq=12, Lk=24, shells=3, mu=-0.8)
+    ff = FormFactors(pt.shells)
+    ctx = tf.Context([pt], symmetric_state=True)
+    X = synth.random_channels(pt.nq, ff.nff, seed=41)
+    Xs = osym.symmetrize(X, ff, pt.Lq)
+    print("[wedge] symmetry defect", flush=True)
+    assert ctx.symmetry_defect(_to_dev(ctx, X)) > 1e-2
+    assert ctx.symmetry_defect(_to_dev(ctx, Xs)) <= 1e-14
+    assert ctx.symmetry_defect(ctx.rhs(0.1, _to_dev(ctx, Xs))) <= 1e-12
+    assert ctx.symmetry_defect(torch.zeros((3, ctx.S), dtype=torch.float64, device="cuda")) == 0.0
+    opts = tf.FlowOptions(T0=10.0, Tmin=0.1, Xmax=20.0, scheme="rk4", nsteps=10)
+    with pytest.raises(TufrgError, match="not C4v-symmetric"):
+        ctx.flow(_to_dev(ctx, X), opts)
+    r = ctx.flow(_to_dev(ctx, 1e-3 * Xs), opts)
+    assert r[0].status in ("reached_tmin", "diverged")
