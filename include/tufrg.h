@@ -24,8 +24,9 @@
  * every state of a flow started at zero is) and part of the work runs at one
  * transfer momentum per point-group orbit; see the flag.
  * Transfer momenta live on a uniform Lq x Lq grid
- * q_i = 2 pi (i - Lq/2)/Lq per axis (flat index ix*Lq + iy); loops are
- * plain averages over the unshifted uniform Lk x Lk grid p_j = 2 pi j/Lk.
+ * q_i = 2 pi (i - Lq/2)/Lq per axis (flat index ix*Lq + iy), or on a
+ * non-uniform mesh given to tufrg_init_mesh; loops are plain averages over
+ * the unshifted uniform Lk x Lk grid p_j = 2 pi j/Lk.
  *
  * Form factors (Sec. 3, footnote on C4v irreps): shells of bond length
  * 0, 1, sqrt2, 2, sqrt5; per shell ordered A1, B1, B2, A2, E:
@@ -209,6 +210,34 @@ typedef struct tufrg_mlp tufrg_mlp;
  * tufrg_free.  Errors: EINVAL (bad point, message names it), ENOMEM, EHIP. */
 tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_options* opt,
                         void* stream, tufrg_ctx** out);
+
+/* A non-uniform transfer-momentum mesh (Sec. 4: the exchange propagators on
+ * an adaptively dense set of momenta, denser where they are expected to
+ * peak).  nq momenta (qx[i], qy[i]) in [-pi, pi)^2 with quadrature weights
+ * w[i] > 0, the fractions of the zone's area their cells cover (sum 1 to
+ * 1e-12); host arrays, copied by the init call.  The loops and the products
+ * are evaluated at the mesh momenta; the projections' Fourier coefficients of
+ * the gauged exchange propagators (the Fourier series of the appendix on
+ * symmetries) are the mesh quadrature
+ *   Yhat_{R1R2}(W) = sum_u w_u X_{R1R2}(u) exp(i u.(W - (R1+R2)/2)),
+ * which on the uniform Lq grid (w = 1/Lq^2) is the transform tufrg_init uses.
+ * The point's Lq names the coarse grid the mesh refines (the same condition
+ * Lq > 4 * largest bond component applies).  Flat index: the mesh order. */
+typedef struct {
+  int32_t nq;              /* 1 .. 65535; 0 selects the uniform Lq x Lq grid */
+  const double* qx;
+  const double* qy;
+  const double* w;
+} tufrg_mesh;
+
+/* tufrg_init with a transfer mesh per point (meshes: host array [npts]; an
+ * entry with nq = 0, or meshes = NULL, keeps the uniform grid).  A point on a
+ * non-uniform mesh integrates its loops at every mesh momentum (no
+ * point-group reduction); TUFRG_SYMMETRIC_STATE and the surrogate are not
+ * available for it (EUNSUPPORTED).  EINVAL for a mesh outside the zone,
+ * non-positive or non-finite weights, or weights not summing to 1. */
+tufrg_status tufrg_init_mesh(const tufrg_point* pts, const tufrg_mesh* meshes, int32_t npts,
+                             const tufrg_options* opt, void* stream, tufrg_ctx** out);
 
 /* Offset (in elements, within one channel), Nq and Nff of point `point`;
  * any output pointer may be NULL.  *total (if non-NULL) receives S. */

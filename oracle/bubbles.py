@@ -45,7 +45,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .lattice import FormFactors, dispersion, k_grid, q_grid
+from .lattice import FormFactors, dispersion, k_grid, transfer_points
 
 LN2 = np.log(2.0)
 
@@ -184,7 +184,7 @@ def bubbles(point, T: float, which: str = "dot", ff: FormFactors | None = None,
     if regulator not in REGULATORS:
         raise ValueError(regulator)
     ff = ff or FormFactors(point.shells)
-    qx, qy = q_grid(point.Lq)
+    qx, qy, _ = transfer_points(point)
     if q_index is not None:
         qx, qy = qx[q_index], qy[q_index]
     px, py = k_grid(point.Lk)

@@ -31,7 +31,7 @@ from typing import Callable, List, Optional
 
 import numpy as np
 
-from .lattice import FormFactors
+from .lattice import FormFactors, transfer_points
 from .rhs import rhs
 
 CHANNELS = ("P", "C", "D")
@@ -94,7 +94,7 @@ def flow_rk4(point, T0: float, Tmin: float, nsteps: int, Xmax: float,
     """Classical RK4 with nsteps uniform steps in s = ln T from T0 to Tmin."""
     ff = FormFactors(point.shells)
     f = rhs_fn or (lambda T, X: rhs(point, T, X, ff, no_cross=no_cross, regulator=regulator))
-    X = np.zeros((3, point.Lq ** 2, ff.nff, ff.nff)) if X0 is None else X0.copy()
+    X = np.zeros((3, transfer_points(point)[0].size, ff.nff, ff.nff)) if X0 is None else X0.copy()
     s, h = math.log(T0), (math.log(Tmin) - math.log(T0)) / nsteps
 
     def g(sv, Xv):
@@ -169,7 +169,7 @@ def flow_dopri5(point, T0: float, Tmin: float, Xmax: float, rtol: float = 1e-7,
     diverging ends with STATUS_MAX_STEPS."""
     ff = FormFactors(point.shells)
     f = rhs_fn or (lambda T, X: rhs(point, T, X, ff, no_cross=no_cross, regulator=regulator))
-    X = np.zeros((3, point.Lq ** 2, ff.nff, ff.nff)) if X0 is None else X0.copy()
+    X = np.zeros((3, transfer_points(point)[0].size, ff.nff, ff.nff)) if X0 is None else X0.copy()
     s, s_end = math.log(T0), math.log(Tmin)
     if h0 is not None and not h0 * (s_end - s) > 0.0:
         raise ValueError("h0 must point from T0 towards Tmin")

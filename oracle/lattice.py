@@ -129,6 +129,23 @@ def q_grid(Lq: int):
     return qx.ravel(), qy.ravel()
 
 
+def transfer_points(point):
+    """Transfer momenta of a point and their quadrature weights: (qx, qy, w).
+
+    The uniform grid q_grid(point.Lq) with weights 1/N_q, or the point's
+    non-uniform mesh (point.mesh: arrays qx, qy in [-pi, pi) and weights w,
+    the fractions of the zone's area that the mesh cells of the points cover,
+    summing to 1).  The weights are the quadrature of the Fourier integrals
+    over the zone (the projections' "Fourier series" of the exchange
+    propagators); every other step is evaluated pointwise at the momenta.
+    """
+    mesh = getattr(point, "mesh", None)
+    if mesh is None:
+        qx, qy = q_grid(point.Lq)
+        return qx, qy, np.full(qx.size, 1.0 / qx.size)
+    return np.asarray(mesh.qx, float), np.asarray(mesh.qy, float), np.asarray(mesh.w, float)
+
+
 def k_grid(Lk: int):
     """Unshifted fine grid p_j = 2 pi j / Lk per axis; flat index jx*Lk + jy."""
     k1 = 2 * np.pi * np.arange(Lk) / Lk

@@ -17,7 +17,9 @@ exp(-i u.(R1+R2)/2) X_{R1R2}(u) is periodic and has Fourier coefficients
     Yhat_{R1R2}(W) = (1/N_q) sum_u X_{R1R2}(u) exp(i u.(W - (R1+R2)/2)),  W in Z^2
 (the "Fourier series" of the exchange propagator used with the stored
 projection tensors in the appendix on symmetries; on the uniform grid this
-is the DFT, i.e. trigonometric interpolation of the propagator).
+is the DFT, i.e. trigonometric interpolation of the propagator; on a
+non-uniform transfer mesh, Sec. 4, the sum over u carries the quadrature
+weights of the mesh cells instead of 1/N_q).
 Substituting into the projection rules and doing the k, k' integrals with
 int dk f_m(k) exp(i k.R) = c_{m,R} gives two kernels:
     K1[X]_mn(l) = sum_{R1,R2,W} exp(-i l.(R1+R2)/2) c_{m,R2-W} c_{n,R1-W} Yhat_{R1R2}(W)
@@ -39,7 +41,7 @@ import itertools
 
 import numpy as np
 
-from .lattice import FormFactors, q_grid
+from .lattice import FormFactors, transfer_points
 
 
 def bond_space(X: np.ndarray, ff: FormFactors) -> np.ndarray:
@@ -53,22 +55,29 @@ def w_range(ff: FormFactors):
     return list(itertools.product(range(-r, r + 1), repeat=2))
 
 
-def gauged_fourier(X: np.ndarray, ff: FormFactors, Lq: int) -> dict:
+def gauged_fourier(X: np.ndarray, ff: FormFactors, point) -> dict:
     """Yhat_{R1R2}(W) for every W of w_range: {W: array [b1, b2] complex}.
 
-    Yhat_{R1R2}(W) = (1/N_q) sum_u X_{R1R2}(u) exp(i u.(W - (R1+R2)/2)).
+    Yhat_{R1R2}(W) = sum_u w_u X_{R1R2}(u) exp(i u.(W - (R1+R2)/2)), the
+    quadrature of the Fourier integral over the zone with the weights w_u of
+    the transfer momenta: 1/N_q on the uniform grid (the DFT), the cell area
+    fractions on a non-uniform mesh.
     """
-    if Lq <= 4 * ff.rmax:
+    if point.Lq <= 4 * ff.rmax:
         raise ValueError("transfer grid too coarse: need Lq > 4 * largest bond component")
-    qx, qy = q_grid(Lq)
+    qx, qy, w = transfer_points(point)
     XB = bond_space(X, ff)
     B = np.array(ff.bonds, dtype=float)
     gx = 0.5 * (B[:, None, 0] + B[None, :, 0])
     gy = 0.5 * (B[:, None, 1] + B[None, :, 1])
     G = XB * np.exp(-1j * (qx[:, None, None] * gx[None] + qy[:, None, None] * gy[None]))
     Ws = w_range(ff)
-    ph = np.exp(1j * (np.outer([w[0] for w in Ws], qx) + np.outer([w[1] for w in Ws], qy)))
-    Yall = (ph @ G.reshape(qx.size, -1) / qx.size).reshape(len(Ws), ff.nff, ff.nff)
+    ph = np.exp(1j * (np.outer([v[0] for v in Ws], qx) + np.outer([v[1] for v in Ws], qy)))
+    if getattr(point, "mesh", None) is None:
+        Yall = ph @ G.reshape(qx.size, -1) / qx.size
+    else:
+        Yall = ph @ (w[:, None] * G.reshape(qx.size, -1))
+    Yall = Yall.reshape(len(Ws), ff.nff, ff.nff)
     return {W: Yall[i] for i, W in enumerate(Ws)}
 
 
@@ -77,13 +86,13 @@ def _coef_vector(ff: FormFactors, R) -> np.ndarray:
     return ff.coefficient_column(R)
 
 
-def kernel_K1(X: np.ndarray, ff: FormFactors, Lq: int, l_index=None) -> np.ndarray:
-    """K1[X]_mn(l) on the transfer grid (or at the momenta l_index): [nl, nff, nff] complex.
+def kernel_K1(X: np.ndarray, ff: FormFactors, point, l_index=None) -> np.ndarray:
+    """K1[X]_mn(l) at the transfer momenta (or at the momenta l_index): [nl, nff, nff] complex.
 
     K1[X]_mn(l) = sum_{R1,R2} exp(-i l.(R1+R2)/2) sum_W c_{m,R2-W} c_{n,R1-W} Yhat_{R1R2}(W).
     """
-    Y = gauged_fourier(X, ff, Lq)
-    qx, qy = q_grid(Lq)
+    Y = gauged_fourier(X, ff, point)
+    qx, qy, _ = transfer_points(point)
     if l_index is not None:
         qx, qy = qx[l_index], qy[l_index]
     out = np.zeros((qx.size, ff.nff, ff.nff), dtype=complex)
@@ -101,13 +110,13 @@ def kernel_K1(X: np.ndarray, ff: FormFactors, Lq: int, l_index=None) -> np.ndarr
     return out
 
 
-def kernel_K2(X: np.ndarray, ff: FormFactors, Lq: int, l_index=None) -> np.ndarray:
-    """K2[X]_mn(l) on the transfer grid (or at the momenta l_index): [nl, nff, nff] complex.
+def kernel_K2(X: np.ndarray, ff: FormFactors, point, l_index=None) -> np.ndarray:
+    """K2[X]_mn(l) at the transfer momenta (or at the momenta l_index): [nl, nff, nff] complex.
 
     K2[X]_mn(l) = sum_{R1,R2} exp(-i l.(R1-R2)/2) sum_W c_{m,-W} c_{n,W-R1-R2} Yhat_{R1R2}(W).
     """
-    Y = gauged_fourier(X, ff, Lq)
-    qx, qy = q_grid(Lq)
+    Y = gauged_fourier(X, ff, point)
+    qx, qy, _ = transfer_points(point)
     if l_index is not None:
         qx, qy = qx[l_index], qy[l_index]
     out = np.zeros((qx.size, ff.nff, ff.nff), dtype=complex)
@@ -142,8 +151,8 @@ def cross_projections(point, X: np.ndarray, ff: FormFactors | None = None, l_ind
     ff = ff or FormFactors(point.shells)
     P, C, D = X
     pi = ff.parity
-    K1C, K1D, K1P = (kernel_K1(Z, ff, point.Lq, l_index) for Z in (C, D, P))
-    K2D, K2C, K2P = (kernel_K2(Z, ff, point.Lq, l_index) for Z in (D, C, P))
+    K1C, K1D, K1P = (kernel_K1(Z, ff, point, l_index) for Z in (C, D, P))
+    K2D, K2C, K2P = (kernel_K2(Z, ff, point, l_index) for Z in (D, C, P))
     return {
         "P[C]": _real(K1C, "P[C]"),
         "P[D]": _real(K1D * pi[None, None, :], "P[D]"),

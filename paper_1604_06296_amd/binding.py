@@ -24,7 +24,7 @@ SYMMETRIC_STATE = 64
 REGULATORS = {"T": 0, "omega": OMEGA_CUTOFF}
 
 # every entry point declared in include/tufrg.h
-EXPORTS = ("tufrg_init", "tufrg_layout", "tufrg_geometry", "tufrg_bubbles", "tufrg_project",
+EXPORTS = ("tufrg_init", "tufrg_init_mesh", "tufrg_layout", "tufrg_geometry", "tufrg_bubbles", "tufrg_project",
            "tufrg_rhs", "tufrg_rhs_noalloc", "tufrg_flow", "tufrg_symmetry_defect", "tufrg_sync", "tufrg_flop_count", "tufrg_loop_kernel_time",
            "tufrg_mu_from_filling",
            "tufrg_harmonics", "tufrg_loop_harmonics", "tufrg_surrogate_dataset",
@@ -43,6 +43,11 @@ class _Point(C.Structure):
     _fields_ = [("t", C.c_double), ("tp", C.c_double), ("mu", C.c_double), ("U", C.c_double),
                 ("Lq", C.c_int32), ("Lk", C.c_int32), ("shells", C.c_int32),
                 ("reserved", C.c_int32)]
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("nq", C.c_int32), ("qx", C.POINTER(C.c_double)), ("qy", C.POINTER(C.c_double)),
+                ("w", C.POINTER(C.c_double))]
 
 
 class _Options(C.Structure):
@@ -80,6 +85,8 @@ def load_library():
     lib = C.CDLL(path)
     vp, dp, i32, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int64
     lib.tufrg_init.argtypes = [C.POINTER(_Point), i32, C.POINTER(_Options), vp, C.POINTER(vp)]
+    lib.tufrg_init_mesh.argtypes = [C.POINTER(_Point), C.POINTER(_Mesh), i32, C.POINTER(_Options), vp,
+                                    C.POINTER(vp)]
     lib.tufrg_layout.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
                                  C.POINTER(i64)]
     lib.tufrg_geometry.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
@@ -292,9 +299,24 @@ class Context:
                        | (SYMMETRIC_STATE if symmetric_state else 0))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = C.c_void_p()
-        _check(self.lib, None, self.lib.tufrg_init(arr, n, C.byref(opt),
-                                                    C.c_void_p(self.stream.cuda_stream),
-                                                    C.byref(handle)))
+        meshes = [getattr(p, "mesh", None) for p in points]
+        if any(m is not None for m in meshes):
+            # non-uniform transfer meshes (host arrays, copied by the init call)
+            import numpy as np
+            keep = []
+            marr = (_Mesh * n)()
+            for i, m in enumerate(meshes):
+                if m is None:
+                    continue
+                cols = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (m.qx, m.qy, m.w)]
+                keep.append(cols)
+                dpp = C.POINTER(C.c_double)
+                marr[i] = _Mesh(len(cols[0]), *(c.ctypes.data_as(dpp) for c in cols))
+            st = self.lib.tufrg_init_mesh(arr, marr, n, C.byref(opt), C.c_void_p(self.stream.cuda_stream),
+                                          C.byref(handle))
+        else:
+            st = self.lib.tufrg_init(arr, n, C.byref(opt), C.c_void_p(self.stream.cuda_stream), C.byref(handle))
+        _check(self.lib, None, st)
         self.ctx = handle
         self.npts = n
         self.layouts = []

@@ -248,10 +248,14 @@ int fwd_kt_of(const DevTables& d) {
 }
 
 // loop items of one point: one per (representative momentum, row slice),
-// (p, slot * nsplit + split, flat q of the representative)
+// (p, slot * nsplit + split, flat q of the representative, its axis indices
+// ix << 16 | iy into the shifted-cosine tables)
 void add_loop_items(const DevTables& d, const HostTables& t, int p, std::vector<int4>& v, ItemRange& r) {
   mark(v, r, [&](std::vector<int4>& w) {
-    for (int b = 0; b < d.nirr * d.nsplit; ++b) w.push_back(make_int4(p, b, t.irr[b / d.nsplit], 0));
+    for (int b = 0; b < d.nirr * d.nsplit; ++b) {
+      const int q = t.irr[b / d.nsplit];
+      w.push_back(make_int4(p, b, q, t.qax[(size_t)q]));
+    }
   });
 }
 
@@ -755,6 +759,11 @@ extern "C" {
 
 tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_options* opt, void* stream,
                         tufrg_ctx** out) {
+  return tufrg_init_mesh(pts, nullptr, npts, opt, stream, out);
+}
+
+tufrg_status tufrg_init_mesh(const tufrg_point* pts, const tufrg_mesh* meshes, int32_t npts,
+                             const tufrg_options* opt, void* stream, tufrg_ctx** out) {
   if (!out) return fail(nullptr, TUFRG_EINVAL, "out is NULL");
   *out = nullptr;
   if (!pts || npts <= 0) return fail(nullptr, TUFRG_EINVAL, "need at least one point");
@@ -774,8 +783,14 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
   ctx->dev.assign(npts, DevTables());
   int64_t S = 0, ws_yb = 0, ws_g2 = 0, ws_k = 0, ws_xp = 0;
   for (int p = 0; p < npts; ++p) {
-    std::string e = build_tables(pts[p], ctx->host[p], !(o.flags & TUFRG_NO_SYMMETRY),
+    const tufrg_mesh* mp = meshes && meshes[p].nq != 0 ? &meshes[p] : nullptr;
+    std::string e = build_tables(pts[p], mp, ctx->host[p], !(o.flags & TUFRG_NO_SYMMETRY),
                                  (o.flags & TUFRG_OMEGA_CUTOFF) != 0);
+    if (e.empty() && mp && (o.flags & TUFRG_SYMMETRIC_STATE)) {
+      delete ctx;
+      return fail(nullptr, TUFRG_EUNSUPPORTED, "point " + std::to_string(p) +
+                                                   ": symmetric states need the uniform transfer grid");
+    }
     if (e.empty() && ctx->host[p].lk > kLoopThreadsMax)
       e = "Lk must be <= " + std::to_string(kLoopThreadsMax);
     for (int sh = 0; e.empty() && sh < ctx->host[p].nshell; ++sh)
@@ -851,12 +866,20 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
     std::vector<double> ebub_t(t.ebub.size());
     for (int mn = 0; mn < t.nff * t.nff; ++mn)
       for (int j = 0; j < t.nsh; ++j) ebub_t[(size_t)j * t.nff * t.nff + mn] = t.ebub[(size_t)mn * t.nsh + j];
-    std::vector<double> ephp((size_t)t.nq * kEpad, 0.0);
+    // the forward transform's copy of the phase table carries N_q times the
+    // quadrature weight of each momentum (exactly 1 on the uniform grid; the
+    // bond-basis kernel divides the sums by N_q); the inverse transform's
+    // tables are the plain phases
+    std::vector<double> ephp((size_t)t.nq * kEpad, 0.0), ephu((size_t)t.nq * kEpad, 0.0);
     for (int u = 0; u < t.nq; ++u)
-      for (int k = 0; k < t.ncol; ++k) ephp[(size_t)u * kEpad + k] = t.eph[(size_t)u * t.ncol + k];
+      for (int k = 0; k < t.ncol; ++k) {
+        ephu[(size_t)u * kEpad + k] = t.eph[(size_t)u * t.ncol + k];
+        ephp[(size_t)u * kEpad + k] = t.wq[u] * t.eph[(size_t)u * t.ncol + k];
+      }
     // BF16 splits of the phase table in the two layouts of the mixed transforms
-    std::vector<unsigned short> ehi, elo;
+    std::vector<unsigned short> ehi, elo, uhi, ulo;
     split_table(ephp, ehi, elo);
+    split_table(ephu, uhi, ulo);
     const size_t nq16 = (size_t)(t.nq + 15) / 16 * 16, nq64 = (size_t)(t.nq + 63) / 64 * 64;
     std::vector<unsigned short> qhi(nq16 * kEpad, 0), qlo(nq16 * kEpad, 0);
     std::vector<unsigned short> rhi(nq64 * kEpad, 0), rlo(nq64 * kEpad, 0);
@@ -865,8 +888,8 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
         const size_t src = (size_t)u * kEpad + k, q = ((size_t)(u / 4) * kEpad + k) * 4 + u % 4;
         qhi[q] = ehi[src];
         qlo[q] = elo[src];
-        rhi[src] = ehi[src];
-        rlo[src] = elo[src];
+        rhi[src] = uhi[src];
+        rlo[src] = ulo[src];
       }
     tufrg_status st;
     if ((st = upload(ctx, cre, &d.cre, A)) || (st = upload(ctx, cim, &d.cim, A)) ||
@@ -875,6 +898,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
         (st = upload(ctx, t.pytab, &d.pytab, A)) || (st = upload(ctx, t.eph, &d.eph, A)) ||
         (st = upload(ctx, ephp, &d.ephp, A)) ||
         (st = upload(ctx, t.cshift, &d.cshift, A)) || (st = upload(ctx, qhi, &d.ephq_hi, A)) ||
+        (!t.cshift_y.empty() && (st = upload(ctx, t.cshift_y, &d.cshift_y, A))) ||
         (st = upload(ctx, qlo, &d.ephq_lo, A)) || (st = upload(ctx, rhi, &d.ephr_hi, A)) ||
         (st = upload(ctx, rlo, &d.ephr_lo, A)) || (st = upload(ctx, hx, &d.hx, A)) ||
         (st = upload(ctx, hy, &d.hy, A)) || (st = upload(ctx, t.pairs, &d.pairs, A)) ||
@@ -882,6 +906,7 @@ tufrg_status tufrg_init(const tufrg_point* pts, int32_t npts, const tufrg_option
         (st = upload(ctx, t.tperm, &d.tperm, A)) || (st = upload(ctx, t.orb_start, &d.orb_start, A)) ||
         (st = upload(ctx, t.orb_q, &d.orb_q, A)) || (st = upload(ctx, t.orb_tr, &d.orb_tr, A)))
       return bad(st);
+    if (t.cshift_y.empty()) d.cshift_y = d.cshift;   // the uniform grid: one table for both axes
   }
   // workspace, state buffers and control words
   Batch& B = ctx->L.b;
@@ -1063,6 +1088,8 @@ tufrg_status tufrg_surrogate_dataset(tufrg_ctx* ctx, const double* T_host, int64
   if (n < 0) return fail(ctx, TUFRG_EINVAL, "n must be >= 0");
   if (mixed_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "training labels come from FP64 contexts");
   if (omega_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves the temperature flow");
+  for (const HostTables& t : ctx->host)
+    if (t.mesh) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves the uniform transfer grid");
   ST_TRY(check_temperatures(ctx, T_host));
   launch_set_T_values(ctx->Tp, T_host, (int)ctx->dev.size(), ctx->stream);
   const Launch& L = ctx->L;
@@ -1085,6 +1112,7 @@ tufrg_status tufrg_surrogate_attach(tufrg_ctx* ctx, tufrg_mlp* a, tufrg_mlp* b, 
   if (ctx->dev.size() != 1) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves single-point contexts");
   if (mixed_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves FP64 contexts");
   if (omega_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves the temperature flow");
+  if (ctx->host[0].mesh) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves the uniform transfer grid");
   for (tufrg_mlp* m : {a, b})
     if (mlp_width(m, 0) != 9 || mlp_width(m, -1) != 4)
       return fail(ctx, TUFRG_EINVAL, "surrogate networks map 9 features to 4 targets");

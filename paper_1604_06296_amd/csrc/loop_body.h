@@ -36,10 +36,12 @@ __device__ __forceinline__ void neumaier_add(float& s, float& c, float v) {
 
 // ------------------------------------------------------------------ loops
 // Step ii.) of Sec. 2.4, eqn. chis, at the point's temperature.  Work item
-// (p, slot * nsplit + split, q): one representative transfer momentum q =
-// irr[slot] (point-group orbits; every other momentum follows by symmetry in
-// the expansion kernel; q travels in the item, which saves the kernel a
-// dependent load) and one slice of the rows
+// (p, slot * nsplit + split, q, ix << 16 | iy): one representative transfer
+// momentum q = irr[slot] (point-group orbits; every other momentum follows by
+// symmetry in the expansion kernel; on a non-uniform mesh every momentum is
+// its own representative) with the indices of its x and y components in the
+// shifted-cosine tables (in the item, which saves the kernel a dependent
+// load), and one slice of the rows
 // py in [0, Lk/2] of the fine grid (the loop weight is even in p: the
 // self-paired rows py = 0 and Lk/2 carry weight 1, the others weight 2).
 // Threads own one column px and a chunk of the slice's rows; they accumulate
@@ -56,7 +58,7 @@ __device__ __forceinline__ void neumaier_add(float& s, float& c, float v) {
 // One loop work item with the point's exact harmonic count NH = 2 smax + 1
 // (compile-time, so the per-row harmonic loops carry no guards).
 template <int SMAX, bool MIXED, bool OMEGA, bool UNROLL>
-__device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, int p, int item_b, int q,
+__device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, int p, int item_b, int qa,
                                           double T, double* smem) {
   constexpr int NH = 2 * SMAX + 1;
   const int t = threadIdx.x;
@@ -67,8 +69,7 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
   const int R0 = (int)((int64_t)rows * split / nsplit);
   const int R1 = (int)((int64_t)rows * (split + 1) / nsplit);
   const int nr = R1 - R0;
-  const int lq = d.lq;
-  const int ix = q / lq, iy = q % lq;
+  const int ix = qa >> 16, iy = qa & 0xffff;   // axis indices of the momentum (from the item)
   // loop arguments: eps/(2T) for the temperature flow, eps/Om for the Omega cutoff
   const double inv_s = OMEGA ? 1.0 / T : 0.5 / T;
 
@@ -79,7 +80,7 @@ __device__ __forceinline__ void loop_item(const Batch& b, const DevTables& d, in
   double* pxs = rs + lk * 2 * NH;           // px harmonics          [lk][NH]
   double* gh = pxs + lk * NH;               // harmonic partials     [nseg][2 nsh]
   for (int j = t; j < nr; j += blockDim.x) {
-    const double* c = d.cshift + ((size_t)iy * lk + (R0 + j)) * 2;
+    const double* c = d.cshift_y + ((size_t)iy * lk + (R0 + j)) * 2;
     y1[j] = c[0];
     y2[j] = c[1];
   }
@@ -258,21 +259,21 @@ __device__ __forceinline__ double point_T(const Batch& b, const TArg* ta, int p)
 
 // Runs the body compiled for the item's own smax.
 template <int SMAX, bool MIXED, bool OMEGA, bool UNROLL>
-__device__ __forceinline__ void loop_smax(const Batch& b, const DevTables& d, int p, int item_b, int q,
+__device__ __forceinline__ void loop_smax(const Batch& b, const DevTables& d, int p, int item_b, int qa,
                                           double T, double* smem) {
   if constexpr (SMAX >= 4) {
     if (d.smax == 4) {
-      loop_item<4, MIXED, OMEGA, UNROLL>(b, d, p, item_b, q, T, smem);
+      loop_item<4, MIXED, OMEGA, UNROLL>(b, d, p, item_b, qa, T, smem);
       return;
     }
   }
   if constexpr (SMAX >= 2) {
     if (d.smax == 2) {
-      loop_item<2, MIXED, OMEGA, UNROLL>(b, d, p, item_b, q, T, smem);
+      loop_item<2, MIXED, OMEGA, UNROLL>(b, d, p, item_b, qa, T, smem);
       return;
     }
   }
-  loop_item<0, MIXED, OMEGA, UNROLL>(b, d, p, item_b, q, T, smem);
+  loop_item<0, MIXED, OMEGA, UNROLL>(b, d, p, item_b, qa, T, smem);
 }
 
 template <int SMAX, bool MIXED, bool OMEGA, bool UNROLL>
@@ -281,7 +282,7 @@ __device__ __forceinline__ void loop_dispatch(const Batch& b, const int4 item, d
   const int p = item.x;
   if (skip_point(b, p)) return;
   const DevTables& d = b.pts[p];
-  loop_smax<SMAX, MIXED, OMEGA, UNROLL>(b, d, p, item.y, item.z, point_T(b, ta, p), smem);
+  loop_smax<SMAX, MIXED, OMEGA, UNROLL>(b, d, p, item.y, item.w, point_T(b, ta, p), smem);
 }
 
 }  // namespace

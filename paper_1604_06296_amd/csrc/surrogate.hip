@@ -176,7 +176,8 @@ __global__ void __launch_bounds__(1024) k_sur_compact(Batch b, int p, SurState s
   int pos = sums[threadIdx.x] - c;     // exclusive prefix: first slot of this thread
   for (int q = q0; q < q1; ++q)
     if (st.need[q]) {
-      for (int s = 0; s < ns; ++s) st.items[(size_t)pos * ns + s] = make_int4(p, q * ns + s, d.irr[q], 0);
+      for (int s = 0; s < ns; ++s) st.items[(size_t)pos * ns + s] =
+            make_int4(p, q * ns + s, d.irr[q], ((d.irr[q] / d.lq) << 16) | (d.irr[q] % d.lq));
       ++pos;
     }
   if (threadIdx.x == 1023) {

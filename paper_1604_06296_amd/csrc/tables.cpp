@@ -85,7 +85,8 @@ int nff_of_shells(int shells) {
   return (shells >= 0 && shells <= 4) ? n[shells] : -1;
 }
 
-std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric, bool omega) {
+std::string build_tables(const tufrg_point& p, const tufrg_mesh* mesh, HostTables& t, bool symmetric,
+                         bool omega) {
   char msg[256];
   if (!(p.t > 0.0) || !std::isfinite(p.t)) return "t must be finite and > 0";
   if (!std::isfinite(p.tp) || !std::isfinite(p.mu) || !std::isfinite(p.U))
@@ -107,7 +108,36 @@ std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric, bo
   }
   if ((int64_t)p.Lk * p.Lk > (int64_t)1 << 28) return "Lk too large";
   if (p.Lq > 256) return "Lq must be <= 256";
-  t.nq = p.Lq * p.Lq;
+  t.mesh = mesh != nullptr && mesh->nq != 0;
+  if (t.mesh) {
+    // a non-uniform transfer mesh: momenta in the zone [-pi, pi)^2, positive
+    // weights summing to 1; every momentum is its own orbit representative
+    if (mesh->nq < 1 || mesh->nq > 65535) return "mesh nq must be in 1..65535";
+    if (!mesh->qx || !mesh->qy || !mesh->w) return "mesh arrays must not be NULL";
+    double wsum = 0.0;
+    for (int i = 0; i < mesh->nq; ++i) {
+      const double x = mesh->qx[i], y = mesh->qy[i], w = mesh->w[i];
+      if (!(x >= -M_PI && x < M_PI) || !(y >= -M_PI && y < M_PI)) return "mesh momenta must lie in [-pi, pi)";
+      if (!(w > 0.0) || !std::isfinite(w)) return "mesh weights must be finite and > 0";
+      wsum += w;
+    }
+    if (!(std::fabs(wsum - 1.0) <= 1e-12)) return "mesh weights must sum to 1";
+    symmetric = false;
+    t.nq = mesh->nq;
+    t.qxv.assign(mesh->qx, mesh->qx + t.nq);
+    t.qyv.assign(mesh->qy, mesh->qy + t.nq);
+    t.wq.resize(t.nq);
+    for (int i = 0; i < t.nq; ++i) t.wq[i] = (double)t.nq * mesh->w[i];
+  } else {
+    t.nq = p.Lq * p.Lq;
+    t.qxv.resize(t.nq);
+    t.qyv.resize(t.nq);
+    for (int q = 0; q < t.nq; ++q) {
+      t.qxv[q] = 2.0 * M_PI * (double)(q / p.Lq - p.Lq / 2) / (double)p.Lq;
+      t.qyv[q] = 2.0 * M_PI * (double)(q % p.Lq - p.Lq / 2) / (double)p.Lq;
+    }
+    t.wq.assign(t.nq, 1.0);
+  }
   t.lk = p.Lk;
   const int nff = t.nff;
 
@@ -194,7 +224,25 @@ std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric, bo
   // its orbit (smallest flat index) through an operation h with h q = r + G,
   // G in {0, 2 pi}^2, so that ghat(q, S_j) = (-1)^{G.hS_j / 2 pi} ghat(r, +-h S_j)
   // (ghat is even in S).  Without `symmetric` every q is its own representative.
-  {
+  if (t.mesh) {
+    // no point-group reduction on a mesh: every momentum represents itself,
+    // each orbit is the momentum alone with the identity permutation
+    t.nirr = t.nq;
+    t.irr.resize(t.nq);
+    t.symmap.assign((size_t)t.nq * t.nsh, 0);
+    for (int q = 0; q < t.nq; ++q) {
+      t.irr[q] = q;
+      for (int j = 0; j < t.nsh; ++j) t.symmap[(size_t)q * t.nsh + j] = pack_sym(q, j, 0);
+    }
+    t.tperm.resize(nff);
+    for (int m = 0; m < nff; ++m) t.tperm[m] = pack_perm(m, 0);
+    t.ntr = 1;
+    t.orb_start.resize((size_t)t.nq + 1);
+    t.orb_q.resize(t.nq);
+    t.orb_tr.assign(t.nq, 0);
+    for (int q = 0; q <= t.nq; ++q) t.orb_start[q] = q;
+    for (int q = 0; q < t.nq; ++q) t.orb_q[q] = q;
+  } else {
     static const int ops[8][4] = {{1, 0, 0, 1},  {-1, 0, 0, 1}, {1, 0, 0, -1}, {-1, 0, 0, -1},
                                   {0, 1, 1, 0},  {0, -1, 1, 0}, {0, 1, -1, 0}, {0, -1, -1, 0}};
     const int lq = p.Lq, half = lq / 2;
@@ -335,23 +383,56 @@ std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric, bo
     }
   }
 
-  // shifted cosines of the loop energies, one axis: p_j = 2 pi j/Lk,
-  // q_i = 2 pi (i - Lq/2)/Lq
-  t.cshift.assign((size_t)p.Lq * lk * 2, 0.0);
-  for (int i = 0; i < p.Lq; ++i) {
-    const double qh = M_PI * (double)(i - p.Lq / 2) / (double)p.Lq;   // q_i / 2
-    for (int j = 0; j < lk; ++j) {
-      const double pj = two_pi * (double)j / (double)lk;
-      t.cshift[((size_t)i * lk + j) * 2] = std::cos(pj + qh);
-      t.cshift[((size_t)i * lk + j) * 2 + 1] = std::cos(pj - qh);
+  // shifted cosines of the loop energies per axis value: p_j = 2 pi j/Lk,
+  // cos(p_j + q/2), cos(p_j - q/2)
+  auto shift_table = [&](const std::vector<double>& vals, std::vector<double>& tab) {
+    tab.assign(vals.size() * lk * 2, 0.0);
+    for (size_t i = 0; i < vals.size(); ++i) {
+      const double qh = 0.5 * vals[i];
+      for (int j = 0; j < lk; ++j) {
+        const double pj = two_pi * (double)j / (double)lk;
+        tab[(i * lk + j) * 2] = std::cos(pj + qh);
+        tab[(i * lk + j) * 2 + 1] = std::cos(pj - qh);
+      }
+    }
+  };
+  t.qax.resize(t.nq);
+  if (!t.mesh) {
+    // one table for both axes: q_i = 2 pi (i - Lq/2)/Lq, halved exactly
+    std::vector<double> vals(p.Lq);
+    for (int i = 0; i < p.Lq; ++i) vals[i] = 2.0 * M_PI * (double)(i - p.Lq / 2) / (double)p.Lq;
+    shift_table(vals, t.cshift);
+    t.cshift_y.clear();
+    for (int q = 0; q < t.nq; ++q) t.qax[q] = ((q / p.Lq) << 16) | (q % p.Lq);
+  } else {
+    // the distinct x and y components of the mesh, each axis its own table
+    std::vector<double> xs(t.qxv), ys(t.qyv);
+    std::sort(xs.begin(), xs.end());
+    xs.erase(std::unique(xs.begin(), xs.end()), xs.end());
+    std::sort(ys.begin(), ys.end());
+    ys.erase(std::unique(ys.begin(), ys.end()), ys.end());
+    shift_table(xs, t.cshift);
+    shift_table(ys, t.cshift_y);
+    for (int q = 0; q < t.nq; ++q) {
+      const int ix = (int)(std::lower_bound(xs.begin(), xs.end(), t.qxv[q]) - xs.begin());
+      const int iy = (int)(std::lower_bound(ys.begin(), ys.end(), t.qyv[q]) - ys.begin());
+      t.qax[q] = (ix << 16) | iy;
     }
   }
 
-  // projection phase table E[u][k] over the transfer grid, u.S/2 with
-  // u_i = 2 pi (i - Lq/2)/Lq; reduced exactly modulo 2 pi in units of pi/Lq
+  // projection phase table E[u][k] over the transfer momenta, u.S/2: on the
+  // uniform grid u_i = 2 pi (i - Lq/2)/Lq, reduced exactly modulo 2 pi in
+  // units of pi/Lq; on a mesh from the coordinates
   const int lq = p.Lq;
   t.eph.assign((size_t)t.nq * t.ncol, 0.0);
-  for (int ix = 0; ix < lq; ++ix)
+  if (t.mesh)
+    for (int u = 0; u < t.nq; ++u)
+      for (int j = 0; j < t.nsh; ++j) {
+        const double ang = 0.5 * (t.qxv[u] * t.hx[j] + t.qyv[u] * t.hy[j]);
+        t.eph[(size_t)u * t.ncol + j] = std::cos(ang);
+        if (j > 0) t.eph[(size_t)u * t.ncol + t.nsh - 1 + j] = std::sin(ang);
+      }
+  for (int ix = 0; ix < (t.mesh ? 0 : lq); ++ix)
     for (int iy = 0; iy < lq; ++iy) {
       int u = ix * lq + iy;
       for (int j = 0; j < t.nsh; ++j) {

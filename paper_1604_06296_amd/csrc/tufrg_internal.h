@@ -55,8 +55,15 @@ struct HostTables {
   // per-py weighted harmonics w(py) cos(n py), w(py) sin(n py) for py in [0, Lk/2]
   std::vector<double> pxtab;      // [Lk][2*smax+1]
   std::vector<double> pytab;      // [Lk/2+1][2*smax+1]
-  // loops: cos(p_j + q_i/2), cos(p_j - q_i/2) for one axis, [Lq][Lk][2]
-  std::vector<double> cshift;
+  // loops: cos(p_j + q_i/2), cos(p_j - q_i/2) per axis value, [nx][Lk][2]
+  // (x components) and [ny][Lk][2] (y components; the same table on the
+  // uniform grid), and per momentum the two axis indices (ix << 16 | iy)
+  std::vector<double> cshift, cshift_y;
+  std::vector<int32_t> qax;
+  // transfer momenta (coordinates) and N_q times their quadrature weights
+  // (1 on the uniform grid; the cells' area fractions times N_q on a mesh)
+  std::vector<double> qxv, qyv, wq;
+  bool mesh = false;
   // projections: phase table E[u][k] = cos(u.S'_k/2) (k < nsh), sin(u.S'_{k-nsh+1}/2)
   std::vector<double> eph;        // [nq][ncol]
   // projections: entry lists per (out channel, V in full set index, A, B)
@@ -81,8 +88,8 @@ inline int32_t pack_perm(int n, int neg) { return n | (neg << 8); }
 // symmetry map entry: representative slot (16 bits), harmonic (7 bits), sign (1 bit)
 inline int32_t pack_sym(int slot, int j, int neg) { return slot | (j << 16) | (neg << 24); }
 
-std::string build_tables(const tufrg_point& p, HostTables& t, bool symmetric,
-                         bool omega);   // "" on success
+std::string build_tables(const tufrg_point& p, const tufrg_mesh* mesh, HostTables& t, bool symmetric,
+                         bool omega);   // "" on success; mesh null or nq = 0: uniform grid
 int nff_of_shells(int shells);
 
 // ---------------------------------------------------------- device side
@@ -111,7 +118,8 @@ struct DevTables {
   double* ebub;           // [nsh][nff*nff] (the host table transposed: coalesced over mn)
   double* pxtab;          // [lk][2 smax + 1]
   double* pytab;          // [lk/2+1][2 smax + 1]
-  double* cshift;         // [lq][lk][2]: cos(p_j + q_i/2), cos(p_j - q_i/2) per axis
+  double* cshift;         // [nx][lk][2]: cos(p_j + q_x/2), cos(p_j - q_x/2) per x value
+  double* cshift_y;       // [ny][lk][2]: the same per y value (= cshift on the uniform grid)
   double* eph;            // [nq][ncol]
   double* ephp;           // [nq][kEpad]: eph padded with zero columns
   // BF16 splits of the phase table (mixed precision: E ~ hi + lo), zero-padded

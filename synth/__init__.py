@@ -27,11 +27,57 @@ SHELLS_OF_NFF = {v: k for k, v in NFF_OF_SHELLS.items()}
 
 
 @dataclasses.dataclass
+class Mesh:
+    """A non-uniform transfer-momentum mesh: points (qx, qy) in [-pi, pi)^2 and
+    the fractions w of the zone's area covered by their cells (sum 1)."""
+    qx: np.ndarray
+    qy: np.ndarray
+    w: np.ndarray
+
+    @property
+    def nq(self) -> int:
+        return int(self.qx.size)
+
+
+def refined_mesh(Lq: int, factor: int, centers, radius: int) -> Mesh:
+    """The uniform Lq x Lq transfer grid with the cells near the given centers
+    refined: a coarse cell (side 2 pi / Lq around q_i = 2 pi (i - Lq/2)/Lq per
+    axis) within `radius` cells of a center (Chebyshev distance on the
+    periodic grid) is replaced by factor x factor sub-cells (factor odd) whose
+    centers are its points, each of weight 1/(Lq^2 factor^2); the other cells
+    keep their point with weight 1/Lq^2.  Points are wrapped into [-pi, pi).
+    Order: coarse cells in flat order ix * Lq + iy, the sub-points of a
+    refined cell in their own flat order.  This is a geometry description
+    only (the method's arithmetic lives in the oracle and in the library)."""
+    if factor < 1 or factor % 2 == 0:
+        raise ValueError("factor must be odd")
+    h = 2 * np.pi / Lq
+    cen = [(int(round(c[0] / h)) % Lq, int(round(c[1] / h)) % Lq) for c in centers]
+    qx, qy, w = [], [], []
+    for ix in range(Lq):
+        for iy in range(Lq):
+            x0, y0 = h * (ix - Lq // 2), h * (iy - Lq // 2)
+            a, b = (ix - Lq // 2) % Lq, (iy - Lq // 2) % Lq
+            near = any(min(abs(a - cx), Lq - abs(a - cx)) <= radius and
+                       min(abs(b - cy), Lq - abs(b - cy)) <= radius for cx, cy in cen)
+            f = factor if near else 1
+            for sa in range(f):
+                for sb in range(f):
+                    dx, dy = h * (sa - (f - 1) // 2) / f, h * (sb - (f - 1) // 2) / f
+                    qx.append((x0 + dx + np.pi) % (2 * np.pi) - np.pi)
+                    qy.append((y0 + dy + np.pi) % (2 * np.pi) - np.pi)
+                    w.append(1.0 / (Lq * Lq * f * f))
+    return Mesh(np.array(qx), np.array(qy), np.array(w))
+
+
+@dataclasses.dataclass
 class Point:
     """One model/discretisation point.
 
     mu is None when the point is defined by a filling n; each side then
-    solves mu(n) itself at temperature mu_T on a mu_L x mu_L grid.
+    solves mu(n) itself at temperature mu_T on a mu_L x mu_L grid.  mesh, when
+    set, replaces the uniform Lq x Lq transfer grid (Lq then names the coarse
+    grid the mesh refines).
     """
     t: float
     tp: float
@@ -43,6 +89,7 @@ class Point:
     filling: Optional[float] = None
     mu_T: float = 1e-3
     mu_L: int = 1024
+    mesh: Optional[Mesh] = None
 
     @property
     def nff(self) -> int:
@@ -50,7 +97,7 @@ class Point:
 
     @property
     def nq(self) -> int:
-        return self.Lq * self.Lq
+        return self.mesh.nq if self.mesh is not None else self.Lq * self.Lq
 
 
 @dataclasses.dataclass

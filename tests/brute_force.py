@@ -134,3 +134,35 @@ def project_brute(ff, prop, onto, kind, lx, ly, Lf):
     fm = ff.values(kx, ky)
     fn = ff.values(kpx, kpy)
     return (fm * F) @ fn.T / F.size
+
+
+class MeshFourierPropagator(TrigPropagator):
+    """The exchange propagator that a non-uniform transfer mesh represents:
+    its values X_mn(u) at the mesh points give the Fourier coefficients of
+    the gauged bond-space propagator by the mesh quadrature
+        Y_{R1R2}(W) = sum_u w_u X_{R1R2}(u) exp(i u.(W - (R1+R2)/2)),
+        X_{R1R2}(u) = sum_{m'n'} c_{m'R1} c_{n'R2} X_{m'n'}(u),
+    for every |W_x|, |W_y| <= wmax, and the propagator at any momentum l is
+    the series exp(i l.(R1+R2)/2) sum_W Y(W) exp(-i l.W) (the TrigPropagator
+    form).  Written with explicit loops over bonds, independently of the
+    oracle's transform."""
+
+    def __init__(self, ff, qx, qy, w, Xm, wmax):
+        self.ff = ff
+        self.Ws = list(itertools.product(range(-wmax, wmax + 1), repeat=2))
+        nb = ff.nff
+        self.B = np.array(ff.bonds, dtype=float)
+        Y = np.zeros((len(self.Ws), nb, nb), dtype=complex)
+        for b1 in range(nb):
+            for b2 in range(nb):
+                xb = np.zeros(qx.size, dtype=complex)
+                for m in range(nb):
+                    for n in range(nb):
+                        coef = ff.c[m, b1] * ff.c[n, b2]
+                        if coef != 0:
+                            xb += coef * Xm[:, m, n]
+                gx = 0.5 * (self.B[b1, 0] + self.B[b2, 0])
+                gy = 0.5 * (self.B[b1, 1] + self.B[b2, 1])
+                for i, (wx, wy) in enumerate(self.Ws):
+                    Y[i, b1, b2] = np.sum(w * xb * np.exp(1j * (qx * (wx - gx) + qy * (wy - gy))))
+        self.Y = Y

@@ -106,3 +106,31 @@ def test_omega_workload_definition():
     assert w.regulator == "omega" and w2.regulator == "T"
     assert w.points[0] == w2.points[0]
     assert w.T0 == 100 * 8.0 and w.Xmax == 10 * 8.0    # bandwidth 8t, t = 1
+
+
+@pytest.mark.parametrize("case,msg", [
+    ("wsum", "sum to 1"), ("zone", "[-pi, pi)"), ("wneg", "weights must be finite"), ("sym", "uniform transfer grid"),
+])
+def test_mesh_validation_without_gpu(lib, case, msg):
+    """Invalid transfer meshes (and a mesh with symmetric states) are rejected
+    before any device call."""
+    import numpy as np
+    from paper_1604_06296_amd.binding import _Mesh, _Options, _Point
+    mesh = synth.refined_mesh(8, 3, [(0.0, 0.0)], radius=1)
+    qx, qy, w = mesh.qx.copy(), mesh.qy.copy(), mesh.w.copy()
+    flags = 0
+    if case == "wsum":
+        w *= 1.001
+    elif case == "zone":
+        qx[3] = 3.5
+    elif case == "wneg":
+        w[0] = -w[0]
+    elif case == "sym":
+        flags = 64    # TUFRG_SYMMETRIC_STATE
+    arr = (_Point * 1)(_Point(1.0, -0.2, -0.3, 3.0, 8, 16, 1, 0))
+    dpp = C.POINTER(C.c_double)
+    m = (_Mesh * 1)(_Mesh(qx.size, qx.ctypes.data_as(dpp), qy.ctypes.data_as(dpp), w.ctypes.data_as(dpp)))
+    h = C.c_void_p()
+    st = lib.tufrg_init_mesh(arr, m, 1, C.byref(_Options(0, flags)), None, C.byref(h))
+    assert st in (-1, -5) and not h.value
+    assert msg in lib.tufrg_last_error(None).decode()
