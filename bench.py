@@ -432,6 +432,22 @@ def leg_surrogate(tf, synth, train_steps):
     Xs = ctx.empty(3)
     rs, ts = timed_flow(ctx, Xs, opts)
     st = ctx.surrogate_stats()
+    # one network (half the inference) at the same tolerance and at a looser one
+    single = {}
+    for tol in (1e-3, 2e-2):
+        c1 = tf.Context([pt], autotune=True)
+        c1.attach_surrogate(nets[0][0], None, tol=tol, check_stride=8)
+        X1 = c1.empty(3)
+        r1, t1 = timed_flow(c1, X1, opts)
+        s1 = c1.surrogate_stats()
+        single[f"tol_{tol:g}"] = {
+            "flow_s": t1, "flow_speedup": te / t1, "exact_fraction": s1["exact_q"] / max(s1["queried_q"], 1),
+            "failed_checks": s1["failed_checks"], "status": r1[0].status, "Tc": r1[0].Tc,
+            "Tc_rel_err": (abs(r1[0].Tc / re[0].Tc - 1) if (re[0].Tc and r1[0].Tc) else None),
+            "X_end_rel_err": float((X1 - Xe).abs().max() / Xe.abs().max())}
+        log(f"[surrogate] one network, tol {tol:g}: {single[f'tol_{tol:g}']}")
+        c1.close()
+    out["single_network"] = single
     X = torch.from_numpy(synth.random_channels(pt.nq, pt.nff, seed=5).reshape(3, -1)).cuda()
     o = exact.empty(3)
     out.update({

@@ -356,15 +356,19 @@ tufrg_status tufrg_loop_harmonics(tufrg_ctx* ctx, const double* T_host, double* 
 tufrg_status tufrg_surrogate_dataset(tufrg_ctx* ctx, const double* T_host, int64_t n, uint64_t seed,
                                      float* x, float* y, int32_t* idx);
 
-/* Route the loops of tufrg_bubbles, tufrg_rhs and tufrg_flow through two
- * surrogate networks (9 inputs, 4 outputs) with an exact fallback, or
+/* Route the loops of tufrg_bubbles, tufrg_rhs and tufrg_flow through one or
+ * two surrogate networks (9 inputs, 4 outputs) with an exact fallback, or
  * detach (a = b = NULL).  Per call, momentum q takes the exact loop kernel
  * when the networks' predicted harmonics differ by more than
- * tol * max_S |prediction at q|, when q = phase (mod check_stride) with the
- * phase advancing by one per call, or while q is flagged; a checked q whose
- * prediction misses the exact harmonics by more than tol * max_S |exact| is
- * flagged together with its 8 neighbours, and a later passing check clears
- * the flag.  Single-point FP64 contexts only (EUNSUPPORTED otherwise).  The
+ * tol * max_S |prediction at q| (two networks only), when q = phase (mod
+ * check_stride) with the phase advancing by one per call, or while q is
+ * flagged; a checked q whose prediction misses the exact harmonics by more
+ * than tol * max_S |exact| is flagged together with its 8 neighbours, and a
+ * later passing check clears the flag.  With b = NULL (one network, half the
+ * inference cost) acceptance rests on the rotating check and the flags.
+ * Either way a prediction is verified at most check_stride calls before it
+ * is used: predictions that are wrong everywhere are all flagged within
+ * check_stride calls, but in between they are used unverified.  Single-point FP64 contexts only (EUNSUPPORTED otherwise).  The
  * networks must outlive the attachment and are used on the context's
  * streams.  Allocates the surrogate's buffers. */
 tufrg_status tufrg_surrogate_attach(tufrg_ctx* ctx, tufrg_mlp* a, tufrg_mlp* b, double tol,

@@ -448,9 +448,11 @@ class Context:
             _dev_array(y, t.float32, 4 * n, "y"), C.c_void_p(idx.data_ptr()) if with_index else None))
         return (x, y, idx) if with_index else (x, y)
 
-    def attach_surrogate(self, a: "MLP", b: "MLP", tol: float = 1e-3, check_stride: int = 8):
+    def attach_surrogate(self, a: "MLP", b: Optional["MLP"] = None, tol: float = 1e-3, check_stride: int = 8):
+        """One network (b None) or an ensemble of two."""
         self._surrogates = (a, b)      # keep the networks alive while attached
-        _check(self.lib, self.ctx, self.lib.tufrg_surrogate_attach(self.ctx, a.net, b.net, tol, check_stride))
+        _check(self.lib, self.ctx, self.lib.tufrg_surrogate_attach(self.ctx, a.net, b.net if b is not None else None,
+                                                                   tol, check_stride))
 
     def detach_surrogate(self):
         _check(self.lib, self.ctx, self.lib.tufrg_surrogate_attach(self.ctx, None, None, 0.0, 0))

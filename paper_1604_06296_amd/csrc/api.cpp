@@ -488,8 +488,14 @@ void surrogate_loops(tufrg_ctx* ctx, const Launch& L, double* dchi, hipStream_t 
   const int64_t rows = (int64_t)d.nirr * d.nsh;
   launch_surrogate_front(L, 0, d, ctx->sur_x, s);
   mlp_forward_on(ctx->sur_a, ctx->sur_x, ctx->sur_ya, rows, s);
-  mlp_forward_on(ctx->sur_b, ctx->sur_x, ctx->sur_yb, rows, s);
-  launch_surrogate_decide(L, 0, d, ctx->sur_ya, ctx->sur_yb, ctx->sur, s);
+  // one network: its prediction is compared with itself (no disagreement),
+  // so acceptance rests on the rotating check and the fallback flags
+  const float* yb = ctx->sur_ya;
+  if (ctx->sur_b) {
+    mlp_forward_on(ctx->sur_b, ctx->sur_x, ctx->sur_yb, rows, s);
+    yb = ctx->sur_yb;
+  }
+  launch_surrogate_decide(L, 0, d, ctx->sur_ya, yb, ctx->sur, s);
   Launch Lg = L;
   Lg.b.item_count = ctx->sur.count;
   Lg.loop_items = ctx->sur.items;
@@ -1108,13 +1114,13 @@ tufrg_status tufrg_surrogate_attach(tufrg_ctx* ctx, tufrg_mlp* a, tufrg_mlp* b, 
   ctx->sur_allocations.clear();
   ctx->sur_a = ctx->sur_b = nullptr;
   if (!a && !b) return TUFRG_OK;
-  if (!a || !b) return fail(ctx, TUFRG_EINVAL, "attach two networks (or none to detach)");
+  if (!a) return fail(ctx, TUFRG_EINVAL, "attach network a (b optional), or none to detach");
   if (ctx->dev.size() != 1) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves single-point contexts");
   if (mixed_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves FP64 contexts");
   if (omega_of(ctx)) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves the temperature flow");
   if (ctx->host[0].mesh) return fail(ctx, TUFRG_EUNSUPPORTED, "the surrogate serves the uniform transfer grid");
   for (tufrg_mlp* m : {a, b})
-    if (mlp_width(m, 0) != 9 || mlp_width(m, -1) != 4)
+    if (m && (mlp_width(m, 0) != 9 || mlp_width(m, -1) != 4))
       return fail(ctx, TUFRG_EINVAL, "surrogate networks map 9 features to 4 targets");
   if (!(tol > 0.0) || check_stride < 1) return fail(ctx, TUFRG_EINVAL, "need tol > 0 and check_stride >= 1");
   const DevTables& d = ctx->dev[0];
@@ -1126,7 +1132,7 @@ tufrg_status tufrg_surrogate_attach(tufrg_ctx* ctx, tufrg_mlp* a, tufrg_mlp* b, 
   st.stride = check_stride;
   ST_TRY(dalloc(ctx, rows * 9, &ctx->sur_x, g));
   ST_TRY(dalloc(ctx, rows * 4, &ctx->sur_ya, g));
-  ST_TRY(dalloc(ctx, rows * 4, &ctx->sur_yb, g));
+  if (b) ST_TRY(dalloc(ctx, rows * 4, &ctx->sur_yb, g));
   ST_TRY(dalloc(ctx, 1, &st.phase, g));
   ST_TRY(dalloc(ctx, (size_t)d.nirr, &st.state, g));
   ST_TRY(dalloc(ctx, (size_t)d.nirr, &st.need, g));

@@ -8,8 +8,8 @@
 // with (R_a, R_b) the canonical bond pair of S_j; targets (4):
 //   (T (1 + 4T) ghat_pp, (1 + 4T^2) ghat_ph, 0, 0).
 // Inference runs on the representatives of the transfer momenta (point-group
-// orbits; the expansion kernel serves the rest).  Two networks predict every
-// query; a representative takes the exact loop kernel when the networks
+// orbits; the expansion kernel serves the rest).  One or two networks predict
+// every query; a representative takes the exact loop kernel when two networks
 // disagree by more than tol relative to its largest predicted harmonic, when
 // it is in this call's check set (slot = phase mod stride, rotating per
 // call), or when its fallback flag is set.  Checked representatives compare

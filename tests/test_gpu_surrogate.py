@@ -12,6 +12,7 @@ import pytest
 
 import synth
 from oracle import bubbles as obub
+from oracle import rhs as orhs
 from oracle import surrogate as osur
 from oracle.lattice import FormFactors, q_grid
 
@@ -221,3 +222,70 @@ def test_surrogate_flow_graph_equals_exact(tf):
         assert abs(rs.Tc / re.Tc - 1) < 1e-9
     ref = Xe.cpu().numpy()
     assert np.abs(Xs.cpu().numpy() - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def _high_T_nets(tf, pt, nets=2, steps=3000):
+    """Networks trained briefly on the point's own exact loop harmonics at
+    2 <= T <= 8 (smooth loops), with their validation error there."""
+    import torch
+    from paper_1604_06296_amd import surrogate as sur
+    temps = np.exp(np.random.default_rng(7).uniform(np.log(2.0), np.log(8.0), (5, 16)))
+    x, y = sur.make_training_set([pt] * 16, temps[:4], 16384, seed=40)
+    xv, yv = sur.make_training_set([pt] * 16, temps[4:], 8192, seed=90)
+    out = sur.train_ensemble(x, y, steps=steps, batch=1024, lr=2e-3, seeds=tuple(range(1, nets + 1)),
+                             max_rows=4096)
+    errs = [sur.validation_error(n, xv, yv)["rel_rms"] for n, _, _ in out]
+    torch.cuda.synchronize()
+    return [n for n, _, _ in out], max(errs)
+
+
+@pytest.mark.parametrize("nets", [2, 1])
+def test_surrogate_accepted_predictions_match_oracle(tf, nets):
+    """Where predictions are accepted (networks trained at high T, a tolerance
+    that admits them), the loops and the right-hand side stay within the
+    acceptance tolerance of the oracle's: chi' within 8 tol max|chi'| (each
+    entry sums a few harmonics, each off by at most ~tol of the largest),
+    and the stats show that predictions were used."""
+    torch = _torch()
+    from oracle import bubbles as obub
+    pt = _pt(1, 8, 16, tp=-0.25, mu=-0.7)
+    ff = FormFactors(1)
+    models, err = _high_T_nets(tf, pt, nets=nets)
+    tol = max(4.0 * err, 1e-3)
+    print(f"[surrogate] {nets} net(s): validation rel. error {err:.2e}, tol {tol:.2e}", flush=True)
+    assert tol < 0.2
+    ctx = tf.Context([pt])
+    ctx.attach_surrogate(models[0], models[1] if nets == 2 else None, tol=tol, check_stride=8)
+    X = synth.random_channels(pt.nq, ff.nff, seed=8, scale=0.3)
+    Xd = torch.from_numpy(X.reshape(3, -1)).cuda()
+    for T in (4.0, 3.0, 5.0):
+        got = ctx.view(ctx.bubbles(T)).cpu().numpy()
+        ref = obub.bubbles(pt, T, "dot", ff)
+        assert np.abs(got - ref).max() <= 8 * tol * np.abs(ref).max(), T
+        gr = ctx.view(ctx.rhs(T, Xd)).cpu().numpy()
+        rr = orhs.rhs(pt, T, X, ff)
+        assert np.abs(gr - rr).max() <= 30 * tol * np.abs(rr).max(), T
+    st = ctx.surrogate_stats()
+    print(f"[surrogate] stats {st}", flush=True)
+    assert st["exact_q"] < st["queried_q"]          # predictions were accepted
+
+
+def test_single_network_wrong_everywhere_is_flagged_within_one_rotation(tf):
+    """One untrained network (no ensemble): only the rotating check guards it.
+    Within check_stride calls every representative is checked, fails and is
+    flagged, after which the loops are exact again."""
+    torch = _torch()
+    pt = _pt(1, 8, 16)
+    exact = tf.Context([pt])
+    ctx = tf.Context([pt])
+    a = tf.MLP(WIDTHS, max_rows=4096, seed=23)
+    stride = 4
+    ctx.attach_surrogate(a, None, tol=1e-3, check_stride=stride)
+    T = 0.4
+    for _ in range(stride):
+        ctx.bubbles(T)
+    st = ctx.surrogate_stats()
+    assert st["failed_checks"] == _orbits(pt.Lq)
+    ref = exact.bubbles(T).cpu().numpy()
+    got = ctx.bubbles(T).cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
