@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-omega", action="store_true")
     ap.add_argument("--no-wedge", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--train-steps", type=int, default=8000)
     ap.add_argument("--probe-loops", type=int, default=0,
@@ -399,6 +400,35 @@ def leg_wedge(tf, synth, steps, Tc_ref):
     return out
 
 
+def leg_dense(tf, synth, steps):
+    """The dense projection operator against the factored projections at small
+    sizes (the precomputed-projection-data option of the paper): projection
+    and right-hand side times, and the operator's size."""
+    import torch
+    out = {}
+    for name, pt in (("q8_nff1", synth.Point(t=1.0, tp=0.0, U=3.0, Lq=8, Lk=32, shells=0, mu=0.0)),
+                     ("q16_nff1", synth.Point(t=1.0, tp=0.0, U=3.0, Lq=16, Lk=64, shells=0, mu=0.0)),
+                     ("q8_nff5", synth.cfg1().points[0])):
+        X = torch.from_numpy(synth.random_channels(pt.nq, pt.nff, seed=5).reshape(3, -1)).cuda()
+        row = {"N": 3 * pt.nq * pt.nff ** 2, "operator_MB": 8e-6 * (3 * pt.nq * pt.nff ** 2) ** 2}
+        for form, dense in (("factored", False), ("dense", True)):
+            ctx = tf.Context([pt], dense_projection=dense)
+            o = ctx.empty(3)
+            for _ in range(10):
+                ctx.project(X, o)
+            _sync()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ctx.project(X, o)
+            _sync()
+            row[f"project_us_{form}"] = 1e6 * (time.perf_counter() - t0) / steps
+            row[f"rhs_us_{form}"] = 1e6 * time_rhs(ctx, 0.05, X, o, n=steps)
+            ctx.close()
+        out[name] = row
+        log(f"[dense] {name}: {row}")
+    return out
+
+
 def leg_surrogate(tf, synth, train_steps):
     """cfg5: surrogate trained on 2M exact samples; flow with and without it."""
     import torch
@@ -539,6 +569,7 @@ def main():
     Tc_ref = flow_info["Tc"] if flow_info else None
     for name, skip, fn in (("omega", args.no_omega, lambda: leg_omega(tf, synth, args.steps)),
                            ("wedge", args.no_wedge, lambda: leg_wedge(tf, synth, args.steps, Tc_ref)),
+                           ("dense", args.no_dense, lambda: leg_dense(tf, synth, args.steps)),
                            ("mixed", args.no_mixed, lambda: leg_mixed(tf, synth)),
                            ("batched", args.no_batched, lambda: leg_batched(tf, synth)),
                            ("surrogate", args.no_surrogate, lambda: leg_surrogate(tf, synth, args.train_steps))):

@@ -141,6 +141,19 @@ enum {
                                validate states with tufrg_symmetry_defect;
                                tufrg_flow checks its initial state and returns
                                EINVAL when its relative defect exceeds 1e-12. */
+  TUFRG_DENSE_PROJECTION = 1u << 7, /* precompute the projections' cross terms as
+                               one dense operator per point (the reusable
+                               projection data of Sec. 2.5, the stored tensors of
+                               the appendix on symmetries): tufrg_init applies the
+                               factored projections to every unit state
+                               (3 Nq Nff^2 of them) and stores the results, a
+                               (3 Nq Nff^2)^2 FP64 matrix; the step calls then
+                               replace forward transform, bond basis, gather and
+                               inverse transform by one operator product.  Small
+                               points only (3 Nq Nff^2 <= 8192, else EINVAL); FP64
+                               per-momentum contexts (EUNSUPPORTED with
+                               TUFRG_MIXED or TUFRG_SYMMETRIC_STATE).  Results equal
+                               the factored path's up to summation order. */
   TUFRG_NO_FUSE = 1u << 4  /* never run the right-hand side in fused launches.  By
                                default a context whose channel state (sum of
                                Nq Nff^2 over its points) is at most 2^18 runs the
@@ -156,7 +169,7 @@ typedef struct {
   int32_t precision;       /* TUFRG_FP64 or TUFRG_MIXED */
   uint32_t flags;          /* TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE |
                               TUFRG_NO_SYMMETRY | TUFRG_NO_FUSE | TUFRG_OMEGA_CUTOFF |
-                              TUFRG_SYMMETRIC_STATE */
+                              TUFRG_SYMMETRIC_STATE | TUFRG_DENSE_PROJECTION */
 } tufrg_options;
 
 enum { TUFRG_RK4_LOG = 0, TUFRG_DOPRI5_LOG = 1 };

@@ -114,6 +114,8 @@ hipError_t resolve_scratch(int dev, void** out) {
 }
 
 constexpr double kSymmetryTol = 1e-12;   // relative covariance defect accepted as symmetric
+constexpr int64_t kDenseMaxN = 8192;      // largest 3 Nq Nff^2 of the dense projection operator (512 MiB)
+constexpr int kDenseColsHost = 64;        // its column splits (the kernel's kDenseCols)
 
 double word_to_double(unsigned long long w) {
   double d;
@@ -155,7 +157,7 @@ void default_geometry(DevTables& d) {
 
 // ------------------------------------------------------------ item tables
 struct HostItems {
-  std::vector<int4> loop, exp, expw, fwd, basis, gather, inv, prod, seg;
+  std::vector<int4> loop, exp, expw, fwd, basis, gather, inv, prod, seg, dpart, dsum;
   std::vector<int2> gent;   // gather rows' entries, gather_cap per row
 };
 
@@ -238,6 +240,17 @@ void add_point_items(const DevTables& d, const HostTables& t, int p, int inv_lt,
     for (int c = 0; c < 3; ++c)
       for (int k = 0; k < chunks; ++k) v.push_back(make_int4(p, c, k, 0));
   });
+  // dense projection operator: (p, tile of 256 rows, column split), (p, tile)
+  if (d.dense_A) {
+    const int tiles = (3 * d.nq * nff2 + 255) / 256;
+    mark(h.dpart, r.dpart, [&](std::vector<int4>& v) {
+      for (int s2 = 0; s2 < d.dense_splits; ++s2)
+        for (int rt = 0; rt < tiles; ++rt) v.push_back(make_int4(p, rt, s2, 0));
+    });
+    mark(h.dsum, r.dsum, [&](std::vector<int4>& v) {
+      for (int rt = 0; rt < tiles; ++rt) v.push_back(make_int4(p, rt, 0, 0));
+    });
+  }
 }
 
 // harmonic tiles of 16 rows the forward transform of point d needs (the
@@ -360,6 +373,8 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   all.basis = whole(h.basis); all.gather = whole(h.gather);
   all.inv = whole(h.inv); all.prod = whole(h.prod);
   all.seg = whole(h.seg);
+  all.dpart = whole(h.dpart);
+  all.dsum = whole(h.dsum);
   all.nfwd_cls = 0;
   for (int p : by_nff) {
     const ItemRange& fr = ctx->per_point[p].fwd;
@@ -406,6 +421,8 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   }
   ST_TRY(upload(ctx, h.prod, &t, g)); L.prod_items = t;
   ST_TRY(upload(ctx, h.seg, &t, g)); L.seg_items = t;
+  ST_TRY(upload(ctx, h.dpart, &t, g)); L.dpart_items = t;
+  ST_TRY(upload(ctx, h.dsum, &t, g)); L.dsum_items = t;
   ST_TRY(dalloc(ctx, (size_t)std::max<int64_t>(gh, 1), &L.b.ghat, g));
   ctx->ghat = L.b.ghat;
   DevTables* dp = nullptr;
@@ -579,9 +596,13 @@ void rhs_launch(tufrg_ctx* ctx, const Launch& L0, const Ranges& r0, const double
     } else {
       set_T_launch(ctx, ts, ms);
     }
-    launch_loops_fwd(L, r, X, mixed, cross, ta, ms);
-    launch_expand_basis(L, r, L.b.dchi, cross, ms);
-    if (cross) launch_gather_inv(L, r, mixed, ms);
+    // with the dense projection operator the loops share no launch with the
+    // forward transform: the cross terms come from one operator product
+    const bool factored = cross && !L.dense;
+    launch_loops_fwd(L, r, X, mixed, factored, ta, ms);
+    launch_expand_basis(L, r, L.b.dchi, factored, ms);
+    if (factored) launch_gather_inv(L, r, mixed, ms);
+    else if (cross) launch_dense(L, r, X, ms);
     launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms);
     return;
   }
@@ -591,7 +612,8 @@ void rhs_launch(tufrg_ctx* ctx, const Launch& L0, const Ranges& r0, const double
   set_T_launch(ctx, ts, ctx->side);
   loops_launch(ctx, L, r, L.b.dchi, ctx->side);
   (void)hipEventRecord(ctx->ev_join, ctx->side);
-  if (cross) launch_front(L, r, X, mixed, ms);
+  if (cross && L.dense) launch_dense(L, r, X, ms);
+  else if (cross) launch_front(L, r, X, mixed, ms);
   (void)hipStreamWaitEvent(ms, ctx->ev_join, 0);
   launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms);
 }
@@ -610,6 +632,37 @@ tufrg_status check_temperatures(tufrg_ctx* ctx, const double* T_host) {
   for (size_t p = 0; p < ctx->dev.size(); ++p)
     if (!(T_host[p] > 0.0) || !std::isfinite(T_host[p]))
       return fail(ctx, TUFRG_EINVAL, "T must be finite and > 0 (point " + std::to_string(p) + ")");
+  return TUFRG_OK;
+}
+
+// The dense projection operator of every point (precomputed projection data,
+// Sec. 2.5 and the stored projection tensors of the appendix on symmetries):
+// column j of A is the projections' cross terms K of the unit state e_j,
+// computed by the factored path, so that afterwards one operator product
+// replaces the forward transform, bond basis, gather and inverse transform.
+tufrg_status build_dense(tufrg_ctx* ctx) {
+  double* Xp = nullptr;
+  const size_t n3 = 3 * (size_t)ctx->S;
+  if (hipMalloc(&Xp, n3 * sizeof(double)) != hipSuccess) return fail(ctx, TUFRG_ENOMEM, "dense operator probe");
+  hipError_t e = hipMemsetAsync(Xp, 0, n3 * sizeof(double), ctx->stream);
+  int64_t prev = -1;
+  for (size_t p = 0; p < ctx->dev.size() && e == hipSuccess; ++p) {
+    const DevTables& d = ctx->dev[p];
+    const int64_t nqn = (int64_t)d.nq * d.nff * d.nff, N = 3 * nqn;
+    for (int64_t j = 0; j < N && e == hipSuccess; ++j) {
+      const int64_t cur = (j / nqn) * ctx->S + d.off + j % nqn;
+      launch_set_unit(Xp, prev, cur, ctx->stream);
+      prev = cur;
+      launch_front(ctx->L, ctx->per_point[p], Xp, false, ctx->stream);
+      e = hipMemcpyAsync(d.dense_A + j * N, ctx->L.b.kinv64 + d.ws_k, (size_t)N * sizeof(double),
+                         hipMemcpyDeviceToDevice, ctx->stream);
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  (void)hipFree(Xp);
+  if (e != hipSuccess) return fail(ctx, TUFRG_EHIP, std::string("dense operator: ") + hipGetErrorString(e));
+  ctx->L.dense = true;
   return TUFRG_OK;
 }
 
@@ -778,8 +831,10 @@ tufrg_status tufrg_init_mesh(const tufrg_point* pts, const tufrg_mesh* meshes, i
   if (o.precision != TUFRG_FP64 && o.precision != TUFRG_MIXED)
     return fail(nullptr, TUFRG_EINVAL, "precision must be TUFRG_FP64 or TUFRG_MIXED");
   if (o.flags & ~(uint32_t)(TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE | TUFRG_NO_SYMMETRY |
-                            TUFRG_NO_FUSE | TUFRG_OMEGA_CUTOFF | TUFRG_SYMMETRIC_STATE))
+                            TUFRG_NO_FUSE | TUFRG_OMEGA_CUTOFF | TUFRG_SYMMETRIC_STATE | TUFRG_DENSE_PROJECTION))
     return fail(nullptr, TUFRG_EINVAL, "unknown flag bits");
+  if ((o.flags & TUFRG_DENSE_PROJECTION) && (o.precision != TUFRG_FP64 || (o.flags & TUFRG_SYMMETRIC_STATE)))
+    return fail(nullptr, TUFRG_EUNSUPPORTED, "the dense projection operator serves FP64 per-momentum contexts");
   auto* ctx = new tufrg_ctx();
   ctx->opt = o;
   ctx->stream = static_cast<hipStream_t>(stream);
@@ -924,6 +979,25 @@ tufrg_status tufrg_init_mesh(const tufrg_point* pts, const tufrg_mesh* meshes, i
   if (!st && o.precision == TUFRG_MIXED) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_k, 1), &B.kinv, A);
   if (!st && o.precision != TUFRG_MIXED) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_k, 1), &B.kinv64, A);
   if (!st) st = dalloc(ctx, (size_t)std::max<int64_t>(ws_xp, 1), &B.xp, A);
+  B.dense_ws = nullptr;
+  if (!st && (o.flags & TUFRG_DENSE_PROJECTION)) {
+    // the dense operator of every point (filled below) and the partial sums
+    int64_t wsd = 0;
+    for (int p = 0; p < npts && !st; ++p) {
+      DevTables& d = ctx->dev[p];
+      const int64_t N = 3 * (int64_t)d.nq * d.nff * d.nff;
+      if (N > kDenseMaxN) {
+        st = fail(ctx, TUFRG_EINVAL, "point " + std::to_string(p) + ": the dense projection operator needs 3 Nq Nff^2 <= " +
+                                         std::to_string(kDenseMaxN) + " (it stores (3 Nq Nff^2)^2 doubles)");
+        break;
+      }
+      st = dalloc(ctx, (size_t)(N * N), &d.dense_A, A);
+      d.dense_splits = (int)((N + kDenseColsHost - 1) / kDenseColsHost);
+      d.ws_dp = wsd;
+      wsd += (int64_t)d.dense_splits * N;
+    }
+    if (!st) st = dalloc(ctx, (size_t)std::max<int64_t>(wsd, 1), &B.dense_ws, A);
+  }
   if (!st) st = dalloc(ctx, (size_t)npts, &ctx->Tp, A);
   if (!st) st = dalloc(ctx, (size_t)npts, &ctx->frozen, A);
   if (!st) st = dalloc(ctx, 2, &ctx->queue, A);
@@ -952,6 +1026,7 @@ tufrg_status tufrg_init_mesh(const tufrg_point* pts, const tufrg_mesh* meshes, i
   // item tables and launch shapes, tuned on request
   st = build_launch(ctx);
   if (!st && (o.flags & TUFRG_AUTOTUNE)) st = autotune(ctx);
+  if (!st && (o.flags & TUFRG_DENSE_PROJECTION)) st = build_dense(ctx);
   if (st) return bad(st);
   if (hipDeviceSynchronize() != hipSuccess)
     return bad(fail(ctx, TUFRG_EHIP, "device synchronize failed after init"));
@@ -998,7 +1073,8 @@ tufrg_status tufrg_project(tufrg_ctx* ctx, const double* X, double* V) {
   if (!X || !V) return fail(ctx, TUFRG_EINVAL, "NULL argument");
   if (X == V) return fail(ctx, TUFRG_EINVAL, "X and V must not alias");
   const bool mixed = mixed_of(ctx), cross = cross_of(ctx);
-  if (cross) launch_front(ctx->L, ctx->all, X, mixed, ctx->stream);
+  if (cross && ctx->L.dense) launch_dense(ctx->L, ctx->all, X, ctx->stream);
+  else if (cross) launch_front(ctx->L, ctx->all, X, mixed, ctx->stream);
   launch_back(ctx->L, ctx->all, X, V, 0, cross, false, mixed, ctx->stream);
   HIP_TRY(ctx, hipGetLastError());
   return TUFRG_OK;

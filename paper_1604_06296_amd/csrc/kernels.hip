@@ -834,6 +834,76 @@ __global__ void k_set_T_sh(double* Tp, int npts, const double* __restrict__ s_ar
   if (i < npts) Tp[i] = exp(fma(c, h_arr[i], s_arr[i]));
 }
 
+// Dense projection operator (TUFRG_DENSE_PROJECTION, small contexts): the
+// cross terms K of the projections as one matrix A of the point's state,
+// K_i = sum_j A_ij X_j over the point's local index i = ch Nq Nff^2 + q Nff^2 +
+// mn (the layout of K), A stored column-major (column j = K of the unit state
+// e_j).  Item (p, tile of 256 rows, split of kDenseCols columns): the partial
+// sum over the split's columns, each thread one row (column loads coalesced
+// across the block, the split's X values staged in LDS).
+constexpr int kDenseCols = 64;
+__global__ void __launch_bounds__(256)
+k_dense_part(Batch b, const int4* __restrict__ items, const double* __restrict__ X) {
+  __shared__ double xs[kDenseCols];
+  const int4 it = items[blockIdx.x];
+  if (skip_point(b, it.x)) return;
+  const DevTables& d = b.pts[it.x];
+  const int64_t nqn = (int64_t)d.nq * d.nff * d.nff, N = 3 * nqn;
+  const int64_t j0 = (int64_t)it.z * kDenseCols;
+  const int nj = (int)min((int64_t)kDenseCols, N - j0);
+  if ((int)threadIdx.x < nj) {
+    const int64_t j = j0 + threadIdx.x;
+    xs[threadIdx.x] = X[(j / nqn) * b.S + d.off + j % nqn];
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)it.y * 256 + threadIdx.x;
+  if (i >= N) return;
+  const double* a = d.dense_A + j0 * N + i;
+  double acc = 0.0;
+  int j = 0;
+  for (; j + 4 <= nj; j += 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = a[(int64_t)(j + u) * N];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = fma(v[u], xs[j + u], acc);
+  }
+  for (; j < nj; ++j) acc = fma(a[(int64_t)j * N], xs[j], acc);
+  double* part = b.dense_ws + d.ws_dp;
+  part[(int64_t)it.z * N + i] = acc;
+}
+
+// K_i = the splits' partial sums added in split order; item (p, tile of 256 rows)
+__global__ void __launch_bounds__(256)
+k_dense_sum(Batch b, const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  if (skip_point(b, it.x)) return;
+  const DevTables& d = b.pts[it.x];
+  const int64_t N = 3 * (int64_t)d.nq * d.nff * d.nff;
+  const int64_t i = (int64_t)it.y * 256 + threadIdx.x;
+  if (i >= N) return;
+  const double* part = b.dense_ws + d.ws_dp + i;
+  double acc = 0.0;
+  int s = 0;
+  for (; s + 4 <= d.dense_splits; s += 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = part[(int64_t)(s + u) * N];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += v[u];
+  }
+  for (; s < d.dense_splits; ++s) acc += part[(int64_t)s * N];
+  b.kinv64[d.ws_k + i] = acc;
+}
+
+// X[prev] = 0, X[cur] = 1 (the unit states that probe the dense operator)
+__global__ void k_set_unit(double* X, int64_t prev, int64_t cur) {
+  if (threadIdx.x == 0) {
+    if (prev >= 0) X[prev] = 0.0;
+    if (cur >= 0) X[cur] = 1.0;
+  }
+}
+
 // Largest deviation of a state from the C4v covariance law, per point:
 // max over channels, orbit members q of representative r and (m, n) of
 // |X(q)_mn - s_m s_n X(r)_{pi(m) pi(n)}| as an ordered bit pattern (NaN sorts
@@ -1001,6 +1071,17 @@ void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed,
   if (r.basis.n > 0)
     hipLaunchKernelGGL(k_bond_basis, dim3(r.basis.n), dim3(256), 0, s, L.b, L.basis_items + r.basis.begin);
   launch_gather_inv(L, r, mixed, s);
+}
+
+void launch_dense(const Launch& L, const Ranges& r, const double* X, hipStream_t s) {
+  if (r.dpart.n > 0)
+    hipLaunchKernelGGL(k_dense_part, dim3(r.dpart.n), dim3(256), 0, s, L.b, L.dpart_items + r.dpart.begin, X);
+  if (r.dsum.n > 0)
+    hipLaunchKernelGGL(k_dense_sum, dim3(r.dsum.n), dim3(256), 0, s, L.b, L.dsum_items + r.dsum.begin);
+}
+
+void launch_set_unit(double* X, int64_t prev, int64_t cur, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_unit, dim3(1), dim3(64), 0, s, X, prev, cur);
 }
 
 void launch_expand_basis(const Launch& L, const Ranges& r, double* dchi, bool cross, hipStream_t s) {

@@ -111,6 +111,9 @@ struct DevTables {
   int64_t ws_xp;          // offset of the forward-transform partial sums [nsu][ncol][3 nff^2]
   int64_t ws_gh;          // offset of the point's loop-harmonic slices [nsplit][nirr][2][nsh]
   int64_t gh_off;         // offset of the point's harmonics [nq][2][nsh] in harmonic outputs
+  double* dense_A;        // dense projection operator [N][N] column-major (N = 3 nq nff^2), or null
+  int64_t ws_dp;          // offset of its partial products [dense_splits][N] in the dense workspace
+  int dense_splits;       // splits of the operator's columns
   double* cre;            // [nff*nff]
   double* cim;
   int* shell_start;       // [nshell+1]
@@ -151,6 +154,7 @@ struct Batch {
   float* kinv;            // inverse transforms (mixed precision)
   double* kinv64;         // inverse transforms (FP64)
   double* ghat;           // loop-harmonic slices (all points, at ws_gh)
+  double* dense_ws;       // partial products of the dense projection operator (or null)
   const int* item_count;  // loops: when set, only the first *item_count items run
   int loop_threads;       // threads of the loop geometry (fixes the loops' summation order)
   int wedge;              // symmetric states: inverse transform and products at the orbit
@@ -165,6 +169,7 @@ struct ItemRange {
 struct Ranges {
   ItemRange loop, exp, fwd, basis, gather, inv, prod, seg;
   ItemRange exp_w;   // loop expansion at the orbit representatives (symmetric states)
+  ItemRange dpart, dsum;   // dense projection operator: partial products, their sums
   // the product items by N_ff (contiguous runs of prod): one launch each, with
   // the shared memory of its own N_ff, so that small matrices are not held to
   // the occupancy of the largest
@@ -221,6 +226,9 @@ struct Launch {
   int gather_cap;          // entries per gather row (padded with re = -1)
   const int4* prod_items;
   const int4* seg_items;
+  const int4* dpart_items;  // dense projection: (p, row tile, column split)
+  const int4* dsum_items;   // (p, row tile)
+  bool dense = false;       // projections by the dense operator (TUFRG_DENSE_PROJECTION)
   int loop_threads, loop_blocks, smax_max;
   int fwd_kt;             // forward transform: 16-row harmonic tiles (1, 2, 3 or 5)
   int inv_lt;             // inverse transform: 16-momentum tiles per item (1, 2 or 4)
@@ -258,6 +266,9 @@ void launch_loops(const Launch& L, const ItemRange& r, int* queue, bool mixed, h
 void launch_chi_expand(const Launch& L, const ItemRange& r, const double* fin, double* dchi,
                        hipStream_t s);
 void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s);
+// the projections' cross terms K (inverse-transform output) by the dense operator
+void launch_dense(const Launch& L, const Ranges& r, const double* X, hipStream_t s);
+void launch_set_unit(double* X, int64_t prev, int64_t cur, hipStream_t s);
 void launch_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s);
 void launch_gather_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t s);
 void launch_loops_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, bool cross,
