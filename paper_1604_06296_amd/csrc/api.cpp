@@ -563,7 +563,7 @@ void set_T_launch(tufrg_ctx* ctx, const TSource& ts, hipStream_t s) {
 // loops run on the side stream (fork and join by events) alongside the
 // whole projection chain.
 void rhs_launch(tufrg_ctx* ctx, const Launch& L0, const Ranges& r0, const double* X, double* out,
-                bool scale_T, hipStream_t ms, const TSource& ts) {
+                bool scale_T, hipStream_t ms, const TSource& ts, const StageNext* sn = nullptr) {
   const bool mixed = mixed_of(ctx), cross = cross_of(ctx);
   // symmetric states: the loop expansion at the representatives only
   Launch L = L0;
@@ -603,7 +603,7 @@ void rhs_launch(tufrg_ctx* ctx, const Launch& L0, const Ranges& r0, const double
     launch_expand_basis(L, r, L.b.dchi, factored, ms);
     if (factored) launch_gather_inv(L, r, mixed, ms);
     else if (cross) launch_dense(L, r, X, ms);
-    launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms);
+    launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms, sn);
     return;
   }
   // fork and join: errors of these calls are read with hipGetLastError by every caller
@@ -615,13 +615,14 @@ void rhs_launch(tufrg_ctx* ctx, const Launch& L0, const Ranges& r0, const double
   if (cross && L.dense) launch_dense(L, r, X, ms);
   else if (cross) launch_front(L, r, X, mixed, ms);
   (void)hipStreamWaitEvent(ms, ctx->ev_join, 0);
-  launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms);
+  launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms, sn);
 }
 
 tufrg_status ensure_flow_buffers(tufrg_ctx* ctx) {
   if (ctx->flow_ready) return TUFRG_OK;
   const size_t s3 = 3 * (size_t)ctx->S;
   ST_TRY(dalloc(ctx, s3, &ctx->stage, ctx->allocations));
+  ST_TRY(dalloc(ctx, s3, &ctx->stage2, ctx->allocations));
   ST_TRY(dalloc(ctx, s3, &ctx->ytmp, ctx->allocations));
   for (int i = 0; i < 7; ++i) ST_TRY(dalloc(ctx, s3, &ctx->kk[i], ctx->allocations));
   ctx->flow_ready = true;
@@ -1408,14 +1409,42 @@ void rk4_step(tufrg_ctx* ctx, const Launch& L, double* X, double h, double xmax,
   const double fin[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
   const Ranges& r = ctx->all;
   auto stage_T = [](int stage) { return TSource{nullptr, 0, 0, stage}; };
-  rhs_launch(ctx, L, r, X, k[0], true, ms, stage_T(0));
-  launch_axpy(L, r.seg, X, &k[0], half, 1, h, ctx->stage, true, ms);
-  rhs_launch(ctx, L, r, ctx->stage, k[1], true, ms, stage_T(1));
-  launch_axpy(L, r.seg, X, &k[1], half, 1, h, ctx->stage, true, ms);
-  rhs_launch(ctx, L, r, ctx->stage, k[2], true, ms, stage_T(2));
-  launch_axpy(L, r.seg, X, &k[2], one, 1, h, ctx->stage, true, ms);
-  rhs_launch(ctx, L, r, ctx->stage, k[3], true, ms, stage_T(3));
-  launch_axpy(L, r.seg, X, k, fin, 4, h, X, true, ms);
+  if (!L.fused) {
+    // large contexts: the stage combinations as streaming kernels of their own
+    rhs_launch(ctx, L, r, X, k[0], true, ms, stage_T(0));
+    launch_axpy(L, r.seg, X, &k[0], half, 1, h, ctx->stage, true, ms);
+    rhs_launch(ctx, L, r, ctx->stage, k[1], true, ms, stage_T(1));
+    launch_axpy(L, r.seg, X, &k[1], half, 1, h, ctx->stage, true, ms);
+    rhs_launch(ctx, L, r, ctx->stage, k[2], true, ms, stage_T(2));
+    launch_axpy(L, r.seg, X, &k[2], one, 1, h, ctx->stage, true, ms);
+    rhs_launch(ctx, L, r, ctx->stage, k[3], true, ms, stage_T(3));
+    launch_axpy(L, r.seg, X, k, fin, 4, h, X, true, ms);
+    launch_maxabs(L, r.seg, X, ctx->umax, ms);
+    launch_step_end(ctx->umax, npts, ctx->frozen, ctx->hist, ctx->step, nsteps, xmax, ms);
+    return;
+  }
+  // small (launch-bound) contexts: each stage combination is formed by the
+  // products of the slope before it (X + h/2 k1, X + h/2 k2, X + h k3 in
+  // alternating buffers, then the update of X in place)
+  auto next = [&](double* dst, const double* coef, int nk, double* const* ks) {
+    StageNext sn{};
+    sn.X = X;
+    for (int j = 0; j < nk; ++j) {
+      sn.k[j] = ks[j];
+      sn.coef[j] = coef[j];
+    }
+    sn.out = dst;
+    sn.h = h;
+    sn.nk = nk;
+    return sn;
+  };
+  double* st[2] = {ctx->stage, ctx->stage2};
+  const StageNext n1 = next(st[0], half, 1, &k[0]), n2 = next(st[1], half, 1, &k[1]);
+  const StageNext n3 = next(st[0], one, 1, &k[2]), n4 = next(X, fin, 4, k);
+  rhs_launch(ctx, L, r, X, k[0], true, ms, stage_T(0), &n1);
+  rhs_launch(ctx, L, r, st[0], k[1], true, ms, stage_T(1), &n2);
+  rhs_launch(ctx, L, r, st[1], k[2], true, ms, stage_T(2), &n3);
+  rhs_launch(ctx, L, r, st[0], k[3], true, ms, stage_T(3), &n4);
   launch_maxabs(L, r.seg, X, ctx->umax, ms);
   launch_step_end(ctx->umax, npts, ctx->frozen, ctx->hist, ctx->step, nsteps, xmax, ms);
 }
@@ -1551,7 +1580,6 @@ tufrg_status flow_dopri5_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X
   const int npts = (int)ctx->dev.size();
   double* k[7];
   for (int i = 0; i < 7; ++i) k[i] = ctx->kk[i];
-  double* stage = ctx->stage;
   double* y5 = ctx->ytmp;
   const Ranges& r = ctx->all;
   if (ctx->nred < r.seg.n) {
@@ -1613,6 +1641,13 @@ tufrg_status flow_dopri5_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X
     return ts;
   };
   rhs_launch(ctx, Lf, r, X, k[0], true, ms, stage_T(0.0));
+  // stage i of an attempt lives in stg[i & 1]; the acceptance kernel forms
+  // stage 1 of the next attempt, and in small (launch-bound) contexts the
+  // products of stage i form stage i + 1 (i < 6), in large ones streaming
+  // stage kernels of their own
+  double* stg[2] = {ctx->stage, ctx->stage2};
+  const bool fuse_stages = Lf.fused;
+  launch_axpy(Lf, r.seg, X, k, kDpA[1], 1, 0.0, stg[1], true, ms, h_arr);
   double e[7];
   for (int j = 0; j < 7; ++j) e[j] = kDpB5[j] - kDpB4[j];
   DpControl dc{};
@@ -1630,12 +1665,23 @@ tufrg_status flow_dopri5_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X
   dc.npts = npts;
   auto attempt = [&]() {
     for (int i = 1; i < 7; ++i) {
-      launch_axpy(Lf, r.seg, X, k, kDpA[i], i, 0.0, stage, true, ms, h_arr);
-      rhs_launch(ctx, Lf, r, stage, k[i], true, ms, stage_T(kDpC[i]));
+      if (i > 1 && !fuse_stages) launch_axpy(Lf, r.seg, X, k, kDpA[i], i, 0.0, stg[i & 1], true, ms, h_arr);
+      StageNext sn{};
+      if (i < 6 && fuse_stages) {
+        sn.X = X;
+        for (int j = 0; j <= i; ++j) {
+          sn.k[j] = k[j];
+          sn.coef[j] = kDpA[i + 1][j];
+        }
+        sn.out = stg[(i + 1) & 1];
+        sn.hp = h_arr;
+        sn.nk = i + 1;
+      }
+      rhs_launch(ctx, Lf, r, stg[i & 1], k[i], true, ms, stage_T(kDpC[i]), sn.nk > 0 ? &sn : nullptr);
     }
     launch_dp_final(Lf, r.seg, X, k, kDpB5, e, 0.0, o->rtol, o->atol, y5, ctx->red, ctx->umax, ms, h_arr);
     launch_dp_control(dc, ms);
-    launch_dp_accept(Lf, r.seg, ctx->dp_state, y5, k[6], X, k[0], ms);
+    launch_dp_accept(Lf, r.seg, ctx->dp_state, y5, k[6], X, k[0], kDpA[1][0], h_arr, stg[1], ms);
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;

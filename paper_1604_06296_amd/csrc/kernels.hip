@@ -10,6 +10,8 @@
 // flow has stopped are skipped through a per-point device flag.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cstdint>
 
@@ -384,11 +386,14 @@ k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
 // s = ln T, if scale_T, else 1) or V (mode 0), in FP64.  With symmetric
 // states (b.wedge) the item is (p, representative l, its slot) and the result
 // goes to every member q of the orbit as Y(q)_mn = s_m s_n Y(l)_{pi(m) pi(n)}
-// (the point-group law of the form factors; exact sign copies).
-template <typename R, bool ONE>
+// (the point-group law of the form factors; exact sign copies).  STAGE
+// (mode 1, sn.nk > 0): every element of dX also forms its element of the next
+// Runge-Kutta stage as it is written (a form of its own, so that plain
+// right-hand sides keep the smaller register footprint).
+template <typename R, bool ONE, bool STAGE>
 __global__ void __launch_bounds__(256)
 k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X, const R* __restrict__ Kall,
-           double* __restrict__ out, int mode, int cross, int scale_T) {
+           double* __restrict__ out, int mode, int cross, int scale_T, StageNext sn) {
   const int4 item = items[blockIdx.x];
   const int p = ONE ? 0 : item.x;   // ONE: a single-point launch
   if (skip_point(b, p)) return;
@@ -398,6 +403,25 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
   const double scale = scale_T ? b.Tp[p] : 1.0;
   const size_t S = (size_t)b.S;
   const R* K = Kall + d.ws_k;
+  // element e of [3][S] gets the slope value v and, with a next stage,
+  // sn.out[e] = X[e] + h (sum_{j < nk-1} coef_j k_j[e] + coef_{nk-1} v):
+  // stage_part(e, x0, a) reads X[e] and forms the partial sum a over the
+  // slopes already known, stage_put completes it with v
+  const bool stage = STAGE && mode == 1 && sn.nk > 0;
+  const double hstep = stage ? (sn.hp != nullptr ? sn.hp[p] : sn.h) : 0.0;
+  auto stage_part = [&](size_t e, double& x0, double& a) {
+    double kv[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) kv[j] = j + 1 < sn.nk ? sn.k[j][e] : 0.0;
+    x0 = sn.X[e];
+    a = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (j + 1 < sn.nk) a = fma(sn.coef[j], kv[j], a);
+  };
+  auto stage_put = [&](size_t e, double v, double x0, double a) {
+    sn.out[e] = fma(hstep, fma(sn.coef[sn.nk - 1], v, a), x0);
+  };
   extern __shared__ double smem_prod[];
   R* Vs = reinterpret_cast<R*>(smem_prod);   // [3][nff2]
   R* Ch = Vs + 3 * nff2;                    // [2][nff2]
@@ -421,6 +445,7 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
   // the thread's entries mn = tid + 256 h (h < 2; 256 threads, nff^2 <= 441):
   // all of their loads in flight together, then V (and W, the loops) to LDS
   double xv[2][3], kv[2][3], cv[2][2];
+  double sx[2][3], sa[2][3];   // the next stage's X and partial sums (own elements)
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int mn = threadIdx.x + 256 * h;
@@ -429,6 +454,8 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
     for (int ch = 0; ch < 3; ++ch) {
       xv[h][ch] = ok ? X[ch * S + d.off + (size_t)l * nff2 + mn] : 0.0;
       kv[h][ch] = (ok && cross) ? (double)K[((size_t)ch * nq + l) * nff2 + mn] : 0.0;
+      sx[h][ch] = sa[h][ch] = 0.0;
+      if (ok && stage && !b.wedge) stage_part(ch * S + d.off + (size_t)l * nff2 + mn, sx[h][ch], sa[h][ch]);
     }
 #pragma unroll
     for (int ch = 0; ch < 2; ++ch)
@@ -562,17 +589,33 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
   __syncthreads();
   if (b.wedge) {
     orbit([&](size_t o, int w, double sg) {
-      out[o] = sg * (scale * (double)T2[w]);
-      out[S + o] = sg * (-scale * (double)T2[nff2 + w]);
-      out[2 * S + o] = sg * (0.5 * scale * ((double)T2[2 * nff2 + w] - (double)T2[nff2 + w]));
+      const double v[3] = {sg * (scale * (double)T2[w]), sg * (-scale * (double)T2[nff2 + w]),
+                           sg * (0.5 * scale * ((double)T2[2 * nff2 + w] - (double)T2[nff2 + w]))};
+      double x0[3], a[3];
+      if (stage) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) stage_part(ch * S + o, x0[ch], a[ch]);
+      }
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        out[ch * S + o] = v[ch];
+        if (stage) stage_put(ch * S + o, v[ch], x0[ch], a[ch]);
+      }
     });
     return;
   }
-  for (int w = threadIdx.x; w < nff2; w += blockDim.x) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int w = threadIdx.x + 256 * h;   // the elements whose operands were loaded first
+    if (w >= nff2) continue;
     const size_t o = d.off + (size_t)l * nff2 + w;
-    out[o] = scale * (double)T2[w];
-    out[S + o] = -scale * (double)T2[nff2 + w];
-    out[2 * S + o] = 0.5 * scale * ((double)T2[2 * nff2 + w] - (double)T2[nff2 + w]);
+    const double v[3] = {scale * (double)T2[w], -scale * (double)T2[nff2 + w],
+                         0.5 * scale * ((double)T2[2 * nff2 + w] - (double)T2[nff2 + w])};
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      out[ch * S + o] = v[ch];
+      if (stage) stage_put(ch * S + o, v[ch], sx[h][ch], sa[h][ch]);
+    }
   }
 }
 
@@ -800,29 +843,38 @@ __global__ void __launch_bounds__(256) k_dp_control(DpControl c) {
 }
 
 // y = y5 and k0 = k6 (first same as last) for the points whose attempt was
-// accepted; segment items as k_axpy
+// accepted; then, for every point still flowing (accepted or not), the first
+// stage of its next attempt, stage1 = y + h (a10 k0) with the step the
+// control has just set (the operations of k_axpy<1>); segment items as k_axpy
 __global__ void __launch_bounds__(256)
 k_dp_accept(Batch b, const int4* __restrict__ items, const DpState* __restrict__ st, const double* __restrict__ y5,
-            const double* __restrict__ k6, double* __restrict__ y, double* __restrict__ k0) {
+            const double* __restrict__ k6, double* __restrict__ y, double* __restrict__ k0, double a10,
+            const double* __restrict__ h_arr, double* __restrict__ stage1) {
   const int4 it = items[blockIdx.x];
-  if (!st[it.x].accept) return;
+  const bool acc = st[it.x].accept != 0;
+  const bool flowing = !skip_point(b, it.x);
+  if (!acc && !flowing) return;
   size_t base;
   int n;
   if (!seg_range(b, it, base, n)) return;
+  const double h = flowing ? h_arr[it.x] : 0.0;
   double yv[kSegPer], kv[kSegPer];
 #pragma unroll
   for (int u = 0; u < kSegPer; ++u) {
     const int i = threadIdx.x + 256 * u;
     const size_t e = base + (i < n ? i : 0);
-    yv[u] = y5[e];
-    kv[u] = k6[e];
+    yv[u] = acc ? y5[e] : y[e];
+    kv[u] = acc ? k6[e] : k0[e];
   }
 #pragma unroll
   for (int u = 0; u < kSegPer; ++u) {
     const int i = threadIdx.x + 256 * u;
     if (i < n) {
-      y[base + i] = yv[u];
-      k0[base + i] = kv[u];
+      if (acc) {
+        y[base + i] = yv[u];
+        k0[base + i] = kv[u];
+      }
+      if (flowing) stage1[base + i] = fma(h, a10 * kv[u], yv[u]);
     }
   }
 }
@@ -1096,26 +1148,33 @@ void launch_expand_basis(const Launch& L, const Ranges& r, double* dchi, bool cr
 }
 
 void launch_back(const Launch& L, const Ranges& r, const double* X, double* out, int mode,
-                 bool cross, bool scale_T, bool mixed, hipStream_t s) {
+                 bool cross, bool scale_T, bool mixed, hipStream_t s, const StageNext* sn) {
   if (r.prod.n <= 0) return;
+  StageNext sv{};
+  if (sn != nullptr && mode == 1) sv = *sn;
   auto launch = [&](const ItemRange& ir, size_t smem64) {
     if (ir.n <= 0) return;
     const int4* it = L.prod_items + ir.begin;
     const int c = cross ? 1 : 0, st = scale_T ? 1 : 0;
     const float* k32 = (const float*)L.b.kinv;
     const double* k64 = (const double*)L.b.kinv64;
-    if (mixed && L.one_point)
-      hipLaunchKernelGGL((k_products<float, true>), dim3(ir.n), dim3(256), smem64 / 2, s, L.b, it, X, k32, out,
-                         mode, c, st);
-    else if (mixed)
-      hipLaunchKernelGGL((k_products<float, false>), dim3(ir.n), dim3(256), smem64 / 2, s, L.b, it, X, k32, out,
-                         mode, c, st);
-    else if (L.one_point)
-      hipLaunchKernelGGL((k_products<double, true>), dim3(ir.n), dim3(256), smem64, s, L.b, it, X, k64, out,
-                         mode, c, st);
-    else
-      hipLaunchKernelGGL((k_products<double, false>), dim3(ir.n), dim3(256), smem64, s, L.b, it, X, k64, out,
-                         mode, c, st);
+    auto go = [&](auto stage_form) {
+      constexpr bool SF = decltype(stage_form)::value;
+      if (mixed && L.one_point)
+        hipLaunchKernelGGL((k_products<float, true, SF>), dim3(ir.n), dim3(256), smem64 / 2, s, L.b, it, X, k32,
+                           out, mode, c, st, sv);
+      else if (mixed)
+        hipLaunchKernelGGL((k_products<float, false, SF>), dim3(ir.n), dim3(256), smem64 / 2, s, L.b, it, X, k32,
+                           out, mode, c, st, sv);
+      else if (L.one_point)
+        hipLaunchKernelGGL((k_products<double, true, SF>), dim3(ir.n), dim3(256), smem64, s, L.b, it, X, k64,
+                           out, mode, c, st, sv);
+      else
+        hipLaunchKernelGGL((k_products<double, false, SF>), dim3(ir.n), dim3(256), smem64, s, L.b, it, X, k64,
+                           out, mode, c, st, sv);
+    };
+    if (sv.nk > 0) go(std::true_type{});
+    else go(std::false_type{});
   };
   if (r.nprod_cls == 0) {
     launch(r.prod, L.prod_smem);
@@ -1175,9 +1234,10 @@ void launch_dp_control(const DpControl& c, hipStream_t s) {
 }
 
 void launch_dp_accept(const Launch& L, const ItemRange& r, const DpState* st, const double* y5, const double* k6,
-                      double* y, double* k0, hipStream_t s) {
+                      double* y, double* k0, double a10, const double* h_arr, double* stage1, hipStream_t s) {
   if (r.n <= 0) return;
-  hipLaunchKernelGGL(k_dp_accept, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, st, y5, k6, y, k0);
+  hipLaunchKernelGGL(k_dp_accept, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, st, y5, k6, y, k0, a10,
+                     h_arr, stage1);
 }
 
 void launch_set_T_sh(double* Tp, int npts, const double* s_arr, const double* h_arr, double c, hipStream_t s) {

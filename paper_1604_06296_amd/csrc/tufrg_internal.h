@@ -202,6 +202,22 @@ struct TArg {
   double v[64];
 };
 
+// The next stage of an explicit Runge-Kutta step, formed by the kernel that
+// writes a slope, element by element as the slope is written:
+// out = X + h_p sum_{j < nk} coef_j k_j, where k_{nk-1} is the slope being
+// written (its value is taken from the kernel, not read back) and h_p is
+// hp[p] (the adaptive flow) or h.  The same operations in the same order as
+// the stand-alone stage combination.  nk = 0: no next stage.
+struct StageNext {
+  const double* X;
+  const double* k[7];
+  double coef[7];
+  double* out;
+  const double* hp;
+  double h;
+  int nk;
+};
+
 // Device state of the adaptive (Dormand-Prince) flow, one entry per point.
 struct DpState {
   double s, h;            // current scale s = ln T and the step of the next attempt
@@ -274,8 +290,9 @@ void launch_gather_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t
 void launch_loops_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, bool cross,
                       const TArg& ta, hipStream_t s);
 void launch_expand_basis(const Launch& L, const Ranges& r, double* dchi, bool cross, hipStream_t s);
+// sn (or null): the next stage formed where the products write dX (mode 1)
 void launch_back(const Launch& L, const Ranges& r, const double* X, double* out, int mode,
-                 bool cross, bool scale_T, bool mixed, hipStream_t s);
+                 bool cross, bool scale_T, bool mixed, hipStream_t s, const StageNext* sn = nullptr);
 // hp (device, per point) or null: the step of point p is hp[p] (the adaptive
 // flow) instead of h
 void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const double* const* k,
@@ -302,8 +319,10 @@ struct DpControl {
   int max_steps, npts;
 };
 void launch_dp_control(const DpControl& c, hipStream_t s);
+// y = y5 and k0 = k6 where the attempt was accepted, then the first stage of
+// the next attempt, stage1 = y + h_p (a10 k0), for every point still flowing
 void launch_dp_accept(const Launch& L, const ItemRange& r, const DpState* st, const double* y5, const double* k6,
-                      double* y, double* k0, hipStream_t s);
+                      double* y, double* k0, double a10, const double* h_arr, double* stage1, hipStream_t s);
 void launch_set_T_sh(double* Tp, int npts, const double* s_arr, const double* h_arr, double c, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t s);
 // per-point largest deviation of X from the C4v covariance law (items (p, slot))
@@ -348,7 +367,8 @@ struct tufrg_ctx {
   int* frozen = nullptr;                   // per-point stop flags
   int* queue = nullptr;                    // loop-kernel work queue: next item, finished blocks
   bool flow_ready = false;                 // flow state buffers allocated (first tufrg_flow)
-  double* stage = nullptr;                 // RK stage state [3][S]
+  double* stage = nullptr;                 // RK stage states [3][S] (two, alternating)
+  double* stage2 = nullptr;
   double* kk[7] = {nullptr};               // RK slopes [3][S]
   double* ytmp = nullptr;                  // [3][S]
   double* red = nullptr;                   // reduction scratch
