@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1001,6 +1002,7 @@ tufrg_status tufrg_init_mesh(const tufrg_point* pts, const tufrg_mesh* meshes, i
   }
   if (!st) st = dalloc(ctx, (size_t)npts, &ctx->Tp, A);
   if (!st) st = dalloc(ctx, (size_t)npts, &ctx->frozen, A);
+  if (!st) st = dalloc(ctx, (size_t)npts, &ctx->first_max, A);
   if (!st) st = dalloc(ctx, 2, &ctx->queue, A);
   if (!st) st = dalloc(ctx, (size_t)npts, &ctx->umax, A);
   if (!st) st = dalloc(ctx, 1, &ctx->step, A);
@@ -1333,21 +1335,11 @@ void jacobi_eig(std::vector<double> a, int n, std::vector<double>& w, std::vecto
   for (int i = 0; i < n; ++i) w[i] = a[(size_t)i * n + i];
 }
 
-// channel, momentum and irrep of the largest |X_mn(q)| (first in flat order)
-void classify(const HostTables& t, const std::vector<double>& x /*[3][nq][nff][nff]*/,
-              tufrg_flow_result* r) {
+// irrep of the leading eigenvector of the form-factor matrix src = X(ch, q)
+// that holds the largest |X_mn(q)| (channel and momentum found on the device)
+void classify(const HostTables& t, int ch, int q, const double* src /*[nff][nff]*/, tufrg_flow_result* r) {
   const int nff = t.nff, nff2 = nff * nff;
-  size_t best = 0;
-  double bv = -1.0;
-  for (size_t i = 0; i < x.size(); ++i)
-    if (std::fabs(x[i]) > bv) {
-      bv = std::fabs(x[i]);
-      best = i;
-    }
-  const int ch = (int)(best / ((size_t)t.nq * nff2));
-  const int q = (int)((best / nff2) % t.nq);
   std::vector<double> m((size_t)nff2);
-  const double* src = x.data() + ((size_t)ch * t.nq + q) * nff2;
   for (int i = 0; i < nff; ++i)
     for (int j = 0; j < nff; ++j) m[(size_t)i * nff + j] = 0.5 * (src[i * nff + j] + src[j * nff + i]);
   std::vector<double> w, v;
@@ -1375,7 +1367,7 @@ double interp_tc(double s0, double s1, double m0, double m1, double xmax) {
 // interpolation between the last two accepted steps (s0, m0) -> (s1, m1) and
 // the classification of the stopped state X.
 tufrg_status finish_point(tufrg_ctx* ctx, int p, const double* X, int status, double s0, double s1,
-                          double m0, double m1, double xmax, int64_t n_rhs, int64_t n_steps,
+                          double m0, double m1, double xmax, int64_t n_rhs, int64_t n_steps, int first,
                           hipStream_t ms, tufrg_flow_result* r) {
   std::memset(r, 0, sizeof *r);
   r->status = status;
@@ -1387,14 +1379,30 @@ tufrg_status finish_point(tufrg_ctx* ctx, int p, const double* X, int status, do
   if (status == TUFRG_FLOW_DIVERGED) {
     r->Tc = interp_tc(s0, s1, m0, m1, xmax);
     const HostTables& t = ctx->host[p];
-    const int64_t n = (int64_t)t.nq * t.nff * t.nff;
-    std::vector<double> x((size_t)3 * n);
-    for (int c = 0; c < 3; ++c)
-      HIP_TRY(ctx, hipMemcpyAsync(x.data() + c * n, X + c * ctx->S + ctx->off[p], n * sizeof(double),
-                                  hipMemcpyDeviceToHost, ms));
+    const int nff2 = t.nff * t.nff;
+    if (first < 0 || first >= 3 * t.nq * nff2) return TUFRG_OK;   // no finite maximum: unclassified
+    const int ch = first / (t.nq * nff2), q = (first / nff2) % t.nq;
+    std::vector<double> m((size_t)nff2);
+    HIP_TRY(ctx, hipMemcpyAsync(m.data(), X + ch * ctx->S + ctx->off[p] + (size_t)q * nff2, nff2 * sizeof(double),
+                                hipMemcpyDeviceToHost, ms));
     HIP_TRY(ctx, hipStreamSynchronize(ms));
-    classify(t, x, r);
+    classify(t, ch, q, m.data(), r);
   }
+  return TUFRG_OK;
+}
+
+// Per point, the first flat index (channel, q, m, n) of the largest |X| of
+// the stopped state, on the device (the classification then copies one
+// form-factor matrix per diverged point instead of the state)
+tufrg_status locate_maxima(tufrg_ctx* ctx, const double* X, hipStream_t ms, std::vector<int>& first) {
+  const int npts = (int)ctx->dev.size();
+  launch_fill_u64(ctx->umax, npts, 0ull, ms);
+  launch_maxabs(ctx->L, ctx->all.seg, X, ctx->umax, ms);
+  launch_fill_i32(ctx->first_max, npts, INT_MAX, ms);
+  launch_first_max(ctx->L, ctx->all.seg, X, ctx->umax, ctx->first_max, ms);
+  first.assign(npts, INT_MAX);
+  HIP_TRY(ctx, hipMemcpyAsync(first.data(), ctx->first_max, sizeof(int) * npts, hipMemcpyDeviceToHost, ms));
+  HIP_TRY(ctx, hipStreamSynchronize(ms));
   return TUFRG_OK;
 }
 
@@ -1539,6 +1547,8 @@ tufrg_status flow_rk4_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, t
   HIP_TRY(ctx, hipMemcpyAsync(hist.data(), ctx->hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost, ms));
   HIP_TRY(ctx, hipStreamSynchronize(ms));
   for (int p = 0; p < npts; ++p) hist[p] = m0[p];
+  std::vector<int> first;
+  ST_TRY(locate_maxima(ctx, X, ms, first));
   for (int p = 0; p < npts; ++p) {
     const int f = frozen[p];
     const int last = f ? f : done;
@@ -1547,7 +1557,7 @@ tufrg_status flow_rk4_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, t
     int status = TUFRG_FLOW_REACHED_TMIN;
     if (f) status = std::isfinite(mlast) ? TUFRG_FLOW_DIVERGED : TUFRG_FLOW_NONFINITE;
     ST_TRY(finish_point(ctx, p, X, status, s0 + (last - 1) * h, s0 + last * h, mprev, mlast, o->Xmax,
-                        4 * (int64_t)last, last, ms, &res[p]));
+                        4 * (int64_t)last, last, first[p], ms, &res[p]));
   }
   return TUFRG_OK;
 }
@@ -1723,23 +1733,41 @@ tufrg_status flow_dopri5_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X
       cleanup();
       return fail(ctx, TUFRG_EHIP, std::string("adaptive flow: ") + hipGetErrorString(ge));
     }
-    bool all_done = true, near = false;
-    double steps_left = 1.0;
+    // the next batch: the attempts the slowest flowing point still needs at
+    // most, to T_min at its current step or, once its max|X| is a quarter of
+    // the way to the stop rule, 0.4 times the log-linear extrapolation of its
+    // last two accepted steps to X_max (growth towards a divergence is faster
+    // than log-linear, so the extrapolation is long); attempts after every
+    // point has stopped would be no-ops, the batch only bounds their number
+    bool all_done = true;
+    double need = 1.0;
     for (const DpState& q : stv)
       if (q.status == 0) {
         all_done = false;
-        steps_left = std::max(steps_left, std::ceil((q.s - s_end) / std::max(std::fabs(q.h), 1e-300)));
-        near = near || q.m1 > 0.25 * o->Xmax;   // close to the stop rule: check after every attempt
+        const double ah = std::max(std::fabs(q.h), 1e-300);
+        double n_p = std::ceil((q.s - s_end) / ah);
+        if (q.m1 > 0.25 * o->Xmax) {
+          double est = 1.0;
+          if (q.m0 > 0.0 && q.m1 > q.m0 && q.s0 != q.s1) {
+            const double sc =
+                q.s1 + (std::log(o->Xmax) - std::log(q.m1)) * (q.s1 - q.s0) / (std::log(q.m1) - std::log(q.m0));
+            est = std::max(1.0, std::floor(0.4 * (q.s1 - sc) / ah));
+          }
+          n_p = std::min(n_p, est);
+        }
+        need = std::max(need, n_p);
       }
     if (all_done || attempted > max_steps + 1) break;
-    batch = near ? 1 : (int)std::min(8.0, std::max(1.0, steps_left));
+    batch = (int)std::min(8.0, std::max(1.0, need));
   }
   cleanup();
+  std::vector<int> first;
+  ST_TRY(locate_maxima(ctx, X, ms, first));
   for (int p = 0; p < npts; ++p) {
     const DpState& q = stv[p];
     const int status = q.status != 0 ? q.status : TUFRG_FLOW_MAX_STEPS;
     ST_TRY(finish_point(ctx, p, X, status, q.s0, q.s1, q.m0, q.m1, o->Xmax, 1 + 6 * (int64_t)q.n_att, q.n_acc,
-                        ms, &res[p]));
+                        first[p], ms, &res[p]));
   }
   return TUFRG_OK;
 }

@@ -13,6 +13,7 @@
 #include <type_traits>
 
 #include <algorithm>
+#include <climits>
 #include <cstdint>
 
 #include "proj_bodies.h"
@@ -706,6 +707,33 @@ k_maxabs(Batch b, const int4* __restrict__ items, const double* __restrict__ X,
   if (threadIdx.x == 0 && red[0] != 0ull) atomicMax(words + it.x, red[0]);
 }
 
+// The first local flat index (channel, q, m, n) of point p whose |x| has the
+// bit pattern words[p] (its max|x| from k_maxabs, NaN ordered as there):
+// atomic minimum into first[p]; segment items as k_maxabs.
+__global__ void __launch_bounds__(256)
+k_first_max(Batch b, const int4* __restrict__ items, const double* __restrict__ X,
+            const unsigned long long* __restrict__ words, int* __restrict__ first) {
+  const int4 it = items[blockIdx.x];
+  size_t base;
+  int n;
+  if (skip_point(b, it.x) || !seg_range(b, it, base, n)) return;
+  const DevTables& d = b.pts[it.x];
+  const int len = d.nq * d.nff * d.nff;
+  const unsigned long long target = words[it.x];
+  int best = INT_MAX;
+#pragma unroll
+  for (int u = 0; u < kSegPer; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    if (i < n) {
+      const double v = X[base + i];
+      unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(v));
+      if (v != v) bits = 0x7ff8000000000000ull;
+      if (bits == target) best = min(best, it.y * len + it.z * kSeg + i);
+    }
+  }
+  if (best != INT_MAX) atomicMin(first + it.x, best);
+}
+
 // The last stage of a Dormand-Prince step in one pass: y5 = y0 + h sum_j b5_j k_j
 // (as k_axpy<7>); per segment the partial sum of ((h sum_j e_j k_j) / (atol +
 // rtol max(|y0|,|y5|)))^2 in a fixed order (each thread's elements in turn,
@@ -1227,6 +1255,12 @@ void launch_dp_final(const Launch& L, const ItemRange& r, const double* y0, cons
   }
   hipLaunchKernelGGL(k_dp_final, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, y0, ks, ec, h,
                      rtol, atol, y5, red, max_words, hp);
+}
+
+void launch_first_max(const Launch& L, const ItemRange& r, const double* X, const unsigned long long* words,
+                      int* first, hipStream_t s) {
+  if (r.n <= 0) return;
+  hipLaunchKernelGGL(k_first_max, dim3(r.n), dim3(256), 0, s, L.b, L.seg_items + r.begin, X, words, first);
 }
 
 void launch_dp_control(const DpControl& c, hipStream_t s) {

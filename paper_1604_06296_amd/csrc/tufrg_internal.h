@@ -300,6 +300,10 @@ void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const dou
                  const double* hp = nullptr);
 void launch_maxabs(const Launch& L, const ItemRange& r, const double* X, unsigned long long* words,
                    hipStream_t s);
+// per point, the smallest local flat index whose |X| has the bit pattern
+// words[p] (atomic minimum into first[p], which starts at INT_MAX)
+void launch_first_max(const Launch& L, const ItemRange& r, const double* X, const unsigned long long* words,
+                      int* first, hipStream_t s);
 // the last Dormand-Prince stage: y5, the error partial sums and max|y5| per point
 void launch_dp_final(const Launch& L, const ItemRange& r, const double* y0, const double* const* k,
                      const double* b5, const double* e, double h, double rtol, double atol, double* y5,
@@ -365,6 +369,7 @@ struct tufrg_ctx {
   // device buffers owned by the context
   double* Tp = nullptr;                    // per-point temperatures
   int* frozen = nullptr;                   // per-point stop flags
+  int* first_max = nullptr;                // per-point first index of max|X| (classification)
   int* queue = nullptr;                    // loop-kernel work queue: next item, finished blocks
   bool flow_ready = false;                 // flow state buffers allocated (first tufrg_flow)
   double* stage = nullptr;                 // RK stage states [3][S] (two, alternating)
