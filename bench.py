@@ -31,9 +31,10 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CUs x 64 lanes x 2 fl
 # HBM bytes per launch of the loop kernel at the headline workload (default
 # geometry), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by
 # the counters of a plain 64 MiB device copy; valid only for the kernel
-# sources they were taken with (profiles/loop_kernel_traffic_*.md).
-LOOP_TRAFFIC = {"sources_sha256": "0cadc6ebabbd1ecbac3c98ab46ce8b2038627eae32098c2accad1adfd37f3c26",
-                "bytes": 558783}
+# sources they were taken with (loops.hip, loop_body.h, loop_math.h;
+# profiles/loop_kernel_traffic_*.md).
+LOOP_TRAFFIC = {"sources_sha256": "7dc8e06af7c27877d153600a67f3ddf4a50fed107904289ab8fda3ff8342b6b4",
+                "bytes": 546357}
 
 
 def loop_flops_algorithmic(Lq, Lk, n_harm, c_pair=157.0):

@@ -32,6 +32,11 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // B[4(l/16)+j][l%16] (j = 0..3) and D[4(l/16)+j][l%16].
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// v_mfma_f32_16x16x32_bf16 (CDNA4: twice the K of the _1k form per
+// instruction, at the same issue cost): lane l holds A[l%16][8(l/16)+j],
+// B[8(l/16)+j][l%16] (j = 0..7), D as above; an operand is two quads of
+// consecutive k, kept together in LDS.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ unsigned short bf16_rne(float f) {
   unsigned int u = __float_as_uint(f);
@@ -128,16 +133,22 @@ __device__ __forceinline__ void fwd_part_body(const Batch& b, const DevTables& d
 // [u/4][kEpad][4], zero beyond Nq) as hi and lo quads for the KT harmonic
 // tiles, and the block's columns of X, split to hi and lo quads as they are
 // staged (each thread stages two (quad, column) pairs: 8 loads in flight).
-// Each wave then reads its operand quads from LDS for 2 steps of 16 momenta.
+// Each wave then takes the chunk in one v_mfma_f32_16x16x32_bf16 step per
+// product and tile; the next chunk's loads are in flight meanwhile.  LDS
+// holds the quads in pairs of consecutive quads (one 16-byte operand read).
 template <int KT>
 __device__ __forceinline__ void fwd_mix_body(const Batch& b, const DevTables& d, const int4 item,
                                              const double* __restrict__ X, double* smem) {
   constexpr int TK = 16 * KT;
   const int nw = (int)blockDim.x >> 6, CW = 16 * nw, nt = blockDim.x;
-  bf16x4* Eh = reinterpret_cast<bf16x4*>(smem);   // [8][TK]
-  bf16x4* El = Eh + 8 * TK;
-  bf16x4* Xh = El + 8 * TK;                        // [8][CW]
-  bf16x4* Xl = Xh + 8 * CW;
+  bf16x8* Eh = reinterpret_cast<bf16x8*>(smem);   // [4][TK] quad pairs
+  bf16x8* El = Eh + 4 * TK;
+  bf16x8* Xh = El + 4 * TK;                        // [4][CW]
+  bf16x8* Xl = Xh + 4 * CW;
+  // quad q of column (or harmonic) c in a [4][C] pair array
+  auto quad = [](bf16x8* a, int C, int q, int c) -> bf16x4& {
+    return reinterpret_cast<bf16x4*>(a)[((q >> 1) * C + c) * 2 + (q & 1)];
+  };
   const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
   const int split = item.z, nq16 = (nq + 15) >> 4;
   const int u0 = 16 * (int)((int64_t)nq16 * split / d.nsu);
@@ -156,10 +167,10 @@ __device__ __forceinline__ void fwd_mix_body(const Batch& b, const DevTables& d,
   f32x4 acc[KT];
 #pragma unroll
   for (int t = 0; t < KT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int ub = u0; ub < u1; ub += 32) {
+  bf16x4 eh[EPT], el[EPT];
+  double xv[2][4];
+  auto load = [&](int ub) {
     const int nst = min(32, u1 - ub) >> 4;   // steps of 16 in this chunk (1 or 2)
-    bf16x4 eh[EPT], el[EPT];
-    double xv[2][4];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * nt, q = e / TK, k = e % TK;
@@ -175,12 +186,15 @@ __device__ __forceinline__ void fwd_mix_body(const Batch& b, const DevTables& d,
         const int u = ub + 4 * (xq + 4 * h) + j;
         xv[h][j] = (xok && u < nq && u < u1) ? xsrc[(size_t)u * nff2] : 0.0;
       }
+  };
+  if (u0 < u1) load(u0);
+  for (int ub = u0; ub < u1; ub += 32) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * nt;
       if (e < 8 * TK) {
-        Eh[e] = eh[i];
-        El[e] = el[i];
+        quad(Eh, TK, e / TK, e % TK) = eh[i];
+        quad(El, TK, e / TK, e % TK) = el[i];
       }
     }
 #pragma unroll
@@ -193,20 +207,19 @@ __device__ __forceinline__ void fwd_mix_body(const Batch& b, const DevTables& d,
         qh[j] = (short)hi;
         ql[j] = (short)lo;
       }
-      Xh[(xq + 4 * h) * CW + xc] = qh;
-      Xl[(xq + 4 * h) * CW + xc] = ql;
+      quad(Xh, CW, xq + 4 * h, xc) = qh;
+      quad(Xl, CW, xq + 4 * h, xc) = ql;
     }
     __syncthreads();
-    for (int st = 0; st < nst; ++st) {
-      const int q = 4 * st + k4;
-      const bf16x4 bh = Xh[q * CW + 16 * w + r16], bl = Xl[q * CW + 16 * w + r16];
+    if (ub + 32 < u1) load(ub + 32);
+    // lane (r16, k4): momenta 8 k4 .. 8 k4 + 7 of the chunk (quad pair k4)
+    const bf16x8 bh = Xh[k4 * CW + 16 * w + r16], bl = Xl[k4 * CW + 16 * w + r16];
 #pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        const bf16x4 ah = Eh[q * TK + 16 * t + r16], al = El[q * TK + 16 * t + r16];
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[t], 0, 0, 0);
-      }
+    for (int t = 0; t < KT; ++t) {
+      const bf16x8 ah = Eh[k4 * TK + 16 * t + r16], al = El[k4 * TK + 16 * t + r16];
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[t], 0, 0, 0);
     }
     __syncthreads();
   }
