@@ -352,7 +352,23 @@ k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
   f32x4 acc[LT];
 #pragma unroll
   for (int t = 0; t < LT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int q0 = 0; q0 < nk; q0 += 4) {
+  // steps of 32 harmonics on v_mfma_f32_16x16x32_bf16 (lane (r16, k4):
+  // quads q0 + 2 k4, q0 + 2 k4 + 1), a last step of 16 on the 16x16x16 form
+  int q0 = 0;
+  for (; q0 + 8 <= nk; q0 += 8) {
+    const int q = q0 + 2 * k4;
+    const bf16x8 bh = quad_pair(Gh[q][16 * w + r16], Gh[q + 1][16 * w + r16]);
+    const bf16x8 bl = quad_pair(Gl[q][16 * w + r16], Gl[q + 1][16 * w + r16]);
+#pragma unroll
+    for (int t = 0; t < LT; ++t) {
+      const bf16x8 ah = quad_pair(Eh[16 * t + r16][q], Eh[16 * t + r16][q + 1]);
+      const bf16x8 al = quad_pair(El[16 * t + r16][q], El[16 * t + r16][q + 1]);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[t], 0, 0, 0);
+    }
+  }
+  if (q0 < nk) {
     const int q = q0 + k4;
     const bf16x4 bh = Gh[q][16 * w + r16], bl = Gl[q][16 * w + r16];
 #pragma unroll

@@ -37,6 +37,11 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // B[8(l/16)+j][l%16] (j = 0..7), D as above; an operand is two quads of
 // consecutive k, kept together in LDS.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short short8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ bf16x8 quad_pair(bf16x4 a, bf16x4 b) {
+  const short8 s = __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_bit_cast(bf16x8, s);
+}
 
 __device__ __forceinline__ unsigned short bf16_rne(float f) {
   unsigned int u = __float_as_uint(f);
