@@ -33,8 +33,8 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CUs x 64 lanes x 2 fl
 # the counters of a plain 64 MiB device copy; valid only for the kernel
 # sources they were taken with (loops.hip, loop_body.h, loop_math.h;
 # profiles/loop_kernel_traffic_*.md).
-LOOP_TRAFFIC = {"sources_sha256": "7dc8e06af7c27877d153600a67f3ddf4a50fed107904289ab8fda3ff8342b6b4",
-                "bytes": 546357}
+LOOP_TRAFFIC = {"sources_sha256": "3102942e7854bb619e9476afc61f552e07e8a62fabfcaf87aa2aabe346318ac4",
+                "bytes": 584064}
 
 
 def loop_flops_algorithmic(Lq, Lk, n_harm, c_pair=157.0):

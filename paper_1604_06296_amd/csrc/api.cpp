@@ -429,6 +429,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   DevTables* dp = nullptr;
   ST_TRY(upload(ctx, ctx->dev, &dp, g));
   L.b.pts = dp;
+  L.b.pt0 = ctx->dev[0];
   L.b.S = ctx->S;
   L.b.Tp = ctx->Tp;
   L.b.frozen = nullptr;
@@ -453,8 +454,8 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   if (cus < 1) cus = 1;
   auto per_cu_of = [&](bool unroll) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, loop_kernel_symbol(smax_max, mixed, omega_of(ctx), unroll),
-                                                     threads, lsm) != hipSuccess || n < 1)
+    const void* k = loop_kernel_symbol(smax_max, mixed, omega_of(ctx), unroll);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lsm) != hipSuccess || n < 1)
       n = 1;
     return n;
   };

@@ -43,7 +43,7 @@ __device__ __forceinline__ void expand_body(const Batch& b, const int4 item, con
                                             double* __restrict__ dchi, ExpandShared& sh) {
   const int p = ONE ? 0 : item.x;
   if (skip_point(b, p)) return;
-  const DevTables& d = b.pts[p];
+  const DevTables& d = point_tables<ONE>(b, p);
   auto& As = sh.As;
   auto& Bs = sh.Bs;
   const int nq = d.nq, nsh = d.nsh, nout = 2 * nsh, nff2 = d.nff * d.nff;
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
   const int4 item = items[blockIdx.x];
   const int p = ONE ? 0 : item.x;   // ONE: a single-point launch
   if (skip_point(b, p)) return;
-  const DevTables& d = b.pts[p];
+  const DevTables& d = point_tables<ONE>(b, p);
   const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
   const int l0 = item.y * TL, c0 = item.z * 64, tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, r16 = lane & 15, k4 = lane >> 4;
@@ -295,7 +295,7 @@ k_dft_inv_mix(Batch b, const int4* __restrict__ items) {
   const int4 item = items[blockIdx.x];
   const int p = ONE ? 0 : item.x;   // ONE: a single-point launch
   if (skip_point(b, p)) return;
-  const DevTables& d = b.pts[p];
+  const DevTables& d = point_tables<ONE>(b, p);
   const int nq = d.nq, ncol = d.ncol, nff2 = d.nff * d.nff, N = 3 * nff2;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, k4 = lane >> 4;
@@ -414,7 +414,7 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
   const int4 item = items[blockIdx.x];
   const int p = ONE ? 0 : item.x;   // ONE: a single-point launch
   if (skip_point(b, p)) return;
-  const DevTables& d = b.pts[p];
+  const DevTables& d = point_tables<ONE>(b, p);
   const int nff = d.nff, nff2 = nff * nff, nq = d.nq;
   const int l = item.y;
   const double scale = scale_T ? b.Tp[p] : 1.0;

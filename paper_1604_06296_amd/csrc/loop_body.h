@@ -276,13 +276,16 @@ __device__ __forceinline__ void loop_smax(const Batch& b, const DevTables& d, in
   loop_item<0, MIXED, OMEGA, UNROLL>(b, d, p, item_b, qa, T, smem);
 }
 
-template <int SMAX, bool MIXED, bool OMEGA, bool UNROLL>
+// ONE (a single-point launch, compiled for the point's own smax): point 0,
+// its tables from the launch's arguments
+template <int SMAX, bool MIXED, bool OMEGA, bool UNROLL, bool ONE = false>
 __device__ __forceinline__ void loop_dispatch(const Batch& b, const int4 item, double* smem,
                                               const TArg* ta = nullptr) {
-  const int p = item.x;
+  const int p = ONE ? 0 : item.x;
   if (skip_point(b, p)) return;
-  const DevTables& d = b.pts[p];
-  loop_smax<SMAX, MIXED, OMEGA, UNROLL>(b, d, p, item.y, item.w, point_T(b, ta, p), smem);
+  const DevTables& d = point_tables<ONE>(b, p);
+  if constexpr (ONE) loop_item<SMAX, MIXED, OMEGA, UNROLL>(b, d, p, item.y, item.w, point_T(b, ta, p), smem);
+  else loop_smax<SMAX, MIXED, OMEGA, UNROLL>(b, d, p, item.y, item.w, point_T(b, ta, p), smem);
 }
 
 }  // namespace

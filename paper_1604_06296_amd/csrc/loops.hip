@@ -23,6 +23,8 @@ namespace {
 // smax of the batch, and each item runs the body compiled for its own smax;
 // OMEGA selects the regulator (Omega cutoff at T = 0, else temperature);
 // UNROLL keeps two FP64 rows in flight (more registers, fewer blocks per CU).
+// (A single-point form reading its tables from the launch's arguments, as
+// the fused launch below does, ran slower here: 9.9 -> 10.2 us.)
 // Without a queue every block runs item blockIdx.x (the hardware dispatcher
 // balances the load, items being ordered costliest first); with a queue the
 // kernel is persistent and blocks take items until the queue is empty.
@@ -55,8 +57,10 @@ k_loops(Batch b, const int4* __restrict__ items, int nitems, int* __restrict__ q
 // are independent: the loops read only the temperature, the transform only
 // the couplings): blocks below nloop run loop items, the others forward-
 // transform items, so that both fill the machine together without a second
-// stream.  Dynamic shared memory holds the larger of the two layouts.
-template <int SMAX, bool MIXED, int KT, bool OMEGA>
+// stream.  Dynamic shared memory holds the larger of the two layouts.  ONE:
+// a single-point launch (compiled for the point's own smax; its tables come
+// from the launch's arguments, one dependent load fewer per block).
+template <int SMAX, bool MIXED, int KT, bool OMEGA, bool ONE>
 __global__ void __launch_bounds__(kLoopThreadsMax)
 k_loops_fwd(Batch b, const int4* __restrict__ loop_items, int nloop, const int4* __restrict__ fwd_items,
             const double* __restrict__ X, TArg ta) {
@@ -74,13 +78,14 @@ k_loops_fwd(Batch b, const int4* __restrict__ loop_items, int nloop, const int4*
     }
   }
   if ((int)blockIdx.x < nloop) {
-    loop_dispatch<SMAX, MIXED, OMEGA, true>(b, loop_items[blockIdx.x], smem, &ta);
+    loop_dispatch<SMAX, MIXED, OMEGA, true, ONE>(b, loop_items[blockIdx.x], smem, &ta);
     return;
   }
   const int4 item = fwd_items[blockIdx.x - nloop];
-  if (skip_point(b, item.x)) return;
-  if constexpr (MIXED) fwd_mix_body<KT>(b, b.pts[item.x], item, X, smem);
-  else fwd_part_body<KT>(b, b.pts[item.x], item, X, smem);
+  const int p = ONE ? 0 : item.x;
+  if (skip_point(b, p)) return;
+  if constexpr (MIXED) fwd_mix_body<KT>(b, point_tables<ONE>(b, p), item, X, smem);
+  else fwd_part_body<KT>(b, point_tables<ONE>(b, p), item, X, smem);
 }
 
 // Calls f(smax, mixed, omega) with the runtime values as compile-time constants.
@@ -131,12 +136,21 @@ void launch_loops_fwd(const Launch& L, const Ranges& r, const double* X, bool mi
   with_loop_variant(L.smax_max, mixed, L.omega, [&](auto S, auto M, auto O) {
     constexpr int SM = decltype(S)::value;
     constexpr bool MX = decltype(M)::value, OM = decltype(O)::value;
-    switch (L.fwd_kt) {
-      case 1: hipLaunchKernelGGL((k_loops_fwd<SM, MX, 1, OM>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
-      case 2: hipLaunchKernelGGL((k_loops_fwd<SM, MX, 2, OM>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
-      case 3: hipLaunchKernelGGL((k_loops_fwd<SM, MX, 3, OM>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
-      default: hipLaunchKernelGGL((k_loops_fwd<SM, MX, 5, OM>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta); break;
-    }
+    auto go = [&](auto one) {
+      constexpr bool ON = decltype(one)::value;
+      switch (L.fwd_kt) {
+        case 1: hipLaunchKernelGGL((k_loops_fwd<SM, MX, 1, OM, ON>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta);
+          break;
+        case 2: hipLaunchKernelGGL((k_loops_fwd<SM, MX, 2, OM, ON>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta);
+          break;
+        case 3: hipLaunchKernelGGL((k_loops_fwd<SM, MX, 3, OM, ON>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta);
+          break;
+        default: hipLaunchKernelGGL((k_loops_fwd<SM, MX, 5, OM, ON>), g, blk, sm, s, L.b, li, r.loop.n, fi, X, ta);
+          break;
+      }
+    };
+    if (L.one_point) go(std::true_type{});
+    else go(std::false_type{});
   });
 }
 

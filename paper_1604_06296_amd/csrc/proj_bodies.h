@@ -28,7 +28,7 @@ template <bool ONE, int NT = 256>
 __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, BasisShared& sh) {
   const int p = ONE ? 0 : item.x;
   if (skip_point(b, p)) return;
-  const DevTables& d = b.pts[p];
+  const DevTables& d = point_tables<ONE>(b, p);
   const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol, nv = 2 * nsh - 1;
   const int total = 3 * nv * nff2;
   const int in = item.y / nv, v = item.y % nv;

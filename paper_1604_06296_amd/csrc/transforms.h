@@ -25,6 +25,14 @@ __device__ __forceinline__ bool skip_point(const Batch& b, int p) {
   return b.frozen != nullptr && b.frozen[p] != 0;
 }
 
+// The tables of point p; ONE (a single-point launch, p = 0): the copy in the
+// launch's arguments, which needs no load of the device array first
+template <bool ONE>
+__device__ __forceinline__ const DevTables& point_tables(const Batch& b, int p) {
+  if constexpr (ONE) return b.pt0;
+  else return b.pts[p];
+}
+
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 // BF16 hi/lo split with round to nearest even: x ~ hi + lo (about 16 mantissa
 // bits); products hi*hi + hi*lo + lo*hi accumulate in FP32 on the matrix cores.

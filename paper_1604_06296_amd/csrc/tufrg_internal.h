@@ -159,6 +159,8 @@ struct Batch {
   int loop_threads;       // threads of the loop geometry (fixes the loops' summation order)
   int wedge;              // symmetric states: inverse transform and products at the orbit
                           // representatives, the increments copied to every orbit member
+  DevTables pt0;          // copy of pts[0] (single-point launches read their descriptor
+                          // from the kernel arguments: one dependent load fewer)
 };
 
 struct ItemRange {
