@@ -22,6 +22,9 @@ namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// v_mfma_f32_16x16x32_bf16 operands: lane l holds A[l%16][8(l/16)+j] and
+// B[8(l/16)+j][l%16], j = 0..7 (eight consecutive k of an LDS row)
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ unsigned short bf16_rne(float f) {
   unsigned int u = __float_as_uint(f);
@@ -57,8 +60,9 @@ struct GemmArgs {
 constexpr int kTM = 64, kTN = 64, kKC = 32, kLDK = kKC + 8;   // LDS row stride in halfwords
 
 // C tile 64 x 64 per block of 4 waves; each wave owns a 32 x 32 quarter as
-// 2 x 2 tiles of v_mfma_f32_16x16x16bf16_1k.  Operands are read as FP32,
-// rounded to BF16 (and split hi/lo when PASSES == 3) into LDS, K chunk 32.
+// 2 x 2 tiles of v_mfma_f32_16x16x32_bf16 (one step per K chunk of 32).
+// Operands are read as FP32, rounded to BF16 (and split hi/lo when
+// PASSES == 3) into LDS.
 // VEC: op(A) = A and op(B) = B^T with rows of K contiguous and 16-byte
 // aligned (lda, ldb multiples of 4): each thread stages two 4-wide K quads of
 // A and of B with one 16-byte load each and one 8-byte LDS store per BF16 quad.
@@ -164,19 +168,19 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     }
     __syncthreads();
     if (k0 + kKC < ke) load(k0 + kKC);
-#pragma unroll
-    for (int kk = 0; kk < kKC; kk += 16) {
-      const int kq = kk + 4 * (lane >> 4);
-      bf16x4 ah[2], bh[2], al[2], bl[2];
+    {
+      // the chunk's 32 k in one v_mfma_f32_16x16x32_bf16 step per product
+      const int kq = 8 * (lane >> 4);
+      bf16x8 ah[2], bh[2], al[2], bl[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int r = wm + 16 * i + (lane & 15);
         const int c = wn + 16 * i + (lane & 15);
-        ah[i] = *reinterpret_cast<const bf16x4*>(&Ah[r * kLDK + kq]);
-        bh[i] = *reinterpret_cast<const bf16x4*>(&Bh[c * kLDK + kq]);
+        ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[r * kLDK + kq]);
+        bh[i] = *reinterpret_cast<const bf16x8*>(&Bh[c * kLDK + kq]);
         if constexpr (PASSES == 3) {
-          al[i] = *reinterpret_cast<const bf16x4*>(&Al[r * kLDK + kq]);
-          bl[i] = *reinterpret_cast<const bf16x4*>(&Bl[c * kLDK + kq]);
+          al[i] = *reinterpret_cast<const bf16x8*>(&Al[r * kLDK + kq]);
+          bl[i] = *reinterpret_cast<const bf16x8*>(&Bl[c * kLDK + kq]);
         }
       }
 #pragma unroll
@@ -184,10 +188,10 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           if constexpr (PASSES == 3) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
           }
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
         }
     }
     __syncthreads();
