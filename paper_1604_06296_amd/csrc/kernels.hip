@@ -558,7 +558,7 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
         }
       }
     };
-    // round 1: T1 = (chi'pp VP, chi'ph VC, chi'ph W); round 2: T2 = (VP T1_0, VC T1_1, W T1_2)
+    // first products T1 = (chi'pp VP, chi'ph VC, chi'ph W); second T2 = (VP T1_0, VC T1_1, W T1_2)
     for (int which = wv; which < 3; which += nwv)
       mm_tile(Ch + (which == 0 ? 0 : nff2), which == 0 ? VP : (which == 1 ? VC : Wm), T1 + which * nff2);
     __syncthreads();
