@@ -26,7 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "flow-RHS evals/sec and full-flow time vs plain FP64 GPU at Λ_c err ≤1%"
-PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CUs x 64 lanes x 2 flops x 2.4 GHz)
+PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CUs x 64 lanes x 2 flops x 2.4 GHz); FP64 MFMA the same
+PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector (and FP32 MFMA) peak
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 MFMA peak
 
 # HBM bytes per launch of the loop kernel at the headline workload (default
 # geometry), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by
@@ -247,6 +249,26 @@ def timed_flow(ctx, X, opts):
     return res, time.perf_counter() - t0
 
 
+def kernel_table(ctx, T, X, out, reps, precision):
+    """Each projection kernel and the products timed alone (the library's HIP events on the
+    context's stream): microseconds per launch, algorithmic TFLOP/s, and its fraction of the
+    peak of the unit that computes it.  The split-precision transforms execute three BF16
+    products (hi.hi, hi.lo, lo.hi) per algorithmic multiply-add: executed = 3 x algorithmic."""
+    mixed = precision == "mixed"
+    units = {"forward_transform": ("bf16 mfma", PEAK_BF16_TFLOPS, 3) if mixed else ("fp64 mfma", PEAK_FP64_TFLOPS, 1),
+             "bond_basis": ("fp64 valu", PEAK_FP64_TFLOPS, 1),
+             "gather": ("fp64 valu", PEAK_FP64_TFLOPS, 1),
+             "products": ("fp32", PEAK_FP32_TFLOPS, 1) if mixed else ("fp64", PEAK_FP64_TFLOPS, 1)}
+    units["inverse_transform"] = units["forward_transform"]
+    table = {}
+    for k, (us, fl) in ctx.kernel_times(T, X, out, reps=reps).items():
+        unit, peak, ex = units[k]
+        tfl = fl / (us * 1e-6) / 1e12
+        table[k] = {"us": us, "flops": fl, "tflops": tfl, "unit": unit, "peak": peak, "frac": tfl / peak,
+                    "executed_per_algorithmic": ex}
+    return table
+
+
 def leg_mixed(tf, synth):
     """cfg3: plain FP64 against the mixed-precision form, per result."""
     import torch
@@ -260,6 +282,8 @@ def leg_mixed(tf, synth):
     for p, ctx in ctxs.items():
         o = ctx.empty(3)
         out[f"rhs_ms_{p}"] = 1e3 * time_rhs(ctx, 0.05, X, o)
+        out[f"kernels_{p}"] = kernel_table(ctx, 0.05, X, o, 20, p)
+        log(f"[mixed] {p} kernels (us): " + ", ".join(f"{k} {v['us']:.2f}" for k, v in out[f"kernels_{p}"].items()))
         Xf = ctx.empty(3)
         r, el = timed_flow(ctx, Xf, opts)
         V = ctx.project(Xf)
@@ -570,6 +594,9 @@ def main():
     flops = ctx.flop_count()
     log(f"[bench] loop kernel {loop_us:.2f} us/launch, {achieved:.2f} TFLOP/s")
     traffic = LOOP_TRAFFIC["bytes"] if LOOP_TRAFFIC["sources_sha256"] == loop_kernel_sources_sha() else None
+    # the projection kernels and the products, each alone (outside the timed region)
+    kernels = kernel_table(ctx, 0.05, X, out, max(args.steps, 20), "fp64")
+    log("[bench] kernels (us): " + ", ".join(f"{k} {v['us']:.2f}" for k, v in kernels.items()))
 
     flow_info = None
     if not args.no_flow:
@@ -614,7 +641,7 @@ def main():
         "config": {"workload": w.name, "Lq": pt.Lq, "Lk": pt.Lk, "nff": nff, "t": pt.t,
                    "tp": pt.tp, "filling": pt.filling, "mu": pt.mu, "U": pt.U,
                    "loop_geometry": list(ctx.geometry(0)),
-                   "flow": flow_info, "flops_per_rhs": flops, **legs},
+                   "flow": flow_info, "flops_per_rhs": flops, "kernels": kernels, **legs},
         "roofline": {"bound": "alu", "kernel": "k_loops", "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic, "launch_us": loop_us, "flops_per_launch": alg_flops,

@@ -324,6 +324,24 @@ tufrg_status tufrg_flop_count(const tufrg_ctx* ctx, double out[3]);
 tufrg_status tufrg_loop_kernel_time(tufrg_ctx* ctx, const double* T_host, int32_t reps, double* us,
                                     double* flops);
 
+/* Diagnostic: average duration in microseconds of each kernel of the
+ * projections (Sec. 2.5: forward transform, bond basis, gather, inverse
+ * transform) and of the products (the right-hand side of Sec. 2.4), each
+ * measured alone: one right-hand side at temperatures T_host fills the
+ * workspace, then per stage one warm-up launch and `reps` back-to-back
+ * launches between HIP events on the context's stream.  Stage i: 0 forward
+ * transform, 1 bond basis, 2 gather, 3 inverse transform, 4 products (which
+ * write dX/dT into dXdT, device, caller-owned, the size of X; X and dXdT must
+ * not alias).  us[i] is that stage's average per launch (the launch and its
+ * kernels; several kernels where a stage is launched per class of points),
+ * flops[i] (may be NULL) its algorithmic flop count per launch, FMA = 2
+ * (parts of tufrg_flop_count's out[1] and out[2]; with symmetric states the
+ * inverse transform and the products count the orbit representatives only).
+ * TUFRG_EUNSUPPORTED with a surrogate attached, a dense projection operator
+ * or TUFRG_NO_CROSS.  Synchronises the stream. */
+tufrg_status tufrg_kernel_times(tufrg_ctx* ctx, const double* T_host, const double* X, double* dXdT,
+                                int32_t reps, double us[5], double flops[5]);
+
 /* Chemical potential for electron density n (both spins) at temperature T:
  * n = (2/L^2) sum_k n_F(eps_k) on the unshifted L x L grid, by bisection to
  * |dmu| < 1e-13.  Host-only; no context needed.  EINVAL for n outside (0, 2),

@@ -27,6 +27,7 @@ REGULATORS = {"T": 0, "omega": OMEGA_CUTOFF}
 # every entry point declared in include/tufrg.h
 EXPORTS = ("tufrg_init", "tufrg_init_mesh", "tufrg_layout", "tufrg_geometry", "tufrg_bubbles", "tufrg_project",
            "tufrg_rhs", "tufrg_rhs_noalloc", "tufrg_flow", "tufrg_symmetry_defect", "tufrg_sync", "tufrg_flop_count", "tufrg_loop_kernel_time",
+           "tufrg_kernel_times",
            "tufrg_mu_from_filling",
            "tufrg_harmonics", "tufrg_loop_harmonics", "tufrg_surrogate_dataset",
            "tufrg_surrogate_attach", "tufrg_surrogate_stats",
@@ -101,6 +102,7 @@ def load_library():
     lib.tufrg_symmetry_defect.argtypes = [vp, vp, dp]
     lib.tufrg_flop_count.argtypes = [vp, dp]
     lib.tufrg_loop_kernel_time.argtypes = [vp, dp, i32, dp, dp]
+    lib.tufrg_kernel_times.argtypes = [vp, dp, vp, vp, i32, dp, dp]
     lib.tufrg_mu_from_filling.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, i32, dp]
     u64, f32 = C.c_uint64, C.c_float
     lib.tufrg_harmonics.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)]
@@ -400,6 +402,17 @@ class Context:
         _check(self.lib, self.ctx, self.lib.tufrg_loop_kernel_time(self.ctx, self._T(T), reps, C.byref(us),
                                                                    C.byref(fl)))
         return us.value, fl.value
+
+    KERNEL_STAGES = ("forward_transform", "bond_basis", "gather", "inverse_transform", "products")
+
+    def kernel_times(self, T, X, out, reps: int = 50):
+        """{stage: (average microseconds per launch, algorithmic flops per launch)} of the
+        projection kernels and the products, each timed alone on one right-hand side's data
+        (the products write dX/dT into out)."""
+        us, fl = (C.c_double * 5)(), (C.c_double * 5)()
+        _check(self.lib, self.ctx, self.lib.tufrg_kernel_times(self.ctx, self._T(T), self._dev(X, 3),
+                                                               self._dev(out, 3), reps, us, fl))
+        return {k: (us[i], fl[i]) for i, k in enumerate(self.KERNEL_STAGES)}
 
     def flow(self, X, opts: FlowOptions, raise_nonfinite: bool = False) -> List[FlowResult]:
         o = _FlowOpts(opts.T0, opts.Tmin, opts.Xmax, SCHEMES[opts.scheme], opts.nsteps, opts.rtol,

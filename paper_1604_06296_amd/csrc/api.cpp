@@ -1269,6 +1269,65 @@ tufrg_status tufrg_loop_kernel_time(tufrg_ctx* ctx, const double* T_host, int32_
   return TUFRG_OK;
 }
 
+tufrg_status tufrg_kernel_times(tufrg_ctx* ctx, const double* T_host, const double* X, double* dXdT,
+                                int32_t reps, double us[5], double flops[5]) {
+  if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
+  if (!T_host || !X || !dXdT || !us || reps < 1) return fail(ctx, TUFRG_EINVAL, "need T_host, X, dXdT, us and reps >= 1");
+  if (X == dXdT) return fail(ctx, TUFRG_EINVAL, "X and dXdT must not alias");
+  if (ctx->sur_a) return fail(ctx, TUFRG_EUNSUPPORTED, "kernel timing is not available with a surrogate attached");
+  if (ctx->L.dense || !cross_of(ctx))
+    return fail(ctx, TUFRG_EUNSUPPORTED, "kernel timing needs the factored projections (no dense operator, no NO_CROSS)");
+  ST_TRY(check_temperatures(ctx, T_host));
+  hipStream_t s = ctx->stream;
+  const bool mixed = mixed_of(ctx);
+  const Launch& L = ctx->L;
+  const Ranges& r = ctx->all;
+  // one right-hand side leaves every stage's input in the workspace
+  rhs_launch(ctx, L, r, X, dXdT, false, s, TSource{T_host, 0, (int)ctx->dev.size(), 0});
+  HIP_TRY(ctx, hipGetLastError());
+  auto stage = [&](int i) {
+    switch (i) {
+      case 0: launch_fwd(L, r, X, mixed, s); break;
+      case 1: launch_basis(L, r, s); break;
+      case 2: launch_gather(L, r, s); break;
+      case 3: launch_inv(L, r, mixed, s); break;
+      default: launch_back(L, r, X, dXdT, 1, true, false, mixed, s); break;
+    }
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  for (int i = 0; i < 5 && e == hipSuccess; ++i) {
+    stage(i);   // warm-up
+    e = hipEventRecord(e0, s);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) stage(i);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    us[i] = 1e3 * (double)ms / reps;
+  }
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  if (e != hipSuccess) return fail(ctx, TUFRG_EHIP, std::string("kernel timing: ") + hipGetErrorString(e));
+  HIP_TRY(ctx, hipGetLastError());
+  if (flops) {
+    for (int i = 0; i < 5; ++i) flops[i] = 0.0;
+    const bool wedge = L.b.wedge != 0;
+    for (const HostTables& t : ctx->host) {
+      // with symmetric states the inverse transform and the products run at
+      // the orbit representatives only
+      const double rows = wedge ? (double)t.nirr / t.nq : 1.0;
+      flops[0] += (double)t.flops_fwd;
+      flops[1] += (double)t.flops_basis;
+      flops[2] += (double)t.flops_gather;
+      flops[3] += (double)t.flops_inv * rows;
+      flops[4] += (double)t.flops_prod * rows;
+    }
+  }
+  return TUFRG_OK;
+}
+
 tufrg_status tufrg_symmetry_defect(tufrg_ctx* ctx, const double* X, double* rel) {
   if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
   if (!X || !rel) return fail(ctx, TUFRG_EINVAL, "NULL argument");

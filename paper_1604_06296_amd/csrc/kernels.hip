@@ -1126,10 +1126,18 @@ void launch_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, h
   }
 }
 
-void launch_gather_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t s) {
+void launch_gather(const Launch& L, const Ranges& r, hipStream_t s) {
   if (r.gather.n > 0)
     hipLaunchKernelGGL(k_gather_g2, dim3(r.gather.n), dim3(64), 0, s, L.b, L.gather_items + r.gather.begin,
                        L.gather_ent, L.gather_cap);
+}
+
+void launch_gather_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t s) {
+  launch_gather(L, r, s);
+  launch_inv(L, r, mixed, s);
+}
+
+void launch_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t s) {
   if (r.inv.n > 0) {
     const int4* it = L.inv_items + r.inv.begin;
     const dim3 g(r.inv.n), blk(256);
@@ -1162,10 +1170,14 @@ void launch_gather_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t
   }
 }
 
-void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s) {
-  launch_fwd(L, r, X, mixed, s);
+void launch_basis(const Launch& L, const Ranges& r, hipStream_t s) {
   if (r.basis.n > 0)
     hipLaunchKernelGGL(k_bond_basis, dim3(r.basis.n), dim3(256), 0, s, L.b, L.basis_items + r.basis.begin);
+}
+
+void launch_front(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s) {
+  launch_fwd(L, r, X, mixed, s);
+  launch_basis(L, r, s);
   launch_gather_inv(L, r, mixed, s);
 }
 

@@ -546,7 +546,11 @@ std::string build_tables(const tufrg_point& p, const tufrg_mesh* mesh, HostTable
     bb += ns * ns;
   }
   const double basis = 3.0 * nv * 8.0 * bb * f2 * 2.0;   // two sides, complex, both stages
-  t.flops_proj = (int64_t)(2.0 * 3.0 * f2 * t.ncol * nq * 2.0 + basis + 2.0 * t.ment.size());
+  t.flops_fwd = (int64_t)(3.0 * f2 * t.ncol * nq * 2.0);
+  t.flops_inv = t.flops_fwd;
+  t.flops_basis = (int64_t)basis;
+  t.flops_gather = (int64_t)(2.0 * t.ment.size());
+  t.flops_proj = t.flops_fwd + t.flops_basis + t.flops_gather + t.flops_inv;
   t.flops_prod = (int64_t)(nq * 6.0 * 2.0 * f3);
   return "";
 }

@@ -73,6 +73,8 @@ struct HostTables {
   std::vector<int32_t> ment;      // packed entries (see pack_entry)
   int64_t flops_loops = 0, flops_proj = 0, flops_prod = 0;
   int64_t flops_loop_kernel = 0;  // the loop kernel alone (flops_loops adds the chi' expansion)
+  // the parts of flops_proj: forward transform, bond basis, gather, inverse transform
+  int64_t flops_fwd = 0, flops_basis = 0, flops_gather = 0, flops_inv = 0;
 };
 
 // packed gather entry: input channel (2 bits), bonds b1, b2 (5 bits each),
@@ -289,6 +291,10 @@ void launch_dense(const Launch& L, const Ranges& r, const double* X, hipStream_t
 void launch_set_unit(double* X, int64_t prev, int64_t cur, hipStream_t s);
 void launch_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, hipStream_t s);
 void launch_gather_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t s);
+// the parts of launch_front one at a time (bond basis, gather, inverse transform)
+void launch_basis(const Launch& L, const Ranges& r, hipStream_t s);
+void launch_gather(const Launch& L, const Ranges& r, hipStream_t s);
+void launch_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t s);
 void launch_loops_fwd(const Launch& L, const Ranges& r, const double* X, bool mixed, bool cross,
                       const TArg& ta, hipStream_t s);
 void launch_expand_basis(const Launch& L, const Ranges& r, double* dchi, bool cross, hipStream_t s);
