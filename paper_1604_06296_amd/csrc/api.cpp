@@ -1023,7 +1023,9 @@ tufrg_status tufrg_init_mesh(const tufrg_point* pts, const tufrg_mesh* meshes, i
       hipStreamCreateWithFlags(&ctx->gs, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->ev_gs, hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&ctx->ev_gs, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_att[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_att[1], hipEventDisableTiming) != hipSuccess)
     return bad(fail(ctx, TUFRG_EHIP, "stream or event creation failed"));
   // loop-kernel work queue: zero once, then reset by every launch at its end
   launch_fill_i32(ctx->queue, 2, 0, ctx->stream);
@@ -1668,6 +1670,16 @@ tufrg_status flow_dopri5_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X
     ST_TRY(upload(ctx, seg, &ctx->dp_seg, ctx->allocations));
     ST_TRY(upload(ctx, nel, &ctx->dp_nel, ctx->allocations));
   }
+  if (!ctx->dp_status_host) {
+    void* hp = nullptr;
+    void* dp = nullptr;
+    if (hipHostMalloc(&hp, sizeof(int) * npts, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+      return fail(ctx, TUFRG_ENOMEM, "pinned host allocation failed");
+    ctx->dp_status_host = static_cast<int*>(hp);
+    if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess)
+      return fail(ctx, TUFRG_EHIP, "no device address for the mapped status words");
+    ctx->dp_status_dev = static_cast<int*>(dp);
+  }
   const double s0 = std::log(o->T0), s_end = std::log(o->Tmin);
   const double h0 = (o->h0 != 0.0) ? o->h0 : (s_end - s0) / 200.0;
   const int max_steps = o->max_steps > 0 ? o->max_steps : 100000;
@@ -1733,6 +1745,8 @@ tufrg_status flow_dopri5_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X
   dc.xmax = o->Xmax;
   dc.max_steps = max_steps;
   dc.npts = npts;
+  dc.status_out = ctx->dp_status_dev;
+  for (int p = 0; p < npts; ++p) ctx->dp_status_host[p] = 0;
   auto attempt = [&]() {
     for (int i = 1; i < 7; ++i) {
       if (i > 1 && !fuse_stages) launch_axpy(Lf, r.seg, X, k, kDpA[i], i, 0.0, stg[i & 1], true, ms, h_arr);
@@ -1769,56 +1783,44 @@ tufrg_status flow_dopri5_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X
       return fail(ctx, TUFRG_EHIP, std::string("graph capture of the adaptive step: ") + hipGetErrorString(ge));
     }
   }
-  // attempts in batches; the host reads the points' states between batches
-  // (a batch is sized by the remaining distance of the slowest point)
-  std::vector<DpState> stv(npts);
-  int attempted = 0, batch = 4;
-  for (;;) {
-    for (int i = 0; i < batch; ++i) {
-      if (exec) {
-        const hipError_t ge = hipGraphLaunch(exec, ms);
-        if (ge != hipSuccess) {
-          cleanup();
-          return fail(ctx, TUFRG_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(ge));
-        }
-      } else {
-        attempt();
-      }
+  // attempts are issued one ahead of the host's view: after issuing attempt n
+  // the host waits for attempt n - 1 and reads the points' status words (the
+  // control kernel writes them to mapped host memory), so the stream always
+  // holds the next attempt and never drains mid-flow; once every point has
+  // stopped, the one attempt issued after that runs as a no-op (its kernels
+  // skip stopped points).  max_steps bounds the attempts of every point on
+  // the device; the count here is only a backstop.
+  int attempted = 0;
+  auto issue = [&]() -> hipError_t {
+    if (exec) {
+      const hipError_t ge = hipGraphLaunch(exec, ms);
+      if (ge != hipSuccess) return ge;
+    } else {
+      attempt();
     }
-    attempted += batch;
-    hipError_t ge = hipMemcpyAsync(stv.data(), ctx->dp_state, sizeof(DpState) * npts, hipMemcpyDeviceToHost, ms);
-    if (ge == hipSuccess) ge = hipStreamSynchronize(ms);
+    return hipEventRecord(ctx->ev_att[attempted++ & 1], ms);
+  };
+  hipError_t ge = issue();
+  while (ge == hipSuccess) {
+    const bool more = attempted <= max_steps;
+    if (more) ge = issue();
+    if (ge != hipSuccess) break;
+    ge = hipEventSynchronize(ctx->ev_att[(attempted - (more ? 2 : 1)) & 1]);
     if (ge == hipSuccess) ge = hipGetLastError();
-    if (ge != hipSuccess) {
-      cleanup();
-      return fail(ctx, TUFRG_EHIP, std::string("adaptive flow: ") + hipGetErrorString(ge));
-    }
-    // the next batch: the attempts the slowest flowing point still needs at
-    // most, to T_min at its current step or, once its max|X| is a quarter of
-    // the way to the stop rule, 0.4 times the log-linear extrapolation of its
-    // last two accepted steps to X_max (growth towards a divergence is faster
-    // than log-linear, so the extrapolation is long); attempts after every
-    // point has stopped would be no-ops, the batch only bounds their number
+    if (ge != hipSuccess) break;
     bool all_done = true;
-    double need = 1.0;
-    for (const DpState& q : stv)
-      if (q.status == 0) {
-        all_done = false;
-        const double ah = std::max(std::fabs(q.h), 1e-300);
-        double n_p = std::ceil((q.s - s_end) / ah);
-        if (q.m1 > 0.25 * o->Xmax) {
-          double est = 1.0;
-          if (q.m0 > 0.0 && q.m1 > q.m0 && q.s0 != q.s1) {
-            const double sc =
-                q.s1 + (std::log(o->Xmax) - std::log(q.m1)) * (q.s1 - q.s0) / (std::log(q.m1) - std::log(q.m0));
-            est = std::max(1.0, std::floor(0.4 * (q.s1 - sc) / ah));
-          }
-          n_p = std::min(n_p, est);
-        }
-        need = std::max(need, n_p);
-      }
-    if (all_done || attempted > max_steps + 1) break;
-    batch = (int)std::min(8.0, std::max(1.0, need));
+    const volatile int* hs = ctx->dp_status_host;
+    for (int p = 0; p < npts && all_done; ++p) all_done = hs[p] != 0;
+    if (all_done || !more) break;
+  }
+  std::vector<DpState> stv(npts);
+  if (ge == hipSuccess)
+    ge = hipMemcpyAsync(stv.data(), ctx->dp_state, sizeof(DpState) * npts, hipMemcpyDeviceToHost, ms);
+  if (ge == hipSuccess) ge = hipStreamSynchronize(ms);
+  if (ge == hipSuccess) ge = hipGetLastError();
+  if (ge != hipSuccess) {
+    cleanup();
+    return fail(ctx, TUFRG_EHIP, std::string("adaptive flow: ") + hipGetErrorString(ge));
   }
   cleanup();
   std::vector<int> first;
@@ -1878,7 +1880,10 @@ void tufrg_free(tufrg_ctx* ctx) {
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   if (ctx->ev_gs) (void)hipEventDestroy(ctx->ev_gs);
+  for (hipEvent_t e : ctx->ev_att)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->umax_host) (void)hipHostFree(ctx->umax_host);
+  if (ctx->dp_status_host) (void)hipHostFree(ctx->dp_status_host);
   if (ctx->red_host) (void)hipHostFree(ctx->red_host);
   for (void* p : ctx->sur_allocations) (void)hipFree(p);
   for (void* p : ctx->geometry_allocations) (void)hipFree(p);

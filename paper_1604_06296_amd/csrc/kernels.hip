@@ -884,6 +884,7 @@ __global__ void __launch_bounds__(256) k_dp_control(DpControl c) {
   c.s_arr[p] = st.s;
   c.h_arr[p] = st.h;
   c.st[p] = st;
+  if (c.status_out != nullptr) c.status_out[p] = st.status;
 }
 
 // y = y5 and k0 = k6 (first same as last) for the points whose attempt was

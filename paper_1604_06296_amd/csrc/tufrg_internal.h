@@ -329,6 +329,7 @@ struct DpControl {
   double* h_arr;
   double s_end, xmax;
   int max_steps, npts;
+  int* status_out;        // mapped host memory or null: each point's status after the attempt
 };
 void launch_dp_control(const DpControl& c, hipStream_t s);
 // y = y5 and k0 = k6 where the attempt was accepted, then the first stage of
@@ -371,6 +372,7 @@ struct tufrg_ctx {
   hipStream_t side = nullptr;              // loops run here, concurrently with the projections
   hipStream_t gs = nullptr;                // capture and replay stream of the graph-driven flow
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gs = nullptr;
+  hipEvent_t ev_att[2] = {nullptr, nullptr}; // the adaptive flow's attempts, alternating
   tufrg::Launch L{};
   tufrg::Ranges all;                       // item ranges of all points
   std::vector<tufrg::Ranges> per_point;    // item ranges of each point
@@ -389,6 +391,8 @@ struct tufrg_ctx {
   int nred = 0;
   unsigned long long* umax = nullptr;      // per-point max words
   unsigned long long* umax_host = nullptr; // pinned
+  int* dp_status_host = nullptr;           // pinned, mapped: per-point status of the adaptive flow
+  int* dp_status_dev = nullptr;            // its device address
   double* Ttab = nullptr;                  // RK4 stage temperatures [nsteps][4]
   double* hist = nullptr;                  // max|X| history [nsteps+1][npts]
   int* step = nullptr;                     // device step counter
