@@ -1647,7 +1647,7 @@ const double kDpB4[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640, -9209
 // acceptance copy (y = y5, k0 = k6).  Each point has its own s and h in device
 // memory; the kernels read them, so the attempt can be captured in a HIP
 // graph and replayed.  A point that has stopped is skipped by every kernel.
-// The host checks the stop flags only between batches of attempts.
+// The host follows the points' status words one attempt behind the stream.
 tufrg_status flow_dopri5_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tufrg_flow_result* res) {
   const int npts = (int)ctx->dev.size();
   double* k[7];
