@@ -345,7 +345,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
     DevTables& d = ctx->dev[p];
     smax_max = std::max(smax_max, d.smax);
     const int nff2 = d.nff * d.nff;
-    psm = std::max(psm, sizeof(double) * 12 * (size_t)nff2);
+    psm = std::max(psm, sizeof(double) * 10 * (size_t)nff2);
     kpt = std::max(kpt, (d.ncol + 15) / 16);
     d.ws_gh = gh;
     gh += (int64_t)d.nsplit * d.nirr * 2 * d.nsh;

@@ -439,12 +439,14 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
   auto stage_put = [&](size_t e, double v, double x0, double a) {
     sn.out[e] = fma(hstep, fma(sn.coef[sn.nk - 1], v, a), x0);
   };
+  // shared memory [10][nff2]: the second products T2 take the loops' rows
+  // (read only by the first products) and one row more
   extern __shared__ double smem_prod[];
   R* Vs = reinterpret_cast<R*>(smem_prod);   // [3][nff2]
-  R* Ch = Vs + 3 * nff2;                    // [2][nff2]
-  R* Wm = Ch + 2 * nff2;                    // [nff2]
+  R* Wm = Vs + 3 * nff2;                    // [nff2]
   R* T1 = Wm + nff2;                        // [3][nff2]
-  R* T2 = T1 + 3 * nff2;                    // [3][nff2]
+  R* Ch = T1 + 3 * nff2;                    // [2][nff2]
+  R* T2 = Ch;                               // [3][nff2], after the first products
   // symmetric states: the representative's orbit (at most 8 members), each
   // member's q and form-factor permutation, staged with the block's loads
   __shared__ int orb_q_s[8];
@@ -1237,9 +1239,9 @@ void launch_back(const Launch& L, const Ranges& r, const double* X, double* out,
     launch(r.prod, L.prod_smem);
     return;
   }
-  // one launch per N_ff, each with the [12][N_ff^2] shared memory of its own matrices
+  // one launch per N_ff, each with the [10][N_ff^2] shared memory of its own matrices
   for (int c = 0; c < r.nprod_cls; ++c)
-    launch(r.prod_cls[c], sizeof(double) * 12 * (size_t)r.prod_cls_nff[c] * r.prod_cls_nff[c]);
+    launch(r.prod_cls[c], sizeof(double) * 10 * (size_t)r.prod_cls_nff[c] * r.prod_cls_nff[c]);
 }
 
 void launch_axpy(const Launch& L, const ItemRange& r, const double* X, const double* const* k,
