@@ -37,38 +37,39 @@ __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, Basi
   double* cs = sh.cs;
   double* xs = sh.xs;
   {
-    // 2 nff^2 sums of nsu terms; each of the NT threads keeps up to 4 sums and
-    // 8 splits of each in flight, then adds them in split order
+    // 2 nff^2 sums of nsu terms; each of the NT threads keeps up to kSums sums
+    // and kSplits splits of each in flight, then adds them in split order
+    constexpr int kSums = 2, kSplits = 16;
     const int N = 3 * nff2, nel = 2 * nff2;
     const size_t sstride = (size_t)ncol * N;
     const double* base = b.xp + d.ws_xp + (size_t)in * nff2;
     const double inv = 1.0 / (double)d.nq;
-    for (int e0 = threadIdx.x; e0 < nel; e0 += 4 * NT) {
-      const double* src[4];
-      bool ok[4];
-      double acc[4];
+    for (int e0 = threadIdx.x; e0 < nel; e0 += kSums * NT) {
+      const double* src[kSums];
+      bool ok[kSums];
+      double acc[kSums];
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
+      for (int s4 = 0; s4 < kSums; ++s4) {
         const int e = e0 + NT * s4;
         const bool im = e >= nff2;
         ok[s4] = e < nel && (!im || j > 0);
         src[s4] = base + (size_t)(im ? nsh - 1 + j : j) * N + (im ? e - nff2 : e);
         acc[s4] = 0.0;
       }
-      for (int sp0 = 0; sp0 < d.nsu; sp0 += 8) {
-        double v[4][8];
+      for (int sp0 = 0; sp0 < d.nsu; sp0 += kSplits) {
+        double v[kSums][kSplits];
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
+        for (int s4 = 0; s4 < kSums; ++s4)
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
+          for (int u = 0; u < kSplits; ++u)
             v[s4][u] = (ok[s4] && sp0 + u < d.nsu) ? src[s4][(size_t)(sp0 + u) * sstride] : 0.0;
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
+        for (int s4 = 0; s4 < kSums; ++s4)
 #pragma unroll
-          for (int u = 0; u < 8; ++u) acc[s4] += v[s4][u];
+          for (int u = 0; u < kSplits; ++u) acc[s4] += v[s4][u];
       }
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
+      for (int s4 = 0; s4 < kSums; ++s4) {
         const int e = e0 + NT * s4;
         if (e < nel) xs[e] = (e < nff2 ? 1.0 : sim) * acc[s4] * inv;
       }
