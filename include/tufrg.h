@@ -54,8 +54,12 @@
  * Concurrency: a context belongs to one host thread and one HIP stream.
  * Calls on one context must not overlap.  The step calls (bubbles, project,
  * rhs) allocate nothing; all their workspace is allocated by tufrg_init.
- * tufrg_flow allocates its RK4 step tables the first time a larger nsteps
- * is asked for, and instantiates (then destroys) a HIP graph when use_graph
+ * tufrg_flow allocates its state buffers on its first call, its RK4 step
+ * tables the first time a larger nsteps is asked for, and for the adaptive
+ * scheme the step-control state and a small pinned, mapped host array of the
+ * points' status words (which its control kernel writes, so that the host
+ * follows the flow without synchronising the stream each step) on its first
+ * adaptive call; it instantiates (then destroys) a HIP graph when use_graph
  * is set.
  */
 #ifndef TUFRG_H

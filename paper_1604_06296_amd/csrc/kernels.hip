@@ -473,12 +473,20 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
     for (int ch = 0; ch < 3; ++ch) {
       xv[h][ch] = ok ? X[ch * S + d.off + (size_t)l * nff2 + mn] : 0.0;
       kv[h][ch] = (ok && cross) ? (double)K[((size_t)ch * nq + l) * nff2 + mn] : 0.0;
-      sx[h][ch] = sa[h][ch] = 0.0;
-      if (ok && stage && !b.wedge) stage_part(ch * S + d.off + (size_t)l * nff2 + mn, sx[h][ch], sa[h][ch]);
     }
 #pragma unroll
     for (int ch = 0; ch < 2; ++ch)
       cv[h][ch] = (ok && mode != 0) ? b.dchi[(size_t)ch * S + d.off + (size_t)l * nff2 + mn] : 0.0;
+  }
+  // the next stage's operands after the products' own (they are needed last)
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int mn = threadIdx.x + 256 * h;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      sx[h][ch] = sa[h][ch] = 0.0;
+      if (mn < nff2 && stage && !b.wedge) stage_part(ch * S + d.off + (size_t)l * nff2 + mn, sx[h][ch], sa[h][ch]);
+    }
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
