@@ -156,7 +156,7 @@ k_dft_fwd_part(Batch b, const int4* __restrict__ items, const double* __restrict
 __global__ void __launch_bounds__(256)
 k_bond_basis(Batch b, const int4* __restrict__ items) {
   __shared__ BasisShared sh;
-  basis_body<false>(b, items[blockIdx.x], sh);
+  basis_body<false, false>(b, items[blockIdx.x], sh);
 }
 
 // The loop expansion and the bond basis in one launch (they are independent:
@@ -171,7 +171,7 @@ k_expand_basis(Batch b, const int4* __restrict__ exp_items, int nexp, const int4
     BasisShared s;
   } sh;
   if ((int)blockIdx.x < nexp) expand_body<ONE>(b, exp_items[blockIdx.x], nullptr, dchi, sh.e);
-  else basis_body<ONE>(b, basis_items[blockIdx.x - nexp], sh.s);
+  else basis_body<ONE, true>(b, basis_items[blockIdx.x - nexp], sh.s);
 }
 
 __global__ void __launch_bounds__(64)

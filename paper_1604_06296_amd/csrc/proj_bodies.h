@@ -24,7 +24,10 @@ struct alignas(16) BasisShared {
   double cs[2 * 441];
   double xs[2 * 441];
 };
-template <bool ONE, int NT = 256>
+// WIDE: all splits of a sum in one round of loads where the splits are few
+// (the launches of small contexts); otherwise 8 splits of 4 sums per round
+// (fewer registers for the many blocks of large contexts).
+template <bool ONE, bool WIDE, int NT = 256>
 __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, BasisShared& sh) {
   const int p = ONE ? 0 : item.x;
   if (skip_point(b, p)) return;
@@ -39,7 +42,7 @@ __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, Basi
   {
     // 2 nff^2 sums of nsu terms; each of the NT threads keeps up to kSums sums
     // and kSplits splits of each in flight, then adds them in split order
-    constexpr int kSums = 2, kSplits = 16;
+    constexpr int kSums = WIDE ? 2 : 4, kSplits = WIDE ? 16 : 8;
     const int N = 3 * nff2, nel = 2 * nff2;
     const size_t sstride = (size_t)ncol * N;
     const double* base = b.xp + d.ws_xp + (size_t)in * nff2;
