@@ -128,6 +128,8 @@ struct GatherShared {
   double Mim[2][kShellMax * kShellMax];
   double C1[2][kShellMax * kShellMax];   // c_{m a}, m and a in shell sm (re, im)
   double C2[2][kShellMax * kShellMax];   // c_{n b}, n and b in shell sn
+  double Tre[2][kShellMax * kShellMax];  // M C^T of the shell block, [a][n]
+  double Tim[2][kShellMax * kShellMax];
 };
 
 // phase 1 (lane of the wave): the rows' entries and their yb values, and the
@@ -178,13 +180,28 @@ __device__ __forceinline__ void gather_load(const Batch& b, const int4 item, con
   }
 }
 
-// phase 2 (after the barrier): N = C M C^T of the shell block and its
-// inverse-transform coefficients into g2
-__device__ __forceinline__ void gather_store(const Batch& b, const int4 item, int lane, const GatherShared& sh) {
+// phase 2 (after the barrier): N = C M C^T of the shell block as two
+// products, T = M C^T (each entry a sum over b in bond order) and then
+// N = C T (a sum over a), with a barrier of the caller's block between them,
+// and its inverse-transform coefficients into g2
+__device__ __forceinline__ void gather_store(const Batch& b, const int4 item, int lane, GatherShared& sh) {
   const int p = item.x;
   const int j = item.y & 0xff, X = (item.y >> 8) & 3, na = (item.y >> 10) & 15, nb = (item.y >> 14) & 15;
   const int a0 = (item.y >> 18) & 31, b0 = (item.y >> 23) & 31;
   const int nab = na * nb, nvl = j == 0 ? 1 : 2;
+  for (int w = lane; w < nvl * nab; w += 64) {
+    const int vi = w / nab, a = w % nab / nb, n = w % nb;   // T[vi][a][n]
+    double tr = 0.0, ti = 0.0;
+    for (int bb = 0; bb < nb; ++bb) {
+      const double c2r = sh.C2[0][n * nb + bb], c2i = sh.C2[1][n * nb + bb];
+      const double mr = sh.Mre[vi][a * nb + bb], mi = sh.Mim[vi][a * nb + bb];
+      tr += c2r * mr - c2i * mi;
+      ti += c2r * mi + c2i * mr;
+    }
+    sh.Tre[vi][a * nb + n] = tr;
+    sh.Tim[vi][a * nb + n] = ti;
+  }
+  __syncthreads();
   const DevTables& d = b.pts[p];
   const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol;
   double* g2 = b.g2 + d.ws_g2;
@@ -193,14 +210,10 @@ __device__ __forceinline__ void gather_store(const Batch& b, const int4 item, in
     double nr[2] = {0.0, 0.0}, ni[2] = {0.0, 0.0};
     for (int a = 0; a < na; ++a) {
       const double c1r = sh.C1[0][(m - a0) * na + a], c1i = sh.C1[1][(m - a0) * na + a];
-      for (int bb = 0; bb < nb; ++bb) {
-        const double c2r = sh.C2[0][(n - b0) * nb + bb], c2i = sh.C2[1][(n - b0) * nb + bb];
-        const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
-        for (int vi = 0; vi < nvl; ++vi) {
-          const double mr = sh.Mre[vi][a * nb + bb], mi = sh.Mim[vi][a * nb + bb];
-          nr[vi] += wr * mr - wi * mi;
-          ni[vi] += wr * mi + wi * mr;
-        }
+      for (int vi = 0; vi < nvl; ++vi) {
+        const double tr = sh.Tre[vi][a * nb + n - b0], ti = sh.Tim[vi][a * nb + n - b0];
+        nr[vi] += c1r * tr - c1i * ti;
+        ni[vi] += c1r * ti + c1i * tr;
       }
     }
     if (j == 0) {
