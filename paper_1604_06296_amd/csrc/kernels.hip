@@ -190,12 +190,14 @@ k_gather_g2(Batch b, const int4* __restrict__ items, const int2* __restrict__ ge
 // accumulator tiles of v_mfma_f64_16x16x4f64 (16 momenta each; lane layout
 // as in the forward transform).  LT is the largest of 4, 2, 1 that still gives
 // the launch enough items.  With symmetric states (b.wedge) the rows are the
-// orbit representatives irr[r] only.
-template <int LT, bool ONE>
+// orbit representatives irr[r] only.  NC: chunks of 16 harmonics staged
+// together (3 for the one-tile form of small points, whose few harmonics
+// then pass through LDS in one stage).
+template <int LT, bool ONE, int NC = 1>
 __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict__ items) {
-  constexpr int TL = 16 * LT;
-  __shared__ double Es[16][TL + 2];   // [k][l]
-  __shared__ double Gs[16][64 + 2];   // [k][col]
+  constexpr int TL = 16 * LT, KC = 16 * NC;
+  __shared__ double Es[KC][TL + 2];   // [k][l]
+  __shared__ double Gs[KC][64 + 2];   // [k][col]
   const int4 item = items[blockIdx.x];
   const int p = ONE ? 0 : item.x;   // ONE: a single-point launch
   if (skip_point(b, p)) return;
@@ -219,33 +221,39 @@ __global__ void __launch_bounds__(256) k_dft_inv(Batch b, const int4* __restrict
     const int r = l0 + ((tid + 256 * i) >> 4);
     lrow[i] = r < nrow ? (b.wedge ? d.irr[r] : r) : -1;
   }
-  // software pipeline: chunk c + 1's loads are in flight during chunk c's MFMAs
-  double ev[LT], gv[4];
+  // software pipeline: stage c + 1's loads are in flight during stage c's MFMAs
+  double ev[NC][LT], gv[NC][4];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < LT; ++i) {
-      const int k = k0 + ((tid + 256 * i) & 15);
-      ev[i] = (lrow[i] >= 0 && k < ncol) ? d.eph[(size_t)lrow[i] * ncol + k] : 0.0;
-    }
+    for (int c = 0; c < NC; ++c) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int k = k0 + gk + 4 * i;
-      gv[i] = (gok && k < ncol) ? gsrc[(size_t)k * nff2] : 0.0;
+      for (int i = 0; i < LT; ++i) {
+        const int k = k0 + 16 * c + ((tid + 256 * i) & 15);
+        ev[c][i] = (lrow[i] >= 0 && k < ncol) ? d.eph[(size_t)lrow[i] * ncol + k] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = k0 + 16 * c + gk + 4 * i;
+        gv[c][i] = (gok && k < ncol) ? gsrc[(size_t)k * nff2] : 0.0;
+      }
     }
   };
   load(0);
-  for (int k0 = 0; k0 < ncol; k0 += 16) {
+  for (int k0 = 0; k0 < ncol; k0 += KC) {
 #pragma unroll
-    for (int i = 0; i < LT; ++i) {
-      const int e = tid + 256 * i;
-      Es[e & 15][e >> 4] = ev[i];
+    for (int c = 0; c < NC; ++c) {
+#pragma unroll
+      for (int i = 0; i < LT; ++i) {
+        const int e = tid + 256 * i;
+        Es[16 * c + (e & 15)][e >> 4] = ev[c][i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Gs[16 * c + gk + 4 * i][gc] = gv[c][i];
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) Gs[gk + 4 * i][gc] = gv[i];
     __syncthreads();
-    if (k0 + 16 < ncol) load(k0 + 16);
+    if (k0 + KC < ncol) load(k0 + KC);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
+    for (int kk = 0; kk < KC; kk += 4) {
       const double bv = Gs[kk + k4][16 * w + r16];
 #pragma unroll
       for (int t = 0; t < LT; ++t)
@@ -1167,8 +1175,8 @@ void launch_inv(const Launch& L, const Ranges& r, bool mixed, hipStream_t s) {
       }
     } else {
       switch (L.inv_lt) {
-        case 1: if (one) hipLaunchKernelGGL((k_dft_inv<1, true>), g, blk, 0, s, L.b, it);
-          else hipLaunchKernelGGL((k_dft_inv<1, false>), g, blk, 0, s, L.b, it);
+        case 1: if (one) hipLaunchKernelGGL((k_dft_inv<1, true, 3>), g, blk, 0, s, L.b, it);
+          else hipLaunchKernelGGL((k_dft_inv<1, false, 3>), g, blk, 0, s, L.b, it);
           break;
         case 2: if (one) hipLaunchKernelGGL((k_dft_inv<2, true>), g, blk, 0, s, L.b, it);
           else hipLaunchKernelGGL((k_dft_inv<2, false>), g, blk, 0, s, L.b, it);
