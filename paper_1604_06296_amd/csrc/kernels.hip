@@ -448,13 +448,15 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
     sn.out[e] = fma(hstep, fma(sn.coef[sn.nk - 1], v, a), x0);
   };
   // shared memory [10][nff2]: the second products T2 take the loops' rows
-  // (read only by the first products) and one row more
+  // (read only by the first products) and one row more, after a barrier;
+  // on the FP64 matrix-core path the first products stay in registers and
+  // T2 takes their rows (no barrier between the two products)
   extern __shared__ double smem_prod[];
   R* Vs = reinterpret_cast<R*>(smem_prod);   // [3][nff2]
   R* Wm = Vs + 3 * nff2;                    // [nff2]
   R* T1 = Wm + nff2;                        // [3][nff2]
   R* Ch = T1 + 3 * nff2;                    // [2][nff2]
-  R* T2 = Ch;                               // [3][nff2], after the first products
+  R* T2 = (sizeof(R) == 8 && nff <= 16) ? T1 : Ch;   // [3][nff2]
   // symmetric states: the representative's orbit (at most 8 members), each
   // member's q and form-factor permutation, staged with the block's loads
   __shared__ int orb_q_s[8];
@@ -577,11 +579,40 @@ k_products(Batch b, const int4* __restrict__ items, const double* __restrict__ X
       }
     };
     // first products T1 = (chi'pp VP, chi'ph VC, chi'ph W); second T2 = (VP T1_0, VC T1_1, W T1_2)
-    for (int which = wv; which < 3; which += nwv)
-      mm_tile(Ch + (which == 0 ? 0 : nff2), which == 0 ? VP : (which == 1 ? VC : Wm), T1 + which * nff2);
-    __syncthreads();
-    for (int which = wv; which < 3; which += nwv)
-      mm_tile(which == 0 ? VP : (which == 1 ? VC : Wm), T1 + which * nff2, T2 + which * nff2);
+    if constexpr (sizeof(R) == 8) {
+      // FP64: a wave's first product stays in its registers, since the f64
+      // result layout (row 4j + l/16 of column l%16 in element j) is the
+      // layout of the second product's B operand for the k rows 4j .. 4j + 3
+      for (int which = wv; which < 3; which += nwv) {
+        const R* V1 = which == 0 ? VP : (which == 1 ? VC : Wm);
+        const R* A1 = Ch + (which == 0 ? 0 : nff2);
+        f64x4 t1 = {0.0, 0.0, 0.0, 0.0}, t2 = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < 16; k0 += 4) {
+          const int k = k0 + k4;
+          const double av = (r16 < nff && k < nff) ? (double)A1[r16 * nff + k] : 0.0;
+          const double bv = (k < nff && r16 < nff) ? (double)V1[k * nff + r16] : 0.0;
+          t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, t1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int k = 4 * j + k4;
+          const double av = (r16 < nff && k < nff) ? (double)V1[r16 * nff + k] : 0.0;
+          t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, t1[j], t2, 0, 0, 0);
+        }
+        R* C = T2 + which * nff2;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = 4 * j + k4;
+          if (r < nff && r16 < nff) C[r * nff + r16] = (R)t2[j];
+        }
+      }
+    } else {
+      for (int which = wv; which < 3; which += nwv)
+        mm_tile(Ch + (which == 0 ? 0 : nff2), which == 0 ? VP : (which == 1 ? VC : Wm), T1 + which * nff2);
+      __syncthreads();
+      for (int which = wv; which < 3; which += nwv)
+        mm_tile(which == 0 ? VP : (which == 1 ? VC : Wm), T1 + which * nff2, T2 + which * nff2);
+    }
   } else {
     // 3x3 register tiles: each A and B entry is read from LDS once per tile,
     // and every output sums k in order
