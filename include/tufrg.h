@@ -332,8 +332,11 @@ tufrg_status tufrg_loop_kernel_time(tufrg_ctx* ctx, const double* T_host, int32_
  * projections (Sec. 2.5: forward transform, bond basis, gather, inverse
  * transform) and of the products (the right-hand side of Sec. 2.4), each
  * measured alone: one right-hand side at temperatures T_host fills the
- * workspace, then per stage one warm-up launch and `reps` back-to-back
- * launches between HIP events on the context's stream.  Stage i: 0 forward
+ * workspace, then per stage `reps` back-to-back launches are captured in a
+ * HIP graph on the context's own capture stream (ordered after the
+ * caller's), replayed once as warm-up and once between HIP events: the GPU's
+ * time per launch, the gap to the next launch included, without the host's
+ * launch costs.  Stage i: 0 forward
  * transform, 1 bond basis, 2 gather, 3 inverse transform, 4 products (which
  * write dX/dT into dXdT, device, caller-owned, the size of X; X and dXdT must
  * not alias).  us[i] is that stage's average per launch (the launch and its

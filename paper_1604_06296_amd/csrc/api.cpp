@@ -1287,27 +1287,43 @@ tufrg_status tufrg_kernel_times(tufrg_ctx* ctx, const double* T_host, const doub
   // one right-hand side leaves every stage's input in the workspace
   rhs_launch(ctx, L, r, X, dXdT, false, s, TSource{T_host, 0, (int)ctx->dev.size(), 0});
   HIP_TRY(ctx, hipGetLastError());
-  auto stage = [&](int i) {
-    switch (i) {
-      case 0: launch_fwd(L, r, X, mixed, s); break;
-      case 1: launch_basis(L, r, s); break;
-      case 2: launch_gather(L, r, s); break;
-      case 3: launch_inv(L, r, mixed, s); break;
-      default: launch_back(L, r, X, dXdT, 1, true, false, mixed, s); break;
-    }
-  };
+  // each stage's reps launches are captured in a HIP graph on the context's
+  // capture stream (ordered after the caller's) and replayed, so that the
+  // time is the GPU's (kernels and the gaps between them), not the host's
+  // launch rate
+  hipStream_t gs = ctx->gs;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev_gs, s));
+  HIP_TRY(ctx, hipStreamWaitEvent(gs, ctx->ev_gs, 0));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(ctx, hipEventCreate(&e0));
   hipError_t e = hipEventCreate(&e1);
   for (int i = 0; i < 5 && e == hipSuccess; ++i) {
-    stage(i);   // warm-up
-    e = hipEventRecord(e0, s);
-    for (int k = 0; k < reps && e == hipSuccess; ++k) stage(i);
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    e = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int k = 0; k < reps; ++k) {
+        switch (i) {
+          case 0: launch_fwd(L, r, X, mixed, gs); break;
+          case 1: launch_basis(L, r, gs); break;
+          case 2: launch_gather(L, r, gs); break;
+          case 3: launch_inv(L, r, mixed, gs); break;
+          default: launch_back(L, r, X, dXdT, 1, true, false, mixed, gs); break;
+        }
+      }
+      e = hipStreamEndCapture(gs, &graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, gs);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, gs);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, gs);
+    if (e == hipSuccess) e = hipEventRecord(e1, gs);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     us[i] = 1e3 * (double)ms / reps;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
   }
   if (e1) (void)hipEventDestroy(e1);
   (void)hipEventDestroy(e0);
