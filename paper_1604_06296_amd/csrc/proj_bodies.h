@@ -25,10 +25,9 @@ struct alignas(16) BasisShared {
   double xs[2 * 441];
   double ts[2 * 441];
 };
-// WIDE (the launches of small contexts): all splits of a sum in one round of
-// loads, and the change of basis in one pass; otherwise 8 splits of 4 sums
-// per round (fewer registers for the many blocks of large contexts) and the
-// change of basis as two products.
+// WIDE: all splits of a sum in one round of loads where the splits are few
+// (the launches of small contexts); otherwise 8 splits of 4 sums per round
+// (fewer registers for the many blocks of large contexts).
 template <bool ONE, bool WIDE, int NT = 256>
 __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, BasisShared& sh) {
   const int p = ONE ? 0 : item.x;
@@ -85,34 +84,7 @@ __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, Basi
     cs[nff2 + i] = d.cim[i];
   }
   __syncthreads();
-  double* yb = b.yb + d.ws_yb;
-  if constexpr (WIDE) {
-    // small contexts: one pass, each output the double sum over its shells
-    for (int bb = threadIdx.x; bb < nff2; bb += blockDim.x) {
-      const int b1 = bb / nff, b2 = bb % nff;
-      const int s1 = d.shell_of[b1], s2 = d.shell_of[b2];
-      const int m0 = d.shell_start[s1], m1 = d.shell_start[s1 + 1];
-      const int n0 = d.shell_start[s2], n1 = d.shell_start[s2 + 1];
-      double yr = 0.0, yi = 0.0;
-      for (int mp = m0; mp < m1; ++mp) {
-        const double c1r = cs[mp * nff + b1], c1i = cs[nff2 + mp * nff + b1];
-#pragma unroll 4
-        for (int np = n0; np < n1; ++np) {
-          const double c2r = cs[np * nff + b2], c2i = cs[nff2 + np * nff + b2];
-          const double wr = c1r * c2r - c1i * c2i, wi = c1r * c2i + c1i * c2r;
-          const double ar = xs[mp * nff + np], ai = xs[nff2 + mp * nff + np];
-          yr = fma(wr, ar, fma(-wi, ai, yr));
-          yi = fma(wr, ai, fma(wi, ar, yi));
-        }
-      }
-      const size_t idx = ((size_t)in * nv + v) * nff2 + bb;
-      yb[idx] = yr;
-      yb[(size_t)total + idx] = yi;
-    }
-    return;
-  }
-  // large contexts: the change of basis as two products through shared
-  // memory (fewer terms; the 8-bond shell makes the double sum 4x longer):
+  // the change of basis as two products through shared memory:
   // ts[m'][b2] = sum_{n' in shell(b2)} c_{n'b2} xt_{m'n'}, then
   // yb[b1 b2] = sum_{m' in shell(b1)} c_{m'b1} ts[m'][b2]
   double* ts = sh.ts;
@@ -131,6 +103,7 @@ __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, Basi
     ts[nff2 + i] = ti;
   }
   __syncthreads();
+  double* yb = b.yb + d.ws_yb;
   for (int bb = threadIdx.x; bb < nff2; bb += blockDim.x) {
     const int b1 = bb / nff, b2 = bb % nff;
     const int s1 = d.shell_of[b1];
