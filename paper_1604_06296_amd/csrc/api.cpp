@@ -620,6 +620,23 @@ void rhs_launch(tufrg_ctx* ctx, const Launch& L0, const Ranges& r0, const double
   launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms, sn);
 }
 
+// The flows' per-point stop words in pinned, mapped host memory: the step
+// kernels write them, so that the host can follow a flow without
+// synchronising the stream (allocated on the first flow, kept until
+// tufrg_free).
+tufrg_status ensure_status_words(tufrg_ctx* ctx) {
+  if (ctx->flow_status_host) return TUFRG_OK;
+  void* hp = nullptr;
+  void* dp = nullptr;
+  if (hipHostMalloc(&hp, sizeof(int) * ctx->dev.size(), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+    return fail(ctx, TUFRG_ENOMEM, "pinned host allocation failed");
+  ctx->flow_status_host = static_cast<int*>(hp);
+  if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess)
+    return fail(ctx, TUFRG_EHIP, "no device address for the mapped status words");
+  ctx->flow_status_dev = static_cast<int*>(dp);
+  return TUFRG_OK;
+}
+
 tufrg_status ensure_flow_buffers(tufrg_ctx* ctx) {
   if (ctx->flow_ready) return TUFRG_OK;
   const size_t s3 = 3 * (size_t)ctx->S;
@@ -1506,7 +1523,7 @@ void rk4_step(tufrg_ctx* ctx, const Launch& L, double* X, double h, double xmax,
     rhs_launch(ctx, L, r, ctx->stage, k[3], true, ms, stage_T(3));
     launch_axpy(L, r.seg, X, k, fin, 4, h, X, true, ms);
     launch_maxabs(L, r.seg, X, ctx->umax, ms);
-    launch_step_end(ctx->umax, npts, ctx->frozen, ctx->hist, ctx->step, nsteps, xmax, ms);
+    launch_step_end(ctx->umax, npts, ctx->frozen, ctx->hist, ctx->step, nsteps, xmax, ms, ctx->flow_status_dev);
     return;
   }
   // small (launch-bound) contexts: each stage combination is formed by the
@@ -1532,7 +1549,7 @@ void rk4_step(tufrg_ctx* ctx, const Launch& L, double* X, double h, double xmax,
   rhs_launch(ctx, L, r, st[1], k[2], true, ms, stage_T(2), &n3);
   rhs_launch(ctx, L, r, st[0], k[3], true, ms, stage_T(3), &n4);
   launch_maxabs(L, r.seg, X, ctx->umax, ms);
-  launch_step_end(ctx->umax, npts, ctx->frozen, ctx->hist, ctx->step, nsteps, xmax, ms);
+  launch_step_end(ctx->umax, npts, ctx->frozen, ctx->hist, ctx->step, nsteps, xmax, ms, ctx->flow_status_dev);
 }
 
 tufrg_status flow_rk4_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tufrg_flow_result* res) {
@@ -1568,6 +1585,8 @@ tufrg_status flow_rk4_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, t
   launch_fill_i32(ctx->frozen, npts, 0, ms);
   launch_fill_i32(ctx->step, 1, 0, ms);
   launch_fill_u64(ctx->umax, npts, 0ull, ms);
+  ST_TRY(ensure_status_words(ctx));
+  for (int p = 0; p < npts; ++p) ctx->flow_status_host[p] = 0;
   Launch Lf = ctx->L;
   Lf.b.frozen = ctx->frozen;
   launch_maxabs(Lf, ctx->all.seg, X, ctx->umax, ms);
@@ -1593,32 +1612,42 @@ tufrg_status flow_rk4_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, t
       return fail(ctx, TUFRG_EHIP, std::string("graph capture of the RK4 step: ") + hipGetErrorString(e));
     }
   }
-  // steps in batches; the host checks the stop flags between batches
-  std::vector<int> frozen(npts, 0);
+  // steps are issued one ahead of the host's view (as the adaptive flow's
+  // attempts): after issuing step n the host waits for step n - 1 and reads
+  // the points' stop words, which the step-end kernel writes into mapped host
+  // memory; once every point has stopped, the one step issued after that
+  // runs as a no-op
   int done = 0;
-  const int batch = 8;
-  while (done < nsteps) {
-    const int nb = std::min(batch, nsteps - done);
-    for (int i = 0; i < nb; ++i) {
-      if (exec) {
-        hipError_t e = hipGraphLaunch(exec, ms);
-        if (e != hipSuccess) {
-          cleanup();
-          return fail(ctx, TUFRG_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
-        }
-      } else {
-        rk4_step(ctx, Lf, X, h, o->Xmax, nsteps, ms);
-      }
+  auto issue = [&]() -> hipError_t {
+    if (exec) {
+      const hipError_t e = hipGraphLaunch(exec, ms);
+      if (e != hipSuccess) return e;
+    } else {
+      rk4_step(ctx, Lf, X, h, o->Xmax, nsteps, ms);
     }
-    done += nb;
-    hipError_t e = hipMemcpyAsync(frozen.data(), ctx->frozen, sizeof(int) * npts, hipMemcpyDeviceToHost, ms);
-    if (e == hipSuccess) e = hipStreamSynchronize(ms);
+    return hipEventRecord(ctx->ev_att[done++ & 1], ms);
+  };
+  hipError_t e = issue();
+  while (e == hipSuccess) {
+    const bool more = done < nsteps;
+    if (more) e = issue();
+    if (e != hipSuccess) break;
+    e = hipEventSynchronize(ctx->ev_att[(done - (more ? 2 : 1)) & 1]);
     if (e == hipSuccess) e = hipGetLastError();
-    if (e != hipSuccess) {
-      cleanup();
-      return fail(ctx, TUFRG_EHIP, std::string("RK4 flow: ") + hipGetErrorString(e));
-    }
-    if (std::all_of(frozen.begin(), frozen.end(), [](int f) { return f != 0; })) break;
+    if (e != hipSuccess) break;
+    bool all_done = true;
+    const volatile int* hs = ctx->flow_status_host;
+    for (int p = 0; p < npts && all_done; ++p) all_done = hs[p] != 0;
+    if (all_done || !more) break;
+  }
+  std::vector<int> frozen(npts, 0);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(frozen.data(), ctx->frozen, sizeof(int) * npts, hipMemcpyDeviceToHost, ms);
+  if (e == hipSuccess) e = hipStreamSynchronize(ms);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(ctx, TUFRG_EHIP, std::string("RK4 flow: ") + hipGetErrorString(e));
   }
   cleanup();
   std::vector<double> hist((size_t)(done + 1) * npts);
@@ -1686,16 +1715,7 @@ tufrg_status flow_dopri5_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X
     ST_TRY(upload(ctx, seg, &ctx->dp_seg, ctx->allocations));
     ST_TRY(upload(ctx, nel, &ctx->dp_nel, ctx->allocations));
   }
-  if (!ctx->dp_status_host) {
-    void* hp = nullptr;
-    void* dp = nullptr;
-    if (hipHostMalloc(&hp, sizeof(int) * npts, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
-      return fail(ctx, TUFRG_ENOMEM, "pinned host allocation failed");
-    ctx->dp_status_host = static_cast<int*>(hp);
-    if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess)
-      return fail(ctx, TUFRG_EHIP, "no device address for the mapped status words");
-    ctx->dp_status_dev = static_cast<int*>(dp);
-  }
+  ST_TRY(ensure_status_words(ctx));
   const double s0 = std::log(o->T0), s_end = std::log(o->Tmin);
   const double h0 = (o->h0 != 0.0) ? o->h0 : (s_end - s0) / 200.0;
   const int max_steps = o->max_steps > 0 ? o->max_steps : 100000;
@@ -1761,8 +1781,8 @@ tufrg_status flow_dopri5_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X
   dc.xmax = o->Xmax;
   dc.max_steps = max_steps;
   dc.npts = npts;
-  dc.status_out = ctx->dp_status_dev;
-  for (int p = 0; p < npts; ++p) ctx->dp_status_host[p] = 0;
+  dc.status_out = ctx->flow_status_dev;
+  for (int p = 0; p < npts; ++p) ctx->flow_status_host[p] = 0;
   auto attempt = [&]() {
     for (int i = 1; i < 7; ++i) {
       if (i > 1 && !fuse_stages) launch_axpy(Lf, r.seg, X, k, kDpA[i], i, 0.0, stg[i & 1], true, ms, h_arr);
@@ -1825,7 +1845,7 @@ tufrg_status flow_dopri5_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X
     if (ge == hipSuccess) ge = hipGetLastError();
     if (ge != hipSuccess) break;
     bool all_done = true;
-    const volatile int* hs = ctx->dp_status_host;
+    const volatile int* hs = ctx->flow_status_host;
     for (int p = 0; p < npts && all_done; ++p) all_done = hs[p] != 0;
     if (all_done || !more) break;
   }
@@ -1899,7 +1919,7 @@ void tufrg_free(tufrg_ctx* ctx) {
   for (hipEvent_t e : ctx->ev_att)
     if (e) (void)hipEventDestroy(e);
   if (ctx->umax_host) (void)hipHostFree(ctx->umax_host);
-  if (ctx->dp_status_host) (void)hipHostFree(ctx->dp_status_host);
+  if (ctx->flow_status_host) (void)hipHostFree(ctx->flow_status_host);
   if (ctx->red_host) (void)hipHostFree(ctx->red_host);
   for (void* p : ctx->sur_allocations) (void)hipFree(p);
   for (void* p : ctx->geometry_allocations) (void)hipFree(p);

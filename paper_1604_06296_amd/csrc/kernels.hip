@@ -1112,17 +1112,23 @@ __global__ void k_set_Tv(double* Tp, int n, TValues tv) {
 
 // End of an RK4 step: record max|X| per point, stop points whose state passed
 // Xmax or became non-finite (frozen = step index of the stop), clear the max
-// words and advance the step counter.
+// words and advance the step counter; status_out (mapped host memory, may be
+// null) receives every point's frozen word.
 __global__ void k_step_end(unsigned long long* words, int npts, int* frozen, double* hist,
-                           int* step, int nsteps, double xmax) {
+                           int* step, int nsteps, double xmax, int* status_out) {
   const int i = threadIdx.x;
   const int s = step[0];
   for (int p = i; p < npts; p += blockDim.x) {
     const double m = __longlong_as_double((long long)words[p]);
-    if (!frozen[p]) {
+    int f = frozen[p];
+    if (!f) {
       hist[(size_t)(s + 1) * npts + p] = m;
-      if (!(m <= xmax)) frozen[p] = s + 1;
+      if (!(m <= xmax)) {
+        f = s + 1;
+        frozen[p] = f;
+      }
     }
+    if (status_out != nullptr) status_out[p] = f;
     words[p] = 0ull;
   }
   __syncthreads();
@@ -1385,9 +1391,9 @@ void launch_set_T_values(double* Tp, const double* T_host, int n, hipStream_t s)
 }
 
 void launch_step_end(unsigned long long* words, int npts, int* frozen, double* hist, int* step,
-                     int nsteps, double xmax, hipStream_t s) {
+                     int nsteps, double xmax, hipStream_t s, int* status_out) {
   hipLaunchKernelGGL(k_step_end, dim3(1), dim3(256), 0, s, words, npts, frozen, hist, step, nsteps,
-                     xmax);
+                     xmax, status_out);
 }
 
 }  // namespace tufrg

@@ -346,7 +346,7 @@ void launch_set_T(double* Tp, int npts, const double* Ttab, const int* step, int
                   hipStream_t s);
 void launch_set_T_values(double* Tp, const double* T_host, int n, hipStream_t s);
 void launch_step_end(unsigned long long* words, int npts, int* frozen, double* hist, int* step,
-                     int nsteps, double xmax, hipStream_t s);
+                     int nsteps, double xmax, hipStream_t s, int* status_out = nullptr);
 const void* loop_kernel_symbol(int smax_max, bool mixed, bool omega, bool unroll);
 void launch_ghat_sum(const Launch& L, int p, const DevTables& d, double* out, hipStream_t s);
 void launch_sur_dataset(const Launch& L, int npts, int64_t n, uint64_t seed, float* x, float* y,
@@ -391,8 +391,8 @@ struct tufrg_ctx {
   int nred = 0;
   unsigned long long* umax = nullptr;      // per-point max words
   unsigned long long* umax_host = nullptr; // pinned
-  int* dp_status_host = nullptr;           // pinned, mapped: per-point status of the adaptive flow
-  int* dp_status_dev = nullptr;            // its device address
+  int* flow_status_host = nullptr;         // pinned, mapped: per-point stop words of a flow
+  int* flow_status_dev = nullptr;          // its device address
   double* Ttab = nullptr;                  // RK4 stage temperatures [nsteps][4]
   double* hist = nullptr;                  // max|X| history [nsteps+1][npts]
   int* step = nullptr;                     // device step counter
