@@ -213,6 +213,8 @@ typedef struct {
   int32_t status;
   int32_t channel, q_index, irrep;
   double Tc, max_abs_X;
+  double max_abs_V;   /* max |V| of the point's projected couplings (eqns.
+                         proj_VP/VC/VD, as tufrg_project) at the end state */
   int64_t n_rhs, n_steps;
 } tufrg_flow_result;
 

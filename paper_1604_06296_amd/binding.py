@@ -66,7 +66,7 @@ class _FlowOpts(C.Structure):
 class _FlowResult(C.Structure):
     _fields_ = [("status", C.c_int32), ("channel", C.c_int32), ("q_index", C.c_int32),
                 ("irrep", C.c_int32), ("Tc", C.c_double), ("max_abs_X", C.c_double),
-                ("n_rhs", C.c_int64), ("n_steps", C.c_int64)]
+                ("max_abs_V", C.c_double), ("n_rhs", C.c_int64), ("n_steps", C.c_int64)]
 
 
 _LIB = None
@@ -264,6 +264,7 @@ class FlowResult:
     max_abs_X: float
     n_rhs: int
     n_steps: int
+    max_abs_V: float = float("nan")
 
 
 class Context:
@@ -426,7 +427,8 @@ class Context:
             div = r.status == 1
             out.append(FlowResult(FLOW_STATUS.get(r.status, str(r.status)), r.Tc if div else None,
                                   CHANNELS[r.channel] if div else None, r.q_index if div else None,
-                                  IRREPS[r.irrep] if div else None, r.max_abs_X, r.n_rhs, r.n_steps))
+                                  IRREPS[r.irrep] if div else None, r.max_abs_X, r.n_rhs, r.n_steps,
+                                  max_abs_V=r.max_abs_V))
         return out
 
     # ------------------------------------------------------------- surrogate

@@ -620,6 +620,30 @@ void rhs_launch(tufrg_ctx* ctx, const Launch& L0, const Ranges& r0, const double
   launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms, sn);
 }
 
+// V of every point (eqns. proj_VP/VC/VD) on the context's stream.
+void project_launch(tufrg_ctx* ctx, const double* X, double* V) {
+  const bool mixed = mixed_of(ctx), cross = cross_of(ctx);
+  if (cross && ctx->L.dense) launch_dense(ctx->L, ctx->all, X, ctx->stream);
+  else if (cross) launch_front(ctx->L, ctx->all, X, mixed, ctx->stream);
+  launch_back(ctx->L, ctx->all, X, V, 0, cross, false, mixed, ctx->stream);
+}
+
+// max |V| of every point's projected couplings at the state X (V in the
+// flow's stage buffer) into res[p].max_abs_V.  Synchronises the stream.
+tufrg_status flow_max_abs_V(tufrg_ctx* ctx, const double* X, tufrg_flow_result* res) {
+  const int npts = (int)ctx->dev.size();
+  project_launch(ctx, X, ctx->stage);
+  launch_fill_u64(ctx->umax, npts, 0ull, ctx->stream);
+  launch_maxabs(ctx->L, ctx->all.seg, ctx->stage, ctx->umax, ctx->stream);
+  std::vector<unsigned long long> w(npts);
+  HIP_TRY(ctx, hipMemcpyAsync(w.data(), ctx->umax, sizeof(unsigned long long) * npts, hipMemcpyDeviceToHost,
+                              ctx->stream));
+  launch_fill_u64(ctx->umax, npts, 0ull, ctx->stream);
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (int p = 0; p < npts; ++p) res[p].max_abs_V = word_to_double(w[p]);
+  return TUFRG_OK;
+}
+
 // The flows' per-point stop words in pinned, mapped host memory: the step
 // kernels write them, so that the host can follow a flow without
 // synchronising the stream (allocated on the first flow, kept until
@@ -1095,10 +1119,7 @@ tufrg_status tufrg_project(tufrg_ctx* ctx, const double* X, double* V) {
   if (!ctx) return fail(nullptr, TUFRG_EINVAL, "ctx is NULL");
   if (!X || !V) return fail(ctx, TUFRG_EINVAL, "NULL argument");
   if (X == V) return fail(ctx, TUFRG_EINVAL, "X and V must not alias");
-  const bool mixed = mixed_of(ctx), cross = cross_of(ctx);
-  if (cross && ctx->L.dense) launch_dense(ctx->L, ctx->all, X, ctx->stream);
-  else if (cross) launch_front(ctx->L, ctx->all, X, mixed, ctx->stream);
-  launch_back(ctx->L, ctx->all, X, V, 0, cross, false, mixed, ctx->stream);
+  project_launch(ctx, X, V);
   HIP_TRY(ctx, hipGetLastError());
   return TUFRG_OK;
 }
@@ -1900,7 +1921,7 @@ tufrg_status tufrg_flow(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, tuf
   } else {
     return fail(ctx, TUFRG_EINVAL, "unknown scheme");
   }
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  ST_TRY(flow_max_abs_V(ctx, X, res));
   for (size_t p = 0; p < ctx->dev.size(); ++p)
     if (res[p].status == TUFRG_FLOW_NONFINITE)
       return fail(ctx, TUFRG_ENONFINITE, "flow state of point " + std::to_string(p) + " became non-finite");

@@ -239,6 +239,25 @@ def test_flow_dopri5_small(tf):
     assert (r.channel, r.q_index, r.irrep) == (ref.channel, ref.q_index, ref.irrep)
 
 
+@pytest.mark.parametrize("scheme", ["rk4", "dopri5"])
+def test_flow_result_max_abs_V(tf, scheme):
+    """The flow result's max|V| is that of the end state's projected couplings:
+    against the oracle's projection of the same state (1e-10) and against the
+    library's own tufrg_project (bit for bit)."""
+    pt = _pt(2, 8, 16, tp=-0.2, mu=-0.5, U=1.5)
+    ff = FormFactors(pt.shells)
+    ctx = tf.Context([pt])
+    X = ctx.empty(3).zero_()
+    opts = tf.FlowOptions(T0=10.0, Tmin=0.3, Xmax=1e9, scheme=scheme, nsteps=60, rtol=1e-8, atol=1e-10)
+    r = ctx.flow(X, opts)[0]
+    Xh = _host(ctx, X)
+    Vref = oproj.project(pt, Xh, ff)
+    mref = float(np.abs(Vref).max())
+    assert r.max_abs_V > 0.0
+    assert abs(r.max_abs_V - mref) <= 1e-10 * mref
+    assert r.max_abs_V == float(ctx.project(X).abs().max())
+
+
 @pytest.mark.parametrize("Tmin", [0.6, 0.45, 0.33])
 def test_flow_dopri5_state_matches_oracle(tf, Tmin):
     """Adaptive flow that reaches Tmin: the same accepted steps as the oracle and
