@@ -135,8 +135,9 @@ __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, Basi
 // imaginary parts, a negative imaginary offset for a negated entry, a
 // negative real offset for padding), so that the yb loads wait for two loads
 // only; the entries of a row are added in the order of the entry lists.
-// The wave's work is two phases with a barrier between them (the caller's:
-// a block of one wave, or of several waves running one item each).
+// The wave's work is two phases with a barrier of the caller's block between
+// them (a block of one wave, or of several waves running one item each, all
+// of which call both phases); the second phase has a block barrier of its own.
 struct GatherShared {
   double Mre[2][kShellMax * kShellMax];
   double Mim[2][kShellMax * kShellMax];
