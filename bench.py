@@ -545,8 +545,9 @@ def main():
             probe_projections(args.probe_projections)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the right-hand side would shard over transfer momenta; see DESIGN.md)",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the right-hand side would shard over transfer momenta, with one all-reduce of the "
+              "forward transform's partial sums per right-hand side)",
               file=sys.stderr)
         sys.exit(2)
     import synth
