@@ -158,6 +158,13 @@ enum {
                                per-momentum contexts (EUNSUPPORTED with
                                TUFRG_MIXED or TUFRG_SYMMETRIC_STATE).  Results equal
                                the factored path's up to summation order. */
+  TUFRG_NO_LOOP_REUSE = 1u << 8, /* flows: evaluate the loops at every stage.  By
+                               default a stage at the temperature of the stage
+                               just before it (RK4's second and third,
+                               Dormand-Prince's sixth and seventh) takes that
+                               stage's loops, still in the workspace, instead of
+                               evaluating them again (the loops depend on T
+                               alone).  Bit-identical results. */
   TUFRG_NO_FUSE = 1u << 4  /* never run the right-hand side in fused launches.  By
                                default a context whose channel state (sum of
                                Nq Nff^2 over its points) is at most 2^18 runs the
@@ -173,7 +180,8 @@ typedef struct {
   int32_t precision;       /* TUFRG_FP64 or TUFRG_MIXED */
   uint32_t flags;          /* TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE |
                               TUFRG_NO_SYMMETRY | TUFRG_NO_FUSE | TUFRG_OMEGA_CUTOFF |
-                              TUFRG_SYMMETRIC_STATE | TUFRG_DENSE_PROJECTION */
+                              TUFRG_SYMMETRIC_STATE | TUFRG_DENSE_PROJECTION |
+                              TUFRG_NO_LOOP_REUSE */
 } tufrg_options;
 
 enum { TUFRG_RK4_LOG = 0, TUFRG_DOPRI5_LOG = 1 };

@@ -22,6 +22,7 @@ NO_FUSE = 16
 OMEGA_CUTOFF = 32
 SYMMETRIC_STATE = 64
 DENSE_PROJECTION = 128
+NO_LOOP_REUSE = 256
 REGULATORS = {"T": 0, "omega": OMEGA_CUTOFF}
 
 # every entry point declared in include/tufrg.h
@@ -284,7 +285,7 @@ class Context:
     def __init__(self, points: Sequence, precision: str = "fp64", no_cross: bool = False,
                  stream=None, autotune: bool = False, loop_queue: bool = False,
                  no_symmetry: bool = False, fuse: bool = True, regulator: str = "T",
-                 symmetric_state: bool = False, dense_projection: bool = False):
+                 symmetric_state: bool = False, dense_projection: bool = False, loop_reuse: bool = True):
         import torch
         if not torch.cuda.is_available():
             raise TufrgError("a GPU is required (torch.cuda.is_available() is False)")
@@ -301,7 +302,8 @@ class Context:
                        | (LOOP_QUEUE if loop_queue else 0) | (NO_SYMMETRY if no_symmetry else 0)
                        | (0 if fuse else NO_FUSE) | REGULATORS[regulator]
                        | (SYMMETRIC_STATE if symmetric_state else 0)
-                       | (DENSE_PROJECTION if dense_projection else 0))
+                       | (DENSE_PROJECTION if dense_projection else 0)
+                       | (0 if loop_reuse else NO_LOOP_REUSE))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = C.c_void_p()
         meshes = [getattr(p, "mesh", None) for p in points]

@@ -564,8 +564,15 @@ void set_T_launch(tufrg_ctx* ctx, const TSource& ts, hipStream_t s) {
 // costs to dominate (Launch::fused).  Otherwise, and with the surrogate, the
 // loops run on the side stream (fork and join by events) alongside the
 // whole projection chain.
+// same_T: the right-hand side issued just before this one on the context
+// took the same temperatures (two stages of one step at the same s: RK4's
+// second and third, Dormand-Prince's sixth and seventh), so its loop
+// expansion, still in dchi, is used again and the loop and expansion work is
+// not issued (the loops read only T; the bits are those of a fresh
+// evaluation).  Not with the surrogate, whose checks count its calls.
 void rhs_launch(tufrg_ctx* ctx, const Launch& L0, const Ranges& r0, const double* X, double* out,
-                bool scale_T, hipStream_t ms, const TSource& ts, const StageNext* sn = nullptr) {
+                bool scale_T, hipStream_t ms, const TSource& ts, const StageNext* sn = nullptr,
+                bool same_T = false) {
   const bool mixed = mixed_of(ctx), cross = cross_of(ctx);
   // symmetric states: the loop expansion at the representatives only
   Launch L = L0;
@@ -573,6 +580,11 @@ void rhs_launch(tufrg_ctx* ctx, const Launch& L0, const Ranges& r0, const double
   if (L0.b.wedge && L0.expw_items) {
     L.exp_items = L0.expw_items;
     r.exp = r0.exp_w;
+  }
+  const bool reuse = same_T && !ctx->sur_a && !(ctx->opt.flags & TUFRG_NO_LOOP_REUSE);
+  if (reuse) {
+    r.loop.n = 0;
+    r.exp.n = 0;
   }
   if (!ctx->sur_a && L.fused) {
     // the fused launch takes the temperatures itself (and stores them for the
@@ -605,6 +617,12 @@ void rhs_launch(tufrg_ctx* ctx, const Launch& L0, const Ranges& r0, const double
     launch_expand_basis(L, r, L.b.dchi, factored, ms);
     if (factored) launch_gather_inv(L, r, mixed, ms);
     else if (cross) launch_dense(L, r, X, ms);
+    launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms, sn);
+    return;
+  }
+  if (reuse) {
+    if (cross && L.dense) launch_dense(L, r, X, ms);
+    else if (cross) launch_front(L, r, X, mixed, ms);
     launch_back(L, r, X, out, 1, cross, scale_T, mixed, ms, sn);
     return;
   }
@@ -875,7 +893,8 @@ tufrg_status tufrg_init_mesh(const tufrg_point* pts, const tufrg_mesh* meshes, i
   if (o.precision != TUFRG_FP64 && o.precision != TUFRG_MIXED)
     return fail(nullptr, TUFRG_EINVAL, "precision must be TUFRG_FP64 or TUFRG_MIXED");
   if (o.flags & ~(uint32_t)(TUFRG_NO_CROSS | TUFRG_AUTOTUNE | TUFRG_LOOP_QUEUE | TUFRG_NO_SYMMETRY |
-                            TUFRG_NO_FUSE | TUFRG_OMEGA_CUTOFF | TUFRG_SYMMETRIC_STATE | TUFRG_DENSE_PROJECTION))
+                            TUFRG_NO_FUSE | TUFRG_OMEGA_CUTOFF | TUFRG_SYMMETRIC_STATE | TUFRG_DENSE_PROJECTION |
+                            TUFRG_NO_LOOP_REUSE))
     return fail(nullptr, TUFRG_EINVAL, "unknown flag bits");
   if ((o.flags & TUFRG_DENSE_PROJECTION) && (o.precision != TUFRG_FP64 || (o.flags & TUFRG_SYMMETRIC_STATE)))
     return fail(nullptr, TUFRG_EUNSUPPORTED, "the dense projection operator serves FP64 per-momentum contexts");
@@ -1539,7 +1558,7 @@ void rk4_step(tufrg_ctx* ctx, const Launch& L, double* X, double h, double xmax,
     launch_axpy(L, r.seg, X, &k[0], half, 1, h, ctx->stage, true, ms);
     rhs_launch(ctx, L, r, ctx->stage, k[1], true, ms, stage_T(1));
     launch_axpy(L, r.seg, X, &k[1], half, 1, h, ctx->stage, true, ms);
-    rhs_launch(ctx, L, r, ctx->stage, k[2], true, ms, stage_T(2));
+    rhs_launch(ctx, L, r, ctx->stage, k[2], true, ms, stage_T(2), nullptr, true);
     launch_axpy(L, r.seg, X, &k[2], one, 1, h, ctx->stage, true, ms);
     rhs_launch(ctx, L, r, ctx->stage, k[3], true, ms, stage_T(3));
     launch_axpy(L, r.seg, X, k, fin, 4, h, X, true, ms);
@@ -1567,7 +1586,7 @@ void rk4_step(tufrg_ctx* ctx, const Launch& L, double* X, double h, double xmax,
   const StageNext n3 = next(st[0], one, 1, &k[2]), n4 = next(X, fin, 4, k);
   rhs_launch(ctx, L, r, X, k[0], true, ms, stage_T(0), &n1);
   rhs_launch(ctx, L, r, st[0], k[1], true, ms, stage_T(1), &n2);
-  rhs_launch(ctx, L, r, st[1], k[2], true, ms, stage_T(2), &n3);
+  rhs_launch(ctx, L, r, st[1], k[2], true, ms, stage_T(2), &n3, true);
   rhs_launch(ctx, L, r, st[0], k[3], true, ms, stage_T(3), &n4);
   launch_maxabs(L, r.seg, X, ctx->umax, ms);
   launch_step_end(ctx->umax, npts, ctx->frozen, ctx->hist, ctx->step, nsteps, xmax, ms, ctx->flow_status_dev);
@@ -1818,7 +1837,8 @@ tufrg_status flow_dopri5_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X
         sn.hp = h_arr;
         sn.nk = i + 1;
       }
-      rhs_launch(ctx, Lf, r, stg[i & 1], k[i], true, ms, stage_T(kDpC[i]), sn.nk > 0 ? &sn : nullptr);
+      rhs_launch(ctx, Lf, r, stg[i & 1], k[i], true, ms, stage_T(kDpC[i]), sn.nk > 0 ? &sn : nullptr,
+                 kDpC[i] == kDpC[i - 1]);
     }
     launch_dp_final(Lf, r.seg, X, k, kDpB5, e, 0.0, o->rtol, o->atol, y5, ctx->red, ctx->umax, ms, h_arr);
     launch_dp_control(dc, ms);

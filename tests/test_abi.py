@@ -92,12 +92,12 @@ def test_flag_values_match_header(lib):
     hdr = open(os.path.join(ROOT, "include", "tufrg.h")).read()
     bits = {m.group(1): 1 << int(m.group(2)) for m in re.finditer(r"TUFRG_([A-Z_]+)\s*=\s*1u\s*<<\s*(\d+)", hdr)}
     for name in ("NO_CROSS", "AUTOTUNE", "NO_SYMMETRY", "LOOP_QUEUE", "NO_FUSE", "OMEGA_CUTOFF",
-                 "SYMMETRIC_STATE", "DENSE_PROJECTION"):
+                 "SYMMETRIC_STATE", "DENSE_PROJECTION", "NO_LOOP_REUSE"):
         assert getattr(b, name) == bits[name], name
     assert b.REGULATORS == {"T": 0, "omega": bits["OMEGA_CUTOFF"]}
     arr = (_Point * 1)(_Point(1.0, -0.2, -0.3, 3.0, 10, 16, 1, 0))
     h = C.c_void_p()
-    assert lib.tufrg_init(arr, 1, C.byref(_Options(0, 1 << 8)), None, C.byref(h)) == -1
+    assert lib.tufrg_init(arr, 1, C.byref(_Options(0, 1 << 9)), None, C.byref(h)) == -1
     assert "flag" in lib.tufrg_last_error(None).decode()
 
 
