@@ -176,7 +176,7 @@ void mark(std::vector<int4>& v, ItemRange& rg, F fill) {
 int inv_rows_of(const DevTables& d, bool wedge) { return wedge ? d.nirr : d.nq; }
 
 void add_point_items(const DevTables& d, const HostTables& t, int p, int inv_lt, int fwd_cols, bool wedge,
-                     int gcap, HostItems& h, Ranges& r) {
+                     int gcap, bool split_basis, HostItems& h, Ranges& r) {
   const int nff2 = d.nff * d.nff, nv = 2 * d.nsh - 1;
   const int nrow = inv_rows_of(d, wedge);
   mark(h.exp, r.exp, [&](std::vector<int4>& v) {
@@ -198,8 +198,22 @@ void add_point_items(const DevTables& d, const HostTables& t, int p, int inv_lt,
     for (int lt = 0; lt < (nrow + 16 * inv_lt - 1) / (16 * inv_lt); ++lt)
       for (int c = 0; c < (3 * nff2 + 63) / 64; ++c) v.push_back(make_int4(p, lt, c, 0));
   });
+  // bond-basis items (p, harmonic, r0, r1): with split_basis (the fused
+  // launches of small contexts, whose basis blocks are fewer than the CUs) the
+  // rows in two groups of whole shells, cut at the shell boundary closest to
+  // the middle (three shells or more), so that the launch has twice the
+  // blocks; otherwise all rows in one item (measured: the split made the
+  // two-stream right-hand side at 48x48, N_ff = 21 slower in the mixed form)
   mark(h.basis, r.basis, [&](std::vector<int4>& v) {
-    for (int b = 0; b < 3 * nv; ++b) v.push_back(make_int4(p, b, 0, 0));
+    int cut = d.nff;
+    if (split_basis && d.nshell >= 3) {
+      for (int s = 1; s < d.nshell; ++s)
+        if (std::abs(2 * t.shell_start[s] - d.nff) < std::abs(2 * cut - d.nff)) cut = t.shell_start[s];
+    }
+    for (int b = 0; b < 3 * nv; ++b) {
+      v.push_back(make_int4(p, b, 0, cut));
+      if (cut < d.nff) v.push_back(make_int4(p, b, cut, d.nff));
+    }
   });
   // gather items (p, packed block, -, first entry): the block's harmonic j,
   // output channel X and shell pair (start and size of each) packed into y,
@@ -329,7 +343,7 @@ tufrg_status build_launch(tufrg_ctx* ctx) {
   std::stable_sort(by_nff.begin(), by_nff.end(), [&](int x, int y) { return ctx->dev[x].nff > ctx->dev[y].nff; });
   for (int p : by_nff) {
     Ranges& rp = ctx->per_point[p];
-    add_point_items(ctx->dev[p], ctx->host[p], p, inv_lt, fwd_cols, wedge, gcap, h, rp);
+    add_point_items(ctx->dev[p], ctx->host[p], p, inv_lt, fwd_cols, wedge, gcap, fused, h, rp);
     rp.nprod_cls = 1;
     rp.prod_cls[0] = rp.prod;
     rp.prod_cls_nff[0] = ctx->dev[p].nff;

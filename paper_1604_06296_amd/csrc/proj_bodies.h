@@ -17,9 +17,11 @@ namespace {
 //   yb[in][v][b1 b2] = sum_{m' in shell(b1), n' in shell(b2)} c_{m'b1} c_{n'b2} xt^{in}_{m'n'}(v)
 // with xt(-S') = conj(xt(S')).  These are the bond-space Fourier coefficients
 // Yhat_{R1R2}(W) of the propagators at frequency 2W - R1 - R2 = v.
-// Item (p, in * nv + v): the harmonic's transform and the coefficients are
-// staged in LDS; threads own bond pairs (b1, b2).  The transform is the
-// in-order FP64 sum of the forward-transform splits (xp), taken here.
+// Item (p, in * nv + v, r0, r1): the rows m' in [r0, r1) (whole shells) of the
+// harmonic's transform and the coefficients are staged in LDS; threads own
+// bond pairs (b1, b2) with b1 in [r0, r1), which need only those rows since
+// c is block diagonal over shells.  The transform is the in-order FP64 sum
+// of the forward-transform splits (xp), taken here.
 struct alignas(16) BasisShared {
   double cs[2 * 441];
   double xs[2 * 441];
@@ -36,15 +38,17 @@ __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, Basi
   const int nff = d.nff, nff2 = nff * nff, nsh = d.nsh, ncol = d.ncol, nv = 2 * nsh - 1;
   const int total = 3 * nv * nff2;
   const int in = item.y / nv, v = item.y % nv;
+  const int r0 = item.z, r1 = item.w;   // rows m' (and b1) of the item
   const int j = v < nsh ? v : v - nsh + 1;
   const double sim = v < nsh ? 1.0 : -1.0;
   double* cs = sh.cs;
   double* xs = sh.xs;
   {
-    // 2 nff^2 sums of nsu terms; each of the NT threads keeps up to kSums sums
-    // and kSplits splits of each in flight, then adds them in split order
+    // 2 (r1 - r0) nff sums of nsu terms (real and imaginary parts of the
+    // item's rows); each of the NT threads keeps up to kSums sums and kSplits
+    // splits of each in flight, then adds them in split order
     constexpr int kSums = WIDE ? 2 : 4, kSplits = WIDE ? 16 : 8;
-    const int N = 3 * nff2, nel = 2 * nff2;
+    const int N = 3 * nff2, nrow = (r1 - r0) * nff, nel = 2 * nrow, e_lo = r0 * nff;
     const size_t sstride = (size_t)ncol * N;
     const double* base = b.xp + d.ws_xp + (size_t)in * nff2;
     const double inv = 1.0 / (double)d.nq;
@@ -52,12 +56,15 @@ __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, Basi
       const double* src[kSums];
       bool ok[kSums];
       double acc[kSums];
+      int dst[kSums];   // element of xs: [re | im][m' n']
 #pragma unroll
       for (int s4 = 0; s4 < kSums; ++s4) {
         const int e = e0 + NT * s4;
-        const bool im = e >= nff2;
+        const bool im = e >= nrow;
+        const int g = e_lo + (im ? e - nrow : e);
         ok[s4] = e < nel && (!im || j > 0);
-        src[s4] = base + (size_t)(im ? nsh - 1 + j : j) * N + (im ? e - nff2 : e);
+        src[s4] = base + (size_t)(im ? nsh - 1 + j : j) * N + g;
+        dst[s4] = e < nel ? (im ? nff2 + g : g) : -1;
         acc[s4] = 0.0;
       }
       for (int sp0 = 0; sp0 < d.nsu; sp0 += kSplits) {
@@ -73,10 +80,8 @@ __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, Basi
           for (int u = 0; u < kSplits; ++u) acc[s4] += v[s4][u];
       }
 #pragma unroll
-      for (int s4 = 0; s4 < kSums; ++s4) {
-        const int e = e0 + NT * s4;
-        if (e < nel) xs[e] = (e < nff2 ? 1.0 : sim) * acc[s4] * inv;
-      }
+      for (int s4 = 0; s4 < kSums; ++s4)
+        if (dst[s4] >= 0) xs[dst[s4]] = (dst[s4] < nff2 ? 1.0 : sim) * acc[s4] * inv;
     }
   }
   for (int i = threadIdx.x; i < nff2; i += blockDim.x) {
@@ -88,7 +93,7 @@ __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, Basi
   // ts[m'][b2] = sum_{n' in shell(b2)} c_{n'b2} xt_{m'n'}, then
   // yb[b1 b2] = sum_{m' in shell(b1)} c_{m'b1} ts[m'][b2]
   double* ts = sh.ts;
-  for (int i = threadIdx.x; i < nff2; i += blockDim.x) {
+  for (int i = r0 * nff + threadIdx.x; i < r1 * nff; i += blockDim.x) {
     const int mp = i / nff, b2 = i % nff;
     const int s2 = d.shell_of[b2];
     const int n0 = d.shell_start[s2], n1 = d.shell_start[s2 + 1];
@@ -104,7 +109,7 @@ __device__ __forceinline__ void basis_body(const Batch& b, const int4 item, Basi
   }
   __syncthreads();
   double* yb = b.yb + d.ws_yb;
-  for (int bb = threadIdx.x; bb < nff2; bb += blockDim.x) {
+  for (int bb = r0 * nff + threadIdx.x; bb < r1 * nff; bb += blockDim.x) {
     const int b1 = bb / nff, b2 = bb % nff;
     const int s1 = d.shell_of[b1];
     const int m0 = d.shell_start[s1], m1 = d.shell_start[s1 + 1];
