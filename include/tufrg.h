@@ -160,7 +160,8 @@ enum {
                                the factored path's up to summation order. */
   TUFRG_NO_LOOP_REUSE = 1u << 8, /* flows: evaluate the loops at every stage.  By
                                default a stage at the temperature of the stage
-                               just before it (RK4's second and third,
+                               just before it (RK4's second and third, RK4's
+                               first and the last stage of the step before,
                                Dormand-Prince's sixth and seventh) takes that
                                stage's loops, still in the workspace, instead of
                                evaluating them again (the loops depend on T

@@ -579,8 +579,9 @@ void set_T_launch(tufrg_ctx* ctx, const TSource& ts, hipStream_t s) {
 // loops run on the side stream (fork and join by events) alongside the
 // whole projection chain.
 // same_T: the right-hand side issued just before this one on the context
-// took the same temperatures (two stages of one step at the same s: RK4's
-// second and third, Dormand-Prince's sixth and seventh), so its loop
+// took the same temperatures (two stages at the same s: RK4's second and
+// third, RK4's first and the last of the step before, Dormand-Prince's sixth
+// and seventh), so its loop
 // expansion, still in dchi, is used again and the loop and expansion work is
 // not issued (the loops read only T; the bits are those of a fresh
 // evaluation).  Not with the surrogate, whose checks count its calls.
@@ -1558,8 +1559,12 @@ tufrg_status locate_maxima(tufrg_ctx* ctx, const double* X, hipStream_t ms, std:
 // One RK4 step of every point still flowing, in s = ln T: stage temperatures
 // from the device table at the device step counter, slopes dX/ds, the update
 // (stopped points untouched), per-point max|X| and the device-side stop test.
+// The third stage takes the second's loops (same temperature); with
+// reuse_first (every step after a flow's first) the first stage takes the
+// loops of the step before's last stage, whose table temperature exp(s0 +
+// (i + 1) h) is bit for bit the first stage's of step i + 1.
 void rk4_step(tufrg_ctx* ctx, const Launch& L, double* X, double h, double xmax, int nsteps,
-              hipStream_t ms) {
+              hipStream_t ms, bool reuse_first) {
   double* const* k = ctx->kk;
   const int npts = (int)ctx->dev.size();
   const double half[1] = {0.5}, one[1] = {1.0};
@@ -1568,7 +1573,7 @@ void rk4_step(tufrg_ctx* ctx, const Launch& L, double* X, double h, double xmax,
   auto stage_T = [](int stage) { return TSource{nullptr, 0, 0, stage}; };
   if (!L.fused) {
     // large contexts: the stage combinations as streaming kernels of their own
-    rhs_launch(ctx, L, r, X, k[0], true, ms, stage_T(0));
+    rhs_launch(ctx, L, r, X, k[0], true, ms, stage_T(0), nullptr, reuse_first);
     launch_axpy(L, r.seg, X, &k[0], half, 1, h, ctx->stage, true, ms);
     rhs_launch(ctx, L, r, ctx->stage, k[1], true, ms, stage_T(1));
     launch_axpy(L, r.seg, X, &k[1], half, 1, h, ctx->stage, true, ms);
@@ -1598,7 +1603,7 @@ void rk4_step(tufrg_ctx* ctx, const Launch& L, double* X, double h, double xmax,
   double* st[2] = {ctx->stage, ctx->stage2};
   const StageNext n1 = next(st[0], half, 1, &k[0]), n2 = next(st[1], half, 1, &k[1]);
   const StageNext n3 = next(st[0], one, 1, &k[2]), n4 = next(X, fin, 4, k);
-  rhs_launch(ctx, L, r, X, k[0], true, ms, stage_T(0), &n1);
+  rhs_launch(ctx, L, r, X, k[0], true, ms, stage_T(0), &n1, reuse_first);
   rhs_launch(ctx, L, r, st[0], k[1], true, ms, stage_T(1), &n2);
   rhs_launch(ctx, L, r, st[1], k[2], true, ms, stage_T(2), &n3, true);
   rhs_launch(ctx, L, r, st[0], k[3], true, ms, stage_T(3), &n4);
@@ -1656,9 +1661,11 @@ tufrg_status flow_rk4_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, t
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
   };
+  // the graph holds a step after the first (its first stage takes the loops
+  // of the step before); the first step is issued directly
   if (o->use_graph) {
     HIP_TRY(ctx, hipStreamBeginCapture(ms, hipStreamCaptureModeThreadLocal));
-    rk4_step(ctx, Lf, X, h, o->Xmax, nsteps, ms);
+    rk4_step(ctx, Lf, X, h, o->Xmax, nsteps, ms, true);
     hipError_t e = hipStreamEndCapture(ms, &graph);
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -1673,11 +1680,11 @@ tufrg_status flow_rk4_all(tufrg_ctx* ctx, const tufrg_flow_opts* o, double* X, t
   // runs as a no-op
   int done = 0;
   auto issue = [&]() -> hipError_t {
-    if (exec) {
+    if (exec && done > 0) {
       const hipError_t e = hipGraphLaunch(exec, ms);
       if (e != hipSuccess) return e;
     } else {
-      rk4_step(ctx, Lf, X, h, o->Xmax, nsteps, ms);
+      rk4_step(ctx, Lf, X, h, o->Xmax, nsteps, ms, done > 0);
     }
     return hipEventRecord(ctx->ev_att[done++ & 1], ms);
   };

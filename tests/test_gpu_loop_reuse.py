@@ -1,12 +1,14 @@
 """Flows that take the loops of the stage before at an equal temperature.
 
-RK4's second and third stages share one temperature, and so do the sixth and
-seventh stages of Dormand-Prince; the loops depend on the temperature alone,
-so by default the second of each pair takes the loops its predecessor left in
-the workspace.  Checked here: every flow equals, bit for bit, the same flow
-with the loops evaluated at every stage (TUFRG_NO_LOOP_REUSE), in the fused
-single-stream form and in the two-stream form, for one point and for a batch
-of uneven points, in FP64 and in the mixed precision form.
+RK4's second and third stages share one temperature, so do RK4's first stage
+and the last stage of the step before (its table temperature is the same
+expression), and so do the sixth and seventh stages of Dormand-Prince; the
+loops depend on the temperature alone, so by default the second of each pair
+takes the loops its predecessor left in the workspace.  Checked here: every
+flow equals, bit for bit, the same flow with the loops evaluated at every
+stage (TUFRG_NO_LOOP_REUSE), in the fused single-stream form and in the
+two-stream form, eager and graph-replayed, for one point and for a batch of
+uneven points, in FP64 and in the mixed precision form.
 """
 import pytest
 
@@ -74,5 +76,23 @@ def test_reuse_is_bit_identical_mixed(tf):
     import torch
     print("[reuse] mixed dopri5", flush=True)
     (ra, Xa), (rb, Xb) = _both(tf, PTS[:1], _opts(tf, "dopri5", graph=False), precision="mixed")
+    assert ra == rb
+    assert torch.equal(Xa, Xb)
+
+
+@pytest.mark.parametrize("fuse", [True, False])
+def test_reuse_is_bit_identical_rk4_graph_single_point(tf, fuse):
+    """The RK4 graph holds a step after the first; the first step runs eagerly."""
+    import torch
+    print(f"[reuse] rk4 graph fuse={fuse}", flush=True)
+    (ra, Xa), (rb, Xb) = _both(tf, PTS[:1], _opts(tf, "rk4", graph=True), fuse=fuse)
+    assert ra == rb
+    assert torch.equal(Xa, Xb)
+
+
+def test_reuse_is_bit_identical_mixed_rk4(tf):
+    import torch
+    print("[reuse] mixed rk4 graph", flush=True)
+    (ra, Xa), (rb, Xb) = _both(tf, PTS[:1], _opts(tf, "rk4", graph=True), precision="mixed")
     assert ra == rb
     assert torch.equal(Xa, Xb)
